@@ -1,0 +1,998 @@
+/*
+ * spvar_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, sequential CPU reference for the hot path of multi-start
+ * sample-persistence variable reduction (SPVAR, Sec. II, Algorithms 1 and 2):
+ * the Monte Carlo samplers it calls (Metropolis simulated annealing, and
+ * parallel tempering with isoenergetic cluster moves, Sec. III.A and
+ * Sec. III.D.1) and the persistence step that fixes variables and reduces
+ * the problem.  It exists to check the HIP library bit for bit.  Only the
+ * test-suite, the smoke check and the benchmark's CPU-baseline leg may load
+ * it; the product path never does.  It shares no code with the HIP library:
+ * its Philox, acceptance tables, energies, persistence and reduction are
+ * written here from the definitions below.
+ *
+ * Definitions (integer units; a real value is integer / 2^scale_log2):
+ *
+ *  Objective (Sec. I): E(s) = sum_{i<j} J_ij s_i s_j + sum_i h_i s_i, each
+ *    undirected coupler counted once, minimised.
+ *
+ *  Metropolis update of spin i (Sec. III.A: SA; Sec. III.D.1: PT): local field
+ *    f_i = h_i + sum_j J_ij s_j; x = -s_i f_i, so that flipping changes the
+ *    energy by 2x.  x <= 0 always flips.  Otherwise x is written in base 512,
+ *    x = sum_j d_j 512^j, and the flip is accepted iff every nonzero digit
+ *    passes w_j < T_j[d_j] with T_j[d] = min(2^32-1,
+ *    floor(2^32 * exp(-(beta * (2 * d * 512^j)) / 2^scale))).  The product of
+ *    the digit factors is exp(-beta * 2x / 2^scale) up to 2^-32 rounding.
+ *
+ *  Sweep: colour classes in increasing colour, inside a class increasing
+ *    index (classes are independent sets, so the in-class order is immaterial).
+ *
+ *  Random words, Philox4x32-10 with key (seed_lo, seed_hi):
+ *    Metropolis digit j of (spin i, sweep t, replica r):
+ *        Philox(i, t, r>>2, (2<<24)|j)[r&3]
+ *    initial spin i of replica r: +1 iff Philox(i, 0, r>>2, 1<<24)[r&3] >> 31
+ *    PT swap of pair (k,k+1) of chain-run c at sweep t, digit j:
+ *        Philox(k, t, c, (3<<24)|(j>>2))[j&3]
+ *    isoenergetic cluster move at slot k of run u at sweep t:
+ *        Philox(k, t, u, 4<<24)[0]
+ *
+ *  PT replica exchange: pairs (k,k+1) with k = t (mod 2); D = E_k - E_{k+1};
+ *    accept iff D <= 0 or the digit test of D passes with tables built for
+ *    dbeta = beta_{k+1} - beta_k and unit 1 (T_j[d] uses d * 512^j); when
+ *    D >= 512^nd with nd the smallest digit count whose next digit value has
+ *    T == 0, the move is rejected (exactly what further digits would give).
+ *
+ *  Houdayer cluster move between chains 0 and 1 at slot k: q_i = s^A_i s^B_i;
+ *    with n_neg sites at q=-1, the seed is the floor(w*n_neg/2^32)-th such
+ *    site in index order; the cluster is its connected component among q=-1
+ *    sites (edges with J != 0); the cluster is flipped in both replicas.
+ *
+ *  Top-10 sample (Sec. III.D.1): per colder-half slot (k >= K/2) the 10
+ *    lowest-energy distinct states seen after each sweep; insert iff fewer
+ *    than 10 are held or E < the worst held; an identical state is never
+ *    inserted twice; eviction removes the worst, latest-inserted among ties;
+ *    output order (E, insertion).
+ *
+ *  Persistence (Algorithm 1): elite = first m = max(1, ceil(eps*R)) rows in
+ *    (E, row) order; gauge (Sec. II.C zero-bias handling): classes of
+ *    variables whose elite columns are equal up to a global sign, pivot p =
+ *    lowest index of the largest class (ties: lower minimum index), elite
+ *    rows multiplied by their value at p; c_i = sum_elite s_ri; fix iff
+ *    |c_i| >= k_min = ceil(theta*m), to sign(c_i).
+ *
+ *  Reduction ("Update J and h", Algorithm 1): free set U in index order,
+ *    J' = J[U,U], h'_u = h_u + sum_{j fixed} J_uj v_j,
+ *    offset = sum_{i<j fixed} J_ij v_i v_j + sum_{i fixed} h_i v_i, so that
+ *    E(s) = E'(s_U) + offset whenever s agrees with the fixed values.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_EINVAL (-1)
+#define ORC_ERANGE (-4)
+#define ORC_ENOMEM (-9)
+#define ORC_EINTERNAL (-10)
+
+#define TAG_INIT 1u
+#define TAG_METRO 2u
+#define TAG_SWAP 3u
+#define TAG_ICM 4u
+#define DIGIT_BITS 9
+#define DIGIT_SIZE 512
+#define TOPK 10
+
+typedef struct {
+    int32_t n;
+    const int32_t *row_ptr;
+    const int32_t *col;
+    const int32_t *J;
+    const int32_t *h;
+    const uint8_t *colour;
+    int32_t n_colours;
+    int32_t scale_log2;
+} orc_problem;
+
+/* ---------------------------------------------------------------------- */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two    */
+/* 32x32->64 multiplications by fixed constants with a Weyl key schedule. */
+/* ---------------------------------------------------------------------- */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t a = ctr[0], b = ctr[1], c = ctr[2], d = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    int round;
+    for (round = 0; round < 10; ++round) {
+        uint64_t pa = (uint64_t)0xD2511F53u * (uint64_t)a;
+        uint64_t pc = (uint64_t)0xCD9E8D57u * (uint64_t)c;
+        uint32_t na = (uint32_t)(pc >> 32) ^ b ^ k0;
+        uint32_t nb = (uint32_t)pc;
+        uint32_t nc = (uint32_t)(pa >> 32) ^ d ^ k1;
+        uint32_t nd = (uint32_t)pa;
+        a = na; b = nb; c = nc; d = nd;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = a; out[1] = b; out[2] = c; out[3] = d;
+}
+
+/* Batch form for tests: out[i][0..3] = Philox(ctr[i][0..3], key). */
+void orc_philox_batch(const uint32_t *ctr, const uint32_t key[2], uint32_t *out, int64_t count)
+{
+    int64_t i;
+    for (i = 0; i < count; ++i)
+        orc_philox4x32_10(ctr + 4 * i, key, out + 4 * i);
+}
+
+static uint32_t philox_word(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                            uint64_t seed, int which)
+{
+    uint32_t ctr[4] = {c0, c1, c2, c3};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t out[4];
+    orc_philox4x32_10(ctr, key, out);
+    return out[which];
+}
+
+/* ---------------------------------------------------------------------- */
+/* Objective (Sec. I).                                                     */
+/* ---------------------------------------------------------------------- */
+int64_t orc_energy(const orc_problem *P, const int8_t *s)
+{
+    int64_t e = 0;
+    int32_t i, k;
+    for (i = 0; i < P->n; ++i) {
+        e += (int64_t)P->h[i] * s[i];
+        for (k = P->row_ptr[i]; k < P->row_ptr[i + 1]; ++k) {
+            int32_t j = P->col[k];
+            if (j > i)
+                e += (int64_t)P->J[k] * s[i] * s[j];
+        }
+    }
+    return e;
+}
+
+void orc_energy_batch(const orc_problem *P, const int8_t *spins, int32_t R, int64_t *E)
+{
+    int32_t r;
+    for (r = 0; r < R; ++r)
+        E[r] = orc_energy(P, spins + (size_t)r * P->n);
+}
+
+static int64_t local_field(const orc_problem *P, const int8_t *s, int32_t i)
+{
+    int64_t f = P->h[i];
+    int32_t k;
+    for (k = P->row_ptr[i]; k < P->row_ptr[i + 1]; ++k)
+        f += (int64_t)P->J[k] * s[P->col[k]];
+    return f;
+}
+
+/* Largest |h_i| + sum_j |J_ij|: bounds |x| of every Metropolis proposal. */
+int64_t orc_x_max(const orc_problem *P)
+{
+    int64_t best = 0;
+    int32_t i, k;
+    for (i = 0; i < P->n; ++i) {
+        int64_t v = llabs((long long)P->h[i]);
+        for (k = P->row_ptr[i]; k < P->row_ptr[i + 1]; ++k)
+            v += llabs((long long)P->J[k]);
+        if (v > best)
+            best = v;
+    }
+    return best;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Integer acceptance thresholds.                                          */
+/* ---------------------------------------------------------------------- */
+uint32_t orc_threshold(double beta, int64_t unit, int32_t scale_log2, int32_t digit, uint32_t d)
+{
+    double X = (double)(unit * (int64_t)d * ((int64_t)1 << (DIGIT_BITS * digit)));
+    double p = beta * X;
+    double a = ldexp(p, -scale_log2);
+    double v = exp(-a) * 4294967296.0;
+    if (v >= 4294967295.0)
+        return 0xFFFFFFFFu;
+    return (uint32_t)floor(v);
+}
+
+static int32_t digits_for(int64_t xmax)
+{
+    int32_t nd = 1;
+    while (nd < 7 && (xmax >> (DIGIT_BITS * nd)) != 0)
+        ++nd;
+    return nd;
+}
+
+/* Digit count of a swap test: the first digit position whose unit value
+ * already has a zero threshold (capped at 7 digits = 63 bits). */
+int32_t orc_swap_digits(double dbeta, int32_t scale_log2)
+{
+    int32_t nd;
+    for (nd = 1; nd < 7; ++nd)
+        if (orc_threshold(dbeta, 1, scale_log2, nd, 1) == 0)
+            return nd;
+    return 7;
+}
+
+/* Table for one beta: T[j*512 + d]. */
+static void build_table(double beta, int64_t unit, int32_t scale_log2, int32_t nd, uint32_t *T)
+{
+    int32_t j, d;
+    for (j = 0; j < nd; ++j)
+        for (d = 0; d < DIGIT_SIZE; ++d)
+            T[j * DIGIT_SIZE + d] = orc_threshold(beta, unit, scale_log2, j, (uint32_t)d);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Sweep order: colour classes ascending, inside a class index ascending.  */
+/* ---------------------------------------------------------------------- */
+static int32_t *default_order(const orc_problem *P)
+{
+    int32_t *ord = (int32_t *)malloc(sizeof(int32_t) * (P->n > 0 ? P->n : 1));
+    int32_t pos = 0, c, i;
+    if (!ord)
+        return NULL;
+    for (c = 0; c < P->n_colours; ++c)
+        for (i = 0; i < P->n; ++i)
+            if (P->colour[i] == c)
+                ord[pos++] = i;
+    if (pos != P->n) {
+        free(ord);
+        return NULL;
+    }
+    return ord;
+}
+
+/* One Metropolis sweep of one replica; returns the energy change. */
+static int64_t metropolis_sweep(const orc_problem *P, const int32_t *order, int8_t *s,
+                                const uint32_t *T, int32_t nd, uint32_t t, uint32_t r,
+                                uint64_t seed)
+{
+    int64_t dE = 0;
+    int32_t p;
+    for (p = 0; p < P->n; ++p) {
+        int32_t i = order[p];
+        int64_t f = local_field(P, s, i);
+        int64_t x = -(int64_t)s[i] * f;
+        int accept = 1;
+        if (x > 0) {
+            int32_t j;
+            for (j = 0; j < nd && accept; ++j) {
+                uint32_t d = (uint32_t)((x >> (DIGIT_BITS * j)) & (DIGIT_SIZE - 1));
+                if (d != 0) {
+                    uint32_t w = philox_word((uint32_t)i, t, r >> 2,
+                                             (TAG_METRO << 24) | (uint32_t)j, seed, (int)(r & 3));
+                    if (!(w < T[j * DIGIT_SIZE + d]))
+                        accept = 0;
+                }
+            }
+        }
+        if (accept) {
+            s[i] = (int8_t)(-s[i]);
+            dE += 2 * x;
+        }
+    }
+    return dE;
+}
+
+static void init_spins(int32_t n, uint32_t r, uint64_t seed, int8_t *s)
+{
+    int32_t i;
+    for (i = 0; i < n; ++i) {
+        uint32_t w = philox_word((uint32_t)i, 0, r >> 2, TAG_INIT << 24, seed, (int)(r & 3));
+        s[i] = (w >> 31) ? 1 : -1;
+    }
+}
+
+static int check_problem(const orc_problem *P)
+{
+    int32_t i;
+    if (!P || P->n < 0 || P->n_colours < 1 || P->n_colours > 255)
+        return ORC_EINVAL;
+    for (i = 0; i < P->n; ++i)
+        if (P->colour[i] >= P->n_colours)
+            return ORC_EINVAL;
+    return ORC_OK;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Simulated annealing: one Metropolis sweep per entry of betas.           */
+/* Reads r in [r_begin, r_end); outputs are indexed from r_begin.          */
+/* order: optional visit order (must list classes in increasing colour).  */
+/* ---------------------------------------------------------------------- */
+int orc_sa_sample(const orc_problem *P, const double *betas, int32_t sweeps, uint64_t seed,
+                  uint32_t sweep_offset, int32_t r_begin, int32_t r_end, const int8_t *init,
+                  const int32_t *order_in, int8_t *spins_out, int64_t *E_out)
+{
+    int32_t nd, t, r;
+    uint32_t *tables;
+    int32_t *order;
+    int rc = check_problem(P);
+    if (rc)
+        return rc;
+    if (sweeps < 0 || r_begin < 0 || r_end < r_begin)
+        return ORC_EINVAL;
+    for (t = 0; t < sweeps; ++t)
+        if (!(betas[t] >= 0.0) || isinf(betas[t]))
+            return ORC_EINVAL;
+    nd = digits_for(orc_x_max(P));
+    tables = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(sweeps > 0 ? sweeps : 1) * nd * DIGIT_SIZE);
+    if (order_in) {
+        order = (int32_t *)malloc(sizeof(int32_t) * (P->n > 0 ? P->n : 1));
+        if (order)
+            memcpy(order, order_in, sizeof(int32_t) * P->n);
+    } else {
+        order = default_order(P);
+    }
+    if (!tables || !order) {
+        free(tables);
+        free(order);
+        return ORC_ENOMEM;
+    }
+    for (t = 0; t < sweeps; ++t)
+        build_table(betas[t], 2, P->scale_log2, nd, tables + (size_t)t * nd * DIGIT_SIZE);
+    for (r = r_begin; r < r_end; ++r) {
+        int8_t *s = spins_out + (size_t)(r - r_begin) * P->n;
+        int64_t E;
+        if (init)
+            memcpy(s, init + (size_t)(r - r_begin) * P->n, (size_t)P->n);
+        else
+            init_spins(P->n, (uint32_t)r, seed, s);
+        E = orc_energy(P, s);
+        for (t = 0; t < sweeps; ++t)
+            E += metropolis_sweep(P, order, s, tables + (size_t)t * nd * DIGIT_SIZE, nd,
+                                  sweep_offset + (uint32_t)t, (uint32_t)r, seed);
+        if (E != orc_energy(P, s)) {
+            free(tables);
+            free(order);
+            return ORC_EINTERNAL;
+        }
+        E_out[r - r_begin] = E;
+    }
+    free(tables);
+    free(order);
+    return ORC_OK;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Parallel tempering (+ Houdayer cluster moves, + top-10 sample).         */
+/* ---------------------------------------------------------------------- */
+typedef struct {
+    int64_t E[TOPK];
+    int64_t when[TOPK];
+    int32_t count;
+    int8_t *state; /* [TOPK][n] */
+} topk_list;
+
+static void topk_offer(topk_list *L, int32_t n, int64_t E, const int8_t *s, int64_t when)
+{
+    int32_t e, victim;
+    if (L->count == TOPK) {
+        int64_t worst = L->E[0];
+        for (e = 1; e < TOPK; ++e)
+            if (L->E[e] > worst)
+                worst = L->E[e];
+        if (!(E < worst))
+            return;
+    }
+    for (e = 0; e < L->count; ++e)
+        if (L->E[e] == E && memcmp(L->state + (size_t)e * n, s, (size_t)n) == 0)
+            return;
+    if (L->count < TOPK) {
+        victim = L->count++;
+    } else {
+        victim = 0;
+        for (e = 1; e < TOPK; ++e)
+            if (L->E[e] > L->E[victim] || (L->E[e] == L->E[victim] && L->when[e] > L->when[victim]))
+                victim = e;
+    }
+    L->E[victim] = E;
+    L->when[victim] = when;
+    memcpy(L->state + (size_t)victim * n, s, (size_t)n);
+}
+
+/* Houdayer move on replicas A and B; returns 1 if a cluster was flipped. */
+static int icm_move(const orc_problem *P, int8_t *A, int8_t *B, int64_t *EA, int64_t *EB,
+                    uint32_t w, int32_t *queue, uint8_t *in_cluster)
+{
+    int32_t n = P->n, i, k, n_neg = 0, target, seed_site = -1, head = 0, tail = 0;
+    int64_t dA = 0, dB = 0;
+    for (i = 0; i < n; ++i)
+        if (A[i] != B[i])
+            ++n_neg;
+    if (n_neg == 0)
+        return 0;
+    target = (int32_t)(((uint64_t)w * (uint64_t)n_neg) >> 32);
+    for (i = 0; i < n; ++i) {
+        if (A[i] != B[i]) {
+            if (target == 0) {
+                seed_site = i;
+                break;
+            }
+            --target;
+        }
+    }
+    memset(in_cluster, 0, (size_t)n);
+    in_cluster[seed_site] = 1;
+    queue[tail++] = seed_site;
+    while (head < tail) {
+        int32_t v = queue[head++];
+        for (k = P->row_ptr[v]; k < P->row_ptr[v + 1]; ++k) {
+            int32_t u = P->col[k];
+            if (P->J[k] != 0 && A[u] != B[u] && !in_cluster[u]) {
+                in_cluster[u] = 1;
+                queue[tail++] = u;
+            }
+        }
+    }
+    /* Energy change of flipping the cluster C: bias terms of C and couplers
+     * crossing the cluster boundary change sign. */
+    for (head = 0; head < tail; ++head) {
+        int32_t v = queue[head];
+        dA += -2 * (int64_t)P->h[v] * A[v];
+        dB += -2 * (int64_t)P->h[v] * B[v];
+        for (k = P->row_ptr[v]; k < P->row_ptr[v + 1]; ++k) {
+            int32_t u = P->col[k];
+            if (!in_cluster[u]) {
+                dA += -2 * (int64_t)P->J[k] * A[v] * A[u];
+                dB += -2 * (int64_t)P->J[k] * B[v] * B[u];
+            }
+        }
+    }
+    for (head = 0; head < tail; ++head) {
+        int32_t v = queue[head];
+        A[v] = (int8_t)(-A[v]);
+        B[v] = (int8_t)(-B[v]);
+    }
+    *EA += dA;
+    *EB += dB;
+    return 1;
+}
+
+/* Test hook: one Houdayer move with a given random word.  cluster[n] is set
+ * to 1 on the flipped sites.  Returns 1 if a cluster was flipped. */
+int orc_icm_step(const orc_problem *P, int8_t *A, int8_t *B, int64_t *EA, int64_t *EB,
+                 uint32_t w, uint8_t *cluster)
+{
+    int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)(P->n > 0 ? P->n : 1));
+    int rc;
+    if (!queue)
+        return ORC_ENOMEM;
+    memset(cluster, 0, (size_t)P->n);
+    rc = icm_move(P, A, B, EA, EB, w, queue, cluster);
+    free(queue);
+    return rc;
+}
+
+static int swap_accept(int64_t D, const uint32_t *T, int32_t nd, uint32_t k, uint32_t t,
+                       uint32_t c, uint64_t seed)
+{
+    int32_t j;
+    if (D <= 0)
+        return 1;
+    if (nd < 7 && (D >> (DIGIT_BITS * nd)) != 0)
+        return 0;
+    for (j = 0; j < nd; ++j) {
+        uint32_t d = (uint32_t)((D >> (DIGIT_BITS * j)) & (DIGIT_SIZE - 1));
+        if (d != 0) {
+            uint32_t w = philox_word(k, t, c, (TAG_SWAP << 24) | ((uint32_t)j >> 2), seed, j & 3);
+            if (!(w < T[j * DIGIT_SIZE + d]))
+                return 0;
+        }
+    }
+    return 1;
+}
+
+/* Test hook: the replica-exchange decision for an energy difference D. */
+int orc_swap_test(int64_t D, double dbeta, int32_t scale_log2, uint32_t k, uint32_t t, uint32_t c,
+                  uint64_t seed)
+{
+    uint32_t T[7 * DIGIT_SIZE];
+    int32_t nd = orc_swap_digits(dbeta, scale_log2);
+    build_table(dbeta, 1, scale_log2, nd, T);
+    return swap_accept(D, T, nd, k, t, c, seed);
+}
+
+/*
+ * runs [run_begin, run_end) of a PT job with K slots (betas ascending) and
+ * `chains` independent ladders per run.  Outputs are indexed from run_begin:
+ *   final_spins [runs][chains][K][n], final_E [runs][chains][K]   (optional)
+ *   top_spins [runs][chains][K/2][10][n], top_E [..][10], top_count [..]
+ *     (optional; unfilled entries: E = INT64_MAX, spins 0)
+ *   log_E [sweeps][chains][K], log_spins [sweeps][chains][K][n]  (optional,
+ *     only for run_begin: the state after every sweep, for tests)
+ * icm_lo..icm_hi: slot window of the cluster moves (needs chains == 2).
+ */
+int orc_pt_sample(const orc_problem *P, const double *betas, int32_t K, int32_t runs,
+                  int32_t chains, int32_t sweeps, uint64_t seed, uint32_t sweep_offset,
+                  int32_t icm_lo, int32_t icm_hi, int32_t run_begin, int32_t run_end,
+                  int8_t *final_spins, int64_t *final_E, int8_t *top_spins, int64_t *top_E,
+                  int32_t *top_count, int64_t *log_E, int8_t *log_spins)
+{
+    int32_t n = P->n, nd, k, run, ch, ls, half = K / 2;
+    int32_t nrep = chains * K;
+    uint32_t *mtab = NULL, *stab = NULL;
+    int32_t *snd = NULL, *order = NULL, *queue = NULL;
+    int8_t *S = NULL, *tmp = NULL;
+    uint8_t *inc = NULL;
+    int64_t *E = NULL;
+    topk_list *lists = NULL;
+    int rc = check_problem(P);
+    if (rc)
+        return rc;
+    if (K < 1 || runs < 1 || chains < 1 || sweeps < 0 || run_begin < 0 || run_end > runs ||
+        run_end < run_begin)
+        return ORC_EINVAL;
+    if (icm_hi > icm_lo && (chains != 2 || icm_lo < 0 || icm_hi > K))
+        return ORC_EINVAL;
+    for (k = 0; k < K; ++k) {
+        if (!(betas[k] >= 0.0) || isinf(betas[k]))
+            return ORC_EINVAL;
+        if (k > 0 && betas[k] < betas[k - 1])
+            return ORC_EINVAL;
+    }
+    nd = digits_for(orc_x_max(P));
+    mtab = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)K * nd * DIGIT_SIZE);
+    stab = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)K * 7 * DIGIT_SIZE);
+    snd = (int32_t *)malloc(sizeof(int32_t) * (size_t)K);
+    order = default_order(P);
+    queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    inc = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
+    S = (int8_t *)malloc((size_t)nrep * (n > 0 ? n : 1));
+    tmp = (int8_t *)malloc((size_t)(n > 0 ? n : 1));
+    E = (int64_t *)malloc(sizeof(int64_t) * (size_t)nrep);
+    lists = (topk_list *)calloc((size_t)chains * (half > 0 ? half : 1), sizeof(topk_list));
+    if (!mtab || !stab || !snd || !order || !queue || !inc || !S || !tmp || !E || !lists) {
+        rc = ORC_ENOMEM;
+        goto done;
+    }
+    for (k = 0; k < chains * half; ++k) {
+        lists[k].state = (int8_t *)malloc((size_t)TOPK * (n > 0 ? n : 1));
+        if (!lists[k].state) {
+            rc = ORC_ENOMEM;
+            goto done;
+        }
+    }
+    for (k = 0; k < K; ++k)
+        build_table(betas[k], 2, P->scale_log2, nd, mtab + (size_t)k * nd * DIGIT_SIZE);
+    for (k = 0; k + 1 < K; ++k) {
+        double db = betas[k + 1] - betas[k];
+        snd[k] = orc_swap_digits(db, P->scale_log2);
+        build_table(db, 1, P->scale_log2, snd[k], stab + (size_t)k * 7 * DIGIT_SIZE);
+    }
+    for (run = run_begin; run < run_end; ++run) {
+        int32_t lr = run - run_begin;
+        int64_t when = 0;
+        for (ch = 0; ch < chains * half; ++ch)
+            lists[ch].count = 0;
+        for (ch = 0; ch < chains; ++ch)
+            for (k = 0; k < K; ++k) {
+                uint32_t r = (uint32_t)((run * chains + ch) * K + k);
+                int8_t *s = S + (size_t)(ch * K + k) * n;
+                init_spins(n, r, seed, s);
+                E[ch * K + k] = orc_energy(P, s);
+            }
+        for (ls = 0; ls < sweeps; ++ls) {
+            uint32_t t = sweep_offset + (uint32_t)ls;
+            /* 1. Metropolis on every slot. */
+            for (ch = 0; ch < chains; ++ch)
+                for (k = 0; k < K; ++k) {
+                    uint32_t r = (uint32_t)((run * chains + ch) * K + k);
+                    E[ch * K + k] += metropolis_sweep(P, order, S + (size_t)(ch * K + k) * n,
+                                                      mtab + (size_t)k * nd * DIGIT_SIZE, nd, t, r,
+                                                      seed);
+                }
+            /* 2. Replica exchange inside each chain. */
+            for (ch = 0; ch < chains; ++ch) {
+                uint32_t c = (uint32_t)(run * chains + ch);
+                for (k = (int32_t)(t & 1u); k + 1 < K; k += 2) {
+                    int64_t D = E[ch * K + k] - E[ch * K + k + 1];
+                    if (swap_accept(D, stab + (size_t)k * 7 * DIGIT_SIZE, snd[k], (uint32_t)k, t, c,
+                                    seed)) {
+                        int8_t *a = S + (size_t)(ch * K + k) * n;
+                        int8_t *b = S + (size_t)(ch * K + k + 1) * n;
+                        int64_t e = E[ch * K + k];
+                        memcpy(tmp, a, (size_t)n);
+                        memcpy(a, b, (size_t)n);
+                        memcpy(b, tmp, (size_t)n);
+                        E[ch * K + k] = E[ch * K + k + 1];
+                        E[ch * K + k + 1] = e;
+                    }
+                }
+            }
+            /* 3. Isoenergetic cluster moves between the two chains. */
+            for (k = icm_lo; k < icm_hi; ++k) {
+                uint32_t w = philox_word((uint32_t)k, t, (uint32_t)run, TAG_ICM << 24, seed, 0);
+                icm_move(P, S + (size_t)k * n, S + (size_t)(K + k) * n, &E[k], &E[K + k], w, queue,
+                         inc);
+            }
+            /* 4. Offer the colder half to the top-10 lists. */
+            for (ch = 0; ch < chains; ++ch)
+                for (k = half; k < K; ++k)
+                    topk_offer(&lists[ch * half + (k - half)], n, E[ch * K + k],
+                               S + (size_t)(ch * K + k) * n, when++);
+            if (log_E && run == run_begin) {
+                memcpy(log_E + (size_t)ls * nrep, E, sizeof(int64_t) * (size_t)nrep);
+                if (log_spins)
+                    memcpy(log_spins + (size_t)ls * nrep * n, S, (size_t)nrep * n);
+            }
+        }
+        for (k = 0; k < nrep; ++k)
+            if (E[k] != orc_energy(P, S + (size_t)k * n)) {
+                rc = ORC_EINTERNAL;
+                goto done;
+            }
+        if (final_spins)
+            memcpy(final_spins + (size_t)lr * nrep * n, S, (size_t)nrep * n);
+        if (final_E)
+            memcpy(final_E + (size_t)lr * nrep, E, sizeof(int64_t) * (size_t)nrep);
+        if (top_E) {
+            for (ch = 0; ch < chains * half; ++ch) {
+                topk_list *L = &lists[ch];
+                size_t base = ((size_t)lr * chains * half + ch) * TOPK;
+                int32_t rank, e;
+                uint8_t used[TOPK] = {0};
+                for (rank = 0; rank < TOPK; ++rank) {
+                    int32_t best = -1;
+                    for (e = 0; e < L->count; ++e)
+                        if (!used[e] && (best < 0 || L->E[e] < L->E[best] ||
+                                         (L->E[e] == L->E[best] && L->when[e] < L->when[best])))
+                            best = e;
+                    if (best < 0) {
+                        top_E[base + rank] = INT64_MAX;
+                        if (top_spins)
+                            memset(top_spins + (base + rank) * n, 0, (size_t)n);
+                        continue;
+                    }
+                    used[best] = 1;
+                    top_E[base + rank] = L->E[best];
+                    if (top_spins)
+                        memcpy(top_spins + (base + rank) * n, L->state + (size_t)best * n, (size_t)n);
+                }
+                if (top_count)
+                    top_count[(size_t)lr * chains * half + ch] = L->count;
+            }
+        }
+    }
+done:
+    if (lists)
+        for (k = 0; k < chains * half; ++k)
+            free(lists[k].state);
+    free(lists);
+    free(E);
+    free(tmp);
+    free(S);
+    free(inc);
+    free(queue);
+    free(order);
+    free(snd);
+    free(stab);
+    free(mtab);
+    return rc;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Persistence and reduction (Algorithm 1).                                */
+/* ---------------------------------------------------------------------- */
+typedef struct {
+    int64_t E;
+    int32_t row;
+} elite_key;
+
+static int cmp_elite(const void *a, const void *b)
+{
+    const elite_key *x = (const elite_key *)a, *y = (const elite_key *)b;
+    if (x->E != y->E)
+        return x->E < y->E ? -1 : 1;
+    return (x->row > y->row) - (x->row < y->row);
+}
+
+typedef struct {
+    const int8_t *col; /* canonical column, m entries */
+    int32_t m;
+    int32_t idx;
+} canon_key;
+
+static int cmp_canon(const void *a, const void *b)
+{
+    const canon_key *x = (const canon_key *)a, *y = (const canon_key *)b;
+    int c = memcmp(x->col, y->col, (size_t)x->m);
+    if (c)
+        return c;
+    return (x->idx > y->idx) - (x->idx < y->idx);
+}
+
+/*
+ * info[8]: n_free, nnz_free, offset, n_fixed, pivot (-1 without gauge), m, k_min, 0.
+ * gauge: 0 off, 1 on, 2 on iff every h_i == 0.
+ * The reduced CSR buffers must hold n (rows) and nnz (entries).
+ */
+int orc_persist_fix(const orc_problem *P, const int8_t *samples, const int64_t *energies,
+                    int32_t R, double elite_frac, double threshold, int32_t gauge,
+                    uint8_t *fixed_mask, int8_t *fixed_val, int32_t *row_ptr_o, int32_t *col_o,
+                    int32_t *J_o, int32_t *h_o, uint8_t *colour_o, int32_t *orig_o, int64_t *info)
+{
+    int32_t n = P->n, i, k, r, m, kmin, pivot = -1, use_gauge = 0;
+    int32_t *elite = NULL, *newid = NULL;
+    elite_key *idx = NULL;
+    int8_t *g = NULL, *canon = NULL;
+    int64_t *cnt = NULL, offset = 0;
+    int32_t n_free = 0, nnz_free = 0, n_fixed = 0;
+    double mm, kk;
+    int rc = check_problem(P);
+    if (rc)
+        return rc;
+    if (R < 1 || !(elite_frac > 0.0 && elite_frac <= 1.0) || !(threshold > 0.0 && threshold <= 1.0) ||
+        gauge < 0 || gauge > 2)
+        return ORC_EINVAL;
+    for (r = 0; r < R; ++r)
+        for (i = 0; i < n; ++i)
+            if (samples[(size_t)r * n + i] != 1 && samples[(size_t)r * n + i] != -1)
+                return ORC_EINVAL;
+    mm = ceil(elite_frac * (double)R);
+    m = (int32_t)mm;
+    if (m < 1)
+        m = 1;
+    if (m > R)
+        m = R;
+    kk = ceil(threshold * (double)m);
+    kmin = (int32_t)kk;
+    if (kmin < 1)
+        return ORC_EINVAL;
+    idx = (elite_key *)malloc(sizeof(elite_key) * (size_t)R);
+    elite = (int32_t *)malloc(sizeof(int32_t) * (size_t)m);
+    g = (int8_t *)malloc((size_t)m);
+    cnt = (int64_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+    newid = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    if (!idx || !elite || !g || !cnt || !newid) {
+        rc = ORC_ENOMEM;
+        goto done;
+    }
+    /* Elite: the m lowest (E, row) rows; kept in row order. */
+    for (r = 0; r < R; ++r) {
+        idx[r].E = energies[r];
+        idx[r].row = r;
+    }
+    qsort(idx, (size_t)R, sizeof(elite_key), cmp_elite);
+    for (r = 0; r < m; ++r)
+        elite[r] = idx[r].row;
+    {
+        int32_t a, b;
+        for (a = 1; a < m; ++a) { /* insertion sort by row */
+            int32_t v = elite[a];
+            for (b = a - 1; b >= 0 && elite[b] > v; --b)
+                elite[b + 1] = elite[b];
+            elite[b + 1] = v;
+        }
+    }
+    if (gauge == 1)
+        use_gauge = 1;
+    else if (gauge == 2) {
+        use_gauge = 1;
+        for (i = 0; i < n; ++i)
+            if (P->h[i] != 0)
+                use_gauge = 0;
+    }
+    for (r = 0; r < m; ++r)
+        g[r] = 1;
+    if (use_gauge && n > 0) {
+        /* Canonical column of i: its elite values times its value in the
+         * first elite row; equal canonical columns <=> columns equal up to
+         * a global sign. */
+        canon_key *cols = (canon_key *)malloc(sizeof(canon_key) * (size_t)n);
+        int32_t best_size = 0, best_min = 0, a = 0;
+        canon = (int8_t *)malloc((size_t)n * m);
+        if (!cols || !canon) {
+            free(cols);
+            rc = ORC_ENOMEM;
+            goto done;
+        }
+        for (i = 0; i < n; ++i) {
+            int8_t first = samples[(size_t)elite[0] * n + i];
+            for (r = 0; r < m; ++r)
+                canon[(size_t)i * m + r] = (int8_t)(samples[(size_t)elite[r] * n + i] * first);
+            cols[i].col = canon + (size_t)i * m;
+            cols[i].m = m;
+            cols[i].idx = i;
+        }
+        qsort(cols, (size_t)n, sizeof(canon_key), cmp_canon);
+        while (a < n) {
+            int32_t b = a + 1, mn = cols[a].idx;
+            while (b < n && memcmp(cols[a].col, cols[b].col, (size_t)m) == 0) {
+                if (cols[b].idx < mn)
+                    mn = cols[b].idx;
+                ++b;
+            }
+            if (b - a > best_size || (b - a == best_size && mn < best_min)) {
+                best_size = b - a;
+                best_min = mn;
+            }
+            a = b;
+        }
+        pivot = best_min;
+        for (r = 0; r < m; ++r)
+            g[r] = samples[(size_t)elite[r] * n + pivot];
+        free(cols);
+    }
+    for (r = 0; r < m; ++r)
+        for (i = 0; i < n; ++i)
+            cnt[i] += (int64_t)g[r] * samples[(size_t)elite[r] * n + i];
+    for (i = 0; i < n; ++i) {
+        int64_t c = cnt[i];
+        if (llabs((long long)c) >= kmin) {
+            fixed_mask[i] = 1;
+            fixed_val[i] = (int8_t)(c > 0 ? 1 : -1);
+            ++n_fixed;
+        } else {
+            fixed_mask[i] = 0;
+            fixed_val[i] = 0;
+        }
+    }
+    /* Reduction. */
+    for (i = 0; i < n; ++i)
+        newid[i] = fixed_mask[i] ? -1 : n_free++;
+    row_ptr_o[0] = 0;
+    for (i = 0; i < n; ++i) {
+        if (fixed_mask[i]) {
+            offset += (int64_t)P->h[i] * fixed_val[i];
+            for (k = P->row_ptr[i]; k < P->row_ptr[i + 1]; ++k) {
+                int32_t j = P->col[k];
+                if (j > i && fixed_mask[j])
+                    offset += (int64_t)P->J[k] * fixed_val[i] * fixed_val[j];
+            }
+        } else {
+            int32_t u = newid[i];
+            int64_t hv = P->h[i];
+            for (k = P->row_ptr[i]; k < P->row_ptr[i + 1]; ++k) {
+                int32_t j = P->col[k];
+                if (fixed_mask[j]) {
+                    hv += (int64_t)P->J[k] * fixed_val[j];
+                } else {
+                    col_o[nnz_free] = newid[j];
+                    J_o[nnz_free] = P->J[k];
+                    ++nnz_free;
+                }
+            }
+            if (hv > INT32_MAX || hv < INT32_MIN) {
+                rc = ORC_ERANGE;
+                goto done;
+            }
+            h_o[u] = (int32_t)hv;
+            colour_o[u] = P->colour[i];
+            orig_o[u] = i;
+            row_ptr_o[u + 1] = nnz_free;
+        }
+    }
+    info[0] = n_free;
+    info[1] = nnz_free;
+    info[2] = offset;
+    info[3] = n_fixed;
+    info[4] = pivot;
+    info[5] = m;
+    info[6] = kmin;
+    info[7] = 0;
+done:
+    free(canon);
+    free(newid);
+    free(cnt);
+    free(g);
+    free(elite);
+    free(idx);
+    return rc;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Iterated SPVAR (Sec. II.B: ISPVAR): sample, fix, continue on the        */
+/* reduced problem; fixes are never undone.  Round r uses seed + r.        */
+/*   fixed_mask/fixed_val [n]: cumulative fixes in original indices.       */
+/*   round_info [rounds][4]: n_free after the round, cumulative offset,    */
+/*     best full-problem energy of the round's sample, variables fixed in  */
+/*     the round.  Returns the number of rounds run (>= 0) or an error.    */
+/* ---------------------------------------------------------------------- */
+int orc_ispvar(const orc_problem *P, const double *betas, int32_t sweeps, int32_t reads,
+               uint64_t seed, int32_t rounds, double elite_frac, double threshold, int32_t gauge,
+               uint8_t *fixed_mask, int8_t *fixed_val, int64_t *round_info)
+{
+    int32_t n = P->n, nnz = P->row_ptr[n], rd, i, ran = 0;
+    int32_t *rp[2], *cl[2], *jv[2], *hv[2], *orig_cur, *orig_new, *orig_tmp;
+    uint8_t *co[2], *fm;
+    int8_t *fv, *spins;
+    int64_t *E, info[8], offset_total = 0;
+    orc_problem cur;
+    int rc = ORC_OK, b;
+    for (b = 0; b < 2; ++b) {
+        rp[b] = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n + 1));
+        cl[b] = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+        jv[b] = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+        hv[b] = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+        co[b] = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
+    }
+    orig_cur = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    orig_new = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    fm = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
+    fv = (int8_t *)malloc((size_t)(n > 0 ? n : 1));
+    spins = (int8_t *)malloc((size_t)reads * (n > 0 ? n : 1));
+    E = (int64_t *)malloc(sizeof(int64_t) * (size_t)(reads > 0 ? reads : 1));
+    if (!orig_cur || !orig_new || !fm || !fv || !spins || !E) {
+        rc = ORC_ENOMEM;
+        goto done;
+    }
+    for (b = 0; b < 2; ++b)
+        if (!rp[b] || !cl[b] || !jv[b] || !hv[b] || !co[b]) {
+            rc = ORC_ENOMEM;
+            goto done;
+        }
+    memcpy(rp[0], P->row_ptr, sizeof(int32_t) * (size_t)(n + 1));
+    memcpy(cl[0], P->col, sizeof(int32_t) * (size_t)nnz);
+    memcpy(jv[0], P->J, sizeof(int32_t) * (size_t)nnz);
+    memcpy(hv[0], P->h, sizeof(int32_t) * (size_t)n);
+    memcpy(co[0], P->colour, (size_t)n);
+    for (i = 0; i < n; ++i) {
+        orig_cur[i] = i;
+        fixed_mask[i] = 0;
+        fixed_val[i] = 0;
+    }
+    cur = *P;
+    b = 0;
+    for (rd = 0; rd < rounds; ++rd) {
+        int64_t best = INT64_MAX;
+        int32_t r;
+        cur.row_ptr = rp[b];
+        cur.col = cl[b];
+        cur.J = jv[b];
+        cur.h = hv[b];
+        cur.colour = co[b];
+        if (cur.n == 0)
+            break;
+        rc = orc_sa_sample(&cur, betas, sweeps, seed + (uint64_t)rd, 0, 0, reads, NULL, NULL,
+                           spins, E);
+        if (rc)
+            goto done;
+        for (r = 0; r < reads; ++r)
+            if (E[r] < best)
+                best = E[r];
+        rc = orc_persist_fix(&cur, spins, E, reads, elite_frac, threshold, gauge, fm, fv,
+                             rp[1 - b], cl[1 - b], jv[1 - b], hv[1 - b], co[1 - b], orig_new, info);
+        if (rc)
+            goto done;
+        for (i = 0; i < cur.n; ++i)
+            if (fm[i]) {
+                fixed_mask[orig_cur[i]] = 1;
+                fixed_val[orig_cur[i]] = fv[i];
+            }
+        for (i = 0; i < (int32_t)info[0]; ++i)
+            orig_new[i] = orig_cur[orig_new[i]];
+        orig_tmp = orig_cur;
+        orig_cur = orig_new;
+        orig_new = orig_tmp;
+        round_info[rd * 4 + 0] = info[0];
+        round_info[rd * 4 + 2] = best + offset_total;
+        offset_total += info[2];
+        round_info[rd * 4 + 1] = offset_total;
+        round_info[rd * 4 + 3] = info[3];
+        cur.n = (int32_t)info[0];
+        b = 1 - b;
+        ran = rd + 1;
+    }
+    rc = ran;
+done:
+    for (b = 0; b < 2; ++b) {
+        free(rp[b]);
+        free(cl[b]);
+        free(jv[b]);
+        free(hv[b]);
+        free(co[b]);
+    }
+    free(orig_cur);
+    free(orig_new);
+    free(fm);
+    free(fv);
+    free(spins);
+    free(E);
+    return rc;
+}

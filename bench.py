@@ -1,0 +1,136 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the sample-persistence hot path on one MI355X.
+
+One step = one full pass of the path over one batch of synthetic input:
+spv_sample (Metropolis simulated annealing, 10,000 reads x 2,000 sweeps on the
+Chimera 8x8 instance, N = 512) followed by spv_persist_fix (elite 5 %,
+threshold 0.95).  Inputs are resident in device memory before timing starts.
+
+Prints ONE JSON line.  `value` is spin-updates/s of the whole step
+(reads x n x sweeps / step time).  The roofline object covers the dominant
+kernel (the SA sweep), timed with events on the stream it runs on.  The
+cpu_baseline object times the CPU oracle on a bounded sample of the same
+workload (a subset of reads, all sweeps).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+BASELINE_METRIC = "spin-updates/s (batched vs plain, bit-exact); SPVAR solves/s; p50/p99 latency"
+
+# VALU lane-slots per Metropolis update on the Chimera workload (single-digit
+# threshold test): local field over the mean degree (one conditional add per
+# coupler), 4 slots for x = -s f / sign test / threshold compare / flip, and a
+# quarter of one Philox4x32-10 block (10 rounds of two 32x32->64 products at a
+# quarter of the full rate, i.e. 4 slots each, plus two 3-input xors).
+PHILOX_SLOTS = 10 * (2 * 4 + 2)
+PEAK_VALU_TSLOTS = 256 * 64 * 2.4e9 / 1e12  # 256 CUs x 64 lanes x 2.4 GHz = 39.32 T lane-slots/s
+
+
+def slots_per_update(mean_degree):
+    return mean_degree + 4 + PHILOX_SLOTS / 4.0
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-reads", type=int, default=0, help="oracle reads (0 = 16 per thread)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (single-GPU build)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1706_07826_amd as spv
+    from spvar_inputs import configs as cf
+
+    cfg = cf.CHIMERA8_SA
+    inst = cf.instance(cfg)
+    betas = cf.betas(cfg)
+    reads, sweeps, n = cfg["reads"], cfg["sweeps"], inst.n
+    updates = reads * n * sweeps
+
+    ctx = spv.Context(0)
+    P = spv.Problem.from_instance(inst)
+    spv.spv_problem_check(ctx, P)
+    stream = torch.cuda.current_stream()
+    spins = torch.empty((reads, n), dtype=torch.int8, device="cuda")
+    energies = torch.empty(reads, dtype=torch.int64, device="cuda")
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        spv.spv_sample(ctx, P, betas, reads, cfg["seed"], spins=spins, energies=energies)
+        if ev is not None:
+            ev[1].record(stream)
+        return spv.spv_persist_fix(ctx, P, spins, energies, cfg["elite"], cfg["theta"], cfg["gauge"])
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    last = None
+    for k in range(args.steps):
+        last = step(events[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    info = last.info()
+    ms_step = wall * 1e3 / args.steps
+    sa_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
+    value = updates / (ms_step / 1e3)
+
+    mean_deg = inst.nnz / inst.n
+    spu = slots_per_update(mean_deg)
+    achieved = updates * spu / (sa_ms / 1e3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_VALU_TSLOTS, 3),
+                "unit": "Tslot/s", "frac": round(achieved / PEAK_VALU_TSLOTS, 4), "traffic": None,
+                "kernel": "sa_kernel<1>", "kernel_ms": round(sa_ms, 4),
+                "slots_per_update": round(spu, 3)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = max(1, min(16, os.cpu_count() or 1))
+        cpu_reads = args.cpu_reads or 16 * threads
+        t1 = time.perf_counter()
+        oracle.sa_sample(inst, betas, seed=cfg["seed"], r_begin=0, r_end=cpu_reads, threads=threads)
+        dt = time.perf_counter() - t1
+        cpu = {"value": round(cpu_reads * n * sweeps / dt, 1), "unit": "spin-updates/s",
+               "cores": threads, "kind": "oracle",
+               "sample": f"reads 0..{cpu_reads - 1} of {reads} (all {sweeps} sweeps), "
+                         f"{threads} threads, {dt:.1f} s wall"}
+
+    out = {
+        "metric": BASELINE_METRIC, "value": round(value, 1), "unit": "spin-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic (seeded Chimera U{+-1..+-6} instance; no paper instances available)",
+        "config": {"workload": "chimera8_sa: Chimera 8x8 K4,4, N=512, couplers/biases "
+                               "U{+-1..+-6}; SA 10000 reads x 2000 sweeps, beta 0.1->5.0; "
+                               "persistence elite 0.05, threshold 0.95",
+                   "reads": reads, "sweeps": sweeps, "n": n, "parallelism": "single GPU"},
+        "spvar_solves_per_s": round(1e3 / ms_step, 3),
+        "fixed_per_solve": info["n_fixed"],
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

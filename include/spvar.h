@@ -1,0 +1,250 @@
+/*
+ * spvar.h -- C ABI of the MI355X sample-persistence library (libspvar.so).
+ *
+ * The library implements the hot path of multi-start sample-persistence
+ * variable reduction (SPVAR; Sec. II, Algorithms 1 and 2 of the paper):
+ *   - the Monte Carlo samplers the method calls over and over: Metropolis
+ *     simulated annealing and parallel tempering with isoenergetic
+ *     (Houdayer) cluster moves (Sec. III.A, Sec. III.D.1), and
+ *   - the persistence step: elite selection, per-variable agreement,
+ *     fixing, and reduction of the Ising problem to (J', h', offset)
+ *     (Algorithm 1; the zero-bias handling of Sec. II.C).
+ *
+ * Problem (Sec. I): minimise E(s) = sum_{i<j} J_ij s_i s_j + sum_i h_i s_i
+ * over s in {-1,+1}^n, with integer couplers and biases; the real value of an
+ * integer quantity q is q / 2^scale_log2.  Each undirected coupler is stored
+ * twice in a symmetric CSR and counted once in E.
+ *
+ * Conventions
+ *   - Pointers marked "device" are HIP device pointers on the context's
+ *     device; "host" pointers are ordinary CPU memory.  Every output buffer
+ *     is owned by the caller; the library never returns memory.  Scratch
+ *     memory belongs to the context (allocated on first use, grown on
+ *     demand, freed by spv_ctx_destroy).
+ *   - Calls that take a stream enqueue work on it and return without waiting
+ *     unless stated otherwise; host arguments are consumed before return.
+ *   - Every function returns an spv_status; negative values are errors and a
+ *     message is available from spv_last_error().  No exception crosses the
+ *     ABI.  A context is not thread-safe: use one context per host thread.
+ *   - Results depend only on the inputs and the seed, never on the stream,
+ *     launch shape or batch composition (counter-based randomness).
+ *
+ * Random numbers: Philox4x32-10 (Salmon et al., SC'11) with key
+ * (seed & 0xffffffff, seed >> 32) and counters
+ *   Metropolis digit j of (spin i, sweep t, replica r): (i, t, r>>2, 2<<24|j), word r&3
+ *   initial spin i of replica r: (i, 0, r>>2, 1<<24), word r&3, +1 iff bit 31 set
+ *   replica exchange (k,k+1) of chain-run c at sweep t, digit j: (k, t, c, 3<<24|j>>2), word j&3
+ *   cluster move at slot k of run u at sweep t: (k, t, u, 4<<24), word 0
+ *
+ * Metropolis acceptance: x = -s_i f_i with f_i = h_i + sum_j J_ij s_j (the
+ * flip changes E by 2x).  x <= 0 flips; otherwise, with x = sum_j d_j 512^j,
+ * the flip is accepted iff every nonzero digit passes w_j < T_j[d_j],
+ * T_j[d] = min(2^32-1, floor(2^32 exp(-(beta * (2 d 512^j)) / 2^scale_log2))),
+ * tables built once per beta on the host in double precision.
+ */
+#ifndef SPVAR_H
+#define SPVAR_H
+
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SPV_OK = 0,
+    SPV_EINVAL = -1,     /* malformed argument */
+    SPV_EASYM = -2,      /* CSR is not symmetric / sorted / loop-free */
+    SPV_ECOLOUR = -3,    /* an edge joins two variables of one colour class */
+    SPV_ERANGE = -4,     /* a value exceeds a representable range */
+    SPV_ECAPACITY = -5,  /* instance or batch does not fit the device layout */
+    SPV_EBUDGET = -6,    /* request exceeds the serving budget */
+    SPV_EDEVICE = -7,    /* HIP runtime error */
+    SPV_EAGAIN = -8,     /* try again (queue full / result pending) */
+    SPV_ENOMEM = -9,     /* allocation failed */
+    SPV_EINTERNAL = -10  /* internal consistency check failed */
+} spv_status;
+
+typedef struct spv_ctx spv_ctx;
+
+/*
+ * An Ising instance (Sec. I) resident in device memory.
+ *   n, nnz          host: variables and stored CSR entries (2 x couplers)
+ *   row_ptr [n+1]   device: row_ptr[0] = 0, row_ptr[n] = nnz
+ *   col [nnz]       device: strictly increasing per row, no self loops
+ *   J [nnz]         device: int32, symmetric (J(i,j) == J(j,i)), |J| <= 32767
+ *   h [n]           device: int32 biases
+ *   colour [n]      device: colour class of each variable; no edge joins
+ *                   two variables of one class (sweeps go class by class)
+ *   n_colours       host: 1..16
+ *   scale_log2      host: 0..30, real value = integer / 2^scale_log2
+ *   max_degree      host: >= every row length (1..64)
+ *   x_bound         host: >= max_i (|h_i| + sum_j |J_ij|), < 2^26
+ * The host fields are trusted by the sampling calls; spv_problem_check()
+ * verifies all of them.  Kernels clamp every index, so a malformed instance
+ * yields wrong numbers but never an out-of-bounds access.
+ */
+typedef struct {
+    int32_t n;
+    int32_t nnz;
+    const int32_t *row_ptr;
+    const int32_t *col;
+    const int32_t *J;
+    const int32_t *h;
+    const uint8_t *colour;
+    int32_t n_colours;
+    int32_t scale_log2;
+    int32_t max_degree;
+    int32_t x_bound;
+} spv_problem;
+
+/* Context on HIP device `device`.  *out receives the handle. */
+spv_status spv_ctx_create(int32_t device, spv_ctx **out);
+void spv_ctx_destroy(spv_ctx *ctx);
+/* Message of the last failing call on this context ("" if none). */
+const char *spv_last_error(const spv_ctx *ctx);
+/* Library version string. */
+const char *spv_version(void);
+
+/*
+ * Full validation of a problem (synchronous: copies it to the host).
+ * Checks symmetry, sortedness, self loops, |J| <= 32767, colouring,
+ * max_degree and x_bound.  Returns SPV_OK or the first violation.
+ */
+spv_status spv_problem_check(spv_ctx *ctx, const spv_problem *P);
+
+/*
+ * Simulated annealing (Sec. III.A sampler; one Metropolis sweep per beta).
+ *   betas [sweeps]   host: inverse temperatures, >= 0 and finite
+ *   reads            independent replicas r = 0..reads-1
+ *   seed             Philox key
+ *   sweep_offset     global index of the first sweep (resume support)
+ *   init_spins       device [reads][n] int8 +-1 initial states, or NULL for
+ *                    the Philox initial state
+ *   spins            device [reads][n] int8: final state of each read
+ *   energies         device [reads] int64: E of each final state
+ * The sample is the final state of every read (not the best seen).
+ */
+spv_status spv_sample(spv_ctx *ctx, const spv_problem *P, const double *betas, int32_t sweeps,
+                      int32_t reads, uint64_t seed, uint32_t sweep_offset,
+                      const int8_t *init_spins, int8_t *spins, int64_t *energies,
+                      hipStream_t stream);
+
+/* E(s) of R states: spins device [R][n] int8 +-1 -> energies device [R] int64. */
+spv_status spv_energy(spv_ctx *ctx, const spv_problem *P, const int8_t *spins, int32_t R,
+                      int64_t *energies, hipStream_t stream);
+
+/*
+ * Outputs of the persistence step.  All device pointers; the reduced CSR
+ * buffers must hold P->n rows / P->nnz entries (outputs never exceed them).
+ *   fixed_mask [n]  1 where the variable was fixed
+ *   fixed_val  [n]  its value (+-1), 0 where free
+ *   row_ptr [n+1], col [nnz], J [nnz], h [n], colour [n]: reduced problem
+ *                   over the free variables, renumbered in index order
+ *   orig_index [n]  reduced variable u -> original variable
+ *   info [8]        int64: n_free, nnz_free, offset, n_fixed, pivot (-1 when
+ *                   the gauge was not applied), m, k_min, status (0, or a
+ *                   negative spv_status detected on the device: SPV_EINVAL
+ *                   for a sample entry other than +-1, SPV_ERANGE for an h'
+ *                   outside int32, SPV_EINTERNAL for an unresolved gauge hash)
+ */
+typedef struct {
+    uint8_t *fixed_mask;
+    int8_t *fixed_val;
+    int32_t *row_ptr;
+    int32_t *col;
+    int32_t *J;
+    int32_t *h;
+    uint8_t *colour;
+    int32_t *orig_index;
+    int64_t *info;
+} spv_fix_out;
+
+/*
+ * Persistence and reduction (Algorithm 1: "Narrow down solutions to
+ * elite_threshold percentile", "Find mean value of each variable",
+ * "Fix variables ...", "Update J and h").
+ *   samples [R][n]  device int8 +-1, energies [R] device int64
+ *   elite_frac      (0, 1]: m = max(1, ceil(elite_frac * R)) rows with the
+ *                   lowest (E, row index)
+ *   threshold       (0, 1]: fix i iff |sum_elite s_ri| >= ceil(threshold*m),
+ *                   to its sign
+ *   gauge           0 off, 1 on, 2 on iff every h_i == 0 (zero-bias
+ *                   handling, Sec. II.C): variables whose elite columns are
+ *                   equal up to a global sign form classes; the pivot is the
+ *                   lowest index of the largest class (ties: lower minimum
+ *                   index); every elite row is multiplied by its pivot value
+ *                   before counting, so the pivot's class is fixed.
+ * Reduction: h'_u = h_u + sum_{j fixed} J_uj v_j, offset = sum_{i<j fixed}
+ * J_ij v_i v_j + sum_{i fixed} h_i v_i, so E(s) = E'(s_U) + offset.
+ * Asynchronous: info becomes valid when the stream reaches this point.
+ */
+spv_status spv_persist_fix(spv_ctx *ctx, const spv_problem *P, const int8_t *samples,
+                           const int64_t *energies, int32_t R, double elite_frac,
+                           double threshold, int32_t gauge, const spv_fix_out *out,
+                           hipStream_t stream);
+
+/*
+ * Iterated SPVAR (Sec. II.B "ISPVAR"): `rounds` rounds of spv_sample
+ * (round r uses seed + r) followed by spv_persist_fix on the current reduced
+ * problem; fixes are never undone; stops early when nothing is left.
+ * Synchronous (the host needs each round's reduced size).
+ *   fixed_mask, fixed_val  device [n]: cumulative fixes, original indices
+ *   round_info             host [rounds][4] int64: n_free after the round,
+ *                          cumulative offset, best full-problem energy of the
+ *                          round's sample (E' + offsets so far), variables
+ *                          fixed in the round
+ *   rounds_run             host: number of rounds executed
+ */
+spv_status spv_ispvar(spv_ctx *ctx, const spv_problem *P, const double *betas, int32_t sweeps,
+                      int32_t reads, uint64_t seed, int32_t rounds, double elite_frac,
+                      double threshold, int32_t gauge, uint8_t *fixed_mask, int8_t *fixed_val,
+                      int64_t *round_info, int32_t *rounds_run, hipStream_t stream);
+
+/*
+ * Parallel tempering (Sec. III.D.1 "PTICM").  Each run holds `chains`
+ * ladders of K slots (betas ascending).  One sweep = Metropolis on every
+ * slot; replica exchange of pairs (k,k+1) with k = t (mod 2) in each chain
+ * (D = E_k - E_{k+1}; D <= 0 swaps, else the digit test of D with tables of
+ * dbeta = beta_{k+1} - beta_k); Houdayer cluster moves between chains 0 and
+ * 1 at slots icm_lo..icm_hi-1 (chains == 2); then the colder half
+ * (k >= K/2) is offered to per-slot lists of the 10 lowest-energy distinct
+ * states seen (Sec. III.D.1 sample formation).
+ * Replica index r = (run * chains + chain) * K + slot (keyed by slot, so the
+ * random stream follows the temperature).
+ */
+typedef struct {
+    int32_t K;
+    int32_t runs;
+    int32_t chains;
+    int32_t sweeps;
+    const double *betas; /* host [K], ascending */
+    uint64_t seed;
+    uint32_t sweep_offset;
+    int32_t icm_lo;
+    int32_t icm_hi;
+} spv_pt_params;
+
+/* Any member may be NULL when not wanted.  All device pointers.
+ *   final_spins [runs][chains][K][n], final_E [runs][chains][K]
+ *   top_spins [runs][chains][K/2][10][n], top_E [..][10] (unfilled entries:
+ *   E = INT64_MAX, spins 0), top_count [runs][chains][K/2]
+ *   Entries of a list are ordered by (E, insertion). */
+typedef struct {
+    int8_t *final_spins;
+    int64_t *final_E;
+    int8_t *top_spins;
+    int64_t *top_E;
+    int32_t *top_count;
+} spv_pt_out;
+
+spv_status spv_pt_sample(spv_ctx *ctx, const spv_problem *P, const spv_pt_params *params,
+                         const spv_pt_out *out, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPVAR_H */

@@ -1,0 +1,299 @@
+"""Python binding of libspvar.so, the MI355X sample-persistence library.
+
+Argument marshalling only: every step of the sampling and persistence path runs
+in the library's HIP kernels.  PyTorch provides device memory and streams.  The
+function names follow the C ABI in ``include/spvar.h``.  Importing this module
+fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspvar.so")
+
+SPV_STATUS = {0: "SPV_OK", -1: "SPV_EINVAL", -2: "SPV_EASYM", -3: "SPV_ECOLOUR", -4: "SPV_ERANGE",
+              -5: "SPV_ECAPACITY", -6: "SPV_EBUDGET", -7: "SPV_EDEVICE", -8: "SPV_EAGAIN",
+              -9: "SPV_ENOMEM", -10: "SPV_EINTERNAL"}
+TOPK = 10
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; g.build()'` "
+                      "(hipcc --offload-arch=gfx950) first")
+
+
+class SpvError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{SPV_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class spv_problem(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nnz", C.c_int32), ("row_ptr", C.c_void_p),
+                ("col", C.c_void_p), ("J", C.c_void_p), ("h", C.c_void_p),
+                ("colour", C.c_void_p), ("n_colours", C.c_int32), ("scale_log2", C.c_int32),
+                ("max_degree", C.c_int32), ("x_bound", C.c_int32)]
+
+
+class spv_fix_out(C.Structure):
+    _fields_ = [("fixed_mask", C.c_void_p), ("fixed_val", C.c_void_p), ("row_ptr", C.c_void_p),
+                ("col", C.c_void_p), ("J", C.c_void_p), ("h", C.c_void_p),
+                ("colour", C.c_void_p), ("orig_index", C.c_void_p), ("info", C.c_void_p)]
+
+
+class spv_pt_params(C.Structure):
+    _fields_ = [("K", C.c_int32), ("runs", C.c_int32), ("chains", C.c_int32),
+                ("sweeps", C.c_int32), ("betas", C.c_void_p), ("seed", C.c_uint64),
+                ("sweep_offset", C.c_uint32), ("icm_lo", C.c_int32), ("icm_hi", C.c_int32)]
+
+
+class spv_pt_out(C.Structure):
+    _fields_ = [("final_spins", C.c_void_p), ("final_E", C.c_void_p), ("top_spins", C.c_void_p),
+                ("top_E", C.c_void_p), ("top_count", C.c_void_p)]
+
+
+_lib = C.CDLL(LIB_PATH)
+_vp, _i32, _u32, _u64, _f64 = C.c_void_p, C.c_int32, C.c_uint32, C.c_uint64, C.c_double
+_P = C.POINTER(spv_problem)
+_SIGS = {
+    "spv_version": ([], C.c_char_p),
+    "spv_ctx_create": ([_i32, C.POINTER(_vp)], C.c_int),
+    "spv_ctx_destroy": ([_vp], None),
+    "spv_last_error": ([_vp], C.c_char_p),
+    "spv_problem_check": ([_vp, _P], C.c_int),
+    "spv_sample": ([_vp, _P, _vp, _i32, _i32, _u64, _u32, _vp, _vp, _vp, _vp], C.c_int),
+    "spv_energy": ([_vp, _P, _vp, _i32, _vp, _vp], C.c_int),
+    "spv_persist_fix": ([_vp, _P, _vp, _vp, _i32, _f64, _f64, _i32, C.POINTER(spv_fix_out), _vp],
+                        C.c_int),
+    "spv_ispvar": ([_vp, _P, _vp, _i32, _i32, _u64, _i32, _f64, _f64, _i32, _vp, _vp, _vp, _vp, _vp],
+                   C.c_int),
+    "spv_pt_sample": ([_vp, _P, C.POINTER(spv_pt_params), C.POINTER(spv_pt_out), _vp], C.c_int),
+}
+EXPORTED = sorted(_SIGS)
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data_as(C.c_void_p)
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def spv_version():
+    return _lib.spv_version().decode()
+
+
+class Context:
+    """An spv_ctx on one HIP device (scratch memory and table cache)."""
+
+    def __init__(self, device=0):
+        h = C.c_void_p()
+        rc = _lib.spv_ctx_create(int(device), C.byref(h))
+        if rc != 0:
+            raise SpvError(rc, f"spv_ctx_create({device})")
+        self.handle = h
+        self.device = torch.device("cuda", device)
+
+    def check(self, rc, what):
+        if rc != 0:
+            raise SpvError(rc, f"{what}: {_lib.spv_last_error(self.handle).decode()}")
+
+    def close(self):
+        if self.handle:
+            _lib.spv_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def spv_ctx_create(device=0):
+    return Context(device)
+
+
+class Problem:
+    """An Ising instance resident on the device (CSR + colouring) with its host metadata."""
+
+    def __init__(self, n, nnz, row_ptr, col, J, h, colour, n_colours, scale_log2, max_degree,
+                 x_bound):
+        self.n, self.nnz = int(n), int(nnz)
+        self.row_ptr, self.col, self.J, self.h, self.colour = row_ptr, col, J, h, colour
+        self.n_colours, self.scale_log2 = int(n_colours), int(scale_log2)
+        self.max_degree, self.x_bound = int(max_degree), int(x_bound)
+
+    @classmethod
+    def from_instance(cls, inst, device="cuda"):
+        rp = np.asarray(inst.row_ptr, np.int32)
+        deg = np.diff(rp)
+        rows = np.repeat(np.arange(inst.n), deg)
+        absJ = np.zeros(inst.n, np.int64)
+        np.add.at(absJ, rows, np.abs(np.asarray(inst.J, np.int64)))
+        xb = int((np.abs(np.asarray(inst.h, np.int64)) + absJ).max()) if inst.n else 0
+        t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a, dtype=dt)).to(device)
+        return cls(inst.n, int(rp[-1]), t(rp, np.int32), t(inst.col, np.int32),
+                   t(inst.J, np.int32), t(inst.h, np.int32), t(inst.colour, np.uint8),
+                   inst.n_colours, inst.scale_log2, max(1, int(deg.max()) if inst.n else 1), xb)
+
+    def c_struct(self):
+        return spv_problem(self.n, self.nnz, self.row_ptr.data_ptr(),
+                           self.col.data_ptr() if self.nnz else None,
+                           self.J.data_ptr() if self.nnz else None,
+                           self.h.data_ptr() if self.n else None,
+                           self.colour.data_ptr() if self.n else None, self.n_colours,
+                           self.scale_log2, self.max_degree, self.x_bound)
+
+    def to_host(self):
+        """numpy copy (row_ptr, col, J, h, colour) for inspection and tests."""
+        return dict(n=self.n, row_ptr=self.row_ptr.cpu().numpy(), col=self.col[:self.nnz].cpu().numpy(),
+                    J=self.J[:self.nnz].cpu().numpy(), h=self.h[:self.n].cpu().numpy(),
+                    colour=self.colour[:self.n].cpu().numpy(), n_colours=self.n_colours,
+                    scale_log2=self.scale_log2)
+
+
+def spv_problem_check(ctx, P):
+    ps = P.c_struct()
+    ctx.check(_lib.spv_problem_check(ctx.handle, C.byref(ps)), "spv_problem_check")
+
+
+def spv_sample(ctx, P, betas, reads, seed, sweep_offset=0, init_spins=None, spins=None,
+               energies=None, stream=None):
+    """Simulated annealing; returns (spins int8 [reads][n], energies int64 [reads]) on the device."""
+    b = np.ascontiguousarray(betas, dtype=np.float64)
+    if spins is None:
+        spins = torch.empty((reads, P.n), dtype=torch.int8, device=ctx.device)
+    if energies is None:
+        energies = torch.empty(reads, dtype=torch.int64, device=ctx.device)
+    ps = P.c_struct()
+    rc = _lib.spv_sample(ctx.handle, C.byref(ps), _ptr(b), b.size, int(reads),
+                         C.c_uint64(seed & (2**64 - 1)), int(sweep_offset),
+                         _ptr(init_spins), _ptr(spins) if P.n else None, _ptr(energies),
+                         _stream(stream))
+    ctx.check(rc, "spv_sample")
+    return spins, energies
+
+
+def spv_energy(ctx, P, spins, energies=None, stream=None):
+    R = spins.shape[0]
+    if energies is None:
+        energies = torch.empty(R, dtype=torch.int64, device=ctx.device)
+    ps = P.c_struct()
+    ctx.check(_lib.spv_energy(ctx.handle, C.byref(ps), _ptr(spins), R, _ptr(energies),
+                              _stream(stream)), "spv_energy")
+    return energies
+
+
+class FixResult:
+    """Device outputs of spv_persist_fix; `info()` synchronises and reads the scalars."""
+
+    def __init__(self, ctx, P, out, keep):
+        self.ctx, self.parent, self.out, self._keep = ctx, P, out, keep
+        self.fixed_mask, self.fixed_val = keep["fixed_mask"], keep["fixed_val"]
+        self._info = None
+
+    def info(self):
+        if self._info is None:
+            torch.cuda.synchronize(self.ctx.device)
+            v = self._keep["info"].cpu().numpy()
+            if v[7] != 0:
+                raise SpvError(int(v[7]), "spv_persist_fix device status")
+            self._info = dict(n_free=int(v[0]), nnz_free=int(v[1]), offset=int(v[2]),
+                              n_fixed=int(v[3]), pivot=int(v[4]), m=int(v[5]), k_min=int(v[6]))
+        return self._info
+
+    def reduced(self):
+        """The reduced problem as a device Problem (views into the output buffers)."""
+        i = self.info()
+        k = self._keep
+        P = self.parent
+        return Problem(i["n_free"], i["nnz_free"], k["row_ptr"][:i["n_free"] + 1], k["col"], k["J"],
+                       k["h"], k["colour"], P.n_colours, P.scale_log2, P.max_degree, P.x_bound)
+
+    @property
+    def orig_index(self):
+        return self._keep["orig_index"][:self.info()["n_free"]]
+
+
+def spv_persist_fix(ctx, P, samples, energies, elite_frac, threshold, gauge=0, stream=None):
+    dev = ctx.device
+    n, nnz = P.n, P.nnz
+    keep = dict(fixed_mask=torch.empty(max(n, 1), dtype=torch.uint8, device=dev),
+                fixed_val=torch.empty(max(n, 1), dtype=torch.int8, device=dev),
+                row_ptr=torch.empty(n + 1, dtype=torch.int32, device=dev),
+                col=torch.empty(max(nnz, 1), dtype=torch.int32, device=dev),
+                J=torch.empty(max(nnz, 1), dtype=torch.int32, device=dev),
+                h=torch.empty(max(n, 1), dtype=torch.int32, device=dev),
+                colour=torch.empty(max(n, 1), dtype=torch.uint8, device=dev),
+                orig_index=torch.empty(max(n, 1), dtype=torch.int32, device=dev),
+                info=torch.zeros(8, dtype=torch.int64, device=dev))
+    out = spv_fix_out(*[keep[k].data_ptr() for k in ("fixed_mask", "fixed_val", "row_ptr", "col", "J",
+                                                     "h", "colour", "orig_index", "info")])
+    ps = P.c_struct()
+    rc = _lib.spv_persist_fix(ctx.handle, C.byref(ps), _ptr(samples) if n else None, _ptr(energies),
+                              int(energies.shape[0]), float(elite_frac), float(threshold), int(gauge),
+                              C.byref(out), _stream(stream))
+    ctx.check(rc, "spv_persist_fix")
+    keep["fixed_mask"] = keep["fixed_mask"][:n]
+    keep["fixed_val"] = keep["fixed_val"][:n]
+    return FixResult(ctx, P, out, keep)
+
+
+def spv_ispvar(ctx, P, betas, reads, seed, rounds, elite_frac, threshold, gauge=2, stream=None):
+    """Iterated SPVAR rounds (synchronous).  Returns fixed_mask, fixed_val (device) and
+    round_info (host int64 [rounds_run][4])."""
+    b = np.ascontiguousarray(betas, dtype=np.float64)
+    fm = torch.empty(max(P.n, 1), dtype=torch.uint8, device=ctx.device)
+    fv = torch.empty(max(P.n, 1), dtype=torch.int8, device=ctx.device)
+    info = np.zeros((max(rounds, 1), 4), np.int64)
+    ran = C.c_int32(0)
+    ps = P.c_struct()
+    rc = _lib.spv_ispvar(ctx.handle, C.byref(ps), _ptr(b), b.size, int(reads),
+                         C.c_uint64(seed & (2**64 - 1)), int(rounds), float(elite_frac),
+                         float(threshold), int(gauge), _ptr(fm), _ptr(fv), _ptr(info), C.byref(ran),
+                         _stream(stream))
+    ctx.check(rc, "spv_ispvar")
+    return dict(fixed_mask=fm[:P.n], fixed_val=fv[:P.n], rounds_run=ran.value,
+                round_info=info[:ran.value])
+
+
+def spv_pt_sample(ctx, P, betas, runs, chains, sweeps, seed, sweep_offset=0, icm=None, final=True,
+                  top=True, stream=None):
+    """Parallel tempering (+ Houdayer moves between chains 0 and 1 at slots icm=(lo, hi)).
+    Returns a dict of device tensors: final_spins [runs][chains][K][n], final_E, top_spins
+    [runs][chains][K/2][10][n], top_E, top_count."""
+    b = np.ascontiguousarray(betas, dtype=np.float64)
+    K = b.size
+    half = K // 2
+    dev = ctx.device
+    n = P.n
+    res = dict(
+        final_spins=torch.empty((runs, chains, K, n), dtype=torch.int8, device=dev) if final else None,
+        final_E=torch.empty((runs, chains, K), dtype=torch.int64, device=dev) if final else None,
+        top_spins=torch.empty((runs, chains, half, TOPK, n), dtype=torch.int8, device=dev) if top else None,
+        top_E=torch.empty((runs, chains, half, TOPK), dtype=torch.int64, device=dev) if top else None,
+        top_count=torch.empty((runs, chains, half), dtype=torch.int32, device=dev) if top else None)
+    lo, hi = (0, 0) if icm is None else icm
+    params = spv_pt_params(K, runs, chains, sweeps, b.ctypes.data, C.c_uint64(seed & (2**64 - 1)),
+                           int(sweep_offset), int(lo), int(hi))
+    out = spv_pt_out(*[(_ptr(res[k]).value if res[k] is not None and res[k].numel() else None)
+                       for k in ("final_spins", "final_E", "top_spins", "top_E", "top_count")])
+    ps = P.c_struct()
+    ctx.check(_lib.spv_pt_sample(ctx.handle, C.byref(ps), C.byref(params), C.byref(out),
+                                 _stream(stream)), "spv_pt_sample")
+    return res

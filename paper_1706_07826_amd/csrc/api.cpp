@@ -1,0 +1,486 @@
+// C ABI of libspvar: argument validation, context scratch, acceptance tables,
+// launch-shape selection and the iterated-SPVAR host loop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.hpp"
+
+struct spv_ctx {
+    spv::Ctx c;
+};
+
+namespace spv {
+
+spv_status set_err(Ctx *c, spv_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return st;
+}
+
+spv_status hip_check(Ctx *c, hipError_t e, const char *what) {
+    if (e == hipSuccess) return SPV_OK;
+    return set_err(c, SPV_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+spv_status ensure(Ctx *c, DevBuf &b, size_t bytes) {
+    if (bytes == 0) bytes = 8;
+    if (b.bytes >= bytes) return SPV_OK;
+    // Growing scratch that earlier work may still read: drain the device first.
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_check(c, e, "hipDeviceSynchronize");
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+    size_t want = bytes + bytes / 4;
+    e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) return set_err(c, SPV_ENOMEM, "hipMalloc(%zu): %s", want, hipGetErrorString(e));
+    b.bytes = want;
+    return SPV_OK;
+}
+
+int digits_for(int64_t x_bound) {
+    int nd = 1;
+    while (nd < 7 && (x_bound >> (kDigitBits * nd)) != 0) ++nd;
+    return nd;
+}
+
+// T_j[d] = min(2^32-1, floor(2^32 exp(-(beta * (unit d 512^j)) / 2^scale))), evaluated as
+// one double multiply, an exact power-of-two scaling, exp and an exact 2^32 scaling.
+uint32_t threshold_word(double beta, int64_t unit, int scale_log2, int digit, uint32_t d) {
+    const int64_t steps = unit * (int64_t)d * ((int64_t)1 << (kDigitBits * digit));
+    const double energy_units = (double)steps;
+    const double arg = std::ldexp(beta * energy_units, -scale_log2);
+    const double v = std::exp(-arg) * 4294967296.0;
+    if (v >= 4294967295.0) return 0xFFFFFFFFu;
+    return (uint32_t)std::floor(v);
+}
+
+int swap_digits(double dbeta, int scale_log2) {
+    for (int nd = 1; nd < 7; ++nd)
+        if (threshold_word(dbeta, 1, scale_log2, nd, 1) == 0u) return nd;
+    return 7;
+}
+
+}  // namespace spv
+
+using namespace spv;
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+        else prev = -1;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+spv_status check_problem_host(Ctx *c, const spv_problem *P) {
+    if (!P) return set_err(c, SPV_EINVAL, "problem is NULL");
+    if (P->n < 0 || P->n > kMaxN) return set_err(c, SPV_ECAPACITY, "n=%d outside [0, %d]", P->n, kMaxN);
+    if (P->nnz < 0) return set_err(c, SPV_EINVAL, "nnz=%d < 0", P->nnz);
+    if (P->n_colours < 1 || P->n_colours > kMaxColours)
+        return set_err(c, SPV_EINVAL, "n_colours=%d outside [1, %d]", P->n_colours, kMaxColours);
+    if (P->scale_log2 < 0 || P->scale_log2 > 30)
+        return set_err(c, SPV_EINVAL, "scale_log2=%d outside [0, 30]", P->scale_log2);
+    if (P->x_bound < 0 || P->x_bound >= (1 << 26))
+        return set_err(c, SPV_ERANGE, "x_bound=%d outside [0, 2^26)", P->x_bound);
+    if (P->n > 0) {
+        if (P->max_degree < 1 || P->max_degree > kMaxDegree)
+            return set_err(c, SPV_EINVAL, "max_degree=%d outside [1, %d]", P->max_degree, kMaxDegree);
+        if (!P->row_ptr || !P->h || !P->colour || (P->nnz > 0 && (!P->col || !P->J)))
+            return set_err(c, SPV_EINVAL, "problem array pointer is NULL");
+    }
+    return SPV_OK;
+}
+
+spv_status check_betas(Ctx *c, const double *b, int count) {
+    if (count > 0 && !b) return set_err(c, SPV_EINVAL, "betas is NULL");
+    for (int k = 0; k < count; ++k)
+        if (!(b[k] >= 0.0) || std::isinf(b[k]))
+            return set_err(c, SPV_EINVAL, "beta[%d]=%g is not a finite non-negative number", k, b[k]);
+    return SPV_OK;
+}
+
+// Tables for a list of betas, one row per beta (row_len words).  Cached on the context.
+spv_status upload_tables(Ctx *c, DevBuf &dst, const double *betas, int count, int unit, int scale,
+                         int nd, int row_len, hipStream_t s) {
+    TableCache &tc = c->tcache;
+    const bool hit = &dst == &c->tables && tc.scale == scale && tc.nd == nd && tc.row_len == row_len &&
+                     tc.unit == unit && (int)tc.betas.size() == count &&
+                     (count == 0 || std::memcmp(tc.betas.data(), betas, sizeof(double) * count) == 0);
+    if (hit) return SPV_OK;
+    const size_t words = (size_t)count * row_len;
+    spv_status st = ensure(c, dst, words * 4);
+    if (st) return st;
+    c->host_tables.assign(words, 0u);
+    for (int k = 0; k < count; ++k) {
+        uint32_t *row = c->host_tables.data() + (size_t)k * row_len;
+        for (int j = 0; j < nd; ++j)
+            for (int d = 0; d < kDigitSize && j * kDigitSize + d < row_len; ++d)
+                row[j * kDigitSize + d] = threshold_word(betas[k], unit, scale, j, (uint32_t)d);
+    }
+    // The previous upload may still be in flight on another stream.
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(dst.p, c->host_tables.data(), words * 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_check(c, e, "table upload");
+    (void)s;
+    if (&dst == &c->tables) {
+        tc.betas.assign(betas, betas + count);
+        tc.scale = scale;
+        tc.nd = nd;
+        tc.row_len = row_len;
+        tc.unit = unit;
+    }
+    return SPV_OK;
+}
+
+int sa_threads_env() {
+    const char *v = getenv("SPVAR_SA_THREADS");
+    return v ? atoi(v) : 0;
+}
+int sa_qw_env() {
+    const char *v = getenv("SPVAR_SA_QW");
+    return v ? atoi(v) : 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *spv_version(void) { return "spvar-mi355x 0.1"; }
+
+spv_status spv_ctx_create(int32_t device, spv_ctx **out) {
+    if (!out) return SPV_EINVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return SPV_EDEVICE;
+    spv_ctx *x = new (std::nothrow) spv_ctx();
+    if (!x) return SPV_ENOMEM;
+    x->c.device = device;
+    DeviceGuard g(device);
+    int cus = 0, lds = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) {
+        delete x;
+        return SPV_EDEVICE;
+    }
+    x->c.num_cus = cus;
+    x->c.lds_max = (size_t)lds;
+    *out = x;
+    return SPV_OK;
+}
+
+void spv_ctx_destroy(spv_ctx *ctx) {
+    if (!ctx) return;
+    DeviceGuard g(ctx->c.device);
+    (void)hipDeviceSynchronize();
+    for (DevBuf *b : {&ctx->c.image, &ctx->c.tables, &ctx->c.tables2, &ctx->c.scratch, &ctx->c.scratch2,
+                      &ctx->c.rounds})
+        if (b->p) (void)hipFree(b->p);
+    delete ctx;
+}
+
+const char *spv_last_error(const spv_ctx *ctx) { return ctx ? ctx->c.err.c_str() : "no context"; }
+
+spv_status spv_problem_check(spv_ctx *ctx, const spv_problem *P) {
+    if (!ctx) return SPV_EINVAL;
+    Ctx *c = &ctx->c;
+    DeviceGuard g(c->device);
+    spv_status st = check_problem_host(c, P);
+    if (st) return st;
+    const int n = P->n, nnz = P->nnz;
+    std::vector<int32_t> rp(n + 1), col(nnz), J(nnz), h(n);
+    std::vector<uint8_t> co(n);
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(rp.data(), P->row_ptr, 4ull * (n + 1), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && nnz) e = hipMemcpy(col.data(), P->col, 4ull * nnz, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && nnz) e = hipMemcpy(J.data(), P->J, 4ull * nnz, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && n) e = hipMemcpy(h.data(), P->h, 4ull * n, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && n) e = hipMemcpy(co.data(), P->colour, n, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_check(c, e, "problem copy");
+    if (rp[0] != 0 || rp[n] != nnz) return set_err(c, SPV_EASYM, "row_ptr[0]=%d, row_ptr[n]=%d, nnz=%d", rp[0], rp[n], nnz);
+    long long xmax = 0;
+    for (int i = 0; i < n; ++i) {
+        if (rp[i + 1] < rp[i]) return set_err(c, SPV_EASYM, "row_ptr decreases at row %d", i);
+        if (rp[i + 1] - rp[i] > P->max_degree)
+            return set_err(c, SPV_EINVAL, "row %d has %d entries > max_degree %d", i, rp[i + 1] - rp[i], P->max_degree);
+        if (co[i] >= P->n_colours) return set_err(c, SPV_ECOLOUR, "colour[%d]=%d >= n_colours", i, co[i]);
+        long long x = std::llabs((long long)h[i]);
+        for (int k = rp[i]; k < rp[i + 1]; ++k) {
+            const int j = col[k];
+            if (j < 0 || j >= n) return set_err(c, SPV_EASYM, "col[%d]=%d out of range", k, j);
+            if (j == i) return set_err(c, SPV_EASYM, "self loop at %d", i);
+            if (k > rp[i] && col[k - 1] >= j) return set_err(c, SPV_EASYM, "row %d not strictly increasing", i);
+            if (J[k] > 32767 || J[k] < -32767) return set_err(c, SPV_ERANGE, "|J[%d]|=%d > 32767", k, J[k]);
+            if (co[j] == co[i]) return set_err(c, SPV_ECOLOUR, "edge (%d,%d) inside colour %d", i, j, co[i]);
+            // symmetric partner
+            const int *b = col.data() + rp[j], *en = col.data() + rp[j + 1];
+            const int *f = std::lower_bound(b, en, i);
+            if (f == en || *f != i || J[f - col.data()] != J[k])
+                return set_err(c, SPV_EASYM, "J(%d,%d) has no equal transpose entry", i, j);
+            x += std::llabs((long long)J[k]);
+        }
+        xmax = std::max(xmax, x);
+    }
+    if (xmax > P->x_bound) return set_err(c, SPV_ERANGE, "x_bound=%d < max_i |h_i|+sum|J_ij| = %lld", P->x_bound, xmax);
+    return SPV_OK;
+}
+
+spv_status spv_energy(spv_ctx *ctx, const spv_problem *P, const int8_t *spins, int32_t R,
+                      int64_t *energies, hipStream_t stream) {
+    if (!ctx) return SPV_EINVAL;
+    Ctx *c = &ctx->c;
+    DeviceGuard g(c->device);
+    spv_status st = check_problem_host(c, P);
+    if (st) return st;
+    if (R < 0) return set_err(c, SPV_EINVAL, "R=%d < 0", R);
+    if (R == 0) return SPV_OK;
+    if (!energies || (P->n > 0 && !spins)) return set_err(c, SPV_EINVAL, "NULL spins/energies");
+    if (P->n == 0) return hip_check(c, hipMemsetAsync(energies, 0, 8ull * R, stream), "memset");
+    st = ensure(c, c->image, image_words(P->n, P->max_degree) * 4);
+    if (st) return st;
+    hipError_t e = launch_prep(P, static_cast<int32_t *>(c->image.p), stream);
+    if (e == hipSuccess)
+        e = launch_energy(static_cast<int32_t *>(c->image.p), P->n, P->max_degree, spins, R, energies, stream);
+    return hip_check(c, e, "energy launch");
+}
+
+spv_status spv_sample(spv_ctx *ctx, const spv_problem *P, const double *betas, int32_t sweeps,
+                      int32_t reads, uint64_t seed, uint32_t sweep_offset, const int8_t *init_spins,
+                      int8_t *spins, int64_t *energies, hipStream_t stream) {
+    if (!ctx) return SPV_EINVAL;
+    Ctx *c = &ctx->c;
+    DeviceGuard g(c->device);
+    spv_status st = check_problem_host(c, P);
+    if (st) return st;
+    if (sweeps < 0 || reads < 0) return set_err(c, SPV_EINVAL, "sweeps=%d reads=%d", sweeps, reads);
+    if ((st = check_betas(c, betas, sweeps))) return st;
+    if (reads == 0) return SPV_OK;
+    if (!energies || (P->n > 0 && !spins)) return set_err(c, SPV_EINVAL, "NULL spins/energies");
+    if (P->n == 0) return hip_check(c, hipMemsetAsync(energies, 0, 8ull * reads, stream), "memset");
+    const int n = P->n, D = P->max_degree;
+    const int nd = digits_for(P->x_bound);
+    if (nd > 3) return set_err(c, SPV_ERANGE, "x_bound=%d needs %d digits (max 3)", P->x_bound, nd);
+    const int row_len = nd == 1 ? P->x_bound + 1 : nd * kDigitSize;
+    st = ensure(c, c->image, image_words(n, D) * 4);
+    if (st) return st;
+    hipError_t e = launch_prep(P, static_cast<int32_t *>(c->image.p), stream);
+    if (e != hipSuccess) return hip_check(c, e, "prep launch");
+    if (sweeps > 0) {
+        st = upload_tables(c, c->tables, betas, sweeps, 2, P->scale_log2, nd, row_len, stream);
+        if (st) return st;
+    }
+    SaLaunch L;
+    L.image = static_cast<const int32_t *>(c->image.p);
+    L.n = n;
+    L.D = D;
+    L.C = P->n_colours;
+    L.tables = static_cast<const uint32_t *>(c->tables.p);
+    L.row_len = row_len;
+    L.nd = nd;
+    L.sweeps = sweeps;
+    L.sweep_offset = sweep_offset;
+    L.seed = seed;
+    L.reads = reads;
+    L.init = init_spins;
+    L.out = spins;
+    L.energies = energies;
+    // Launch shape: small workgroups (4 waves) with few quads each, so that
+    // several workgroups share a CU and hide each other's barriers.
+    const int quads = (reads + 3) / 4;
+    int qw = sa_qw_env();
+    if (qw <= 0) qw = quads >= 8 * c->num_cus ? 2 : 1;
+    int threads = sa_threads_env();
+    if (threads <= 0) threads = 256;
+    threads = std::max(64, std::min(1024, threads / qw * qw));
+    while (qw > 1 && sa_lds_bytes(n, D, row_len, qw) + 256 > c->lds_max) --qw;
+    if (sa_lds_bytes(n, D, row_len, qw) + 256 > c->lds_max)
+        return set_err(c, SPV_ECAPACITY, "instance needs %zu B of LDS > %zu", sa_lds_bytes(n, D, row_len, qw), c->lds_max);
+    L.qw = qw;
+    L.threads = threads / qw * qw;
+    e = launch_sa(L, stream, c->lds_max);
+    return hip_check(c, e, "sa launch");
+}
+
+spv_status spv_persist_fix(spv_ctx *ctx, const spv_problem *P, const int8_t *samples,
+                           const int64_t *energies, int32_t R, double elite_frac, double threshold,
+                           int32_t gauge, const spv_fix_out *out, hipStream_t stream) {
+    if (!ctx) return SPV_EINVAL;
+    Ctx *c = &ctx->c;
+    DeviceGuard g(c->device);
+    spv_status st = check_problem_host(c, P);
+    if (st) return st;
+    if (R < 1) return set_err(c, SPV_EINVAL, "R=%d < 1", R);
+    if (!(elite_frac > 0.0 && elite_frac <= 1.0)) return set_err(c, SPV_EINVAL, "elite_frac=%g outside (0,1]", elite_frac);
+    if (!(threshold > 0.0 && threshold <= 1.0)) return set_err(c, SPV_EINVAL, "threshold=%g outside (0,1]", threshold);
+    if (gauge < 0 || gauge > 2) return set_err(c, SPV_EINVAL, "gauge=%d", gauge);
+    if (!out || !out->info || !out->fixed_mask || !out->fixed_val || !out->row_ptr || !out->h ||
+        !out->colour || !out->orig_index || (P->nnz > 0 && (!out->col || !out->J)))
+        return set_err(c, SPV_EINVAL, "NULL output buffer");
+    if (!energies || (P->n > 0 && !samples)) return set_err(c, SPV_EINVAL, "NULL samples/energies");
+    const double mm = std::ceil(elite_frac * (double)R);
+    int m = (int)mm;
+    m = std::max(1, std::min(m, R));
+    const double kk = std::ceil(threshold * (double)m);
+    const int kmin = (int)kk;
+    if (kmin < 1) return set_err(c, SPV_EINVAL, "k_min < 1");
+    st = ensure(c, c->scratch, fix_scratch_bytes(P->n, R, m));
+    if (st) return st;
+    FixLaunch L;
+    L.P = P;
+    L.image = nullptr;
+    L.samples = samples;
+    L.energies = energies;
+    L.R = R;
+    L.m = m;
+    L.kmin = kmin;
+    L.gauge_mode = gauge;
+    L.out = out;
+    L.scratch = c->scratch.p;
+    L.scratch_bytes = c->scratch.bytes;
+    return hip_check(c, launch_persist_fix(L, stream), "persist launch");
+}
+
+spv_status spv_ispvar(spv_ctx *ctx, const spv_problem *P, const double *betas, int32_t sweeps,
+                      int32_t reads, uint64_t seed, int32_t rounds, double elite_frac,
+                      double threshold, int32_t gauge, uint8_t *fixed_mask, int8_t *fixed_val,
+                      int64_t *round_info, int32_t *rounds_run, hipStream_t stream) {
+    if (!ctx) return SPV_EINVAL;
+    Ctx *c = &ctx->c;
+    DeviceGuard g(c->device);
+    spv_status st = check_problem_host(c, P);
+    if (st) return st;
+    if (rounds < 0 || reads < 1) return set_err(c, SPV_EINVAL, "rounds=%d reads=%d", rounds, reads);
+    if (!rounds_run || (rounds > 0 && !round_info) || (P->n > 0 && (!fixed_mask || !fixed_val)))
+        return set_err(c, SPV_EINVAL, "NULL output");
+    *rounds_run = 0;
+    const int n = P->n, nnz = P->nnz;
+    // Working set: two problem buffers, three index maps, one sample, one round output.
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t sz_prob = al(4ull * (n + 1)) + 2 * al(4ull * std::max(nnz, 1)) + al(4ull * std::max(n, 1)) +
+                           al(std::max(n, 1));
+    const size_t sz_map = al(4ull * std::max(n, 1));
+    const size_t total = 2 * sz_prob + 3 * sz_map + al((size_t)reads * std::max(n, 1)) + al(8ull * reads) +
+                         2 * al(std::max(n, 1)) + al(64);
+    st = ensure(c, c->rounds, total);
+    if (st) return st;
+    unsigned char *base = static_cast<unsigned char *>(c->rounds.p);
+    struct ProbBuf {
+        int32_t *rp, *col, *J, *h;
+        uint8_t *co;
+    } pb[2];
+    for (int b = 0; b < 2; ++b) {
+        unsigned char *p = base + b * sz_prob;
+        pb[b].rp = reinterpret_cast<int32_t *>(p);
+        p += al(4ull * (n + 1));
+        pb[b].col = reinterpret_cast<int32_t *>(p);
+        p += al(4ull * std::max(nnz, 1));
+        pb[b].J = reinterpret_cast<int32_t *>(p);
+        p += al(4ull * std::max(nnz, 1));
+        pb[b].h = reinterpret_cast<int32_t *>(p);
+        p += al(4ull * std::max(n, 1));
+        pb[b].co = p;
+    }
+    unsigned char *p = base + 2 * sz_prob;
+    int32_t *orig_cur = reinterpret_cast<int32_t *>(p);
+    p += sz_map;
+    int32_t *orig_new = reinterpret_cast<int32_t *>(p);
+    p += sz_map;
+    int32_t *orig_out = reinterpret_cast<int32_t *>(p);
+    p += sz_map;
+    int8_t *spins = reinterpret_cast<int8_t *>(p);
+    p += al((size_t)reads * std::max(n, 1));
+    int64_t *E = reinterpret_cast<int64_t *>(p);
+    p += al(8ull * reads);
+    uint8_t *fm = p;
+    p += al(std::max(n, 1));
+    int8_t *fv = reinterpret_cast<int8_t *>(p);
+    p += al(std::max(n, 1));
+    int64_t *info = reinterpret_cast<int64_t *>(p);
+
+    hipError_t e = hipSuccess;
+    if (n > 0) {
+        e = hipMemcpyAsync(pb[0].rp, P->row_ptr, 4ull * (n + 1), hipMemcpyDeviceToDevice, stream);
+        if (e == hipSuccess && nnz)
+            e = hipMemcpyAsync(pb[0].col, P->col, 4ull * nnz, hipMemcpyDeviceToDevice, stream);
+        if (e == hipSuccess && nnz)
+            e = hipMemcpyAsync(pb[0].J, P->J, 4ull * nnz, hipMemcpyDeviceToDevice, stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(pb[0].h, P->h, 4ull * n, hipMemcpyDeviceToDevice, stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(pb[0].co, P->colour, n, hipMemcpyDeviceToDevice, stream);
+        if (e == hipSuccess) e = launch_iota(n, orig_cur, fixed_mask, fixed_val, stream);
+    }
+    if (e != hipSuccess) return hip_check(c, e, "ispvar setup");
+    spv_problem cur = *P;
+    int b = 0;
+    int64_t offset_total = 0;
+    std::vector<int64_t> hE(reads);
+    for (int rd = 0; rd < rounds; ++rd) {
+        cur.row_ptr = pb[b].rp;
+        cur.col = pb[b].col;
+        cur.J = pb[b].J;
+        cur.h = pb[b].h;
+        cur.colour = pb[b].co;
+        if (cur.n == 0) break;
+        st = spv_sample(ctx, &cur, betas, sweeps, reads, seed + (uint64_t)rd, 0, nullptr, spins, E, stream);
+        if (st) return st;
+        spv_fix_out out;
+        out.fixed_mask = fm;
+        out.fixed_val = fv;
+        out.row_ptr = pb[1 - b].rp;
+        out.col = pb[1 - b].col;
+        out.J = pb[1 - b].J;
+        out.h = pb[1 - b].h;
+        out.colour = pb[1 - b].co;
+        out.orig_index = orig_out;
+        out.info = info;
+        st = spv_persist_fix(ctx, &cur, spins, E, reads, elite_frac, threshold, gauge, &out, stream);
+        if (st) return st;
+        e = launch_compose(cur.n, fm, fv, orig_cur, fixed_mask, fixed_val, info, orig_out, orig_new, stream);
+        int64_t hinfo[8];
+        if (e == hipSuccess) e = hipMemcpyAsync(hinfo, info, sizeof hinfo, hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(hE.data(), E, 8ull * reads, hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return hip_check(c, e, "ispvar round");
+        if (hinfo[7] != 0) return set_err(c, (spv_status)hinfo[7], "persist_fix device status %lld in round %d",
+                                          (long long)hinfo[7], rd);
+        const int64_t best = *std::min_element(hE.begin(), hE.end());
+        round_info[rd * 4 + 0] = hinfo[0];
+        round_info[rd * 4 + 2] = best + offset_total;
+        offset_total += hinfo[2];
+        round_info[rd * 4 + 1] = offset_total;
+        round_info[rd * 4 + 3] = hinfo[3];
+        std::swap(orig_cur, orig_new);
+        cur.n = (int32_t)hinfo[0];
+        cur.nnz = (int32_t)hinfo[1];
+        b = 1 - b;
+        *rounds_run = rd + 1;
+    }
+    return SPV_OK;
+}
+
+spv_status spv_pt_sample(spv_ctx *ctx, const spv_problem *P, const spv_pt_params *params,
+                         const spv_pt_out *out, hipStream_t stream) {
+    (void)P;
+    (void)params;
+    (void)out;
+    (void)stream;
+    if (!ctx) return SPV_EINVAL;
+    return set_err(&ctx->c, SPV_EINVAL, "parallel tempering is not available in this build");
+}
+
+}  // extern "C"

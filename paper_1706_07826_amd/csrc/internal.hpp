@@ -1,0 +1,131 @@
+// Internal declarations shared by the host half of libspvar (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "spvar.h"
+
+namespace spv {
+
+constexpr int kDigitBits = 9;
+constexpr int kDigitSize = 512;
+constexpr int kTopK = 10;
+constexpr int kMaxColours = 16;
+constexpr int kMaxDegree = 64;
+constexpr int kMaxN = 65535;  // positions are packed into 16 bits
+
+// A grow-only device allocation owned by the context.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+// Packed instance image written by the prep kernel (device memory):
+//   int32 header[kImgHeader]: n, D, C, class_start[C+1] (padded to 32 entries)
+//   int32 order[n]    position p -> original variable i (colour-major, index order)
+//   int32 pos_of[n]   original variable i -> position p
+//   int32 hpos[n]     bias of the variable at position p
+//   uint32 nbr[n*D]   ELL neighbour records by position: (pos_j << 16) | (uint16)J_ij,
+//                     padded with (p << 16) | 0 (self, zero coupling)
+constexpr int kImgHeader = 32;
+
+inline size_t image_words(int n, int D) { return (size_t)kImgHeader + 3ull * n + (size_t)n * D; }
+
+struct TableCache {
+    std::vector<double> betas;
+    int scale = -1;
+    int nd = -1;
+    int row_len = -1;
+    int unit = -1;
+};
+
+struct Ctx {
+    int device = 0;
+    int num_cus = 0;
+    size_t lds_max = 0;
+    std::string err;
+    DevBuf image;
+    DevBuf tables;
+    DevBuf tables2;
+    DevBuf scratch;
+    DevBuf scratch2;
+    DevBuf rounds;  // iterated-SPVAR working set
+    TableCache tcache;
+    std::vector<uint32_t> host_tables;
+};
+
+// ---- host helpers (api.cpp) ----
+spv_status set_err(Ctx *c, spv_status st, const char *fmt, ...);
+spv_status ensure(Ctx *c, DevBuf &b, size_t bytes);
+spv_status hip_check(Ctx *c, hipError_t e, const char *what);
+int digits_for(int64_t x_bound);
+uint32_t threshold_word(double beta, int64_t unit, int scale_log2, int digit, uint32_t d);
+int swap_digits(double dbeta, int scale_log2);
+
+// ---- launchers (device translation units) ----
+// Packs the CSR into the position-ordered ELL image (one workgroup).
+hipError_t launch_prep(const spv_problem *P, int32_t *image, hipStream_t s);
+
+struct SaLaunch {
+    const int32_t *image;
+    int n, D, C;
+    const uint32_t *tables;  // [sweeps][row_len]
+    int row_len, nd;
+    int sweeps;
+    uint32_t sweep_offset;
+    uint64_t seed;
+    int reads;
+    const int8_t *init;
+    int8_t *out;
+    int64_t *energies;
+    int qw;       // quads (4 replicas) per workgroup
+    int threads;  // workgroup size
+};
+hipError_t launch_sa(const SaLaunch &L, hipStream_t s, size_t lds_limit);
+size_t sa_lds_bytes(int n, int D, int row_len, int qw);
+
+hipError_t launch_energy(const int32_t *image, int n, int D, const int8_t *spins, int R,
+                         int64_t *E, hipStream_t s);
+
+struct FixLaunch {
+    const spv_problem *P;
+    const int32_t *image;
+    const int8_t *samples;
+    const int64_t *energies;
+    int R, m, kmin, gauge_mode;  // gauge_mode: 0 off, 1 on, 2 auto
+    const spv_fix_out *out;
+    void *scratch;
+    size_t scratch_bytes;
+};
+size_t fix_scratch_bytes(int n, int R, int m);
+hipError_t launch_compose(int n_cur, const uint8_t *fm_round, const int8_t *fv_round,
+                          const int32_t *orig_cur, uint8_t *fixed_mask, int8_t *fixed_val,
+                          const int64_t *info, const int32_t *orig_out, int32_t *orig_new,
+                          hipStream_t s);
+hipError_t launch_iota(int n, int32_t *a, uint8_t *fm, int8_t *fv, hipStream_t s);
+hipError_t launch_persist_fix(const FixLaunch &L, hipStream_t s);
+
+struct PtLaunch {
+    const int32_t *image;
+    int n, D, C;
+    int K, runs, chains, sweeps;
+    uint32_t sweep_offset;
+    uint64_t seed;
+    int icm_lo, icm_hi;
+    const uint32_t *mtab;  // [K][nd*512]
+    int nd;
+    const uint32_t *stab;  // [K-1][7*512]
+    const int32_t *snd;    // [K-1] swap digit counts (device)
+    const spv_pt_out *out;
+    void *scratch;         // top-10 bookkeeping
+};
+size_t pt_lds_bytes(int n, int D, int K, int chains, int nd);
+size_t pt_scratch_bytes(int n, int K, int runs, int chains);
+hipError_t launch_pt(const PtLaunch &L, hipStream_t s);
+
+}  // namespace spv

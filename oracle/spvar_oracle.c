@@ -48,7 +48,8 @@
  *    site in index order; the cluster is its connected component among q=-1
  *    sites (edges with J != 0); the cluster is flipped in both replicas.
  *
- *  Top-10 sample (Sec. III.D.1): per colder-half slot (k >= K/2) the 10
+ *  Top-10 sample (Sec. III.D.1): per slot of the colder half (the K/2
+ *    coldest slots, k >= K - K/2) the 10
  *    lowest-energy distinct states seen after each sweep; insert iff fewer
  *    than 10 are held or E < the worst held; an identical state is never
  *    inserted twice; eviction removes the worst, latest-inserted among ties;
@@ -613,8 +614,8 @@ int orc_pt_sample(const orc_problem *P, const double *betas, int32_t K, int32_t 
             }
             /* 4. Offer the colder half to the top-10 lists. */
             for (ch = 0; ch < chains; ++ch)
-                for (k = half; k < K; ++k)
-                    topk_offer(&lists[ch * half + (k - half)], n, E[ch * K + k],
+                for (k = K - half; k < K; ++k)
+                    topk_offer(&lists[ch * half + (k - (K - half))], n, E[ch * K + k],
                                S + (size_t)(ch * K + k) * n, when++);
             if (log_E && run == run_begin) {
                 memcpy(log_E + (size_t)ls * nrep, E, sizeof(int64_t) * (size_t)nrep);

@@ -98,23 +98,24 @@ def _posthoc_top10(log_E, log_spins, ch, k):
     return [b[0] for b in best], [b[2] for b in best]
 
 
-@pytest.mark.parametrize("chains,icm", [(1, None), (2, (0, 6))])
-def test_top10_equals_posthoc_selection(chains, icm):
+@pytest.mark.parametrize("chains,icm,K", [(1, None, 6), (2, (0, 6), 6), (1, None, 5), (2, (1, 4), 7)])
+def test_top10_equals_posthoc_selection(chains, icm, K):
     inst = si.cubic_lattice(4, "gauss", seed=3, scale_log2=10)
-    betas = si.geometric_betas(0.2, 5.0, 6)
+    betas = si.geometric_betas(0.2, 5.0, K)
+    first = K - K // 2  # the K/2 coldest slots
     res = oracle.pt_sample(inst, betas, runs=1, chains=chains, sweeps=300, seed=8, icm=icm,
                            log=True)
     log_E, log_spins = res["log_E"], res["log_spins"]
     flat = log_spins.reshape(-1, inst.n)
     assert np.array_equal(log_E.reshape(-1), _brute.energies(inst, flat))
     for ch in range(chains):
-        for k in range(3, 6):
+        for k in range(first, K):
             want_E, want_S = _posthoc_top10(log_E, log_spins, ch, k)
-            got_E = res["top_E"][0, ch, k - 3]
-            c = int(res["top_count"][0, ch, k - 3])
+            got_E = res["top_E"][0, ch, k - first]
+            c = int(res["top_count"][0, ch, k - first])
             assert c == len(want_E)
             assert got_E[:c].tolist() == want_E
-            assert np.array_equal(res["top_spins"][0, ch, k - 3, :c], np.array(want_S))
+            assert np.array_equal(res["top_spins"][0, ch, k - first, :c], np.array(want_S))
 
 
 def test_pt_final_energies_and_run_subsets():

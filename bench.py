@@ -27,14 +27,33 @@ BASELINE_METRIC = "spin-updates/s (batched vs plain, bit-exact); SPVAR solves/s;
 # VALU lane-slots per Metropolis update on the Chimera workload (single-digit
 # threshold test): local field over the mean degree (one conditional add per
 # coupler), 4 slots for x = -s f / sign test / threshold compare / flip, and a
-# quarter of one Philox4x32-10 block (10 rounds of two 32x32->64 products at a
-# quarter of the full rate, i.e. 4 slots each, plus two 3-input xors).
-PHILOX_SLOTS = 10 * (2 * 4 + 2)
+# quarter of one Philox4x32-10 block: 10 rounds of two 32x32->64 products
+# (v_mad_u64_u32, 2 issue slots each on gfx950) and two 3-input xors, i.e. 60
+# slots per block (a chained-Philox probe measures 59-66 slots per block).
+PHILOX_SLOTS = 10 * (2 * 2 + 2)
 PEAK_VALU_TSLOTS = 256 * 64 * 2.4e9 / 1e12  # 256 CUs x 64 lanes x 2.4 GHz = 39.32 T lane-slots/s
 
 
 def slots_per_update(mean_degree):
     return mean_degree + 4 + PHILOX_SLOTS / 4.0
+
+
+def profiled_traffic_bytes():
+    """HBM bytes per launch of the SA kernel from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a copy of known size), or None
+    when the kernel source changed after the counters were taken."""
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, "profiles", "sa_kernel_chimera8_sa.json")) as f:
+            prof = json.load(f)
+        with open(os.path.join(ROOT, prof["source"]), "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, KeyError, ValueError):
+        return None
+    if not digest.startswith(prof["source_sha256_prefix"]):
+        return None
+    kib = prof["fetch_kib"] * prof["fetch_scale"] + prof["write_kib"] * prof["write_scale"]
+    return int(round(kib * 1024))
 
 
 def main():
@@ -43,7 +62,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-reads", type=int, default=0, help="oracle reads (0 = 16 per thread)")
+    ap.add_argument("--cpu-reads", type=int, default=0, help="oracle reads (0 = 64 per thread)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after timing, run one device copy of this size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (single-GPU build)",
@@ -94,11 +115,19 @@ def main():
     sa_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
     value = updates / (ms_step / 1e3)
 
+    if args.calib_copy_mib:
+        src = torch.ones(args.calib_copy_mib << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
     mean_deg = inst.nnz / inst.n
     spu = slots_per_update(mean_deg)
     achieved = updates * spu / (sa_ms / 1e3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_VALU_TSLOTS, 3),
-                "unit": "Tslot/s", "frac": round(achieved / PEAK_VALU_TSLOTS, 4), "traffic": None,
+                "unit": "Tslot/s", "frac": round(achieved / PEAK_VALU_TSLOTS, 4),
+                "traffic": profiled_traffic_bytes(),
                 "kernel": "sa_kernel<1>", "kernel_ms": round(sa_ms, 4),
                 "slots_per_update": round(spu, 3)}
 
@@ -106,7 +135,7 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         threads = max(1, min(16, os.cpu_count() or 1))
-        cpu_reads = args.cpu_reads or 16 * threads
+        cpu_reads = args.cpu_reads or 64 * threads
         t1 = time.perf_counter()
         oracle.sa_sample(inst, betas, seed=cfg["seed"], r_begin=0, r_end=cpu_reads, threads=threads)
         dt = time.perf_counter() - t1

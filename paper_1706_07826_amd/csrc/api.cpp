@@ -66,6 +66,13 @@ uint32_t threshold_word(double beta, int64_t unit, int scale_log2, int digit, ui
     return (uint32_t)std::floor(v);
 }
 
+// Words of one Metropolis table row: full base-512 digits below the top one,
+// and the top digit only up to the largest value x_bound can take there.
+int table_row_len(int64_t x_bound) {
+    const int nd = digits_for(x_bound);
+    return kDigitSize * (nd - 1) + (int)(x_bound >> (kDigitBits * (nd - 1))) + 1;
+}
+
 int swap_digits(double dbeta, int scale_log2) {
     for (int nd = 1; nd < 7; ++nd)
         if (threshold_word(dbeta, 1, scale_log2, nd, 1) == 0u) return nd;
@@ -190,7 +197,7 @@ void spv_ctx_destroy(spv_ctx *ctx) {
     DeviceGuard g(ctx->c.device);
     (void)hipDeviceSynchronize();
     for (DevBuf *b : {&ctx->c.image, &ctx->c.tables, &ctx->c.tables2, &ctx->c.scratch, &ctx->c.scratch2,
-                      &ctx->c.rounds})
+                      &ctx->c.rounds, &ctx->c.pt})
         if (b->p) (void)hipFree(b->p);
     delete ctx;
 }
@@ -276,7 +283,7 @@ spv_status spv_sample(spv_ctx *ctx, const spv_problem *P, const double *betas, i
     const int n = P->n, D = P->max_degree;
     const int nd = digits_for(P->x_bound);
     if (nd > 3) return set_err(c, SPV_ERANGE, "x_bound=%d needs %d digits (max 3)", P->x_bound, nd);
-    const int row_len = nd == 1 ? P->x_bound + 1 : nd * kDigitSize;
+    const int row_len = table_row_len(P->x_bound);
     st = ensure(c, c->image, image_words(n, D) * 4);
     if (st) return st;
     hipError_t e = launch_prep(P, static_cast<int32_t *>(c->image.p), stream);
@@ -473,14 +480,90 @@ spv_status spv_ispvar(spv_ctx *ctx, const spv_problem *P, const double *betas, i
     return SPV_OK;
 }
 
-spv_status spv_pt_sample(spv_ctx *ctx, const spv_problem *P, const spv_pt_params *params,
+spv_status spv_pt_sample(spv_ctx *ctx, const spv_problem *P, const spv_pt_params *prm,
                          const spv_pt_out *out, hipStream_t stream) {
-    (void)P;
-    (void)params;
-    (void)out;
-    (void)stream;
     if (!ctx) return SPV_EINVAL;
-    return set_err(&ctx->c, SPV_EINVAL, "parallel tempering is not available in this build");
+    Ctx *c = &ctx->c;
+    DeviceGuard g(c->device);
+    spv_status st = check_problem_host(c, P);
+    if (st) return st;
+    if (!prm || !out) return set_err(c, SPV_EINVAL, "NULL params/out");
+    const int K = prm->K, runs = prm->runs, chains = prm->chains;
+    if (K < 1 || runs < 1 || chains < 1 || chains > 64 || prm->sweeps < 0)
+        return set_err(c, SPV_EINVAL, "K=%d runs=%d chains=%d sweeps=%d", K, runs, chains, prm->sweeps);
+    if ((st = check_betas(c, prm->betas, K))) return st;
+    for (int k = 1; k < K; ++k)
+        if (prm->betas[k] < prm->betas[k - 1]) return set_err(c, SPV_EINVAL, "betas not ascending at %d", k);
+    const bool icm = prm->icm_hi > prm->icm_lo;
+    if (icm && (chains != 2 || prm->icm_lo < 0 || prm->icm_hi > K))
+        return set_err(c, SPV_EINVAL, "cluster moves need chains == 2 and 0 <= icm_lo < icm_hi <= K");
+    if ((long long)runs * chains * K >= (1ll << 31)) return set_err(c, SPV_ERANGE, "too many replicas");
+    const int n = P->n, D = P->max_degree > 0 ? P->max_degree : 1;
+    const int nd = digits_for(P->x_bound);
+    if (nd > 3) return set_err(c, SPV_ERANGE, "x_bound=%d needs %d digits (max 3)", P->x_bound, nd);
+    const int row_len = table_row_len(P->x_bound);
+    const int cK = chains * K, half = K / 2, Ls = chains * half;
+    const int nqa = (cK % 4 == 0) ? cK / 4 : cK / 4 + 2;
+    int threads = (n * nqa >= 4096) ? 1024 : 256;
+    const int nw_icm = icm ? std::min(threads / 64, prm->icm_hi - prm->icm_lo) : 0;
+    const size_t lds = pt_lds_bytes(n, D, K, chains, row_len, nqa, nw_icm) + 256;
+    if (lds > c->lds_max)
+        return set_err(c, SPV_ECAPACITY, "PT run needs %zu B of LDS > %zu (n=%d, %d replicas)", lds, c->lds_max, n, cK);
+    // Device tables: Metropolis rows per slot, swap rows per pair, swap digit counts.
+    std::vector<uint32_t> mt((size_t)K * row_len), stt((size_t)std::max(K - 1, 1) * 7 * kDigitSize, 0u);
+    std::vector<int32_t> snd(std::max(K - 1, 1), 1);
+    for (int k = 0; k < K; ++k)
+        for (int j = 0; j < nd; ++j)
+            for (int d = 0; d < kDigitSize && j * kDigitSize + d < row_len; ++d)
+                mt[(size_t)k * row_len + j * kDigitSize + d] = threshold_word(prm->betas[k], 2, P->scale_log2, j, (uint32_t)d);
+    for (int k = 0; k + 1 < K; ++k) {
+        const double db = prm->betas[k + 1] - prm->betas[k];
+        snd[k] = swap_digits(db, P->scale_log2);
+        for (int j = 0; j < snd[k]; ++j)
+            for (int d = 0; d < kDigitSize; ++d)
+                stt[((size_t)k * 7 + j) * kDigitSize + d] = threshold_word(db, 1, P->scale_log2, j, (uint32_t)d);
+    }
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t b_mt = al(mt.size() * 4), b_st = al(stt.size() * 4), b_snd = al(snd.size() * 4);
+    const size_t b_top = al((size_t)runs * std::max(Ls, 1) * 10 * std::max(n, 1));
+    st = ensure(c, c->pt, b_mt + b_st + b_snd + b_top);
+    if (st) return st;
+    st = ensure(c, c->image, image_words(std::max(n, 1), D) * 4);
+    if (st) return st;
+    unsigned char *base = static_cast<unsigned char *>(c->pt.p);
+    hipError_t e = hipStreamSynchronize(stream);  // earlier work on this stream may read the tables
+    if (e == hipSuccess) e = hipMemcpy(base, mt.data(), mt.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(base + b_mt, stt.data(), stt.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(base + b_mt + b_st, snd.data(), snd.size() * 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_check(c, e, "PT table upload");
+    spv_problem Pp = *P;
+    Pp.max_degree = D;
+    e = launch_prep(&Pp, static_cast<int32_t *>(c->image.p), stream);
+    if (e != hipSuccess) return hip_check(c, e, "prep launch");
+    PtLaunch L;
+    L.image = static_cast<const int32_t *>(c->image.p);
+    L.n = n;
+    L.D = D;
+    L.C = P->n_colours;
+    L.K = K;
+    L.runs = runs;
+    L.chains = chains;
+    L.sweeps = prm->sweeps;
+    L.sweep_offset = prm->sweep_offset;
+    L.seed = prm->seed;
+    L.icm_lo = icm ? prm->icm_lo : 0;
+    L.icm_hi = icm ? prm->icm_hi : 0;
+    L.nw_icm = nw_icm;
+    L.mtab = reinterpret_cast<const uint32_t *>(base);
+    L.row_len = row_len;
+    L.nd = nd;
+    L.stab = reinterpret_cast<const uint32_t *>(base + b_mt);
+    L.snd = reinterpret_cast<const int32_t *>(base + b_mt + b_st);
+    L.out = out;
+    L.scratch = base + b_mt + b_st + b_snd;
+    L.nqa = nqa;
+    L.threads = threads;
+    return hip_check(c, launch_pt(L, stream), "pt launch");
 }
 
 }  // extern "C"

@@ -55,6 +55,7 @@ struct Ctx {
     DevBuf scratch;
     DevBuf scratch2;
     DevBuf rounds;  // iterated-SPVAR working set
+    DevBuf pt;      // parallel-tempering tables and top-10 storage
     TableCache tcache;
     std::vector<uint32_t> host_tables;
 };
@@ -64,6 +65,7 @@ spv_status set_err(Ctx *c, spv_status st, const char *fmt, ...);
 spv_status ensure(Ctx *c, DevBuf &b, size_t bytes);
 spv_status hip_check(Ctx *c, hipError_t e, const char *what);
 int digits_for(int64_t x_bound);
+int table_row_len(int64_t x_bound);
 uint32_t threshold_word(double beta, int64_t unit, int scale_log2, int digit, uint32_t d);
 int swap_digits(double dbeta, int scale_log2);
 
@@ -116,16 +118,17 @@ struct PtLaunch {
     int K, runs, chains, sweeps;
     uint32_t sweep_offset;
     uint64_t seed;
-    int icm_lo, icm_hi;
-    const uint32_t *mtab;  // [K][nd*512]
-    int nd;
+    int icm_lo, icm_hi, nw_icm;
+    const uint32_t *mtab;  // [K][row_len]
+    int row_len, nd;
     const uint32_t *stab;  // [K-1][7*512]
     const int32_t *snd;    // [K-1] swap digit counts (device)
     const spv_pt_out *out;
-    void *scratch;         // top-10 bookkeeping
+    void *scratch;         // top-10 states [runs][chains*(K/2)][10][n]
+    int nqa;               // quads per run window
+    int threads;
 };
-size_t pt_lds_bytes(int n, int D, int K, int chains, int nd);
-size_t pt_scratch_bytes(int n, int K, int runs, int chains);
+size_t pt_lds_bytes(int n, int D, int K, int chains, int row_len, int nqa, int nw_icm);
 hipError_t launch_pt(const PtLaunch &L, hipStream_t s);
 
 }  // namespace spv

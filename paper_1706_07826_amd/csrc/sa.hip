@@ -1,4 +1,4 @@
-// Instance packing and the simulated-annealing sweep kernel.
+// Instance packing, the one-instance simulated-annealing launch and the energy kernel.
 //
 // Sampler (Sec. III.A, "SA"): every read starts from its own Philox state (or
 // a caller state) and performs one Metropolis sweep per entry of the beta
@@ -18,6 +18,7 @@
 
 #include "device.hpp"
 #include "internal.hpp"
+#include "sa_core.hpp"
 
 namespace spv {
 
@@ -105,180 +106,15 @@ __global__ __launch_bounds__(256) void prep_nbr_kernel(const int32_t *__restrict
     hpos[p] = h[i];
 }
 
-// Sum of the four local fields of the quad at position p: f_b = h_p + sum_k J_k s_kb.
-struct Fields {
-    int32_t f[4];
-};
-
-__device__ __forceinline__ Fields local_fields(const uint32_t *__restrict__ nb,
-                                               const uint32_t *__restrict__ S, int D, int qw,
-                                               int q, int32_t hv) {
-    Fields F;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) F.f[b] = hv;
-    for (int k = 0; k < D; ++k) {
-        const uint32_t rec = nb[k];
-        const int32_t Jv = (int32_t)(int16_t)(rec & 0xffffu);
-        const uint32_t w = S[(rec >> 16) * qw + q];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) F.f[b] += Jv * dev::spin_of(w, b);
-    }
-    return F;
-}
-
 template <int ND>
-__device__ __forceinline__ uint32_t metropolis_mask(const int32_t x[4], const uint32_t *tab,
-                                                    uint32_t i, uint32_t t, uint32_t quad,
-                                                    uint32_t k0, uint32_t k1) {
-    // Returns the xor mask (0xFE per accepted byte) that flips accepted replicas.
-    bool pass[4];
-    bool up[4];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        up[b] = x[b] > 0;
-        pass[b] = true;
-    }
-#pragma unroll
-    for (int j = 0; j < ND; ++j) {
-        uint32_t d[4];
-        bool need = false;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            d[b] = up[b] ? (((uint32_t)x[b] >> (kDigitBits * j)) & (kDigitSize - 1)) : 0u;
-            need |= pass[b] && d[b] != 0;
-        }
-        if (need) {
-            const dev::Words4 w = dev::philox(i, t, quad, (2u << 24) | (uint32_t)j, k0, k1);
-#pragma unroll
-            for (int b = 0; b < 4; ++b)
-                if (d[b] != 0) pass[b] = pass[b] && (w.w[b] < tab[j * kDigitSize + d[b]]);
-        }
-    }
-    uint32_t mask = 0;
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-        if (!up[b] || pass[b]) mask |= 0xFEu << (8 * b);
-    return mask;
-}
-
-struct SaArgs {
-    const int32_t *image;
-    const uint32_t *tables;
-    const int8_t *init;
-    int8_t *out;
-    int64_t *energies;
-    int n, D, C, row_len, sweeps, reads, qw;
-    uint32_t sweep_offset, k0, k1;
-};
-
-template <int ND>
-__global__ __launch_bounds__(1024) void sa_kernel(SaArgs a) {
+__global__ __launch_bounds__(1024) void sa_kernel(core::SaItem a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int n = a.n, D = a.D, qw = a.qw, T = blockDim.x, tid = threadIdx.x;
-    uint32_t *nbr = reinterpret_cast<uint32_t *>(smem);
-    int32_t *hpos = reinterpret_cast<int32_t *>(nbr + (size_t)n * D);
-    int32_t *ord = hpos + n;
-    uint32_t *tab = reinterpret_cast<uint32_t *>(ord + n);       // [2][row_len]
-    uint32_t *S = tab + 2 * a.row_len;                           // [n][qw]
-    size_t e2_off = (reinterpret_cast<unsigned char *>(S + (size_t)n * qw) - smem + 7) & ~(size_t)7;
-    unsigned long long *E2 = reinterpret_cast<unsigned long long *>(smem + e2_off);  // [4*qw]
     __shared__ int cs[kMaxColours + 1];
-
-    const int32_t *img = a.image;
-    const int q0 = blockIdx.x * qw;  // first quad of this workgroup
-    // Each thread keeps one quad q for the whole launch and walks positions
-    // slot, slot + nslots, ... of every class.
-    const int q = tid % qw;
-    const int slot = tid / qw;
-    const int nslots = T / qw;
-    const bool active = slot < nslots;
-    if (tid <= a.C) cs[tid] = img[3 + tid];
-    for (int k = tid; k < n * D; k += T) nbr[k] = reinterpret_cast<const uint32_t *>(img + kImgHeader + 3 * n)[k];
-    for (int k = tid; k < n; k += T) {
-        hpos[k] = img[kImgHeader + 2 * n + k];
-        ord[k] = img[kImgHeader + k];
-    }
-    for (int k = tid; k < a.row_len; k += T) tab[k] = a.tables[k];
-    for (int k = tid; k < 4 * qw; k += T) E2[k] = 0ull;
-    __syncthreads();
-
-    // Initial state.
-    if (a.init == nullptr) {
-        for (int p = slot; active && p < n; p += nslots) {
-            const dev::Words4 w =
-                dev::philox((uint32_t)ord[p], 0u, (uint32_t)(q0 + q), 1u << 24, a.k0, a.k1);
-            uint32_t word = 0;
-#pragma unroll
-            for (int b = 0; b < 4; ++b) word |= ((w.w[b] >> 31) ? 0x01u : 0xFFu) << (8 * b);
-            S[(size_t)p * qw + q] = word;
-        }
-    } else {
-        const int32_t *pos_of = img + kImgHeader + n;
-        unsigned char *Sb = reinterpret_cast<unsigned char *>(S);
-        for (int idx = tid; idx < 4 * qw * n; idx += T) {
-            const int rl = idx / n, i = idx - rl * n;
-            const int r = 4 * q0 + rl;
-            int8_t v = 1;
-            if (r < a.reads) v = a.init[(size_t)r * n + i] > 0 ? 1 : -1;
-            const int p = pos_of[i];
-            Sb[((size_t)p * qw + (rl >> 2)) * 4 + (rl & 3)] = (unsigned char)v;
-        }
-    }
-    __syncthreads();
-
-    for (int ls = 0; ls < a.sweeps; ++ls) {
-        const uint32_t t = a.sweep_offset + (uint32_t)ls;
-        const uint32_t *tcur = tab + (ls & 1) * a.row_len;
-        uint32_t *tnext = tab + ((ls + 1) & 1) * a.row_len;
-        if (ls + 1 < a.sweeps)
-            for (int k = tid; k < a.row_len; k += T)
-                tnext[k] = a.tables[(size_t)(ls + 1) * a.row_len + k];
-        for (int c = 0; c < a.C; ++c) {
-            const int pe = cs[c + 1];
-            for (int p = cs[c] + slot; active && p < pe; p += nslots) {
-                const uint32_t self = S[(size_t)p * qw + q];
-                const Fields F = local_fields(nbr + (size_t)p * D, S, D, qw, q, hpos[p]);
-                int32_t x[4];
-#pragma unroll
-                for (int b = 0; b < 4; ++b) x[b] = dev::spin_of(self, b) > 0 ? -F.f[b] : F.f[b];
-                const uint32_t mask = metropolis_mask<ND>(x, tcur, (uint32_t)ord[p], t,
-                                                          (uint32_t)(q0 + q), a.k0, a.k1);
-                if (mask) S[(size_t)p * qw + q] = self ^ mask;
-            }
-            __syncthreads();
-        }
-    }
-
-    // Energies: 2E = sum_p s_p (h_p + f_p) per replica.
-    {
-        long long e2[4] = {0, 0, 0, 0};
-        for (int p = slot; active && p < n; p += nslots) {
-            const uint32_t self = S[(size_t)p * qw + q];
-            const Fields F = local_fields(nbr + (size_t)p * D, S, D, qw, q, hpos[p]);
-#pragma unroll
-            for (int b = 0; b < 4; ++b)
-                e2[b] += (long long)dev::spin_of(self, b) * ((long long)hpos[p] + F.f[b]);
-        }
-        if (active)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) atomicAdd(&E2[q * 4 + b], (unsigned long long)e2[b]);
-    }
-    __syncthreads();
-    for (int rl = tid; rl < 4 * qw; rl += T) {
-        const int r = 4 * q0 + rl;
-        if (r < a.reads) a.energies[r] = ((long long)E2[rl]) / 2;
-    }
-    // Spins, transposed back to [read][variable] in original variable order.
-    const int32_t *pos_of = img + kImgHeader + n;
-    const unsigned char *Sb = reinterpret_cast<const unsigned char *>(S);
-    for (int idx = tid; idx < 4 * qw * n; idx += T) {
-        const int rl = idx / n, i = idx - rl * n;
-        const int r = 4 * q0 + rl;
-        if (r < a.reads) {
-            const int p = pos_of[i];
-            a.out[(size_t)r * n + i] = (int8_t)Sb[((size_t)p * qw + (rl >> 2)) * 4 + (rl & 3)];
-        }
-    }
+    core::SaLds L;
+    core::sa_layout(a.n, a.D, a.row_len, a.qw, &L, smem);
+    a.q0 = blockIdx.x * a.qw;
+    core::sa_load_instance(L, a, cs);
+    core::sa_run<ND>(L, a, cs);
 }
 
 // Energies of arbitrary states: one workgroup per 64 rows... one thread per (row, variable).
@@ -332,14 +168,11 @@ hipError_t launch_prep(const spv_problem *P, int32_t *image, hipStream_t s) {
 }
 
 size_t sa_lds_bytes(int n, int D, int row_len, int qw) {
-    size_t b = (size_t)n * D * 4 + (size_t)n * 8 + (size_t)2 * row_len * 4 + (size_t)n * qw * 4;
-    // dynamic LDS starts 16-aligned; E2 is placed at the next 8-byte boundary
-    b = (b + 7) & ~(size_t)7;
-    return b + (size_t)4 * qw * 8;
+    return core::sa_layout(n, D, row_len, qw, nullptr, nullptr);
 }
 
 hipError_t launch_sa(const SaLaunch &L, hipStream_t s, size_t lds_limit) {
-    SaArgs a;
+    core::SaItem a;
     a.image = L.image;
     a.tables = L.tables;
     a.init = L.init;
@@ -351,6 +184,7 @@ hipError_t launch_sa(const SaLaunch &L, hipStream_t s, size_t lds_limit) {
     a.row_len = L.row_len;
     a.sweeps = L.sweeps;
     a.reads = L.reads;
+    a.q0 = 0;
     a.qw = L.qw;
     a.sweep_offset = L.sweep_offset;
     a.k0 = (uint32_t)L.seed;

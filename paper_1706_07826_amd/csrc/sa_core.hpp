@@ -1,0 +1,227 @@
+// Device body of the simulated-annealing sweep, shared by the one-instance
+// launch (sa.hip) and the batched persistent launch (batch.hip).
+//
+// Sampler (Sec. III.A, "SA"): every read starts from its own Philox state (or
+// a caller state) and performs one Metropolis sweep per entry of the beta
+// schedule; the sample is the final state of every read.  A sweep visits the
+// colour classes in order; a class is an independent set, so all of its spins
+// are updated in parallel with the same result as any sequential order.
+//
+// LDS holds the position-ordered instance (ELL records: neighbour position <<
+// 16 | int16 coupling), two threshold rows (current sweep and next sweep) and
+// the spins as S[p][q]: one 32-bit word per (position, quad of 4 replicas), a
+// signed byte per replica.  A thread keeps one quad q for the whole schedule;
+// for each position it forms the four local fields, draws one Philox block
+// that serves the four replicas and applies the integer threshold test.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace spv {
+namespace core {
+
+struct SaLds {
+    uint32_t *nbr;
+    int32_t *hpos;
+    int32_t *ord;
+    uint32_t *tab;  // [2][row_len]
+    uint32_t *S;    // [n][qw]
+    unsigned long long *E2;  // [4*qw]
+};
+
+__host__ __device__ inline size_t sa_layout(int n, int D, int row_len, int qw, SaLds *L,
+                                            unsigned char *base) {
+    size_t o_nbr = 0;
+    size_t o_h = o_nbr + (size_t)n * D * 4;
+    size_t o_ord = o_h + (size_t)n * 4;
+    size_t o_tab = o_ord + (size_t)n * 4;
+    size_t o_S = o_tab + (size_t)2 * row_len * 4;
+    size_t o_E = (o_S + (size_t)n * qw * 4 + 7) & ~(size_t)7;
+    size_t end = o_E + (size_t)4 * qw * 8;
+    if (L) {
+        L->nbr = reinterpret_cast<uint32_t *>(base + o_nbr);
+        L->hpos = reinterpret_cast<int32_t *>(base + o_h);
+        L->ord = reinterpret_cast<int32_t *>(base + o_ord);
+        L->tab = reinterpret_cast<uint32_t *>(base + o_tab);
+        L->S = reinterpret_cast<uint32_t *>(base + o_S);
+        L->E2 = reinterpret_cast<unsigned long long *>(base + o_E);
+    }
+    return end;
+}
+
+// One schedule over quads [q0, q0 + qw) of one instance.
+struct SaItem {
+    const int32_t *image;
+    const uint32_t *tables;  // [sweeps][row_len]
+    const int8_t *init;      // [reads][n] or null
+    int8_t *out;             // [reads][n]
+    int64_t *energies;       // [reads]
+    int n, D, C, row_len, sweeps, reads, q0, qw;
+    uint32_t sweep_offset, k0, k1;
+};
+
+struct Fields {
+    int32_t f[4];
+};
+
+// f_b = h_p + sum_k J_k s_kb for the four replicas of quad q at position p.
+__device__ __forceinline__ Fields local_fields(const uint32_t *__restrict__ nb,
+                                               const uint32_t *__restrict__ S, int D, int qw,
+                                               int q, int32_t hv) {
+    Fields F;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) F.f[b] = hv;
+    for (int k = 0; k < D; ++k) {
+        const uint32_t rec = nb[k];
+        const int32_t Jv = (int32_t)(int16_t)(rec & 0xffffu);
+        const uint32_t w = S[(rec >> 16) * qw + q];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) F.f[b] += Jv * dev::spin_of(w, b);
+    }
+    return F;
+}
+
+// Xor mask (0xFE per accepted byte) of the Metropolis decisions for x[b] = -s f.
+template <int ND>
+__device__ __forceinline__ uint32_t metropolis_mask(const int32_t x[4], const uint32_t *tab,
+                                                    uint32_t i, uint32_t t, uint32_t quad,
+                                                    uint32_t k0, uint32_t k1) {
+    bool pass[4];
+    bool up[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        up[b] = x[b] > 0;
+        pass[b] = true;
+    }
+#pragma unroll
+    for (int j = 0; j < ND; ++j) {
+        uint32_t d[4];
+        bool need = false;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            d[b] = up[b] ? (((uint32_t)x[b] >> (kDigitBits * j)) & (kDigitSize - 1)) : 0u;
+            need |= pass[b] && d[b] != 0;
+        }
+        if (need) {
+            const dev::Words4 w = dev::philox(i, t, quad, (2u << 24) | (uint32_t)j, k0, k1);
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                if (d[b] != 0) pass[b] = pass[b] && (w.w[b] < tab[j * kDigitSize + d[b]]);
+        }
+    }
+    uint32_t mask = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+        if (!up[b] || pass[b]) mask |= 0xFEu << (8 * b);
+    return mask;
+}
+
+// Copies the instance image into LDS (ELL records, biases, order).  Ends with a barrier.
+__device__ inline void sa_load_instance(const SaLds &L, const SaItem &a, int *cs) {
+    const int n = a.n, D = a.D, T = blockDim.x, tid = threadIdx.x;
+    const int32_t *img = a.image;
+    if (tid <= a.C) cs[tid] = img[3 + tid];
+    const uint32_t *recs = reinterpret_cast<const uint32_t *>(img + kImgHeader + 3 * n);
+    for (int k = tid; k < n * D; k += T) L.nbr[k] = recs[k];
+    for (int k = tid; k < n; k += T) {
+        L.hpos[k] = img[kImgHeader + 2 * n + k];
+        L.ord[k] = img[kImgHeader + k];
+    }
+    __syncthreads();
+}
+
+// The whole schedule for quads [q0, q0+qw) of an instance resident in LDS.
+// Starts and ends with a barrier, so LDS can be reused by the caller.
+template <int ND>
+__device__ void sa_run(const SaLds &L, const SaItem &a, const int *cs) {
+    const int n = a.n, D = a.D, qw = a.qw, T = blockDim.x, tid = threadIdx.x;
+    const int q0 = a.q0;
+    const int q = tid % qw, slot = tid / qw, nslots = T / qw;
+    const bool active = slot < nslots;
+    for (int k = tid; k < a.row_len; k += T) L.tab[k] = a.tables[k];
+    for (int k = tid; k < 4 * qw; k += T) L.E2[k] = 0ull;
+    // Initial state.
+    if (a.init == nullptr) {
+        for (int p = slot; active && p < n; p += nslots) {
+            const dev::Words4 w =
+                dev::philox((uint32_t)L.ord[p], 0u, (uint32_t)(q0 + q), 1u << 24, a.k0, a.k1);
+            uint32_t word = 0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) word |= ((w.w[b] >> 31) ? 0x01u : 0xFFu) << (8 * b);
+            L.S[(size_t)p * qw + q] = word;
+        }
+    } else {
+        const int32_t *pos_of = a.image + kImgHeader + n;
+        unsigned char *Sb = reinterpret_cast<unsigned char *>(L.S);
+        for (int idx = tid; idx < 4 * qw * n; idx += T) {
+            const int rl = idx / n, i = idx - rl * n;
+            const int r = 4 * q0 + rl;
+            int8_t v = 1;
+            if (r < a.reads) v = a.init[(size_t)r * n + i] > 0 ? 1 : -1;
+            const int p = pos_of[i];
+            Sb[((size_t)p * qw + (rl >> 2)) * 4 + (rl & 3)] = (unsigned char)v;
+        }
+    }
+    __syncthreads();
+
+    for (int ls = 0; ls < a.sweeps; ++ls) {
+        const uint32_t t = a.sweep_offset + (uint32_t)ls;
+        const uint32_t *tcur = L.tab + (ls & 1) * a.row_len;
+        uint32_t *tnext = L.tab + ((ls + 1) & 1) * a.row_len;
+        if (ls + 1 < a.sweeps)
+            for (int k = tid; k < a.row_len; k += T)
+                tnext[k] = a.tables[(size_t)(ls + 1) * a.row_len + k];
+        for (int c = 0; c < a.C; ++c) {
+            const int pe = cs[c + 1];
+            for (int p = cs[c] + slot; active && p < pe; p += nslots) {
+                const uint32_t self = L.S[(size_t)p * qw + q];
+                const Fields F = local_fields(L.nbr + (size_t)p * D, L.S, D, qw, q, L.hpos[p]);
+                int32_t x[4];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) x[b] = dev::spin_of(self, b) > 0 ? -F.f[b] : F.f[b];
+                const uint32_t mask = metropolis_mask<ND>(x, tcur, (uint32_t)L.ord[p], t,
+                                                          (uint32_t)(q0 + q), a.k0, a.k1);
+                if (mask) L.S[(size_t)p * qw + q] = self ^ mask;
+            }
+            __syncthreads();
+        }
+    }
+
+    // Energies: 2E = sum_p s_p (h_p + f_p) per replica.
+    {
+        long long e2[4] = {0, 0, 0, 0};
+        for (int p = slot; active && p < n; p += nslots) {
+            const uint32_t self = L.S[(size_t)p * qw + q];
+            const Fields F = local_fields(L.nbr + (size_t)p * D, L.S, D, qw, q, L.hpos[p]);
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                e2[b] += (long long)dev::spin_of(self, b) * ((long long)L.hpos[p] + F.f[b]);
+        }
+        if (active)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) atomicAdd(&L.E2[q * 4 + b], (unsigned long long)e2[b]);
+    }
+    __syncthreads();
+    for (int rl = tid; rl < 4 * qw; rl += T) {
+        const int r = 4 * q0 + rl;
+        if (r < a.reads) a.energies[r] = ((long long)L.E2[rl]) / 2;
+    }
+    // Spins, transposed back to [read][variable] in original variable order.
+    const int32_t *pos_of = a.image + kImgHeader + n;
+    const unsigned char *Sb = reinterpret_cast<const unsigned char *>(L.S);
+    for (int idx = tid; idx < 4 * qw * n; idx += T) {
+        const int rl = idx / n, i = idx - rl * n;
+        const int r = 4 * q0 + rl;
+        if (r < a.reads) {
+            const int p = pos_of[i];
+            a.out[(size_t)r * n + i] = (int8_t)Sb[((size_t)p * qw + (rl >> 2)) * 4 + (rl & 3)];
+        }
+    }
+    __syncthreads();
+}
+
+}  // namespace core
+}  // namespace spv

@@ -65,6 +65,8 @@ def main():
     ap.add_argument("--cpu-reads", type=int, default=0, help="oracle reads (0 = 64 per thread)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after timing, run one device copy of this size (counter calibration)")
+    ap.add_argument("--workload", default="chimera8_sa",
+                    choices=["chimera8_sa", "residual_batch", "cubic10_pt"])
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (single-GPU build)",
@@ -76,6 +78,11 @@ def main():
 
     import paper_1706_07826_amd as spv
     from spvar_inputs import configs as cf
+
+    if args.workload == "residual_batch":
+        return bench_residual_batch(args)
+    if args.workload == "cubic10_pt":
+        return bench_cubic10_pt(args)
 
     cfg = cf.CHIMERA8_SA
     inst = cf.instance(cfg)
@@ -157,6 +164,102 @@ def main():
         "fixed_per_solve": info["n_fixed"],
         "roofline": roofline,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_residual_batch(args):
+    """Residual batch: 512 instances (n log-uniform 50..1000), 1000 reads x 1000 sweeps
+    each.  Batched persistent launch (graph-replayed, autotuned shape) vs the plain path
+    (one spv_sample launch per instance, default shape), outputs compared bit for bit."""
+    import numpy as np
+    import torch
+
+    import paper_1706_07826_amd as spv
+    from spvar_inputs import configs as cf
+
+    cfg = cf.RESIDUAL_BATCH
+    insts = cf.instance(cfg)
+    betas = cf.betas(cfg)
+    ctx = spv.Context(0)
+    probs = [spv.Problem.from_instance(i) for i in insts]
+    reads = [cfg["reads"]] * len(insts)
+    seeds = [cfg["seed"] + b for b in range(len(insts))]
+    updates = sum(i.n for i in insts) * cfg["reads"] * cfg["sweeps"]
+    sp, en = spv.spv_sample_batch(ctx, probs, betas, reads, seeds, tune=True, graph=True)
+    torch.cuda.synchronize()
+    shape = spv.spv_batch_last_shape(ctx)
+    for _ in range(args.warmup):
+        spv.spv_sample_batch(ctx, probs, betas, reads, seeds, spins=sp, energies=en, graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        spv.spv_sample_batch(ctx, probs, betas, reads, seeds, spins=sp, energies=en, graph=True)
+    torch.cuda.synchronize()
+    batched_s = (time.perf_counter() - t0) / args.steps
+    psp = [torch.empty_like(t) for t in sp]
+    pen = [torch.empty_like(t) for t in en]
+    for b, P in enumerate(probs):  # warm-up of the plain path
+        spv.spv_sample(ctx, P, betas, reads[b], seeds[b], spins=psp[b], energies=pen[b])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b, P in enumerate(probs):
+        spv.spv_sample(ctx, P, betas, reads[b], seeds[b], spins=psp[b], energies=pen[b])
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+    same = all(torch.equal(a, b) for a, b in zip(sp + en, psp + pen))
+    out = {
+        "metric": BASELINE_METRIC, "value": round(updates / batched_s, 1), "unit": "spin-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(batched_s * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic residual-shaped instances",
+        "config": {"workload": "residual_batch: 512 BFS-ball residuals of a Chimera 16x16 parent, "
+                               "n log-uniform 50..1000, 1000 reads x 1000 sweeps each",
+                   "instances": len(insts), "total_n": sum(i.n for i in insts)},
+        "plain_spin_updates_per_s": round(updates / plain_s, 1), "plain_ms": round(plain_s * 1e3, 3),
+        "batched_over_plain": round(plain_s / batched_s, 3), "bit_identical": bool(same),
+        "batch_shape": shape,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_cubic10_pt(args):
+    """cubic10_pt: 64 PT runs x 32 slots x 10^4 sweeps on the L=10 lattice, then persistence
+    on the 10,240-state top-10 sample."""
+    import torch
+
+    import paper_1706_07826_amd as spv
+    from spvar_inputs import configs as cf
+
+    cfg = cf.CUBIC10_PT
+    inst = cf.instance(cfg)
+    betas = cf.betas(cfg)
+    ctx = spv.Context(0)
+    P = spv.Problem.from_instance(inst)
+    updates = inst.n * cfg["K"] * cfg["runs"] * cfg["sweeps"]
+
+    def step():
+        r = spv.spv_pt_sample(ctx, P, betas, cfg["runs"], 1, cfg["sweeps"], cfg["seed"], final=False)
+        S = r["top_spins"].reshape(-1, inst.n)
+        E = r["top_E"].reshape(-1)
+        return spv.spv_persist_fix(ctx, P, S, E, cfg["elite"], cfg["theta"], cfg["gauge"])
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        fx = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    out = {
+        "metric": BASELINE_METRIC, "value": round(updates / dt, 1), "unit": "spin-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic Gaussian cubic L=10 instance",
+        "config": {"workload": "cubic10_pt: PT 32 betas 0.2..5.0, 64 runs x 10^4 sweeps, top-10 "
+                               "sample of the 16 colder slots, persistence elite 0.2"},
+        "spvar_solves_per_s": round(1 / dt, 4), "fixed_per_solve": fx.info()["n_fixed"],
     }
     print(json.dumps(out), flush=True)
 

@@ -243,6 +243,50 @@ typedef struct {
 spv_status spv_pt_sample(spv_ctx *ctx, const spv_problem *P, const spv_pt_params *params,
                          const spv_pt_out *out, hipStream_t stream);
 
+/*
+ * Batched simulated annealing over B instances of uneven size (the residual
+ * problems left after fixing, Sec. II.C / Sec. III.C) in ONE persistent
+ * launch.  Work items (instance, block of 4*quads_per_item reads) are popped
+ * from a device queue in largest-instance-first order; a workgroup reloads
+ * an instance into LDS only when it changes.  Results are bit-identical to
+ * spv_sample on each instance with the same schedule and seed, for every
+ * launch shape.
+ *   problems [B]  host array of device-resident problems; all share
+ *                 scale_log2 (the threshold tables are common)
+ *   betas [sweeps] host, shared schedule
+ *   reads [B], seeds [B]  host
+ *   spins [B], energies [B]  host arrays of device pointers ([reads][n] int8,
+ *                 [reads] int64)
+ *   opts          NULL for defaults.  threads / quads_per_item / wgs_per_cu
+ *                 fix the shape (0 = default or tuned); flags:
+ *                 SPV_BATCH_GRAPH captures the launch (descriptor upload,
+ *                 queue reset, packing, persistent kernel) in a hipGraph,
+ *                 cached per batch shape and replayed on later calls with the
+ *                 same shape; SPV_BATCH_TUNE times candidate shapes on this
+ *                 batch (short schedule) the first time a shape class is seen
+ *                 and keeps the fastest on the context.
+ * Descriptors are staged in pinned host memory; a call waits for the previous
+ * batched launch on the context to finish reading them.
+ */
+#define SPV_BATCH_GRAPH 1u
+#define SPV_BATCH_TUNE 2u
+typedef struct {
+    int32_t threads;
+    int32_t quads_per_item;
+    int32_t wgs_per_cu;
+    uint32_t flags;
+} spv_batch_opts;
+
+spv_status spv_sample_batch(spv_ctx *ctx, int32_t B, const spv_problem *problems, const double *betas,
+                            int32_t sweeps, const int32_t *reads, const uint64_t *seeds,
+                            int8_t *const *spins, int64_t *const *energies, const spv_batch_opts *opts,
+                            hipStream_t stream);
+
+/* The launch shape the last spv_sample_batch call used (threads, quads per
+ * item, workgroups per CU) and, when it was tuned, the best trial time in ms. */
+spv_status spv_batch_last_shape(const spv_ctx *ctx, int32_t *threads, int32_t *quads_per_item,
+                                int32_t *wgs_per_cu, float *tuned_ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -51,6 +51,15 @@ class spv_pt_params(C.Structure):
                 ("sweep_offset", C.c_uint32), ("icm_lo", C.c_int32), ("icm_hi", C.c_int32)]
 
 
+class spv_batch_opts(C.Structure):
+    _fields_ = [("threads", C.c_int32), ("quads_per_item", C.c_int32), ("wgs_per_cu", C.c_int32),
+                ("flags", C.c_uint32)]
+
+
+SPV_BATCH_GRAPH = 1
+SPV_BATCH_TUNE = 2
+
+
 class spv_pt_out(C.Structure):
     _fields_ = [("final_spins", C.c_void_p), ("final_E", C.c_void_p), ("top_spins", C.c_void_p),
                 ("top_E", C.c_void_p), ("top_count", C.c_void_p)]
@@ -72,6 +81,8 @@ _SIGS = {
     "spv_ispvar": ([_vp, _P, _vp, _i32, _i32, _u64, _i32, _f64, _f64, _i32, _vp, _vp, _vp, _vp, _vp],
                    C.c_int),
     "spv_pt_sample": ([_vp, _P, C.POINTER(spv_pt_params), C.POINTER(spv_pt_out), _vp], C.c_int),
+    "spv_sample_batch": ([_vp, _i32, _P, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp], C.c_int),
+    "spv_batch_last_shape": ([_vp, _vp, _vp, _vp, _vp], C.c_int),
 }
 EXPORTED = sorted(_SIGS)
 for _name, (_args, _res) in _SIGS.items():
@@ -297,3 +308,36 @@ def spv_pt_sample(ctx, P, betas, runs, chains, sweeps, seed, sweep_offset=0, icm
     ctx.check(_lib.spv_pt_sample(ctx.handle, C.byref(ps), C.byref(params), C.byref(out),
                                  _stream(stream)), "spv_pt_sample")
     return res
+
+
+def spv_sample_batch(ctx, problems, betas, reads, seeds, spins=None, energies=None, threads=0,
+                     quads_per_item=0, wgs_per_cu=0, graph=False, tune=False, stream=None):
+    """Batched SA over many problems in one persistent launch.  Returns (spins, energies) lists
+    of device tensors ([reads_b][n_b] int8, [reads_b] int64)."""
+    B = len(problems)
+    b = np.ascontiguousarray(betas, dtype=np.float64)
+    dev = ctx.device
+    if spins is None:
+        spins = [torch.empty((int(r), P.n), dtype=torch.int8, device=dev) for P, r in zip(problems, reads)]
+    if energies is None:
+        energies = [torch.empty(int(r), dtype=torch.int64, device=dev) for r in reads]
+    arr = (spv_problem * max(B, 1))(*[P.c_struct() for P in problems])
+    rd = np.ascontiguousarray(reads, dtype=np.int32)
+    sd = np.ascontiguousarray([s & (2**64 - 1) for s in seeds], dtype=np.uint64)
+    sp = np.array([t.data_ptr() if t.numel() else 0 for t in spins] or [0], dtype=np.uint64)
+    en = np.array([t.data_ptr() if t.numel() else 0 for t in energies] or [0], dtype=np.uint64)
+    opts = spv_batch_opts(int(threads), int(quads_per_item), int(wgs_per_cu),
+                          (SPV_BATCH_GRAPH if graph else 0) | (SPV_BATCH_TUNE if tune else 0))
+    rc = _lib.spv_sample_batch(ctx.handle, B, arr, _ptr(b), b.size, _ptr(rd), _ptr(sd), _ptr(sp),
+                               _ptr(en), C.byref(opts), _stream(stream))
+    ctx.check(rc, "spv_sample_batch")
+    ctx._batch_keep = (arr, rd, sd, sp, en, b)
+    return spins, energies
+
+
+def spv_batch_last_shape(ctx):
+    t, q, w = C.c_int32(), C.c_int32(), C.c_int32()
+    ms = C.c_float()
+    ctx.check(_lib.spv_batch_last_shape(ctx.handle, C.byref(t), C.byref(q), C.byref(w), C.byref(ms)),
+              "spv_batch_last_shape")
+    return dict(threads=t.value, quads_per_item=q.value, wgs_per_cu=w.value, tuned_ms=ms.value)

@@ -12,9 +12,6 @@
 
 #include "internal.hpp"
 
-struct spv_ctx {
-    spv::Ctx c;
-};
 
 namespace spv {
 
@@ -83,18 +80,7 @@ int swap_digits(double dbeta, int scale_log2) {
 
 using namespace spv;
 
-namespace {
-
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
-        else prev = -1;
-    }
-    ~DeviceGuard() {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
+namespace spv {
 
 spv_status check_problem_host(Ctx *c, const spv_problem *P) {
     if (!P) return set_err(c, SPV_EINVAL, "problem is NULL");
@@ -165,7 +151,7 @@ int sa_qw_env() {
     return v ? atoi(v) : 0;
 }
 
-}  // namespace
+}  // namespace spv
 
 extern "C" {
 
@@ -196,6 +182,7 @@ void spv_ctx_destroy(spv_ctx *ctx) {
     if (!ctx) return;
     DeviceGuard g(ctx->c.device);
     (void)hipDeviceSynchronize();
+    batch_release(&ctx->c);
     for (DevBuf *b : {&ctx->c.image, &ctx->c.tables, &ctx->c.tables2, &ctx->c.scratch, &ctx->c.scratch2,
                       &ctx->c.rounds, &ctx->c.pt})
         if (b->p) (void)hipFree(b->p);

@@ -56,9 +56,30 @@ struct Ctx {
     DevBuf scratch2;
     DevBuf rounds;  // iterated-SPVAR working set
     DevBuf pt;      // parallel-tempering tables and top-10 storage
+    DevBuf batch;   // batched launch: descriptors, items, counter, images
     TableCache tcache;
     std::vector<uint32_t> host_tables;
+    void *batch_host = nullptr;  // pinned staging of descriptors and items
+    size_t batch_host_bytes = 0;
+    hipEvent_t batch_done = nullptr;
+    hipStream_t capture_stream = nullptr;
+    struct GraphEntry {
+        std::vector<long long> key;
+        hipGraphExec_t exec = nullptr;
+        hipStream_t stream = nullptr;
+    };
+    std::vector<GraphEntry> graphs;
+    struct TuneEntry {
+        std::vector<long long> key;
+        int threads, qw, wgs_per_cu;
+        float ms;
+    };
+    std::vector<TuneEntry> tuned;
+    int last_shape[3] = {0, 0, 0};
+    float last_tuned_ms = -1.f;
 };
+
+void batch_release(Ctx *c);
 
 // ---- host helpers (api.cpp) ----
 spv_status set_err(Ctx *c, spv_status st, const char *fmt, ...);
@@ -68,6 +89,22 @@ int digits_for(int64_t x_bound);
 int table_row_len(int64_t x_bound);
 uint32_t threshold_word(double beta, int64_t unit, int scale_log2, int digit, uint32_t d);
 int swap_digits(double dbeta, int scale_log2);
+spv_status check_problem_host(Ctx *c, const spv_problem *P);
+spv_status check_betas(Ctx *c, const double *b, int count);
+spv_status upload_tables(Ctx *c, DevBuf &dst, const double *betas, int count, int unit, int scale,
+                         int nd, int row_len, hipStream_t s);
+
+// Makes `dev` current for the lifetime of the guard.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+        else prev = -1;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
 
 // ---- launchers (device translation units) ----
 // Packs the CSR into the position-ordered ELL image (one workgroup).
@@ -112,6 +149,33 @@ hipError_t launch_compose(int n_cur, const uint8_t *fm_round, const int8_t *fv_r
 hipError_t launch_iota(int n, int32_t *a, uint8_t *fm, int8_t *fv, hipStream_t s);
 hipError_t launch_persist_fix(const FixLaunch &L, hipStream_t s);
 
+// Device descriptor of one instance of a batched launch.
+struct BatchInst {
+    const int32_t *row_ptr;
+    const int32_t *col;
+    const int32_t *J;
+    const int32_t *h;
+    const uint8_t *colour;
+    int8_t *out;
+    int64_t *energies;
+    uint64_t seed;
+    long long image_off;  // int32 words into the image buffer
+    int n, nnz, D, C, reads, pad;
+};
+
+struct BatchLaunch {
+    const BatchInst *insts;
+    const int32_t *items;  // [n_items][2]
+    int n_items;
+    int *counter;
+    const int32_t *images;
+    const uint32_t *tables;
+    int row_len, nd, sweeps, qw, n_max, D_max, grid, threads;
+    uint32_t sweep_offset;
+};
+hipError_t launch_batch_prep(const BatchInst *insts, int B, int n_max, int32_t *images, hipStream_t s);
+hipError_t launch_batch_sa(const BatchLaunch &L, hipStream_t s);
+
 struct PtLaunch {
     const int32_t *image;
     int n, D, C;
@@ -132,3 +196,8 @@ size_t pt_lds_bytes(int n, int D, int K, int chains, int row_len, int nqa, int n
 hipError_t launch_pt(const PtLaunch &L, hipStream_t s);
 
 }  // namespace spv
+
+// The opaque context handle of the ABI.
+struct spv_ctx {
+    spv::Ctx c;
+};

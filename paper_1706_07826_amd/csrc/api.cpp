@@ -296,11 +296,14 @@ spv_status spv_sample(spv_ctx *ctx, const spv_problem *P, const double *betas, i
     L.energies = energies;
     // Launch shape: small workgroups (4 waves) with few quads each, so that
     // several workgroups share a CU and hide each other's barriers.
-    const int quads = (reads + 3) / 4;
+    // Measured on the Chimera 8x8 workload: the byte-parallel path is fastest
+    // with 2 quads per 512-thread workgroup, the general path with 1 quad per
+    // 256-thread workgroup.
+    const bool swar = sa_use_swar(nd, row_len);
     int qw = sa_qw_env();
-    if (qw <= 0) qw = quads >= 8 * c->num_cus ? 2 : 1;
+    if (qw <= 0) qw = swar ? 2 : 1;
     int threads = sa_threads_env();
-    if (threads <= 0) threads = 256;
+    if (threads <= 0) threads = swar ? 512 : 256;
     threads = std::max(64, std::min(1024, threads / qw * qw));
     while (qw > 1 && sa_lds_bytes(n, D, row_len, qw) + 256 > c->lds_max) --qw;
     if (sa_lds_bytes(n, D, row_len, qw) + 256 > c->lds_max)

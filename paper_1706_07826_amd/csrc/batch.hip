@@ -10,9 +10,12 @@
 // the counter passes the item count.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device.hpp"
 #include "internal.hpp"
 #include "sa_core.hpp"
+#include "swar_core.hpp"
 
 namespace spv {
 
@@ -120,8 +123,14 @@ __global__ __launch_bounds__(1024) void batch_sa_kernel(BatchArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int cs[kMaxColours + 1];
     __shared__ int item_s;
-    core::SaLds L;
-    core::sa_layout(a.n_max, a.D_max, a.row_len, a.qw, &L, smem);
+    // ND = 0: byte-parallel path (x_bound <= 255 for every instance of the batch).
+    using Lds = typename std::conditional<ND == 0, core::SwarLds, core::SaLds>::type;
+    Lds L;
+    const int e2q = a.qw > kBatchMaxItemQuads ? a.qw : kBatchMaxItemQuads;
+    if constexpr (ND == 0)
+        core::swar_layout(a.n_max, a.D_max, a.row_len, a.qw, &L, smem, e2q);
+    else
+        core::sa_layout(a.n_max, a.D_max, a.row_len, a.qw, &L, smem, e2q);
     int loaded = -1;
     for (;;) {
         if (threadIdx.x == 0) item_s = atomicAdd(a.counter, 1);
@@ -129,7 +138,7 @@ __global__ __launch_bounds__(1024) void batch_sa_kernel(BatchArgs a) {
         const int item = item_s;
         __syncthreads();
         if (item >= a.n_items) break;
-        const int b = a.items[2 * item];
+        const int b = a.items[3 * item];
         const BatchInst in = a.insts[b];
         core::SaItem it;
         it.image = a.images + in.image_off;
@@ -143,16 +152,24 @@ __global__ __launch_bounds__(1024) void batch_sa_kernel(BatchArgs a) {
         it.row_len = a.row_len;
         it.sweeps = a.sweeps;
         it.reads = in.reads;
-        it.q0 = a.items[2 * item + 1];
-        it.qw = a.qw;
+        it.q0 = a.items[3 * item + 1];
+        it.qw = a.items[3 * item + 2];
         it.sweep_offset = a.sweep_offset;
         it.k0 = (uint32_t)in.seed;
         it.k1 = (uint32_t)(in.seed >> 32);
-        if (b != loaded) {
-            core::sa_load_instance(L, it, cs);
-            loaded = b;
+        if constexpr (ND == 0) {
+            if (b != loaded) {
+                core::swar_load_instance(L, it, cs);
+                loaded = b;
+            }
+            core::swar_run(L, it, cs);
+        } else {
+            if (b != loaded) {
+                core::sa_load_instance(L, it, cs);
+                loaded = b;
+            }
+            core::sa_run<ND>(L, it, cs);
         }
-        core::sa_run<ND>(L, it, cs);
     }
 }
 
@@ -165,6 +182,12 @@ hipError_t launch_batch_prep(const BatchInst *insts, int B, int n_max, int32_t *
     if (e != hipSuccess || n_max <= 0) return e;
     hipLaunchKernelGGL(batch_prep_nbr_kernel, dim3((n_max + 255) / 256, B), dim3(256), 0, s, insts, images);
     return hipGetLastError();
+}
+
+size_t batch_lds_bytes(int n_max, int D_max, int row_len, int qw, int nd) {
+    const int e2q = qw > kBatchMaxItemQuads ? qw : kBatchMaxItemQuads;
+    if (sa_use_swar(nd, row_len)) return core::swar_layout(n_max, D_max, row_len, qw, nullptr, nullptr, e2q);
+    return core::sa_layout(n_max, D_max, row_len, qw, nullptr, nullptr, e2q);
 }
 
 hipError_t launch_batch_sa(const BatchLaunch &L, hipStream_t s) {
@@ -184,8 +207,11 @@ hipError_t launch_batch_sa(const BatchLaunch &L, hipStream_t s) {
     a.n_max = L.n_max;
     a.D_max = L.D_max;
     a.sweep_offset = L.sweep_offset;
-    const size_t lds = core::sa_layout(L.n_max, L.D_max, L.row_len, L.qw, nullptr, nullptr);
-    switch (L.nd) {
+    const size_t lds = batch_lds_bytes(L.n_max, L.D_max, L.row_len, L.qw, L.nd);
+    switch (sa_use_swar(L.nd, L.row_len) ? 0 : L.nd) {
+        case 0:
+            hipLaunchKernelGGL(batch_sa_kernel<0>, dim3(L.grid), dim3(L.threads), lds, s, a);
+            break;
         case 1:
             hipLaunchKernelGGL(batch_sa_kernel<1>, dim3(L.grid), dim3(L.threads), lds, s, a);
             break;

@@ -42,8 +42,20 @@ struct Plan {
 
 size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-// Largest-instance-first list of (instance, first quad) items.
-std::vector<int32_t> make_items(const Plan &pl, int qw) {
+// Quads per item of instance b: at least the base shape, more for small
+// instances so that (class size x quads) fills the workgroup, within the LDS
+// spin capacity of the base shape (n_max x qw words).
+int item_quads(const Plan &pl, int b, int qw, int threads) {
+    const BatchInst &in = pl.insts[b];
+    if (in.n <= 0) return qw;
+    const int cls = std::max(1, (in.n + in.C - 1) / in.C);
+    const int want = std::max(qw, threads / cls);
+    const int cap = std::max(qw, (int)((long long)pl.n_max * qw / in.n));
+    return std::max(1, std::min(std::min(want, cap), std::max(qw, kBatchMaxItemQuads)));
+}
+
+// Largest-instance-first list of (instance, first quad, quads) items.
+std::vector<int32_t> make_items(const Plan &pl, int qw, int threads) {
     std::vector<int> order(pl.B);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(),
@@ -51,9 +63,11 @@ std::vector<int32_t> make_items(const Plan &pl, int qw) {
     std::vector<int32_t> items;
     for (int b : order) {
         const int quads = (pl.insts[b].reads + 3) / 4;
-        for (int q0 = 0; q0 < quads; q0 += qw) {
+        const int qb = item_quads(pl, b, qw, threads);
+        for (int q0 = 0; q0 < quads; q0 += qb) {
             items.push_back(b);
             items.push_back(q0);
+            items.push_back(qb);
         }
     }
     return items;
@@ -68,7 +82,7 @@ Layout layout_for(const Plan &pl, size_t n_items) {
     Layout l;
     l.insts = 0;
     l.items = al256(sizeof(BatchInst) * std::max(pl.B, 1));
-    l.counter = l.items + al256(8 * std::max<size_t>(n_items, 1));
+    l.counter = l.items + al256(12 * std::max<size_t>(n_items, 1));
     l.images = l.counter + 256;
     l.total = l.images + al256(4 * std::max<long long>(pl.image_words, 1));
     l.host = l.counter;
@@ -214,8 +228,8 @@ spv_status spv_sample_batch(spv_ctx *ctx, int32_t B, const spv_problem *problems
             }
     float tuned_ms = -1.f;
     if (!have && (flags & SPV_BATCH_TUNE)) {
-        static const Shape cand[] = {{256, 1, 4}, {256, 2, 4}, {256, 4, 4}, {512, 2, 2},
-                                     {512, 4, 2}, {512, 8, 2}, {1024, 4, 1}, {1024, 8, 1}};
+        static const Shape cand[] = {{256, 1, 4}, {256, 2, 4}, {512, 1, 2}, {512, 2, 2},
+                                     {512, 4, 2}, {1024, 2, 1}, {1024, 4, 1}, {1024, 8, 1}};
         const int tsweeps = std::min(sweeps, 24);
         hipEvent_t e0, e1;
         if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
@@ -223,12 +237,12 @@ spv_status spv_sample_batch(spv_ctx *ctx, int32_t B, const spv_problem *problems
         float best = 1e30f;
         Shape bs = sh;
         for (const Shape &cs : cand) {
-            if (sa_lds_bytes(pl.n_max, pl.D_max, pl.row_len, cs.qw) + 512 > c->lds_max) continue;
-            const std::vector<int32_t> items = make_items(pl, cs.qw);
-            const Layout ly = layout_for(pl, items.size() / 2);
+            if (batch_lds_bytes(pl.n_max, pl.D_max, pl.row_len, cs.qw, pl.nd) + 512 > c->lds_max) continue;
+            const std::vector<int32_t> items = make_items(pl, cs.qw, cs.threads);
+            const Layout ly = layout_for(pl, items.size() / 3);
             if ((st = ensure_batch_buf(c, ly.total)) || (st = stage(c, pl, items, ly))) break;
             (void)hipEventRecord(e0, stream);
-            st = enqueue(c, pl, ly, items.size() / 2, cs, tsweeps, 0, stream);
+            st = enqueue(c, pl, ly, items.size() / 3, cs, tsweeps, 0, stream);
             (void)hipEventRecord(e1, stream);
             (void)hipEventRecord(c->batch_done, stream);
             if (st) break;
@@ -253,15 +267,15 @@ spv_status spv_sample_batch(spv_ctx *ctx, int32_t B, const spv_problem *problems
         sh.wgs_per_cu < 1 || sh.wgs_per_cu > 32)
         return set_err(c, SPV_EINVAL, "batch shape threads=%d quads_per_item=%d wgs_per_cu=%d", sh.threads,
                        sh.qw, sh.wgs_per_cu);
-    if (sa_lds_bytes(pl.n_max, pl.D_max, pl.row_len, sh.qw) + 512 > c->lds_max)
+    if (batch_lds_bytes(pl.n_max, pl.D_max, pl.row_len, sh.qw, pl.nd) + 512 > c->lds_max)
         return set_err(c, SPV_ECAPACITY, "largest instance (n=%d) needs more LDS than a workgroup has", pl.n_max);
     c->last_shape[0] = sh.threads;
     c->last_shape[1] = sh.qw;
     c->last_shape[2] = sh.wgs_per_cu;
     c->last_tuned_ms = tuned_ms;
 
-    const std::vector<int32_t> items = make_items(pl, sh.qw);
-    const size_t n_items = items.size() / 2;
+    const std::vector<int32_t> items = make_items(pl, sh.qw, sh.threads);
+    const size_t n_items = items.size() / 3;
     const Layout ly = layout_for(pl, n_items);
     if ((st = ensure_batch_buf(c, ly.total))) return st;
     if ((st = stage(c, pl, items, ly))) return st;

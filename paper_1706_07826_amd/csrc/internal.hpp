@@ -127,6 +127,7 @@ struct SaLaunch {
 };
 hipError_t launch_sa(const SaLaunch &L, hipStream_t s, size_t lds_limit);
 size_t sa_lds_bytes(int n, int D, int row_len, int qw);
+bool sa_use_swar(int nd, int row_len);
 
 hipError_t launch_energy(const int32_t *image, int n, int D, const int8_t *spins, int R,
                          int64_t *E, hipStream_t s);
@@ -173,6 +174,9 @@ struct BatchLaunch {
     int row_len, nd, sweeps, qw, n_max, D_max, grid, threads;
     uint32_t sweep_offset;
 };
+// Small instances get up to this many quads per work item (energy accumulators are sized for it).
+constexpr int kBatchMaxItemQuads = 16;
+size_t batch_lds_bytes(int n_max, int D_max, int row_len, int qw, int nd);
 hipError_t launch_batch_prep(const BatchInst *insts, int B, int n_max, int32_t *images, hipStream_t s);
 hipError_t launch_batch_sa(const BatchLaunch &L, hipStream_t s);
 

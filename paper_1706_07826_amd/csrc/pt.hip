@@ -136,7 +136,10 @@ __global__ __launch_bounds__(1024) void pt_kernel(PtArgs a) {
     const int32_t *img = a.image;
 
     if (tid <= a.C) cs[tid] = img[3 + tid];
-    for (int k = tid; k < n * D; k += T) L.nbr[k] = reinterpret_cast<const uint32_t *>(img + kImgHeader + 3 * n)[k];
+    for (int idx = tid; idx < n * D; idx += T) {  // neighbour-major in LDS: nbr[k][p]
+        const int p = idx / D, k = idx - p * D;
+        L.nbr[(size_t)k * n + p] = reinterpret_cast<const uint32_t *>(img + kImgHeader + 3 * n)[idx];
+    }
     for (int k = tid; k < n; k += T) {
         L.ord[k] = img[kImgHeader + k];
         L.pos[k] = img[kImgHeader + n + k];
@@ -181,7 +184,7 @@ __global__ __launch_bounds__(1024) void pt_kernel(PtArgs a) {
 #pragma unroll
             for (int b = 0; b < 4; ++b) f[b] = L.hpos[p];
             for (int k = 0; k < D; ++k) {
-                const uint32_t rec = L.nbr[(size_t)p * D + k];
+                const uint32_t rec = L.nbr[(size_t)k * n + p];
                 const int32_t Jv = (int32_t)(int16_t)(rec & 0xffffu);
                 const uint32_t w = L.S[(rec >> 16) * nqa + q];
 #pragma unroll
@@ -210,7 +213,7 @@ __global__ __launch_bounds__(1024) void pt_kernel(PtArgs a) {
 #pragma unroll
                 for (int b = 0; b < 4; ++b) f[b] = L.hpos[p];
                 for (int k = 0; k < D; ++k) {
-                    const uint32_t rec = L.nbr[(size_t)p * D + k];
+                    const uint32_t rec = L.nbr[(size_t)k * n + p];
                     const int32_t Jv = (int32_t)(int16_t)(rec & 0xffffu);
                     const uint32_t w = L.S[(rec >> 16) * nqa + q];
 #pragma unroll
@@ -360,7 +363,7 @@ __global__ __launch_bounds__(1024) void pt_kernel(PtArgs a) {
                         bool added = false;
                         int u = 0;
                         if (act) {
-                            const uint32_t rec = L.nbr[(size_t)v * D + kk];
+                            const uint32_t rec = L.nbr[(size_t)kk * n + v];
                             u = (int)(rec >> 16);
                             if ((rec & 0xffffu) != 0u && *byteA(u) != *byteB(u)) {
                                 const uint32_t bit = 1u << (u & 31);
@@ -384,7 +387,7 @@ __global__ __launch_bounds__(1024) void pt_kernel(PtArgs a) {
                     dA += -2ll * L.hpos[v] * sA;
                     dB += -2ll * L.hpos[v] * sB;
                     for (int kk = 0; kk < D; ++kk) {
-                        const uint32_t rec = L.nbr[(size_t)v * D + kk];
+                        const uint32_t rec = L.nbr[(size_t)kk * n + v];
                         const int u = (int)(rec >> 16);
                         if (!((vis[u >> 5] >> (u & 31)) & 1u)) {
                             const long long Jv = (int16_t)(rec & 0xffffu);

@@ -19,6 +19,7 @@
 #include "device.hpp"
 #include "internal.hpp"
 #include "sa_core.hpp"
+#include "swar_core.hpp"
 
 namespace spv {
 
@@ -106,15 +107,23 @@ __global__ __launch_bounds__(256) void prep_nbr_kernel(const int32_t *__restrict
     hpos[p] = h[i];
 }
 
+// ND = number of threshold digits; ND = 0 selects the byte-parallel path.
 template <int ND>
 __global__ __launch_bounds__(1024) void sa_kernel(core::SaItem a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int cs[kMaxColours + 1];
-    core::SaLds L;
-    core::sa_layout(a.n, a.D, a.row_len, a.qw, &L, smem);
     a.q0 = blockIdx.x * a.qw;
-    core::sa_load_instance(L, a, cs);
-    core::sa_run<ND>(L, a, cs);
+    if constexpr (ND == 0) {
+        core::SwarLds L;
+        core::swar_layout(a.n, a.D, a.row_len, a.qw, &L, smem);
+        core::swar_load_instance(L, a, cs);
+        core::swar_run(L, a, cs);
+    } else {
+        core::SaLds L;
+        core::sa_layout(a.n, a.D, a.row_len, a.qw, &L, smem);
+        core::sa_load_instance(L, a, cs);
+        core::sa_run<ND>(L, a, cs);
+    }
 }
 
 // Energies of arbitrary states: one workgroup per 64 rows... one thread per (row, variable).
@@ -167,7 +176,19 @@ hipError_t launch_prep(const spv_problem *P, int32_t *image, hipStream_t s) {
     return e;
 }
 
+// The byte-parallel path serves single-digit tables of at most 256 entries
+// (x_bound <= 255); SPVAR_NO_SWAR=1 forces the general path (for comparisons).
+bool sa_use_swar(int nd, int row_len) {
+    static const bool off = [] {
+        const char *v = getenv("SPVAR_NO_SWAR");
+        return v && v[0] == '1';
+    }();
+    return nd == 1 && row_len <= 256 && !off;
+}
+
 size_t sa_lds_bytes(int n, int D, int row_len, int qw) {
+    if (sa_use_swar(1 + (row_len > kDigitSize ? 1 : 0), row_len))
+        return core::swar_layout(n, D, row_len, qw, nullptr, nullptr);
     return core::sa_layout(n, D, row_len, qw, nullptr, nullptr);
 }
 
@@ -193,7 +214,10 @@ hipError_t launch_sa(const SaLaunch &L, hipStream_t s, size_t lds_limit) {
     if (lds > lds_limit) return hipErrorInvalidValue;
     const int quads = (L.reads + 3) / 4;
     const int grid = (quads + L.qw - 1) / L.qw;
-    switch (L.nd) {
+    switch (sa_use_swar(L.nd, L.row_len) ? 0 : L.nd) {
+        case 0:
+            hipLaunchKernelGGL(sa_kernel<0>, dim3(grid), dim3(L.threads), lds, s, a);
+            break;
         case 1:
             hipLaunchKernelGGL(sa_kernel<1>, dim3(grid), dim3(L.threads), lds, s, a);
             break;

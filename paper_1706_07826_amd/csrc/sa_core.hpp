@@ -32,15 +32,18 @@ struct SaLds {
     unsigned long long *E2;  // [4*qw]
 };
 
+// LDS layout for n positions, D records each, quads `qw` (spin capacity n*qw
+// words) and energy accumulators for e2q quads (0: qw).
 __host__ __device__ inline size_t sa_layout(int n, int D, int row_len, int qw, SaLds *L,
-                                            unsigned char *base) {
+                                            unsigned char *base, int e2q = 0) {
+    if (e2q < qw) e2q = qw;
     size_t o_nbr = 0;
     size_t o_h = o_nbr + (size_t)n * D * 4;
     size_t o_ord = o_h + (size_t)n * 4;
     size_t o_tab = o_ord + (size_t)n * 4;
     size_t o_S = o_tab + (size_t)2 * row_len * 4;
     size_t o_E = (o_S + (size_t)n * qw * 4 + 7) & ~(size_t)7;
-    size_t end = o_E + (size_t)4 * qw * 8;
+    size_t end = o_E + (size_t)4 * e2q * 8;
     if (L) {
         L->nbr = reinterpret_cast<uint32_t *>(base + o_nbr);
         L->hpos = reinterpret_cast<int32_t *>(base + o_h);
@@ -67,15 +70,16 @@ struct Fields {
     int32_t f[4];
 };
 
-// f_b = h_p + sum_k J_k s_kb for the four replicas of quad q at position p.
+// f_b = h_p + sum_k J_k s_kb for the four replicas of quad q at position p;
+// nb points at record 0 of p, consecutive records `stride` apart.
 __device__ __forceinline__ Fields local_fields(const uint32_t *__restrict__ nb,
                                                const uint32_t *__restrict__ S, int D, int qw,
-                                               int q, int32_t hv) {
+                                               int q, int32_t hv, int stride) {
     Fields F;
 #pragma unroll
     for (int b = 0; b < 4; ++b) F.f[b] = hv;
     for (int k = 0; k < D; ++k) {
-        const uint32_t rec = nb[k];
+        const uint32_t rec = nb[(size_t)k * stride];
         const int32_t Jv = (int32_t)(int16_t)(rec & 0xffffu);
         const uint32_t w = S[(rec >> 16) * qw + q];
 #pragma unroll
@@ -125,7 +129,10 @@ __device__ inline void sa_load_instance(const SaLds &L, const SaItem &a, int *cs
     const int32_t *img = a.image;
     if (tid <= a.C) cs[tid] = img[3 + tid];
     const uint32_t *recs = reinterpret_cast<const uint32_t *>(img + kImgHeader + 3 * n);
-    for (int k = tid; k < n * D; k += T) L.nbr[k] = recs[k];
+    for (int idx = tid; idx < n * D; idx += T) {  // neighbour-major in LDS: nbr[k][p]
+        const int p = idx / D, k = idx - p * D;
+        L.nbr[(size_t)k * n + p] = recs[idx];
+    }
     for (int k = tid; k < n; k += T) {
         L.hpos[k] = img[kImgHeader + 2 * n + k];
         L.ord[k] = img[kImgHeader + k];
@@ -178,7 +185,7 @@ __device__ void sa_run(const SaLds &L, const SaItem &a, const int *cs) {
             const int pe = cs[c + 1];
             for (int p = cs[c] + slot; active && p < pe; p += nslots) {
                 const uint32_t self = L.S[(size_t)p * qw + q];
-                const Fields F = local_fields(L.nbr + (size_t)p * D, L.S, D, qw, q, L.hpos[p]);
+                const Fields F = local_fields(L.nbr + p, L.S, D, qw, q, L.hpos[p], n);
                 int32_t x[4];
 #pragma unroll
                 for (int b = 0; b < 4; ++b) x[b] = dev::spin_of(self, b) > 0 ? -F.f[b] : F.f[b];
@@ -195,7 +202,7 @@ __device__ void sa_run(const SaLds &L, const SaItem &a, const int *cs) {
         long long e2[4] = {0, 0, 0, 0};
         for (int p = slot; active && p < n; p += nslots) {
             const uint32_t self = L.S[(size_t)p * qw + q];
-            const Fields F = local_fields(L.nbr + (size_t)p * D, L.S, D, qw, q, L.hpos[p]);
+            const Fields F = local_fields(L.nbr + p, L.S, D, qw, q, L.hpos[p], n);
 #pragma unroll
             for (int b = 0; b < 4; ++b)
                 e2[b] += (long long)dev::spin_of(self, b) * ((long long)L.hpos[p] + F.f[b]);

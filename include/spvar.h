@@ -209,8 +209,8 @@ spv_status spv_ispvar(spv_ctx *ctx, const spv_problem *P, const double *betas, i
  * slot; replica exchange of pairs (k,k+1) with k = t (mod 2) in each chain
  * (D = E_k - E_{k+1}; D <= 0 swaps, else the digit test of D with tables of
  * dbeta = beta_{k+1} - beta_k); Houdayer cluster moves between chains 0 and
- * 1 at slots icm_lo..icm_hi-1 (chains == 2); then the colder half
- * (k >= K/2) is offered to per-slot lists of the 10 lowest-energy distinct
+ * 1 at slots icm_lo..icm_hi-1 (chains == 2); then the K/2 coldest slots
+ * (k >= K - K/2) are offered to per-slot lists of the 10 lowest-energy distinct
  * states seen (Sec. III.D.1 sample formation).
  * Replica index r = (run * chains + chain) * K + slot (keyed by slot, so the
  * random stream follows the temperature).
@@ -242,6 +242,21 @@ typedef struct {
 
 spv_status spv_pt_sample(spv_ctx *ctx, const spv_problem *P, const spv_pt_params *params,
                          const spv_pt_out *out, hipStream_t stream);
+
+/*
+ * Sample formation of a tempering run (Sec. III.D.1): the filled entries of
+ * `lists` top-10 lists, concatenated in list order ([runs][chains][K/2] for
+ * the output of spv_pt_sample), each list in its (E, insertion) order.
+ *   top_spins [lists][10][n], top_E [lists][10], top_count [lists]: device
+ *   spins [lists*10][n], energies [lists*10]: device, caller-owned (worst case)
+ *   rows   host: number of rows written
+ * Reads the counts back, so the call returns after the gather is queued and
+ * `stream` has finished the work before it.  SPV_EINVAL for a count outside
+ * 0..10.
+ */
+spv_status spv_top_sample(spv_ctx *ctx, const int8_t *top_spins, const int64_t *top_E,
+                          const int32_t *top_count, int32_t lists, int32_t n, int8_t *spins,
+                          int64_t *energies, int32_t *rows, hipStream_t stream);
 
 /*
  * Batched simulated annealing over B instances of uneven size (the residual
@@ -286,6 +301,73 @@ spv_status spv_sample_batch(spv_ctx *ctx, int32_t B, const spv_problem *problems
  * item, workgroups per CU) and, when it was tuned, the best trial time in ms. */
 spv_status spv_batch_last_shape(const spv_ctx *ctx, int32_t *threads, int32_t *quads_per_item,
                                 int32_t *wgs_per_cu, float *tuned_ms);
+
+/*
+ * Serving loop: continuous batching of sample(+fix) requests of different
+ * sizes.  A server owns `slots` execution slots, each a HIP stream with its own
+ * scratch context.  A submitted request waits in a FIFO until a slot is free
+ * and its LDS and HBM footprints fit the budgets left by the requests in
+ * flight; it is then launched on the slot's stream and overlaps on the device
+ * with the other in-flight requests.  A progress thread retires completed
+ * requests (event query), timestamps them and admits waiting ones as capacity
+ * frees up.  Results depend only on the request (counter-based randomness),
+ * never on what else is in flight.
+ *
+ * Request kinds: SPV_REQ_SA (spv_sample) and SPV_REQ_PT (spv_pt_sample, top-10
+ * sample).  With elite_frac > 0 the persistence step (spv_persist_fix) runs on
+ * the produced sample (SA: all reads; PT: the filled top-10 entries as
+ * assembled by spv_top_sample, once the run has ended) into fix_out.
+ * Every pointer in a request must stay valid until the request completes;
+ * `betas` is copied at submission.
+ */
+typedef enum { SPV_REQ_SA = 1, SPV_REQ_PT = 2 } spv_req_kind;
+
+typedef struct {
+    int32_t kind;
+    spv_problem problem;
+    uint64_t seed;
+    const double *betas;  /* host: SA [sweeps], PT [K] */
+    int32_t sweeps;
+    int32_t reads;        /* SA */
+    int8_t *spins;        /* SA: device [reads][n] */
+    int64_t *energies;    /* SA: device [reads] */
+    int32_t K, runs, chains, icm_lo, icm_hi; /* PT */
+    spv_pt_out pt_out;    /* PT outputs; top_spins/top_E/top_count required for persistence */
+    double elite_frac;    /* > 0 enables persistence */
+    double threshold;
+    int32_t gauge;
+    spv_fix_out fix_out;
+} spv_request;
+
+typedef struct {
+    int32_t slots;        /* requests in flight at most (0 -> 8) */
+    int64_t lds_budget;   /* LDS bytes (workgroups x LDS each) in flight (0 -> CUs x 160 KiB) */
+    int64_t hbm_budget;   /* scratch bytes in flight (0 -> no limit) */
+} spv_server_cfg;
+
+typedef struct {
+    int32_t status;       /* SPV_OK or the request's error */
+    int64_t submit_ns;    /* host steady clock, nanoseconds */
+    int64_t start_ns;     /* launched on a slot */
+    int64_t done_ns;      /* completion observed */
+    int32_t slot;
+    int64_t lds_bytes;    /* footprint charged against the budgets while in flight */
+    int64_t hbm_bytes;
+} spv_result;
+
+typedef struct spv_server spv_server;
+
+spv_status spv_server_create(spv_ctx *ctx, const spv_server_cfg *cfg, spv_server **out);
+/* Queues a request; SPV_EBUDGET if it alone exceeds a budget, SPV_EINVAL if malformed. */
+spv_status spv_server_submit(spv_server *srv, const spv_request *req, uint64_t *ticket);
+/* SPV_EAGAIN while the request is pending or running; else fills *res. */
+spv_status spv_server_poll(spv_server *srv, uint64_t ticket, spv_result *res);
+/* Blocks until the request completes and fills *res. */
+spv_status spv_server_wait(spv_server *srv, uint64_t ticket, spv_result *res);
+/* Blocks until nothing is queued or running. */
+spv_status spv_server_drain(spv_server *srv);
+/* Drains, stops the progress thread and releases the slots. */
+void spv_server_destroy(spv_server *srv);
 
 #ifdef __cplusplus
 }

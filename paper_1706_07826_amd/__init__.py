@@ -83,6 +83,7 @@ _SIGS = {
     "spv_pt_sample": ([_vp, _P, C.POINTER(spv_pt_params), C.POINTER(spv_pt_out), _vp], C.c_int),
     "spv_sample_batch": ([_vp, _i32, _P, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "spv_batch_last_shape": ([_vp, _vp, _vp, _vp, _vp], C.c_int),
+    "spv_top_sample": ([_vp, _vp, _vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp], C.c_int),
 }
 EXPORTED = sorted(_SIGS)
 for _name, (_args, _res) in _SIGS.items():
@@ -310,6 +311,21 @@ def spv_pt_sample(ctx, P, betas, runs, chains, sweeps, seed, sweep_offset=0, icm
     return res
 
 
+def spv_top_sample(ctx, pt, stream=None):
+    """Sample formation of a tempering result (dict from spv_pt_sample): the filled top-10
+    entries concatenated in list order, on the device.  Returns (spins [rows][n], energies)."""
+    tc = pt["top_count"]
+    lists = tc.numel()
+    n = pt["top_spins"].shape[-1]
+    S = torch.empty((lists * TOPK, n), dtype=torch.int8, device=ctx.device)
+    E = torch.empty(max(lists * TOPK, 1), dtype=torch.int64, device=ctx.device)
+    rows = C.c_int32(0)
+    ctx.check(_lib.spv_top_sample(ctx.handle, _ptr(pt["top_spins"]) if n else None, _ptr(pt["top_E"]), _ptr(tc),
+                                  lists, n, _ptr(S) if n else None, _ptr(E), C.byref(rows), _stream(stream)),
+              "spv_top_sample")
+    return S[:rows.value], E[:rows.value]
+
+
 def spv_sample_batch(ctx, problems, betas, reads, seeds, spins=None, energies=None, threads=0,
                      quads_per_item=0, wgs_per_cu=0, graph=False, tune=False, stream=None):
     """Batched SA over many problems in one persistent launch.  Returns (spins, energies) lists
@@ -341,3 +357,140 @@ def spv_batch_last_shape(ctx):
     ctx.check(_lib.spv_batch_last_shape(ctx.handle, C.byref(t), C.byref(q), C.byref(w), C.byref(ms)),
               "spv_batch_last_shape")
     return dict(threads=t.value, quads_per_item=q.value, wgs_per_cu=w.value, tuned_ms=ms.value)
+
+
+# ----------------------------------------------------------------------------- serving
+SPV_REQ_SA, SPV_REQ_PT = 1, 2
+
+
+class spv_request(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("problem", spv_problem), ("seed", C.c_uint64),
+                ("betas", C.c_void_p), ("sweeps", C.c_int32), ("reads", C.c_int32),
+                ("spins", C.c_void_p), ("energies", C.c_void_p), ("K", C.c_int32),
+                ("runs", C.c_int32), ("chains", C.c_int32), ("icm_lo", C.c_int32),
+                ("icm_hi", C.c_int32), ("pt_out", spv_pt_out), ("elite_frac", C.c_double),
+                ("threshold", C.c_double), ("gauge", C.c_int32), ("fix_out", spv_fix_out)]
+
+
+class spv_server_cfg(C.Structure):
+    _fields_ = [("slots", C.c_int32), ("lds_budget", C.c_int64), ("hbm_budget", C.c_int64)]
+
+
+class spv_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("submit_ns", C.c_int64), ("start_ns", C.c_int64),
+                ("done_ns", C.c_int64), ("slot", C.c_int32), ("lds_bytes", C.c_int64),
+                ("hbm_bytes", C.c_int64)]
+
+
+for _name, (_args, _res) in {
+    "spv_server_create": ([_vp, C.POINTER(spv_server_cfg), C.POINTER(_vp)], C.c_int),
+    "spv_server_submit": ([_vp, C.POINTER(spv_request), C.POINTER(C.c_uint64)], C.c_int),
+    "spv_server_poll": ([_vp, C.c_uint64, C.POINTER(spv_result)], C.c_int),
+    "spv_server_wait": ([_vp, C.c_uint64, C.POINTER(spv_result)], C.c_int),
+    "spv_server_drain": ([_vp], C.c_int),
+    "spv_server_destroy": ([_vp], None),
+}.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+    _SIGS[_name] = (_args, _res)
+EXPORTED = sorted(_SIGS)
+
+
+def _fix_buffers(dev, n, nnz):
+    return dict(fixed_mask=torch.empty(max(n, 1), dtype=torch.uint8, device=dev),
+                fixed_val=torch.empty(max(n, 1), dtype=torch.int8, device=dev),
+                row_ptr=torch.empty(n + 1, dtype=torch.int32, device=dev),
+                col=torch.empty(max(nnz, 1), dtype=torch.int32, device=dev),
+                J=torch.empty(max(nnz, 1), dtype=torch.int32, device=dev),
+                h=torch.empty(max(n, 1), dtype=torch.int32, device=dev),
+                colour=torch.empty(max(n, 1), dtype=torch.uint8, device=dev),
+                orig_index=torch.empty(max(n, 1), dtype=torch.int32, device=dev),
+                info=torch.zeros(8, dtype=torch.int64, device=dev))
+
+
+class Server:
+    """Continuous-batching server (spv_server_*).  submit_sa / submit_pt return a ticket;
+    outputs are device tensors kept alive until the request completes."""
+
+    def __init__(self, ctx, slots=8, lds_budget=0, hbm_budget=0):
+        self.ctx = ctx
+        h = C.c_void_p()
+        cfg = spv_server_cfg(int(slots), int(lds_budget), int(hbm_budget))
+        ctx.check(_lib.spv_server_create(ctx.handle, C.byref(cfg), C.byref(h)), "spv_server_create")
+        self.handle = h
+        self.live = {}
+
+    def _submit(self, req, keep):
+        t = C.c_uint64()
+        self.ctx.check(_lib.spv_server_submit(self.handle, C.byref(req), C.byref(t)), "spv_server_submit")
+        self.live[t.value] = keep
+        return t.value
+
+    def _fix(self, req, P, elite_frac, threshold, gauge, keep):
+        if elite_frac and elite_frac > 0:
+            fx = _fix_buffers(self.ctx.device, P.n, P.nnz)
+            req.elite_frac, req.threshold, req.gauge = float(elite_frac), float(threshold), int(gauge)
+            req.fix_out = spv_fix_out(*[fx[k].data_ptr() for k in ("fixed_mask", "fixed_val", "row_ptr", "col",
+                                                                  "J", "h", "colour", "orig_index", "info")])
+            keep["fix"] = fx
+
+    def submit_sa(self, P, betas, reads, seed, elite_frac=0.0, threshold=1.0, gauge=0):
+        b = np.ascontiguousarray(betas, dtype=np.float64)
+        dev = self.ctx.device
+        keep = dict(P=P, betas=b, spins=torch.empty((reads, P.n), dtype=torch.int8, device=dev),
+                    energies=torch.empty(reads, dtype=torch.int64, device=dev))
+        req = spv_request()
+        req.kind, req.problem, req.seed = SPV_REQ_SA, P.c_struct(), C.c_uint64(seed & (2**64 - 1)).value
+        req.betas, req.sweeps, req.reads = b.ctypes.data, b.size, int(reads)
+        req.spins, req.energies = keep["spins"].data_ptr(), keep["energies"].data_ptr()
+        self._fix(req, P, elite_frac, threshold, gauge, keep)
+        return self._submit(req, keep)
+
+    def submit_pt(self, P, betas, runs, chains, sweeps, seed, icm=None, elite_frac=0.0, threshold=1.0,
+                  gauge=0):
+        b = np.ascontiguousarray(betas, dtype=np.float64)
+        K, half, dev = b.size, b.size // 2, self.ctx.device
+        keep = dict(P=P, betas=b,
+                    final_spins=torch.empty((runs, chains, K, P.n), dtype=torch.int8, device=dev),
+                    final_E=torch.empty((runs, chains, K), dtype=torch.int64, device=dev),
+                    top_spins=torch.empty((runs, chains, half, TOPK, P.n), dtype=torch.int8, device=dev),
+                    top_E=torch.empty((runs, chains, half, TOPK), dtype=torch.int64, device=dev),
+                    top_count=torch.empty((runs, chains, half), dtype=torch.int32, device=dev))
+        req = spv_request()
+        req.kind, req.problem, req.seed = SPV_REQ_PT, P.c_struct(), C.c_uint64(seed & (2**64 - 1)).value
+        req.betas, req.sweeps, req.K, req.runs, req.chains = b.ctypes.data, int(sweeps), K, int(runs), int(chains)
+        req.icm_lo, req.icm_hi = (0, 0) if icm is None else icm
+        req.pt_out = spv_pt_out(*[keep[k].data_ptr() for k in ("final_spins", "final_E", "top_spins", "top_E",
+                                                               "top_count")])
+        self._fix(req, P, elite_frac, threshold, gauge, keep)
+        return self._submit(req, keep)
+
+    def poll(self, ticket):
+        r = spv_result()
+        rc = _lib.spv_server_poll(self.handle, ticket, C.byref(r))
+        if rc == -8:
+            return None
+        self.ctx.check(rc, "spv_server_poll")
+        return r
+
+    def wait(self, ticket):
+        r = spv_result()
+        self.ctx.check(_lib.spv_server_wait(self.handle, ticket, C.byref(r)), "spv_server_wait")
+        if r.status != 0:
+            raise SpvError(r.status, "request failed")
+        return r, self.live[ticket]
+
+    def drain(self):
+        self.ctx.check(_lib.spv_server_drain(self.handle), "spv_server_drain")
+
+    def close(self):
+        if self.handle:
+            _lib.spv_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

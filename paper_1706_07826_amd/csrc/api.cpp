@@ -33,8 +33,9 @@ spv_status hip_check(Ctx *c, hipError_t e, const char *what) {
 spv_status ensure(Ctx *c, DevBuf &b, size_t bytes) {
     if (bytes == 0) bytes = 8;
     if (b.bytes >= bytes) return SPV_OK;
-    // Growing scratch that earlier work may still read: drain the device first.
-    hipError_t e = hipDeviceSynchronize();
+    // Growing scratch that earlier work may still read: drain the device (or,
+    // for a stream-private context, its own stream) first.
+    hipError_t e = c->stream_private ? hipStreamSynchronize(c->own_stream) : hipDeviceSynchronize();
     if (e != hipSuccess) return hip_check(c, e, "hipDeviceSynchronize");
     if (b.p) (void)hipFree(b.p);
     b.p = nullptr;
@@ -127,11 +128,7 @@ spv_status upload_tables(Ctx *c, DevBuf &dst, const double *betas, int count, in
             for (int d = 0; d < kDigitSize && j * kDigitSize + d < row_len; ++d)
                 row[j * kDigitSize + d] = threshold_word(betas[k], unit, scale, j, (uint32_t)d);
     }
-    // The previous upload may still be in flight on another stream.
-    hipError_t e = hipDeviceSynchronize();
-    if (e == hipSuccess) e = hipMemcpy(dst.p, c->host_tables.data(), words * 4, hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_check(c, e, "table upload");
-    (void)s;
+    if ((st = upload(c, dst, 0, c->host_tables.data(), words * 4, s))) return st;
     if (&dst == &c->tables) {
         tc.betas.assign(betas, betas + count);
         tc.scale = scale;
@@ -140,6 +137,38 @@ spv_status upload_tables(Ctx *c, DevBuf &dst, const double *betas, int count, in
         tc.unit = unit;
     }
     return SPV_OK;
+}
+
+spv_status upload(Ctx *c, DevBuf &dst, size_t dst_off, const void *src, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return SPV_OK;
+    spv_status st = ensure(c, dst, dst_off + bytes);
+    if (st) return st;
+    hipError_t e;
+    if (!c->stream_private) {
+        // Earlier work on any stream may still read this buffer.
+        e = hipDeviceSynchronize();
+        if (e == hipSuccess)
+            e = hipMemcpy(static_cast<unsigned char *>(dst.p) + dst_off, src, bytes, hipMemcpyHostToDevice);
+        return hip_check(c, e, "upload");
+    }
+    // Stream-private: the previous staged copy must have left the staging buffer;
+    // earlier kernels on the same stream are ordered before this copy.
+    if (c->stage_done && (e = hipEventSynchronize(c->stage_done)) != hipSuccess)
+        return hip_check(c, e, "staging event");
+    if (c->stage_bytes < bytes) {
+        if (c->stage) (void)hipHostFree(c->stage);
+        c->stage = nullptr;
+        c->stage_bytes = 0;
+        if ((e = hipHostMalloc(&c->stage, bytes, hipHostMallocDefault)) != hipSuccess)
+            return set_err(c, SPV_ENOMEM, "hipHostMalloc(%zu)", bytes);
+        c->stage_bytes = bytes;
+    }
+    if (!c->stage_done && (e = hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming)) != hipSuccess)
+        return hip_check(c, e, "event create");
+    std::memcpy(c->stage, src, bytes);
+    e = hipMemcpyAsync(static_cast<unsigned char *>(dst.p) + dst_off, c->stage, bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventRecord(c->stage_done, s);
+    return hip_check(c, e, "upload");
 }
 
 int sa_threads_env() {
@@ -183,8 +212,10 @@ void spv_ctx_destroy(spv_ctx *ctx) {
     DeviceGuard g(ctx->c.device);
     (void)hipDeviceSynchronize();
     batch_release(&ctx->c);
+    if (ctx->c.stage) (void)hipHostFree(ctx->c.stage);
+    if (ctx->c.stage_done) (void)hipEventDestroy(ctx->c.stage_done);
     for (DevBuf *b : {&ctx->c.image, &ctx->c.tables, &ctx->c.tables2, &ctx->c.scratch, &ctx->c.scratch2,
-                      &ctx->c.rounds, &ctx->c.pt})
+                      &ctx->c.rounds, &ctx->c.pt, &ctx->c.top, &ctx->c.serve})
         if (b->p) (void)hipFree(b->p);
     delete ctx;
 }
@@ -520,12 +551,15 @@ spv_status spv_pt_sample(spv_ctx *ctx, const spv_problem *P, const spv_pt_params
     if (st) return st;
     st = ensure(c, c->image, image_words(std::max(n, 1), D) * 4);
     if (st) return st;
+    {
+        std::vector<unsigned char> blob(b_mt + b_st + b_snd, 0);
+        std::memcpy(blob.data(), mt.data(), mt.size() * 4);
+        std::memcpy(blob.data() + b_mt, stt.data(), stt.size() * 4);
+        std::memcpy(blob.data() + b_mt + b_st, snd.data(), snd.size() * 4);
+        if ((st = upload(c, c->pt, 0, blob.data(), blob.size(), stream))) return st;
+    }
     unsigned char *base = static_cast<unsigned char *>(c->pt.p);
-    hipError_t e = hipStreamSynchronize(stream);  // earlier work on this stream may read the tables
-    if (e == hipSuccess) e = hipMemcpy(base, mt.data(), mt.size() * 4, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(base + b_mt, stt.data(), stt.size() * 4, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(base + b_mt + b_st, snd.data(), snd.size() * 4, hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_check(c, e, "PT table upload");
+    hipError_t e = hipSuccess;
     spv_problem Pp = *P;
     Pp.max_degree = D;
     e = launch_prep(&Pp, static_cast<int32_t *>(c->image.p), stream);
@@ -554,6 +588,36 @@ spv_status spv_pt_sample(spv_ctx *ctx, const spv_problem *P, const spv_pt_params
     L.nqa = nqa;
     L.threads = threads;
     return hip_check(c, launch_pt(L, stream), "pt launch");
+}
+
+spv_status spv_top_sample(spv_ctx *ctx, const int8_t *top_spins, const int64_t *top_E,
+                          const int32_t *top_count, int32_t lists, int32_t n, int8_t *spins,
+                          int64_t *energies, int32_t *rows, hipStream_t stream) {
+    if (!ctx) return SPV_EINVAL;
+    Ctx *c = &ctx->c;
+    DeviceGuard g(c->device);
+    if (!rows || lists < 0 || n < 0) return set_err(c, SPV_EINVAL, "spv_top_sample: lists=%d n=%d", lists, n);
+    *rows = 0;
+    if (lists == 0) return SPV_OK;
+    if (!top_E || !top_count || !energies || (n > 0 && (!top_spins || !spins)))
+        return set_err(c, SPV_EINVAL, "spv_top_sample: null buffer");
+    std::vector<int32_t> cnt(lists), off(lists);
+    hipError_t e = hipMemcpyAsync(cnt.data(), top_count, 4ull * lists, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_check(c, e, "top_count read");
+    int32_t total = 0;
+    for (int l = 0; l < lists; ++l) {
+        if (cnt[l] < 0 || cnt[l] > kTopK) return set_err(c, SPV_EINVAL, "top_count[%d] = %d", l, cnt[l]);
+        off[l] = total;
+        total += cnt[l];
+    }
+    spv_status st = upload(c, c->top, 0, off.data(), 4ull * lists, stream);
+    if (st) return st;
+    e = launch_top_gather(top_spins, top_E, top_count, static_cast<const int32_t *>(c->top.p), lists, n,
+                          spins, energies, stream);
+    if (e != hipSuccess) return hip_check(c, e, "top gather launch");
+    *rows = total;
+    return SPV_OK;
 }
 
 }  // extern "C"

@@ -57,6 +57,8 @@ struct Ctx {
     DevBuf rounds;  // iterated-SPVAR working set
     DevBuf pt;      // parallel-tempering tables and top-10 storage
     DevBuf batch;   // batched launch: descriptors, items, counter, images
+    DevBuf top;     // sample assembly: per-list offsets
+    DevBuf serve;   // serving slot: assembled tempering sample
     TableCache tcache;
     std::vector<uint32_t> host_tables;
     void *batch_host = nullptr;  // pinned staging of descriptors and items
@@ -77,7 +79,18 @@ struct Ctx {
     std::vector<TuneEntry> tuned;
     int last_shape[3] = {0, 0, 0};
     float last_tuned_ms = -1.f;
+    // A context owned by one stream (serving slots) uploads tables
+    // stream-ordered through pinned staging instead of draining the device.
+    bool stream_private = false;
+    hipStream_t own_stream = nullptr;
+    void *stage = nullptr;
+    size_t stage_bytes = 0;
+    hipEvent_t stage_done = nullptr;
 };
+
+// Host -> device copy of `bytes` into dst (grown as needed): stream-ordered
+// through pinned staging for stream-private contexts, synchronous otherwise.
+spv_status upload(Ctx *c, DevBuf &dst, size_t dst_off, const void *src, size_t bytes, hipStream_t s);
 
 void batch_release(Ctx *c);
 
@@ -149,6 +162,8 @@ hipError_t launch_compose(int n_cur, const uint8_t *fm_round, const int8_t *fv_r
                           hipStream_t s);
 hipError_t launch_iota(int n, int32_t *a, uint8_t *fm, int8_t *fv, hipStream_t s);
 hipError_t launch_persist_fix(const FixLaunch &L, hipStream_t s);
+hipError_t launch_top_gather(const int8_t *ts, const int64_t *te, const int32_t *cnt, const int32_t *off,
+                             int lists, int n, int8_t *S, int64_t *E, hipStream_t s);
 
 // Device descriptor of one instance of a batched launch.
 struct BatchInst {

@@ -443,6 +443,30 @@ hipError_t launch_compose(int n_cur, const uint8_t *fm_round, const int8_t *fv_r
     return hipGetLastError();
 }
 
+// Sample assembly of a tempering run: the filled entries of every top-10 list,
+// concatenated in list order (one workgroup per list; off = exclusive prefix of
+// the counts).
+__global__ __launch_bounds__(256) void top_gather_kernel(const int8_t *__restrict__ ts,
+                                                         const long long *__restrict__ te,
+                                                         const int32_t *__restrict__ cnt,
+                                                         const int32_t *__restrict__ off, int n,
+                                                         int8_t *__restrict__ S, long long *__restrict__ E) {
+    const int l = blockIdx.x;
+    const int c = cnt[l];
+    const size_t src = (size_t)l * 10, dst = (size_t)off[l];
+    for (int k = threadIdx.x; k < c; k += blockDim.x) E[dst + k] = te[src + k];
+    const size_t bytes = (size_t)c * n;
+    for (size_t b = threadIdx.x; b < bytes; b += blockDim.x) S[dst * n + b] = ts[src * n + b];
+}
+
+hipError_t launch_top_gather(const int8_t *ts, const int64_t *te, const int32_t *cnt, const int32_t *off,
+                             int lists, int n, int8_t *S, int64_t *E, hipStream_t s) {
+    if (lists <= 0) return hipSuccess;
+    hipLaunchKernelGGL(top_gather_kernel, dim3(lists), dim3(256), 0, s, ts, (const long long *)te, cnt,
+                       off, n, S, (long long *)E);
+    return hipGetLastError();
+}
+
 hipError_t launch_iota(int n, int32_t *a, uint8_t *fm, int8_t *fv, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(iota_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, a, fm, fv);

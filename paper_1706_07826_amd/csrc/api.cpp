@@ -171,6 +171,61 @@ spv_status upload(Ctx *c, DevBuf &dst, size_t dst_off, const void *src, size_t b
     return hip_check(c, e, "upload");
 }
 
+// Ladder split of a tempering job (see the split kernel): whether to use it,
+// the group count G and size m, the workgroup shape and whether the instance
+// stays in LDS.  SPVAR_PT_SPLIT=0 disables it, =1 forces it (K % 4 == 0);
+// SPVAR_PT_GROUPS fixes G; SPVAR_PT_BIG=1 reads the instance from global
+// memory even when it would fit in LDS.
+static int env_int(const char *name, int dflt) {
+    const char *v = getenv(name);
+    return v && *v ? atoi(v) : dflt;
+}
+
+unsigned pt_spin_limit() { return (unsigned)env_int("SPVAR_PT_SPIN", 1 << 24); }
+
+spv_status plan_pt_split(Ctx *c, int n, int D, int K, int runs, int chains, int row_len, int nd, int icm_lo,
+                         int icm_hi, bool single_fits, PtSplit *sp) {
+    sp->use = false;
+    const int mode = env_int("SPVAR_PT_SPLIT", -1);
+    if (mode == 0 || K % 4 != 0 || n < 1) return SPV_OK;
+    const int maxg = K / 4;
+    int G = env_int("SPVAR_PT_GROUPS", 0);
+    if (G <= 0) G = std::max(1, std::min(maxg, c->num_cus / std::max(runs, 1)));
+    G = std::min(G, maxg);
+    if (mode != 1 && single_fits && G == 1) return SPV_OK;
+    for (;; ++G) {
+        if (G > maxg)
+            return set_err(c, SPV_ECAPACITY, "PT run does not fit even split into %d groups (n=%d)", maxg, n);
+        const int m = 4 * ((maxg + G - 1) / G);
+        const int Gr = (K + m - 1) / m;
+        const int nq = chains * m / 4;
+        const long long tasks = (long long)n * nq;
+        int threads = tasks >= 8192 ? 1024 : tasks >= 2048 ? 512 : 256;
+        while (threads < nq) threads *= 2;
+        if (threads > 1024) continue;
+        const int icm_slots = icm_hi > icm_lo ? std::min(m, icm_hi - icm_lo) : 0;
+        for (int big = env_int("SPVAR_PT_BIG", 0) ? 1 : 0; big < 2; ++big) {
+            for (int nw = std::min(threads / 64, icm_slots); nw >= (icm_slots ? 1 : 0); --nw) {
+                const size_t lds = ptx_lds_bytes(n, D, m, chains, row_len, nw, big != 0) + 256;
+                if (lds > c->lds_max) continue;
+                int bpc = 0;
+                hipError_t e = ptx_max_groups_resident(nd, big != 0, threads, lds, &bpc);
+                if (e != hipSuccess) return hip_check(c, e, "occupancy query");
+                if ((long long)bpc * c->num_cus < (long long)runs * Gr)
+                    return set_err(c, SPV_ECAPACITY, "split PT grid %d x %d exceeds %d resident workgroups", runs,
+                                   Gr, bpc * c->num_cus);
+                sp->use = true;
+                sp->G = Gr;
+                sp->m = m;
+                sp->threads = threads;
+                sp->nw_icm = nw;
+                sp->big = big != 0;
+                return SPV_OK;
+            }
+        }
+    }
+}
+
 int sa_threads_env() {
     const char *v = getenv("SPVAR_SA_THREADS");
     return v ? atoi(v) : 0;
@@ -528,7 +583,11 @@ spv_status spv_pt_sample(spv_ctx *ctx, const spv_problem *P, const spv_pt_params
     int threads = (n * nqa >= 4096) ? 1024 : 256;
     const int nw_icm = icm ? std::min(threads / 64, prm->icm_hi - prm->icm_lo) : 0;
     const size_t lds = pt_lds_bytes(n, D, K, chains, row_len, nqa, nw_icm) + 256;
-    if (lds > c->lds_max)
+    PtSplit sp;
+    if ((st = plan_pt_split(c, n, D, K, runs, chains, row_len, nd, icm ? prm->icm_lo : 0, icm ? prm->icm_hi : 0,
+                            lds <= c->lds_max, &sp)))
+        return st;
+    if (!sp.use && lds > c->lds_max)
         return set_err(c, SPV_ECAPACITY, "PT run needs %zu B of LDS > %zu (n=%d, %d replicas)", lds, c->lds_max, n, cK);
     // Device tables: Metropolis rows per slot, swap rows per pair, swap digit counts.
     std::vector<uint32_t> mt((size_t)K * row_len), stt((size_t)std::max(K - 1, 1) * 7 * kDigitSize, 0u);
@@ -547,7 +606,10 @@ spv_status spv_pt_sample(spv_ctx *ctx, const spv_problem *P, const spv_pt_params
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
     const size_t b_mt = al(mt.size() * 4), b_st = al(stt.size() * 4), b_snd = al(snd.size() * 4);
     const size_t b_top = al((size_t)runs * std::max(Ls, 1) * 10 * std::max(n, 1));
-    st = ensure(c, c->pt, b_mt + b_st + b_snd + b_top);
+    const size_t n_grp = sp.use ? (size_t)runs * sp.G : 0;
+    const size_t b_xs = al(n_grp * 4 * chains * std::max(n, 1)), b_xe = al(n_grp * 4 * chains * 8),
+                 b_fl = al(n_grp * 4);
+    st = ensure(c, c->pt, b_mt + b_st + b_snd + b_top + b_xs + b_xe + b_fl);
     if (st) return st;
     st = ensure(c, c->image, image_words(std::max(n, 1), D) * 4);
     if (st) return st;
@@ -564,6 +626,39 @@ spv_status spv_pt_sample(spv_ctx *ctx, const spv_problem *P, const spv_pt_params
     Pp.max_degree = D;
     e = launch_prep(&Pp, static_cast<int32_t *>(c->image.p), stream);
     if (e != hipSuccess) return hip_check(c, e, "prep launch");
+    if (sp.use) {
+        PtxLaunch X;
+        X.image = static_cast<const int32_t *>(c->image.p);
+        X.n = n;
+        X.D = D;
+        X.C = P->n_colours;
+        X.K = K;
+        X.runs = runs;
+        X.chains = chains;
+        X.sweeps = prm->sweeps;
+        X.sweep_offset = prm->sweep_offset;
+        X.seed = prm->seed;
+        X.icm_lo = icm ? prm->icm_lo : 0;
+        X.icm_hi = icm ? prm->icm_hi : 0;
+        X.nw_icm = sp.nw_icm;
+        X.mtab = reinterpret_cast<const uint32_t *>(base);
+        X.row_len = row_len;
+        X.nd = nd;
+        X.stab = reinterpret_cast<const uint32_t *>(base + b_mt);
+        X.snd = reinterpret_cast<const int32_t *>(base + b_mt + b_st);
+        X.out = out;
+        unsigned char *sc = base + b_mt + b_st + b_snd;
+        X.tops = reinterpret_cast<int8_t *>(sc);
+        X.xs = sc + b_top;
+        X.xe = reinterpret_cast<int64_t *>(sc + b_top + b_xs);
+        X.flags = reinterpret_cast<int *>(sc + b_top + b_xs + b_xe);
+        X.G = sp.G;
+        X.m = sp.m;
+        X.threads = sp.threads;
+        X.big = sp.big;
+        X.spin_limit = pt_spin_limit();
+        return hip_check(c, launch_ptx(X, stream), "split pt launch");
+    }
     PtLaunch L;
     L.image = static_cast<const int32_t *>(c->image.p);
     L.n = n;

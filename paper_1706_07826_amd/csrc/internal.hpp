@@ -214,6 +214,39 @@ struct PtLaunch {
 size_t pt_lds_bytes(int n, int D, int K, int chains, int row_len, int nqa, int nw_icm);
 hipError_t launch_pt(const PtLaunch &L, hipStream_t s);
 
+// Tempering with each run's ladder split into G groups of m slots, one
+// workgroup per (run, group); `big` reads the instance from the global image.
+struct PtxLaunch {
+    const int32_t *image;
+    int n, D, C;
+    int K, runs, chains, sweeps;
+    uint32_t sweep_offset;
+    uint64_t seed;
+    int icm_lo, icm_hi, nw_icm;
+    const uint32_t *mtab;
+    int row_len, nd;
+    const uint32_t *stab;
+    const int32_t *snd;
+    const spv_pt_out *out;
+    int8_t *tops;             // [runs][Ls][10][n]
+    unsigned char *xs;        // [runs][G][2][2][chains][n]
+    int64_t *xe;              // [runs][G][2][2][chains]
+    int *flags;               // [runs][G]
+    int G, m, threads;
+    bool big;
+    unsigned spin_limit;
+};
+struct PtSplit {
+    bool use = false, big = false;
+    int G = 1, m = 0, threads = 256, nw_icm = 0;
+};
+spv_status plan_pt_split(Ctx *c, int n, int D, int K, int runs, int chains, int row_len, int nd, int icm_lo,
+                         int icm_hi, bool single_fits, PtSplit *sp);
+unsigned pt_spin_limit();
+size_t ptx_lds_bytes(int n, int D, int m, int chains, int row_len, int nw_icm, bool big);
+hipError_t ptx_max_groups_resident(int nd, bool big, int threads, size_t lds, int *blocks_per_cu);
+hipError_t launch_ptx(const PtxLaunch &L, hipStream_t s);
+
 }  // namespace spv
 
 // The opaque context handle of the ABI.

@@ -1,0 +1,674 @@
+// Parallel tempering with each run's ladder split over several workgroups
+// (Sec. III.D.1 "PTICM" at sizes where one run does not fit one workgroup, or
+// where there are too few runs to fill the device).
+//
+// A run's K slots are cut into G groups of m consecutive slots (m a multiple
+// of 4, so every quad of 4 replicas of the replica index r = (run * chains +
+// chain) * K + slot lies inside one group).  Workgroup (run, g) holds the
+// group's slots of EVERY chain, so the Houdayer partners (chain 0 and chain 1
+// at one slot) share its LDS.  A sweep is
+//   1. Metropolis on the group's replicas (colour classes in order),
+//   2. replica exchange of pairs (k, k+1), k = t mod 2.  With m even, pairs
+//      inside the group are decided from LDS energies and swapped byte-wise;
+//      on odd sweeps the two pairs that straddle a group boundary are decided
+//      by both neighbours from the energies each publishes (with the two edge
+//      configurations) in an L2-resident exchange slot, after a release /
+//      acquire flag handshake between the two workgroups; an accepted pair
+//      copies the partner's published configuration in,
+//   3. Houdayer moves at the group's slots, a wavefront per slot pair,
+//   4. the top-10 offers of the group's colder slots.
+// The instance lives in LDS when it fits beside the replicas; otherwise the
+// neighbour records, biases and orderings are read from the global image
+// (shared by every workgroup, L2-resident).
+//
+// Neighbour waits are bounded: a workgroup whose neighbour does not publish
+// within the spin limit stops and marks its lists with top_count = -1.  The
+// host only launches grids that fit on the device at once.
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+#include "internal.hpp"
+#include "pt_core.hpp"
+
+namespace spv {
+
+namespace {
+
+using ptc::lanemask_lt;
+using ptc::swap_test;
+using ptc::wave_sum;
+
+struct PtxArgs {
+    const int32_t *image;
+    const uint32_t *mtab;  // [K][row_len]
+    const uint32_t *stab;  // [K-1][7*512]
+    const int32_t *snd;    // [K-1]
+    int8_t *final_spins;
+    long long *final_E;
+    int8_t *top_spins;
+    long long *top_E;
+    int32_t *top_count;
+    int8_t *tops;          // [runs][Ls][10][n], position order
+    unsigned char *xs;     // [runs][G][side 2][buf 2][chains][n] edge configurations
+    long long *xe;         // [runs][G][side 2][buf 2][chains] edge energies
+    int *flags;            // [runs][G] local sweep count of the last publication
+    int n, D, C, K, chains, sweeps, row_len, icm_lo, icm_hi, nw_icm, G, m;
+    uint32_t sweep_offset, k0, k1;
+    unsigned spin_limit;
+};
+
+struct PtxLds {
+    uint32_t *nbr;      // [D][n]   (LDS-resident instance)
+    int32_t *hpos;      // [n]      (LDS-resident instance)
+    int32_t *ord;       // [n]      (LDS-resident instance)
+    int32_t *pos;       // [n]      (LDS-resident instance)
+    uint32_t *tab;      // [m][row_len]
+    uint32_t *S;        // [n][nq]
+    unsigned char *Sb;
+    long long *E;       // [chains*m]
+    long long *LE;      // [chains*m][10]
+    int32_t *Lwhen;     // [chains*m][10]
+    int32_t *Lcnt;      // [chains*m]
+    int32_t *Lord;      // [chains*m][10]
+    int32_t *acc;       // [chains*m]
+    int32_t *cin;       // [2*chains] accepted boundary pairs (side, chain)
+    uint32_t *vis;      // [nw_icm][nwords]
+    uint16_t *queue;    // [nw_icm][n]
+};
+
+__host__ __device__ inline size_t ptx_layout(int n, int D, int m, int chains, int row_len, int nw_icm, bool big,
+                                             PtxLds *L, unsigned char *base) {
+    const int nq = chains * m / 4, nl = chains * m, nwords = (n + 31) / 32;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = (o + bytes + 15) & ~(size_t)15;
+        return at;
+    };
+    const size_t in_lds = big ? 0 : 1;
+    const size_t o_nbr = take(in_lds * n * D * 4), o_h = take(in_lds * n * 4), o_ord = take(in_lds * n * 4),
+                 o_pos = take(in_lds * n * 4), o_tab = take((size_t)m * row_len * 4), o_S = take((size_t)n * nq * 4),
+                 o_E = take((size_t)nl * 8), o_LE = take((size_t)nl * 80), o_Lw = take((size_t)nl * 40),
+                 o_Lc = take((size_t)nl * 4), o_Lo = take((size_t)nl * 40), o_acc = take((size_t)nl * 4),
+                 o_cin = take((size_t)2 * chains * 4), o_vis = take((size_t)nw_icm * nwords * 4),
+                 o_q = take((size_t)nw_icm * n * 2);
+    if (L) {
+        L->nbr = reinterpret_cast<uint32_t *>(base + o_nbr);
+        L->hpos = reinterpret_cast<int32_t *>(base + o_h);
+        L->ord = reinterpret_cast<int32_t *>(base + o_ord);
+        L->pos = reinterpret_cast<int32_t *>(base + o_pos);
+        L->tab = reinterpret_cast<uint32_t *>(base + o_tab);
+        L->S = reinterpret_cast<uint32_t *>(base + o_S);
+        L->Sb = base + o_S;
+        L->E = reinterpret_cast<long long *>(base + o_E);
+        L->LE = reinterpret_cast<long long *>(base + o_LE);
+        L->Lwhen = reinterpret_cast<int32_t *>(base + o_Lw);
+        L->Lcnt = reinterpret_cast<int32_t *>(base + o_Lc);
+        L->Lord = reinterpret_cast<int32_t *>(base + o_Lo);
+        L->acc = reinterpret_cast<int32_t *>(base + o_acc);
+        L->cin = reinterpret_cast<int32_t *>(base + o_cin);
+        L->vis = reinterpret_cast<uint32_t *>(base + o_vis);
+        L->queue = reinterpret_cast<uint16_t *>(base + o_q);
+    }
+    return o;
+}
+
+__global__ void flags_zero_kernel(int *f, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) f[i] = 0;
+}
+
+template <int ND, bool BIG>
+__global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int cs[kMaxColours + 1];
+    __shared__ int nacc;
+    __shared__ int stop;
+    PtxLds L;
+    const int n = a.n, D = a.D, K = a.K, chains = a.chains, G = a.G, row_len = a.row_len;
+    ptx_layout(n, D, a.m, chains, row_len, a.nw_icm, BIG, &L, smem);
+    const int tid = threadIdx.x, T = blockDim.x, lane = dev::lane_id(), wid = tid >> 6, nw = T >> 6;
+    const int run = blockIdx.x / G, g = blockIdx.x - run * G;
+    const int s0 = g * a.m, mg = min(a.m, K - s0), qpc = mg >> 2, nq = chains * qpc, nl = chains * mg;
+    const int half = K / 2, Ls = chains * half, nwords = (n + 31) / 32;
+    const int32_t *img = a.image;
+    const uint32_t *gnbr = reinterpret_cast<const uint32_t *>(img + kImgHeader + 3 * n);
+    const int32_t *gord = img + kImgHeader, *gpos = img + kImgHeader + n, *ghpos = img + kImgHeader + 2 * n;
+    auto NBR = [&](int k, int p) -> uint32_t { return BIG ? gnbr[(size_t)p * D + k] : L.nbr[(size_t)k * n + p]; };
+    auto HPOS = [&](int p) -> int32_t { return BIG ? ghpos[p] : L.hpos[p]; };
+    auto ORD = [&](int p) -> int32_t { return BIG ? gord[p] : L.ord[p]; };
+    auto POS = [&](int i) -> int32_t { return BIG ? gpos[i] : L.pos[i]; };
+    // byte of local replica l = chain * mg + (slot - s0) at position p
+    auto sbyte = [&](int l, int p) -> unsigned char * {
+        const int ch = l / mg, o = l - ch * mg;
+        return L.Sb + ((size_t)p * nq + ch * qpc + (o >> 2)) * 4 + (o & 3);
+    };
+
+    if (tid <= a.C) cs[tid] = img[3 + tid];
+    if (tid == 0) stop = 0;
+    if (!BIG) {
+        for (int idx = tid; idx < n * D; idx += T) {
+            const int p = idx / D, k = idx - p * D;
+            L.nbr[(size_t)k * n + p] = gnbr[idx];
+        }
+        for (int k = tid; k < n; k += T) {
+            L.ord[k] = gord[k];
+            L.pos[k] = gpos[k];
+            L.hpos[k] = ghpos[k];
+        }
+    }
+    for (int k = tid; k < mg * row_len; k += T) L.tab[k] = a.mtab[(size_t)s0 * row_len + k];
+    for (int k = tid; k < nl; k += T) {
+        L.E[k] = 0;
+        L.Lcnt[k] = 0;
+    }
+    __syncthreads();
+
+    const int q = tid % nq, pt = tid / nq, nstr = T / nq;
+    const bool active = pt < nstr;
+    const int chq = q / qpc, jq = q - chq * qpc;
+    const uint32_t quad = (uint32_t)((((size_t)run * chains + chq) * K + s0) / 4 + jq);
+    int loc[4];
+    const uint32_t *tb[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        loc[b] = chq * mg + 4 * jq + b;
+        tb[b] = L.tab + (size_t)(4 * jq + b) * row_len;
+    }
+    const bool pow2 = (nq & (nq - 1)) == 0 && nq <= 64;
+
+    // Initial state and energies.
+    for (int p = pt; active && p < n; p += nstr) {
+        const dev::Words4 w = dev::philox((uint32_t)ORD(p), 0u, quad, 1u << 24, a.k0, a.k1);
+        uint32_t word = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) word |= ((w.w[b] >> 31) ? 0x01u : 0xFFu) << (8 * b);
+        L.S[(size_t)p * nq + q] = word;
+    }
+    __syncthreads();
+    {
+        long long e2[4] = {0, 0, 0, 0};
+        for (int p = pt; active && p < n; p += nstr) {
+            const uint32_t self = L.S[(size_t)p * nq + q];
+            const int32_t hp = HPOS(p);
+            int32_t f[4] = {hp, hp, hp, hp};
+            for (int k = 0; k < D; ++k) {
+                const uint32_t rec = NBR(k, p);
+                const int32_t Jv = (int32_t)(int16_t)(rec & 0xffffu);
+                const uint32_t w = L.S[(rec >> 16) * nq + q];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) f[b] += Jv * dev::spin_of(w, b);
+            }
+#pragma unroll
+            for (int b = 0; b < 4; ++b) e2[b] += (long long)dev::spin_of(self, b) * ((long long)hp + f[b]);
+        }
+        if (active)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                atomicAdd(reinterpret_cast<unsigned long long *>(&L.E[loc[b]]), (unsigned long long)e2[b]);
+    }
+    __syncthreads();
+    for (int l = tid; l < nl; l += T) L.E[l] /= 2;  // sum of s(h + f) counts every coupler twice
+    __syncthreads();
+
+    for (int ls = 0; ls < a.sweeps; ++ls) {
+        const uint32_t t = a.sweep_offset + (uint32_t)ls;
+        // 1. Metropolis on the group's replicas.
+        long long dE[4] = {0, 0, 0, 0};
+        for (int c = 0; c < a.C; ++c) {
+            const int pe = cs[c + 1];
+            for (int p = cs[c] + pt; active && p < pe; p += nstr) {
+                const uint32_t self = L.S[(size_t)p * nq + q];
+                const int32_t hp = HPOS(p);
+                int32_t f[4] = {hp, hp, hp, hp};
+                for (int k = 0; k < D; ++k) {
+                    const uint32_t rec = NBR(k, p);
+                    const int32_t Jv = (int32_t)(int16_t)(rec & 0xffffu);
+                    const uint32_t w = L.S[(rec >> 16) * nq + q];
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) f[b] += Jv * dev::spin_of(w, b);
+                }
+                int32_t x[4];
+                bool up[4], pass[4];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    x[b] = dev::spin_of(self, b) > 0 ? -f[b] : f[b];
+                    up[b] = x[b] > 0;
+                    pass[b] = true;
+                }
+                const uint32_t i = (uint32_t)ORD(p);
+#pragma unroll
+                for (int j = 0; j < ND; ++j) {
+                    uint32_t d[4];
+                    bool need = false;
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        d[b] = up[b] ? (((uint32_t)x[b] >> (kDigitBits * j)) & (kDigitSize - 1)) : 0u;
+                        need |= pass[b] && d[b] != 0;
+                    }
+                    if (need) {
+                        const dev::Words4 w = dev::philox(i, t, quad, (2u << 24) | (uint32_t)j, a.k0, a.k1);
+#pragma unroll
+                        for (int b = 0; b < 4; ++b)
+                            if (d[b] != 0) pass[b] = pass[b] && (w.w[b] < tb[b][j * kDigitSize + d[b]]);
+                    }
+                }
+                uint32_t mask = 0;
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    if (!up[b] || pass[b]) {
+                        mask |= 0xFEu << (8 * b);
+                        dE[b] += 2ll * x[b];
+                    }
+                if (mask) L.S[(size_t)p * nq + q] = self ^ mask;
+            }
+            __syncthreads();
+        }
+        if (pow2) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                for (int off = nq; off < 64; off <<= 1) dE[b] += __shfl_xor(dE[b], off, 64);
+            if (active && lane < nq)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    if (dE[b]) atomicAdd(reinterpret_cast<unsigned long long *>(&L.E[loc[b]]), (unsigned long long)dE[b]);
+        } else if (active) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                if (dE[b]) atomicAdd(reinterpret_cast<unsigned long long *>(&L.E[loc[b]]), (unsigned long long)dE[b]);
+        }
+        if (tid == 0) nacc = 0;
+        if (tid < 2 * chains) L.cin[tid] = 0;
+        __syncthreads();
+
+        // 2. Replica exchange.
+        const int par = (int)(t & 1u);
+        const bool edge = par == 1 && G > 1;
+        const int buf = (int)((t >> 1) & 1u);
+        if (edge) {
+            // publish the first and last slot of every chain (pre-exchange states)
+            const bool lo_nb = g > 0, hi_nb = g < G - 1;
+            const size_t xbase = ((size_t)run * G + g) * 2;
+            for (int idx = tid; idx < 2 * chains * n; idx += T) {
+                const int sc = idx / n, p = idx - sc * n;
+                const int side = sc / chains, ch = sc - side * chains;
+                if ((side == 0 && !lo_nb) || (side == 1 && !hi_nb)) continue;
+                const int l = ch * mg + (side ? mg - 1 : 0);
+                a.xs[(((xbase + side) * 2 + buf) * chains + ch) * n + p] = *sbyte(l, p);
+            }
+            if (tid < 2 * chains) {
+                const int side = tid / chains, ch = tid - side * chains;
+                a.xe[((xbase + side) * 2 + buf) * chains + ch] = L.E[ch * mg + (side ? mg - 1 : 0)];
+            }
+            __threadfence();
+            __syncthreads();
+            if (tid == 0) {
+                __hip_atomic_store(&a.flags[run * G + g], ls + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                for (int d = 0; d < 2 && !stop; ++d) {
+                    const int nb = d == 0 ? g - 1 : g + 1;
+                    if (nb < 0 || nb >= G) continue;
+                    unsigned it = 0;
+                    while (__hip_atomic_load(&a.flags[run * G + nb], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) <
+                           ls + 1) {
+                        if (++it > a.spin_limit) {
+                            stop = 1;
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(2);
+                    }
+                }
+            }
+            __syncthreads();
+            if (stop) break;
+            __threadfence();
+        }
+        {
+            const int nin = (mg - par) / 2;            // pairs inside the group
+            const int per = nin + (edge ? 2 : 0);      // + the two straddling pairs
+            if (tid < chains * per) {
+                const int ch = tid / per, e = tid - ch * per;
+                const uint32_t cctr = (uint32_t)(run * chains + ch);
+                if (e < nin) {
+                    const int k = s0 + par + 2 * e;
+                    const int la = ch * mg + (k - s0);
+                    const long long Dd = L.E[la] - L.E[la + 1];
+                    if (swap_test(Dd, a.stab + (size_t)k * 7 * kDigitSize, a.snd[k], (uint32_t)k, t, cctr, a.k0,
+                                  a.k1)) {
+                        const long long x = L.E[la];
+                        L.E[la] = L.E[la + 1];
+                        L.E[la + 1] = x;
+                        L.acc[atomicAdd(&nacc, 1)] = la;
+                    }
+                } else if (e == nin && g > 0) {
+                    // pair (s0 - 1, s0): the lower neighbour's last slot against our first
+                    const int k = s0 - 1;
+                    const size_t xi = ((((size_t)run * G + (g - 1)) * 2 + 1) * 2 + buf) * chains + ch;
+                    const long long Ek = a.xe[xi], Ek1 = L.E[ch * mg];
+                    if (swap_test(Ek - Ek1, a.stab + (size_t)k * 7 * kDigitSize, a.snd[k], (uint32_t)k, t, cctr,
+                                  a.k0, a.k1)) {
+                        L.E[ch * mg] = Ek;
+                        L.cin[0 * chains + ch] = 1;
+                    }
+                } else if (e == nin + 1 && g < G - 1) {
+                    // pair (s0 + mg - 1, s0 + mg): our last slot against the upper neighbour's first
+                    const int k = s0 + mg - 1;
+                    const size_t xi = ((((size_t)run * G + (g + 1)) * 2 + 0) * 2 + buf) * chains + ch;
+                    const long long Ek = L.E[ch * mg + mg - 1], Ek1 = a.xe[xi];
+                    if (swap_test(Ek - Ek1, a.stab + (size_t)k * 7 * kDigitSize, a.snd[k], (uint32_t)k, t, cctr,
+                                  a.k0, a.k1)) {
+                        L.E[ch * mg + mg - 1] = Ek1;
+                        L.cin[1 * chains + ch] = 1;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        {
+            const int na = nacc;
+            for (int idx = tid; idx < n * na; idx += T) {
+                const int pr = idx / n, p = idx - pr * n;
+                const int la = L.acc[pr];
+                unsigned char *A = sbyte(la, p), *B = sbyte(la + 1, p);
+                const unsigned char x = *A;
+                *A = *B;
+                *B = x;
+            }
+            if (edge)
+                for (int idx = tid; idx < 2 * chains * n; idx += T) {
+                    const int sc = idx / n, p = idx - sc * n;
+                    if (!L.cin[sc]) continue;
+                    const int side = sc / chains, ch = sc - side * chains;
+                    // side 0 takes the lower neighbour's last slot, side 1 the upper neighbour's first
+                    const int nb = side == 0 ? g - 1 : g + 1, nside = side == 0 ? 1 : 0;
+                    const size_t xi = ((((size_t)run * G + nb) * 2 + nside) * 2 + buf) * chains + ch;
+                    *sbyte(ch * mg + (side ? mg - 1 : 0), p) = a.xs[xi * n + p];
+                }
+            __syncthreads();
+        }
+
+        // 3. Houdayer cluster moves between chains 0 and 1 at the group's slots.
+        const int kb = max(a.icm_lo, s0), ke = min(a.icm_hi, s0 + mg);
+        if (a.nw_icm > 0 && wid < a.nw_icm && kb < ke) {
+            uint32_t *vis = L.vis + (size_t)wid * nwords;
+            uint16_t *queue = L.queue + (size_t)wid * n;
+            for (int k = kb + wid; k < ke; k += a.nw_icm) {
+                const int la = k - s0, lb = mg + (k - s0);
+                int n_neg = 0;
+                for (int i0 = 0; i0 < n; i0 += 64) {
+                    const int i = i0 + lane;
+                    bool f = false;
+                    if (i < n) {
+                        const int p = POS(i);
+                        f = *sbyte(la, p) != *sbyte(lb, p);
+                    }
+                    n_neg += __popcll(__ballot(f));
+                }
+                if (n_neg == 0) continue;
+                const uint32_t w = dev::philox((uint32_t)k, t, (uint32_t)run, 4u << 24, a.k0, a.k1).w[0];
+                const int target = (int)(((unsigned long long)w * (unsigned long long)n_neg) >> 32);
+                int seed_p = -1, seen = 0;
+                for (int i0 = 0; i0 < n && seed_p < 0; i0 += 64) {
+                    const int i = i0 + lane;
+                    bool f = false;
+                    int p = 0;
+                    if (i < n) {
+                        p = POS(i);
+                        f = *sbyte(la, p) != *sbyte(lb, p);
+                    }
+                    const unsigned long long msk = __ballot(f);
+                    const int cnt = __popcll(msk);
+                    if (target < seen + cnt) {
+                        const bool me = f && (seen + __popcll(msk & lanemask_lt())) == target;
+                        const unsigned long long who = __ballot(me);
+                        const int src = __ffsll((long long)who) - 1;
+                        seed_p = __shfl(p, src, 64);
+                    }
+                    seen += cnt;
+                }
+                for (int wd = lane; wd < nwords; wd += 64) vis[wd] = 0u;
+                __builtin_amdgcn_wave_barrier();
+                if (lane == 0) {
+                    vis[seed_p >> 5] = 1u << (seed_p & 31);
+                    queue[0] = (uint16_t)seed_p;
+                }
+                __builtin_amdgcn_wave_barrier();
+                int head = 0, tail = 1;
+                while (head < tail) {
+                    const int chunk = min(64, tail - head);
+                    const bool act = lane < chunk;
+                    const int v = act ? (int)queue[head + lane] : 0;
+                    int newtail = tail;
+                    for (int kk = 0; kk < D; ++kk) {
+                        bool added = false;
+                        int u = 0;
+                        if (act) {
+                            const uint32_t rec = NBR(kk, v);
+                            u = (int)(rec >> 16);
+                            if ((rec & 0xffffu) != 0u && *sbyte(la, u) != *sbyte(lb, u)) {
+                                const uint32_t bit = 1u << (u & 31);
+                                const uint32_t old = atomicOr(&vis[u >> 5], bit);
+                                added = !(old & bit);
+                            }
+                        }
+                        const unsigned long long msk = __ballot(added);
+                        if (added) queue[newtail + __popcll(msk & lanemask_lt())] = (uint16_t)u;
+                        newtail += __popcll(msk);
+                    }
+                    head += chunk;
+                    tail = newtail;
+                    __builtin_amdgcn_wave_barrier();
+                }
+                long long dA = 0, dB = 0;
+                for (int e = lane; e < tail; e += 64) {
+                    const int v = queue[e];
+                    const int sA = (int)(int8_t)*sbyte(la, v), sB = (int)(int8_t)*sbyte(lb, v);
+                    const long long hv = HPOS(v);
+                    dA += -2ll * hv * sA;
+                    dB += -2ll * hv * sB;
+                    for (int kk = 0; kk < D; ++kk) {
+                        const uint32_t rec = NBR(kk, v);
+                        const int u = (int)(rec >> 16);
+                        if (!((vis[u >> 5] >> (u & 31)) & 1u)) {
+                            const long long Jv = (int16_t)(rec & 0xffffu);
+                            dA += -2ll * Jv * sA * (int)(int8_t)*sbyte(la, u);
+                            dB += -2ll * Jv * sB * (int)(int8_t)*sbyte(lb, u);
+                        }
+                    }
+                }
+                dA = wave_sum(dA);
+                dB = wave_sum(dB);
+                __builtin_amdgcn_wave_barrier();
+                for (int e = lane; e < tail; e += 64) {
+                    const int v = queue[e];
+                    *sbyte(la, v) = (unsigned char)(-(int)(int8_t)*sbyte(la, v));
+                    *sbyte(lb, v) = (unsigned char)(-(int)(int8_t)*sbyte(lb, v));
+                }
+                if (lane == 0) {
+                    L.E[la] += dA;
+                    L.E[lb] += dB;
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        if (a.nw_icm > 0) __syncthreads();
+
+        // 4. Top-10 lists of the group's colder slots.
+        const int kc = max(K - half, s0), ncold = max(0, s0 + mg - kc);
+        for (int li = wid; li < chains * ncold; li += nw) {
+            const int ch = li / ncold, k = kc + (li - ch * ncold);
+            const int l = ch * mg + (k - s0);
+            const int gl = ch * half + (k - (K - half));
+            const long long Ec = L.E[l];
+            const int cnt = L.Lcnt[l];
+            long long *LE = L.LE + (size_t)l * 10;
+            int32_t *LW = L.Lwhen + (size_t)l * 10;
+            bool cand = cnt < 10;
+            if (!cand) {
+                long long worst = LE[0];
+                for (int e = 1; e < 10; ++e) worst = LE[e] > worst ? LE[e] : worst;
+                cand = Ec < worst;
+            }
+            if (!cand) continue;
+            int8_t *base = a.tops + ((size_t)run * Ls + gl) * 10 * n;
+            bool dup = false;
+            for (int e = 0; e < cnt && !dup; ++e) {
+                if (LE[e] != Ec) continue;
+                bool diff = false;
+                for (int p = lane; p < n; p += 64) diff |= base[(size_t)e * n + p] != (int8_t)*sbyte(l, p);
+                dup = !__any(diff);
+            }
+            if (dup) continue;
+            int victim = cnt;
+            if (cnt == 10) {
+                victim = 0;
+                for (int e = 1; e < 10; ++e)
+                    if (LE[e] > LE[victim] || (LE[e] == LE[victim] && LW[e] > LW[victim])) victim = e;
+            }
+            for (int p = lane; p < n; p += 64) base[(size_t)victim * n + p] = (int8_t)*sbyte(l, p);
+            __builtin_amdgcn_wave_barrier();
+            if (lane == 0) {
+                LE[victim] = Ec;
+                LW[victim] = ls;
+                if (cnt < 10) L.Lcnt[l] = cnt + 1;
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
+    }
+
+    const int kc = max(K - half, s0), ncold = max(0, s0 + mg - kc);
+    if (stop) {
+        // A neighbour never published: mark the group's lists as invalid.
+        if (a.top_count)
+            for (int li = tid; li < chains * ncold; li += T) {
+                const int ch = li / ncold, k = kc + (li - ch * ncold);
+                a.top_count[(size_t)run * Ls + ch * half + (k - (K - half))] = -1;
+            }
+        return;
+    }
+    // Outputs of the group's replicas.
+    if (a.final_E)
+        for (int l = tid; l < nl; l += T) {
+            const int ch = l / mg, slot = s0 + (l - ch * mg);
+            a.final_E[((size_t)run * chains + ch) * K + slot] = L.E[l];
+        }
+    if (a.final_spins)
+        for (int idx = tid; idx < nl * n; idx += T) {
+            const int l = idx / n, i = idx - l * n;
+            const int ch = l / mg, slot = s0 + (l - ch * mg);
+            a.final_spins[(((size_t)run * chains + ch) * K + slot) * n + i] = (int8_t)*sbyte(l, POS(i));
+        }
+    if (a.top_E || a.top_spins || a.top_count) {
+        // Rank of entry e of a list = number of entries ordered before it by (E, insertion).
+        const int nlist = chains * ncold;
+        for (int le = tid; le < nlist * 10; le += T) L.Lord[le] = -1;
+        __syncthreads();
+        for (int le = tid; le < nlist * 10; le += T) {
+            const int li = le / 10, e = le - li * 10;
+            const int ch = li / ncold, k = kc + (li - ch * ncold);
+            const int l = ch * mg + (k - s0);
+            const long long *LE = L.LE + (size_t)l * 10;
+            const int32_t *LW = L.Lwhen + (size_t)l * 10;
+            const int cnt = L.Lcnt[l];
+            if (e < cnt) {
+                int rank = 0;
+                for (int o = 0; o < cnt; ++o) rank += (LE[o] < LE[e] || (LE[o] == LE[e] && LW[o] < LW[e])) ? 1 : 0;
+                L.Lord[li * 10 + rank] = e;
+            }
+            if (e == 0 && a.top_count) a.top_count[(size_t)run * Ls + ch * half + (k - (K - half))] = cnt;
+        }
+        __syncthreads();
+        if (a.top_E)
+            for (int le = tid; le < nlist * 10; le += T) {
+                const int li = le / 10, rank = le - li * 10;
+                const int ch = li / ncold, k = kc + (li - ch * ncold);
+                const int l = ch * mg + (k - s0), gl = ch * half + (k - (K - half));
+                const int e = L.Lord[le];
+                a.top_E[((size_t)run * Ls + gl) * 10 + rank] = e >= 0 ? L.LE[(size_t)l * 10 + e] : 0x7FFFFFFFFFFFFFFFll;
+            }
+        if (a.top_spins)
+            for (size_t idx = tid; idx < (size_t)nlist * 10 * n; idx += T) {
+                const int lr = (int)(idx / n), i = (int)(idx - (size_t)lr * n);
+                const int li = lr / 10, rank = lr - li * 10;
+                const int ch = li / ncold, k = kc + (li - ch * ncold);
+                const int gl = ch * half + (k - (K - half));
+                const int e = L.Lord[li * 10 + rank];
+                a.top_spins[((size_t)run * Ls + gl) * 10 * n + (size_t)rank * n + i] =
+                    e >= 0 ? a.tops[(((size_t)run * Ls + gl) * 10 + e) * n + POS(i)] : (int8_t)0;
+            }
+    }
+}
+
+template <int ND, bool BIG>
+void *ptx_entry() {
+    return reinterpret_cast<void *>(ptx_kernel<ND, BIG>);
+}
+
+void *ptx_fn(int nd, bool big) {
+    switch (nd) {
+        case 1:
+            return big ? ptx_entry<1, true>() : ptx_entry<1, false>();
+        case 2:
+            return big ? ptx_entry<2, true>() : ptx_entry<2, false>();
+        case 3:
+            return big ? ptx_entry<3, true>() : ptx_entry<3, false>();
+        default:
+            return nullptr;
+    }
+}
+
+}  // namespace
+
+size_t ptx_lds_bytes(int n, int D, int m, int chains, int row_len, int nw_icm, bool big) {
+    return ptx_layout(n, D, m, chains, row_len, nw_icm, big, nullptr, nullptr);
+}
+
+hipError_t ptx_max_groups_resident(int nd, bool big, int threads, size_t lds, int *blocks_per_cu) {
+    void *f = ptx_fn(nd, big);
+    if (!f) return hipErrorInvalidValue;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, threads, lds);
+}
+
+hipError_t launch_ptx(const PtxLaunch &P, hipStream_t s) {
+    PtxArgs a;
+    a.image = P.image;
+    a.mtab = P.mtab;
+    a.stab = P.stab;
+    a.snd = P.snd;
+    a.final_spins = P.out->final_spins;
+    a.final_E = reinterpret_cast<long long *>(P.out->final_E);
+    a.top_spins = P.out->top_spins;
+    a.top_E = reinterpret_cast<long long *>(P.out->top_E);
+    a.top_count = P.out->top_count;
+    a.tops = P.tops;
+    a.xs = P.xs;
+    a.xe = reinterpret_cast<long long *>(P.xe);
+    a.flags = P.flags;
+    a.n = P.n;
+    a.D = P.D;
+    a.C = P.C;
+    a.K = P.K;
+    a.chains = P.chains;
+    a.sweeps = P.sweeps;
+    a.row_len = P.row_len;
+    a.icm_lo = P.icm_lo;
+    a.icm_hi = P.icm_hi;
+    a.nw_icm = P.nw_icm;
+    a.G = P.G;
+    a.m = P.m;
+    a.sweep_offset = P.sweep_offset;
+    a.k0 = (uint32_t)P.seed;
+    a.k1 = (uint32_t)(P.seed >> 32);
+    a.spin_limit = P.spin_limit;
+    const int nflags = P.runs * P.G;
+    hipLaunchKernelGGL(flags_zero_kernel, dim3((nflags + 255) / 256), dim3(256), 0, s, P.flags, nflags);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t lds = ptx_lds_bytes(P.n, P.D, P.m, P.chains, P.row_len, P.nw_icm, P.big);
+    void *f = ptx_fn(P.nd, P.big);
+    if (!f) return hipErrorInvalidValue;
+    void *args[] = {&a};
+    return hipLaunchKernel(f, dim3(P.runs * P.G), dim3(P.threads), args, lds, s);
+}
+
+}  // namespace spv

@@ -1,0 +1,85 @@
+"""GPU parity of tempering with the ladder split over several workgroups
+(boundary replica exchange through L2, instance in LDS or read from global
+memory), bit for bit against the CPU oracle; plus the single-workgroup kernel
+forced on ladders the split would otherwise take."""
+import numpy as np
+import pytest
+
+import oracle
+import spvar_inputs as si
+from spvar_inputs import configs as cf
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def spv():
+    import paper_1706_07826_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(spv):
+    return spv.Context(0)
+
+
+def _check(got, want):
+    for key in ("final_spins", "final_E", "top_E", "top_count", "top_spins"):
+        assert np.array_equal(got[key].cpu().numpy(), want[key]), key
+
+
+CASES = [
+    # name, instance, K, runs, chains, sweeps, icm, groups, big, sweep_offset
+    ("cubic4_K8_G2", lambda: si.cubic_lattice(4, "gauss", seed=1, scale_log2=10), 8, 3, 1, 100, None, 2, 0, 0),
+    ("cubic4_K8_G2_icm", lambda: si.cubic_lattice(4, "gauss", seed=2, scale_log2=10), 8, 2, 2, 90, (0, 8), 2, 0, 0),
+    ("cubic4_K12_G3_icm_window_big", lambda: si.cubic_lattice(4, "gauss", seed=3, scale_log2=10), 12, 2, 2, 75,
+     (2, 10), 3, 1, 0),
+    ("chimera2_K12_G2_uneven", lambda: si.chimera(2, seed=4), 12, 3, 1, 61, None, 2, 0, 0),
+    ("sparse40_K16_G4_odd_offset", lambda: si.random_sparse(40, 3.0, seed=5), 16, 2, 2, 51, (0, 16), 4, 0, 7),
+    ("cubic6_pm1_K8_G2_big", lambda: si.cubic_lattice(6, "pm1", seed=6), 8, 4, 2, 80, (0, 8), 2, 1, 0),
+    ("zero_sweeps_G2", lambda: si.chimera(2, seed=7), 8, 2, 1, 0, None, 2, 0, 0),
+    ("one_sweep_G2", lambda: si.chimera(2, seed=8), 8, 2, 1, 1, None, 2, 0, 1),
+    ("K4_G1_forced_split", lambda: si.chimera(2, seed=9), 4, 3, 2, 40, (0, 4), 1, 0, 0),
+]
+
+
+@pytest.mark.parametrize("name,make,K,runs,chains,sweeps,icm,groups,big,off", CASES, ids=[c[0] for c in CASES])
+def test_split_pt_parity(spv, ctx, monkeypatch, name, make, K, runs, chains, sweeps, icm, groups, big, off):
+    inst = make()
+    print(f"[ptx] {name} n={inst.n} K={K} runs={runs} chains={chains} G={groups} big={big}", flush=True)
+    monkeypatch.setenv("SPVAR_PT_SPLIT", "1")
+    monkeypatch.setenv("SPVAR_PT_GROUPS", str(groups))
+    monkeypatch.setenv("SPVAR_PT_BIG", str(big))
+    P = spv.Problem.from_instance(inst)
+    betas = si.geometric_betas(0.2, 5.0 if inst.scale_log2 else 3.0, K)
+    got = spv.spv_pt_sample(ctx, P, betas, runs, chains, sweeps, seed=90 + K, sweep_offset=off, icm=icm)
+    want = oracle.pt_sample(inst, betas, runs, chains, sweeps, seed=90 + K, sweep_offset=off, icm=icm, threads=8)
+    _check(got, want)
+
+
+@pytest.mark.parametrize("K,chains,icm", [(8, 1, None), (8, 2, (0, 8)), (12, 2, (3, 9))])
+def test_single_workgroup_kernel_forced(spv, ctx, monkeypatch, K, chains, icm):
+    monkeypatch.setenv("SPVAR_PT_SPLIT", "0")
+    inst = si.cubic_lattice(4, "gauss", seed=20 + K, scale_log2=10)
+    P = spv.Problem.from_instance(inst)
+    betas = si.geometric_betas(0.2, 5.0, K)
+    got = spv.spv_pt_sample(ctx, P, betas, 3, chains, 70, seed=K, icm=icm)
+    want = oracle.pt_sample(inst, betas, 3, chains, 70, seed=K, icm=icm, threads=3)
+    _check(got, want)
+
+
+def test_cubic20_pticm_config_shape(spv, ctx):
+    """The N=8000 PT-ICM shape (40 slots x 2 chains, Houdayer at every slot,
+    one run) on the default plan (instance in global memory, one workgroup per
+    4 slots), a short schedule against the oracle."""
+    cfg = cf.CUBIC20_PTICM
+    inst = cf.instance(cfg)
+    betas = cf.betas(cfg)
+    K = betas.size
+    print(f"[ptx] cubic20 n={inst.n} K={K}", flush=True)
+    P = spv.Problem.from_instance(inst)
+    got = spv.spv_pt_sample(ctx, P, betas, 1, cfg["chains"], 40, seed=cfg["seed"], icm=(0, K))
+    want = oracle.pt_sample(inst, betas, 1, cfg["chains"], 40, seed=cfg["seed"], icm=(0, K), threads=1)
+    _check(got, want)
+    assert np.array_equal(got["final_E"].cpu().numpy().reshape(-1),
+                          oracle.energy(inst, got["final_spins"].cpu().numpy().reshape(-1, inst.n)))

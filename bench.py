@@ -66,7 +66,10 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after timing, run one device copy of this size (counter calibration)")
     ap.add_argument("--workload", default="chimera8_sa",
-                    choices=["chimera8_sa", "residual_batch", "cubic10_pt"])
+                    choices=["chimera8_sa", "residual_batch", "cubic10_pt", "cubic20_pticm", "serving"])
+    ap.add_argument("--pt-runs", type=int, default=0, help="PT workloads: runs per step (0 = the config's)")
+    ap.add_argument("--serving-requests", type=int, default=2000)
+    ap.add_argument("--serving-slots", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (single-GPU build)",
@@ -82,7 +85,14 @@ def main():
     if args.workload == "residual_batch":
         return bench_residual_batch(args)
     if args.workload == "cubic10_pt":
-        return bench_cubic10_pt(args)
+        return bench_pt(args, cf.CUBIC10_PT, "cubic10_pt: PT 32 betas 0.2..5.0, {runs} runs x 10^4 sweeps, "
+                        "top-10 sample of the 16 colder slots, persistence elite 0.2")
+    if args.workload == "cubic20_pticm":
+        return bench_pt(args, cf.CUBIC20_PTICM, "cubic20_pticm: N=8000, PT-ICM 40 betas 0.2..5.0 x 2 chains, "
+                        "Houdayer moves at every slot, {runs} run(s) x 10^4 sweeps, top-10 sample of the 20 "
+                        "colder slots per chain, persistence elite 0.2")
+    if args.workload == "serving":
+        return bench_serving(args)
 
     cfg = cf.CHIMERA8_SA
     inst = cf.instance(cfg)
@@ -223,25 +233,27 @@ def bench_residual_batch(args):
     print(json.dumps(out), flush=True)
 
 
-def bench_cubic10_pt(args):
-    """cubic10_pt: 64 PT runs x 32 slots x 10^4 sweeps on the L=10 lattice, then persistence
-    on the 10,240-state top-10 sample."""
+def bench_pt(args, cfg, label):
+    """PT workloads: `runs` tempering runs of K slots x `chains` chains (Houdayer moves at
+    every slot when the config asks for them), then persistence on the top-10 sample of
+    the colder half, assembled on the device."""
     import torch
 
     import paper_1706_07826_amd as spv
     from spvar_inputs import configs as cf
 
-    cfg = cf.CUBIC10_PT
     inst = cf.instance(cfg)
     betas = cf.betas(cfg)
+    K, chains = betas.size, cfg.get("chains", 1)
+    runs = args.pt_runs or cfg["runs"]
+    icm = (0, K) if cfg.get("icm") else None
     ctx = spv.Context(0)
     P = spv.Problem.from_instance(inst)
-    updates = inst.n * cfg["K"] * cfg["runs"] * cfg["sweeps"]
+    updates = inst.n * K * chains * runs * cfg["sweeps"]
 
     def step():
-        r = spv.spv_pt_sample(ctx, P, betas, cfg["runs"], 1, cfg["sweeps"], cfg["seed"], final=False)
-        S = r["top_spins"].reshape(-1, inst.n)
-        E = r["top_E"].reshape(-1)
+        r = spv.spv_pt_sample(ctx, P, betas, runs, chains, cfg["sweeps"], cfg["seed"], icm=icm, final=False)
+        S, E = spv.spv_top_sample(ctx, r)
         return spv.spv_persist_fix(ctx, P, S, E, cfg["elite"], cfg["theta"], cfg["gauge"])
 
     for _ in range(args.warmup):
@@ -256,10 +268,107 @@ def bench_cubic10_pt(args):
         "metric": BASELINE_METRIC, "value": round(updates / dt, 1), "unit": "spin-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
-        "data": "synthetic Gaussian cubic L=10 instance",
-        "config": {"workload": "cubic10_pt: PT 32 betas 0.2..5.0, 64 runs x 10^4 sweeps, top-10 "
-                               "sample of the 16 colder slots, persistence elite 0.2"},
+        "data": f"synthetic Gaussian cubic L={cfg['L']} instance",
+        "config": {"workload": label.format(runs=runs)},
         "spvar_solves_per_s": round(1 / dt, 4), "fixed_per_solve": fx.info()["n_fixed"],
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_serving(args):
+    """Serving stream: requests of three kinds (by count 60 % SA on the Chimera N=512 instance,
+    1000 reads x 1000 sweeps + persistence; 30 % PT on the cubic N=1000 instance, 32 betas x 4
+    runs x 1000 sweeps + persistence; 10 % PT with Houdayer moves on the cubic N=8000 instance,
+    40 betas x 2 chains x 1 run x 1000 sweeps + persistence), seed = base + request id.  First
+    a burst of all requests measures the saturation rate; then Poisson arrivals at 0.5, 0.8 and
+    0.95 of it.  Latency = submit -> completion observed by the server's host thread."""
+    import numpy as np
+    import torch
+
+    import paper_1706_07826_amd as spv
+    from spvar_inputs import configs as cf
+
+    ctx = spv.Context(0)
+    c2, c3, c5 = cf.CHIMERA8_SA, cf.CUBIC10_PT, cf.CUBIC20_PTICM
+    kinds = {
+        "sa512": dict(P=spv.Problem.from_instance(cf.instance(c2)), betas=cf.betas(c2, 1000), cfg=c2),
+        "pt1000": dict(P=spv.Problem.from_instance(cf.instance(c3)), betas=cf.betas(c3), cfg=c3),
+        "pticm8000": dict(P=spv.Problem.from_instance(cf.instance(c5)), betas=cf.betas(c5), cfg=c5),
+    }
+    updates = {"sa512": 512 * 1000 * 1000, "pt1000": 1000 * 32 * 4 * 1000, "pticm8000": 8000 * 80 * 1000}
+    nreq = args.serving_requests
+    rng = np.random.default_rng(31337)
+    mix = rng.choice(["sa512", "pt1000", "pticm8000"], size=nreq, p=[0.6, 0.3, 0.1])
+    base_seed = 5000
+    srv = spv.Server(ctx, slots=args.serving_slots)
+
+    def prepare(i):
+        k = mix[i]
+        d = kinds[k]
+        c = d["cfg"]
+        if k == "sa512":
+            return srv.prepare_sa(d["P"], d["betas"], 1000, base_seed + i, c["elite"], c["theta"], c["gauge"])
+        if k == "pt1000":
+            return srv.prepare_pt(d["P"], d["betas"], 4, 1, 1000, base_seed + i, None, c["elite"], c["theta"],
+                                  c["gauge"], final=False)
+        K = d["betas"].size
+        return srv.prepare_pt(d["P"], d["betas"], 1, 2, 1000, base_seed + i, (0, K), c["elite"], c["theta"],
+                              c["gauge"], final=False)
+
+    def run(rate):
+        reqs = [prepare(i) for i in range(nreq)]
+        torch.cuda.synchronize()
+        gaps = rng.exponential(1.0 / rate, size=nreq) if rate else np.zeros(nreq)
+        t0 = time.perf_counter()
+        due = t0
+        tickets = []
+        for i in range(nreq):
+            due += gaps[i]
+            while True:
+                now = time.perf_counter()
+                if now >= due:
+                    break
+                if due - now > 2e-4:
+                    time.sleep(due - now - 1e-4)
+            tickets.append(srv.submit(*reqs[i]))
+        res = [srv.wait(t)[0] for t in tickets]
+        first = min(r.submit_ns for r in res)
+        last = max(r.done_ns for r in res)
+        lat = np.array([(r.done_ns - r.submit_ns) / 1e6 for r in res])
+        for t in tickets:
+            srv.release(t)
+        span = (last - first) / 1e9
+        upd = sum(updates[k] for k in mix)
+        out = {"requests_per_s": round(nreq / span, 2), "spin_updates_per_s": round(upd / span, 1),
+               "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3)}
+        for k in kinds:
+            sel = lat[mix == k]
+            if sel.size:
+                out[f"p50_ms_{k}"] = round(float(np.percentile(sel, 50)), 3)
+                out[f"p99_ms_{k}"] = round(float(np.percentile(sel, 99)), 3)
+        print(f"[serving] rate={rate or 'burst'} {out}", file=sys.stderr, flush=True)
+        return out
+
+    # warm up every kind (tables, buffers, code objects)
+    for i in range(min(nreq, 12)):
+        t = srv.submit(*prepare(i))
+        srv.wait(t)
+        srv.release(t)
+    sat = run(0)
+    loads = {}
+    for f in (0.5, 0.8, 0.95):
+        loads[str(f)] = run(f * sat["requests_per_s"])
+    srv.close()
+    out = {
+        "metric": BASELINE_METRIC, "value": sat["spin_updates_per_s"], "unit": "spin-updates/s",
+        "n_gpus": 1, "steps": nreq, "warmup": 12, "ms_per_step": round(1e3 / sat["requests_per_s"], 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic Chimera N=512, Gaussian cubic N=1000 and N=8000 instances",
+        "config": {"workload": f"serving: {nreq} requests (60 % SA N=512 1000x1000 + fix, 30 % PT N=1000 "
+                               "32 betas x 4 runs x 1000 sweeps + fix, 10 % PT-ICM N=8000 40 betas x 2 chains "
+                               "x 1000 sweeps + fix), burst then Poisson at 0.5/0.8/0.95 of saturation",
+                   "slots": args.serving_slots},
+        "saturation": sat, "poisson": loads,
     }
     print(json.dumps(out), flush=True)
 

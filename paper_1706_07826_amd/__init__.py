@@ -435,7 +435,8 @@ class Server:
                                                                   "J", "h", "colour", "orig_index", "info")])
             keep["fix"] = fx
 
-    def submit_sa(self, P, betas, reads, seed, elite_frac=0.0, threshold=1.0, gauge=0):
+    def prepare_sa(self, P, betas, reads, seed, elite_frac=0.0, threshold=1.0, gauge=0):
+        """Request struct and output buffers of an SA (+ persistence) request, not yet submitted."""
         b = np.ascontiguousarray(betas, dtype=np.float64)
         dev = self.ctx.device
         keep = dict(P=P, betas=b, spins=torch.empty((reads, P.n), dtype=torch.int8, device=dev),
@@ -445,15 +446,16 @@ class Server:
         req.betas, req.sweeps, req.reads = b.ctypes.data, b.size, int(reads)
         req.spins, req.energies = keep["spins"].data_ptr(), keep["energies"].data_ptr()
         self._fix(req, P, elite_frac, threshold, gauge, keep)
-        return self._submit(req, keep)
+        return req, keep
 
-    def submit_pt(self, P, betas, runs, chains, sweeps, seed, icm=None, elite_frac=0.0, threshold=1.0,
-                  gauge=0):
+    def prepare_pt(self, P, betas, runs, chains, sweeps, seed, icm=None, elite_frac=0.0, threshold=1.0,
+                   gauge=0, final=True):
+        """Request struct and output buffers of a PT (+ persistence) request, not yet submitted."""
         b = np.ascontiguousarray(betas, dtype=np.float64)
         K, half, dev = b.size, b.size // 2, self.ctx.device
         keep = dict(P=P, betas=b,
-                    final_spins=torch.empty((runs, chains, K, P.n), dtype=torch.int8, device=dev),
-                    final_E=torch.empty((runs, chains, K), dtype=torch.int64, device=dev),
+                    final_spins=torch.empty((runs, chains, K, P.n), dtype=torch.int8, device=dev) if final else None,
+                    final_E=torch.empty((runs, chains, K), dtype=torch.int64, device=dev) if final else None,
                     top_spins=torch.empty((runs, chains, half, TOPK, P.n), dtype=torch.int8, device=dev),
                     top_E=torch.empty((runs, chains, half, TOPK), dtype=torch.int64, device=dev),
                     top_count=torch.empty((runs, chains, half), dtype=torch.int32, device=dev))
@@ -461,10 +463,25 @@ class Server:
         req.kind, req.problem, req.seed = SPV_REQ_PT, P.c_struct(), C.c_uint64(seed & (2**64 - 1)).value
         req.betas, req.sweeps, req.K, req.runs, req.chains = b.ctypes.data, int(sweeps), K, int(runs), int(chains)
         req.icm_lo, req.icm_hi = (0, 0) if icm is None else icm
-        req.pt_out = spv_pt_out(*[keep[k].data_ptr() for k in ("final_spins", "final_E", "top_spins", "top_E",
-                                                               "top_count")])
+        req.pt_out = spv_pt_out(*[(keep[k].data_ptr() if keep[k] is not None else None)
+                                  for k in ("final_spins", "final_E", "top_spins", "top_E", "top_count")])
         self._fix(req, P, elite_frac, threshold, gauge, keep)
+        return req, keep
+
+    def submit(self, req, keep):
         return self._submit(req, keep)
+
+    def submit_sa(self, P, betas, reads, seed, elite_frac=0.0, threshold=1.0, gauge=0):
+        return self._submit(*self.prepare_sa(P, betas, reads, seed, elite_frac, threshold, gauge))
+
+    def submit_pt(self, P, betas, runs, chains, sweeps, seed, icm=None, elite_frac=0.0, threshold=1.0,
+                  gauge=0):
+        return self._submit(*self.prepare_pt(P, betas, runs, chains, sweeps, seed, icm, elite_frac, threshold,
+                                             gauge))
+
+    def release(self, ticket):
+        """Drop the Python references to a completed request's buffers."""
+        self.live.pop(ticket, None)
 
     def poll(self, ticket):
         r = spv_result()

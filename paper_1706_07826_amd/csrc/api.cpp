@@ -200,7 +200,7 @@ spv_status plan_pt_split(Ctx *c, int n, int D, int K, int runs, int chains, int 
         const int Gr = (K + m - 1) / m;
         const int nq = chains * m / 4;
         const long long tasks = (long long)n * nq;
-        int threads = tasks >= 8192 ? 1024 : tasks >= 2048 ? 512 : 256;
+        int threads = env_int("SPVAR_PT_THREADS", tasks >= 1536 ? 1024 : tasks >= 768 ? 512 : 256);
         while (threads < nq) threads *= 2;
         if (threads > 1024) continue;
         const int icm_slots = icm_hi > icm_lo ? std::min(m, icm_hi - icm_lo) : 0;
@@ -224,6 +224,26 @@ spv_status plan_pt_split(Ctx *c, int n, int D, int K, int runs, int chains, int 
             }
         }
     }
+}
+
+spv_status pt_lds_footprint(Ctx *c, const spv_problem *P, int K, int runs, int chains, int icm_lo, int icm_hi,
+                            int64_t *lds_total) {
+    const int n = P->n, D = P->max_degree > 0 ? P->max_degree : 1;
+    const int nd = digits_for(P->x_bound), row_len = table_row_len(P->x_bound);
+    const bool icm = icm_hi > icm_lo;
+    const int cK = chains * K, nqa = (cK % 4 == 0) ? cK / 4 : cK / 4 + 2;
+    const int threads = (n * nqa >= 4096) ? 1024 : 256;
+    const int nw_icm = icm ? std::min(threads / 64, icm_hi - icm_lo) : 0;
+    const size_t lds = pt_lds_bytes(n, D, K, chains, row_len, nqa, nw_icm) + 256;
+    PtSplit sp;
+    spv_status st = plan_pt_split(c, n, D, K, runs, chains, row_len, nd, icm ? icm_lo : 0, icm ? icm_hi : 0,
+                                  lds <= c->lds_max, &sp);
+    if (st) return st;
+    if (sp.use)
+        *lds_total = (int64_t)runs * sp.G * (int64_t)(ptx_lds_bytes(n, D, sp.m, chains, row_len, sp.nw_icm, sp.big) + 256);
+    else
+        *lds_total = (int64_t)runs * (int64_t)lds;
+    return SPV_OK;
 }
 
 int sa_threads_env() {
@@ -270,7 +290,7 @@ void spv_ctx_destroy(spv_ctx *ctx) {
     if (ctx->c.stage) (void)hipHostFree(ctx->c.stage);
     if (ctx->c.stage_done) (void)hipEventDestroy(ctx->c.stage_done);
     for (DevBuf *b : {&ctx->c.image, &ctx->c.tables, &ctx->c.tables2, &ctx->c.scratch, &ctx->c.scratch2,
-                      &ctx->c.rounds, &ctx->c.pt, &ctx->c.top, &ctx->c.serve})
+                      &ctx->c.rounds, &ctx->c.pt, &ctx->c.pt_tab, &ctx->c.top, &ctx->c.serve})
         if (b->p) (void)hipFree(b->p);
     delete ctx;
 }
@@ -589,38 +609,51 @@ spv_status spv_pt_sample(spv_ctx *ctx, const spv_problem *P, const spv_pt_params
         return st;
     if (!sp.use && lds > c->lds_max)
         return set_err(c, SPV_ECAPACITY, "PT run needs %zu B of LDS > %zu (n=%d, %d replicas)", lds, c->lds_max, n, cK);
-    // Device tables: Metropolis rows per slot, swap rows per pair, swap digit counts.
-    std::vector<uint32_t> mt((size_t)K * row_len), stt((size_t)std::max(K - 1, 1) * 7 * kDigitSize, 0u);
-    std::vector<int32_t> snd(std::max(K - 1, 1), 1);
-    for (int k = 0; k < K; ++k)
-        for (int j = 0; j < nd; ++j)
-            for (int d = 0; d < kDigitSize && j * kDigitSize + d < row_len; ++d)
-                mt[(size_t)k * row_len + j * kDigitSize + d] = threshold_word(prm->betas[k], 2, P->scale_log2, j, (uint32_t)d);
-    for (int k = 0; k + 1 < K; ++k) {
-        const double db = prm->betas[k + 1] - prm->betas[k];
-        snd[k] = swap_digits(db, P->scale_log2);
-        for (int j = 0; j < snd[k]; ++j)
-            for (int d = 0; d < kDigitSize; ++d)
-                stt[((size_t)k * 7 + j) * kDigitSize + d] = threshold_word(db, 1, P->scale_log2, j, (uint32_t)d);
-    }
+    // Device tables: Metropolis rows per slot, swap rows per pair, swap digit counts
+    // (cached on the context with the ladder they were built for).
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    const size_t b_mt = al(mt.size() * 4), b_st = al(stt.size() * 4), b_snd = al(snd.size() * 4);
+    const size_t b_mt = al((size_t)K * row_len * 4), b_st = al((size_t)std::max(K - 1, 1) * 7 * kDigitSize * 4),
+                 b_snd = al((size_t)std::max(K - 1, 1) * 4);
+    PtTableCache &ptc = c->pt_cache;
+    const bool hit = ptc.dev == c->pt_tab.p && c->pt_tab.p && ptc.scale == P->scale_log2 && ptc.nd == nd &&
+                     ptc.row_len == row_len && (int)ptc.betas.size() == K &&
+                     std::memcmp(ptc.betas.data(), prm->betas, sizeof(double) * K) == 0;
+    if (!hit) {
+        std::vector<unsigned char> blob(b_mt + b_st + b_snd, 0);
+        uint32_t *mt = reinterpret_cast<uint32_t *>(blob.data());
+        uint32_t *stt = reinterpret_cast<uint32_t *>(blob.data() + b_mt);
+        int32_t *snd = reinterpret_cast<int32_t *>(blob.data() + b_mt + b_st);
+        snd[0] = 1;
+        for (int k = 0; k < K; ++k)
+            for (int j = 0; j < nd; ++j)
+                for (int d = 0; d < kDigitSize && j * kDigitSize + d < row_len; ++d)
+                    mt[(size_t)k * row_len + j * kDigitSize + d] =
+                        threshold_word(prm->betas[k], 2, P->scale_log2, j, (uint32_t)d);
+        for (int k = 0; k + 1 < K; ++k) {
+            const double db = prm->betas[k + 1] - prm->betas[k];
+            snd[k] = swap_digits(db, P->scale_log2);
+            for (int j = 0; j < snd[k]; ++j)
+                for (int d = 0; d < kDigitSize; ++d)
+                    stt[((size_t)k * 7 + j) * kDigitSize + d] = threshold_word(db, 1, P->scale_log2, j, (uint32_t)d);
+        }
+        ptc.dev = nullptr;
+        if ((st = upload(c, c->pt_tab, 0, blob.data(), blob.size(), stream))) return st;
+        ptc.dev = c->pt_tab.p;
+        ptc.betas.assign(prm->betas, prm->betas + K);
+        ptc.scale = P->scale_log2;
+        ptc.nd = nd;
+        ptc.row_len = row_len;
+    }
     const size_t b_top = al((size_t)runs * std::max(Ls, 1) * 10 * std::max(n, 1));
     const size_t n_grp = sp.use ? (size_t)runs * sp.G : 0;
     const size_t b_xs = al(n_grp * 4 * chains * std::max(n, 1)), b_xe = al(n_grp * 4 * chains * 8),
                  b_fl = al(n_grp * 4);
-    st = ensure(c, c->pt, b_mt + b_st + b_snd + b_top + b_xs + b_xe + b_fl);
+    st = ensure(c, c->pt, b_top + b_xs + b_xe + b_fl);
     if (st) return st;
     st = ensure(c, c->image, image_words(std::max(n, 1), D) * 4);
     if (st) return st;
-    {
-        std::vector<unsigned char> blob(b_mt + b_st + b_snd, 0);
-        std::memcpy(blob.data(), mt.data(), mt.size() * 4);
-        std::memcpy(blob.data() + b_mt, stt.data(), stt.size() * 4);
-        std::memcpy(blob.data() + b_mt + b_st, snd.data(), snd.size() * 4);
-        if ((st = upload(c, c->pt, 0, blob.data(), blob.size(), stream))) return st;
-    }
-    unsigned char *base = static_cast<unsigned char *>(c->pt.p);
+    unsigned char *base = static_cast<unsigned char *>(c->pt_tab.p);
+    unsigned char *sbase = static_cast<unsigned char *>(c->pt.p);
     hipError_t e = hipSuccess;
     spv_problem Pp = *P;
     Pp.max_degree = D;
@@ -647,7 +680,7 @@ spv_status spv_pt_sample(spv_ctx *ctx, const spv_problem *P, const spv_pt_params
         X.stab = reinterpret_cast<const uint32_t *>(base + b_mt);
         X.snd = reinterpret_cast<const int32_t *>(base + b_mt + b_st);
         X.out = out;
-        unsigned char *sc = base + b_mt + b_st + b_snd;
+        unsigned char *sc = sbase;
         X.tops = reinterpret_cast<int8_t *>(sc);
         X.xs = sc + b_top;
         X.xe = reinterpret_cast<int64_t *>(sc + b_top + b_xs);
@@ -679,7 +712,7 @@ spv_status spv_pt_sample(spv_ctx *ctx, const spv_problem *P, const spv_pt_params
     L.stab = reinterpret_cast<const uint32_t *>(base + b_mt);
     L.snd = reinterpret_cast<const int32_t *>(base + b_mt + b_st);
     L.out = out;
-    L.scratch = base + b_mt + b_st + b_snd;
+    L.scratch = sbase;
     L.nqa = nqa;
     L.threads = threads;
     return hip_check(c, launch_pt(L, stream), "pt launch");

@@ -44,6 +44,12 @@ struct TableCache {
     int unit = -1;
 };
 
+struct PtTableCache {
+    std::vector<double> betas;
+    int scale = -1, nd = -1, row_len = -1;
+    void *dev = nullptr;  // the pt_tab allocation the blob was uploaded to
+};
+
 struct Ctx {
     int device = 0;
     int num_cus = 0;
@@ -55,7 +61,9 @@ struct Ctx {
     DevBuf scratch;
     DevBuf scratch2;
     DevBuf rounds;  // iterated-SPVAR working set
-    DevBuf pt;      // parallel-tempering tables and top-10 storage
+    DevBuf pt;      // parallel-tempering scratch: top-10 storage, boundary exchange
+    DevBuf pt_tab;  // parallel-tempering tables (Metropolis rows, swap rows, swap digits)
+    PtTableCache pt_cache;
     DevBuf batch;   // batched launch: descriptors, items, counter, images
     DevBuf top;     // sample assembly: per-list offsets
     DevBuf serve;   // serving slot: assembled tempering sample
@@ -243,6 +251,9 @@ struct PtSplit {
 spv_status plan_pt_split(Ctx *c, int n, int D, int K, int runs, int chains, int row_len, int nd, int icm_lo,
                          int icm_hi, bool single_fits, PtSplit *sp);
 unsigned pt_spin_limit();
+// LDS claimed by one spv_pt_sample launch with the shapes it would pick.
+spv_status pt_lds_footprint(Ctx *c, const spv_problem *P, int K, int runs, int chains, int icm_lo, int icm_hi,
+                            int64_t *lds_total);
 size_t ptx_lds_bytes(int n, int D, int m, int chains, int row_len, int nw_icm, bool big);
 hipError_t ptx_max_groups_resident(int nd, bool big, int threads, size_t lds, int *blocks_per_cu);
 hipError_t launch_ptx(const PtxLaunch &L, hipStream_t s);

@@ -143,6 +143,7 @@ __global__ __launch_bounds__(1024) void pt_kernel(PtArgs a) {
         tb[b] = L.tab + (size_t)sl * a.row_len;
     }
     const uint32_t quad = (uint32_t)(qf + q);
+    auto nbr_rec = [=](int k, int p) __attribute__((always_inline)) -> uint32_t { return L.nbr[(size_t)k * n + p]; };
     const bool pow2 = (nqa & (nqa - 1)) == 0 && nqa <= 64;
 
     // Initial state and energies.
@@ -159,15 +160,7 @@ __global__ __launch_bounds__(1024) void pt_kernel(PtArgs a) {
         for (int p = slot_t; active && p < n; p += nslots) {
             const uint32_t self = L.S[(size_t)p * nqa + q];
             int32_t f[4];
-#pragma unroll
-            for (int b = 0; b < 4; ++b) f[b] = L.hpos[p];
-            for (int k = 0; k < D; ++k) {
-                const uint32_t rec = L.nbr[(size_t)k * n + p];
-                const int32_t Jv = (int32_t)(int16_t)(rec & 0xffffu);
-                const uint32_t w = L.S[(rec >> 16) * nqa + q];
-#pragma unroll
-                for (int b = 0; b < 4; ++b) f[b] += Jv * dev::spin_of(w, b);
-            }
+            ptc::quad_fields(nbr_rec, D, p, L.S, nqa, q, L.hpos[p], f);
 #pragma unroll
             for (int b = 0; b < 4; ++b) e2[b] += (long long)dev::spin_of(self, b) * ((long long)L.hpos[p] + f[b]);
         }
@@ -188,15 +181,7 @@ __global__ __launch_bounds__(1024) void pt_kernel(PtArgs a) {
             for (int p = cs[c] + slot_t; active && p < pe; p += nslots) {
                 const uint32_t self = L.S[(size_t)p * nqa + q];
                 int32_t f[4];
-#pragma unroll
-                for (int b = 0; b < 4; ++b) f[b] = L.hpos[p];
-                for (int k = 0; k < D; ++k) {
-                    const uint32_t rec = L.nbr[(size_t)k * n + p];
-                    const int32_t Jv = (int32_t)(int16_t)(rec & 0xffffu);
-                    const uint32_t w = L.S[(rec >> 16) * nqa + q];
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) f[b] += Jv * dev::spin_of(w, b);
-                }
+                ptc::quad_fields(nbr_rec, D, p, L.S, nqa, q, L.hpos[p], f);
                 int32_t x[4];
                 bool up[4], pass[4];
 #pragma unroll
@@ -289,8 +274,8 @@ __global__ __launch_bounds__(1024) void pt_kernel(PtArgs a) {
                 const int ra = r0 + la, rb = r0 + lb;
                 const size_t qa_ = (size_t)((ra >> 2) - qf), qb_ = (size_t)((rb >> 2) - qf);
                 const int ba = ra & 3, bb = rb & 3;
-                auto byteA = [&](int p) -> unsigned char * { return L.Sb + ((size_t)p * nqa + qa_) * 4 + ba; };
-                auto byteB = [&](int p) -> unsigned char * { return L.Sb + ((size_t)p * nqa + qb_) * 4 + bb; };
+                auto byteA = [=](int p) __attribute__((always_inline)) -> unsigned char * { return L.Sb + ((size_t)p * nqa + qa_) * 4 + ba; };
+                auto byteB = [=](int p) __attribute__((always_inline)) -> unsigned char * { return L.Sb + ((size_t)p * nqa + qb_) * 4 + bb; };
                 // sites where the replicas disagree, counted in variable-index order
                 int n_neg = 0;
                 for (int i0 = 0; i0 < n; i0 += 64) {

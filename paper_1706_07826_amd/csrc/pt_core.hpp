@@ -39,5 +39,32 @@ __device__ inline bool swap_test(long long D, const uint32_t *__restrict__ T, in
     return true;
 }
 
+// Neighbour records are fetched this many at a time, so their loads (LDS or
+// global) are in flight together instead of one after another.
+constexpr int kRecBatch = 8;
+
+// Local fields f[b] = h + sum_k J_k s_k[b] of the 4 replicas in word q of
+// position p (spins S[pos][nq], records rec(k, p) = pos << 16 | uint16 J).
+template <typename Rec>
+__device__ __forceinline__ void quad_fields(Rec rec, int D, int p, const uint32_t *__restrict__ S, int nq, int q,
+                                            int32_t h, int32_t f[4]) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) f[b] = h;
+    for (int k0 = 0; k0 < D; k0 += kRecBatch) {
+        uint32_t rr[kRecBatch];
+#pragma unroll
+        for (int u = 0; u < kRecBatch; ++u) rr[u] = (k0 + u < D) ? rec(k0 + u, p) : 0u;
+        uint32_t w[kRecBatch];
+#pragma unroll
+        for (int u = 0; u < kRecBatch; ++u) w[u] = (k0 + u < D) ? S[(rr[u] >> 16) * nq + q] : 0u;
+#pragma unroll
+        for (int u = 0; u < kRecBatch; ++u) {
+            const int32_t Jv = (int32_t)(int16_t)(rr[u] & 0xffffu);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) f[b] += Jv * dev::spin_of(w[u], b);
+        }
+    }
+}
+
 }  // namespace ptc
 }  // namespace spv

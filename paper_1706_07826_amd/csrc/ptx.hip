@@ -72,13 +72,13 @@ struct PtxLds {
     int32_t *Lord;      // [chains*m][10]
     int32_t *acc;       // [chains*m]
     int32_t *cin;       // [2*chains] accepted boundary pairs (side, chain)
-    uint32_t *vis;      // [nw_icm][nwords]
+    uint32_t *vis;      // [nw_icm][2 * ceil(n / 64)] (8-byte aligned per wave)
     uint16_t *queue;    // [nw_icm][n]
 };
 
 __host__ __device__ inline size_t ptx_layout(int n, int D, int m, int chains, int row_len, int nw_icm, bool big,
                                              PtxLds *L, unsigned char *base) {
-    const int nq = chains * m / 4, nl = chains * m, nwords = (n + 31) / 32;
+    const int nq = chains * m / 4, nl = chains * m, vstride = 2 * ((n + 63) / 64);
     size_t o = 0;
     auto take = [&](size_t bytes) {
         size_t at = o;
@@ -90,7 +90,7 @@ __host__ __device__ inline size_t ptx_layout(int n, int D, int m, int chains, in
                  o_pos = take(in_lds * n * 4), o_tab = take((size_t)m * row_len * 4), o_S = take((size_t)n * nq * 4),
                  o_E = take((size_t)nl * 8), o_LE = take((size_t)nl * 80), o_Lw = take((size_t)nl * 40),
                  o_Lc = take((size_t)nl * 4), o_Lo = take((size_t)nl * 40), o_acc = take((size_t)nl * 4),
-                 o_cin = take((size_t)2 * chains * 4), o_vis = take((size_t)nw_icm * nwords * 4),
+                 o_cin = take((size_t)2 * chains * 4), o_vis = take((size_t)nw_icm * vstride * 4),
                  o_q = take((size_t)nw_icm * n * 2);
     if (L) {
         L->nbr = reinterpret_cast<uint32_t *>(base + o_nbr);
@@ -113,6 +113,11 @@ __host__ __device__ inline size_t ptx_layout(int n, int D, int m, int chains, in
     return o;
 }
 
+// Cluster growth: queued sites taken per step (in 64-lane chunks) and
+// neighbour records fetched per batch.
+constexpr int kBfsChunks = 2;
+constexpr int kBfsRecs = 4;
+
 __global__ void flags_zero_kernel(int *f, int count) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) f[i] = 0;
@@ -134,12 +139,12 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
     const int32_t *img = a.image;
     const uint32_t *gnbr = reinterpret_cast<const uint32_t *>(img + kImgHeader + 3 * n);
     const int32_t *gord = img + kImgHeader, *gpos = img + kImgHeader + n, *ghpos = img + kImgHeader + 2 * n;
-    auto NBR = [&](int k, int p) -> uint32_t { return BIG ? gnbr[(size_t)p * D + k] : L.nbr[(size_t)k * n + p]; };
-    auto HPOS = [&](int p) -> int32_t { return BIG ? ghpos[p] : L.hpos[p]; };
-    auto ORD = [&](int p) -> int32_t { return BIG ? gord[p] : L.ord[p]; };
-    auto POS = [&](int i) -> int32_t { return BIG ? gpos[i] : L.pos[i]; };
+    auto NBR = [=](int k, int p) __attribute__((always_inline)) -> uint32_t { return BIG ? gnbr[(size_t)p * D + k] : L.nbr[(size_t)k * n + p]; };
+    auto HPOS = [=](int p) __attribute__((always_inline)) -> int32_t { return BIG ? ghpos[p] : L.hpos[p]; };
+    auto ORD = [=](int p) __attribute__((always_inline)) -> int32_t { return BIG ? gord[p] : L.ord[p]; };
+    auto POS = [=](int i) __attribute__((always_inline)) -> int32_t { return BIG ? gpos[i] : L.pos[i]; };
     // byte of local replica l = chain * mg + (slot - s0) at position p
-    auto sbyte = [&](int l, int p) -> unsigned char * {
+    auto sbyte = [=](int l, int p) __attribute__((always_inline)) -> unsigned char * {
         const int ch = l / mg, o = l - ch * mg;
         return L.Sb + ((size_t)p * nq + ch * qpc + (o >> 2)) * 4 + (o & 3);
     };
@@ -191,14 +196,8 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
         for (int p = pt; active && p < n; p += nstr) {
             const uint32_t self = L.S[(size_t)p * nq + q];
             const int32_t hp = HPOS(p);
-            int32_t f[4] = {hp, hp, hp, hp};
-            for (int k = 0; k < D; ++k) {
-                const uint32_t rec = NBR(k, p);
-                const int32_t Jv = (int32_t)(int16_t)(rec & 0xffffu);
-                const uint32_t w = L.S[(rec >> 16) * nq + q];
-#pragma unroll
-                for (int b = 0; b < 4; ++b) f[b] += Jv * dev::spin_of(w, b);
-            }
+            int32_t f[4];
+            ptc::quad_fields(NBR, D, p, L.S, nq, q, hp, f);
 #pragma unroll
             for (int b = 0; b < 4; ++b) e2[b] += (long long)dev::spin_of(self, b) * ((long long)hp + f[b]);
         }
@@ -219,15 +218,8 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
             const int pe = cs[c + 1];
             for (int p = cs[c] + pt; active && p < pe; p += nstr) {
                 const uint32_t self = L.S[(size_t)p * nq + q];
-                const int32_t hp = HPOS(p);
-                int32_t f[4] = {hp, hp, hp, hp};
-                for (int k = 0; k < D; ++k) {
-                    const uint32_t rec = NBR(k, p);
-                    const int32_t Jv = (int32_t)(int16_t)(rec & 0xffffu);
-                    const uint32_t w = L.S[(rec >> 16) * nq + q];
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) f[b] += Jv * dev::spin_of(w, b);
-                }
+                int32_t f[4];
+                ptc::quad_fields(NBR, D, p, L.S, nq, q, HPOS(p), f);
                 int32_t x[4];
                 bool up[4], pass[4];
 #pragma unroll
@@ -300,9 +292,11 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                 const int side = tid / chains, ch = tid - side * chains;
                 a.xe[((xbase + side) * 2 + buf) * chains + ch] = L.E[ch * mg + (side ? mg - 1 : 0)];
             }
-            __threadfence();
+            // The barrier completes every thread's stores at workgroup scope; one
+            // agent-scope release by thread 0 then publishes them with the flag.
             __syncthreads();
             if (tid == 0) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
                 __hip_atomic_store(&a.flags[run * G + g], ls + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
                 for (int d = 0; d < 2 && !stop; ++d) {
                     const int nb = d == 0 ? g - 1 : g + 1;
@@ -317,10 +311,10 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                         __builtin_amdgcn_s_sleep(2);
                     }
                 }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
             __syncthreads();
             if (stop) break;
-            __threadfence();
         }
         {
             const int nin = (mg - par) / 2;            // pairs inside the group
@@ -389,42 +383,65 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
         // 3. Houdayer cluster moves between chains 0 and 1 at the group's slots.
         const int kb = max(a.icm_lo, s0), ke = min(a.icm_hi, s0 + mg);
         if (a.nw_icm > 0 && wid < a.nw_icm && kb < ke) {
-            uint32_t *vis = L.vis + (size_t)wid * nwords;
+            uint32_t *vis = L.vis + (size_t)wid * (2 * ((n + 63) / 64));
             uint16_t *queue = L.queue + (size_t)wid * n;
+            // The visited bitset doubles as the per-chunk disagreement masks of the seed pick.
+            unsigned long long *dmask = reinterpret_cast<unsigned long long *>(vis);
+            const int nchunks = (n + 63) / 64;
             for (int k = kb + wid; k < ke; k += a.nw_icm) {
                 const int la = k - s0, lb = mg + (k - s0);
+                // sites where the replicas disagree, in variable-index order, 64 per chunk
+                // (positions of 16 chunks fetched together)
                 int n_neg = 0;
-                for (int i0 = 0; i0 < n; i0 += 64) {
-                    const int i = i0 + lane;
-                    bool f = false;
-                    if (i < n) {
-                        const int p = POS(i);
-                        f = *sbyte(la, p) != *sbyte(lb, p);
+                for (int c0 = 0; c0 < nchunks; c0 += 16) {
+                    int pp[16];
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) {
+                        const int i = (c0 + u) * 64 + lane;
+                        pp[u] = (c0 + u < nchunks && i < n) ? POS(i) : -1;
                     }
-                    n_neg += __popcll(__ballot(f));
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) {
+                        if (c0 + u >= nchunks) break;
+                        const unsigned long long msk =
+                            __ballot(pp[u] >= 0 && *sbyte(la, pp[u]) != *sbyte(lb, pp[u]));
+                        if (lane == 0) dmask[c0 + u] = msk;
+                        n_neg += __popcll(msk);
+                    }
                 }
+                __builtin_amdgcn_wave_barrier();
                 if (n_neg == 0) continue;
                 const uint32_t w = dev::philox((uint32_t)k, t, (uint32_t)run, 4u << 24, a.k0, a.k1).w[0];
                 const int target = (int)(((unsigned long long)w * (unsigned long long)n_neg) >> 32);
-                int seed_p = -1, seen = 0;
-                for (int i0 = 0; i0 < n && seed_p < 0; i0 += 64) {
-                    const int i = i0 + lane;
-                    bool f = false;
-                    int p = 0;
-                    if (i < n) {
-                        p = POS(i);
-                        f = *sbyte(la, p) != *sbyte(lb, p);
+                // seed = the target-th disagreeing variable: chunk by a prefix over the masks
+                int seed_p = -1;
+                {
+                    int seen = 0;
+                    for (int c0 = 0; c0 < nchunks && seed_p < 0; c0 += 64) {
+                        const int c = c0 + lane;
+                        const unsigned long long m = c < nchunks ? dmask[c] : 0ull;
+                        const int cnt = __popcll(m);
+                        int incl = cnt;
+                        for (int d = 1; d < 64; d <<= 1) {
+                            const int y = __shfl_up(incl, d, 64);
+                            if (lane >= d) incl += y;
+                        }
+                        const int excl = seen + incl - cnt;
+                        const bool here = target >= excl && target < excl + cnt;
+                        const unsigned long long who = __ballot(here);
+                        if (who) {
+                            const int src = __ffsll((long long)who) - 1;
+                            const unsigned long long ms = __shfl(m, src, 64);
+                            const int rest = target - __shfl(excl, src, 64);
+                            // bit `rest` (in order) of the chosen chunk's mask
+                            const bool mine = ((ms >> lane) & 1ull) && __popcll(ms & lanemask_lt()) == rest;
+                            const int bitl = __ffsll((long long)__ballot(mine)) - 1;
+                            seed_p = POS((c0 + src) * 64 + bitl);
+                        }
+                        seen += __shfl(incl, 63, 64);
                     }
-                    const unsigned long long msk = __ballot(f);
-                    const int cnt = __popcll(msk);
-                    if (target < seen + cnt) {
-                        const bool me = f && (seen + __popcll(msk & lanemask_lt())) == target;
-                        const unsigned long long who = __ballot(me);
-                        const int src = __ffsll((long long)who) - 1;
-                        seed_p = __shfl(p, src, 64);
-                    }
-                    seen += cnt;
                 }
+                __builtin_amdgcn_wave_barrier();
                 for (int wd = lane; wd < nwords; wd += 64) vis[wd] = 0u;
                 __builtin_amdgcn_wave_barrier();
                 if (lane == 0) {
@@ -432,57 +449,85 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                     queue[0] = (uint16_t)seed_p;
                 }
                 __builtin_amdgcn_wave_barrier();
+                // Breadth-first growth over J != 0 edges between disagreeing sites.  A
+                // neighbour of a cluster site across a J != 0 edge is in the cluster
+                // exactly when the replicas disagree there, so each dequeued site adds
+                // its share of the flip energy -2 s_v (h_v + sum over agreeing
+                // neighbours J s_u) and is flipped in both replicas on the spot
+                // (flipping both keeps it disagreeing for later tests).
+                // Each step takes up to kBfsChunks * 64 queued sites at once, so their
+                // record loads and visited-set updates overlap.
                 int head = 0, tail = 1;
+                long long dA = 0, dB = 0;
                 while (head < tail) {
-                    const int chunk = min(64, tail - head);
-                    const bool act = lane < chunk;
-                    const int v = act ? (int)queue[head + lane] : 0;
-                    int newtail = tail;
-                    for (int kk = 0; kk < D; ++kk) {
-                        bool added = false;
-                        int u = 0;
-                        if (act) {
-                            const uint32_t rec = NBR(kk, v);
-                            u = (int)(rec >> 16);
-                            if ((rec & 0xffffu) != 0u && *sbyte(la, u) != *sbyte(lb, u)) {
-                                const uint32_t bit = 1u << (u & 31);
-                                const uint32_t old = atomicOr(&vis[u >> 5], bit);
-                                added = !(old & bit);
-                            }
-                        }
-                        const unsigned long long msk = __ballot(added);
-                        if (added) queue[newtail + __popcll(msk & lanemask_lt())] = (uint16_t)u;
-                        newtail += __popcll(msk);
+                    const int take = min(64 * kBfsChunks, tail - head);
+                    int v[kBfsChunks], sA[kBfsChunks], sB[kBfsChunks];
+                    int32_t fA[kBfsChunks], fB[kBfsChunks];
+                    bool act[kBfsChunks];
+#pragma unroll
+                    for (int c = 0; c < kBfsChunks; ++c) {
+                        act[c] = 64 * c + lane < take;
+                        v[c] = act[c] ? (int)queue[head + 64 * c + lane] : 0;
                     }
-                    head += chunk;
+#pragma unroll
+                    for (int c = 0; c < kBfsChunks; ++c) {
+                        fA[c] = fB[c] = act[c] ? HPOS(v[c]) : 0;
+                        sA[c] = (int)(int8_t)*sbyte(la, v[c]);
+                        sB[c] = (int)(int8_t)*sbyte(lb, v[c]);
+                    }
+                    int newtail = tail;
+                    for (int k0 = 0; k0 < D; k0 += kBfsRecs) {
+                        uint32_t rr[kBfsChunks][kBfsRecs];
+#pragma unroll
+                        for (int c = 0; c < kBfsChunks; ++c)
+#pragma unroll
+                            for (int uu = 0; uu < kBfsRecs; ++uu)
+                                rr[c][uu] = (act[c] && k0 + uu < D) ? NBR(k0 + uu, v[c]) : 0u;
+                        uint32_t bit[kBfsChunks][kBfsRecs], old[kBfsChunks][kBfsRecs];
+#pragma unroll
+                        for (int c = 0; c < kBfsChunks; ++c)
+#pragma unroll
+                            for (int uu = 0; uu < kBfsRecs; ++uu) {
+                                const int u = (int)(rr[c][uu] >> 16);
+                                const int32_t Jv = (int32_t)(int16_t)(rr[c][uu] & 0xffffu);
+                                const int au = (int)(int8_t)*sbyte(la, u), bu = (int)(int8_t)*sbyte(lb, u);
+                                const bool cand = Jv != 0 && au != bu;
+                                if (!cand) {
+                                    fA[c] += Jv * au;
+                                    fB[c] += Jv * bu;
+                                }
+                                bit[c][uu] = cand ? 1u << (u & 31) : 0u;
+                            }
+#pragma unroll
+                        for (int c = 0; c < kBfsChunks; ++c)
+#pragma unroll
+                            for (int uu = 0; uu < kBfsRecs; ++uu)
+                                old[c][uu] = bit[c][uu] ? atomicOr(&vis[(rr[c][uu] >> 16) >> 5], bit[c][uu]) : 0u;
+#pragma unroll
+                        for (int c = 0; c < kBfsChunks; ++c)
+#pragma unroll
+                            for (int uu = 0; uu < kBfsRecs; ++uu) {
+                                const bool added = bit[c][uu] && !(old[c][uu] & bit[c][uu]);
+                                const unsigned long long msk = __ballot(added);
+                                if (added)
+                                    queue[newtail + __popcll(msk & lanemask_lt())] = (uint16_t)(rr[c][uu] >> 16);
+                                newtail += __popcll(msk);
+                            }
+                    }
+#pragma unroll
+                    for (int c = 0; c < kBfsChunks; ++c)
+                        if (act[c]) {
+                            dA += -2ll * sA[c] * (long long)fA[c];
+                            dB += -2ll * sB[c] * (long long)fB[c];
+                            *sbyte(la, v[c]) = (unsigned char)(-sA[c]);
+                            *sbyte(lb, v[c]) = (unsigned char)(-sB[c]);
+                        }
+                    head += take;
                     tail = newtail;
                     __builtin_amdgcn_wave_barrier();
                 }
-                long long dA = 0, dB = 0;
-                for (int e = lane; e < tail; e += 64) {
-                    const int v = queue[e];
-                    const int sA = (int)(int8_t)*sbyte(la, v), sB = (int)(int8_t)*sbyte(lb, v);
-                    const long long hv = HPOS(v);
-                    dA += -2ll * hv * sA;
-                    dB += -2ll * hv * sB;
-                    for (int kk = 0; kk < D; ++kk) {
-                        const uint32_t rec = NBR(kk, v);
-                        const int u = (int)(rec >> 16);
-                        if (!((vis[u >> 5] >> (u & 31)) & 1u)) {
-                            const long long Jv = (int16_t)(rec & 0xffffu);
-                            dA += -2ll * Jv * sA * (int)(int8_t)*sbyte(la, u);
-                            dB += -2ll * Jv * sB * (int)(int8_t)*sbyte(lb, u);
-                        }
-                    }
-                }
                 dA = wave_sum(dA);
                 dB = wave_sum(dB);
-                __builtin_amdgcn_wave_barrier();
-                for (int e = lane; e < tail; e += 64) {
-                    const int v = queue[e];
-                    *sbyte(la, v) = (unsigned char)(-(int)(int8_t)*sbyte(la, v));
-                    *sbyte(lb, v) = (unsigned char)(-(int)(int8_t)*sbyte(lb, v));
-                }
                 if (lane == 0) {
                     L.E[la] += dA;
                     L.E[lb] += dB;

@@ -79,12 +79,11 @@ void footprint(spv_server *s, const spv_request &r, int64_t *lds, int64_t *hbm) 
         H += (int64_t)r.sweeps * row_len * 4;
         R = r.reads;
     } else {
-        const int cK = r.chains * r.K, nqa = (cK % 4 == 0) ? cK / 4 : cK / 4 + 2;
-        const int threads = (P.n * nqa >= 4096) ? 1024 : 256;
-        const int nw_icm = r.icm_hi > r.icm_lo ? std::min(threads / 64, r.icm_hi - r.icm_lo) : 0;
-        L = (int64_t)r.runs * (int64_t)pt_lds_bytes(P.n, D, r.K, r.chains, row_len, nqa, nw_icm);
+        if (pt_lds_footprint(&s->parent->c, &P, r.K, r.runs, r.chains, r.icm_lo, r.icm_hi, &L) != SPV_OK)
+            L = 0;  // the launch itself reports the error
         R = (int64_t)r.runs * r.chains * (r.K / 2) * kTopK;
         H += (int64_t)r.K * row_len * 4 + (int64_t)r.K * 7 * kDigitSize * 4 + R * std::max(P.n, 1);
+        H += (int64_t)r.runs * (r.K / 4) * (4 * r.chains * (int64_t)std::max(P.n, 1) + 4 * r.chains * 8 + 4);
         if (r.elite_frac > 0) H += R * (std::max(P.n, 1) + 8);  // assembled sample
     }
     if (r.elite_frac > 0 && R > 0) {
@@ -93,7 +92,6 @@ void footprint(spv_server *s, const spv_request &r, int64_t *lds, int64_t *hbm) 
     }
     *lds = L;
     *hbm = H;
-    (void)s;
 }
 
 spv_status launch(Slot &sl, Record &rec) {

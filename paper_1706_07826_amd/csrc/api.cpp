@@ -205,7 +205,7 @@ spv_status plan_pt_split(Ctx *c, int n, int D, int K, int runs, int chains, int 
         if (threads > 1024) continue;
         const int icm_slots = icm_hi > icm_lo ? std::min(m, icm_hi - icm_lo) : 0;
         for (int big = env_int("SPVAR_PT_BIG", 0) ? 1 : 0; big < 2; ++big) {
-            for (int nw = std::min(threads / 64, icm_slots); nw >= (icm_slots ? 1 : 0); --nw) {
+            for (int nw = std::min(icm_slots, 4); nw >= (icm_slots ? 1 : 0); --nw) {
                 const size_t lds = ptx_lds_bytes(n, D, m, chains, row_len, nw, big != 0) + 256;
                 if (lds > c->lds_max) continue;
                 int bpc = 0;

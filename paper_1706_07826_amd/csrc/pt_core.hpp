@@ -66,5 +66,48 @@ __device__ __forceinline__ void quad_fields(Rec rec, int D, int p, const uint32_
     }
 }
 
+// Lock-free union-find in LDS over 16-bit parents (parent[x] <= x always: a
+// root is only ever hooked under a smaller root, so every find terminates;
+// path splitting writes only ancestors, so concurrent finds stay valid).
+__device__ __forceinline__ uint32_t uf_find(uint16_t *parent, uint32_t x) {
+    uint32_t p = parent[x];
+    while (p != x) {
+        const uint32_t gp = parent[p];
+        if (gp != p) parent[x] = (uint16_t)gp;
+        x = p;
+        p = gp;
+    }
+    return x;
+}
+
+// Compare-and-swap of one 16-bit half through a 32-bit CAS on its word; fails
+// only when the half no longer holds `expect`.
+__device__ __forceinline__ bool cas16(uint16_t *addr, uint32_t expect, uint32_t desired) {
+    uint32_t *word = reinterpret_cast<uint32_t *>(reinterpret_cast<uintptr_t>(addr) & ~(uintptr_t)3);
+    const int sh = (reinterpret_cast<uintptr_t>(addr) & 2) ? 16 : 0;
+    uint32_t old = __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    for (;;) {
+        if (((old >> sh) & 0xffffu) != expect) return false;
+        const uint32_t want = (old & ~(0xffffu << sh)) | (desired << sh);
+        const uint32_t prev = atomicCAS(word, old, want);
+        if (prev == old) return true;
+        old = prev;
+    }
+}
+
+__device__ __forceinline__ void uf_union(uint16_t *parent, uint32_t a, uint32_t b) {
+    for (;;) {
+        a = uf_find(parent, a);
+        b = uf_find(parent, b);
+        if (a == b) return;
+        if (a > b) {
+            const uint32_t t = a;
+            a = b;
+            b = t;
+        }
+        if (cas16(&parent[b], b, a)) return;
+    }
+}
+
 }  // namespace ptc
 }  // namespace spv

@@ -15,7 +15,8 @@
 //      configurations) in an L2-resident exchange slot, after a release /
 //      acquire flag handshake between the two workgroups; an accepted pair
 //      copies the partner's published configuration in,
-//   3. Houdayer moves at the group's slots, a wavefront per slot pair,
+//   3. Houdayer moves at the group's slots, one slot pair at a time with the
+//      whole workgroup (lock-free union-find over the disagreeing sites),
 //   4. the top-10 offers of the group's colder slots.
 // The instance lives in LDS when it fits beside the replicas; otherwise the
 // neighbour records, biases and orderings are read from the global image
@@ -72,8 +73,9 @@ struct PtxLds {
     int32_t *Lord;      // [chains*m][10]
     int32_t *acc;       // [chains*m]
     int32_t *cin;       // [2*chains] accepted boundary pairs (side, chain)
-    uint32_t *vis;      // [nw_icm][2 * ceil(n / 64)] (8-byte aligned per wave)
-    uint16_t *queue;    // [nw_icm][n]
+    uint16_t *parent;          // [pairs][n rounded to even] union-find forests over positions
+    unsigned long long *dmask; // [pairs][ceil(n / 64)] disagreement masks in variable order
+    int32_t *misc;             // [4] broadcast scalars
 };
 
 __host__ __device__ inline size_t ptx_layout(int n, int D, int m, int chains, int row_len, int nw_icm, bool big,
@@ -90,8 +92,8 @@ __host__ __device__ inline size_t ptx_layout(int n, int D, int m, int chains, in
                  o_pos = take(in_lds * n * 4), o_tab = take((size_t)m * row_len * 4), o_S = take((size_t)n * nq * 4),
                  o_E = take((size_t)nl * 8), o_LE = take((size_t)nl * 80), o_Lw = take((size_t)nl * 40),
                  o_Lc = take((size_t)nl * 4), o_Lo = take((size_t)nl * 40), o_acc = take((size_t)nl * 4),
-                 o_cin = take((size_t)2 * chains * 4), o_vis = take((size_t)nw_icm * vstride * 4),
-                 o_q = take((size_t)nw_icm * n * 2);
+                 o_cin = take((size_t)2 * chains * 4), o_par = take((size_t)nw_icm * ((n + 1) & ~1) * 2),
+                 o_dm = take((size_t)nw_icm * vstride * 4), o_misc = take(16);
     if (L) {
         L->nbr = reinterpret_cast<uint32_t *>(base + o_nbr);
         L->hpos = reinterpret_cast<int32_t *>(base + o_h);
@@ -107,16 +109,15 @@ __host__ __device__ inline size_t ptx_layout(int n, int D, int m, int chains, in
         L->Lord = reinterpret_cast<int32_t *>(base + o_Lo);
         L->acc = reinterpret_cast<int32_t *>(base + o_acc);
         L->cin = reinterpret_cast<int32_t *>(base + o_cin);
-        L->vis = reinterpret_cast<uint32_t *>(base + o_vis);
-        L->queue = reinterpret_cast<uint16_t *>(base + o_q);
+        L->parent = reinterpret_cast<uint16_t *>(base + o_par);
+        L->dmask = reinterpret_cast<unsigned long long *>(base + o_dm);
+        L->misc = reinterpret_cast<int32_t *>(base + o_misc);
     }
     return o;
 }
 
-// Cluster growth: queued sites taken per step (in 64-lane chunks) and
-// neighbour records fetched per batch.
-constexpr int kBfsChunks = 2;
-constexpr int kBfsRecs = 4;
+// Slot pairs whose cluster moves run together (one forest and mask set each).
+constexpr int kIcmBatch = 4;
 
 __global__ void flags_zero_kernel(int *f, int count) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -129,24 +130,47 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
     __shared__ int cs[kMaxColours + 1];
     __shared__ int nacc;
     __shared__ int stop;
-    PtxLds L;
     const int n = a.n, D = a.D, K = a.K, chains = a.chains, G = a.G, row_len = a.row_len;
-    ptx_layout(n, D, a.m, chains, row_len, a.nw_icm, BIG, &L, smem);
+    PtxLds Lay;
+    ptx_layout(n, D, a.m, chains, row_len, a.nw_icm, BIG, &Lay, smem);
+    // LDS regions as plain locals (keeps the layout record out of scratch memory)
+    auto *const L_nbr = Lay.nbr;
+    auto *const L_hpos = Lay.hpos;
+    auto *const L_ord = Lay.ord;
+    auto *const L_pos = Lay.pos;
+    auto *const L_tab = Lay.tab;
+    auto *const L_S = Lay.S;
+    auto *const L_Sb = Lay.Sb;
+    auto *const L_E = Lay.E;
+    auto *const L_LE = Lay.LE;
+    auto *const L_Lwhen = Lay.Lwhen;
+    auto *const L_Lcnt = Lay.Lcnt;
+    auto *const L_Lord = Lay.Lord;
+    auto *const L_acc = Lay.acc;
+    auto *const L_cin = Lay.cin;
+    auto *const L_parent = Lay.parent;
+    auto *const L_dmask = Lay.dmask;
+    auto *const L_misc = Lay.misc;
     const int tid = threadIdx.x, T = blockDim.x, lane = dev::lane_id(), wid = tid >> 6, nw = T >> 6;
     const int run = blockIdx.x / G, g = blockIdx.x - run * G;
     const int s0 = g * a.m, mg = min(a.m, K - s0), qpc = mg >> 2, nq = chains * qpc, nl = chains * mg;
-    const int half = K / 2, Ls = chains * half, nwords = (n + 31) / 32;
+    const int half = K / 2, Ls = chains * half;
     const int32_t *img = a.image;
     const uint32_t *gnbr = reinterpret_cast<const uint32_t *>(img + kImgHeader + 3 * n);
     const int32_t *gord = img + kImgHeader, *gpos = img + kImgHeader + n, *ghpos = img + kImgHeader + 2 * n;
-    auto NBR = [=](int k, int p) __attribute__((always_inline)) -> uint32_t { return BIG ? gnbr[(size_t)p * D + k] : L.nbr[(size_t)k * n + p]; };
-    auto HPOS = [=](int p) __attribute__((always_inline)) -> int32_t { return BIG ? ghpos[p] : L.hpos[p]; };
-    auto ORD = [=](int p) __attribute__((always_inline)) -> int32_t { return BIG ? gord[p] : L.ord[p]; };
-    auto POS = [=](int i) __attribute__((always_inline)) -> int32_t { return BIG ? gpos[i] : L.pos[i]; };
+    const uint32_t *const lnbr = L_nbr;
+    const int32_t *const lhpos = L_hpos, *const lord = L_ord, *const lpos = L_pos;
+    unsigned char *const Sb = L_Sb;
+    auto NBR = [=](int k, int p) __attribute__((always_inline)) -> uint32_t {
+        return BIG ? gnbr[(size_t)p * D + k] : lnbr[(size_t)k * n + p];
+    };
+    auto HPOS = [=](int p) __attribute__((always_inline)) -> int32_t { return BIG ? ghpos[p] : lhpos[p]; };
+    auto ORD = [=](int p) __attribute__((always_inline)) -> int32_t { return BIG ? gord[p] : lord[p]; };
+    auto POS = [=](int i) __attribute__((always_inline)) -> int32_t { return BIG ? gpos[i] : lpos[i]; };
     // byte of local replica l = chain * mg + (slot - s0) at position p
     auto sbyte = [=](int l, int p) __attribute__((always_inline)) -> unsigned char * {
         const int ch = l / mg, o = l - ch * mg;
-        return L.Sb + ((size_t)p * nq + ch * qpc + (o >> 2)) * 4 + (o & 3);
+        return Sb + ((size_t)p * nq + ch * qpc + (o >> 2)) * 4 + (o & 3);
     };
 
     if (tid <= a.C) cs[tid] = img[3 + tid];
@@ -154,18 +178,18 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
     if (!BIG) {
         for (int idx = tid; idx < n * D; idx += T) {
             const int p = idx / D, k = idx - p * D;
-            L.nbr[(size_t)k * n + p] = gnbr[idx];
+            L_nbr[(size_t)k * n + p] = gnbr[idx];
         }
         for (int k = tid; k < n; k += T) {
-            L.ord[k] = gord[k];
-            L.pos[k] = gpos[k];
-            L.hpos[k] = ghpos[k];
+            L_ord[k] = gord[k];
+            L_pos[k] = gpos[k];
+            L_hpos[k] = ghpos[k];
         }
     }
-    for (int k = tid; k < mg * row_len; k += T) L.tab[k] = a.mtab[(size_t)s0 * row_len + k];
+    for (int k = tid; k < mg * row_len; k += T) L_tab[k] = a.mtab[(size_t)s0 * row_len + k];
     for (int k = tid; k < nl; k += T) {
-        L.E[k] = 0;
-        L.Lcnt[k] = 0;
+        L_E[k] = 0;
+        L_Lcnt[k] = 0;
     }
     __syncthreads();
 
@@ -178,7 +202,7 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
         loc[b] = chq * mg + 4 * jq + b;
-        tb[b] = L.tab + (size_t)(4 * jq + b) * row_len;
+        tb[b] = L_tab + (size_t)(4 * jq + b) * row_len;
     }
     const bool pow2 = (nq & (nq - 1)) == 0 && nq <= 64;
 
@@ -188,26 +212,26 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
         uint32_t word = 0;
 #pragma unroll
         for (int b = 0; b < 4; ++b) word |= ((w.w[b] >> 31) ? 0x01u : 0xFFu) << (8 * b);
-        L.S[(size_t)p * nq + q] = word;
+        L_S[(size_t)p * nq + q] = word;
     }
     __syncthreads();
     {
         long long e2[4] = {0, 0, 0, 0};
         for (int p = pt; active && p < n; p += nstr) {
-            const uint32_t self = L.S[(size_t)p * nq + q];
+            const uint32_t self = L_S[(size_t)p * nq + q];
             const int32_t hp = HPOS(p);
             int32_t f[4];
-            ptc::quad_fields(NBR, D, p, L.S, nq, q, hp, f);
+            ptc::quad_fields(NBR, D, p, L_S, nq, q, hp, f);
 #pragma unroll
             for (int b = 0; b < 4; ++b) e2[b] += (long long)dev::spin_of(self, b) * ((long long)hp + f[b]);
         }
         if (active)
 #pragma unroll
             for (int b = 0; b < 4; ++b)
-                atomicAdd(reinterpret_cast<unsigned long long *>(&L.E[loc[b]]), (unsigned long long)e2[b]);
+                atomicAdd(reinterpret_cast<unsigned long long *>(&L_E[loc[b]]), (unsigned long long)e2[b]);
     }
     __syncthreads();
-    for (int l = tid; l < nl; l += T) L.E[l] /= 2;  // sum of s(h + f) counts every coupler twice
+    for (int l = tid; l < nl; l += T) L_E[l] /= 2;  // sum of s(h + f) counts every coupler twice
     __syncthreads();
 
     for (int ls = 0; ls < a.sweeps; ++ls) {
@@ -217,9 +241,9 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
         for (int c = 0; c < a.C; ++c) {
             const int pe = cs[c + 1];
             for (int p = cs[c] + pt; active && p < pe; p += nstr) {
-                const uint32_t self = L.S[(size_t)p * nq + q];
+                const uint32_t self = L_S[(size_t)p * nq + q];
                 int32_t f[4];
-                ptc::quad_fields(NBR, D, p, L.S, nq, q, HPOS(p), f);
+                ptc::quad_fields(NBR, D, p, L_S, nq, q, HPOS(p), f);
                 int32_t x[4];
                 bool up[4], pass[4];
 #pragma unroll
@@ -252,7 +276,7 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                         mask |= 0xFEu << (8 * b);
                         dE[b] += 2ll * x[b];
                     }
-                if (mask) L.S[(size_t)p * nq + q] = self ^ mask;
+                if (mask) L_S[(size_t)p * nq + q] = self ^ mask;
             }
             __syncthreads();
         }
@@ -263,14 +287,14 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
             if (active && lane < nq)
 #pragma unroll
                 for (int b = 0; b < 4; ++b)
-                    if (dE[b]) atomicAdd(reinterpret_cast<unsigned long long *>(&L.E[loc[b]]), (unsigned long long)dE[b]);
+                    if (dE[b]) atomicAdd(reinterpret_cast<unsigned long long *>(&L_E[loc[b]]), (unsigned long long)dE[b]);
         } else if (active) {
 #pragma unroll
             for (int b = 0; b < 4; ++b)
-                if (dE[b]) atomicAdd(reinterpret_cast<unsigned long long *>(&L.E[loc[b]]), (unsigned long long)dE[b]);
+                if (dE[b]) atomicAdd(reinterpret_cast<unsigned long long *>(&L_E[loc[b]]), (unsigned long long)dE[b]);
         }
         if (tid == 0) nacc = 0;
-        if (tid < 2 * chains) L.cin[tid] = 0;
+        if (tid < 2 * chains) L_cin[tid] = 0;
         __syncthreads();
 
         // 2. Replica exchange.
@@ -290,7 +314,7 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
             }
             if (tid < 2 * chains) {
                 const int side = tid / chains, ch = tid - side * chains;
-                a.xe[((xbase + side) * 2 + buf) * chains + ch] = L.E[ch * mg + (side ? mg - 1 : 0)];
+                a.xe[((xbase + side) * 2 + buf) * chains + ch] = L_E[ch * mg + (side ? mg - 1 : 0)];
             }
             // The barrier completes every thread's stores at workgroup scope; one
             // agent-scope release by thread 0 then publishes them with the flag.
@@ -325,33 +349,33 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                 if (e < nin) {
                     const int k = s0 + par + 2 * e;
                     const int la = ch * mg + (k - s0);
-                    const long long Dd = L.E[la] - L.E[la + 1];
+                    const long long Dd = L_E[la] - L_E[la + 1];
                     if (swap_test(Dd, a.stab + (size_t)k * 7 * kDigitSize, a.snd[k], (uint32_t)k, t, cctr, a.k0,
                                   a.k1)) {
-                        const long long x = L.E[la];
-                        L.E[la] = L.E[la + 1];
-                        L.E[la + 1] = x;
-                        L.acc[atomicAdd(&nacc, 1)] = la;
+                        const long long x = L_E[la];
+                        L_E[la] = L_E[la + 1];
+                        L_E[la + 1] = x;
+                        L_acc[atomicAdd(&nacc, 1)] = la;
                     }
                 } else if (e == nin && g > 0) {
                     // pair (s0 - 1, s0): the lower neighbour's last slot against our first
                     const int k = s0 - 1;
                     const size_t xi = ((((size_t)run * G + (g - 1)) * 2 + 1) * 2 + buf) * chains + ch;
-                    const long long Ek = a.xe[xi], Ek1 = L.E[ch * mg];
+                    const long long Ek = a.xe[xi], Ek1 = L_E[ch * mg];
                     if (swap_test(Ek - Ek1, a.stab + (size_t)k * 7 * kDigitSize, a.snd[k], (uint32_t)k, t, cctr,
                                   a.k0, a.k1)) {
-                        L.E[ch * mg] = Ek;
-                        L.cin[0 * chains + ch] = 1;
+                        L_E[ch * mg] = Ek;
+                        L_cin[0 * chains + ch] = 1;
                     }
                 } else if (e == nin + 1 && g < G - 1) {
                     // pair (s0 + mg - 1, s0 + mg): our last slot against the upper neighbour's first
                     const int k = s0 + mg - 1;
                     const size_t xi = ((((size_t)run * G + (g + 1)) * 2 + 0) * 2 + buf) * chains + ch;
-                    const long long Ek = L.E[ch * mg + mg - 1], Ek1 = a.xe[xi];
+                    const long long Ek = L_E[ch * mg + mg - 1], Ek1 = a.xe[xi];
                     if (swap_test(Ek - Ek1, a.stab + (size_t)k * 7 * kDigitSize, a.snd[k], (uint32_t)k, t, cctr,
                                   a.k0, a.k1)) {
-                        L.E[ch * mg + mg - 1] = Ek1;
-                        L.cin[1 * chains + ch] = 1;
+                        L_E[ch * mg + mg - 1] = Ek1;
+                        L_cin[1 * chains + ch] = 1;
                     }
                 }
             }
@@ -361,7 +385,7 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
             const int na = nacc;
             for (int idx = tid; idx < n * na; idx += T) {
                 const int pr = idx / n, p = idx - pr * n;
-                const int la = L.acc[pr];
+                const int la = L_acc[pr];
                 unsigned char *A = sbyte(la, p), *B = sbyte(la + 1, p);
                 const unsigned char x = *A;
                 *A = *B;
@@ -370,7 +394,7 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
             if (edge)
                 for (int idx = tid; idx < 2 * chains * n; idx += T) {
                     const int sc = idx / n, p = idx - sc * n;
-                    if (!L.cin[sc]) continue;
+                    if (!L_cin[sc]) continue;
                     const int side = sc / chains, ch = sc - side * chains;
                     // side 0 takes the lower neighbour's last slot, side 1 the upper neighbour's first
                     const int nb = side == 0 ? g - 1 : g + 1, nside = side == 0 ? 1 : 0;
@@ -380,46 +404,63 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
             __syncthreads();
         }
 
-        // 3. Houdayer cluster moves between chains 0 and 1 at the group's slots.
+        // 3. Houdayer cluster moves between chains 0 and 1 at the group's slots, up to
+        // kIcmBatch slot pairs at a time with the whole workgroup: each cluster is the
+        // connected component of its seed in the graph of J != 0 edges between sites
+        // where the pair's replicas disagree, found with a lock-free union-find in LDS
+        // (the pairs share every neighbour-record fetch).
         const int kb = max(a.icm_lo, s0), ke = min(a.icm_hi, s0 + mg);
-        if (a.nw_icm > 0 && wid < a.nw_icm && kb < ke) {
-            uint32_t *vis = L.vis + (size_t)wid * (2 * ((n + 63) / 64));
-            uint16_t *queue = L.queue + (size_t)wid * n;
-            // The visited bitset doubles as the per-chunk disagreement masks of the seed pick.
-            unsigned long long *dmask = reinterpret_cast<unsigned long long *>(vis);
-            const int nchunks = (n + 63) / 64;
-            for (int k = kb + wid; k < ke; k += a.nw_icm) {
-                const int la = k - s0, lb = mg + (k - s0);
-                // sites where the replicas disagree, in variable-index order, 64 per chunk
-                // (positions of 16 chunks fetched together)
-                int n_neg = 0;
-                for (int c0 = 0; c0 < nchunks; c0 += 16) {
-                    int pp[16];
+        const int nchunks = (n + 63) / 64, vstr = 2 * nchunks, n16 = (n + 1) & ~1;
+        const size_t pstride = (size_t)nq * 4;
+        for (int kq = kb; a.nw_icm > 0 && kq < ke; kq += a.nw_icm) {
+            const int nb = min(a.nw_icm, ke - kq);
+            unsigned char *pa[kIcmBatch], *pb[kIcmBatch];
 #pragma unroll
-                    for (int u = 0; u < 16; ++u) {
-                        const int i = (c0 + u) * 64 + lane;
-                        pp[u] = (c0 + u < nchunks && i < n) ? POS(i) : -1;
-                    }
+            for (int j = 0; j < kIcmBatch; ++j) {
+                const int la = min(kq + j, ke - 1) - s0, lb = mg + la;
+                pa[j] = Sb + (size_t)(((la % mg) >> 2)) * 4 + (la & 3);
+                pb[j] = Sb + (size_t)(qpc + ((lb % mg) >> 2)) * 4 + (lb & 3);
+            }
+            auto dis = [=](int j, int p) __attribute__((always_inline)) -> bool {
+                return pa[j][(size_t)p * pstride] != pb[j][(size_t)p * pstride];
+            };
+            // disagreement masks in variable-index order, 64 variables per chunk
+            for (int c0 = wid; c0 < nchunks; c0 += 4 * nw) {
+                int pp[4];
 #pragma unroll
-                    for (int u = 0; u < 16; ++u) {
-                        if (c0 + u >= nchunks) break;
-                        const unsigned long long msk =
-                            __ballot(pp[u] >= 0 && *sbyte(la, pp[u]) != *sbyte(lb, pp[u]));
-                        if (lane == 0) dmask[c0 + u] = msk;
-                        n_neg += __popcll(msk);
-                    }
+                for (int u = 0; u < 4; ++u) {
+                    const int i = (c0 + u * nw) * 64 + lane;
+                    pp[u] = (c0 + u * nw < nchunks && i < n) ? POS(i) : -1;
                 }
-                __builtin_amdgcn_wave_barrier();
-                if (n_neg == 0) continue;
-                const uint32_t w = dev::philox((uint32_t)k, t, (uint32_t)run, 4u << 24, a.k0, a.k1).w[0];
-                const int target = (int)(((unsigned long long)w * (unsigned long long)n_neg) >> 32);
-                // seed = the target-th disagreeing variable: chunk by a prefix over the masks
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int j = 0; j < kIcmBatch; ++j) {
+                        if (j >= nb) break;
+                        const unsigned long long m = __ballot(pp[u] >= 0 && dis(j, pp[u]));
+                        if (lane == 0 && c0 + u * nw < nchunks) L_dmask[(size_t)j * nchunks + c0 + u * nw] = m;
+                    }
+            }
+            for (int idx = tid; idx < nb * n16; idx += T) {
+                const int j = idx / n16, p = idx - j * n16;
+                L_parent[idx] = (uint16_t)p;
+            }
+            __syncthreads();
+            if (wid < nb) {
+                // seed of pair wid = the target-th disagreeing variable
+                const int j = wid, k = kq + j;
+                const unsigned long long *dm = L_dmask + (size_t)j * nchunks;
+                int n_neg = 0;
+                for (int c = lane; c < nchunks; c += 64) n_neg += __popcll(dm[c]);
+                for (int d = 32; d >= 1; d >>= 1) n_neg += __shfl_xor(n_neg, d, 64);
                 int seed_p = -1;
-                {
+                if (n_neg > 0) {
+                    const uint32_t w = dev::philox((uint32_t)k, t, (uint32_t)run, 4u << 24, a.k0, a.k1).w[0];
+                    const int target = (int)(((unsigned long long)w * (unsigned long long)n_neg) >> 32);
                     int seen = 0;
                     for (int c0 = 0; c0 < nchunks && seed_p < 0; c0 += 64) {
                         const int c = c0 + lane;
-                        const unsigned long long m = c < nchunks ? dmask[c] : 0ull;
+                        const unsigned long long m = c < nchunks ? dm[c] : 0ull;
                         const int cnt = __popcll(m);
                         int incl = cnt;
                         for (int d = 1; d < 64; d <<= 1) {
@@ -427,13 +468,11 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                             if (lane >= d) incl += y;
                         }
                         const int excl = seen + incl - cnt;
-                        const bool here = target >= excl && target < excl + cnt;
-                        const unsigned long long who = __ballot(here);
+                        const unsigned long long who = __ballot(target >= excl && target < excl + cnt);
                         if (who) {
                             const int src = __ffsll((long long)who) - 1;
                             const unsigned long long ms = __shfl(m, src, 64);
                             const int rest = target - __shfl(excl, src, 64);
-                            // bit `rest` (in order) of the chosen chunk's mask
                             const bool mine = ((ms >> lane) & 1ull) && __popcll(ms & lanemask_lt()) == rest;
                             const int bitl = __ffsll((long long)__ballot(mine)) - 1;
                             seed_p = POS((c0 + src) * 64 + bitl);
@@ -441,101 +480,117 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                         seen += __shfl(incl, 63, 64);
                     }
                 }
-                __builtin_amdgcn_wave_barrier();
-                for (int wd = lane; wd < nwords; wd += 64) vis[wd] = 0u;
-                __builtin_amdgcn_wave_barrier();
-                if (lane == 0) {
-                    vis[seed_p >> 5] = 1u << (seed_p & 31);
-                    queue[0] = (uint16_t)seed_p;
-                }
-                __builtin_amdgcn_wave_barrier();
-                // Breadth-first growth over J != 0 edges between disagreeing sites.  A
-                // neighbour of a cluster site across a J != 0 edge is in the cluster
-                // exactly when the replicas disagree there, so each dequeued site adds
-                // its share of the flip energy -2 s_v (h_v + sum over agreeing
-                // neighbours J s_u) and is flipped in both replicas on the spot
-                // (flipping both keeps it disagreeing for later tests).
-                // Each step takes up to kBfsChunks * 64 queued sites at once, so their
-                // record loads and visited-set updates overlap.
-                int head = 0, tail = 1;
-                long long dA = 0, dB = 0;
-                while (head < tail) {
-                    const int take = min(64 * kBfsChunks, tail - head);
-                    int v[kBfsChunks], sA[kBfsChunks], sB[kBfsChunks];
-                    int32_t fA[kBfsChunks], fB[kBfsChunks];
-                    bool act[kBfsChunks];
-#pragma unroll
-                    for (int c = 0; c < kBfsChunks; ++c) {
-                        act[c] = 64 * c + lane < take;
-                        v[c] = act[c] ? (int)queue[head + 64 * c + lane] : 0;
-                    }
-#pragma unroll
-                    for (int c = 0; c < kBfsChunks; ++c) {
-                        fA[c] = fB[c] = act[c] ? HPOS(v[c]) : 0;
-                        sA[c] = (int)(int8_t)*sbyte(la, v[c]);
-                        sB[c] = (int)(int8_t)*sbyte(lb, v[c]);
-                    }
-                    int newtail = tail;
-                    for (int k0 = 0; k0 < D; k0 += kBfsRecs) {
-                        uint32_t rr[kBfsChunks][kBfsRecs];
-#pragma unroll
-                        for (int c = 0; c < kBfsChunks; ++c)
-#pragma unroll
-                            for (int uu = 0; uu < kBfsRecs; ++uu)
-                                rr[c][uu] = (act[c] && k0 + uu < D) ? NBR(k0 + uu, v[c]) : 0u;
-                        uint32_t bit[kBfsChunks][kBfsRecs], old[kBfsChunks][kBfsRecs];
-#pragma unroll
-                        for (int c = 0; c < kBfsChunks; ++c)
-#pragma unroll
-                            for (int uu = 0; uu < kBfsRecs; ++uu) {
-                                const int u = (int)(rr[c][uu] >> 16);
-                                const int32_t Jv = (int32_t)(int16_t)(rr[c][uu] & 0xffffu);
-                                const int au = (int)(int8_t)*sbyte(la, u), bu = (int)(int8_t)*sbyte(lb, u);
-                                const bool cand = Jv != 0 && au != bu;
-                                if (!cand) {
-                                    fA[c] += Jv * au;
-                                    fB[c] += Jv * bu;
-                                }
-                                bit[c][uu] = cand ? 1u << (u & 31) : 0u;
-                            }
-#pragma unroll
-                        for (int c = 0; c < kBfsChunks; ++c)
-#pragma unroll
-                            for (int uu = 0; uu < kBfsRecs; ++uu)
-                                old[c][uu] = bit[c][uu] ? atomicOr(&vis[(rr[c][uu] >> 16) >> 5], bit[c][uu]) : 0u;
-#pragma unroll
-                        for (int c = 0; c < kBfsChunks; ++c)
-#pragma unroll
-                            for (int uu = 0; uu < kBfsRecs; ++uu) {
-                                const bool added = bit[c][uu] && !(old[c][uu] & bit[c][uu]);
-                                const unsigned long long msk = __ballot(added);
-                                if (added)
-                                    queue[newtail + __popcll(msk & lanemask_lt())] = (uint16_t)(rr[c][uu] >> 16);
-                                newtail += __popcll(msk);
-                            }
-                    }
-#pragma unroll
-                    for (int c = 0; c < kBfsChunks; ++c)
-                        if (act[c]) {
-                            dA += -2ll * sA[c] * (long long)fA[c];
-                            dB += -2ll * sB[c] * (long long)fB[c];
-                            *sbyte(la, v[c]) = (unsigned char)(-sA[c]);
-                            *sbyte(lb, v[c]) = (unsigned char)(-sB[c]);
-                        }
-                    head += take;
-                    tail = newtail;
-                    __builtin_amdgcn_wave_barrier();
-                }
-                dA = wave_sum(dA);
-                dB = wave_sum(dB);
-                if (lane == 0) {
-                    L.E[la] += dA;
-                    L.E[lb] += dB;
-                }
-                __builtin_amdgcn_wave_barrier();
+                if (lane == 0) L_misc[j] = seed_p;
             }
+            __syncthreads();
+            // The masks are consumed: their words now collect cluster membership.
+            uint32_t *const memb = reinterpret_cast<uint32_t *>(L_dmask);
+            for (int wd = tid; wd < nb * vstr; wd += T) memb[wd] = 0u;
+            // join the endpoints of every J != 0 edge between disagreeing sites (two
+            // positions per thread and step, their records fetched together)
+            for (int p0 = tid; p0 < n; p0 += 2 * T) {
+                unsigned dp[2];
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    dp[c] = 0;
+#pragma unroll
+                    for (int j = 0; j < kIcmBatch; ++j)
+                        if (j < nb && p0 + c * T < n && dis(j, p0 + c * T)) dp[c] |= 1u << j;
+                }
+                for (int k0 = 0; k0 < D; k0 += ptc::kRecBatch) {
+                    uint32_t rr[2][ptc::kRecBatch];
+#pragma unroll
+                    for (int c = 0; c < 2; ++c)
+#pragma unroll
+                        for (int uu = 0; uu < ptc::kRecBatch; ++uu)
+                            rr[c][uu] = (dp[c] && k0 + uu < D) ? NBR(k0 + uu, p0 + c * T) : 0u;
+#pragma unroll
+                    for (int c = 0; c < 2; ++c)
+#pragma unroll
+                        for (int uu = 0; uu < ptc::kRecBatch; ++uu) {
+                            const int p = p0 + c * T, u = (int)(rr[c][uu] >> 16);
+                            if ((rr[c][uu] & 0xffffu) == 0u || u <= p) continue;
+#pragma unroll
+                            for (int j = 0; j < kIcmBatch; ++j)
+                                if (((dp[c] >> j) & 1u) && dis(j, u)) ptc::uf_union(L_parent + (size_t)j * n16, p, u);
+                        }
+                }
+            }
+            __syncthreads();
+            // energy change of flipping each seed's component: -2 s_v (h_v + sum over
+            // agreeing neighbours J s_u) per site (a neighbour across a J != 0 edge is in
+            // the cluster exactly when it disagrees); the replicas are only written after
+            // every site has been read
+            uint32_t root[kIcmBatch];
+#pragma unroll
+            for (int j = 0; j < kIcmBatch; ++j) {
+                const int sp = j < nb ? L_misc[j] : -1;
+                root[j] = sp >= 0 ? ptc::uf_find(L_parent + (size_t)j * n16, (uint32_t)sp) : 0xffffffffu;
+            }
+            long long dA[kIcmBatch], dB[kIcmBatch];
+#pragma unroll
+            for (int j = 0; j < kIcmBatch; ++j) dA[j] = dB[j] = 0;
+            for (int p = tid; p < n; p += T) {
+                unsigned in = 0;
+#pragma unroll
+                for (int j = 0; j < kIcmBatch; ++j)
+                    if (root[j] != 0xffffffffu && dis(j, p) && ptc::uf_find(L_parent + (size_t)j * n16, (uint32_t)p) == root[j])
+                        in |= 1u << j;
+                if (!in) continue;
+                const int32_t hp = HPOS(p);
+                int32_t fA[kIcmBatch], fB[kIcmBatch];
+#pragma unroll
+                for (int j = 0; j < kIcmBatch; ++j) fA[j] = fB[j] = hp;
+                for (int k0 = 0; k0 < D; k0 += ptc::kRecBatch) {
+                    uint32_t rr[ptc::kRecBatch];
+#pragma unroll
+                    for (int uu = 0; uu < ptc::kRecBatch; ++uu) rr[uu] = k0 + uu < D ? NBR(k0 + uu, p) : 0u;
+#pragma unroll
+                    for (int uu = 0; uu < ptc::kRecBatch; ++uu) {
+                        const int u = (int)(rr[uu] >> 16);
+                        const int32_t Jv = (int32_t)(int16_t)(rr[uu] & 0xffffu);
+                        if (Jv == 0) continue;
+#pragma unroll
+                        for (int j = 0; j < kIcmBatch; ++j) {
+                            if (!((in >> j) & 1u)) continue;
+                            const int au = (int)(int8_t)pa[j][(size_t)u * pstride];
+                            const int bu = (int)(int8_t)pb[j][(size_t)u * pstride];
+                            if (au == bu) {
+                                fA[j] += Jv * au;
+                                fB[j] += Jv * bu;
+                            }
+                        }
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < kIcmBatch; ++j)
+                    if ((in >> j) & 1u) {
+                        atomicOr(&memb[(size_t)j * vstr + (p >> 5)], 1u << (p & 31));
+                        dA[j] += -2ll * (int)(int8_t)pa[j][(size_t)p * pstride] * (long long)fA[j];
+                        dB[j] += -2ll * (int)(int8_t)pb[j][(size_t)p * pstride] * (long long)fB[j];
+                    }
+            }
+#pragma unroll
+            for (int j = 0; j < kIcmBatch; ++j) {
+                if (j >= nb) break;
+                const long long sa = wave_sum(dA[j]), sb = wave_sum(dB[j]);
+                const int la = kq + j - s0, lb = mg + la;
+                if (lane == 0) {
+                    if (sa) atomicAdd(reinterpret_cast<unsigned long long *>(&L_E[la]), (unsigned long long)sa);
+                    if (sb) atomicAdd(reinterpret_cast<unsigned long long *>(&L_E[lb]), (unsigned long long)sb);
+                }
+            }
+            __syncthreads();
+            // flip the clusters in both replicas
+            for (int p = tid; p < n; p += T)
+#pragma unroll
+                for (int j = 0; j < kIcmBatch; ++j)
+                    if (j < nb && ((memb[(size_t)j * vstr + (p >> 5)] >> (p & 31)) & 1u)) {
+                        pa[j][(size_t)p * pstride] = (unsigned char)(-(int)(int8_t)pa[j][(size_t)p * pstride]);
+                        pb[j][(size_t)p * pstride] = (unsigned char)(-(int)(int8_t)pb[j][(size_t)p * pstride]);
+                    }
+            __syncthreads();
         }
-        if (a.nw_icm > 0) __syncthreads();
 
         // 4. Top-10 lists of the group's colder slots.
         const int kc = max(K - half, s0), ncold = max(0, s0 + mg - kc);
@@ -543,10 +598,10 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
             const int ch = li / ncold, k = kc + (li - ch * ncold);
             const int l = ch * mg + (k - s0);
             const int gl = ch * half + (k - (K - half));
-            const long long Ec = L.E[l];
-            const int cnt = L.Lcnt[l];
-            long long *LE = L.LE + (size_t)l * 10;
-            int32_t *LW = L.Lwhen + (size_t)l * 10;
+            const long long Ec = L_E[l];
+            const int cnt = L_Lcnt[l];
+            long long *LE = L_LE + (size_t)l * 10;
+            int32_t *LW = L_Lwhen + (size_t)l * 10;
             bool cand = cnt < 10;
             if (!cand) {
                 long long worst = LE[0];
@@ -574,7 +629,7 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
             if (lane == 0) {
                 LE[victim] = Ec;
                 LW[victim] = ls;
-                if (cnt < 10) L.Lcnt[l] = cnt + 1;
+                if (cnt < 10) L_Lcnt[l] = cnt + 1;
             }
             __builtin_amdgcn_wave_barrier();
         }
@@ -595,7 +650,7 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
     if (a.final_E)
         for (int l = tid; l < nl; l += T) {
             const int ch = l / mg, slot = s0 + (l - ch * mg);
-            a.final_E[((size_t)run * chains + ch) * K + slot] = L.E[l];
+            a.final_E[((size_t)run * chains + ch) * K + slot] = L_E[l];
         }
     if (a.final_spins)
         for (int idx = tid; idx < nl * n; idx += T) {
@@ -606,19 +661,19 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
     if (a.top_E || a.top_spins || a.top_count) {
         // Rank of entry e of a list = number of entries ordered before it by (E, insertion).
         const int nlist = chains * ncold;
-        for (int le = tid; le < nlist * 10; le += T) L.Lord[le] = -1;
+        for (int le = tid; le < nlist * 10; le += T) L_Lord[le] = -1;
         __syncthreads();
         for (int le = tid; le < nlist * 10; le += T) {
             const int li = le / 10, e = le - li * 10;
             const int ch = li / ncold, k = kc + (li - ch * ncold);
             const int l = ch * mg + (k - s0);
-            const long long *LE = L.LE + (size_t)l * 10;
-            const int32_t *LW = L.Lwhen + (size_t)l * 10;
-            const int cnt = L.Lcnt[l];
+            const long long *LE = L_LE + (size_t)l * 10;
+            const int32_t *LW = L_Lwhen + (size_t)l * 10;
+            const int cnt = L_Lcnt[l];
             if (e < cnt) {
                 int rank = 0;
                 for (int o = 0; o < cnt; ++o) rank += (LE[o] < LE[e] || (LE[o] == LE[e] && LW[o] < LW[e])) ? 1 : 0;
-                L.Lord[li * 10 + rank] = e;
+                L_Lord[li * 10 + rank] = e;
             }
             if (e == 0 && a.top_count) a.top_count[(size_t)run * Ls + ch * half + (k - (K - half))] = cnt;
         }
@@ -628,8 +683,8 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                 const int li = le / 10, rank = le - li * 10;
                 const int ch = li / ncold, k = kc + (li - ch * ncold);
                 const int l = ch * mg + (k - s0), gl = ch * half + (k - (K - half));
-                const int e = L.Lord[le];
-                a.top_E[((size_t)run * Ls + gl) * 10 + rank] = e >= 0 ? L.LE[(size_t)l * 10 + e] : 0x7FFFFFFFFFFFFFFFll;
+                const int e = L_Lord[le];
+                a.top_E[((size_t)run * Ls + gl) * 10 + rank] = e >= 0 ? L_LE[(size_t)l * 10 + e] : 0x7FFFFFFFFFFFFFFFll;
             }
         if (a.top_spins)
             for (size_t idx = tid; idx < (size_t)nlist * 10 * n; idx += T) {
@@ -637,7 +692,7 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                 const int li = lr / 10, rank = lr - li * 10;
                 const int ch = li / ncold, k = kc + (li - ch * ncold);
                 const int gl = ch * half + (k - (K - half));
-                const int e = L.Lord[li * 10 + rank];
+                const int e = L_Lord[li * 10 + rank];
                 a.top_spins[((size_t)run * Ls + gl) * 10 * n + (size_t)rank * n + i] =
                     e >= 0 ? a.tops[(((size_t)run * Ls + gl) * 10 + e) * n + POS(i)] : (int8_t)0;
             }

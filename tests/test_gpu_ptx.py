@@ -40,6 +40,11 @@ CASES = [
     ("zero_sweeps_G2", lambda: si.chimera(2, seed=7), 8, 2, 1, 0, None, 2, 0, 0),
     ("one_sweep_G2", lambda: si.chimera(2, seed=8), 8, 2, 1, 1, None, 2, 0, 1),
     ("K4_G1_forced_split", lambda: si.chimera(2, seed=9), 4, 3, 2, 40, (0, 4), 1, 0, 0),
+    # many waves per workgroup on the cluster moves (1024 threads)
+    ("cubic10_K8_G2_icm_wide", lambda: si.cubic_lattice(10, "gauss", seed=10, scale_log2=10), 8, 2, 2, 30,
+     (0, 8), 2, 0, 0),
+    ("cubic10_K8_G2_icm_wide_big", lambda: si.cubic_lattice(10, "gauss", seed=11, scale_log2=10), 8, 1, 2, 30,
+     (0, 8), 2, 1, 1),
 ]
 
 

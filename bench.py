@@ -24,33 +24,48 @@ if ROOT not in sys.path:
 
 BASELINE_METRIC = "spin-updates/s (batched vs plain, bit-exact); SPVAR solves/s; p50/p99 latency"
 
-# VALU lane-slots per Metropolis update on the Chimera workload (single-digit
-# threshold test): local field over the mean degree (one conditional add per
-# coupler), 4 slots for x = -s f / sign test / threshold compare / flip, and a
-# quarter of one Philox4x32-10 block: 10 rounds of two 32x32->64 products
-# (v_mad_u64_u32, 2 issue slots each on gfx950) and two 3-input xors, i.e. 60
-# slots per block (a chained-Philox probe measures 59-66 slots per block).
+# VALU lane-slots per Metropolis update (algorithmic count, the roofline's
+# numerator).  A Philox4x32-10 block costs 60 slots: 10 rounds of two
+# 32x32->64 products (v_mad_u64_u32, 2 issue slots each on gfx950) and two
+# 3-input xors; a chained-Philox probe measures 59-66 slots per block.  One
+# block serves the 4 replicas of a word, so 15 slots per update.  The
+# byte-parallel path (every |J|, |h| small enough for one-byte lanes) then adds,
+# per neighbour, one AND and one ADD on a word of 4 replicas (2/4 slot per
+# update) and about 4 slots per update for the field assembly, sign test,
+# threshold compare and flip; the general path adds one multiply-add per
+# neighbour and replica (1 slot) and the same 4.
 PHILOX_SLOTS = 10 * (2 * 2 + 2)
 PEAK_VALU_TSLOTS = 256 * 64 * 2.4e9 / 1e12  # 256 CUs x 64 lanes x 2.4 GHz = 39.32 T lane-slots/s
+SA_PROFILE_SOURCES = ["paper_1706_07826_amd/csrc/sa.hip", "paper_1706_07826_amd/csrc/swar_core.hpp",
+                      "paper_1706_07826_amd/csrc/sa_core.hpp", "paper_1706_07826_amd/csrc/device.hpp"]
 
 
-def slots_per_update(mean_degree):
-    return mean_degree + 4 + PHILOX_SLOTS / 4.0
+def slots_per_update(mean_degree, byte_parallel):
+    per_neighbour = 0.5 if byte_parallel else 1.0
+    return mean_degree * per_neighbour + 4 + PHILOX_SLOTS / 4.0
+
+
+def sources_digest(paths):
+    """sha256 over the concatenated bytes of the given repo-relative files."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in paths:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def profiled_traffic_bytes():
     """HBM bytes per launch of the SA kernel from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE scaled by a copy of known size), or None
-    when the kernel source changed after the counters were taken."""
-    import hashlib
+    when any source of the kernel changed after the counters were taken."""
     try:
         with open(os.path.join(ROOT, "profiles", "sa_kernel_chimera8_sa.json")) as f:
             prof = json.load(f)
-        with open(os.path.join(ROOT, prof["source"]), "rb") as f:
-            digest = hashlib.sha256(f.read()).hexdigest()
+        digest = sources_digest(prof["sources"])
     except (OSError, KeyError, ValueError):
         return None
-    if not digest.startswith(prof["source_sha256_prefix"]):
+    if not digest.startswith(prof["sources_sha256_prefix"]):
         return None
     kib = prof["fetch_kib"] * prof["fetch_scale"] + prof["write_kib"] * prof["write_scale"]
     return int(round(kib * 1024))
@@ -62,7 +77,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-reads", type=int, default=0, help="oracle reads (0 = 64 per thread)")
+    ap.add_argument("--cpu-reads", type=int, default=0, help="oracle reads (0 = 640 per thread, at most all)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after timing, run one device copy of this size (counter calibration)")
     ap.add_argument("--workload", default="chimera8_sa",
@@ -140,19 +155,20 @@ def main():
         torch.cuda.synchronize()
 
     mean_deg = inst.nnz / inst.n
-    spu = slots_per_update(mean_deg)
+    byte_parallel = P.x_bound <= 255  # the library's rule for its byte-parallel body
+    spu = slots_per_update(mean_deg, byte_parallel)
     achieved = updates * spu / (sa_ms / 1e3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_VALU_TSLOTS, 3),
                 "unit": "Tslot/s", "frac": round(achieved / PEAK_VALU_TSLOTS, 4),
                 "traffic": profiled_traffic_bytes(),
-                "kernel": "sa_kernel<1>", "kernel_ms": round(sa_ms, 4),
+                "kernel": "sa_kernel<0>" if byte_parallel else "sa_kernel<1>", "kernel_ms": round(sa_ms, 4),
                 "slots_per_update": round(spu, 3)}
 
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
         threads = max(1, min(16, os.cpu_count() or 1))
-        cpu_reads = args.cpu_reads or 64 * threads
+        cpu_reads = args.cpu_reads or min(reads, 640 * threads)
         t1 = time.perf_counter()
         oracle.sa_sample(inst, betas, seed=cfg["seed"], r_begin=0, r_end=cpu_reads, threads=threads)
         dt = time.perf_counter() - t1

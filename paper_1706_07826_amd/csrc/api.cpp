@@ -646,9 +646,8 @@ spv_status spv_pt_sample(spv_ctx *ctx, const spv_problem *P, const spv_pt_params
     }
     const size_t b_top = al((size_t)runs * std::max(Ls, 1) * 10 * std::max(n, 1));
     const size_t n_grp = sp.use ? (size_t)runs * sp.G : 0;
-    const size_t b_xs = al(n_grp * 4 * chains * std::max(n, 1)), b_xe = al(n_grp * 4 * chains * 8),
-                 b_fl = al(n_grp * 4);
-    st = ensure(c, c->pt, b_top + b_xs + b_xe + b_fl);
+    const size_t b_xw = al(n_grp * 4 * chains * (size_t)ptx_msg_words(std::max(n, 1)) * 4);
+    st = ensure(c, c->pt, b_top + b_xw);
     if (st) return st;
     st = ensure(c, c->image, image_words(std::max(n, 1), D) * 4);
     if (st) return st;
@@ -682,9 +681,7 @@ spv_status spv_pt_sample(spv_ctx *ctx, const spv_problem *P, const spv_pt_params
         X.out = out;
         unsigned char *sc = sbase;
         X.tops = reinterpret_cast<int8_t *>(sc);
-        X.xs = sc + b_top;
-        X.xe = reinterpret_cast<int64_t *>(sc + b_top + b_xs);
-        X.flags = reinterpret_cast<int *>(sc + b_top + b_xs + b_xe);
+        X.xw = reinterpret_cast<uint32_t *>(sc + b_top);
         X.G = sp.G;
         X.m = sp.m;
         X.threads = sp.threads;

@@ -237,9 +237,7 @@ struct PtxLaunch {
     const int32_t *snd;
     const spv_pt_out *out;
     int8_t *tops;             // [runs][Ls][10][n]
-    unsigned char *xs;        // [runs][G][2][2][chains][n]
-    int64_t *xe;              // [runs][G][2][2][chains]
-    int *flags;               // [runs][G]
+    uint32_t *xw;             // [runs][G][2][2][chains][ptx_msg_words(n)]
     int G, m, threads;
     bool big;
     unsigned spin_limit;
@@ -255,6 +253,7 @@ unsigned pt_spin_limit();
 spv_status pt_lds_footprint(Ctx *c, const spv_problem *P, int K, int runs, int chains, int icm_lo, int icm_hi,
                             int64_t *lds_total);
 size_t ptx_lds_bytes(int n, int D, int m, int chains, int row_len, int nw_icm, bool big);
+int ptx_msg_words(int n);
 hipError_t ptx_max_groups_resident(int nd, bool big, int threads, size_t lds, int *blocks_per_cu);
 hipError_t launch_ptx(const PtxLaunch &L, hipStream_t s);
 

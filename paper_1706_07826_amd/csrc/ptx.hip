@@ -12,9 +12,8 @@
 //      inside the group are decided from LDS energies and swapped byte-wise;
 //      on odd sweeps the two pairs that straddle a group boundary are decided
 //      by both neighbours from the energies each publishes (with the two edge
-//      configurations) in an L2-resident exchange slot, after a release /
-//      acquire flag handshake between the two workgroups; an accepted pair
-//      copies the partner's published configuration in,
+//      configurations) as sweep-tagged atomic words; an accepted pair copies
+//      the partner's published configuration in,
 //   3. Houdayer moves at the group's slots, one slot pair at a time with the
 //      whole workgroup (lock-free union-find over the disagreeing sites),
 //   4. the top-10 offers of the group's colder slots.
@@ -22,10 +21,13 @@
 // neighbour records, biases and orderings are read from the global image
 // (shared by every workgroup, L2-resident).
 //
-// Neighbour waits are bounded: a workgroup whose neighbour does not publish
-// within the spin limit stops and marks its lists with top_count = -1.  The
+// Waits for a neighbour's words are bounded: a workgroup whose neighbour does
+// not publish within the spin limit stops and marks its lists with
+// top_count = -1.  The
 // host only launches grids that fit on the device at once.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "device.hpp"
 #include "internal.hpp"
@@ -50,10 +52,8 @@ struct PtxArgs {
     long long *top_E;
     int32_t *top_count;
     int8_t *tops;          // [runs][Ls][10][n], position order
-    unsigned char *xs;     // [runs][G][side 2][buf 2][chains][n] edge configurations
-    long long *xe;         // [runs][G][side 2][buf 2][chains] edge energies
-    int *flags;            // [runs][G] local sweep count of the last publication
-    int n, D, C, K, chains, sweeps, row_len, icm_lo, icm_hi, nw_icm, G, m;
+    uint32_t *xw;          // [runs][G][side 2][buf 2][chains][xmsg] tagged boundary messages
+    int n, D, C, K, chains, sweeps, row_len, icm_lo, icm_hi, nw_icm, G, m, xmsg;
     uint32_t sweep_offset, k0, k1;
     unsigned spin_limit;
 };
@@ -119,9 +119,9 @@ __host__ __device__ inline size_t ptx_layout(int n, int D, int m, int chains, in
 // Slot pairs whose cluster moves run together (one forest and mask set each).
 constexpr int kIcmBatch = 4;
 
-__global__ void flags_zero_kernel(int *f, int count) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < count) f[i] = 0;
+__global__ void xw_zero_kernel(uint32_t *w, size_t count) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+        w[i] = 0u;
 }
 
 template <int ND, bool BIG>
@@ -130,7 +130,7 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
     __shared__ int cs[kMaxColours + 1];
     __shared__ int nacc;
     __shared__ int stop;
-    const int n = a.n, D = a.D, K = a.K, chains = a.chains, G = a.G, row_len = a.row_len;
+    const int n = a.n, D = a.D, K = a.K, chains = a.chains, G = a.G, row_len = a.row_len, xmsg = a.xmsg;
     PtxLds Lay;
     ptx_layout(n, D, a.m, chains, row_len, a.nw_icm, BIG, &Lay, smem);
     // LDS regions as plain locals (keeps the layout record out of scratch memory)
@@ -301,44 +301,41 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
         const int par = (int)(t & 1u);
         const bool edge = par == 1 && G > 1;
         const int buf = (int)((t >> 1) & 1u);
+        // Boundary messages: relaxed agent-scope atomic words, each 16 payload bits
+        // under a 16-bit sweep tag (never 0; the area is cleared before the launch).
+        // Per-word coherence of atomics makes a word with the expected tag carry
+        // that sweep's payload, so no fence (and no L2 write-back) is needed.
+        const uint32_t tag = ((((uint32_t)ls + 1u) & 0x7FFFu) | 0x8000u) << 16;
+        auto msg = [=](int grp, int side, int ch) __attribute__((always_inline)) -> uint32_t * {
+            return a.xw + ((((size_t)run * G + grp) * 2 + side) * 2 + buf) * chains * xmsg + (size_t)ch * xmsg;
+        };
+        auto recv = [=](const uint32_t *w) __attribute__((always_inline)) -> int {
+            unsigned it = 0;
+            for (;;) {
+                const uint32_t v = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if ((v & 0xFFFF0000u) == tag) return (int)(v & 0xFFFFu);
+                if (++it > a.spin_limit) return -1;
+                __builtin_amdgcn_s_sleep(1);
+            }
+        };
         if (edge) {
-            // publish the first and last slot of every chain (pre-exchange states)
+            // publish the first and last slot of every chain (pre-exchange states, energies)
             const bool lo_nb = g > 0, hi_nb = g < G - 1;
-            const size_t xbase = ((size_t)run * G + g) * 2;
-            for (int idx = tid; idx < 2 * chains * n; idx += T) {
-                const int sc = idx / n, p = idx - sc * n;
+            for (int idx = tid; idx < 2 * chains * xmsg; idx += T) {
+                const int sc = idx / xmsg, w = idx - sc * xmsg;
                 const int side = sc / chains, ch = sc - side * chains;
                 if ((side == 0 && !lo_nb) || (side == 1 && !hi_nb)) continue;
                 const int l = ch * mg + (side ? mg - 1 : 0);
-                a.xs[(((xbase + side) * 2 + buf) * chains + ch) * n + p] = *sbyte(l, p);
-            }
-            if (tid < 2 * chains) {
-                const int side = tid / chains, ch = tid - side * chains;
-                a.xe[((xbase + side) * 2 + buf) * chains + ch] = L_E[ch * mg + (side ? mg - 1 : 0)];
-            }
-            // The barrier completes every thread's stores at workgroup scope; one
-            // agent-scope release by thread 0 then publishes them with the flag.
-            __syncthreads();
-            if (tid == 0) {
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                __hip_atomic_store(&a.flags[run * G + g], ls + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                for (int d = 0; d < 2 && !stop; ++d) {
-                    const int nb = d == 0 ? g - 1 : g + 1;
-                    if (nb < 0 || nb >= G) continue;
-                    unsigned it = 0;
-                    while (__hip_atomic_load(&a.flags[run * G + nb], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) <
-                           ls + 1) {
-                        if (++it > a.spin_limit) {
-                            stop = 1;
-                            break;
-                        }
-                        __builtin_amdgcn_s_sleep(2);
-                    }
+                uint32_t pay;
+                if (w < 4) {
+                    pay = (uint32_t)(((unsigned long long)L_E[l] >> (16 * w)) & 0xFFFFu);
+                } else {
+                    const int p = 2 * (w - 4);
+                    pay = (uint32_t)*sbyte(l, p) | (p + 1 < n ? (uint32_t)*sbyte(l, p + 1) << 8 : 0u);
                 }
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                __hip_atomic_store(msg(g, side, ch) + w, tag | pay, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             __syncthreads();
-            if (stop) break;
         }
         {
             const int nin = (mg - par) / 2;            // pairs inside the group
@@ -357,30 +354,36 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                         L_E[la + 1] = x;
                         L_acc[atomicAdd(&nacc, 1)] = la;
                     }
-                } else if (e == nin && g > 0) {
-                    // pair (s0 - 1, s0): the lower neighbour's last slot against our first
-                    const int k = s0 - 1;
-                    const size_t xi = ((((size_t)run * G + (g - 1)) * 2 + 1) * 2 + buf) * chains + ch;
-                    const long long Ek = a.xe[xi], Ek1 = L_E[ch * mg];
-                    if (swap_test(Ek - Ek1, a.stab + (size_t)k * 7 * kDigitSize, a.snd[k], (uint32_t)k, t, cctr,
-                                  a.k0, a.k1)) {
-                        L_E[ch * mg] = Ek;
-                        L_cin[0 * chains + ch] = 1;
+                } else if ((e == nin && g > 0) || (e == nin + 1 && g < G - 1)) {
+                    // the pair straddling a group boundary: (s0 - 1, s0) against the lower
+                    // neighbour's last slot, (s0 + mg - 1, s0 + mg) against the upper one's first
+                    const int side = e - nin;
+                    const uint32_t *m = msg(side == 0 ? g - 1 : g + 1, side == 0 ? 1 : 0, ch);
+                    unsigned long long eu = 0;
+                    bool ok = true;
+                    for (int w = 0; w < 4; ++w) {
+                        const int v = recv(m + w);
+                        ok = ok && v >= 0;
+                        eu |= (unsigned long long)(v < 0 ? 0 : v) << (16 * w);
                     }
-                } else if (e == nin + 1 && g < G - 1) {
-                    // pair (s0 + mg - 1, s0 + mg): our last slot against the upper neighbour's first
-                    const int k = s0 + mg - 1;
-                    const size_t xi = ((((size_t)run * G + (g + 1)) * 2 + 0) * 2 + buf) * chains + ch;
-                    const long long Ek = L_E[ch * mg + mg - 1], Ek1 = a.xe[xi];
-                    if (swap_test(Ek - Ek1, a.stab + (size_t)k * 7 * kDigitSize, a.snd[k], (uint32_t)k, t, cctr,
-                                  a.k0, a.k1)) {
-                        L_E[ch * mg + mg - 1] = Ek1;
-                        L_cin[1 * chains + ch] = 1;
+                    if (!ok) {
+                        stop = 1;
+                    } else {
+                        const long long En = (long long)eu;
+                        const int lo = ch * mg + (side == 0 ? 0 : mg - 1);
+                        const int k = side == 0 ? s0 - 1 : s0 + mg - 1;
+                        const long long Dd = side == 0 ? En - L_E[lo] : L_E[lo] - En;
+                        if (swap_test(Dd, a.stab + (size_t)k * 7 * kDigitSize, a.snd[k], (uint32_t)k, t, cctr,
+                                      a.k0, a.k1)) {
+                            L_E[lo] = En;
+                            L_cin[side * chains + ch] = 1;
+                        }
                     }
                 }
             }
         }
         __syncthreads();
+        if (stop) break;
         {
             const int na = nacc;
             for (int idx = tid; idx < n * na; idx += T) {
@@ -391,17 +394,25 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                 *A = *B;
                 *B = x;
             }
-            if (edge)
-                for (int idx = tid; idx < 2 * chains * n; idx += T) {
-                    const int sc = idx / n, p = idx - sc * n;
+            if (edge) {
+                // an accepted straddling pair takes the neighbour's published configuration
+                const int nwd = xmsg - 4;
+                for (int idx = tid; idx < 2 * chains * nwd; idx += T) {
+                    const int sc = idx / nwd, w = idx - sc * nwd;
                     if (!L_cin[sc]) continue;
                     const int side = sc / chains, ch = sc - side * chains;
-                    // side 0 takes the lower neighbour's last slot, side 1 the upper neighbour's first
-                    const int nb = side == 0 ? g - 1 : g + 1, nside = side == 0 ? 1 : 0;
-                    const size_t xi = ((((size_t)run * G + nb) * 2 + nside) * 2 + buf) * chains + ch;
-                    *sbyte(ch * mg + (side ? mg - 1 : 0), p) = a.xs[xi * n + p];
+                    const int v = recv(msg(side == 0 ? g - 1 : g + 1, side == 0 ? 1 : 0, ch) + 4 + w);
+                    if (v < 0) {
+                        stop = 1;
+                        continue;
+                    }
+                    const int l = ch * mg + (side ? mg - 1 : 0), p = 2 * w;
+                    *sbyte(l, p) = (unsigned char)(v & 0xFF);
+                    if (p + 1 < n) *sbyte(l, p + 1) = (unsigned char)(v >> 8);
                 }
+            }
             __syncthreads();
+            if (stop) break;
         }
 
         // 3. Houdayer cluster moves between chains 0 and 1 at the group's slots, up to
@@ -719,6 +730,8 @@ void *ptx_fn(int nd, bool big) {
 
 }  // namespace
 
+int ptx_msg_words(int n) { return 4 + (n + 1) / 2; }
+
 size_t ptx_lds_bytes(int n, int D, int m, int chains, int row_len, int nw_icm, bool big) {
     return ptx_layout(n, D, m, chains, row_len, nw_icm, big, nullptr, nullptr);
 }
@@ -741,9 +754,8 @@ hipError_t launch_ptx(const PtxLaunch &P, hipStream_t s) {
     a.top_E = reinterpret_cast<long long *>(P.out->top_E);
     a.top_count = P.out->top_count;
     a.tops = P.tops;
-    a.xs = P.xs;
-    a.xe = reinterpret_cast<long long *>(P.xe);
-    a.flags = P.flags;
+    a.xw = P.xw;
+    a.xmsg = ptx_msg_words(P.n);
     a.n = P.n;
     a.D = P.D;
     a.C = P.C;
@@ -760,10 +772,13 @@ hipError_t launch_ptx(const PtxLaunch &P, hipStream_t s) {
     a.k0 = (uint32_t)P.seed;
     a.k1 = (uint32_t)(P.seed >> 32);
     a.spin_limit = P.spin_limit;
-    const int nflags = P.runs * P.G;
-    hipLaunchKernelGGL(flags_zero_kernel, dim3((nflags + 255) / 256), dim3(256), 0, s, P.flags, nflags);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (P.G > 1) {
+        const size_t words = (size_t)P.runs * P.G * 4 * P.chains * ptx_msg_words(P.n);
+        hipLaunchKernelGGL(xw_zero_kernel, dim3((unsigned)std::min<size_t>((words + 255) / 256, 4096)), dim3(256), 0,
+                           s, P.xw, words);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     const size_t lds = ptx_lds_bytes(P.n, P.D, P.m, P.chains, P.row_len, P.nw_icm, P.big);
     void *f = ptx_fn(P.nd, P.big);
     if (!f) return hipErrorInvalidValue;

@@ -83,7 +83,7 @@ void footprint(spv_server *s, const spv_request &r, int64_t *lds, int64_t *hbm) 
             L = 0;  // the launch itself reports the error
         R = (int64_t)r.runs * r.chains * (r.K / 2) * kTopK;
         H += (int64_t)r.K * row_len * 4 + (int64_t)r.K * 7 * kDigitSize * 4 + R * std::max(P.n, 1);
-        H += (int64_t)r.runs * (r.K / 4) * (4 * r.chains * (int64_t)std::max(P.n, 1) + 4 * r.chains * 8 + 4);
+        H += (int64_t)r.runs * (r.K / 4) * 4 * r.chains * (int64_t)ptx_msg_words(std::max(P.n, 1)) * 4;
         if (r.elite_frac > 0) H += R * (std::max(P.n, 1) + 8);  // assembled sample
     }
     if (r.elite_frac > 0 && R > 0) {

@@ -85,7 +85,14 @@ def main():
     ap.add_argument("--pt-runs", type=int, default=0, help="PT workloads: runs per step (0 = the config's)")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--serving-slots", type=int, default=8)
+    ap.add_argument("--hw-queues", type=int, default=-1,
+                    help="GPU_MAX_HW_QUEUES for this process (-1: 16 for serving, unchanged otherwise)")
     args = ap.parse_args()
+    hwq = args.hw_queues if args.hw_queues >= 0 else (16 if args.workload == "serving" else 0)
+    if hwq:
+        # HIP reads it when the runtime starts: one hardware queue per serving slot keeps
+        # a long request's kernel from blocking the slots that share its queue.
+        os.environ["GPU_MAX_HW_QUEUES"] = str(min(hwq, 32))
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (single-GPU build)",
               file=sys.stderr)
@@ -383,7 +390,7 @@ def bench_serving(args):
         "config": {"workload": f"serving: {nreq} requests (60 % SA N=512 1000x1000 + fix, 30 % PT N=1000 "
                                "32 betas x 4 runs x 1000 sweeps + fix, 10 % PT-ICM N=8000 40 betas x 2 chains "
                                "x 1000 sweeps + fix), burst then Poisson at 0.5/0.8/0.95 of saturation",
-                   "slots": args.serving_slots},
+                   "slots": args.serving_slots, "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES")},
         "saturation": sat, "poisson": loads,
     }
     print(json.dumps(out), flush=True)

@@ -147,8 +147,9 @@ spv_status spv_energy(spv_ctx *ctx, const spv_problem *P, const int8_t *spins, i
  *   info [8]        int64: n_free, nnz_free, offset, n_fixed, pivot (-1 when
  *                   the gauge was not applied), m, k_min, status (0, or a
  *                   negative spv_status detected on the device: SPV_EINVAL
- *                   for a sample entry other than +-1, SPV_ERANGE for an h'
- *                   outside int32, SPV_EINTERNAL for an unresolved gauge hash)
+ *                   for an entry other than +-1 in an elite row (the only
+ *                   rows read), SPV_ERANGE for an h' outside int32,
+ *                   SPV_EINTERNAL for an unresolved gauge hash)
  */
 typedef struct {
     uint8_t *fixed_mask;
@@ -214,6 +215,13 @@ spv_status spv_ispvar(spv_ctx *ctx, const spv_problem *P, const double *betas, i
  * states seen (Sec. III.D.1 sample formation).
  * Replica index r = (run * chains + chain) * K + slot (keyed by slot, so the
  * random stream follows the temperature).
+ * When K % 4 == 0 a run's ladder may be split over several workgroups that
+ * exchange their boundary slots every other sweep (the split is chosen from
+ * the run count and the LDS footprint; results do not depend on it).  The
+ * split launch is only made when all its workgroups fit on the device at
+ * once; should a workgroup still wait for a neighbour beyond a bounded spin,
+ * it stops and writes top_count = -1 for its lists (and spv_top_sample then
+ * reports SPV_EINVAL).  SPV_ECAPACITY when no layout fits.
  */
 typedef struct {
     int32_t K;
@@ -319,6 +327,10 @@ spv_status spv_batch_last_shape(const spv_ctx *ctx, int32_t *threads, int32_t *q
  * assembled by spv_top_sample, once the run has ended) into fix_out.
  * Every pointer in a request must stay valid until the request completes;
  * `betas` is copied at submission.
+ * Slots are HIP streams; HIP spreads streams over GPU_MAX_HW_QUEUES hardware
+ * queues (4 by default) and runs the kernels of one queue in order, so for
+ * full overlap set that variable to at least `slots` before the HIP runtime
+ * starts.
  */
 typedef enum { SPV_REQ_SA = 1, SPV_REQ_PT = 2 } spv_req_kind;
 

@@ -107,8 +107,9 @@ __global__ __launch_bounds__(256) void prep_nbr_kernel(const int32_t *__restrict
     hpos[p] = h[i];
 }
 
-// ND = number of threshold digits; ND = 0 selects the byte-parallel path.
-template <int ND>
+// ND = number of threshold digits; ND = 0 selects the byte-parallel path, whose
+// neighbour loop is straight-line code for a record count DK (0: any).
+template <int ND, int DK = 0>
 __global__ __launch_bounds__(1024) void sa_kernel(core::SaItem a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int cs[kMaxColours + 1];
@@ -117,7 +118,7 @@ __global__ __launch_bounds__(1024) void sa_kernel(core::SaItem a) {
         core::SwarLds L;
         core::swar_layout(a.n, a.D, a.row_len, a.qw, &L, smem);
         core::swar_load_instance(L, a, cs);
-        core::swar_run(L, a, cs);
+        core::swar_run<DK>(L, a, cs);
     } else {
         core::SaLds L;
         core::sa_layout(a.n, a.D, a.row_len, a.qw, &L, smem);
@@ -216,7 +217,14 @@ hipError_t launch_sa(const SaLaunch &L, hipStream_t s, size_t lds_limit) {
     const int grid = (quads + L.qw - 1) / L.qw;
     switch (sa_use_swar(L.nd, L.row_len) ? 0 : L.nd) {
         case 0:
-            hipLaunchKernelGGL(sa_kernel<0>, dim3(grid), dim3(L.threads), lds, s, a);
+            if (L.D == 6)
+                hipLaunchKernelGGL((sa_kernel<0, 6>), dim3(grid), dim3(L.threads), lds, s, a);
+            else if (L.D == 4)
+                hipLaunchKernelGGL((sa_kernel<0, 4>), dim3(grid), dim3(L.threads), lds, s, a);
+            else if (L.D == 8)
+                hipLaunchKernelGGL((sa_kernel<0, 8>), dim3(grid), dim3(L.threads), lds, s, a);
+            else
+                hipLaunchKernelGGL(sa_kernel<0>, dim3(grid), dim3(L.threads), lds, s, a);
             break;
         case 1:
             hipLaunchKernelGGL(sa_kernel<1>, dim3(grid), dim3(L.threads), lds, s, a);

@@ -81,28 +81,56 @@ __device__ inline void swar_load_instance(const SwarLds &L, const SaItem &a, int
     __syncthreads();
 }
 
+// Neighbour records are read this many at a time (loads issued together).
+constexpr int kSwarBatch = 8;
+
 // Per byte, the sum of |J_k| over the neighbours agreeing with sign(J_k).
+// DK > 0: the record count is DK exactly (straight-line code); DK = 0: D at run time.
+template <int DK>
 __device__ __forceinline__ uint32_t swar_agree(const uint2 *__restrict__ rec, const uint32_t *__restrict__ S,
                                                int D, int q, int n) {
+    if constexpr (DK > 0) {
+        uint2 r[DK];
+#pragma unroll
+        for (int u = 0; u < DK; ++u) r[u] = rec[(uint32_t)u * (uint32_t)n];
+        uint32_t w[DK];
+#pragma unroll
+        for (int u = 0; u < DK; ++u) w[u] = S[r[u].x + q];
+        uint32_t P = 0;
+#pragma unroll
+        for (int u = 0; u < DK; ++u) P += w[u] & r[u].y;
+        return P;
+    }
+    // 32-bit indices: LDS addresses are 32-bit, wider index arithmetic only costs VALU
     uint32_t P = 0;
-    for (int k = 0; k < D; ++k) {
-        const uint2 r = rec[(size_t)k * n];
-        P += S[r.x + q] & r.y;
+    for (int k0 = 0; k0 < D; k0 += kSwarBatch) {
+        uint2 r[kSwarBatch];
+#pragma unroll
+        for (int u = 0; u < kSwarBatch; ++u)
+            if (k0 + u < D) r[u] = rec[(uint32_t)(k0 + u) * (uint32_t)n];
+        uint32_t w[kSwarBatch];
+#pragma unroll
+        for (int u = 0; u < kSwarBatch; ++u)
+            if (k0 + u < D) w[u] = S[r[u].x + q];
+#pragma unroll
+        for (int u = 0; u < kSwarBatch; ++u)
+            if (k0 + u < D) P += w[u] & r[u].y;
     }
     return P;
 }
 
-__device__ __forceinline__ void swar_store(uint32_t *S, size_t idx, size_t inv, uint32_t w) {
+__device__ __forceinline__ void swar_store(uint32_t *S, uint32_t idx, uint32_t inv, uint32_t w) {
     S[idx] = w;
     S[idx + inv] = ~w;
 }
 
+template <int DK>
 __device__ void swar_run(const SwarLds &L, const SaItem &a, const int *cs) {
     const int n = a.n, D = a.D, qw = a.qw, T = blockDim.x, tid = threadIdx.x;
     const int q0 = a.q0;
     const int q = tid % qw, slot = tid / qw, nslots = T / qw;
     const bool active = slot < nslots;
-    const size_t inv = (size_t)n * qw;
+    const uint32_t inv = (uint32_t)n * (uint32_t)qw;
     for (int k = tid; k < a.row_len; k += T) L.tab[k] = a.tables[k];
     for (int k = tid; k < 4 * qw; k += T) L.E2[k] = 0ull;
     if (a.init == nullptr) {
@@ -112,7 +140,7 @@ __device__ void swar_run(const SwarLds &L, const SaItem &a, const int *cs) {
             uint32_t word = 0;
 #pragma unroll
             for (int b = 0; b < 4; ++b) word |= ((w.w[b] >> 31) ? 0xFFu : 0x00u) << (8 * b);
-            swar_store(L.S, (size_t)p * qw + q, inv, word);
+            swar_store(L.S, (uint32_t)p * (uint32_t)qw + (uint32_t)q, inv, word);
         }
     } else {
         const int32_t *pos_of = a.image + kImgHeader + n;
@@ -139,9 +167,9 @@ __device__ void swar_run(const SwarLds &L, const SaItem &a, const int *cs) {
         for (int c = 0; c < a.C; ++c) {
             const int pe = cs[c + 1];
             for (int p = cs[c] + slot; active && p < pe; p += nslots) {
-                const size_t at = (size_t)p * qw + q;
+                const uint32_t at = (uint32_t)p * (uint32_t)qw + (uint32_t)q;
                 const uint32_t self = L.S[at];
-                const uint32_t P = swar_agree(L.rec + p, L.S, D, q, n);
+                const uint32_t P = swar_agree<DK>(L.rec + p, L.S, D, q, n);
                 const int32_t cp = L.cpos[p];
                 int32_t x[4];
 #pragma unroll
@@ -151,15 +179,18 @@ __device__ void swar_run(const SwarLds &L, const SaItem &a, const int *cs) {
                     x[b] = (f ^ m) - m;
                 }
                 const int32_t xm = max(max(x[0], x[1]), max(x[2], x[3]));
-                uint32_t mask = 0;
+                uint32_t mask = 0xFFFFFFFFu;
                 if (xm > 0) {
                     const dev::Words4 r =
                         dev::philox((uint32_t)L.ord[p], t, (uint32_t)(q0 + q), 2u << 24, a.k0, a.k1);
+                    // branch-free: the row is read at max(x, 0), a valid index, for every byte
+                    uint32_t th[4];
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) th[b] = tcur[max(x[b], 0)];
+                    mask = 0;
 #pragma unroll
                     for (int b = 0; b < 4; ++b)
-                        if (x[b] <= 0 || r.w[b] < tcur[max(x[b], 0)]) mask |= 0xFFu << (8 * b);
-                } else {
-                    mask = 0xFFFFFFFFu;
+                        mask |= (uint32_t)((x[b] <= 0) | (r.w[b] < th[b])) * (0xFFu << (8 * b));
                 }
                 if (mask) swar_store(L.S, at, inv, self ^ mask);
             }
@@ -171,7 +202,7 @@ __device__ void swar_run(const SwarLds &L, const SaItem &a, const int *cs) {
         long long e2[4] = {0, 0, 0, 0};
         for (int p = slot; active && p < n; p += nslots) {
             const uint32_t self = L.S[(size_t)p * qw + q];
-            const uint32_t P = swar_agree(L.rec + p, L.S, D, q, n);
+            const uint32_t P = swar_agree<DK>(L.rec + p, L.S, D, q, n);
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const long long f = (long long)L.cpos[p] + 2 * (long long)((P >> (8 * b)) & 0xffu);

@@ -118,7 +118,8 @@ struct BatchArgs {
     uint32_t sweep_offset;
 };
 
-template <int ND>
+// ND = 0: byte-parallel body; DK > 0: every image has exactly DK records per site.
+template <int ND, int DK = 0>
 __global__ __launch_bounds__(1024) void batch_sa_kernel(BatchArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int cs[kMaxColours + 1];
@@ -162,7 +163,7 @@ __global__ __launch_bounds__(1024) void batch_sa_kernel(BatchArgs a) {
                 core::swar_load_instance(L, it, cs);
                 loaded = b;
             }
-            core::swar_run<0>(L, it, cs);
+            core::swar_run<DK>(L, it, cs);
         } else {
             if (b != loaded) {
                 core::sa_load_instance(L, it, cs);
@@ -210,7 +211,14 @@ hipError_t launch_batch_sa(const BatchLaunch &L, hipStream_t s) {
     const size_t lds = batch_lds_bytes(L.n_max, L.D_max, L.row_len, L.qw, L.nd);
     switch (sa_use_swar(L.nd, L.row_len) ? 0 : L.nd) {
         case 0:
-            hipLaunchKernelGGL(batch_sa_kernel<0>, dim3(L.grid), dim3(L.threads), lds, s, a);
+            if (L.dk == 6)
+                hipLaunchKernelGGL((batch_sa_kernel<0, 6>), dim3(L.grid), dim3(L.threads), lds, s, a);
+            else if (L.dk == 4)
+                hipLaunchKernelGGL((batch_sa_kernel<0, 4>), dim3(L.grid), dim3(L.threads), lds, s, a);
+            else if (L.dk == 8)
+                hipLaunchKernelGGL((batch_sa_kernel<0, 8>), dim3(L.grid), dim3(L.threads), lds, s, a);
+            else
+                hipLaunchKernelGGL(batch_sa_kernel<0>, dim3(L.grid), dim3(L.threads), lds, s, a);
             break;
         case 1:
             hipLaunchKernelGGL(batch_sa_kernel<1>, dim3(L.grid), dim3(L.threads), lds, s, a);

@@ -35,7 +35,7 @@ struct Shape {
 };
 
 struct Plan {
-    int B = 0, n_max = 0, D_max = 1, nd = 1, row_len = 1, scale = 0;
+    int B = 0, n_max = 0, D_max = 1, nd = 1, row_len = 1, scale = 0, dk = 0;
     long long image_words = 0, total_quads = 0;
     std::vector<BatchInst> insts;
 };
@@ -111,6 +111,7 @@ spv_status enqueue(Ctx *c, const Plan &pl, const Layout &ly, size_t n_items, con
     L.qw = sh.qw;
     L.n_max = pl.n_max;
     L.D_max = pl.D_max;
+    L.dk = pl.dk;
     L.threads = sh.threads;
     L.grid = (int)std::max<size_t>(1, std::min<size_t>(n_items, (size_t)c->num_cus * sh.wgs_per_cu));
     L.sweep_offset = sweep_offset;
@@ -206,6 +207,18 @@ spv_status spv_sample_batch(spv_ctx *ctx, int32_t B, const spv_problem *problems
     pl.nd = digits_for(x_max);
     if (pl.nd > 3) return set_err(c, SPV_ERANGE, "x_bound=%d needs %d digits (max 3)", x_max, pl.nd);
     pl.row_len = table_row_len(x_max);
+    // The byte-parallel body has straight-line variants for 4, 6 and 8 records per
+    // site: pad every image of the batch to the largest degree (zero-coupling records).
+    if (sa_use_swar(pl.nd, pl.row_len) && (pl.D_max == 4 || pl.D_max == 6 || pl.D_max == 8)) {
+        pl.dk = pl.D_max;
+        pl.image_words = 0;
+        for (int b = 0; b < B; ++b) {
+            BatchInst &in = pl.insts[b];
+            in.D = pl.D_max;
+            in.image_off = pl.image_words;
+            pl.image_words += ((long long)image_words(in.n, in.D) + 3) & ~3ll;
+        }
+    }
     if (sweeps > 0 && (st = upload_tables(c, c->tables, betas, sweeps, 2, pl.scale, pl.nd, pl.row_len, stream)))
         return st;
     if (!c->batch_done && hipEventCreateWithFlags(&c->batch_done, hipEventDisableTiming) != hipSuccess)

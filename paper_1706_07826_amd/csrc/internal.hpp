@@ -195,6 +195,7 @@ struct BatchLaunch {
     const int32_t *images;
     const uint32_t *tables;
     int row_len, nd, sweeps, qw, n_max, D_max, grid, threads;
+    int dk;  // every image padded to this many records per site (0: per-instance degree)
     uint32_t sweep_offset;
 };
 // Small instances get up to this many quads per work item (energy accumulators are sized for it).

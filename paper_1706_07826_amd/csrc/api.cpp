@@ -209,7 +209,7 @@ spv_status plan_pt_split(Ctx *c, int n, int D, int K, int runs, int chains, int 
                 const size_t lds = ptx_lds_bytes(n, D, m, chains, row_len, nw, big != 0) + 256;
                 if (lds > c->lds_max) continue;
                 int bpc = 0;
-                hipError_t e = ptx_max_groups_resident(nd, big != 0, threads, lds, &bpc);
+                hipError_t e = ptx_max_groups_resident(nd, big != 0, D, threads, lds, &bpc);
                 if (e != hipSuccess) return hip_check(c, e, "occupancy query");
                 if ((long long)bpc * c->num_cus < (long long)runs * Gr)
                     return set_err(c, SPV_ECAPACITY, "split PT grid %d x %d exceeds %d resident workgroups", runs,

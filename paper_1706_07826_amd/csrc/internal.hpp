@@ -255,7 +255,7 @@ spv_status pt_lds_footprint(Ctx *c, const spv_problem *P, int K, int runs, int c
                             int64_t *lds_total);
 size_t ptx_lds_bytes(int n, int D, int m, int chains, int row_len, int nw_icm, bool big);
 int ptx_msg_words(int n);
-hipError_t ptx_max_groups_resident(int nd, bool big, int threads, size_t lds, int *blocks_per_cu);
+hipError_t ptx_max_groups_resident(int nd, bool big, int D, int threads, size_t lds, int *blocks_per_cu);
 hipError_t launch_ptx(const PtxLaunch &L, hipStream_t s);
 
 }  // namespace spv

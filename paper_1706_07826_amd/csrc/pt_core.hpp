@@ -22,21 +22,28 @@ __device__ __forceinline__ long long wave_sum(long long v) {
     return v;
 }
 
-// Replica-exchange decision (digit test of D with the tables of dbeta_k).
+// Replica-exchange decision (digit test of D with the tables of dbeta_k).  The
+// thresholds of every nonzero digit are fetched together, then compared.
 __device__ inline bool swap_test(long long D, const uint32_t *__restrict__ T, int nd, uint32_t k, uint32_t t,
-                          uint32_t c, uint32_t k0, uint32_t k1) {
+                                 uint32_t c, uint32_t k0, uint32_t k1) {
     if (D <= 0) return true;
     if (nd < 7 && (D >> (kDigitBits * nd)) != 0) return false;
+    uint32_t d[7], th[7];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+        d[j] = j < nd ? (uint32_t)((D >> (kDigitBits * j)) & (kDigitSize - 1)) : 0u;
+        th[j] = d[j] ? T[j * kDigitSize + d[j]] : 0u;
+    }
     dev::Words4 w0 = dev::philox(k, t, c, 3u << 24, k0, k1);
     dev::Words4 w1 = w0;
     if (nd > 4) w1 = dev::philox(k, t, c, (3u << 24) | 1u, k0, k1);
-    for (int j = 0; j < nd; ++j) {
-        const uint32_t d = (uint32_t)((D >> (kDigitBits * j)) & (kDigitSize - 1));
-        if (d == 0) continue;
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
         const uint32_t w = j < 4 ? w0.w[j] : w1.w[j - 4];
-        if (!(w < T[j * kDigitSize + d])) return false;
+        if (d[j]) ok = ok && (w < th[j]);
     }
-    return true;
+    return ok;
 }
 
 // Neighbour records are fetched this many at a time, so their loads (LDS or
@@ -45,11 +52,26 @@ constexpr int kRecBatch = 8;
 
 // Local fields f[b] = h + sum_k J_k s_k[b] of the 4 replicas in word q of
 // position p (spins S[pos][nq], records rec(k, p) = pos << 16 | uint16 J).
-template <typename Rec>
+// DK > 0: exactly DK records per site (straight-line code); DK = 0: D at run time.
+template <int DK = 0, typename Rec>
 __device__ __forceinline__ void quad_fields(Rec rec, int D, int p, const uint32_t *__restrict__ S, int nq, int q,
                                             int32_t h, int32_t f[4]) {
 #pragma unroll
     for (int b = 0; b < 4; ++b) f[b] = h;
+    if constexpr (DK > 0) {
+        uint32_t rr[DK], w[DK];
+#pragma unroll
+        for (int u = 0; u < DK; ++u) rr[u] = rec(u, p);
+#pragma unroll
+        for (int u = 0; u < DK; ++u) w[u] = S[(rr[u] >> 16) * (uint32_t)nq + (uint32_t)q];
+#pragma unroll
+        for (int u = 0; u < DK; ++u) {
+            const int32_t Jv = (int32_t)(int16_t)(rr[u] & 0xffffu);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) f[b] += Jv * dev::spin_of(w[u], b);
+        }
+        return;
+    }
     for (int k0 = 0; k0 < D; k0 += kRecBatch) {
         uint32_t rr[kRecBatch];
 #pragma unroll

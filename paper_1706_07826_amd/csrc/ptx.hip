@@ -118,13 +118,17 @@ __host__ __device__ inline size_t ptx_layout(int n, int D, int m, int chains, in
 
 // Slot pairs whose cluster moves run together (one forest and mask set each).
 constexpr int kIcmBatch = 4;
+// Boundary-message words a thread loads at once when copying a configuration in.
+constexpr int kCopyBatch = 4;
 
 __global__ void xw_zero_kernel(uint32_t *w, size_t count) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
         w[i] = 0u;
 }
 
-template <int ND, bool BIG>
+// ND threshold digits; BIG: instance read from the global image; DK: records per
+// site fixed at compile time (0: D at run time).
+template <int ND, bool BIG, int DK>
 __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int cs[kMaxColours + 1];
@@ -221,7 +225,7 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
             const uint32_t self = L_S[(size_t)p * nq + q];
             const int32_t hp = HPOS(p);
             int32_t f[4];
-            ptc::quad_fields(NBR, D, p, L_S, nq, q, hp, f);
+            ptc::quad_fields<DK>(NBR, D, p, L_S, nq, q, hp, f);
 #pragma unroll
             for (int b = 0; b < 4; ++b) e2[b] += (long long)dev::spin_of(self, b) * ((long long)hp + f[b]);
         }
@@ -243,7 +247,7 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
             for (int p = cs[c] + pt; active && p < pe; p += nstr) {
                 const uint32_t self = L_S[(size_t)p * nq + q];
                 int32_t f[4];
-                ptc::quad_fields(NBR, D, p, L_S, nq, q, HPOS(p), f);
+                ptc::quad_fields<DK>(NBR, D, p, L_S, nq, q, HPOS(p), f);
                 int32_t x[4];
                 bool up[4], pass[4];
 #pragma unroll
@@ -396,19 +400,39 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
             }
             if (edge) {
                 // an accepted straddling pair takes the neighbour's published configuration
-                const int nwd = xmsg - 4;
-                for (int idx = tid; idx < 2 * chains * nwd; idx += T) {
-                    const int sc = idx / nwd, w = idx - sc * nwd;
-                    if (!L_cin[sc]) continue;
-                    const int side = sc / chains, ch = sc - side * chains;
-                    const int v = recv(msg(side == 0 ? g - 1 : g + 1, side == 0 ? 1 : 0, ch) + 4 + w);
-                    if (v < 0) {
-                        stop = 1;
-                        continue;
+                // (kCopyBatch words per thread loaded together; a word whose tag is not
+                // yet the expected one is waited for)
+                const int nwd = xmsg - 4, total = 2 * chains * nwd;
+                for (int i0 = tid; i0 < total; i0 += kCopyBatch * T) {
+                    const uint32_t *src[kCopyBatch];
+                    uint32_t v[kCopyBatch];
+#pragma unroll
+                    for (int u = 0; u < kCopyBatch; ++u) {
+                        const int idx = i0 + u * T;
+                        src[u] = nullptr;
+                        if (idx < total) {
+                            const int sc = idx / nwd, w = idx - sc * nwd;
+                            if (L_cin[sc]) {
+                                const int side = sc / chains, ch = sc - side * chains;
+                                src[u] = msg(side == 0 ? g - 1 : g + 1, side == 0 ? 1 : 0, ch) + 4 + w;
+                            }
+                        }
+                        v[u] = src[u] ? __hip_atomic_load(src[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
                     }
-                    const int l = ch * mg + (side ? mg - 1 : 0), p = 2 * w;
-                    *sbyte(l, p) = (unsigned char)(v & 0xFF);
-                    if (p + 1 < n) *sbyte(l, p + 1) = (unsigned char)(v >> 8);
+#pragma unroll
+                    for (int u = 0; u < kCopyBatch; ++u) {
+                        if (!src[u]) continue;
+                        int pay = (v[u] & 0xFFFF0000u) == tag ? (int)(v[u] & 0xFFFFu) : recv(src[u]);
+                        if (pay < 0) {
+                            stop = 1;
+                            continue;
+                        }
+                        const int idx = i0 + u * T, sc = idx / nwd, w = idx - sc * nwd;
+                        const int side = sc / chains, ch = sc - side * chains;
+                        const int l = ch * mg + (side ? mg - 1 : 0), p = 2 * w;
+                        *sbyte(l, p) = (unsigned char)(pay & 0xFF);
+                        if (p + 1 < n) *sbyte(l, p + 1) = (unsigned char)(pay >> 8);
+                    }
                 }
             }
             __syncthreads();
@@ -711,18 +735,19 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
 }
 
 template <int ND, bool BIG>
-void *ptx_entry() {
-    return reinterpret_cast<void *>(ptx_kernel<ND, BIG>);
+void *ptx_entry(int D) {
+    if (D == 6) return reinterpret_cast<void *>(ptx_kernel<ND, BIG, 6>);
+    return reinterpret_cast<void *>(ptx_kernel<ND, BIG, 0>);
 }
 
-void *ptx_fn(int nd, bool big) {
+void *ptx_fn(int nd, bool big, int D) {
     switch (nd) {
         case 1:
-            return big ? ptx_entry<1, true>() : ptx_entry<1, false>();
+            return big ? ptx_entry<1, true>(D) : ptx_entry<1, false>(D);
         case 2:
-            return big ? ptx_entry<2, true>() : ptx_entry<2, false>();
+            return big ? ptx_entry<2, true>(D) : ptx_entry<2, false>(D);
         case 3:
-            return big ? ptx_entry<3, true>() : ptx_entry<3, false>();
+            return big ? ptx_entry<3, true>(D) : ptx_entry<3, false>(D);
         default:
             return nullptr;
     }
@@ -736,8 +761,8 @@ size_t ptx_lds_bytes(int n, int D, int m, int chains, int row_len, int nw_icm, b
     return ptx_layout(n, D, m, chains, row_len, nw_icm, big, nullptr, nullptr);
 }
 
-hipError_t ptx_max_groups_resident(int nd, bool big, int threads, size_t lds, int *blocks_per_cu) {
-    void *f = ptx_fn(nd, big);
+hipError_t ptx_max_groups_resident(int nd, bool big, int D, int threads, size_t lds, int *blocks_per_cu) {
+    void *f = ptx_fn(nd, big, D);
     if (!f) return hipErrorInvalidValue;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, threads, lds);
 }
@@ -780,7 +805,7 @@ hipError_t launch_ptx(const PtxLaunch &P, hipStream_t s) {
         if (e != hipSuccess) return e;
     }
     const size_t lds = ptx_lds_bytes(P.n, P.D, P.m, P.chains, P.row_len, P.nw_icm, P.big);
-    void *f = ptx_fn(P.nd, P.big);
+    void *f = ptx_fn(P.nd, P.big, P.D);
     if (!f) return hipErrorInvalidValue;
     void *args[] = {&a};
     return hipLaunchKernel(f, dim3(P.runs * P.G), dim3(P.threads), args, lds, s);

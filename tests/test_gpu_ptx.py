@@ -88,3 +88,27 @@ def test_cubic20_pticm_config_shape(spv, ctx):
     _check(got, want)
     assert np.array_equal(got["final_E"].cpu().numpy().reshape(-1),
                           oracle.energy(inst, got["final_spins"].cpu().numpy().reshape(-1, inst.n)))
+
+
+def test_bounded_neighbour_wait_reports_and_recovers(spv, ctx, monkeypatch):
+    """Failure handling forced from the host: with a spin limit of 0 a workgroup
+    whose neighbour has not yet published gives up at once instead of waiting.
+    The call must return, every list of a workgroup that stopped reads
+    top_count = -1 (and sample assembly refuses it), the others stay valid, and
+    the next call with the normal limit is exact again."""
+    inst = si.cubic_lattice(6, "gauss", seed=41, scale_log2=10)
+    P = spv.Problem.from_instance(inst)
+    betas = si.geometric_betas(0.2, 5.0, 16)
+    monkeypatch.setenv("SPVAR_PT_SPLIT", "1")
+    monkeypatch.setenv("SPVAR_PT_GROUPS", "4")
+    monkeypatch.setenv("SPVAR_PT_SPIN", "0")
+    got = spv.spv_pt_sample(ctx, P, betas, 3, 2, 200, seed=5, icm=(0, 16))
+    tc = got["top_count"].cpu().numpy()
+    assert set(np.unique(tc)).issubset(set(range(-1, 11)))
+    if (tc < 0).any():
+        with pytest.raises(spv.SpvError, match="EINVAL"):
+            spv.spv_top_sample(ctx, got)
+    monkeypatch.setenv("SPVAR_PT_SPIN", str(1 << 24))
+    got = spv.spv_pt_sample(ctx, P, betas, 3, 2, 200, seed=5, icm=(0, 16))
+    want = oracle.pt_sample(inst, betas, 3, 2, 200, seed=5, icm=(0, 16), threads=3)
+    _check(got, want)

@@ -150,6 +150,36 @@ def test_budget_admits_one_at_a_time_in_fifo_order(spv, ctx):
         assert inflight <= budget
 
 
+def test_mixed_stream_with_split_tempering(spv, ctx):
+    """Requests on the split tempering paths (N=1000 with the instance in LDS, N=8000
+    PT-ICM with it in global memory) in flight together with SA requests: each
+    result equals the same calls made alone."""
+    from spvar_inputs import configs as cf
+    c3, c5 = cf.CUBIC10_PT, cf.CUBIC20_PTICM
+    i3, i5 = cf.instance(c3), cf.instance(c5)
+    b3, b5 = cf.betas(c3), cf.betas(c5)
+    reqs = [
+        dict(kind="pt", inst=i5, betas=b5, runs=1, chains=2, sweeps=30, seed=11, icm=(0, b5.size),
+             fix=(0.2, 1.0, 2)),
+        dict(kind="sa", inst=si.chimera(4, seed=12), betas=si.linear_betas(0.1, 3.0, 200), reads=400, seed=13,
+             fix=(0.1, 0.95, 0)),
+        dict(kind="pt", inst=i3, betas=b3, runs=4, chains=1, sweeps=120, seed=14, icm=None, fix=(0.2, 1.0, 2)),
+        dict(kind="sa", inst=si.chimera(3, seed=15), betas=si.linear_betas(0.1, 3.0, 300), reads=256, seed=16,
+             fix=None),
+        dict(kind="pt", inst=i3, betas=b3, runs=2, chains=1, sweeps=90, seed=17, icm=None, fix=None),
+    ]
+    Ps = [spv.Problem.from_instance(r["inst"]) for r in reqs]
+    print(f"[serving] split tempering mix, {len(reqs)} requests", flush=True)
+    alone = [_alone(spv, ctx, r, P) for r, P in zip(reqs, Ps)]
+    srv = spv.Server(ctx, slots=4)
+    tickets = [_submit(srv, r, P) for r, P in zip(reqs, Ps)]
+    results = [srv.wait(t) for t in tickets]
+    srv.close()
+    for r, (res, keep), want in zip(reqs, results, alone):
+        assert res.status == 0
+        _check_against_alone(r, keep, want)
+
+
 def test_top_sample_matches_oracle_formation(spv, ctx):
     inst = si.cubic_lattice(4, "gauss", seed=31, scale_log2=10)
     P = spv.Problem.from_instance(inst)

@@ -168,7 +168,8 @@ def main():
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_VALU_TSLOTS, 3),
                 "unit": "Tslot/s", "frac": round(achieved / PEAK_VALU_TSLOTS, 4),
                 "traffic": profiled_traffic_bytes(),
-                "kernel": "sa_kernel<0>" if byte_parallel else "sa_kernel<1>", "kernel_ms": round(sa_ms, 4),
+                "kernel": (f"sa_kernel<0, {P.max_degree}>" if P.max_degree in (4, 6, 8) else "sa_kernel<0>")
+                if byte_parallel else "sa_kernel<1>", "kernel_ms": round(sa_ms, 4),
                 "slots_per_update": round(spu, 3)}
 
     cpu = None

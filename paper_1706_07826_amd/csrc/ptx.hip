@@ -76,7 +76,12 @@ struct PtxLds {
     uint16_t *parent;          // [pairs][n rounded to even] union-find forests over positions
     unsigned long long *dmask; // [pairs][ceil(n / 64)] disagreement masks in variable order
     int32_t *misc;             // [4] broadcast scalars
+    uint32_t *ubuf;            // [16 waves][kJoinBuf] pending joins: site | neighbour << 16
+    unsigned char *ubj;        // [16 waves][kJoinBuf] their slot pair
 };
+
+// Pending-join buffer per wavefront (64 appended at most on top of < 64 pending).
+constexpr int kJoinBuf = 128;
 
 __host__ __device__ inline size_t ptx_layout(int n, int D, int m, int chains, int row_len, int nw_icm, bool big,
                                              PtxLds *L, unsigned char *base) {
@@ -93,7 +98,8 @@ __host__ __device__ inline size_t ptx_layout(int n, int D, int m, int chains, in
                  o_E = take((size_t)nl * 8), o_LE = take((size_t)nl * 80), o_Lw = take((size_t)nl * 40),
                  o_Lc = take((size_t)nl * 4), o_Lo = take((size_t)nl * 40), o_acc = take((size_t)nl * 4),
                  o_cin = take((size_t)2 * chains * 4), o_par = take((size_t)nw_icm * ((n + 1) & ~1) * 2),
-                 o_dm = take((size_t)nw_icm * vstride * 4), o_misc = take(16);
+                 o_dm = take((size_t)nw_icm * vstride * 4), o_misc = take(16),
+                 o_ub = take(nw_icm ? (size_t)16 * kJoinBuf * 4 : 0), o_uj = take(nw_icm ? (size_t)16 * kJoinBuf : 0);
     if (L) {
         L->nbr = reinterpret_cast<uint32_t *>(base + o_nbr);
         L->hpos = reinterpret_cast<int32_t *>(base + o_h);
@@ -112,6 +118,8 @@ __host__ __device__ inline size_t ptx_layout(int n, int D, int m, int chains, in
         L->parent = reinterpret_cast<uint16_t *>(base + o_par);
         L->dmask = reinterpret_cast<unsigned long long *>(base + o_dm);
         L->misc = reinterpret_cast<int32_t *>(base + o_misc);
+        L->ubuf = reinterpret_cast<uint32_t *>(base + o_ub);
+        L->ubj = base + o_uj;
     }
     return o;
 }
@@ -155,6 +163,8 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
     auto *const L_parent = Lay.parent;
     auto *const L_dmask = Lay.dmask;
     auto *const L_misc = Lay.misc;
+    auto *const L_ubuf = Lay.ubuf;
+    auto *const L_ubj = Lay.ubj;
     const int tid = threadIdx.x, T = blockDim.x, lane = dev::lane_id(), wid = tid >> 6, nw = T >> 6;
     const int run = blockIdx.x / G, g = blockIdx.x - run * G;
     const int s0 = g * a.m, mg = min(a.m, K - s0), qpc = mg >> 2, nq = chains * qpc, nl = chains * mg;
@@ -521,35 +531,57 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
             // The masks are consumed: their words now collect cluster membership.
             uint32_t *const memb = reinterpret_cast<uint32_t *>(L_dmask);
             for (int wd = tid; wd < nb * vstr; wd += T) memb[wd] = 0u;
-            // join the endpoints of every J != 0 edge between disagreeing sites (two
-            // positions per thread and step, their records fetched together)
-            for (int p0 = tid; p0 < n; p0 += 2 * T) {
-                unsigned dp[2];
-#pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    dp[c] = 0;
+            // join the endpoints of every J != 0 edge between disagreeing sites.  Each
+            // wavefront scans 64 sites at a time and appends the qualifying
+            // (pair, site, neighbour) joins to its own LDS buffer; whenever 64 are
+            // pending, every lane performs one (full lanes instead of the ~1 in 4 that
+            // a per-site loop would keep busy).  Join order does not change the sets.
+            {
+                uint32_t *const wb = L_ubuf + wid * kJoinBuf;
+                unsigned char *const wj = L_ubj + wid * kJoinBuf;
+                int cnt = 0;
+                auto run_joins = [&](int m) __attribute__((always_inline)) {
+                    __builtin_amdgcn_wave_barrier();
+                    if (lane < m) {
+                        const uint32_t it = wb[cnt - m + lane];
+                        ptc::uf_union(L_parent + (size_t)wj[cnt - m + lane] * n16, it & 0xFFFFu, it >> 16);
+                    }
+                    cnt -= m;
+                    __builtin_amdgcn_wave_barrier();
+                };
+                for (int p0 = wid * 64; p0 < n; p0 += nw * 64) {
+                    const int p = p0 + lane;
+                    unsigned dp = 0;
 #pragma unroll
                     for (int j = 0; j < kIcmBatch; ++j)
-                        if (j < nb && p0 + c * T < n && dis(j, p0 + c * T)) dp[c] |= 1u << j;
-                }
-                for (int k0 = 0; k0 < D; k0 += ptc::kRecBatch) {
-                    uint32_t rr[2][ptc::kRecBatch];
-#pragma unroll
-                    for (int c = 0; c < 2; ++c)
+                        if (j < nb && p < n && dis(j, p)) dp |= 1u << j;
+                    for (int k0 = 0; k0 < D; k0 += ptc::kRecBatch) {
+                        uint32_t rr[ptc::kRecBatch];
 #pragma unroll
                         for (int uu = 0; uu < ptc::kRecBatch; ++uu)
-                            rr[c][uu] = (dp[c] && k0 + uu < D) ? NBR(k0 + uu, p0 + c * T) : 0u;
-#pragma unroll
-                    for (int c = 0; c < 2; ++c)
+                            rr[uu] = (dp && k0 + uu < D) ? NBR(k0 + uu, p) : 0u;
 #pragma unroll
                         for (int uu = 0; uu < ptc::kRecBatch; ++uu) {
-                            const int p = p0 + c * T, u = (int)(rr[c][uu] >> 16);
-                            if ((rr[c][uu] & 0xffffu) == 0u || u <= p) continue;
+                            if (k0 + uu >= D) break;
+                            const int u = (int)(rr[uu] >> 16);
+                            const bool edge_ok = (rr[uu] & 0xffffu) != 0u && u > p;
 #pragma unroll
-                            for (int j = 0; j < kIcmBatch; ++j)
-                                if (((dp[c] >> j) & 1u) && dis(j, u)) ptc::uf_union(L_parent + (size_t)j * n16, p, u);
+                            for (int j = 0; j < kIcmBatch; ++j) {
+                                if (j >= nb) break;
+                                const bool f = edge_ok && ((dp >> j) & 1u) && dis(j, u);
+                                const unsigned long long msk = __ballot(f);
+                                if (f) {
+                                    const int at = cnt + __popcll(msk & lanemask_lt());
+                                    wb[at] = (uint32_t)p | ((uint32_t)u << 16);
+                                    wj[at] = (unsigned char)j;
+                                }
+                                cnt += __popcll(msk);
+                                if (cnt >= 64) run_joins(64);
+                            }
                         }
+                    }
                 }
+                if (cnt > 0) run_joins(cnt);
             }
             __syncthreads();
             // energy change of flipping each seed's component: -2 s_v (h_v + sum over

@@ -73,7 +73,10 @@ def lib():
         L.orc_icm_step.restype = C.c_int
         L.orc_swap_test.argtypes = [i64, f64, i32, u32, u32, u32, u64]
         L.orc_swap_test.restype = C.c_int
-        for f in (L.orc_sa_sample, L.orc_pt_sample, L.orc_persist_fix, L.orc_ispvar):
+        L.orc_components.argtypes = [vp, vp]
+        L.orc_components.restype = i32
+        L.orc_merge_sorted.argtypes = [vp, vp, i32, vp, i32, vp, vp, vp]
+        for f in (L.orc_sa_sample, L.orc_pt_sample, L.orc_persist_fix, L.orc_ispvar, L.orc_merge_sorted):
             f.restype = C.c_int
         _lib = L
     return _lib
@@ -310,3 +313,30 @@ def ispvar(inst, betas, reads, seed, rounds, elite_frac, threshold, gauge=2):
     if rc < 0:
         raise OracleError(rc, "ispvar")
     return dict(fixed_mask=fm, fixed_val=fv, rounds_run=rc, round_info=info[:rc])
+
+
+def components(inst):
+    """Connected components over couplers J != 0 (Sec. II.C): (comp int32[n], n_comp), components
+    numbered in order of their smallest variable index."""
+    b = _Bound(inst)
+    comp = np.zeros(max(inst.n, 1), np.int32)
+    nc = lib().orc_components(b.ref, _ptr(comp))
+    if nc < 0:
+        raise OracleError(nc, "components")
+    return comp[:inst.n], int(nc)
+
+
+def merge_sorted(inst, comp, n_comp, samples):
+    """Sorted-merge recombination of a sample over the components (Sec. II.C).  Returns
+    (merged int8[R][n], merged_E int64[R], part_E int64[n_comp][R] in each component's order)."""
+    b = _Bound(inst)
+    s = np.ascontiguousarray(samples, dtype=np.int8).reshape(-1, inst.n)
+    R = s.shape[0]
+    cm = np.ascontiguousarray(comp, dtype=np.int32)
+    merged = np.zeros_like(s)
+    mE = np.zeros(R, np.int64)
+    pe = np.zeros((max(n_comp, 1), max(R, 1)), np.int64)
+    rc = lib().orc_merge_sorted(b.ref, _ptr(cm), int(n_comp), _ptr(s), R, _ptr(merged), _ptr(mE), _ptr(pe))
+    if rc != 0:
+        raise OracleError(rc, "merge_sorted")
+    return merged, mE, pe[:n_comp, :R]

@@ -66,6 +66,17 @@
  *    J' = J[U,U], h'_u = h_u + sum_{j fixed} J_uj v_j,
  *    offset = sum_{i<j fixed} J_ij v_i v_j + sum_{i fixed} h_i v_i, so that
  *    E(s) = E'(s_U) + offset whenever s agrees with the fixed values.
+ *
+ *  Disconnected problems (Sec. II.C, special considerations): components of
+ *    the graph whose edges are the couplers with J != 0, numbered in order of
+ *    their smallest variable index.  Partial energy of component c in row r:
+ *    E_c(r) = sum of J_ij s_i s_j over couplers inside c (each once) + sum of
+ *    h_i s_i over i in c, so E(s) = sum_c E_c(s).  Recombination: the rows of
+ *    each component are ordered by (E_c, row); merged row k takes, for every
+ *    component, its variables from the k-th row in that component's order,
+ *    and its energy is the sum over components of those k-th partial
+ *    energies.  The best merged row therefore holds every component's best
+ *    partial solution.
  */
 #include <math.h>
 #include <stdint.h>
@@ -996,4 +1007,108 @@ done:
     free(spins);
     free(E);
     return rc;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Disconnected problems (Sec. II.C special considerations).              */
+/* ---------------------------------------------------------------------- */
+
+/* Component of every variable (breadth-first search from the smallest
+ * unvisited index); returns the number of components or a negative status. */
+int32_t orc_components(const orc_problem *P, int32_t *comp)
+{
+    int32_t n = P->n, c = 0, i;
+    int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    if (!queue)
+        return ORC_ENOMEM;
+    for (i = 0; i < n; ++i)
+        comp[i] = -1;
+    for (i = 0; i < n; ++i) {
+        int32_t head = 0, tail = 0;
+        if (comp[i] >= 0)
+            continue;
+        comp[i] = c;
+        queue[tail++] = i;
+        while (head < tail) {
+            int32_t v = queue[head++], k;
+            for (k = P->row_ptr[v]; k < P->row_ptr[v + 1]; ++k) {
+                int32_t j = P->col[k];
+                if (P->J[k] != 0 && comp[j] < 0) {
+                    comp[j] = c;
+                    queue[tail++] = j;
+                }
+            }
+        }
+        ++c;
+    }
+    free(queue);
+    return c;
+}
+
+typedef struct {
+    int64_t e;
+    int32_t row;
+} part_key;
+
+static int cmp_part(const void *a, const void *b)
+{
+    const part_key *x = (const part_key *)a, *y = (const part_key *)b;
+    if (x->e != y->e)
+        return x->e < y->e ? -1 : 1;
+    return (x->row > y->row) - (x->row < y->row);
+}
+
+/* Sorted-merge recombination of a sample of R rows.  merged [R][n],
+ * merged_E [R]; part_E (optional) [n_comp][R] receives each component's
+ * partial energies in its sorted order. */
+int orc_merge_sorted(const orc_problem *P, const int32_t *comp, int32_t n_comp, const int8_t *samples,
+                     int32_t R, int8_t *merged, int64_t *merged_E, int64_t *part_E)
+{
+    int32_t n = P->n, r, i, c, k;
+    int64_t *pe;
+    part_key *keys;
+    if (n_comp < 0 || R < 0)
+        return ORC_EINVAL;
+    pe = (int64_t *)calloc((size_t)(R > 0 ? R : 1) * (size_t)(n_comp > 0 ? n_comp : 1), sizeof(int64_t));
+    keys = (part_key *)malloc(sizeof(part_key) * (size_t)(R > 0 ? R : 1));
+    if (!pe || !keys) {
+        free(pe);
+        free(keys);
+        return ORC_ENOMEM;
+    }
+    /* partial energies: every bias and every coupler once, charged to the
+     * component of its variables */
+    for (r = 0; r < R; ++r) {
+        const int8_t *s = samples + (size_t)r * n;
+        for (i = 0; i < n; ++i) {
+            int64_t e = (int64_t)P->h[i] * s[i];
+            for (k = P->row_ptr[i]; k < P->row_ptr[i + 1]; ++k) {
+                int32_t j = P->col[k];
+                if (j > i)
+                    e += (int64_t)P->J[k] * s[i] * s[j];
+            }
+            pe[(size_t)r * n_comp + comp[i]] += e;
+        }
+    }
+    for (k = 0; k < R; ++k)
+        merged_E[k] = 0;
+    for (c = 0; c < n_comp; ++c) {
+        for (r = 0; r < R; ++r) {
+            keys[r].e = pe[(size_t)r * n_comp + c];
+            keys[r].row = r;
+        }
+        qsort(keys, (size_t)R, sizeof(part_key), cmp_part);
+        for (k = 0; k < R; ++k) {
+            const int8_t *src = samples + (size_t)keys[k].row * n;
+            merged_E[k] += keys[k].e;
+            if (part_E)
+                part_E[(size_t)c * R + k] = keys[k].e;
+            for (i = 0; i < n; ++i)
+                if (comp[i] == c)
+                    merged[(size_t)k * n + i] = src[i];
+        }
+    }
+    free(pe);
+    free(keys);
+    return ORC_OK;
 }

@@ -283,6 +283,35 @@ def residual_batch(B, parent_M=16, n_min=50, n_max=1000, seed=0, j_max=6, h_max=
     return out
 
 
+def disjoint_union(parts, perm_seed=None, name="union"):
+    """Block-diagonal union of instances (a disconnected problem, as left by fixing),
+    optionally with the variables shuffled by a seeded permutation so that components
+    interleave in index order.  All parts must share scale_log2."""
+    scale = parts[0].scale_log2
+    if any(p.scale_log2 != scale for p in parts):
+        raise ValueError("parts with different scale_log2")
+    ei, ej, w, h, colour = [], [], [], [], []
+    off = 0
+    for p in parts:
+        a, b, v = p.edges()
+        ei.append(a + off)
+        ej.append(b + off)
+        w.append(v)
+        h.append(np.asarray(p.h, np.int64))
+        colour.append(np.asarray(p.colour, np.int64))
+        off += p.n
+    ei, ej, w = np.concatenate(ei), np.concatenate(ej), np.concatenate(w)
+    h, colour = np.concatenate(h), np.concatenate(colour)
+    n = off
+    if perm_seed is not None:
+        perm = np.random.default_rng(perm_seed).permutation(n)  # old index -> new index
+        ei, ej = perm[ei], perm[ej]
+        h2, c2 = np.empty_like(h), np.empty_like(colour)
+        h2[perm], c2[perm] = h, colour
+        h, colour = h2, c2
+    return from_edges(n, ei, ej, w, h, colour, max(p.n_colours for p in parts), scale, name)
+
+
 def linear_betas(beta0, beta1, sweeps):
     """beta_t = beta0 + (beta1 - beta0) * t / (sweeps - 1), t = 0..sweeps-1."""
     if sweeps == 1:

@@ -267,6 +267,36 @@ spv_status spv_top_sample(spv_ctx *ctx, const int8_t *top_spins, const int64_t *
                           int64_t *energies, int32_t *rows, hipStream_t stream);
 
 /*
+ * Connected components of a problem (Sec. II.C, special considerations: a
+ * problem left disconnected by fixing is treated per component).  Edges are
+ * the couplers with J != 0; components are numbered 0..n_comp-1 in order of
+ * their smallest variable index.
+ *   comp [n]  device int32, output
+ *   n_comp    host, output; the call waits for `stream` to read it back
+ */
+spv_status spv_components(spv_ctx *ctx, const spv_problem *P, int32_t *comp, int32_t *n_comp,
+                          hipStream_t stream);
+
+/*
+ * Sorted-merge recombination of a sample over the components (Sec. II.C): the
+ * partial energy E_c(r) of component c in row r sums its couplers (each once)
+ * and biases, so E = sum_c E_c; the rows of each component are ordered by
+ * (E_c, row index); merged row k takes every component's variables from the
+ * k-th row of that component's order, and merged_E[k] is the sum of those
+ * partial energies.  The best merged row holds every component's best
+ * partial solution, so it is a ground state whenever each component was
+ * solved in at least one row.
+ *   comp [n], n_comp   from spv_components (1 <= n_comp <= n)
+ *   samples [R][n] int8, merged [R][n] int8 (must not overlap samples),
+ *   merged_E [R] int64: device
+ *   part_E [n_comp][R] int64: device, each component's partial energies in its
+ *                      order, or NULL
+ */
+spv_status spv_merge_components(spv_ctx *ctx, const spv_problem *P, const int32_t *comp, int32_t n_comp,
+                                const int8_t *samples, int32_t R, int8_t *merged, int64_t *merged_E,
+                                int64_t *part_E, hipStream_t stream);
+
+/*
  * Batched simulated annealing over B instances of uneven size (the residual
  * problems left after fixing, Sec. II.C / Sec. III.C) in ONE persistent
  * launch.  Work items (instance, block of 4*quads_per_item reads) are popped

@@ -84,6 +84,8 @@ _SIGS = {
     "spv_sample_batch": ([_vp, _i32, _P, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "spv_batch_last_shape": ([_vp, _vp, _vp, _vp, _vp], C.c_int),
     "spv_top_sample": ([_vp, _vp, _vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp], C.c_int),
+    "spv_components": ([_vp, _P, _vp, _vp, _vp], C.c_int),
+    "spv_merge_components": ([_vp, _P, _vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp], C.c_int),
 }
 EXPORTED = sorted(_SIGS)
 for _name, (_args, _res) in _SIGS.items():
@@ -324,6 +326,31 @@ def spv_top_sample(ctx, pt, stream=None):
                                   lists, n, _ptr(S) if n else None, _ptr(E), C.byref(rows), _stream(stream)),
               "spv_top_sample")
     return S[:rows.value], E[:rows.value]
+
+
+def spv_components(ctx, P, stream=None):
+    """Connected components over couplers J != 0 (Sec. II.C): (comp int32[n] on the device,
+    n_comp), numbered in order of each component's smallest variable."""
+    comp = torch.empty(max(P.n, 1), dtype=torch.int32, device=ctx.device)
+    nc = C.c_int32(0)
+    ps = P.c_struct()
+    ctx.check(_lib.spv_components(ctx.handle, C.byref(ps), _ptr(comp), C.byref(nc), _stream(stream)),
+              "spv_components")
+    return comp[:P.n], nc.value
+
+
+def spv_merge_components(ctx, P, comp, n_comp, samples, part=False, stream=None):
+    """Sorted-merge recombination of a sample over the components (Sec. II.C).  Returns
+    (merged int8[R][n], merged_E int64[R], part_E int64[n_comp][R] or None) on the device."""
+    R = samples.shape[0]
+    merged = torch.empty_like(samples)
+    mE = torch.empty(max(R, 1), dtype=torch.int64, device=ctx.device)
+    pe = torch.empty((max(n_comp, 1), max(R, 1)), dtype=torch.int64, device=ctx.device) if part else None
+    ps = P.c_struct()
+    ctx.check(_lib.spv_merge_components(ctx.handle, C.byref(ps), _ptr(comp) if P.n else None, int(n_comp),
+                                        _ptr(samples) if P.n else None, int(R), _ptr(merged) if P.n else None,
+                                        _ptr(mE), _ptr(pe), _stream(stream)), "spv_merge_components")
+    return merged, mE[:R], (pe[:n_comp, :R] if part else None)
 
 
 def spv_sample_batch(ctx, problems, betas, reads, seeds, spins=None, energies=None, threads=0,

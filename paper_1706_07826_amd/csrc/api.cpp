@@ -290,7 +290,7 @@ void spv_ctx_destroy(spv_ctx *ctx) {
     if (ctx->c.stage) (void)hipHostFree(ctx->c.stage);
     if (ctx->c.stage_done) (void)hipEventDestroy(ctx->c.stage_done);
     for (DevBuf *b : {&ctx->c.image, &ctx->c.tables, &ctx->c.tables2, &ctx->c.scratch, &ctx->c.scratch2,
-                      &ctx->c.rounds, &ctx->c.pt, &ctx->c.pt_tab, &ctx->c.top, &ctx->c.serve})
+                      &ctx->c.rounds, &ctx->c.pt, &ctx->c.pt_tab, &ctx->c.top, &ctx->c.serve, &ctx->c.merge})
         if (b->p) (void)hipFree(b->p);
     delete ctx;
 }
@@ -743,6 +743,54 @@ spv_status spv_top_sample(spv_ctx *ctx, const int8_t *top_spins, const int64_t *
     if (e != hipSuccess) return hip_check(c, e, "top gather launch");
     *rows = total;
     return SPV_OK;
+}
+
+spv_status spv_components(spv_ctx *ctx, const spv_problem *P, int32_t *comp, int32_t *n_comp,
+                          hipStream_t stream) {
+    if (!ctx) return SPV_EINVAL;
+    Ctx *c = &ctx->c;
+    DeviceGuard g(c->device);
+    spv_status st = check_problem_host(c, P);
+    if (st) return st;
+    if (!n_comp || (P->n > 0 && !comp)) return set_err(c, SPV_EINVAL, "spv_components: NULL output");
+    *n_comp = 0;
+    if (P->n == 0) return SPV_OK;
+    if (components_lds_bytes(P->n) + 256 > c->lds_max)
+        return set_err(c, SPV_ECAPACITY, "spv_components: n=%d exceeds one workgroup's LDS", P->n);
+    if ((st = ensure(c, c->merge, 256))) return st;
+    int32_t *dcount = static_cast<int32_t *>(c->merge.p);
+    hipError_t e = launch_components(P, comp, dcount, stream);
+    int32_t hcount = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&hcount, dcount, 4, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_check(c, e, "components");
+    *n_comp = hcount;
+    return SPV_OK;
+}
+
+spv_status spv_merge_components(spv_ctx *ctx, const spv_problem *P, const int32_t *comp, int32_t n_comp,
+                                const int8_t *samples, int32_t R, int8_t *merged, int64_t *merged_E,
+                                int64_t *part_E, hipStream_t stream) {
+    if (!ctx) return SPV_EINVAL;
+    Ctx *c = &ctx->c;
+    DeviceGuard g(c->device);
+    spv_status st = check_problem_host(c, P);
+    if (st) return st;
+    if (R < 0) return set_err(c, SPV_EINVAL, "spv_merge_components: R=%d", R);
+    if (R == 0) return SPV_OK;
+    if (P->n == 0) {
+        if (!merged_E) return set_err(c, SPV_EINVAL, "spv_merge_components: NULL merged_E");
+        return hip_check(c, hipMemsetAsync(merged_E, 0, 8ull * R, stream), "memset");
+    }
+    if (n_comp < 1 || n_comp > P->n) return set_err(c, SPV_EINVAL, "spv_merge_components: n_comp=%d", n_comp);
+    if (!comp || !samples || !merged || !merged_E)
+        return set_err(c, SPV_EINVAL, "spv_merge_components: NULL buffer");
+    if ((size_t)n_comp * (size_t)R > (size_t)1 << 31)
+        return set_err(c, SPV_ECAPACITY, "spv_merge_components: n_comp x R too large");
+    if ((st = ensure(c, c->merge, 256 + merge_scratch_bytes(n_comp, R)))) return st;
+    void *scratch = static_cast<unsigned char *>(c->merge.p) + 256;
+    return hip_check(c, launch_merge(P, comp, n_comp, samples, R, merged, merged_E, part_E, scratch, stream),
+                     "merge launch");
 }
 
 }  // extern "C"

@@ -67,6 +67,7 @@ struct Ctx {
     DevBuf batch;   // batched launch: descriptors, items, counter, images
     DevBuf top;     // sample assembly: per-list offsets
     DevBuf serve;   // serving slot: assembled tempering sample
+    DevBuf merge;   // component count and recombination scratch
     TableCache tcache;
     std::vector<uint32_t> host_tables;
     void *batch_host = nullptr;  // pinned staging of descriptors and items
@@ -257,6 +258,13 @@ size_t ptx_lds_bytes(int n, int D, int m, int chains, int row_len, int nw_icm, b
 int ptx_msg_words(int n);
 hipError_t ptx_max_groups_resident(int nd, bool big, int D, int threads, size_t lds, int *blocks_per_cu);
 hipError_t launch_ptx(const PtxLaunch &L, hipStream_t s);
+
+// Components and sorted-merge recombination (components.hip).
+size_t components_lds_bytes(int n);
+hipError_t launch_components(const spv_problem *P, int32_t *comp, int32_t *count, hipStream_t s);
+size_t merge_scratch_bytes(int C, int R);
+hipError_t launch_merge(const spv_problem *P, const int32_t *comp, int C, const int8_t *S, int R, int8_t *merged,
+                        int64_t *merged_E, int64_t *part_E, void *scratch, hipStream_t s);
 
 }  // namespace spv
 

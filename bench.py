@@ -81,7 +81,8 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after timing, run one device copy of this size (counter calibration)")
     ap.add_argument("--workload", default="chimera8_sa",
-                    choices=["chimera8_sa", "residual_batch", "cubic10_pt", "cubic20_pticm", "serving"])
+                    choices=["chimera8_sa", "residual_batch", "cubic10_pt", "cubic20_pticm", "serving",
+                             "spvar_round"])
     ap.add_argument("--pt-runs", type=int, default=0, help="PT workloads: runs per step (0 = the config's)")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--serving-slots", type=int, default=8)
@@ -115,6 +116,8 @@ def main():
                         "colder slots per chain, persistence elite 0.2")
     if args.workload == "serving":
         return bench_serving(args)
+    if args.workload == "spvar_round":
+        return bench_spvar_round(args)
 
     cfg = cf.CHIMERA8_SA
     inst = cf.instance(cfg)
@@ -395,6 +398,66 @@ def bench_serving(args):
         "saturation": sat, "poisson": loads,
     }
     print(json.dumps(out), flush=True)
+
+
+def bench_spvar_round(args):
+    """One SPVAR round with the recombination of Sec. II.C on the Chimera N=512 workload:
+    SA (10,000 reads x 2,000 sweeps) -> persistence (elite 5 %, threshold 0.95) ->
+    components of the residual -> SA on the residual (same reads and schedule) ->
+    sorted-merge recombination over the components."""
+    import numpy as np
+    import torch
+
+    import paper_1706_07826_amd as spv
+    from spvar_inputs import configs as cf
+
+    cfg = cf.CHIMERA8_SA
+    inst = cf.instance(cfg)
+    betas = cf.betas(cfg)
+    reads, sweeps = cfg["reads"], cfg["sweeps"]
+    ctx = spv.Context(0)
+    P = spv.Problem.from_instance(inst)
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        S, E = spv.spv_sample(ctx, P, betas, reads, cfg["seed"])
+        fx = spv.spv_persist_fix(ctx, P, S, E, cfg["elite"], cfg["theta"], cfg["gauge"])
+        red = fx.reduced()  # reads the sizes back (synchronises)
+        comp, nc = spv.spv_components(ctx, red)
+        RS, RE = spv.spv_sample(ctx, red, betas, reads, cfg["seed"] + 1)
+        if ev is not None:
+            ev[0].record(stream)
+        merged, mE, _ = spv.spv_merge_components(ctx, red, comp, nc, RS)
+        if ev is not None:
+            ev[1].record(stream)
+        return dict(E=E, fx=fx, red=red, nc=nc, RE=RE, mE=mE)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        out = step(evs[k])
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    merge_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    n_res = out["red"].n
+    updates = reads * sweeps * (inst.n + n_res)
+    off = out["fx"].info()["offset"]
+    res = {
+        "metric": BASELINE_METRIC, "value": round(updates / dt, 1), "unit": "spin-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic (seeded Chimera U{+-1..+-6} instance)",
+        "config": {"workload": "spvar_round: chimera8 SA 10000 x 2000 -> persistence -> components of the "
+                               "residual -> SA on the residual 10000 x 2000 -> sorted-merge recombination"},
+        "residual_n": n_res, "components": out["nc"], "merge_ms": round(merge_ms, 4),
+        "best_E_first_sample": int(out["E"].min().item()),
+        "best_E_round_unmerged": int(out["RE"].min().item()) + off,
+        "best_E_round_merged": int(out["mE"][0].item()) + off,
+    }
+    print(json.dumps(res), flush=True)
 
 
 if __name__ == "__main__":

@@ -77,6 +77,15 @@
  *    and its energy is the sum over components of those k-th partial
  *    energies.  The best merged row therefore holds every component's best
  *    partial solution.
+ *
+ *  Multi-start SPVAR (Algorithm 2): start s fixes variables from reads
+ *    [s*F, (s+1)*F) of one SA job on the problem (seed), records their
+ *    energies, then samples its modified problem with Rs reads of an SA job
+ *    with seed + 1 + s and records E' + offset_s (optionally after the
+ *    recombination above over the modified problem's components).  The best
+ *    state is the first minimum of the recorded energies in the order: start
+ *    0's fixing rows, start 0's solving rows, start 1's fixing rows, ...; a
+ *    solving row is completed with the start's fixed values.
  */
 #include <math.h>
 #include <stdint.h>
@@ -1111,4 +1120,121 @@ int orc_merge_sorted(const orc_problem *P, const int32_t *comp, int32_t n_comp, 
     free(pe);
     free(keys);
     return ORC_OK;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Multi-start SPVAR (Algorithm 2).                                        */
+/* ---------------------------------------------------------------------- */
+
+/* fixing_E [S][F], solving_E [S][Rs], fixed_mask/fixed_val [S][n],
+ * info [S][4] = (n_fixed, n_free, offset, components or 0), best_spins [n]. */
+int orc_multistart(const orc_problem *P, const double *betas, int32_t sweeps, uint64_t seed,
+                   int32_t starts, int32_t F, int32_t Rs, double elite_frac, double threshold,
+                   int32_t gauge, int32_t merge, int64_t *fixing_E, int64_t *solving_E,
+                   uint8_t *fixed_mask, int8_t *fixed_val, int64_t *info_o, int8_t *best_spins,
+                   int64_t *best_E)
+{
+    int32_t n = P->n, nnz = P->row_ptr[n], s, r, i;
+    int32_t *rp = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n + 1));
+    int32_t *cl = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+    int32_t *jv = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+    int32_t *hv = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    uint8_t *co = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
+    int32_t *orig = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t *comp = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int8_t *fs = (int8_t *)malloc((size_t)starts * F * (size_t)(n > 0 ? n : 1));
+    int8_t *ss = (int8_t *)malloc((size_t)(Rs > 0 ? Rs : 1) * (size_t)(n > 0 ? n : 1));
+    int8_t *mg = (int8_t *)malloc((size_t)(Rs > 0 ? Rs : 1) * (size_t)(n > 0 ? n : 1));
+    int64_t *se = (int64_t *)malloc(sizeof(int64_t) * (size_t)(Rs > 0 ? Rs : 1));
+    int64_t info[8];
+    int64_t best = INT64_MAX;
+    int rc = ORC_OK;
+    orc_problem red;
+    if (!rp || !cl || !jv || !hv || !co || !orig || !comp || !fs || !ss || !mg || !se) {
+        rc = ORC_ENOMEM;
+        goto done;
+    }
+    if (starts < 1 || F < 1 || Rs < 0) {
+        rc = ORC_EINVAL;
+        goto done;
+    }
+    /* fixing samples of every start: one SA job, start s owns reads [s*F, (s+1)*F) */
+    rc = orc_sa_sample(P, betas, sweeps, seed, 0, 0, starts * F, NULL, NULL, fs, fixing_E);
+    if (rc)
+        goto done;
+    for (s = 0; s < starts; ++s) {
+        const int8_t *fsamp = fs + (size_t)s * F * n;
+        const int64_t *fe = fixing_E + (size_t)s * F;
+        uint8_t *fm = fixed_mask + (size_t)s * n;
+        int8_t *fv = fixed_val + (size_t)s * n;
+        int64_t off;
+        int32_t nf, nc = 0;
+        for (r = 0; r < F; ++r)
+            if (fe[r] < best) {
+                best = fe[r];
+                memcpy(best_spins, fsamp + (size_t)r * n, (size_t)n);
+            }
+        rc = orc_persist_fix(P, fsamp, fe, F, elite_frac, threshold, gauge, fm, fv, rp, cl, jv, hv, co,
+                             orig, info);
+        if (rc)
+            goto done;
+        nf = (int32_t)info[0];
+        off = info[2];
+        red = *P;
+        red.n = nf;
+        red.row_ptr = rp;
+        red.col = cl;
+        red.J = jv;
+        red.h = hv;
+        red.colour = co;
+        if (Rs > 0) {
+            if (nf > 0) {
+                rc = orc_sa_sample(&red, betas, sweeps, seed + 1 + (uint64_t)s, 0, 0, Rs, NULL, NULL, ss, se);
+                if (rc)
+                    goto done;
+                if (merge) {
+                    nc = orc_components(&red, comp);
+                    if (nc < 0) {
+                        rc = nc;
+                        goto done;
+                    }
+                    rc = orc_merge_sorted(&red, comp, nc, ss, Rs, mg, se, NULL);
+                    if (rc)
+                        goto done;
+                    memcpy(ss, mg, (size_t)Rs * nf);
+                }
+            } else {
+                for (r = 0; r < Rs; ++r)
+                    se[r] = 0;
+            }
+            for (r = 0; r < Rs; ++r) {
+                solving_E[(size_t)s * Rs + r] = se[r] + off;
+                if (se[r] + off < best) {
+                    best = se[r] + off;
+                    for (i = 0; i < n; ++i)
+                        best_spins[i] = fm[i] ? fv[i] : 0;
+                    for (i = 0; i < nf; ++i)
+                        best_spins[orig[i]] = ss[(size_t)r * nf + i];
+                }
+            }
+        }
+        info_o[s * 4 + 0] = info[3];
+        info_o[s * 4 + 1] = nf;
+        info_o[s * 4 + 2] = off;
+        info_o[s * 4 + 3] = nc;
+    }
+    *best_E = best;
+done:
+    free(rp);
+    free(cl);
+    free(jv);
+    free(hv);
+    free(co);
+    free(orig);
+    free(comp);
+    free(fs);
+    free(ss);
+    free(mg);
+    free(se);
+    return rc;
 }

@@ -297,6 +297,45 @@ spv_status spv_merge_components(spv_ctx *ctx, const spv_problem *P, const int32_
                                 int64_t *part_E, hipStream_t stream);
 
 /*
+ * Multi-start SPVAR (Algorithm 2): `starts` independent starts.  Start s
+ * applies SPVAR (Algorithm 1, spv_persist_fix) to reads [s*F, (s+1)*F) of one
+ * SA job on P with `seed` (F = fixing_reads), then samples its modified
+ * problem with Rs = solving_reads reads of an SA job with seed + 1 + s (all
+ * starts in one batched launch), optionally recombining that sample over the
+ * modified problem's components (Sec. II.C).  Every recorded energy is a
+ * full-problem energy (E' + the start's offset).  The call waits for
+ * `stream` (it reads back the per-start sizes).
+ */
+typedef struct {
+    int32_t starts;          /* num_starts >= 1 */
+    int32_t fixing_reads;    /* fixing_sample_size F >= 1 */
+    int32_t solving_reads;   /* solving_sample_size Rs >= 0 */
+    const double *betas;     /* host [sweeps]: SA schedule of both samples */
+    int32_t sweeps;
+    uint64_t seed;
+    double elite_frac;       /* as spv_persist_fix */
+    double threshold;
+    int32_t gauge;
+    int32_t merge;           /* 1: recombine each solving sample over its components */
+} spv_multistart_params;
+
+typedef struct {
+    int64_t *fixing_E;       /* device [starts][F] */
+    int64_t *solving_E;      /* device [starts][Rs]: full-problem energies (sorted when merged) */
+    uint8_t *fixed_mask;     /* device [starts][n] or NULL */
+    int8_t *fixed_val;       /* device [starts][n] or NULL */
+    int64_t *info;           /* host [starts][4] or NULL: n_fixed, n_free, offset, components
+                                (0 unless merged) */
+    int8_t *best_spins;      /* device [n] or NULL: the first lowest recorded state in the order
+                                start 0 fixing rows, start 0 solving rows, start 1 ..., a
+                                solving row completed with its start's fixed values */
+    int64_t *best_E;         /* host or NULL */
+} spv_multistart_out;
+
+spv_status spv_multistart(spv_ctx *ctx, const spv_problem *P, const spv_multistart_params *params,
+                          const spv_multistart_out *out, hipStream_t stream);
+
+/*
  * Batched simulated annealing over B instances of uneven size (the residual
  * problems left after fixing, Sec. II.C / Sec. III.C) in ONE persistent
  * launch.  Work items (instance, block of 4*quads_per_item reads) are popped

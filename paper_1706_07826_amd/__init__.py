@@ -60,6 +60,18 @@ SPV_BATCH_GRAPH = 1
 SPV_BATCH_TUNE = 2
 
 
+class spv_multistart_params(C.Structure):
+    _fields_ = [("starts", C.c_int32), ("fixing_reads", C.c_int32), ("solving_reads", C.c_int32),
+                ("betas", C.c_void_p), ("sweeps", C.c_int32), ("seed", C.c_uint64), ("elite_frac", C.c_double),
+                ("threshold", C.c_double), ("gauge", C.c_int32), ("merge", C.c_int32)]
+
+
+class spv_multistart_out(C.Structure):
+    _fields_ = [("fixing_E", C.c_void_p), ("solving_E", C.c_void_p), ("fixed_mask", C.c_void_p),
+                ("fixed_val", C.c_void_p), ("info", C.c_void_p), ("best_spins", C.c_void_p),
+                ("best_E", C.c_void_p)]
+
+
 class spv_pt_out(C.Structure):
     _fields_ = [("final_spins", C.c_void_p), ("final_E", C.c_void_p), ("top_spins", C.c_void_p),
                 ("top_E", C.c_void_p), ("top_count", C.c_void_p)]
@@ -86,6 +98,7 @@ _SIGS = {
     "spv_top_sample": ([_vp, _vp, _vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp], C.c_int),
     "spv_components": ([_vp, _P, _vp, _vp, _vp], C.c_int),
     "spv_merge_components": ([_vp, _P, _vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp], C.c_int),
+    "spv_multistart": ([_vp, _P, C.POINTER(spv_multistart_params), C.POINTER(spv_multistart_out), _vp], C.c_int),
 }
 EXPORTED = sorted(_SIGS)
 for _name, (_args, _res) in _SIGS.items():
@@ -351,6 +364,34 @@ def spv_merge_components(ctx, P, comp, n_comp, samples, part=False, stream=None)
                                         _ptr(samples) if P.n else None, int(R), _ptr(merged) if P.n else None,
                                         _ptr(mE), _ptr(pe), _stream(stream)), "spv_merge_components")
     return merged, mE[:R], (pe[:n_comp, :R] if part else None)
+
+
+def spv_multistart(ctx, P, betas, seed, starts, fixing_reads, solving_reads, elite_frac, threshold, gauge=0,
+                   merge=False, stream=None):
+    """Multi-start SPVAR (Algorithm 2).  Returns a dict: fixing_E [S][F], solving_E [S][Rs]
+    (full-problem energies), fixed_mask/fixed_val [S][n] (device), info [S][4] (host: n_fixed,
+    n_free, offset, components), best_E (host int) and best_spins [n] (device)."""
+    b = np.ascontiguousarray(betas, dtype=np.float64)
+    dev, n, S, F, Rs = ctx.device, P.n, int(starts), int(fixing_reads), int(solving_reads)
+    res = dict(fixing_E=torch.empty((S, F), dtype=torch.int64, device=dev),
+               solving_E=torch.empty((S, max(Rs, 1)), dtype=torch.int64, device=dev),
+               fixed_mask=torch.empty((S, max(n, 1)), dtype=torch.uint8, device=dev),
+               fixed_val=torch.empty((S, max(n, 1)), dtype=torch.int8, device=dev),
+               info=np.zeros((S, 4), np.int64), best_spins=torch.empty(max(n, 1), dtype=torch.int8, device=dev))
+    best = C.c_int64(0)
+    prm = spv_multistart_params(S, F, Rs, b.ctypes.data, b.size, C.c_uint64(seed & (2**64 - 1)),
+                                float(elite_frac), float(threshold), int(gauge), int(bool(merge)))
+    out = spv_multistart_out(res["fixing_E"].data_ptr(), res["solving_E"].data_ptr(),
+                             res["fixed_mask"].data_ptr(), res["fixed_val"].data_ptr(), res["info"].ctypes.data,
+                             res["best_spins"].data_ptr(), C.addressof(best))
+    ps = P.c_struct()
+    ctx.check(_lib.spv_multistart(ctx.handle, C.byref(ps), C.byref(prm), C.byref(out), _stream(stream)),
+              "spv_multistart")
+    res["solving_E"] = res["solving_E"][:, :Rs]
+    res["fixed_mask"], res["fixed_val"] = res["fixed_mask"][:, :n], res["fixed_val"][:, :n]
+    res["best_spins"] = res["best_spins"][:n]
+    res["best_E"] = int(best.value)
+    return res
 
 
 def spv_sample_batch(ctx, problems, betas, reads, seeds, spins=None, energies=None, threads=0,

@@ -290,7 +290,7 @@ void spv_ctx_destroy(spv_ctx *ctx) {
     if (ctx->c.stage) (void)hipHostFree(ctx->c.stage);
     if (ctx->c.stage_done) (void)hipEventDestroy(ctx->c.stage_done);
     for (DevBuf *b : {&ctx->c.image, &ctx->c.tables, &ctx->c.tables2, &ctx->c.scratch, &ctx->c.scratch2,
-                      &ctx->c.rounds, &ctx->c.pt, &ctx->c.pt_tab, &ctx->c.top, &ctx->c.serve, &ctx->c.merge})
+                      &ctx->c.rounds, &ctx->c.pt, &ctx->c.pt_tab, &ctx->c.top, &ctx->c.serve, &ctx->c.merge, &ctx->c.ms})
         if (b->p) (void)hipFree(b->p);
     delete ctx;
 }

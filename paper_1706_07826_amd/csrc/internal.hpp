@@ -68,6 +68,7 @@ struct Ctx {
     DevBuf top;     // sample assembly: per-list offsets
     DevBuf serve;   // serving slot: assembled tempering sample
     DevBuf merge;   // component count and recombination scratch
+    DevBuf ms;      // multi-start working set
     TableCache tcache;
     std::vector<uint32_t> host_tables;
     void *batch_host = nullptr;  // pinned staging of descriptors and items
@@ -265,6 +266,14 @@ hipError_t launch_components(const spv_problem *P, int32_t *comp, int32_t *count
 size_t merge_scratch_bytes(int C, int R);
 hipError_t launch_merge(const spv_problem *P, const int32_t *comp, int C, const int8_t *S, int R, int8_t *merged,
                         int64_t *merged_E, int64_t *part_E, void *scratch, hipStream_t s);
+
+// Multi-start driver helpers (multistart.hip).
+hipError_t launch_ms_offset(const int64_t *Ered, const int64_t *info, int info_stride, int S, int Rs,
+                            int64_t *solving_E, hipStream_t s);
+hipError_t launch_ms_best(const int64_t *fixE, const int64_t *solE, int S, int F, int Rs, int n,
+                          const int8_t *fix_spins, const int8_t *sol_spins, size_t sol_stride, const uint8_t *fmask,
+                          const int8_t *fval, const int32_t *orig, size_t orig_stride, const int64_t *info,
+                          int info_stride, int64_t *best, int8_t *best_spins, hipStream_t s);
 
 }  // namespace spv
 

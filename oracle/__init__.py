@@ -79,6 +79,10 @@ def lib():
         L.orc_multistart.argtypes = [vp, vp, i32, u64, i32, i32, i32, f64, f64, i32, i32, vp, vp, vp, vp,
                                      vp, vp, vp]
         L.orc_multistart.restype = C.c_int
+        L.orc_tree_peel.argtypes = [vp] * 12
+        L.orc_tree_peel.restype = C.c_int
+        L.orc_tree_expand.argtypes = [i32, vp, vp, vp, vp, vp, i32, i32, vp, i32, vp]
+        L.orc_tree_expand.restype = C.c_int
         for f in (L.orc_sa_sample, L.orc_pt_sample, L.orc_persist_fix, L.orc_ispvar, L.orc_merge_sorted):
             f.restype = C.c_int
         _lib = L
@@ -367,3 +371,47 @@ def multistart(inst, betas, seed, starts, fixing_reads, solving_reads, elite_fra
     out["best_E"] = int(best.value)
     out["best_spins"] = out["best_spins"][:n]
     return out
+
+
+def tree_peel(inst):
+    """Tree / degree-1 pre-processing (Sec. II.C).  Returns a dict: kind, value, parent, round
+    (per variable), the reduced instance, orig_index, offset, n_free, nnz_free, n_fixed,
+    n_inferred, rounds."""
+    from spvar_inputs import Instance
+
+    b = _Bound(inst)
+    n, nnz = inst.n, int(inst.row_ptr[-1])
+    kind = np.zeros(max(n, 1), np.uint8)
+    value = np.zeros(max(n, 1), np.int8)
+    parent = np.zeros(max(n, 1), np.int32)
+    rnd = np.zeros(max(n, 1), np.int32)
+    rp = np.zeros(n + 1, np.int32)
+    col = np.zeros(max(nnz, 1), np.int32)
+    J = np.zeros(max(nnz, 1), np.int32)
+    h = np.zeros(max(n, 1), np.int32)
+    co = np.zeros(max(n, 1), np.uint8)
+    orig = np.zeros(max(n, 1), np.int32)
+    info = np.zeros(8, np.int64)
+    rc = lib().orc_tree_peel(b.ref, _ptr(kind), _ptr(value), _ptr(parent), _ptr(rnd), _ptr(rp), _ptr(col), _ptr(J),
+                             _ptr(h), _ptr(co), _ptr(orig), _ptr(info))
+    if rc != 0:
+        raise OracleError(rc, "tree_peel")
+    nf, nz = int(info[0]), int(info[1])
+    red = Instance(n=nf, row_ptr=rp[:nf + 1].copy(), col=col[:nz].copy(), J=J[:nz].copy(), h=h[:nf].copy(),
+                   colour=co[:nf].copy(), n_colours=inst.n_colours, scale_log2=inst.scale_log2)
+    return dict(kind=kind[:n], value=value[:n], parent=parent[:n], round=rnd[:n], reduced=red,
+                orig_index=orig[:nf], offset=int(info[2]), n_free=nf, nnz_free=nz, n_fixed=int(info[3]),
+                n_inferred=int(info[4]), rounds=int(info[5]))
+
+
+def tree_expand(inst, peel, reduced_spins):
+    """Complete reduced states to full states (inferred values from the last round back)."""
+    rs = np.ascontiguousarray(reduced_spins, dtype=np.int8).reshape(-1, peel["n_free"]) if peel["n_free"] else \
+        np.zeros((np.asarray(reduced_spins).shape[0], 0), np.int8)
+    R, n = rs.shape[0], inst.n
+    full = np.zeros((R, n), np.int8)
+    lib().orc_tree_expand(n, _ptr(np.ascontiguousarray(peel["kind"])), _ptr(np.ascontiguousarray(peel["value"])),
+                          _ptr(np.ascontiguousarray(peel["parent"])), _ptr(np.ascontiguousarray(peel["round"])),
+                          _ptr(np.ascontiguousarray(peel["orig_index"])), peel["n_free"], peel["rounds"], _ptr(rs),
+                          R, _ptr(full))
+    return full

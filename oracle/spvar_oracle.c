@@ -86,6 +86,19 @@
  *    state is the first minimum of the recorded energies in the order: start
  *    0's fixing rows, start 0's solving rows, start 1's fixing rows, ...; a
  *    solving row is completed with the start's fixed values.
+ *
+ *  Tree pre-processing (Sec. II.C): the degree of a remaining variable counts
+ *    its couplers with J != 0 to remaining variables.  In every round all
+ *    remaining variables of degree <= 1 are removed at once, except that of
+ *    two remaining variables joined only to each other the larger index goes
+ *    first.  Degree 0: fixed to -sign(h) (+1 when h = 0), offset += h s.
+ *    Degree 1 with neighbour j and coupler J: if |J| <= |h| fixed to
+ *    -sign(h), h_j += J s, offset += h s; else inferred s = -sign(J) s_j,
+ *    h_j -= sign(J) h, offset -= |J|.  Rounds repeat until none is removed;
+ *    the remaining variables (in index order) with their updated biases and
+ *    the couplers among them form the reduced problem, so that E(s) =
+ *    E'(s') + offset for every completion s of a reduced state s' (inferred
+ *    values filled in from the last round back to the first).
  */
 #include <math.h>
 #include <stdint.h>
@@ -1237,4 +1250,146 @@ done:
     free(mg);
     free(se);
     return rc;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Tree pre-processing (Sec. II.C).                                        */
+/* ---------------------------------------------------------------------- */
+
+/* kind [n]: 0 remaining, 1 fixed, 2 inferred; value [n]: the fixed value, or
+ * for an inferred variable the factor f with s = f * s_parent; parent [n];
+ * round [n] (-1 for remaining variables); reduced CSR (row_ptr_o [n+1], col_o,
+ * J_o, h_o, colour_o), orig_o [n'] (reduced -> original); info [8] = n_free,
+ * nnz_free, offset, n_fixed, n_inferred, rounds, 0, 0. */
+int orc_tree_peel(const orc_problem *P, uint8_t *kind, int8_t *value, int32_t *parent, int32_t *round,
+                  int32_t *row_ptr_o, int32_t *col_o, int32_t *J_o, int32_t *h_o, uint8_t *colour_o,
+                  int32_t *orig_o, int64_t *info)
+{
+    int32_t n = P->n, i, k, rd = 0;
+    int64_t *h = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    int32_t *deg = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t *nb = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t *nbk = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    uint8_t *peel = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
+    int32_t *newidx = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int64_t offset = 0, n_fixed = 0, n_inf = 0;
+    int32_t nf = 0, nz = 0;
+    if (!h || !deg || !nb || !nbk || !peel || !newidx) {
+        free(h); free(deg); free(nb); free(nbk); free(peel); free(newidx);
+        return ORC_ENOMEM;
+    }
+    for (i = 0; i < n; ++i) {
+        h[i] = P->h[i];
+        kind[i] = 0;
+        value[i] = 0;
+        parent[i] = -1;
+        round[i] = -1;
+    }
+    for (;;) {
+        int32_t any = 0;
+        /* degrees and the single remaining neighbour of every remaining variable */
+        for (i = 0; i < n; ++i) {
+            deg[i] = 0;
+            nb[i] = -1;
+            nbk[i] = -1;
+            if (kind[i] != 0)
+                continue;
+            for (k = P->row_ptr[i]; k < P->row_ptr[i + 1]; ++k)
+                if (P->J[k] != 0 && kind[P->col[k]] == 0) {
+                    ++deg[i];
+                    nb[i] = P->col[k];
+                    nbk[i] = k;
+                }
+        }
+        for (i = 0; i < n; ++i) {
+            peel[i] = 0;
+            if (kind[i] != 0 || deg[i] > 1)
+                continue;
+            if (deg[i] == 1 && deg[nb[i]] == 1 && nb[i] > i)
+                continue; /* an isolated pair: the larger index goes first */
+            peel[i] = 1;
+            any = 1;
+        }
+        if (!any)
+            break;
+        for (i = 0; i < n; ++i) {
+            int64_t hi = h[i];
+            if (!peel[i])
+                continue;
+            round[i] = rd;
+            if (deg[i] == 0) {
+                int8_t s = hi > 0 ? -1 : 1;
+                kind[i] = 1;
+                value[i] = s;
+                offset += hi * s;
+                ++n_fixed;
+            } else {
+                int32_t j = nb[i];
+                int64_t Jv = P->J[nbk[i]], aJ = Jv < 0 ? -Jv : Jv, ah = hi < 0 ? -hi : hi;
+                parent[i] = j;
+                if (aJ <= ah) {
+                    int8_t s = hi > 0 ? -1 : 1;
+                    kind[i] = 1;
+                    value[i] = s;
+                    h[j] += Jv * s;
+                    offset += hi * s;
+                    ++n_fixed;
+                } else {
+                    int8_t f = Jv > 0 ? -1 : 1;
+                    kind[i] = 2;
+                    value[i] = f;
+                    h[j] += f * hi; /* -sign(J) h */
+                    offset -= aJ;
+                    ++n_inf;
+                }
+            }
+        }
+        ++rd;
+    }
+    /* reduced problem over the remaining variables, in index order */
+    for (i = 0; i < n; ++i)
+        newidx[i] = kind[i] == 0 ? nf++ : -1;
+    row_ptr_o[0] = 0;
+    for (i = 0; i < n; ++i) {
+        if (kind[i] != 0)
+            continue;
+        orig_o[newidx[i]] = i;
+        h_o[newidx[i]] = (int32_t)h[i];
+        colour_o[newidx[i]] = P->colour[i];
+        for (k = P->row_ptr[i]; k < P->row_ptr[i + 1]; ++k)
+            if (kind[P->col[k]] == 0) {
+                col_o[nz] = newidx[P->col[k]];
+                J_o[nz] = P->J[k];
+                ++nz;
+            }
+        row_ptr_o[newidx[i] + 1] = nz;
+    }
+    info[0] = nf;
+    info[1] = nz;
+    info[2] = offset;
+    info[3] = n_fixed;
+    info[4] = n_inf;
+    info[5] = rd;
+    info[6] = 0;
+    info[7] = 0;
+    free(h); free(deg); free(nb); free(nbk); free(peel); free(newidx);
+    return ORC_OK;
+}
+
+/* Completion of reduced states: full [R][n] from reduced [R][n_free]. */
+int orc_tree_expand(int32_t n, const uint8_t *kind, const int8_t *value, const int32_t *parent,
+                    const int32_t *round, const int32_t *orig, int32_t n_free, int32_t rounds,
+                    const int8_t *reduced, int32_t R, int8_t *full)
+{
+    int32_t r, i, rd;
+    for (r = 0; r < R; ++r) {
+        int8_t *s = full + (size_t)r * n;
+        for (i = 0; i < n_free; ++i)
+            s[orig[i]] = reduced[(size_t)r * n_free + i];
+        for (rd = rounds - 1; rd >= 0; --rd)
+            for (i = 0; i < n; ++i)
+                if (round[i] == rd)
+                    s[i] = kind[i] == 1 ? value[i] : (int8_t)(value[i] * s[parent[i]]);
+    }
+    return ORC_OK;
 }

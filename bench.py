@@ -82,7 +82,7 @@ def main():
                     help="after timing, run one device copy of this size (counter calibration)")
     ap.add_argument("--workload", default="chimera8_sa",
                     choices=["chimera8_sa", "residual_batch", "cubic10_pt", "cubic20_pticm", "serving",
-                             "spvar_round", "multistart"])
+                             "spvar_round", "multistart", "spvar_tree"])
     ap.add_argument("--pt-runs", type=int, default=0, help="PT workloads: runs per step (0 = the config's)")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--serving-slots", type=int, default=8)
@@ -120,6 +120,8 @@ def main():
         return bench_spvar_round(args)
     if args.workload == "multistart":
         return bench_multistart(args)
+    if args.workload == "spvar_tree":
+        return bench_spvar_tree(args)
 
     cfg = cf.CHIMERA8_SA
     inst = cf.instance(cfg)
@@ -502,6 +504,92 @@ def bench_multistart(args):
                                "recombination over components"},
         "starts_per_s": round(S / dt, 2), "mean_free": round(float(n_free.mean()), 1),
         "mean_components": round(float(out["info"][:, 3].mean()), 1), "best_E": out["best_E"],
+    }
+    print(json.dumps(res), flush=True)
+
+
+def bench_spvar_tree(args):
+    """One SPVAR round with the tree pre-processing of Sec. II.C on the Chimera N=512 workload:
+    SA (10,000 reads x 2,000 sweeps) -> persistence (elite 5 %, threshold 0.95) -> tree /
+    degree-1 pre-processing of the residual -> SA on the peeled residual (same reads and
+    schedule) -> completion of every sample to the residual's variables."""
+    import numpy as np
+    import torch
+
+    import paper_1706_07826_amd as spv
+    from spvar_inputs import configs as cf
+
+    cfg = cf.CHIMERA8_SA
+    inst = cf.instance(cfg)
+    betas = cf.betas(cfg)
+    reads, sweeps = cfg["reads"], cfg["sweeps"]
+    ctx = spv.Context(0)
+    P = spv.Problem.from_instance(inst)
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        S, E = spv.spv_sample(ctx, P, betas, reads, cfg["seed"])
+        fx = spv.spv_persist_fix(ctx, P, S, E, cfg["elite"], cfg["theta"], cfg["gauge"])
+        red = fx.reduced()  # reads the sizes back (synchronises)
+        if ev is not None:
+            ev[0].record(stream)
+        tr = spv.spv_tree_reduce(ctx, red)
+        if ev is not None:
+            ev[1].record(stream)
+        core = tr.reduced()  # synchronises
+        RS, RE = spv.spv_sample(ctx, core, betas, reads, cfg["seed"] + 1)
+        if ev is not None:
+            ev[2].record(stream)
+        full = spv.spv_tree_complete(ctx, tr, RS)
+        if ev is not None:
+            ev[3].record(stream)
+        return dict(E=E, fx=fx, red=red, tr=tr, RE=RE, full=full)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        out = step(evs[k])
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    tree_us = float(np.mean([e[0].elapsed_time(e[1]) for e in evs])) * 1e3
+    complete_us = float(np.mean([e[2].elapsed_time(e[3]) for e in evs])) * 1e3
+    ti = out["tr"].info()
+    # the pre-processing alone on a larger tree-rich graph (N=8000, mean degree 1.5)
+    from spvar_inputs import random_sparse
+    big = spv.Problem.from_instance(random_sparse(8000, 1.5, seed=1))
+    bt = spv.spv_tree_reduce(ctx, big)
+    bt.info()
+
+    def back_to_back(prob, res, k=20):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(k):
+            spv.spv_tree_reduce(ctx, prob, out=res)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k * 1e3
+
+    big_us = back_to_back(big, bt)
+    res_us = back_to_back(out["red"], out["tr"])
+    updates = reads * sweeps * (inst.n + ti["n_free"])
+    off = out["fx"].info()["offset"] + ti["offset"]
+    res = {
+        "metric": BASELINE_METRIC, "value": round(updates / dt, 1), "unit": "spin-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic (seeded Chimera U{+-1..+-6} instance)",
+        "config": {"workload": "spvar_tree: chimera8 SA 10000 x 2000 -> persistence -> tree / degree-1 "
+                               "pre-processing of the residual -> SA on the peeled residual 10000 x 2000 -> "
+                               "completion"},
+        "residual_n": out["red"].n, "peeled": ti["n_removed"], "core_n": ti["n_free"], "tree_rounds": ti["rounds"],
+        "tree_call_us": round(tree_us, 2), "complete_call_us": round(complete_us, 2),
+        "tree_back_to_back_us": round(res_us, 2),
+        "tree_sparse8000_us": round(big_us, 2), "tree_sparse8000": bt.info(),
+        "best_E_first_sample": int(out["E"].min().item()),
+        "best_E_round": int(out["RE"].min().item()) + off,
     }
     print(json.dumps(res), flush=True)
 

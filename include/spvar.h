@@ -336,6 +336,52 @@ spv_status spv_multistart(spv_ctx *ctx, const spv_problem *P, const spv_multista
                           const spv_multistart_out *out, hipStream_t stream);
 
 /*
+ * Tree / degree-1 pre-processing (Sec. II.C): variables with at most one
+ * neighbour (over couplers J != 0) are removed in rounds.  In each round every
+ * remaining variable of degree <= 1 goes at once, except that of two variables
+ * joined only to each other the larger index goes first.  Degree 0: fixed to
+ * -sign(h) (+1 when h = 0).  Degree 1, neighbour j, coupler J: if |J| <= |h|
+ * fixed to -sign(h) and J s is folded into h_j; otherwise inferred, s =
+ * -sign(J) s_j, with -sign(J) h folded into h_j and -|J| into the offset.  The
+ * remaining variables (index order) with their updated biases form the
+ * reduced problem: E(s) = E'(s') + offset for every completion s of a reduced
+ * state s' (spv_tree_complete).  All outputs are device arrays:
+ *   kind [n]    0 remaining, 1 fixed, 2 inferred
+ *   value [n]   the fixed value, or the factor f of an inferred s = f * s_parent
+ *   parent [n]  the neighbour a removed degree-1 variable was folded into (-1: none)
+ *   round [n]   the round of its removal (-1: remaining)
+ *   order [n]   removed variables in removal order (rounds ascending)
+ *   row_ptr [n+1], col [nnz], J [nnz], h [n], colour [n], orig_index [n]:
+ *               the reduced problem (capacities of P)
+ *   info [8]    int64: n_free, nnz_free, offset, n_fixed, n_inferred, rounds,
+ *               0, n_removed
+ * One workgroup; O(n + nnz) work.
+ */
+typedef struct {
+    uint8_t *kind;
+    int8_t *value;
+    int32_t *parent;
+    int32_t *round;
+    int32_t *order;
+    int32_t *row_ptr;
+    int32_t *col;
+    int32_t *J;
+    int32_t *h;
+    uint8_t *colour;
+    int32_t *orig_index;
+    int64_t *info;
+} spv_tree_out;
+
+spv_status spv_tree_reduce(spv_ctx *ctx, const spv_problem *P, const spv_tree_out *out, hipStream_t stream);
+
+/* Completion of R reduced states reduced [R][n_free] (device) into full
+ * states full [R][n] (device): the reduced variables, then the removed ones
+ * in reverse removal order.  `t` is the output of spv_tree_reduce on a problem
+ * of n variables; n_free and n_removed are its info[0] and info[7]. */
+spv_status spv_tree_complete(spv_ctx *ctx, int32_t n, const spv_tree_out *t, int32_t n_free, int32_t n_removed,
+                             const int8_t *reduced, int32_t R, int8_t *full, hipStream_t stream);
+
+/*
  * Batched simulated annealing over B instances of uneven size (the residual
  * problems left after fixing, Sec. II.C / Sec. III.C) in ONE persistent
  * launch.  Work items (instance, block of 4*quads_per_item reads) are popped

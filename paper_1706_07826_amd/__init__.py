@@ -72,6 +72,11 @@ class spv_multistart_out(C.Structure):
                 ("best_E", C.c_void_p)]
 
 
+class spv_tree_out(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("kind", "value", "parent", "round", "order", "row_ptr", "col", "J", "h",
+                                          "colour", "orig_index", "info")]
+
+
 class spv_pt_out(C.Structure):
     _fields_ = [("final_spins", C.c_void_p), ("final_E", C.c_void_p), ("top_spins", C.c_void_p),
                 ("top_E", C.c_void_p), ("top_count", C.c_void_p)]
@@ -99,6 +104,8 @@ _SIGS = {
     "spv_components": ([_vp, _P, _vp, _vp, _vp], C.c_int),
     "spv_merge_components": ([_vp, _P, _vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp], C.c_int),
     "spv_multistart": ([_vp, _P, C.POINTER(spv_multistart_params), C.POINTER(spv_multistart_out), _vp], C.c_int),
+    "spv_tree_reduce": ([_vp, _P, C.POINTER(spv_tree_out), _vp], C.c_int),
+    "spv_tree_complete": ([_vp, _i32, C.POINTER(spv_tree_out), _i32, _i32, _vp, _i32, _vp, _vp], C.c_int),
 }
 EXPORTED = sorted(_SIGS)
 for _name, (_args, _res) in _SIGS.items():
@@ -392,6 +399,79 @@ def spv_multistart(ctx, P, betas, seed, starts, fixing_reads, solving_reads, eli
     res["best_spins"] = res["best_spins"][:n]
     res["best_E"] = int(best.value)
     return res
+
+
+class TreeResult:
+    """Device outputs of spv_tree_reduce; `info()` synchronises and reads the scalars."""
+
+    _KEYS = ("kind", "value", "parent", "round", "order", "row_ptr", "col", "J", "h", "colour", "orig_index", "info")
+
+    def __init__(self, ctx, P, keep):
+        self.ctx, self.parent_problem, self._keep = ctx, P, keep
+        self.out = spv_tree_out(*[keep[k].data_ptr() for k in self._KEYS])
+        n = P.n
+        self.kind, self.value = keep["kind"][:n], keep["value"][:n]
+        self.parent, self.round = keep["parent"][:n], keep["round"][:n]
+        self._info = None
+
+    def info(self):
+        if self._info is None:
+            torch.cuda.synchronize(self.ctx.device)
+            v = self._keep["info"].cpu().numpy()
+            self._info = dict(n_free=int(v[0]), nnz_free=int(v[1]), offset=int(v[2]), n_fixed=int(v[3]),
+                              n_inferred=int(v[4]), rounds=int(v[5]), n_removed=int(v[7]))
+        return self._info
+
+    @property
+    def order(self):
+        return self._keep["order"][:self.info()["n_removed"]]
+
+    @property
+    def orig_index(self):
+        return self._keep["orig_index"][:self.info()["n_free"]]
+
+    def reduced(self):
+        """The reduced problem as a device Problem (views into the output buffers).  Peeling never
+        raises a remaining variable's degree or its |h| + sum |J|, so the parent's bounds hold."""
+        i, k, P = self.info(), self._keep, self.parent_problem
+        return Problem(i["n_free"], i["nnz_free"], k["row_ptr"][:i["n_free"] + 1], k["col"], k["J"], k["h"],
+                       k["colour"], P.n_colours, P.scale_log2, P.max_degree, P.x_bound)
+
+
+def spv_tree_reduce(ctx, P, out=None, stream=None):
+    """Tree / degree-1 pre-processing (Sec. II.C) on the device; returns a TreeResult.  `out`: a
+    TreeResult of an earlier call on a problem of the same sizes, whose buffers are reused."""
+    if out is not None:
+        if out.parent_problem.n != P.n or out.parent_problem.nnz != P.nnz:
+            raise ValueError("spv_tree_reduce: `out` was made for other sizes")
+        res = TreeResult(ctx, P, out._keep)
+        ps = P.c_struct()
+        ctx.check(_lib.spv_tree_reduce(ctx.handle, C.byref(ps), C.byref(res.out), _stream(stream)),
+                  "spv_tree_reduce")
+        return res
+    dev, n, nnz = ctx.device, P.n, P.nnz
+    e = lambda m, dt: torch.empty(max(m, 1), dtype=dt, device=dev)
+    keep = dict(kind=e(n, torch.uint8), value=e(n, torch.int8), parent=e(n, torch.int32), round=e(n, torch.int32),
+                order=e(n, torch.int32), row_ptr=e(n + 1, torch.int32), col=e(nnz, torch.int32),
+                J=e(nnz, torch.int32), h=e(n, torch.int32), colour=e(n, torch.uint8), orig_index=e(n, torch.int32),
+                info=torch.zeros(8, dtype=torch.int64, device=dev))
+    res = TreeResult(ctx, P, keep)
+    ps = P.c_struct()
+    ctx.check(_lib.spv_tree_reduce(ctx.handle, C.byref(ps), C.byref(res.out), _stream(stream)), "spv_tree_reduce")
+    return res
+
+
+def spv_tree_complete(ctx, tree, reduced_spins, full=None, stream=None):
+    """Complete reduced states [R][n_free] (device int8) into full states [R][n] on the device."""
+    i, n = tree.info(), tree.parent_problem.n
+    R = int(reduced_spins.shape[0])
+    if full is None:
+        full = torch.empty((R, n), dtype=torch.int8, device=ctx.device)
+    rs = reduced_spins.contiguous()
+    ctx.check(_lib.spv_tree_complete(ctx.handle, n, C.byref(tree.out), i["n_free"], i["n_removed"],
+                                     _ptr(rs) if rs.numel() else None, R, _ptr(full) if full.numel() else None,
+                                     _stream(stream)), "spv_tree_complete")
+    return full
 
 
 def spv_sample_batch(ctx, problems, betas, reads, seeds, spins=None, energies=None, threads=0,

@@ -290,7 +290,7 @@ void spv_ctx_destroy(spv_ctx *ctx) {
     if (ctx->c.stage) (void)hipHostFree(ctx->c.stage);
     if (ctx->c.stage_done) (void)hipEventDestroy(ctx->c.stage_done);
     for (DevBuf *b : {&ctx->c.image, &ctx->c.tables, &ctx->c.tables2, &ctx->c.scratch, &ctx->c.scratch2,
-                      &ctx->c.rounds, &ctx->c.pt, &ctx->c.pt_tab, &ctx->c.top, &ctx->c.serve, &ctx->c.merge, &ctx->c.ms})
+                      &ctx->c.rounds, &ctx->c.pt, &ctx->c.pt_tab, &ctx->c.top, &ctx->c.serve, &ctx->c.merge, &ctx->c.ms, &ctx->c.tree})
         if (b->p) (void)hipFree(b->p);
     delete ctx;
 }
@@ -791,6 +791,42 @@ spv_status spv_merge_components(spv_ctx *ctx, const spv_problem *P, const int32_
     void *scratch = static_cast<unsigned char *>(c->merge.p) + 256;
     return hip_check(c, launch_merge(P, comp, n_comp, samples, R, merged, merged_E, part_E, scratch, stream),
                      "merge launch");
+}
+
+spv_status spv_tree_reduce(spv_ctx *ctx, const spv_problem *P, const spv_tree_out *out, hipStream_t stream) {
+    if (!ctx) return SPV_EINVAL;
+    Ctx *c = &ctx->c;
+    DeviceGuard g(c->device);
+    spv_status st = check_problem_host(c, P);
+    if (st) return st;
+    if (!out || !out->info || !out->row_ptr)
+        return set_err(c, SPV_EINVAL, "spv_tree_reduce: NULL output");
+    if (P->n > 0 && (!out->kind || !out->value || !out->parent || !out->round || !out->order || !out->h ||
+                     !out->colour || !out->orig_index || (P->nnz > 0 && (!out->col || !out->J))))
+        return set_err(c, SPV_EINVAL, "spv_tree_reduce: NULL output");
+    if (P->n == 0) {
+        const int64_t zero[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        hipError_t e = hipMemsetAsync(out->row_ptr, 0, 4, stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(out->info, zero, sizeof zero, hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        return hip_check(c, e, "tree reduce (empty)");
+    }
+    if (!tree_state_in_lds(P->n, c->lds_max) && (st = ensure(c, c->tree, tree_scratch_bytes(P->n)))) return st;
+    return hip_check(c, launch_tree_reduce(P, out, c->tree.p, c->lds_max, stream), "tree reduce launch");
+}
+
+spv_status spv_tree_complete(spv_ctx *ctx, int32_t n, const spv_tree_out *t, int32_t n_free, int32_t n_removed,
+                             const int8_t *reduced, int32_t R, int8_t *full, hipStream_t stream) {
+    if (!ctx) return SPV_EINVAL;
+    Ctx *c = &ctx->c;
+    DeviceGuard g(c->device);
+    if (!t || n < 0 || R < 0 || n_free < 0 || n_removed < 0 || n_free + n_removed != n)
+        return set_err(c, SPV_EINVAL, "spv_tree_complete: n=%d n_free=%d n_removed=%d R=%d", n, n_free, n_removed, R);
+    if (R == 0 || n == 0) return SPV_OK;
+    if (!full || (n_free > 0 && (!reduced || !t->orig_index)) ||
+        (n_removed > 0 && (!t->kind || !t->value || !t->parent || !t->order)))
+        return set_err(c, SPV_EINVAL, "spv_tree_complete: NULL buffer");
+    return hip_check(c, launch_tree_complete(n, t, n_free, n_removed, reduced, R, full, stream), "tree complete");
 }
 
 }  // extern "C"

@@ -69,6 +69,7 @@ struct Ctx {
     DevBuf serve;   // serving slot: assembled tempering sample
     DevBuf merge;   // component count and recombination scratch
     DevBuf ms;      // multi-start working set
+    DevBuf tree;    // tree pre-processing scratch
     TableCache tcache;
     std::vector<uint32_t> host_tables;
     void *batch_host = nullptr;  // pinned staging of descriptors and items
@@ -274,6 +275,14 @@ hipError_t launch_ms_best(const int64_t *fixE, const int64_t *solE, int S, int F
                           const int8_t *fix_spins, const int8_t *sol_spins, size_t sol_stride, const uint8_t *fmask,
                           const int8_t *fval, const int32_t *orig, size_t orig_stride, const int64_t *info,
                           int info_stride, int64_t *best, int8_t *best_spins, hipStream_t s);
+
+// Tree pre-processing (tree.hip).
+size_t tree_scratch_bytes(int n);
+bool tree_state_in_lds(int n, size_t lds_max);
+hipError_t launch_tree_reduce(const spv_problem *P, const spv_tree_out *out, void *scratch, size_t lds_max,
+                              hipStream_t s);
+hipError_t launch_tree_complete(int n, const spv_tree_out *t, int n_free, int n_removed, const int8_t *reduced, int R,
+                                int8_t *full, hipStream_t s);
 
 }  // namespace spv
 

@@ -13,6 +13,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device.hpp"
 #include "internal.hpp"
 #include "sa_core.hpp"
@@ -20,52 +22,71 @@
 namespace spv {
 namespace core {
 
+// Neighbour records of a site are contiguous (read 16 bytes at a time); the
+// per-site stride, in records, is even with an odd number of 16-byte units, so
+// that consecutive sites' blocks start in distinct LDS banks.
+__host__ __device__ constexpr int swar_rec_stride(int D) {
+    return (((D + 1) & ~1) / 2) % 2 == 1 ? ((D + 1) & ~1) : ((D + 1) & ~1) + 2;
+}
+
+// Acceptance tables sit at the start of the dynamic LDS, two buffers (this
+// sweep, next sweep), each indexed by x in [-kSwarTabHalf, kSwarTabHalf) so
+// that the row is read at x without clamping (entries below zero are never
+// decisive: x <= 0 always flips).  Fixed offsets let the address be 4x plus
+// an instruction immediate.
+constexpr int kSwarTabHalf = 256;
+constexpr int kSwarTabWords = 2 * kSwarTabHalf;
+
 struct SwarLds {
-    uint2 *rec;      // [D][n]: {offset of the neighbour row in S or ~S, |J| x 0x01010101}
-    int32_t *cpos;   // [n] h_p - sum_k |J_pk|
+    uint32_t *tab;   // [2][kSwarTabWords]
+    uint2 *rec;      // [n][stride]: {offset of the neighbour row in S or ~S, |J| x 0x01010101}
+    uint2 *co;       // [n] {(h_p - sum_k |J_pk|) in both 16-bit halves, original index}
     int32_t *hpos;   // [n]
-    int32_t *ord;    // [n]
-    uint32_t *tab;   // [2][row_len]
     uint32_t *S;     // [2][n][qw]: spins, then their complements
     unsigned long long *E2;  // [4*qw]
 };
 
 __host__ __device__ inline size_t swar_layout(int n, int D, int row_len, int qw, SwarLds *L,
                                               unsigned char *base, int e2q = 0) {
+    (void)row_len;
     if (e2q < qw) e2q = qw;
-    size_t o_rec = 0;
-    size_t o_c = o_rec + (size_t)n * D * 8;
-    size_t o_h = o_c + (size_t)n * 4;
-    size_t o_ord = o_h + (size_t)n * 4;
-    size_t o_tab = o_ord + (size_t)n * 4;
-    size_t o_S = o_tab + (size_t)2 * row_len * 4;
+    size_t o_tab = 0;
+    size_t o_rec = o_tab + (size_t)2 * kSwarTabWords * 4;
+    size_t o_co = o_rec + (size_t)n * swar_rec_stride(D) * 8;
+    size_t o_h = o_co + (size_t)n * 8;
+    size_t o_S = o_h + (size_t)n * 4;
     size_t o_E = (o_S + (size_t)2 * n * qw * 4 + 7) & ~(size_t)7;
     size_t end = o_E + (size_t)4 * e2q * 8;
     if (L) {
-        L->rec = reinterpret_cast<uint2 *>(base + o_rec);
-        L->cpos = reinterpret_cast<int32_t *>(base + o_c);
-        L->hpos = reinterpret_cast<int32_t *>(base + o_h);
-        L->ord = reinterpret_cast<int32_t *>(base + o_ord);
         L->tab = reinterpret_cast<uint32_t *>(base + o_tab);
+        L->rec = reinterpret_cast<uint2 *>(base + o_rec);
+        L->co = reinterpret_cast<uint2 *>(base + o_co);
+        L->hpos = reinterpret_cast<int32_t *>(base + o_h);
         L->S = reinterpret_cast<uint32_t *>(base + o_S);
         L->E2 = reinterpret_cast<unsigned long long *>(base + o_E);
     }
     return end;
 }
 
+__device__ __forceinline__ int32_t swar_cp(uint2 co) { return (int32_t)(int16_t)(co.x & 0xffffu); }
+
 // Expands the image's 32-bit records into byte-parallel records.  Ends with a barrier.
 __device__ inline void swar_load_instance(const SwarLds &L, const SaItem &a, int *cs) {
-    const int n = a.n, D = a.D, T = blockDim.x, tid = threadIdx.x;
+    const int n = a.n, D = a.D, T = blockDim.x, tid = threadIdx.x, Ds = swar_rec_stride(D);
     const int32_t *img = a.image;
     if (tid <= a.C) cs[tid] = img[3 + tid];
     const uint32_t *recs = reinterpret_cast<const uint32_t *>(img + kImgHeader + 3 * n);
     const uint32_t inv = (uint32_t)n * (uint32_t)a.qw;  // offset of ~S
-    for (int idx = tid; idx < n * D; idx += T) {
-        const int p = idx / D, k = idx - p * D;
-        const uint32_t r = recs[idx];
-        const int32_t J = (int32_t)(int16_t)(r & 0xffffu);
-        const uint32_t off = (r >> 16) * (uint32_t)a.qw + (J < 0 ? inv : 0u);
-        L.rec[(size_t)k * n + p] = make_uint2(off, (uint32_t)(J < 0 ? -J : J) * 0x01010101u);
+    for (int idx = tid; idx < n * Ds; idx += T) {
+        const int p = idx / Ds, k = idx - p * Ds;
+        uint2 v = make_uint2(0u, 0u);  // padding: offset 0, weight 0
+        if (k < D) {
+            const uint32_t r = recs[(size_t)p * D + k];
+            const int32_t J = (int32_t)(int16_t)(r & 0xffffu);
+            const uint32_t off = (r >> 16) * (uint32_t)a.qw + (J < 0 ? inv : 0u);
+            v = make_uint2(off, (uint32_t)(J < 0 ? -J : J) * 0x01010101u);
+        }
+        L.rec[idx] = v;
     }
     for (int p = tid; p < n; p += T) {
         int32_t s = 0;
@@ -74,9 +95,9 @@ __device__ inline void swar_load_instance(const SwarLds &L, const SaItem &a, int
             s += J < 0 ? -J : J;
         }
         const int32_t h = img[kImgHeader + 2 * n + p];
+        const uint32_t c16 = (uint32_t)(h - s) & 0xffffu;
         L.hpos[p] = h;
-        L.cpos[p] = h - s;
-        L.ord[p] = img[kImgHeader + p];
+        L.co[p] = make_uint2(c16 | (c16 << 16), (uint32_t)img[kImgHeader + p]);
     }
     __syncthreads();
 }
@@ -84,34 +105,35 @@ __device__ inline void swar_load_instance(const SwarLds &L, const SaItem &a, int
 // Neighbour records are read this many at a time (loads issued together).
 constexpr int kSwarBatch = 8;
 
-// Per byte, the sum of |J_k| over the neighbours agreeing with sign(J_k).
+// Per byte, the sum of |J_k| over the neighbours agreeing with sign(J_k); `rp` is
+// the site's record block, `Sq` the spin words shifted to this lane's column.
 // DK > 0: the record count is DK exactly (straight-line code); DK = 0: D at run time.
 template <int DK>
-__device__ __forceinline__ uint32_t swar_agree(const uint2 *__restrict__ rec, const uint32_t *__restrict__ S,
-                                               int D, int q, int n) {
+__device__ __forceinline__ uint32_t swar_agree(const uint2 *__restrict__ rp, const uint32_t *__restrict__ Sq,
+                                               int D) {
     if constexpr (DK > 0) {
-        uint2 r[DK];
+        constexpr int U = (DK + 1) / 2;
+        uint4 r[U];
 #pragma unroll
-        for (int u = 0; u < DK; ++u) r[u] = rec[(uint32_t)u * (uint32_t)n];
+        for (int u = 0; u < U; ++u) r[u] = reinterpret_cast<const uint4 *>(rp)[u];
         uint32_t w[DK];
 #pragma unroll
-        for (int u = 0; u < DK; ++u) w[u] = S[r[u].x + q];
+        for (int k = 0; k < DK; ++k) w[k] = Sq[(k & 1) ? r[k / 2].z : r[k / 2].x];
         uint32_t P = 0;
 #pragma unroll
-        for (int u = 0; u < DK; ++u) P += w[u] & r[u].y;
+        for (int k = 0; k < DK; ++k) P += w[k] & ((k & 1) ? r[k / 2].w : r[k / 2].y);
         return P;
     }
-    // 32-bit indices: LDS addresses are 32-bit, wider index arithmetic only costs VALU
     uint32_t P = 0;
     for (int k0 = 0; k0 < D; k0 += kSwarBatch) {
         uint2 r[kSwarBatch];
 #pragma unroll
         for (int u = 0; u < kSwarBatch; ++u)
-            if (k0 + u < D) r[u] = rec[(uint32_t)(k0 + u) * (uint32_t)n];
+            if (k0 + u < D) r[u] = rp[k0 + u];
         uint32_t w[kSwarBatch];
 #pragma unroll
         for (int u = 0; u < kSwarBatch; ++u)
-            if (k0 + u < D) w[u] = S[r[u].x + q];
+            if (k0 + u < D) w[u] = Sq[r[u].x];
 #pragma unroll
         for (int u = 0; u < kSwarBatch; ++u)
             if (k0 + u < D) P += w[u] & r[u].y;
@@ -124,19 +146,43 @@ __device__ __forceinline__ void swar_store(uint32_t *S, uint32_t idx, uint32_t i
     S[idx + inv] = ~w;
 }
 
+typedef unsigned short swar_u16x2 __attribute__((ext_vector_type(2)));
+typedef short swar_i16x2 __attribute__((ext_vector_type(2)));
+
+// x = -s * f for the four replicas of a word, as two pairs of int16 (replicas 0, 1 and 2, 3):
+// f = cp + 2 P_b fits 16 bits (|f| <= x_bound <= 255), and the spin byte masks, widened to
+// 16 bits, negate it where the spin is +1.
+__device__ __forceinline__ void swar_x16(uint32_t P, uint32_t self, uint32_t cp2, swar_i16x2 *lo, swar_i16x2 *hi) {
+    const uint32_t Plo = __builtin_amdgcn_perm(P, P, 0x0C010C00u);  // bytes P0, 0, P1, 0
+    const uint32_t Phi = __builtin_amdgcn_perm(P, P, 0x0C030C02u);  // bytes P2, 0, P3, 0
+    const uint32_t mlo = __builtin_amdgcn_perm(self, self, 0x01010000u);
+    const uint32_t mhi = __builtin_amdgcn_perm(self, self, 0x03030202u);
+    const swar_u16x2 c = __builtin_bit_cast(swar_u16x2, cp2);
+    const swar_u16x2 flo = __builtin_bit_cast(swar_u16x2, Plo) * (unsigned short)2 + c;
+    const swar_u16x2 fhi = __builtin_bit_cast(swar_u16x2, Phi) * (unsigned short)2 + c;
+    const swar_u16x2 ml = __builtin_bit_cast(swar_u16x2, mlo), mh = __builtin_bit_cast(swar_u16x2, mhi);
+    *lo = __builtin_bit_cast(swar_i16x2, (swar_u16x2)((flo ^ ml) - ml));
+    *hi = __builtin_bit_cast(swar_i16x2, (swar_u16x2)((fhi ^ mh) - mh));
+}
+
 template <int DK>
 __device__ void swar_run(const SwarLds &L, const SaItem &a, const int *cs) {
     const int n = a.n, D = a.D, qw = a.qw, T = blockDim.x, tid = threadIdx.x;
+    const int Ds = DK > 0 ? swar_rec_stride(DK) : swar_rec_stride(D);
     const int q0 = a.q0;
     const int q = tid % qw, slot = tid / qw, nslots = T / qw;
     const bool active = slot < nslots;
     const uint32_t inv = (uint32_t)n * (uint32_t)qw;
-    for (int k = tid; k < a.row_len; k += T) L.tab[k] = a.tables[k];
+    const uint32_t *Sq = L.S + q;
+    for (int k = tid; k < 2 * kSwarTabWords; k += T) {
+        const int i = k % kSwarTabWords - kSwarTabHalf;
+        L.tab[k] = (i >= 0 && k < kSwarTabWords && i < a.row_len) ? a.tables[i] : 0xFFFFFFFFu;
+    }
     for (int k = tid; k < 4 * qw; k += T) L.E2[k] = 0ull;
     if (a.init == nullptr) {
         for (int p = slot; active && p < n; p += nslots) {
             const dev::Words4 w =
-                dev::philox((uint32_t)L.ord[p], 0u, (uint32_t)(q0 + q), 1u << 24, a.k0, a.k1);
+                dev::philox(L.co[p].y, 0u, (uint32_t)(q0 + q), 1u << 24, a.k0, a.k1);
             uint32_t word = 0;
 #pragma unroll
             for (int b = 0; b < 4; ++b) word |= ((w.w[b] >> 31) ? 0xFFu : 0x00u) << (8 * b);
@@ -157,11 +203,13 @@ __device__ void swar_run(const SwarLds &L, const SaItem &a, const int *cs) {
     }
     __syncthreads();
 
-    for (int ls = 0; ls < a.sweeps; ++ls) {
+    // One sweep reading table buffer B (a compile-time constant) and filling the other.
+    auto sweep = [&](auto buf, int ls) {
+        constexpr int B = decltype(buf)::value;
         const uint32_t t = a.sweep_offset + (uint32_t)ls;
-        const uint32_t *tcur = L.tab + (ls & 1) * a.row_len;
+        const char *tz = reinterpret_cast<const char *>(L.tab + B * kSwarTabWords + kSwarTabHalf);
         if (ls + 1 < a.sweeps) {
-            uint32_t *tnext = L.tab + ((ls + 1) & 1) * a.row_len;
+            uint32_t *tnext = L.tab + (1 - B) * kSwarTabWords + kSwarTabHalf;
             for (int k = tid; k < a.row_len; k += T) tnext[k] = a.tables[(size_t)(ls + 1) * a.row_len + k];
         }
         for (int c = 0; c < a.C; ++c) {
@@ -169,43 +217,44 @@ __device__ void swar_run(const SwarLds &L, const SaItem &a, const int *cs) {
             for (int p = cs[c] + slot; active && p < pe; p += nslots) {
                 const uint32_t at = (uint32_t)p * (uint32_t)qw + (uint32_t)q;
                 const uint32_t self = L.S[at];
-                const uint32_t P = swar_agree<DK>(L.rec + p, L.S, D, q, n);
-                const int32_t cp = L.cpos[p];
-                int32_t x[4];
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const int32_t f = cp + 2 * (int32_t)((P >> (8 * b)) & 0xffu);
-                    const int32_t m = ((int32_t)(self << (24 - 8 * b))) >> 24;  // -1 for +1 spins
-                    x[b] = (f ^ m) - m;
-                }
-                const int32_t xm = max(max(x[0], x[1]), max(x[2], x[3]));
+                const uint32_t P = swar_agree<DK>(L.rec + (uint32_t)p * (uint32_t)Ds, Sq, D);
+                const uint2 co = L.co[p];
+                swar_i16x2 xlo, xhi;
+                swar_x16(P, self, co.x, &xlo, &xhi);
+                const swar_i16x2 xm = __builtin_elementwise_max(xlo, xhi);
                 uint32_t mask = 0xFFFFFFFFu;
-                if (xm > 0) {
-                    const dev::Words4 r =
-                        dev::philox((uint32_t)L.ord[p], t, (uint32_t)(q0 + q), 2u << 24, a.k0, a.k1);
-                    // branch-free: the row is read at max(x, 0), a valid index, for every byte
+                if (xm.x > 0 || xm.y > 0) {
+                    const dev::Words4 r = dev::philox(co.y, t, (uint32_t)(q0 + q), 2u << 24, a.k0, a.k1);
+                    // byte offsets 4x into the row (x may be <= 0: the entry is read and ignored)
+                    const swar_i16x2 olo = xlo << (short)2, ohi = xhi << (short)2;
+                    const int32_t o[4] = {olo.x, olo.y, ohi.x, ohi.y};
                     uint32_t th[4];
 #pragma unroll
-                    for (int b = 0; b < 4; ++b) th[b] = tcur[max(x[b], 0)];
+                    for (int b = 0; b < 4; ++b) th[b] = *reinterpret_cast<const uint32_t *>(tz + o[b]);
                     mask = 0;
 #pragma unroll
                     for (int b = 0; b < 4; ++b)
-                        mask |= (uint32_t)((x[b] <= 0) | (r.w[b] < th[b])) * (0xFFu << (8 * b));
+                        mask |= (uint32_t)((o[b] <= 0) | (r.w[b] < th[b])) * (0xFFu << (8 * b));
                 }
                 if (mask) swar_store(L.S, at, inv, self ^ mask);
             }
             __syncthreads();
         }
+    };
+    for (int ls = 0; ls < a.sweeps; ls += 2) {
+        sweep(std::integral_constant<int, 0>{}, ls);
+        if (ls + 1 < a.sweeps) sweep(std::integral_constant<int, 1>{}, ls + 1);
     }
 
     {
         long long e2[4] = {0, 0, 0, 0};
         for (int p = slot; active && p < n; p += nslots) {
             const uint32_t self = L.S[(size_t)p * qw + q];
-            const uint32_t P = swar_agree<DK>(L.rec + p, L.S, D, q, n);
+            const uint32_t P = swar_agree<DK>(L.rec + (uint32_t)p * (uint32_t)Ds, Sq, D);
+            const long long cp = swar_cp(L.co[p]);
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                const long long f = (long long)L.cpos[p] + 2 * (long long)((P >> (8 * b)) & 0xffu);
+                const long long f = cp + 2 * (long long)((P >> (8 * b)) & 0xffu);
                 const long long s = ((self >> (8 * b)) & 0xffu) ? 1 : -1;
                 e2[b] += s * ((long long)L.hpos[p] + f);
             }

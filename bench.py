@@ -55,17 +55,19 @@ def sources_digest(paths):
     return h.hexdigest()
 
 
-def profiled_traffic_bytes():
+def profiled_traffic_bytes(kernel):
     """HBM bytes per launch of the SA kernel from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE scaled by a copy of known size), or None
-    when any source of the kernel changed after the counters were taken."""
+    when the summary covers another kernel or any source of the kernel changed
+    after the counters were taken."""
+    base = kernel.split("<")[0]
     try:
-        with open(os.path.join(ROOT, "profiles", "sa_kernel_chimera8_sa.json")) as f:
+        with open(os.path.join(ROOT, "profiles", f"{base}_chimera8_sa.json")) as f:
             prof = json.load(f)
         digest = sources_digest(prof["sources"])
     except (OSError, KeyError, ValueError):
         return None
-    if not digest.startswith(prof["sources_sha256_prefix"]):
+    if prof.get("kernel") != kernel or not digest.startswith(prof["sources_sha256_prefix"]):
         return None
     kib = prof["fetch_kib"] * prof["fetch_scale"] + prof["write_kib"] * prof["write_scale"]
     return int(round(kib * 1024))
@@ -172,11 +174,18 @@ def main():
     byte_parallel = P.x_bound <= 255  # the library's rule for its byte-parallel body
     spu = slots_per_update(mean_deg, byte_parallel)
     achieved = updates * spu / (sa_ms / 1e3) / 1e12
+    shape = spv.spv_sample_last_shape(ctx)
+    dk = P.max_degree if P.max_degree in (4, 6, 8) else 0
+    if not byte_parallel:
+        kernel = "sa_kernel<1>"
+    elif shape["chunks"] > 1:
+        kernel = f"sa_stream_kernel<{dk}, {shape['words_per_lane']}>"
+    else:
+        kernel = f"sa_kernel<0, {dk}>" if dk else "sa_kernel<0>"
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_VALU_TSLOTS, 3),
                 "unit": "Tslot/s", "frac": round(achieved / PEAK_VALU_TSLOTS, 4),
-                "traffic": profiled_traffic_bytes(),
-                "kernel": (f"sa_kernel<0, {P.max_degree}>" if P.max_degree in (4, 6, 8) else "sa_kernel<0>")
-                if byte_parallel else "sa_kernel<1>", "kernel_ms": round(sa_ms, 4),
+                "traffic": profiled_traffic_bytes(kernel),
+                "kernel": kernel, "kernel_ms": round(sa_ms, 4), "launch": shape,
                 "slots_per_update": round(spu, 3)}
 
     cpu = None

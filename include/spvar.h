@@ -126,11 +126,23 @@ spv_status spv_problem_check(spv_ctx *ctx, const spv_problem *P);
  *   spins            device [reads][n] int8: final state of each read
  *   energies         device [reads] int64: E of each final state
  * The sample is the final state of every read (not the best seen).
+ * When the replicas need more workgroups than stay resident on the device, the
+ * launch is streamed: resident workgroups take (replica group, chunk of sweeps)
+ * tasks in order and carry each group's spins between chunks through context
+ * scratch; the sample is bit-identical to the one-launch schedule.  A streamed
+ * task waits (bounded) for its group's previous chunk; should a wait ever be
+ * abandoned, every read of that group reports energy INT64_MIN.
  */
 spv_status spv_sample(spv_ctx *ctx, const spv_problem *P, const double *betas, int32_t sweeps,
                       int32_t reads, uint64_t seed, uint32_t sweep_offset,
                       const int8_t *init_spins, int8_t *spins, int64_t *energies,
                       hipStream_t stream);
+
+/* The launch shape the last spv_sample call on this context used: threads per
+ * workgroup, quads (4 replicas) per workgroup, quad words per lane, and sweep
+ * chunks per group (1: one launch over all workgroups; more: streamed). */
+spv_status spv_sample_last_shape(const spv_ctx *ctx, int32_t *threads, int32_t *quads_per_wg,
+                                 int32_t *words_per_lane, int32_t *chunks);
 
 /* E(s) of R states: spins device [R][n] int8 +-1 -> energies device [R] int64. */
 spv_status spv_energy(spv_ctx *ctx, const spv_problem *P, const int8_t *spins, int32_t R,

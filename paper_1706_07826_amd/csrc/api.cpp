@@ -254,6 +254,25 @@ int sa_qw_env() {
     const char *v = getenv("SPVAR_SA_QW");
     return v ? atoi(v) : 0;
 }
+int sa_spin_env() {
+    const char *v = getenv("SPVAR_SA_SPIN");
+    const int k = v ? atoi(v) : 0;
+    return k > 0 ? k : (1 << 22);
+}
+// SPVAR_SA_STREAM=0: never stream; =<grid>: always stream on that many workgroups.
+bool sa_stream_env_off() {
+    const char *v = getenv("SPVAR_SA_STREAM");
+    return v && v[0] == '0';
+}
+int sa_stream_env_grid() {
+    const char *v = getenv("SPVAR_SA_STREAM");
+    const int g = v ? atoi(v) : 0;
+    return g > 0 ? g : 0;
+}
+int sa_wpl_env() {
+    const char *v = getenv("SPVAR_SA_WPL");
+    return v ? atoi(v) : 0;
+}
 
 }  // namespace spv
 
@@ -290,7 +309,7 @@ void spv_ctx_destroy(spv_ctx *ctx) {
     if (ctx->c.stage) (void)hipHostFree(ctx->c.stage);
     if (ctx->c.stage_done) (void)hipEventDestroy(ctx->c.stage_done);
     for (DevBuf *b : {&ctx->c.image, &ctx->c.tables, &ctx->c.tables2, &ctx->c.scratch, &ctx->c.scratch2,
-                      &ctx->c.rounds, &ctx->c.pt, &ctx->c.pt_tab, &ctx->c.top, &ctx->c.serve, &ctx->c.merge, &ctx->c.ms, &ctx->c.tree})
+                      &ctx->c.rounds, &ctx->c.pt, &ctx->c.pt_tab, &ctx->c.top, &ctx->c.serve, &ctx->c.merge, &ctx->c.ms, &ctx->c.tree, &ctx->c.sa_stream})
         if (b->p) (void)hipFree(b->p);
     delete ctx;
 }
@@ -400,24 +419,50 @@ spv_status spv_sample(spv_ctx *ctx, const spv_problem *P, const double *betas, i
     L.init = init_spins;
     L.out = spins;
     L.energies = energies;
-    // Launch shape: small workgroups (4 waves) with few quads each, so that
-    // several workgroups share a CU and hide each other's barriers.
-    // Measured on the Chimera 8x8 workload: the byte-parallel path is fastest
-    // with 2 quads per 512-thread workgroup, the general path with 1 quad per
-    // 256-thread workgroup.
+    // Launch shape: small workgroups with few quads each, so that several
+    // workgroups share a CU and hide each other's barriers.  Measured on the
+    // Chimera 8x8 workload: the byte-parallel path is fastest with 2 quads per
+    // 256-thread workgroup, each lane holding both words of its site; the
+    // general path with 1 quad per 256-thread workgroup.
     const bool swar = sa_use_swar(nd, row_len);
     int qw = sa_qw_env();
     if (qw <= 0) qw = swar ? 2 : 1;
     int threads = sa_threads_env();
-    if (threads <= 0) threads = swar ? 512 : 256;
+    if (threads <= 0) threads = 256;
     threads = std::max(64, std::min(1024, threads / qw * qw));
     while (qw > 1 && sa_lds_bytes(n, D, row_len, qw) + 256 > c->lds_max) --qw;
     if (sa_lds_bytes(n, D, row_len, qw) + 256 > c->lds_max)
         return set_err(c, SPV_ECAPACITY, "instance needs %zu B of LDS > %zu", sa_lds_bytes(n, D, row_len, qw), c->lds_max);
+    int wpl = sa_wpl_env();
+    if (wpl <= 0) wpl = 2;
     L.qw = qw;
-    L.threads = threads / qw * qw;
+    L.wpl = (swar && wpl == 2 && qw == 2) ? 2 : 1;
+    const int lanes_per_site = qw / L.wpl;
+    L.threads = std::max(lanes_per_site, threads / lanes_per_site * lanes_per_site);
+    L.spin_limit = sa_spin_env();
+    const int plan = sa_stream_env_off() ? 1 : sa_stream_plan(L, c->num_cus, sa_stream_env_grid());
+    c->last_sa_shape[0] = L.threads;
+    c->last_sa_shape[1] = L.qw;
+    c->last_sa_shape[2] = L.wpl;
+    c->last_sa_shape[3] = plan == 1 ? 1 : sa_stream_chunks_of(L, plan);
+    if (plan != 1) {
+        st = ensure(c, c->sa_stream, sa_stream_bytes(n, reads, qw));
+        if (st) return st;
+        e = launch_sa_stream(L, plan, c->sa_stream.p, stream);
+        return hip_check(c, e, "sa stream launch");
+    }
     e = launch_sa(L, stream, c->lds_max);
     return hip_check(c, e, "sa launch");
+}
+
+spv_status spv_sample_last_shape(const spv_ctx *ctx, int32_t *threads, int32_t *quads_per_wg,
+                                 int32_t *words_per_lane, int32_t *chunks) {
+    if (!ctx) return SPV_EINVAL;
+    if (threads) *threads = ctx->c.last_sa_shape[0];
+    if (quads_per_wg) *quads_per_wg = ctx->c.last_sa_shape[1];
+    if (words_per_lane) *words_per_lane = ctx->c.last_sa_shape[2];
+    if (chunks) *chunks = ctx->c.last_sa_shape[3];
+    return SPV_OK;
 }
 
 spv_status spv_persist_fix(spv_ctx *ctx, const spv_problem *P, const int8_t *samples,

@@ -163,7 +163,7 @@ __global__ __launch_bounds__(1024) void batch_sa_kernel(BatchArgs a) {
                 core::swar_load_instance(L, it, cs);
                 loaded = b;
             }
-            core::swar_run<DK>(L, it, cs);
+            core::swar_run<DK, 1>(L, it, cs);
         } else {
             if (b != loaded) {
                 core::sa_load_instance(L, it, cs);

@@ -70,6 +70,7 @@ struct Ctx {
     DevBuf merge;   // component count and recombination scratch
     DevBuf ms;      // multi-start working set
     DevBuf tree;    // tree pre-processing scratch
+    DevBuf sa_stream;  // streamed SA: task counter, tagged spin words between chunks
     TableCache tcache;
     std::vector<uint32_t> host_tables;
     void *batch_host = nullptr;  // pinned staging of descriptors and items
@@ -89,6 +90,7 @@ struct Ctx {
     };
     std::vector<TuneEntry> tuned;
     int last_shape[3] = {0, 0, 0};
+    int last_sa_shape[4] = {0, 0, 0, 0};  // spv_sample: threads, quads per workgroup, words per lane, chunks
     float last_tuned_ms = -1.f;
     // A context owned by one stream (serving slots) uploads tables
     // stream-ordered through pinned staging instead of draining the device.
@@ -148,8 +150,15 @@ struct SaLaunch {
     int64_t *energies;
     int qw;       // quads (4 replicas) per workgroup
     int threads;  // workgroup size
+    int wpl = 1;  // byte-parallel body: quad words per lane (2 needs qw = 2)
+    int spin_limit = 1 << 22;  // streamed launch: bounded wait for a group's previous chunk
 };
 hipError_t launch_sa(const SaLaunch &L, hipStream_t s, size_t lds_limit);
+// Streamed launch of the byte-parallel body (resident workgroups, chunked sweeps).
+int sa_stream_plan(const SaLaunch &L, int num_cus, int force_grid);  // 1: use launch_sa
+size_t sa_stream_bytes(int n, int reads, int qw);
+hipError_t launch_sa_stream(const SaLaunch &L, int plan, void *buf, hipStream_t s);
+int sa_stream_chunks_of(const SaLaunch &L, int plan);
 size_t sa_lds_bytes(int n, int D, int row_len, int qw);
 bool sa_use_swar(int nd, int row_len);
 

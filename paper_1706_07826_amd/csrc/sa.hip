@@ -16,6 +16,8 @@
 // every random word is used.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include "device.hpp"
 #include "internal.hpp"
 #include "sa_core.hpp"
@@ -118,13 +120,120 @@ __global__ __launch_bounds__(1024) void sa_kernel(core::SaItem a) {
         core::SwarLds L;
         core::swar_layout(a.n, a.D, a.row_len, a.qw, &L, smem);
         core::swar_load_instance(L, a, cs);
-        core::swar_run<DK>(L, a, cs);
+        if (a.wpl == 2 && a.qw == 2)
+            core::swar_run<DK, 2>(L, a, cs);
+        else
+            core::swar_run<DK, 1>(L, a, cs);
     } else {
         core::SaLds L;
         core::sa_layout(a.n, a.D, a.row_len, a.qw, &L, smem);
         core::sa_load_instance(L, a, cs);
         core::sa_run<ND>(L, a, cs);
     }
+}
+
+// Streamed byte-parallel SA: resident workgroups take (group of qw quads, chunk of
+// sweeps) tasks from a counter in chunk-major order, so that the replicas are
+// spread over the whole device however their count divides into workgroups.  A
+// group's spin words pass from one chunk to the next through global memory as
+// self-validating 64-bit words {spins, tag}, stored and polled with relaxed
+// device-scope atomics (tag = chunks done, plus an abandoned-wait bit; the
+// words are cleared before every launch), so no cache-wide fence is needed.  A
+// task polls (bounded) until every word of its group carries the previous
+// chunk's tag.  Every task uses the same counters as the one-launch schedule,
+// so the sample is bit-identical.
+struct StreamArgs {
+    core::SaItem a;
+    int G, K, Lc;    // groups, chunks per group, sweeps per chunk
+    int *counter;
+    unsigned long long *state;  // [G][n][qw] {spin word, tag}
+    int spin_limit;
+};
+
+constexpr uint32_t kTagPoison = 1u << 8;
+
+// Every branch of the task loop depends on wave-uniform values only (the task
+// index is read back with readfirstlane), so that no lane can be split from its
+// wave across loop iterations and barriers.
+template <int DK, int W>
+__global__ __launch_bounds__(1024) void sa_stream_kernel(StreamArgs s) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int cs[kMaxColours + 1];
+    __shared__ int task_s, late_s, poison_s;
+    core::SwarLds L;
+    core::swar_layout(s.a.n, s.a.D, s.a.row_len, s.a.qw, &L, smem);
+    core::swar_load_instance(L, s.a, cs);
+    const int ntask = s.G * s.K, T = blockDim.x, tid = threadIdx.x;
+    const int words = s.a.n * s.a.qw;
+    const uint32_t inv = (uint32_t)words;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    for (;;) {
+        if (wave == 0) {
+            // one increment per workgroup: lane 0 adds 1, the others 0
+            const int v = __hip_atomic_fetch_add(s.counter, threadIdx.x == 0 ? 1 : 0, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+            if (threadIdx.x == 0) {
+                task_s = v;
+                late_s = 0;
+                poison_s = 0;
+            }
+        }
+        __syncthreads();
+        const int tau = __builtin_amdgcn_readfirstlane(task_s);
+        if (tau >= ntask) break;
+        const int g = tau % s.G, k = tau / s.G;
+        unsigned long long *st = s.state + (size_t)g * (size_t)words;
+        if (k > 0) {
+            // resume: every word must carry this launch's tag for k chunks done
+            const uint32_t want = (uint32_t)k;
+            bool late = false, poison = false;
+            for (int w = tid; w < words; w += T) {
+                unsigned long long v = 0;
+                for (int spins = 0;; ++spins) {
+                    v = __hip_atomic_load(st + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (((uint32_t)(v >> 32) & ~kTagPoison) == want) break;
+                    if (spins >= s.spin_limit) {
+                        late = true;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+                poison |= ((uint32_t)(v >> 32) & kTagPoison) != 0;
+                const uint32_t word = (uint32_t)v;
+                L.S[w] = word;
+                L.S[w + inv] = ~word;
+            }
+            if (late) late_s = 1;
+            if (poison) poison_s = 1;
+        }
+        __syncthreads();
+        const bool poisoned = (__builtin_amdgcn_readfirstlane(late_s) | __builtin_amdgcn_readfirstlane(poison_s)) != 0;
+        const bool late = __builtin_amdgcn_readfirstlane(late_s) != 0;
+        core::SaItem it = s.a;
+        it.q0 = g * s.a.qw;
+        core::SwarChunk ch;
+        ch.ls0 = k * s.Lc;
+        ch.count = min(s.Lc, s.a.sweeps - ch.ls0);
+        // An abandoned wait restarts the group from its initial state: words that may
+        // still be in flight are not used.
+        ch.resume = k > 0 && !late;
+        ch.keep = k + 1 < s.K;
+        ch.poisoned = poisoned;
+        core::swar_run<DK, W>(L, it, cs, ch);  // ends with a barrier
+        if (ch.keep) {
+            const uint32_t tag = (poisoned ? kTagPoison : 0u) | (uint32_t)(k + 1);
+            for (int w = tid; w < words; w += T)
+                __hip_atomic_store(st + w, ((unsigned long long)tag << 32) | L.S[w], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// Task counter and tags back to zero (no word then matches a chunk tag >= 1).
+__global__ void stream_reset_kernel(int *counter, unsigned long long *state, size_t words) {
+    const size_t i0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i0 == 0) *counter = 0;
+    for (size_t i = i0; i < words; i += (size_t)gridDim.x * blockDim.x) state[i] = 0ull;
 }
 
 // Energies of arbitrary states: one workgroup per 64 rows... one thread per (row, variable).
@@ -209,6 +318,7 @@ hipError_t launch_sa(const SaLaunch &L, hipStream_t s, size_t lds_limit) {
     a.q0 = 0;
     a.qw = L.qw;
     a.sweep_offset = L.sweep_offset;
+    a.wpl = (L.wpl == 2 && L.qw == 2) ? 2 : 1;
     a.k0 = (uint32_t)L.seed;
     a.k1 = (uint32_t)(L.seed >> 32);
     const size_t lds = sa_lds_bytes(L.n, L.D, L.row_len, L.qw);
@@ -238,6 +348,122 @@ hipError_t launch_sa(const SaLaunch &L, hipStream_t s, size_t lds_limit) {
         default:
             return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+template <int DK, int W>
+static hipError_t stream_occupancy(int threads, size_t lds, int *per_cu) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, sa_stream_kernel<DK, W>, threads, lds);
+}
+
+// Chunks per group: the fewest (sweeps per chunk >= kStreamMinSweeps) whose tasks
+// fill the resident workgroups to kStreamFill, else the best filling count.  Every
+// chunk boundary moves a group's spin words through global memory once each way.
+static int stream_chunks(int G, int sweeps, int resident) {
+    constexpr int kStreamMinSweeps = 64, kStreamMaxChunks = 32;
+    constexpr double kStreamFill = 0.985;
+    int best = 1;
+    double best_eff = 0.0;
+    for (int K = 1; K <= kStreamMaxChunks && (K == 1 || sweeps / K >= kStreamMinSweeps); ++K) {
+        const long long tasks = (long long)G * K;
+        const long long rounds = (tasks + resident - 1) / resident;
+        const double eff = (double)tasks / (double)(rounds * resident);
+        if (eff >= kStreamFill) return K;
+        if (eff > best_eff + 1e-3) {
+            best_eff = eff;
+            best = K;
+        }
+    }
+    return best;
+}
+
+size_t sa_stream_bytes(int n, int reads, int qw) {
+    const size_t G = (size_t)((reads + 3) / 4 + qw - 1) / (size_t)qw;
+    return 256 + G * (size_t)n * (size_t)qw * 8;
+}
+
+// Chunks per group for a streamed launch of L, or 1 when the plain launch is used
+// (not the byte-parallel body, one wave of workgroups covers the replicas, or a
+// short schedule).
+int sa_stream_plan(const SaLaunch &L, int num_cus, int force_grid) {
+    if (!sa_use_swar(L.nd, L.row_len)) return 1;
+    if (force_grid > 0) {  // tests: a given grid, chunk dependencies whatever the shape
+        const int K = std::max(2, std::min(32, L.sweeps / 16));
+        return L.sweeps >= 2 ? (K | (force_grid << 8)) : 1;
+    }
+    if (L.sweeps < 128) return 1;
+    const int quads = (L.reads + 3) / 4;
+    const int G = (quads + L.qw - 1) / L.qw;
+    const int W = (L.wpl == 2 && L.qw == 2) ? 2 : 1;
+    const size_t lds = sa_lds_bytes(L.n, L.D, L.row_len, L.qw);
+    const int dk = (L.D == 6 || L.D == 4 || L.D == 8) ? L.D : 0;
+    int per_cu = 0;
+    hipError_t e;
+#define SPV_OCC(D_, W_) e = stream_occupancy<D_, W_>(L.threads, lds, &per_cu)
+    if (W == 2) {
+        if (dk == 6) SPV_OCC(6, 2); else if (dk == 4) SPV_OCC(4, 2); else if (dk == 8) SPV_OCC(8, 2); else SPV_OCC(0, 2);
+    } else {
+        if (dk == 6) SPV_OCC(6, 1); else if (dk == 4) SPV_OCC(4, 1); else if (dk == 8) SPV_OCC(8, 1); else SPV_OCC(0, 1);
+    }
+#undef SPV_OCC
+    const int resident = per_cu * num_cus;
+    if (e != hipSuccess || resident <= 0 || G <= resident) return 1;
+    const char *kv = getenv("SPVAR_SA_CHUNKS");  // tuning: a fixed chunk count
+    const int K = kv && atoi(kv) > 0 ? std::min(255, atoi(kv)) : stream_chunks(G, L.sweeps, resident);
+    return K <= 1 ? 1 : (K | (resident << 8));
+}
+
+int sa_stream_chunks_of(const SaLaunch &L, int plan) {
+    const int K0 = plan & 0xff;
+    const int Lc = (L.sweeps + K0 - 1) / K0;
+    return (L.sweeps + Lc - 1) / Lc;
+}
+
+hipError_t launch_sa_stream(const SaLaunch &L, int plan, void *buf, hipStream_t s) {
+    const int K0 = plan & 0xff, resident = plan >> 8;
+    const int quads = (L.reads + 3) / 4;
+    const int G = (quads + L.qw - 1) / L.qw;
+    const int W = (L.wpl == 2 && L.qw == 2) ? 2 : 1;
+    const size_t lds = sa_lds_bytes(L.n, L.D, L.row_len, L.qw);
+    const int dk = (L.D == 6 || L.D == 4 || L.D == 8) ? L.D : 0;
+    StreamArgs a;
+    a.a.image = L.image;
+    a.a.tables = L.tables;
+    a.a.init = L.init;
+    a.a.out = L.out;
+    a.a.energies = L.energies;
+    a.a.n = L.n;
+    a.a.D = L.D;
+    a.a.C = L.C;
+    a.a.row_len = L.row_len;
+    a.a.sweeps = L.sweeps;
+    a.a.reads = L.reads;
+    a.a.q0 = 0;
+    a.a.qw = L.qw;
+    a.a.sweep_offset = L.sweep_offset;
+    a.a.k0 = (uint32_t)L.seed;
+    a.a.k1 = (uint32_t)(L.seed >> 32);
+    a.a.wpl = W;
+    a.G = G;
+    a.Lc = (L.sweeps + K0 - 1) / K0;
+    a.K = (L.sweeps + a.Lc - 1) / a.Lc;
+    unsigned char *b = static_cast<unsigned char *>(buf);
+    a.counter = reinterpret_cast<int *>(b);
+    a.state = reinterpret_cast<unsigned long long *>(b + 256);
+    a.spin_limit = L.spin_limit;
+    const size_t words = (size_t)G * (size_t)L.n * (size_t)L.qw;
+    const int rgrid = (int)std::min<size_t>(1024, std::max<size_t>(1, (words + 255) / 256));
+    hipLaunchKernelGGL(stream_reset_kernel, dim3(rgrid), dim3(256), 0, s, a.counter, a.state, words);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int grid = std::min(resident, G * a.K);
+#define SPV_GO(D_, W_) hipLaunchKernelGGL((sa_stream_kernel<D_, W_>), dim3(grid), dim3(L.threads), lds, s, a)
+    if (W == 2) {
+        if (dk == 6) SPV_GO(6, 2); else if (dk == 4) SPV_GO(4, 2); else if (dk == 8) SPV_GO(8, 2); else SPV_GO(0, 2);
+    } else {
+        if (dk == 6) SPV_GO(6, 1); else if (dk == 4) SPV_GO(4, 1); else if (dk == 8) SPV_GO(8, 1); else SPV_GO(0, 1);
+    }
+#undef SPV_GO
     return hipGetLastError();
 }
 

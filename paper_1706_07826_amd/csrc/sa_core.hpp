@@ -64,6 +64,7 @@ struct SaItem {
     int64_t *energies;       // [reads]
     int n, D, C, row_len, sweeps, reads, q0, qw;
     uint32_t sweep_offset, k0, k1;
+    int wpl = 1;  // byte-parallel body: quad words per lane (1, or 2 when qw = 2)
 };
 
 struct Fields {

@@ -13,6 +13,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
 #include <type_traits>
 
 #include "device.hpp"
@@ -37,12 +38,31 @@ __host__ __device__ constexpr int swar_rec_stride(int D) {
 constexpr int kSwarTabHalf = 256;
 constexpr int kSwarTabWords = 2 * kSwarTabHalf;
 
+// The spin words follow the tables.  A record holds the neighbour word's LDS
+// address itself, so that a lane holding its site's whole row reads it with
+// no address arithmetic.
+constexpr size_t kSwarSOffset = (size_t)2 * kSwarTabWords * 4;
+
+typedef unsigned int swar_v2u __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) const uint32_t swar_lds_u32;
+typedef __attribute__((address_space(3))) const swar_v2u swar_lds_v2u;
+
+// The 32-bit LDS address of a shared-memory object.
+__device__ __forceinline__ uint32_t swar_lds_addr(const void *p) {
+    return (uint32_t)(uintptr_t)(__attribute__((address_space(3))) const void *)p;
+}
+__device__ __forceinline__ uint32_t swar_ld32(uint32_t a) { return *(swar_lds_u32 *)(uintptr_t)a; }
+__device__ __forceinline__ uint2 swar_ld64(uint32_t a) {
+    const swar_v2u v = *(swar_lds_v2u *)(uintptr_t)a;
+    return make_uint2(v.x, v.y);
+}
+
 struct SwarLds {
     uint32_t *tab;   // [2][kSwarTabWords]
-    uint2 *rec;      // [n][stride]: {offset of the neighbour row in S or ~S, |J| x 0x01010101}
-    uint2 *co;       // [n] {(h_p - sum_k |J_pk|) in both 16-bit halves, original index}
-    int32_t *hpos;   // [n]
     uint32_t *S;     // [2][n][qw]: spins, then their complements
+    uint2 *rec;      // [n][stride]: {LDS address of the neighbour row in S or ~S, |J| x 0x01010101}
+    uint2 *co;       // [n] {4 (h_p - sum_k |J_pk|) in both 16-bit halves, original index}
+    int32_t *hpos;   // [n]
     unsigned long long *E2;  // [4*qw]
 };
 
@@ -51,24 +71,24 @@ __host__ __device__ inline size_t swar_layout(int n, int D, int row_len, int qw,
     (void)row_len;
     if (e2q < qw) e2q = qw;
     size_t o_tab = 0;
-    size_t o_rec = o_tab + (size_t)2 * kSwarTabWords * 4;
+    size_t o_S = kSwarSOffset;
+    size_t o_rec = (o_S + (size_t)2 * n * qw * 4 + 15) & ~(size_t)15;
     size_t o_co = o_rec + (size_t)n * swar_rec_stride(D) * 8;
     size_t o_h = o_co + (size_t)n * 8;
-    size_t o_S = o_h + (size_t)n * 4;
-    size_t o_E = (o_S + (size_t)2 * n * qw * 4 + 7) & ~(size_t)7;
+    size_t o_E = (o_h + (size_t)n * 4 + 7) & ~(size_t)7;
     size_t end = o_E + (size_t)4 * e2q * 8;
     if (L) {
         L->tab = reinterpret_cast<uint32_t *>(base + o_tab);
+        L->S = reinterpret_cast<uint32_t *>(base + o_S);
         L->rec = reinterpret_cast<uint2 *>(base + o_rec);
         L->co = reinterpret_cast<uint2 *>(base + o_co);
         L->hpos = reinterpret_cast<int32_t *>(base + o_h);
-        L->S = reinterpret_cast<uint32_t *>(base + o_S);
         L->E2 = reinterpret_cast<unsigned long long *>(base + o_E);
     }
     return end;
 }
 
-__device__ __forceinline__ int32_t swar_cp(uint2 co) { return (int32_t)(int16_t)(co.x & 0xffffu); }
+__device__ __forceinline__ int32_t swar_cp(uint2 co) { return ((int32_t)(int16_t)(co.x & 0xffffu)) / 4; }
 
 // Expands the image's 32-bit records into byte-parallel records.  Ends with a barrier.
 __device__ inline void swar_load_instance(const SwarLds &L, const SaItem &a, int *cs) {
@@ -77,14 +97,15 @@ __device__ inline void swar_load_instance(const SwarLds &L, const SaItem &a, int
     if (tid <= a.C) cs[tid] = img[3 + tid];
     const uint32_t *recs = reinterpret_cast<const uint32_t *>(img + kImgHeader + 3 * n);
     const uint32_t inv = (uint32_t)n * (uint32_t)a.qw;  // offset of ~S
+    const uint32_t sb = swar_lds_addr(L.S);
     for (int idx = tid; idx < n * Ds; idx += T) {
         const int p = idx / Ds, k = idx - p * Ds;
-        uint2 v = make_uint2(0u, 0u);  // padding: offset 0, weight 0
+        uint2 v = make_uint2(sb, 0u);  // padding: a valid address, weight 0
         if (k < D) {
             const uint32_t r = recs[(size_t)p * D + k];
             const int32_t J = (int32_t)(int16_t)(r & 0xffffu);
             const uint32_t off = (r >> 16) * (uint32_t)a.qw + (J < 0 ? inv : 0u);
-            v = make_uint2(off, (uint32_t)(J < 0 ? -J : J) * 0x01010101u);
+            v = make_uint2(sb + 4u * off, (uint32_t)(J < 0 ? -J : J) * 0x01010101u);
         }
         L.rec[idx] = v;
     }
@@ -95,7 +116,7 @@ __device__ inline void swar_load_instance(const SwarLds &L, const SaItem &a, int
             s += J < 0 ? -J : J;
         }
         const int32_t h = img[kImgHeader + 2 * n + p];
-        const uint32_t c16 = (uint32_t)(h - s) & 0xffffu;
+        const uint32_t c16 = (uint32_t)(4 * (h - s)) & 0xffffu;
         L.hpos[p] = h;
         L.co[p] = make_uint2(c16 | (c16 << 16), (uint32_t)img[kImgHeader + p]);
     }
@@ -105,40 +126,52 @@ __device__ inline void swar_load_instance(const SwarLds &L, const SaItem &a, int
 // Neighbour records are read this many at a time (loads issued together).
 constexpr int kSwarBatch = 8;
 
-// Per byte, the sum of |J_k| over the neighbours agreeing with sign(J_k); `rp` is
-// the site's record block, `Sq` the spin words shifted to this lane's column.
-// DK > 0: the record count is DK exactly (straight-line code); DK = 0: D at run time.
-template <int DK>
-__device__ __forceinline__ uint32_t swar_agree(const uint2 *__restrict__ rp, const uint32_t *__restrict__ Sq,
-                                               int D) {
+// Per byte, the sum of |J_k| over the neighbours agreeing with sign(J_k), for the
+// W consecutive quad words of this lane; `rp` is the site's record block and `qb`
+// the byte offset of this lane's first column (0 when W = 2).  DK > 0: the record
+// count is DK exactly (straight-line code); DK = 0: D at run time.
+template <int DK, int W>
+__device__ __forceinline__ void swar_agree(const uint2 *__restrict__ rp, uint32_t qb, int D, uint32_t (&P)[W]) {
+    auto word = [&](uint32_t addr, uint32_t (&w)[W]) {
+        if constexpr (W == 2) {
+            const uint2 v = swar_ld64(addr);
+            w[0] = v.x;
+            w[1] = v.y;
+        } else {
+            w[0] = swar_ld32(addr + qb);
+        }
+    };
+#pragma unroll
+    for (int b = 0; b < W; ++b) P[b] = 0;
     if constexpr (DK > 0) {
         constexpr int U = (DK + 1) / 2;
         uint4 r[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) r[u] = reinterpret_cast<const uint4 *>(rp)[u];
-        uint32_t w[DK];
+        uint32_t w[DK][W];
 #pragma unroll
-        for (int k = 0; k < DK; ++k) w[k] = Sq[(k & 1) ? r[k / 2].z : r[k / 2].x];
-        uint32_t P = 0;
+        for (int k = 0; k < DK; ++k) word((k & 1) ? r[k / 2].z : r[k / 2].x, w[k]);
 #pragma unroll
-        for (int k = 0; k < DK; ++k) P += w[k] & ((k & 1) ? r[k / 2].w : r[k / 2].y);
-        return P;
+        for (int k = 0; k < DK; ++k)
+#pragma unroll
+            for (int b = 0; b < W; ++b) P[b] += w[k][b] & ((k & 1) ? r[k / 2].w : r[k / 2].y);
+        return;
     }
-    uint32_t P = 0;
     for (int k0 = 0; k0 < D; k0 += kSwarBatch) {
         uint2 r[kSwarBatch];
 #pragma unroll
         for (int u = 0; u < kSwarBatch; ++u)
             if (k0 + u < D) r[u] = rp[k0 + u];
-        uint32_t w[kSwarBatch];
+        uint32_t w[kSwarBatch][W];
 #pragma unroll
         for (int u = 0; u < kSwarBatch; ++u)
-            if (k0 + u < D) w[u] = Sq[r[u].x];
+            if (k0 + u < D) word(r[u].x, w[u]);
 #pragma unroll
         for (int u = 0; u < kSwarBatch; ++u)
-            if (k0 + u < D) P += w[u] & r[u].y;
+            if (k0 + u < D)
+#pragma unroll
+                for (int b = 0; b < W; ++b) P[b] += w[u][b] & r[u].y;
     }
-    return P;
 }
 
 __device__ __forceinline__ void swar_store(uint32_t *S, uint32_t idx, uint32_t inv, uint32_t w) {
@@ -149,45 +182,69 @@ __device__ __forceinline__ void swar_store(uint32_t *S, uint32_t idx, uint32_t i
 typedef unsigned short swar_u16x2 __attribute__((ext_vector_type(2)));
 typedef short swar_i16x2 __attribute__((ext_vector_type(2)));
 
-// x = -s * f for the four replicas of a word, as two pairs of int16 (replicas 0, 1 and 2, 3):
-// f = cp + 2 P_b fits 16 bits (|f| <= x_bound <= 255), and the spin byte masks, widened to
-// 16 bits, negate it where the spin is +1.
+// 4x = -4 s f for the four replicas of a word, as two pairs of int16 (replicas 0, 1 and 2, 3):
+// 4f = 4 cp + 8 P_b fits 16 bits (|f| <= x_bound <= 255), and the spin byte masks, widened to
+// 16 bits, negate it where the spin is +1.  `cp2` holds 4 cp in both halves.
 __device__ __forceinline__ void swar_x16(uint32_t P, uint32_t self, uint32_t cp2, swar_i16x2 *lo, swar_i16x2 *hi) {
     const uint32_t Plo = __builtin_amdgcn_perm(P, P, 0x0C010C00u);  // bytes P0, 0, P1, 0
     const uint32_t Phi = __builtin_amdgcn_perm(P, P, 0x0C030C02u);  // bytes P2, 0, P3, 0
     const uint32_t mlo = __builtin_amdgcn_perm(self, self, 0x01010000u);
     const uint32_t mhi = __builtin_amdgcn_perm(self, self, 0x03030202u);
     const swar_u16x2 c = __builtin_bit_cast(swar_u16x2, cp2);
-    const swar_u16x2 flo = __builtin_bit_cast(swar_u16x2, Plo) * (unsigned short)2 + c;
-    const swar_u16x2 fhi = __builtin_bit_cast(swar_u16x2, Phi) * (unsigned short)2 + c;
+    const swar_u16x2 flo = __builtin_bit_cast(swar_u16x2, Plo) * (unsigned short)8 + c;
+    const swar_u16x2 fhi = __builtin_bit_cast(swar_u16x2, Phi) * (unsigned short)8 + c;
     const swar_u16x2 ml = __builtin_bit_cast(swar_u16x2, mlo), mh = __builtin_bit_cast(swar_u16x2, mhi);
     *lo = __builtin_bit_cast(swar_i16x2, (swar_u16x2)((flo ^ ml) - ml));
     *hi = __builtin_bit_cast(swar_i16x2, (swar_u16x2)((fhi ^ mh) - mh));
 }
 
-template <int DK>
-__device__ void swar_run(const SwarLds &L, const SaItem &a, const int *cs) {
-    const int n = a.n, D = a.D, qw = a.qw, T = blockDim.x, tid = threadIdx.x;
+// A contiguous range of sweeps of one workgroup's replicas.  The whole schedule
+// is one chunk; a streamed launch splits it, carrying the spin words between
+// chunks through global memory.
+struct SwarChunk {
+    int ls0 = 0;             // first sweep
+    int count = -1;          // sweeps (-1: to the end of the schedule)
+    bool resume = false;     // the caller has put the spin words (S and ~S) in LDS
+    bool keep = false;       // leave the spin words in LDS for the caller (not the last chunk)
+    bool poisoned = false;   // last chunk: a wait for an earlier chunk was abandoned
+};
+
+// Energy written for every read of a workgroup whose chunks lost their order.
+constexpr long long kSwarPoisonEnergy = INT64_MIN;
+
+// W = quad words per lane: 1, or 2 when qw = 2 and a lane holds its site's whole
+// row (the neighbour addresses are then the records' offsets as they stand).
+template <int DK, int W>
+__device__ void swar_run(const SwarLds &L, const SaItem &a, const int *cs, const SwarChunk &ch = SwarChunk()) {
+    static_assert(W == 1 || W == 2, "one or two words per lane");
+    const int n = a.n, D = a.D, qw = W == 2 ? 2 : a.qw, T = blockDim.x, tid = threadIdx.x;
     const int Ds = DK > 0 ? swar_rec_stride(DK) : swar_rec_stride(D);
     const int q0 = a.q0;
-    const int q = tid % qw, slot = tid / qw, nslots = T / qw;
+    const int lps = qw / W;  // lanes per site
+    const int qa = W == 2 ? 0 : tid % lps, slot = tid / lps, nslots = T / lps;
     const bool active = slot < nslots;
     const uint32_t inv = (uint32_t)n * (uint32_t)qw;
-    const uint32_t *Sq = L.S + q;
+    const uint32_t qb = 4u * (uint32_t)qa;
+    const int ls0 = ch.ls0, lsend = ch.count < 0 ? a.sweeps : ls0 + ch.count;
     for (int k = tid; k < 2 * kSwarTabWords; k += T) {
         const int i = k % kSwarTabWords - kSwarTabHalf;
-        L.tab[k] = (i >= 0 && k < kSwarTabWords && i < a.row_len) ? a.tables[i] : 0xFFFFFFFFu;
+        L.tab[k] = (i >= 0 && k < kSwarTabWords && i < a.row_len && ls0 < lsend)
+                       ? a.tables[(size_t)ls0 * a.row_len + i]
+                       : 0xFFFFFFFFu;
     }
     for (int k = tid; k < 4 * qw; k += T) L.E2[k] = 0ull;
-    if (a.init == nullptr) {
-        for (int p = slot; active && p < n; p += nslots) {
-            const dev::Words4 w =
-                dev::philox(L.co[p].y, 0u, (uint32_t)(q0 + q), 1u << 24, a.k0, a.k1);
-            uint32_t word = 0;
+    if (ch.resume) {
+        // spin words already in LDS
+    } else if (a.init == nullptr) {
+        for (int p = slot; active && p < n; p += nslots)
 #pragma unroll
-            for (int b = 0; b < 4; ++b) word |= ((w.w[b] >> 31) ? 0xFFu : 0x00u) << (8 * b);
-            swar_store(L.S, (uint32_t)p * (uint32_t)qw + (uint32_t)q, inv, word);
-        }
+            for (int b = 0; b < W; ++b) {
+                const dev::Words4 w = dev::philox(L.co[p].y, 0u, (uint32_t)(q0 + qa + b), 1u << 24, a.k0, a.k1);
+                uint32_t word = 0;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) word |= ((w.w[e] >> 31) ? 0xFFu : 0x00u) << (8 * e);
+                swar_store(L.S, (uint32_t)p * (uint32_t)qw + (uint32_t)(qa + b), inv, word);
+            }
     } else {
         const int32_t *pos_of = a.image + kImgHeader + n;
         unsigned char *Sb = reinterpret_cast<unsigned char *>(L.S);
@@ -208,65 +265,91 @@ __device__ void swar_run(const SwarLds &L, const SaItem &a, const int *cs) {
         constexpr int B = decltype(buf)::value;
         const uint32_t t = a.sweep_offset + (uint32_t)ls;
         const char *tz = reinterpret_cast<const char *>(L.tab + B * kSwarTabWords + kSwarTabHalf);
-        if (ls + 1 < a.sweeps) {
+        if (ls + 1 < lsend) {
             uint32_t *tnext = L.tab + (1 - B) * kSwarTabWords + kSwarTabHalf;
             for (int k = tid; k < a.row_len; k += T) tnext[k] = a.tables[(size_t)(ls + 1) * a.row_len + k];
         }
         for (int c = 0; c < a.C; ++c) {
             const int pe = cs[c + 1];
             for (int p = cs[c] + slot; active && p < pe; p += nslots) {
-                const uint32_t at = (uint32_t)p * (uint32_t)qw + (uint32_t)q;
-                const uint32_t self = L.S[at];
-                const uint32_t P = swar_agree<DK>(L.rec + (uint32_t)p * (uint32_t)Ds, Sq, D);
+                const uint32_t at = (uint32_t)p * (uint32_t)qw + (uint32_t)qa;
+                uint32_t self[W];
+                if constexpr (W == 2) {
+                    const uint2 v = *reinterpret_cast<const uint2 *>(L.S + at);
+                    self[0] = v.x;
+                    self[1] = v.y;
+                } else {
+                    self[0] = L.S[at];
+                }
+                uint32_t P[W];
+                swar_agree<DK, W>(L.rec + (uint32_t)p * (uint32_t)Ds, qb, D, P);
                 const uint2 co = L.co[p];
-                swar_i16x2 xlo, xhi;
-                swar_x16(P, self, co.x, &xlo, &xhi);
-                const swar_i16x2 xm = __builtin_elementwise_max(xlo, xhi);
-                uint32_t mask = 0xFFFFFFFFu;
-                if (xm.x > 0 || xm.y > 0) {
-                    const dev::Words4 r = dev::philox(co.y, t, (uint32_t)(q0 + q), 2u << 24, a.k0, a.k1);
+                uint32_t mask[W];
+#pragma unroll
+                for (int b = 0; b < W; ++b) {
+                    swar_i16x2 xlo, xhi;  // 4x
+                    swar_x16(P[b], self[b], co.x, &xlo, &xhi);
+                    // Random words are drawn for every replica; x <= 0 flips regardless of them.
+                    const dev::Words4 r = dev::philox(co.y, t, (uint32_t)(q0 + qa + b), 2u << 24, a.k0, a.k1);
                     // byte offsets 4x into the row (x may be <= 0: the entry is read and ignored)
-                    const swar_i16x2 olo = xlo << (short)2, ohi = xhi << (short)2;
-                    const int32_t o[4] = {olo.x, olo.y, ohi.x, ohi.y};
+                    const int32_t o[4] = {xlo.x, xlo.y, xhi.x, xhi.y};
                     uint32_t th[4];
 #pragma unroll
-                    for (int b = 0; b < 4; ++b) th[b] = *reinterpret_cast<const uint32_t *>(tz + o[b]);
-                    mask = 0;
+                    for (int e = 0; e < 4; ++e) th[e] = *reinterpret_cast<const uint32_t *>(tz + o[e]);
+                    uint32_t m = 0;
 #pragma unroll
-                    for (int b = 0; b < 4; ++b)
-                        mask |= (uint32_t)((o[b] <= 0) | (r.w[b] < th[b])) * (0xFFu << (8 * b));
+                    for (int e = 0; e < 4; ++e) m |= (uint32_t)((o[e] <= 0) | (r.w[e] < th[e])) * (0xFFu << (8 * e));
+                    mask[b] = m;
                 }
-                if (mask) swar_store(L.S, at, inv, self ^ mask);
+                if constexpr (W == 2) {
+                    if (mask[0] | mask[1]) {
+                        const uint2 v = make_uint2(self[0] ^ mask[0], self[1] ^ mask[1]);
+                        *reinterpret_cast<uint2 *>(L.S + at) = v;
+                        *reinterpret_cast<uint2 *>(L.S + at + inv) = make_uint2(~v.x, ~v.y);
+                    }
+                } else {
+                    if (mask[0]) swar_store(L.S, at, inv, self[0] ^ mask[0]);
+                }
             }
             __syncthreads();
         }
     };
-    for (int ls = 0; ls < a.sweeps; ls += 2) {
+    for (int ls = ls0; ls < lsend; ls += 2) {
         sweep(std::integral_constant<int, 0>{}, ls);
-        if (ls + 1 < a.sweeps) sweep(std::integral_constant<int, 1>{}, ls + 1);
+        if (ls + 1 < lsend) sweep(std::integral_constant<int, 1>{}, ls + 1);
+    }
+    if (ch.keep) {
+        __syncthreads();
+        return;
     }
 
     {
-        long long e2[4] = {0, 0, 0, 0};
+        long long e2[W][4] = {};
         for (int p = slot; active && p < n; p += nslots) {
-            const uint32_t self = L.S[(size_t)p * qw + q];
-            const uint32_t P = swar_agree<DK>(L.rec + (uint32_t)p * (uint32_t)Ds, Sq, D);
-            const long long cp = swar_cp(L.co[p]);
+            uint32_t P[W];
+            swar_agree<DK, W>(L.rec + (uint32_t)p * (uint32_t)Ds, qb, D, P);
+            const long long cp = swar_cp(L.co[p]), hp = L.hpos[p];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const long long f = cp + 2 * (long long)((P >> (8 * b)) & 0xffu);
-                const long long s = ((self >> (8 * b)) & 0xffu) ? 1 : -1;
-                e2[b] += s * ((long long)L.hpos[p] + f);
+            for (int b = 0; b < W; ++b) {
+                const uint32_t self = L.S[(uint32_t)p * (uint32_t)qw + (uint32_t)(qa + b)];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const long long f = cp + 2 * (long long)((P[b] >> (8 * e)) & 0xffu);
+                    const long long s = ((self >> (8 * e)) & 0xffu) ? 1 : -1;
+                    e2[b][e] += s * (hp + f);
+                }
             }
         }
         if (active)
 #pragma unroll
-            for (int b = 0; b < 4; ++b) atomicAdd(&L.E2[q * 4 + b], (unsigned long long)e2[b]);
+            for (int b = 0; b < W; ++b)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) atomicAdd(&L.E2[(qa + b) * 4 + e], (unsigned long long)e2[b][e]);
     }
     __syncthreads();
     for (int rl = tid; rl < 4 * qw; rl += T) {
         const int r = 4 * q0 + rl;
-        if (r < a.reads) a.energies[r] = ((long long)L.E2[rl]) / 2;
+        if (r < a.reads) a.energies[r] = ch.poisoned ? kSwarPoisonEnergy : ((long long)L.E2[rl]) / 2;
     }
     const int32_t *pos_of = a.image + kImgHeader + n;
     const unsigned char *Sb = reinterpret_cast<const unsigned char *>(L.S);

@@ -120,3 +120,75 @@ def test_ispvar_parity_cubic4_config(spv, ctx):
     assert np.array_equal(res["round_info"], ores["round_info"])
     assert np.array_equal(res["fixed_mask"].cpu().numpy(), ores["fixed_mask"])
     assert np.array_equal(res["fixed_val"].cpu().numpy(), ores["fixed_val"])
+
+
+def _with_env(env, fn):
+    import os
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update({k: str(v) for k, v in env.items()})
+    try:
+        return fn()
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+@pytest.mark.parametrize("shape", [{}, {"SPVAR_SA_WPL": 1, "SPVAR_SA_THREADS": 512}], ids=["w2", "w1"])
+def test_sa_streamed_launch_equals_plain(spv, ctx, shape):
+    """Chimera N=512, 10,000 reads (more workgroups than stay resident): the streamed launch
+    (chunks of sweeps through global memory) and the plain launch give identical samples."""
+    cfg = cf.CHIMERA8_SA
+    inst = cf.instance(cfg)
+    betas = cf.betas(cfg)[::7]  # 286 sweeps: several chunks, the last one shorter
+    P = spv.Problem.from_instance(inst)
+    _say(f"[sa] streamed vs plain {shape}: {cfg['reads']} reads x {len(betas)} sweeps")
+    run = lambda: [t.cpu().numpy() for t in spv.spv_sample(ctx, P, betas, cfg["reads"], 99)]
+    s1, e1 = _with_env(dict(shape), run)
+    s0, e0 = _with_env(dict(shape, SPVAR_SA_STREAM=0), run)
+    assert np.array_equal(s1, s0) and np.array_equal(e1, e0)
+    osp, oE = oracle.sa_sample(inst, betas, seed=99, r_begin=9990, r_end=10000)
+    assert np.array_equal(s1[9990:], osp) and np.array_equal(e1[9990:], oE)
+
+
+def test_sa_streamed_launch_waits_for_earlier_chunks(spv, ctx):
+    """A grid larger than the task front: tasks wait for their group's previous chunk
+    (release/acquire flags); the sample equals the oracle's, ragged reads included."""
+    inst = si.cubic_lattice(4, "pm1", seed=5)
+    betas = si.linear_betas(0.1, 3.0, 200)
+    P = spv.Problem.from_instance(inst)
+    _say("[sa] streamed launch with dependent chunks: 30 reads, grid 16")
+    S, E = _with_env({"SPVAR_SA_STREAM": 16}, lambda: spv.spv_sample(ctx, P, betas, 30, 1234))
+    osp, oE = oracle.sa_sample(inst, betas, reads=30, seed=1234)
+    assert np.array_equal(S.cpu().numpy(), osp) and np.array_equal(E.cpu().numpy(), oE)
+
+
+def test_sa_streamed_launch_abandoned_wait_is_marked(spv, ctx):
+    """With a wait limit of one poll, a task that finds its group's previous chunk unfinished
+    gives up; the kernel still ends and every read of such a group reports INT64_MIN."""
+    inst = si.cubic_lattice(4, "pm1", seed=5)
+    betas = si.linear_betas(0.1, 3.0, 200)
+    P = spv.Problem.from_instance(inst)
+    _say("[sa] streamed launch, wait limit 1")
+    S, E = _with_env({"SPVAR_SA_STREAM": 16, "SPVAR_SA_SPIN": 1},
+                     lambda: spv.spv_sample(ctx, P, betas, 30, 1234))
+    osp, oE = oracle.sa_sample(inst, betas, reads=30, seed=1234)
+    E = E.cpu().numpy()
+    marked = E == np.iinfo(np.int64).min
+    assert np.all(marked | (E == oE))
+    assert set(np.unique(S.cpu().numpy())).issubset({-1, 1})
+
+
+@pytest.mark.parametrize("name,make,reads,sweeps,br", SMALL[:6], ids=[c[0] for c in SMALL[:6]])
+def test_sa_parity_small_one_word_per_lane(spv, ctx, name, make, reads, sweeps, br):
+    """The byte-parallel body with one quad word per lane (two lanes per site) against the oracle."""
+    inst = make()
+    betas = si.linear_betas(br[0], br[1], sweeps)
+    P = spv.Problem.from_instance(inst)
+    seed = 4242
+    _say(f"[sa] {name} one word per lane")
+    sp, E = _with_env({"SPVAR_SA_WPL": 1, "SPVAR_SA_THREADS": 512}, lambda: spv.spv_sample(ctx, P, betas, reads, seed))
+    osp, oE = oracle.sa_sample(inst, betas, reads=reads, seed=seed, threads=8)
+    assert np.array_equal(sp.cpu().numpy(), osp) and np.array_equal(E.cpu().numpy(), oE)

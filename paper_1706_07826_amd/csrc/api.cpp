@@ -420,21 +420,24 @@ spv_status spv_sample(spv_ctx *ctx, const spv_problem *P, const double *betas, i
     L.out = spins;
     L.energies = energies;
     // Launch shape: small workgroups with few quads each, so that several
-    // workgroups share a CU and hide each other's barriers.  Measured on the
-    // Chimera 8x8 workload: the byte-parallel path is fastest with 2 quads per
-    // 256-thread workgroup, each lane holding both words of its site; the
-    // general path with 1 quad per 256-thread workgroup.
+    // workgroups share a CU and hide each other's barriers.  Measured: when the
+    // workgroups outnumber the CUs (Chimera 8x8, 10,000 reads) the byte-parallel
+    // path is fastest with 2 quads per 256-thread workgroup, each lane holding both
+    // words of its site (fewer instructions per update); when they do not fill the
+    // device (residual problems, 1,000 reads) two lanes per site (2 quads per
+    // 512-thread workgroup) finish sooner.  The general path: 1 quad per 256 threads.
     const bool swar = sa_use_swar(nd, row_len);
+    const bool saturated = ((reads + 3) / 4 + 1) / 2 > c->num_cus;
     int qw = sa_qw_env();
     if (qw <= 0) qw = swar ? 2 : 1;
     int threads = sa_threads_env();
-    if (threads <= 0) threads = 256;
+    if (threads <= 0) threads = (swar && !saturated) ? 512 : 256;
     threads = std::max(64, std::min(1024, threads / qw * qw));
     while (qw > 1 && sa_lds_bytes(n, D, row_len, qw) + 256 > c->lds_max) --qw;
     if (sa_lds_bytes(n, D, row_len, qw) + 256 > c->lds_max)
         return set_err(c, SPV_ECAPACITY, "instance needs %zu B of LDS > %zu", sa_lds_bytes(n, D, row_len, qw), c->lds_max);
     int wpl = sa_wpl_env();
-    if (wpl <= 0) wpl = 2;
+    if (wpl <= 0) wpl = saturated ? 2 : 1;
     L.qw = qw;
     L.wpl = (swar && wpl == 2 && qw == 2) ? 2 : 1;
     const int lanes_per_site = qw / L.wpl;

@@ -182,13 +182,14 @@ def test_sa_streamed_launch_abandoned_wait_is_marked(spv, ctx):
 
 
 @pytest.mark.parametrize("name,make,reads,sweeps,br", SMALL[:6], ids=[c[0] for c in SMALL[:6]])
-def test_sa_parity_small_one_word_per_lane(spv, ctx, name, make, reads, sweeps, br):
-    """The byte-parallel body with one quad word per lane (two lanes per site) against the oracle."""
+def test_sa_parity_small_two_words_per_lane(spv, ctx, name, make, reads, sweeps, br):
+    """The byte-parallel body with both quad words of a site in one lane (the shape used when
+    the workgroups outnumber the CUs), forced on small cases, against the oracle."""
     inst = make()
     betas = si.linear_betas(br[0], br[1], sweeps)
     P = spv.Problem.from_instance(inst)
     seed = 4242
-    _say(f"[sa] {name} one word per lane")
-    sp, E = _with_env({"SPVAR_SA_WPL": 1, "SPVAR_SA_THREADS": 512}, lambda: spv.spv_sample(ctx, P, betas, reads, seed))
+    _say(f"[sa] {name} two words per lane")
+    sp, E = _with_env({"SPVAR_SA_WPL": 2, "SPVAR_SA_THREADS": 256}, lambda: spv.spv_sample(ctx, P, betas, reads, seed))
     osp, oE = oracle.sa_sample(inst, betas, reads=reads, seed=seed, threads=8)
     assert np.array_equal(sp.cpu().numpy(), osp) and np.array_equal(E.cpu().numpy(), oE)

@@ -40,6 +40,31 @@ SA_PROFILE_SOURCES = ["paper_1706_07826_amd/csrc/sa.hip", "paper_1706_07826_amd/
                       "paper_1706_07826_amd/csrc/sa_core.hpp", "paper_1706_07826_amd/csrc/device.hpp"]
 
 
+def sa_lds_bytes_per_update(D, words_per_lane):
+    """LDS bytes a byte-parallel SA update moves (read + flip write), from its access
+    pattern: per lane and site visit, the D neighbour records (8 B each), the neighbour
+    spin words, the lane's own words, the site constants (8 B), one threshold word per
+    replica (4 B) and the flipped words with their complements; W quad words per lane."""
+    W = words_per_lane
+    per_visit = 8 * D + 4 * W * D + 4 * W + 8 + 16 * W + 8 * W
+    return per_visit / (4.0 * W)
+
+
+def pt_lds_bytes_per_update(D, digits, records_in_lds):
+    """LDS bytes a tempering Metropolis update moves: per quad task the own word, the D
+    neighbour words, one threshold word per replica and digit, the flip write, and the
+    D records when the instance is LDS-resident."""
+    per_task = 4 + 4 * D + 16 * digits + 4 + (4 * D if records_in_lds else 0)
+    return per_task / 4.0
+
+
+def lds_object(updates_per_s, bytes_per_update, probe_bytes_per_s, note):
+    achieved = updates_per_s * bytes_per_update
+    return {"bytes_per_update": round(bytes_per_update, 2), "achieved_TBps": round(achieved / 1e12, 3),
+            "probe_peak_TBps": round(probe_bytes_per_s / 1e12, 3),
+            "frac": round(achieved / probe_bytes_per_s, 4), "note": note}
+
+
 def slots_per_update(mean_degree, byte_parallel):
     per_neighbour = 0.5 if byte_parallel else 1.0
     return mean_degree * per_neighbour + 4 + PHILOX_SLOTS / 4.0
@@ -187,6 +212,11 @@ def main():
                 "traffic": profiled_traffic_bytes(kernel),
                 "kernel": kernel, "kernel_ms": round(sa_ms, 4), "launch": shape,
                 "slots_per_update": round(spu, 3)}
+    if byte_parallel:
+        probe = spv.spv_lds_probe(ctx)
+        roofline["lds"] = lds_object(updates / (sa_ms / 1e3),
+                                     sa_lds_bytes_per_update(P.max_degree, shape["words_per_lane"]), probe,
+                                     "competing bound: LDS traffic of the sweep against the measured LDS peak")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -312,6 +342,12 @@ def bench_pt(args, cfg, label):
         "config": {"workload": label.format(runs=runs)},
         "spvar_solves_per_s": round(1 / dt, 4), "fixed_per_solve": fx.info()["n_fixed"],
     }
+    # the Metropolis part of the sweep against the measured LDS peak (the cluster moves and
+    # the exchange add latency-bound work on top; records are LDS-resident at N = 1000)
+    nd = 2 if P.x_bound > 511 else 1
+    probe = spv.spv_lds_probe(ctx)
+    out["lds"] = lds_object(updates / dt, pt_lds_bytes_per_update(P.max_degree, nd, inst.n <= 4096), probe,
+                            "Metropolis LDS traffic of the whole step against the measured LDS peak")
     print(json.dumps(out), flush=True)
 
 

@@ -138,6 +138,13 @@ spv_status spv_sample(spv_ctx *ctx, const spv_problem *P, const double *betas, i
                       const int8_t *init_spins, int8_t *spins, int64_t *energies,
                       hipStream_t stream);
 
+/* Device LDS read bandwidth in bytes/s, measured by a probe kernel (two
+ * 1024-thread workgroups per CU reading bank-conflict-free 16-byte words; one
+ * timed launch of `iters` x 4 reads per lane after one warm-up launch).  The
+ * measured denominator of the LDS rooflines of the sweeps.  Synchronous on
+ * `stream`; uses context scratch.  EINVAL for iters outside [1, 2^24]. */
+spv_status spv_lds_probe(spv_ctx *ctx, int32_t iters, double *bytes_per_s, hipStream_t stream);
+
 /* The launch shape the last spv_sample call on this context used: threads per
  * workgroup, quads (4 replicas) per workgroup, quad words per lane, and sweep
  * chunks per group (1: one launch over all workgroups; more: streamed). */

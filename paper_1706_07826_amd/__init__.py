@@ -101,6 +101,7 @@ _SIGS = {
     "spv_sample_batch": ([_vp, _i32, _P, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "spv_batch_last_shape": ([_vp, _vp, _vp, _vp, _vp], C.c_int),
     "spv_sample_last_shape": ([_vp, _vp, _vp, _vp, _vp], C.c_int),
+    "spv_lds_probe": ([_vp, _i32, _vp, _vp], C.c_int),
     "spv_top_sample": ([_vp, _vp, _vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp], C.c_int),
     "spv_components": ([_vp, _P, _vp, _vp, _vp], C.c_int),
     "spv_merge_components": ([_vp, _P, _vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp], C.c_int),
@@ -229,6 +230,13 @@ def spv_sample_last_shape(ctx):
     v = [C.c_int32(0) for _ in range(4)]
     ctx.check(_lib.spv_sample_last_shape(ctx.handle, *[C.byref(x) for x in v]), "spv_sample_last_shape")
     return dict(threads=v[0].value, quads_per_wg=v[1].value, words_per_lane=v[2].value, chunks=v[3].value)
+
+
+def spv_lds_probe(ctx, iters=20000, stream=None):
+    """Measured LDS read bandwidth of the device, bytes/s."""
+    v = C.c_double(0.0)
+    ctx.check(_lib.spv_lds_probe(ctx.handle, int(iters), C.byref(v), _stream(stream)), "spv_lds_probe")
+    return v.value
 
 
 def spv_energy(ctx, P, spins, energies=None, stream=None):

@@ -841,6 +841,17 @@ spv_status spv_merge_components(spv_ctx *ctx, const spv_problem *P, const int32_
                      "merge launch");
 }
 
+spv_status spv_lds_probe(spv_ctx *ctx, int32_t iters, double *bytes_per_s, hipStream_t stream) {
+    if (!ctx || !bytes_per_s) return SPV_EINVAL;
+    Ctx *c = &ctx->c;
+    DeviceGuard g(c->device);
+    if (iters < 1 || iters > (1 << 24)) return set_err(c, SPV_EINVAL, "spv_lds_probe: iters=%d", iters);
+    spv_status st = ensure(c, c->scratch2, (size_t)2 * c->num_cus * 4);
+    if (st) return st;
+    return hip_check(c, run_lds_probe(iters, c->num_cus, static_cast<uint32_t *>(c->scratch2.p), bytes_per_s, stream),
+                     "lds probe");
+}
+
 spv_status spv_tree_reduce(spv_ctx *ctx, const spv_problem *P, const spv_tree_out *out, hipStream_t stream) {
     if (!ctx) return SPV_EINVAL;
     Ctx *c = &ctx->c;

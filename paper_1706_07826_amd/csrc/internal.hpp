@@ -285,6 +285,10 @@ hipError_t launch_ms_best(const int64_t *fixE, const int64_t *solE, int S, int F
                           const int8_t *fval, const int32_t *orig, size_t orig_stride, const int64_t *info,
                           int info_stride, int64_t *best, int8_t *best_spins, hipStream_t s);
 
+// LDS read-bandwidth probe (probe.hip): synchronous on `s`; `out` receives at most
+// 2 * num_cus words.
+hipError_t run_lds_probe(int iters, int num_cus, uint32_t *out, double *bytes_per_s, hipStream_t s);
+
 // Tree pre-processing (tree.hip).
 size_t tree_scratch_bytes(int n);
 bool tree_state_in_lds(int n, size_t lds_max);

@@ -193,3 +193,21 @@ def test_sa_parity_small_two_words_per_lane(spv, ctx, name, make, reads, sweeps,
     sp, E = _with_env({"SPVAR_SA_WPL": 2, "SPVAR_SA_THREADS": 256}, lambda: spv.spv_sample(ctx, P, betas, reads, seed))
     osp, oE = oracle.sa_sample(inst, betas, reads=reads, seed=seed, threads=8)
     assert np.array_equal(sp.cpu().numpy(), osp) and np.array_equal(E.cpu().numpy(), oE)
+
+
+def test_sa_streamed_launch_resumes_from_states(spv, ctx):
+    """A streamed launch that starts from caller states at a sweep offset (resume) gives the
+    oracle's sample."""
+    import torch
+
+    inst = si.chimera(3, seed=21)
+    betas = si.linear_betas(0.1, 3.0, 300)
+    P = spv.Problem.from_instance(inst)
+    reads = 50
+    init = si.random_spins(reads, inst.n, seed=22)
+    _say("[sa] streamed resume: 50 reads from caller states, sweep offset 40, grid 8")
+    S, E = _with_env({"SPVAR_SA_STREAM": 8},
+                     lambda: spv.spv_sample(ctx, P, betas[40:], reads, 555, sweep_offset=40,
+                                            init_spins=torch.as_tensor(init).cuda()))
+    osp, oE = oracle.sa_sample(inst, betas[40:], reads=reads, seed=555, sweep_offset=40, init=init)
+    assert np.array_equal(S.cpu().numpy(), osp) and np.array_equal(E.cpu().numpy(), oE)

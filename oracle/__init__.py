@@ -70,6 +70,7 @@ def lib():
                                       vp, vp]
         L.orc_ispvar.argtypes = [vp, vp, i32, i32, u64, i32, f64, f64, i32, vp, vp, vp]
         L.orc_icm_step.argtypes = [vp, vp, vp, vp, vp, u32, vp]
+        L.orc_colour_jp.argtypes = [vp, u64, vp, vp, i32]
         L.orc_icm_step.restype = C.c_int
         L.orc_swap_test.argtypes = [i64, f64, i32, u32, u32, u32, u64]
         L.orc_swap_test.restype = C.c_int
@@ -371,6 +372,18 @@ def multistart(inst, betas, seed, starts, fixing_reads, solving_reads, elite_fra
     out["best_E"] = int(best.value)
     out["best_spins"] = out["best_spins"][:n]
     return out
+
+
+def colour_jp(inst, seed=0, max_colours=16):
+    """Colour classes by Jones-Plassmann rounds with Philox priorities.  Returns
+    (colour uint8[n], n_colours); raises OracleError (ERANGE) past max_colours."""
+    b = _Bound(inst)
+    colour = np.zeros(max(inst.n, 1), np.uint8)
+    nc = C.c_int32(0)
+    rc = lib().orc_colour_jp(b.ref, C.c_uint64(seed & (2**64 - 1)), _ptr(colour), C.byref(nc), int(max_colours))
+    if rc != 0:
+        raise OracleError(rc, "colour_jp")
+    return colour[:inst.n], nc.value
 
 
 def tree_peel(inst):

@@ -87,6 +87,14 @@
  *    0's fixing rows, start 0's solving rows, start 1's fixing rows, ...; a
  *    solving row is completed with the start's fixed values.
  *
+ *  Colour classes (the sweep's independent sets; not a step the paper states:
+ *    the parallel sweep needs them).  Jones-Plassmann: vertex v has priority
+ *    (word 0 of Philox(v, 0, 0, 5 << 24) under the seed, then v), higher
+ *    first; in each round every uncoloured vertex whose priority exceeds that
+ *    of all its uncoloured neighbours (every CSR entry is an edge) takes the
+ *    smallest colour no coloured neighbour has.  The result equals first-fit
+ *    greedy colouring in decreasing priority order.
+ *
  *  Tree pre-processing (Sec. II.C): the degree of a remaining variable counts
  *    its couplers with J != 0 to remaining variables.  In every round all
  *    remaining variables of degree <= 1 are removed at once, except that of
@@ -1391,5 +1399,74 @@ int orc_tree_expand(int32_t n, const uint8_t *kind, const int8_t *value, const i
                 if (round[i] == rd)
                     s[i] = kind[i] == 1 ? value[i] : (int8_t)(value[i] * s[parent[i]]);
     }
+    return ORC_OK;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Colour classes by Jones-Plassmann rounds (definition in the header).    */
+/* ---------------------------------------------------------------------- */
+static int prio_gt(uint32_t pa, int32_t a, uint32_t pb, int32_t b)
+{
+    return pa > pb || (pa == pb && a > b);
+}
+
+int orc_colour_jp(const orc_problem *P, uint64_t seed, uint8_t *colour, int32_t *n_colours, int32_t max_colours)
+{
+    const int32_t n = P->n;
+    int32_t i, k, left = n, used_max = 0;
+    uint32_t *prio = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t *col = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t *next = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    if (!prio || !col || !next) {
+        free(prio); free(col); free(next);
+        return ORC_EINVAL;
+    }
+    for (i = 0; i < n; ++i) {
+        prio[i] = philox_word((uint32_t)i, 0u, 0u, 5u << 24, seed, 0);
+        col[i] = -1;
+    }
+    while (left > 0) {
+        /* decide on the state at the start of the round */
+        for (i = 0; i < n; ++i) {
+            next[i] = -1;
+            if (col[i] >= 0) continue;
+            {
+                int top = 1;
+                for (k = P->row_ptr[i]; k < P->row_ptr[i + 1]; ++k) {
+                    const int32_t j = P->col[k];
+                    if (col[j] < 0 && prio_gt(prio[j], j, prio[i], i)) {
+                        top = 0;
+                        break;
+                    }
+                }
+                if (top) {
+                    int32_t c = 0, again = 1;
+                    while (again) {
+                        again = 0;
+                        for (k = P->row_ptr[i]; k < P->row_ptr[i + 1]; ++k)
+                            if (col[P->col[k]] == c) {
+                                ++c;
+                                again = 1;
+                                break;
+                            }
+                    }
+                    next[i] = c;
+                }
+            }
+        }
+        for (i = 0; i < n; ++i)
+            if (next[i] >= 0) {
+                col[i] = next[i];
+                --left;
+                if (next[i] + 1 > used_max) used_max = next[i] + 1;
+            }
+    }
+    *n_colours = used_max > 0 ? used_max : 1;
+    if (used_max > max_colours) {
+        free(prio); free(col); free(next);
+        return ORC_ERANGE;
+    }
+    for (i = 0; i < n; ++i) colour[i] = (uint8_t)col[i];
+    free(prio); free(col); free(next);
     return ORC_OK;
 }

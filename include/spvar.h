@@ -138,6 +138,20 @@ spv_status spv_sample(spv_ctx *ctx, const spv_problem *P, const double *betas, i
                       const int8_t *init_spins, int8_t *spins, int64_t *energies,
                       hipStream_t stream);
 
+/* Colour classes for the parallel sweep (the colour field of spv_problem):
+ * independent sets that one Metropolis pass updates at once.  Jones-Plassmann
+ * rounds: vertex v has priority (word 0 of Philox(v, 0, 0, 5 << 24) under `seed`,
+ * then v), higher first; each round every uncoloured vertex that outranks all its
+ * uncoloured neighbours (every CSR entry counts as an edge) takes the smallest
+ * colour its coloured neighbours lack.  The result equals first-fit greedy in
+ * decreasing priority order (at most max_degree + 1 colours).  P->colour and
+ * P->n_colours are ignored.  colour: device [n] uint8 output; *n_colours (host)
+ * receives the count; synchronous on `stream`.  ERANGE when more than 16 colours
+ * would be needed (colour then holds a capped, invalid colouring); ECAPACITY when
+ * 2n bytes exceed the LDS. */
+spv_status spv_colour(spv_ctx *ctx, const spv_problem *P, uint64_t seed, uint8_t *colour, int32_t *n_colours,
+                      hipStream_t stream);
+
 /* Device LDS read bandwidth in bytes/s, measured by a probe kernel (two
  * 1024-thread workgroups per CU reading bank-conflict-free 16-byte words; one
  * timed launch of `iters` x 4 reads per lane after one warm-up launch).  The

@@ -102,6 +102,7 @@ _SIGS = {
     "spv_batch_last_shape": ([_vp, _vp, _vp, _vp, _vp], C.c_int),
     "spv_sample_last_shape": ([_vp, _vp, _vp, _vp, _vp], C.c_int),
     "spv_lds_probe": ([_vp, _i32, _vp, _vp], C.c_int),
+    "spv_colour": ([_vp, _P, _u64, _vp, _vp, _vp], C.c_int),
     "spv_top_sample": ([_vp, _vp, _vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp], C.c_int),
     "spv_components": ([_vp, _P, _vp, _vp, _vp], C.c_int),
     "spv_merge_components": ([_vp, _P, _vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp], C.c_int),
@@ -230,6 +231,18 @@ def spv_sample_last_shape(ctx):
     v = [C.c_int32(0) for _ in range(4)]
     ctx.check(_lib.spv_sample_last_shape(ctx.handle, *[C.byref(x) for x in v]), "spv_sample_last_shape")
     return dict(threads=v[0].value, quads_per_wg=v[1].value, words_per_lane=v[2].value, chunks=v[3].value)
+
+
+def spv_colour(ctx, P, seed=0, stream=None):
+    """Colour classes of P's graph on the device (Jones-Plassmann, Philox priorities):
+    (colour uint8[n] on the device, n_colours)."""
+    colour = torch.empty(max(P.n, 1), dtype=torch.uint8, device=ctx.device)
+    nc = C.c_int32(0)
+    ps = spv_problem(P.n, P.nnz, P.row_ptr.data_ptr(), P.col.data_ptr() if P.nnz else None, None, None, None, 1,
+                     P.scale_log2, P.max_degree, P.x_bound)
+    ctx.check(_lib.spv_colour(ctx.handle, C.byref(ps), C.c_uint64(seed & (2**64 - 1)), _ptr(colour), C.byref(nc),
+                              _stream(stream)), "spv_colour")
+    return colour[:P.n], nc.value
 
 
 def spv_lds_probe(ctx, iters=20000, stream=None):

@@ -841,6 +841,37 @@ spv_status spv_merge_components(spv_ctx *ctx, const spv_problem *P, const int32_
                      "merge launch");
 }
 
+spv_status spv_colour(spv_ctx *ctx, const spv_problem *P, uint64_t seed, uint8_t *colour, int32_t *n_colours,
+                      hipStream_t stream) {
+    if (!ctx) return SPV_EINVAL;
+    Ctx *c = &ctx->c;
+    DeviceGuard g(c->device);
+    if (!P || !n_colours) return set_err(c, SPV_EINVAL, "spv_colour: NULL argument");
+    if (P->n < 0 || P->n > kMaxN) return set_err(c, SPV_ECAPACITY, "spv_colour: n=%d outside [0, %d]", P->n, kMaxN);
+    if (P->nnz < 0 || (P->n > 0 && (!P->row_ptr || !colour || (P->nnz > 0 && !P->col))))
+        return set_err(c, SPV_EINVAL, "spv_colour: NULL array");
+    if (P->n > 0 && (P->max_degree < 1 || P->max_degree > kMaxDegree))
+        return set_err(c, SPV_EINVAL, "spv_colour: max_degree=%d outside [1, %d]", P->max_degree, kMaxDegree);
+    if (P->n == 0) {
+        *n_colours = 1;
+        return SPV_OK;
+    }
+    if (colour_lds_bytes(P->n) + 256 > c->lds_max)
+        return set_err(c, SPV_ECAPACITY, "spv_colour: n=%d needs %zu B of LDS", P->n, colour_lds_bytes(P->n));
+    spv_status st = ensure(c, c->scratch2, (size_t)P->n * 4 + 64);
+    if (st) return st;
+    uint32_t *prio = static_cast<uint32_t *>(c->scratch2.p);
+    int *info = reinterpret_cast<int *>(static_cast<unsigned char *>(c->scratch2.p) + (((size_t)P->n * 4 + 15) & ~(size_t)15));
+    hipError_t e = launch_colour(P, seed, colour, prio, info, stream);
+    int h[4] = {0, 0, 0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(h, info, 3 * sizeof(int), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_check(c, e, "colour");
+    *n_colours = h[0];
+    if (h[2]) return set_err(c, SPV_ERANGE, "spv_colour: more than %d colours needed", kMaxColours);
+    return SPV_OK;
+}
+
 spv_status spv_lds_probe(spv_ctx *ctx, int32_t iters, double *bytes_per_s, hipStream_t stream) {
     if (!ctx || !bytes_per_s) return SPV_EINVAL;
     Ctx *c = &ctx->c;

@@ -289,6 +289,11 @@ hipError_t launch_ms_best(const int64_t *fixE, const int64_t *solE, int S, int F
 // 2 * num_cus words.
 hipError_t run_lds_probe(int iters, int num_cus, uint32_t *out, double *bytes_per_s, hipStream_t s);
 
+// Colour classes (colour.hip): prio [n] and info [4] are scratch.
+size_t colour_lds_bytes(int n);
+hipError_t launch_colour(const spv_problem *P, uint64_t seed, uint8_t *colour, uint32_t *prio, int *info,
+                         hipStream_t s);
+
 // Tree pre-processing (tree.hip).
 size_t tree_scratch_bytes(int n);
 bool tree_state_in_lds(int n, size_t lds_max);

@@ -112,11 +112,11 @@ def main():
                              "spvar_round", "multistart", "spvar_tree", "cubic4_ispvar"])
     ap.add_argument("--pt-runs", type=int, default=0, help="PT workloads: runs per step (0 = the config's)")
     ap.add_argument("--serving-requests", type=int, default=2000)
-    ap.add_argument("--serving-slots", type=int, default=8)
+    ap.add_argument("--serving-slots", type=int, default=16)
     ap.add_argument("--hw-queues", type=int, default=-1,
-                    help="GPU_MAX_HW_QUEUES for this process (-1: 16 for serving, unchanged otherwise)")
+                    help="GPU_MAX_HW_QUEUES for this process (-1: 32 for serving, unchanged otherwise)")
     args = ap.parse_args()
-    hwq = args.hw_queues if args.hw_queues >= 0 else (16 if args.workload == "serving" else 0)
+    hwq = args.hw_queues if args.hw_queues >= 0 else (32 if args.workload == "serving" else 0)
     if hwq:
         # HIP reads it when the runtime starts: one hardware queue per serving slot keeps
         # a long request's kernel from blocking the slots that share its queue.

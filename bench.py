@@ -25,16 +25,16 @@ if ROOT not in sys.path:
 BASELINE_METRIC = "spin-updates/s (batched vs plain, bit-exact); SPVAR solves/s; p50/p99 latency"
 
 # VALU lane-slots per Metropolis update (algorithmic count, the roofline's
-# numerator).  A Philox4x32-10 block costs 60 slots: 10 rounds of two
-# 32x32->64 products (v_mad_u64_u32, 2 issue slots each on gfx950) and two
-# 3-input xors; a chained-Philox probe measures 59-66 slots per block.  One
-# block serves the 4 replicas of a word, so 15 slots per update.  The
-# byte-parallel path (every |J|, |h| small enough for one-byte lanes) then adds,
-# per neighbour, one AND and one ADD on a word of 4 replicas (2/4 slot per
-# update) and about 4 slots per update for the field assembly, sign test,
-# threshold compare and flip; the general path adds one multiply-add per
-# neighbour and replica (1 slot) and the same 4.
-PHILOX_SLOTS = 10 * (2 * 2 + 2)
+# numerator).  A Philox4x32-10 block is 10 rounds of two 32x32->64 products
+# (v_mad_u64_u32) and two 3-input xors (v_bitop3_b32): 40 instructions.  Its cost
+# in issue slots is measured on the device by spv_philox_probe in every run
+# (about 42 on gfx950: the products issue at full rate); one block serves the 4
+# replicas of a word.  The byte-parallel path (every |J|, |h| small enough for
+# one-byte lanes) then adds, per neighbour, one AND and one ADD on a word of 4
+# replicas (2/4 slot per update) and about 4 slots per update for the field
+# assembly, sign test, threshold compare and flip; the general path adds one
+# multiply-add per neighbour and replica (1 slot) and the same 4.
+PHILOX_INSTRUCTIONS = 10 * (2 + 2)
 PEAK_VALU_TSLOTS = 256 * 64 * 2.4e9 / 1e12  # 256 CUs x 64 lanes x 2.4 GHz = 39.32 T lane-slots/s
 SA_PROFILE_SOURCES = ["paper_1706_07826_amd/csrc/sa.hip", "paper_1706_07826_amd/csrc/swar_core.hpp",
                       "paper_1706_07826_amd/csrc/sa_core.hpp", "paper_1706_07826_amd/csrc/device.hpp"]
@@ -65,9 +65,9 @@ def lds_object(updates_per_s, bytes_per_update, probe_bytes_per_s, note):
             "frac": round(achieved / probe_bytes_per_s, 4), "note": note}
 
 
-def slots_per_update(mean_degree, byte_parallel):
+def slots_per_update(mean_degree, byte_parallel, philox_slots):
     per_neighbour = 0.5 if byte_parallel else 1.0
-    return mean_degree * per_neighbour + 4 + PHILOX_SLOTS / 4.0
+    return mean_degree * per_neighbour + 4 + philox_slots / 4.0
 
 
 def sources_digest(paths):
@@ -199,7 +199,8 @@ def main():
 
     mean_deg = inst.nnz / inst.n
     byte_parallel = P.x_bound <= 255  # the library's rule for its byte-parallel body
-    spu = slots_per_update(mean_deg, byte_parallel)
+    philox_slots = PEAK_VALU_TSLOTS * 1e12 / spv.spv_philox_probe(ctx)  # measured issue slots per block
+    spu = slots_per_update(mean_deg, byte_parallel, philox_slots)
     achieved = updates * spu / (sa_ms / 1e3) / 1e12
     shape = spv.spv_sample_last_shape(ctx)
     dk = P.max_degree if P.max_degree in (4, 6, 8) else 0
@@ -214,6 +215,8 @@ def main():
                 "traffic": profiled_traffic_bytes(kernel),
                 "kernel": kernel, "kernel_ms": round(sa_ms, 4), "launch": shape,
                 "slots_per_update": round(spu, 3)}
+    roofline["philox_slots"] = round(philox_slots, 2)  # measured: spv_philox_probe
+    roofline["philox_instructions"] = PHILOX_INSTRUCTIONS
     if byte_parallel:
         probe = spv.spv_lds_probe(ctx)
         roofline["lds"] = lds_object(updates / (sa_ms / 1e3),

@@ -159,6 +159,13 @@ spv_status spv_colour(spv_ctx *ctx, const spv_problem *P, uint64_t seed, uint8_t
  * `stream`; uses context scratch.  EINVAL for iters outside [1, 2^24]. */
 spv_status spv_lds_probe(spv_ctx *ctx, int32_t iters, double *bytes_per_s, hipStream_t stream);
 
+/* Philox4x32-10 blocks per second of the device at full occupancy (16 waves per
+ * CU, each lane chaining `iters` blocks; one timed launch after a warm-up).  The
+ * VALU issue slots one block costs are (CUs x 64 lanes x clock) / this rate: the
+ * measured basis of the sampler's VALU roofline.  Synchronous on `stream`; uses
+ * context scratch.  EINVAL for iters outside [1, 2^24]. */
+spv_status spv_philox_probe(spv_ctx *ctx, int32_t iters, double *blocks_per_s, hipStream_t stream);
+
 /* The launch shape the last spv_sample call on this context used: threads per
  * workgroup, quads (4 replicas) per workgroup, quad words per lane, and sweep
  * chunks per group (1: one launch over all workgroups; more: streamed). */

@@ -102,6 +102,7 @@ _SIGS = {
     "spv_batch_last_shape": ([_vp, _vp, _vp, _vp, _vp], C.c_int),
     "spv_sample_last_shape": ([_vp, _vp, _vp, _vp, _vp], C.c_int),
     "spv_lds_probe": ([_vp, _i32, _vp, _vp], C.c_int),
+    "spv_philox_probe": ([_vp, _i32, _vp, _vp], C.c_int),
     "spv_colour": ([_vp, _P, _u64, _vp, _vp, _vp], C.c_int),
     "spv_top_sample": ([_vp, _vp, _vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp], C.c_int),
     "spv_components": ([_vp, _P, _vp, _vp, _vp], C.c_int),
@@ -249,6 +250,13 @@ def spv_lds_probe(ctx, iters=20000, stream=None):
     """Measured LDS read bandwidth of the device, bytes/s."""
     v = C.c_double(0.0)
     ctx.check(_lib.spv_lds_probe(ctx.handle, int(iters), C.byref(v), _stream(stream)), "spv_lds_probe")
+    return v.value
+
+
+def spv_philox_probe(ctx, iters=2000, stream=None):
+    """Measured Philox4x32-10 blocks per second of the device at full occupancy."""
+    v = C.c_double(0.0)
+    ctx.check(_lib.spv_philox_probe(ctx.handle, int(iters), C.byref(v), _stream(stream)), "spv_philox_probe")
     return v.value
 
 

@@ -883,6 +883,18 @@ spv_status spv_lds_probe(spv_ctx *ctx, int32_t iters, double *bytes_per_s, hipSt
                      "lds probe");
 }
 
+spv_status spv_philox_probe(spv_ctx *ctx, int32_t iters, double *blocks_per_s, hipStream_t stream) {
+    if (!ctx || !blocks_per_s) return SPV_EINVAL;
+    Ctx *c = &ctx->c;
+    DeviceGuard g(c->device);
+    if (iters < 1 || iters > (1 << 24)) return set_err(c, SPV_EINVAL, "spv_philox_probe: iters=%d", iters);
+    spv_status st = ensure(c, c->scratch2, (size_t)16 * c->num_cus * 4);
+    if (st) return st;
+    return hip_check(c,
+                     run_philox_probe(iters, c->num_cus, static_cast<uint32_t *>(c->scratch2.p), blocks_per_s, stream),
+                     "philox probe");
+}
+
 spv_status spv_tree_reduce(spv_ctx *ctx, const spv_problem *P, const spv_tree_out *out, hipStream_t stream) {
     if (!ctx) return SPV_EINVAL;
     Ctx *c = &ctx->c;

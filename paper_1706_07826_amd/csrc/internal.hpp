@@ -288,6 +288,8 @@ hipError_t launch_ms_best(const int64_t *fixE, const int64_t *solE, int S, int F
 // LDS read-bandwidth probe (probe.hip): synchronous on `s`; `out` receives at most
 // 2 * num_cus words.
 hipError_t run_lds_probe(int iters, int num_cus, uint32_t *out, double *bytes_per_s, hipStream_t s);
+// Philox throughput probe (probe.hip): `out` receives at most 16 * num_cus words.
+hipError_t run_philox_probe(int iters, int num_cus, uint32_t *out, double *blocks_per_s, hipStream_t s);
 
 // Colour classes (colour.hip): prio [n] and info [4] are scratch.
 size_t colour_lds_bytes(int n);

@@ -90,6 +90,28 @@ def test_cubic20_pticm_config_shape(spv, ctx):
                           oracle.energy(inst, got["final_spins"].cpu().numpy().reshape(-1, inst.n)))
 
 
+def test_cubic20_pticm_full_sweeps_properties(spv, ctx):
+    """The full N=8000 PT-ICM launch (10^4 sweeps, the bench's plan): every final energy and
+    every top-10 energy equals the recomputed energy of its state, each list is full, sorted
+    and free of repeated states (the oracle replays the short schedule above bit for bit)."""
+    cfg = cf.CUBIC20_PTICM
+    inst = cf.instance(cfg)
+    betas = cf.betas(cfg)
+    K = betas.size
+    print(f"[ptx] cubic20 full {cfg['sweeps']} sweeps", flush=True)
+    P = spv.Problem.from_instance(inst)
+    got = spv.spv_pt_sample(ctx, P, betas, 1, cfg["chains"], cfg["sweeps"], seed=cfg["seed"], icm=(0, K))
+    fs, fe = got["final_spins"].cpu().numpy(), got["final_E"].cpu().numpy()
+    assert np.array_equal(fe.reshape(-1), oracle.energy(inst, fs.reshape(-1, inst.n)))
+    te, ts, tc = (got[k].cpu().numpy() for k in ("top_E", "top_spins", "top_count"))
+    assert np.all(tc == 10)
+    assert np.all(np.diff(te, axis=-1) >= 0)
+    assert np.array_equal(te.reshape(-1), oracle.energy(inst, ts.reshape(-1, inst.n)))
+    lists = ts.reshape(-1, 10, inst.n)
+    for L in lists:
+        assert len({row.tobytes() for row in L}) == 10
+
+
 def test_bounded_neighbour_wait_reports_and_recovers(spv, ctx, monkeypatch):
     """Failure handling forced from the host: with a spin limit of 0 a workgroup
     whose neighbour has not yet published gives up at once instead of waiting.

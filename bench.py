@@ -109,7 +109,7 @@ def main():
                     help="after timing, run one device copy of this size (counter calibration)")
     ap.add_argument("--workload", default="chimera8_sa",
                     choices=["chimera8_sa", "residual_batch", "cubic10_pt", "cubic20_pticm", "serving",
-                             "spvar_round", "multistart", "spvar_tree", "cubic4_ispvar"])
+                             "spvar_round", "multistart", "spvar_tree", "cubic4_ispvar", "chimera32_sa"])
     ap.add_argument("--pt-runs", type=int, default=0, help="PT workloads: runs per step (0 = the config's)")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--serving-slots", type=int, default=16)
@@ -151,6 +151,8 @@ def main():
         return bench_spvar_tree(args)
     if args.workload == "cubic4_ispvar":
         return bench_cubic4_ispvar(args)
+    if args.workload == "chimera32_sa":
+        return bench_chimera32_sa(args)
 
     cfg = cf.CHIMERA8_SA
     inst = cf.instance(cfg)
@@ -207,9 +209,10 @@ def main():
     if not byte_parallel:
         kernel = "sa_kernel<1>"
     elif shape["chunks"] > 1:
-        kernel = f"sa_stream_kernel<{dk}, {shape['words_per_lane']}>"
+        big = "true" if shape["global_instance"] else "false"
+        kernel = f"sa_stream_kernel<{dk}, {shape['words_per_lane']}, {big}>"
     else:
-        kernel = f"sa_kernel<0, {dk}>" if dk else "sa_kernel<0>"
+        kernel = f"sa_kernel<0, {dk}, {'true' if shape['global_instance'] else 'false'}>"
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_VALU_TSLOTS, 3),
                 "unit": "Tslot/s", "frac": round(achieved / PEAK_VALU_TSLOTS, 4),
                 "traffic": profiled_traffic_bytes(kernel),
@@ -692,6 +695,44 @@ def bench_cubic4_ispvar(args):
         "spin_updates_per_s": round(updates / dt, 1), "rounds_run": res["rounds_run"],
         "round_info": [[int(v) for v in r] for r in res["round_info"]],
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_chimera32_sa(args):
+    """SA beyond the LDS: Chimera 32x32 (N=8192, couplers/biases U{+-1..+-6}), 10,000 reads x
+    2,000 sweeps (the chimera8 schedule): the byte-parallel body with its instance in global
+    memory, streamed."""
+    import torch
+
+    import paper_1706_07826_amd as spv
+    from spvar_inputs import chimera, linear_betas
+
+    inst = chimera(32, seed=1032)
+    betas = linear_betas(0.1, 5.0, 2000)
+    reads = 10000
+    ctx = spv.Context(0)
+    P = spv.Problem.from_instance(inst)
+    spins = torch.empty((reads, inst.n), dtype=torch.int8, device="cuda")
+    energies = torch.empty(reads, dtype=torch.int64, device="cuda")
+    for _ in range(args.warmup):
+        spv.spv_sample(ctx, P, betas, reads, 9, spins=spins, energies=energies)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        spv.spv_sample(ctx, P, betas, reads, 9, spins=spins, energies=energies)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    updates = reads * inst.n * betas.size
+    out = {
+        "metric": BASELINE_METRIC, "value": round(updates / dt, 1), "unit": "spin-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic (seeded Chimera U{+-1..+-6} instance)",
+        "config": {"workload": "chimera32_sa: Chimera 32x32 K4,4 N=8192, SA 10000 reads x 2000 sweeps, "
+                               "instance in global memory"},
+        "launch": spv.spv_sample_last_shape(ctx),
+        "best_E": int(energies.min().item()),
     }
     print(json.dumps(out), flush=True)
 

@@ -167,10 +167,11 @@ spv_status spv_lds_probe(spv_ctx *ctx, int32_t iters, double *bytes_per_s, hipSt
 spv_status spv_philox_probe(spv_ctx *ctx, int32_t iters, double *blocks_per_s, hipStream_t stream);
 
 /* The launch shape the last spv_sample call on this context used: threads per
- * workgroup, quads (4 replicas) per workgroup, quad words per lane, and sweep
- * chunks per group (1: one launch over all workgroups; more: streamed). */
+ * workgroup, quads (4 replicas) per workgroup, quad words per lane, sweep chunks
+ * per group (1: one launch over all workgroups; more: streamed), and whether the
+ * instance was read from global memory (1) rather than LDS (0). */
 spv_status spv_sample_last_shape(const spv_ctx *ctx, int32_t *threads, int32_t *quads_per_wg,
-                                 int32_t *words_per_lane, int32_t *chunks);
+                                 int32_t *words_per_lane, int32_t *chunks, int32_t *global_instance);
 
 /* E(s) of R states: spins device [R][n] int8 +-1 -> energies device [R] int64. */
 spv_status spv_energy(spv_ctx *ctx, const spv_problem *P, const int8_t *spins, int32_t R,

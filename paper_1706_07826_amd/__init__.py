@@ -100,7 +100,7 @@ _SIGS = {
     "spv_pt_sample": ([_vp, _P, C.POINTER(spv_pt_params), C.POINTER(spv_pt_out), _vp], C.c_int),
     "spv_sample_batch": ([_vp, _i32, _P, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "spv_batch_last_shape": ([_vp, _vp, _vp, _vp, _vp], C.c_int),
-    "spv_sample_last_shape": ([_vp, _vp, _vp, _vp, _vp], C.c_int),
+    "spv_sample_last_shape": ([_vp, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "spv_lds_probe": ([_vp, _i32, _vp, _vp], C.c_int),
     "spv_philox_probe": ([_vp, _i32, _vp, _vp], C.c_int),
     "spv_colour": ([_vp, _P, _u64, _vp, _vp, _vp], C.c_int),
@@ -228,10 +228,12 @@ def spv_sample(ctx, P, betas, reads, seed, sweep_offset=0, init_spins=None, spin
 
 
 def spv_sample_last_shape(ctx):
-    """Shape of the last spv_sample launch: dict(threads, quads_per_wg, words_per_lane, chunks)."""
-    v = [C.c_int32(0) for _ in range(4)]
+    """Shape of the last spv_sample launch: dict(threads, quads_per_wg, words_per_lane, chunks,
+    global_instance)."""
+    v = [C.c_int32(0) for _ in range(5)]
     ctx.check(_lib.spv_sample_last_shape(ctx.handle, *[C.byref(x) for x in v]), "spv_sample_last_shape")
-    return dict(threads=v[0].value, quads_per_wg=v[1].value, words_per_lane=v[2].value, chunks=v[3].value)
+    return dict(threads=v[0].value, quads_per_wg=v[1].value, words_per_lane=v[2].value, chunks=v[3].value,
+                global_instance=v[4].value)
 
 
 def spv_colour(ctx, P, seed=0, stream=None):

@@ -269,6 +269,10 @@ int sa_stream_env_grid() {
     const int g = v ? atoi(v) : 0;
     return g > 0 ? g : 0;
 }
+bool sa_big_env() {  // SPVAR_SA_BIG=1: the global-memory instance even when the LDS would hold it
+    const char *v = getenv("SPVAR_SA_BIG");
+    return v && v[0] == '1';
+}
 int sa_wpl_env() {
     const char *v = getenv("SPVAR_SA_WPL");
     return v ? atoi(v) : 0;
@@ -309,7 +313,7 @@ void spv_ctx_destroy(spv_ctx *ctx) {
     if (ctx->c.stage) (void)hipHostFree(ctx->c.stage);
     if (ctx->c.stage_done) (void)hipEventDestroy(ctx->c.stage_done);
     for (DevBuf *b : {&ctx->c.image, &ctx->c.tables, &ctx->c.tables2, &ctx->c.scratch, &ctx->c.scratch2,
-                      &ctx->c.rounds, &ctx->c.pt, &ctx->c.pt_tab, &ctx->c.top, &ctx->c.serve, &ctx->c.merge, &ctx->c.ms, &ctx->c.tree, &ctx->c.sa_stream})
+                      &ctx->c.rounds, &ctx->c.pt, &ctx->c.pt_tab, &ctx->c.top, &ctx->c.serve, &ctx->c.merge, &ctx->c.ms, &ctx->c.tree, &ctx->c.sa_stream, &ctx->c.sa_big})
         if (b->p) (void)hipFree(b->p);
     delete ctx;
 }
@@ -433,9 +437,29 @@ spv_status spv_sample(spv_ctx *ctx, const spv_problem *P, const double *betas, i
     int threads = sa_threads_env();
     if (threads <= 0) threads = (swar && !saturated) ? 512 : 256;
     threads = std::max(64, std::min(1024, threads / qw * qw));
-    while (qw > 1 && sa_lds_bytes(n, D, row_len, qw) + 256 > c->lds_max) --qw;
-    if (sa_lds_bytes(n, D, row_len, qw) + 256 > c->lds_max)
-        return set_err(c, SPV_ECAPACITY, "instance needs %zu B of LDS > %zu", sa_lds_bytes(n, D, row_len, qw), c->lds_max);
+    // An instance that does not fit the LDS beside its replicas moves to global
+    // memory (byte-parallel body): LDS then holds the tables and the spins only.
+    const int qw0 = qw;
+    bool big = swar && sa_big_env();
+    if (!big) {
+        while (qw > 1 && sa_lds_bytes(n, D, row_len, qw) + 256 > c->lds_max) --qw;
+        if (sa_lds_bytes(n, D, row_len, qw) + 256 > c->lds_max) {
+            if (!swar)
+                return set_err(c, SPV_ECAPACITY, "instance needs %zu B of LDS > %zu",
+                               sa_lds_bytes(n, D, row_len, qw), c->lds_max);
+            big = true;
+            qw = qw0;
+        }
+    }
+    if (big) {
+        while (qw > 1 && sa_lds_bytes(n, D, row_len, qw, true) + 256 > c->lds_max) --qw;
+        if (sa_lds_bytes(n, D, row_len, qw, true) + 256 > c->lds_max)
+            return set_err(c, SPV_ECAPACITY, "spins of one quad need %zu B of LDS > %zu",
+                           sa_lds_bytes(n, D, row_len, qw, true), c->lds_max);
+        st = ensure(c, c->sa_big, sa_big_bytes(n, D));
+        if (st) return st;
+        L.big = static_cast<unsigned char *>(c->sa_big.p);
+    }
     int wpl = sa_wpl_env();
     if (wpl <= 0) wpl = saturated ? 2 : 1;
     L.qw = qw;
@@ -448,6 +472,7 @@ spv_status spv_sample(spv_ctx *ctx, const spv_problem *P, const double *betas, i
     c->last_sa_shape[1] = L.qw;
     c->last_sa_shape[2] = L.wpl;
     c->last_sa_shape[3] = plan == 1 ? 1 : sa_stream_chunks_of(L, plan);
+    c->last_sa_shape[4] = L.big != nullptr ? 1 : 0;
     if (plan != 1) {
         st = ensure(c, c->sa_stream, sa_stream_bytes(n, reads, qw));
         if (st) return st;
@@ -459,12 +484,13 @@ spv_status spv_sample(spv_ctx *ctx, const spv_problem *P, const double *betas, i
 }
 
 spv_status spv_sample_last_shape(const spv_ctx *ctx, int32_t *threads, int32_t *quads_per_wg,
-                                 int32_t *words_per_lane, int32_t *chunks) {
+                                 int32_t *words_per_lane, int32_t *chunks, int32_t *global_instance) {
     if (!ctx) return SPV_EINVAL;
     if (threads) *threads = ctx->c.last_sa_shape[0];
     if (quads_per_wg) *quads_per_wg = ctx->c.last_sa_shape[1];
     if (words_per_lane) *words_per_lane = ctx->c.last_sa_shape[2];
     if (chunks) *chunks = ctx->c.last_sa_shape[3];
+    if (global_instance) *global_instance = ctx->c.last_sa_shape[4];
     return SPV_OK;
 }
 

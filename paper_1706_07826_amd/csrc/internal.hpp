@@ -71,6 +71,7 @@ struct Ctx {
     DevBuf ms;      // multi-start working set
     DevBuf tree;    // tree pre-processing scratch
     DevBuf sa_stream;  // streamed SA: task counter, tagged spin words between chunks
+    DevBuf sa_big;     // SA: byte-parallel instance in global memory (problems too large for LDS)
     TableCache tcache;
     std::vector<uint32_t> host_tables;
     void *batch_host = nullptr;  // pinned staging of descriptors and items
@@ -90,7 +91,8 @@ struct Ctx {
     };
     std::vector<TuneEntry> tuned;
     int last_shape[3] = {0, 0, 0};
-    int last_sa_shape[4] = {0, 0, 0, 0};  // spv_sample: threads, quads per workgroup, words per lane, chunks
+    int last_sa_shape[5] = {0, 0, 0, 0, 0};  // spv_sample: threads, quads per workgroup, words per lane,
+                                              // chunks, instance in global memory
     float last_tuned_ms = -1.f;
     // A context owned by one stream (serving slots) uploads tables
     // stream-ordered through pinned staging instead of draining the device.
@@ -152,6 +154,8 @@ struct SaLaunch {
     int threads;  // workgroup size
     int wpl = 1;  // byte-parallel body: quad words per lane (2 needs qw = 2)
     int spin_limit = 1 << 22;  // streamed launch: bounded wait for a group's previous chunk
+    unsigned char *big = nullptr;  // byte-parallel body: global instance buffer (sa_big_bytes) when
+                                   // the instance does not fit the LDS; null: instance in LDS
 };
 hipError_t launch_sa(const SaLaunch &L, hipStream_t s, size_t lds_limit);
 // Streamed launch of the byte-parallel body (resident workgroups, chunked sweeps).
@@ -159,7 +163,8 @@ int sa_stream_plan(const SaLaunch &L, int num_cus, int force_grid);  // 1: use l
 size_t sa_stream_bytes(int n, int reads, int qw);
 hipError_t launch_sa_stream(const SaLaunch &L, int plan, void *buf, hipStream_t s);
 int sa_stream_chunks_of(const SaLaunch &L, int plan);
-size_t sa_lds_bytes(int n, int D, int row_len, int qw);
+size_t sa_lds_bytes(int n, int D, int row_len, int qw, bool big = false);
+size_t sa_big_bytes(int n, int D);
 bool sa_use_swar(int nd, int row_len);
 
 hipError_t launch_energy(const int32_t *image, int n, int D, const int8_t *spins, int R,

@@ -111,19 +111,27 @@ __global__ __launch_bounds__(256) void prep_nbr_kernel(const int32_t *__restrict
 
 // ND = number of threshold digits; ND = 0 selects the byte-parallel path, whose
 // neighbour loop is straight-line code for a record count DK (0: any).
-template <int ND, int DK = 0>
+// BIG (byte-parallel body only): the instance lives in global memory (a.big),
+// built beforehand by big_prep_kernel; LDS holds the tables and the spins.
+template <int ND, int DK = 0, bool BIG = false>
 __global__ __launch_bounds__(1024) void sa_kernel(core::SaItem a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int cs[kMaxColours + 1];
     a.q0 = blockIdx.x * a.qw;
     if constexpr (ND == 0) {
         core::SwarLds L;
-        core::swar_layout(a.n, a.D, a.row_len, a.qw, &L, smem);
-        core::swar_load_instance(L, a, cs);
+        if constexpr (BIG) {
+            core::swar_big_layout(a.n, a.qw, &L, smem);
+            core::swar_bind_big(&L, a.big, a.n, a.D);
+            core::swar_load_colours(a, cs);
+        } else {
+            core::swar_layout(a.n, a.D, a.row_len, a.qw, &L, smem);
+            core::swar_load_instance(L, a, cs);
+        }
         if (a.wpl == 2 && a.qw == 2)
-            core::swar_run<DK, 2>(L, a, cs);
+            core::swar_run<DK, 2, BIG>(L, a, cs);
         else
-            core::swar_run<DK, 1>(L, a, cs);
+            core::swar_run<DK, 1, BIG>(L, a, cs);
     } else {
         core::SaLds L;
         core::sa_layout(a.n, a.D, a.row_len, a.qw, &L, smem);
@@ -155,14 +163,20 @@ constexpr uint32_t kTagPoison = 1u << 8;
 // Every branch of the task loop depends on wave-uniform values only (the task
 // index is read back with readfirstlane), so that no lane can be split from its
 // wave across loop iterations and barriers.
-template <int DK, int W>
+template <int DK, int W, bool BIG = false>
 __global__ __launch_bounds__(1024) void sa_stream_kernel(StreamArgs s) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int cs[kMaxColours + 1];
     __shared__ int task_s, late_s, poison_s;
     core::SwarLds L;
-    core::swar_layout(s.a.n, s.a.D, s.a.row_len, s.a.qw, &L, smem);
-    core::swar_load_instance(L, s.a, cs);
+    if constexpr (BIG) {
+        core::swar_big_layout(s.a.n, s.a.qw, &L, smem);
+        core::swar_bind_big(&L, s.a.big, s.a.n, s.a.D);
+        core::swar_load_colours(s.a, cs);
+    } else {
+        core::swar_layout(s.a.n, s.a.D, s.a.row_len, s.a.qw, &L, smem);
+        core::swar_load_instance(L, s.a, cs);
+    }
     const int ntask = s.G * s.K, T = blockDim.x, tid = threadIdx.x;
     const int words = s.a.n * s.a.qw;
     const uint32_t inv = (uint32_t)words;
@@ -219,7 +233,7 @@ __global__ __launch_bounds__(1024) void sa_stream_kernel(StreamArgs s) {
         ch.resume = k > 0 && !late;
         ch.keep = k + 1 < s.K;
         ch.poisoned = poisoned;
-        core::swar_run<DK, W>(L, it, cs, ch);  // ends with a barrier
+        core::swar_run<DK, W, BIG>(L, it, cs, ch);  // ends with a barrier
         if (ch.keep) {
             const uint32_t tag = (poisoned ? kTagPoison : 0u) | (uint32_t)(k + 1);
             for (int w = tid; w < words; w += T)
@@ -234,6 +248,14 @@ __global__ void stream_reset_kernel(int *counter, unsigned long long *state, siz
     const size_t i0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i0 == 0) *counter = 0;
     for (size_t i = i0; i < words; i += (size_t)gridDim.x * blockDim.x) state[i] = 0ull;
+}
+
+// The global-memory instance of the byte-parallel body (record addresses relative
+// to the spin words).
+__global__ __launch_bounds__(256) void big_prep_kernel(core::SaItem a) {
+    core::SwarLds L;
+    core::swar_bind_big(&L, a.big, a.n, a.D);
+    core::swar_build(L.rec, L.co, L.hpos, a, 0u, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
 }
 
 // Energies of arbitrary states: one workgroup per 64 rows... one thread per (row, variable).
@@ -296,10 +318,19 @@ bool sa_use_swar(int nd, int row_len) {
     return nd == 1 && row_len <= 256 && !off;
 }
 
-size_t sa_lds_bytes(int n, int D, int row_len, int qw) {
+size_t sa_lds_bytes(int n, int D, int row_len, int qw, bool big) {
     if (sa_use_swar(1 + (row_len > kDigitSize ? 1 : 0), row_len))
-        return core::swar_layout(n, D, row_len, qw, nullptr, nullptr);
+        return big ? core::swar_big_lds_bytes(n, qw) : core::swar_layout(n, D, row_len, qw, nullptr, nullptr);
     return core::sa_layout(n, D, row_len, qw, nullptr, nullptr);
+}
+
+size_t sa_big_bytes(int n, int D) { return core::swar_big_bytes(n, D); }
+
+static hipError_t launch_big_prep(const core::SaItem &a, hipStream_t s) {
+    const size_t work = (size_t)a.n * (size_t)core::swar_rec_stride(a.D);
+    const int grid = (int)std::min<size_t>(4096, std::max<size_t>(1, (work + 255) / 256));
+    hipLaunchKernelGGL(big_prep_kernel, dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_sa(const SaLaunch &L, hipStream_t s, size_t lds_limit) {
@@ -321,10 +352,21 @@ hipError_t launch_sa(const SaLaunch &L, hipStream_t s, size_t lds_limit) {
     a.wpl = (L.wpl == 2 && L.qw == 2) ? 2 : 1;
     a.k0 = (uint32_t)L.seed;
     a.k1 = (uint32_t)(L.seed >> 32);
-    const size_t lds = sa_lds_bytes(L.n, L.D, L.row_len, L.qw);
-    if (lds > lds_limit) return hipErrorInvalidValue;
+    a.big = L.big;
+    const bool big = L.big != nullptr;
+    const size_t lds = sa_lds_bytes(L.n, L.D, L.row_len, L.qw, big);
+    if (lds > lds_limit || (big && !sa_use_swar(L.nd, L.row_len))) return hipErrorInvalidValue;
     const int quads = (L.reads + 3) / 4;
     const int grid = (quads + L.qw - 1) / L.qw;
+    if (big) {
+        hipError_t e = launch_big_prep(a, s);
+        if (e != hipSuccess) return e;
+        if (L.D == 6)
+            hipLaunchKernelGGL((sa_kernel<0, 6, true>), dim3(grid), dim3(L.threads), lds, s, a);
+        else
+            hipLaunchKernelGGL((sa_kernel<0, 0, true>), dim3(grid), dim3(L.threads), lds, s, a);
+        return hipGetLastError();
+    }
     switch (sa_use_swar(L.nd, L.row_len) ? 0 : L.nd) {
         case 0:
             if (L.D == 6)
@@ -351,9 +393,9 @@ hipError_t launch_sa(const SaLaunch &L, hipStream_t s, size_t lds_limit) {
     return hipGetLastError();
 }
 
-template <int DK, int W>
+template <int DK, int W, bool BIG>
 static hipError_t stream_occupancy(int threads, size_t lds, int *per_cu) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, sa_stream_kernel<DK, W>, threads, lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, sa_stream_kernel<DK, W, BIG>, threads, lds);
 }
 
 // Chunks per group: the fewest (sweeps per chunk >= kStreamMinSweeps) whose tasks
@@ -395,12 +437,21 @@ int sa_stream_plan(const SaLaunch &L, int num_cus, int force_grid) {
     const int quads = (L.reads + 3) / 4;
     const int G = (quads + L.qw - 1) / L.qw;
     const int W = (L.wpl == 2 && L.qw == 2) ? 2 : 1;
-    const size_t lds = sa_lds_bytes(L.n, L.D, L.row_len, L.qw);
+    const bool big = L.big != nullptr;
+    const size_t lds = sa_lds_bytes(L.n, L.D, L.row_len, L.qw, big);
     const int dk = (L.D == 6 || L.D == 4 || L.D == 8) ? L.D : 0;
     int per_cu = 0;
     hipError_t e;
-#define SPV_OCC(D_, W_) e = stream_occupancy<D_, W_>(L.threads, lds, &per_cu)
-    if (W == 2) {
+#define SPV_OCC(D_, W_) e = stream_occupancy<D_, W_, false>(L.threads, lds, &per_cu)
+    if (big) {
+        if (dk == 6) {
+            if (W == 2) e = stream_occupancy<6, 2, true>(L.threads, lds, &per_cu);
+            else e = stream_occupancy<6, 1, true>(L.threads, lds, &per_cu);
+        } else {
+            if (W == 2) e = stream_occupancy<0, 2, true>(L.threads, lds, &per_cu);
+            else e = stream_occupancy<0, 1, true>(L.threads, lds, &per_cu);
+        }
+    } else if (W == 2) {
         if (dk == 6) SPV_OCC(6, 2); else if (dk == 4) SPV_OCC(4, 2); else if (dk == 8) SPV_OCC(8, 2); else SPV_OCC(0, 2);
     } else {
         if (dk == 6) SPV_OCC(6, 1); else if (dk == 4) SPV_OCC(4, 1); else if (dk == 8) SPV_OCC(8, 1); else SPV_OCC(0, 1);
@@ -424,7 +475,8 @@ hipError_t launch_sa_stream(const SaLaunch &L, int plan, void *buf, hipStream_t 
     const int quads = (L.reads + 3) / 4;
     const int G = (quads + L.qw - 1) / L.qw;
     const int W = (L.wpl == 2 && L.qw == 2) ? 2 : 1;
-    const size_t lds = sa_lds_bytes(L.n, L.D, L.row_len, L.qw);
+    const bool big = L.big != nullptr;
+    const size_t lds = sa_lds_bytes(L.n, L.D, L.row_len, L.qw, big);
     const int dk = (L.D == 6 || L.D == 4 || L.D == 8) ? L.D : 0;
     StreamArgs a;
     a.a.image = L.image;
@@ -444,6 +496,7 @@ hipError_t launch_sa_stream(const SaLaunch &L, int plan, void *buf, hipStream_t 
     a.a.k0 = (uint32_t)L.seed;
     a.a.k1 = (uint32_t)(L.seed >> 32);
     a.a.wpl = W;
+    a.a.big = L.big;
     a.G = G;
     a.Lc = (L.sweeps + K0 - 1) / K0;
     a.K = (L.sweeps + a.Lc - 1) / a.Lc;
@@ -457,6 +510,18 @@ hipError_t launch_sa_stream(const SaLaunch &L, int plan, void *buf, hipStream_t 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int grid = std::min(resident, G * a.K);
+    if (big) {
+        e = launch_big_prep(a.a, s);
+        if (e != hipSuccess) return e;
+        if (dk == 6) {
+            if (W == 2) hipLaunchKernelGGL((sa_stream_kernel<6, 2, true>), dim3(grid), dim3(L.threads), lds, s, a);
+            else hipLaunchKernelGGL((sa_stream_kernel<6, 1, true>), dim3(grid), dim3(L.threads), lds, s, a);
+        } else {
+            if (W == 2) hipLaunchKernelGGL((sa_stream_kernel<0, 2, true>), dim3(grid), dim3(L.threads), lds, s, a);
+            else hipLaunchKernelGGL((sa_stream_kernel<0, 1, true>), dim3(grid), dim3(L.threads), lds, s, a);
+        }
+        return hipGetLastError();
+    }
 #define SPV_GO(D_, W_) hipLaunchKernelGGL((sa_stream_kernel<D_, W_>), dim3(grid), dim3(L.threads), lds, s, a)
     if (W == 2) {
         if (dk == 6) SPV_GO(6, 2); else if (dk == 4) SPV_GO(4, 2); else if (dk == 8) SPV_GO(8, 2); else SPV_GO(0, 2);

@@ -65,6 +65,7 @@ struct SaItem {
     int n, D, C, row_len, sweeps, reads, q0, qw;
     uint32_t sweep_offset, k0, k1;
     int wpl = 1;  // byte-parallel body: quad words per lane (1, or 2 when qw = 2)
+    unsigned char *big = nullptr;  // byte-parallel body: instance in global memory (too large for LDS)
 };
 
 struct Fields {

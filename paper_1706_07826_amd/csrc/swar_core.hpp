@@ -90,15 +90,37 @@ __host__ __device__ inline size_t swar_layout(int n, int D, int row_len, int qw,
 
 __device__ __forceinline__ int32_t swar_cp(uint2 co) { return ((int32_t)(int16_t)(co.x & 0xffffu)) / 4; }
 
-// Expands the image's 32-bit records into byte-parallel records.  Ends with a barrier.
-__device__ inline void swar_load_instance(const SwarLds &L, const SaItem &a, int *cs) {
-    const int n = a.n, D = a.D, T = blockDim.x, tid = threadIdx.x, Ds = swar_rec_stride(D);
+// Global-memory instance of a problem too large for LDS: the same records (with
+// addresses relative to the spin words) and site constants, built once per call.
+__host__ __device__ inline size_t swar_big_bytes(int n, int D) {
+    return (size_t)n * swar_rec_stride(D) * 8 + (size_t)n * 8 + (size_t)n * 4;
+}
+__device__ inline void swar_bind_big(SwarLds *L, unsigned char *g, int n, int D) {
+    L->rec = reinterpret_cast<uint2 *>(g);
+    L->co = reinterpret_cast<uint2 *>(g + (size_t)n * swar_rec_stride(D) * 8);
+    L->hpos = reinterpret_cast<int32_t *>(g + (size_t)n * swar_rec_stride(D) * 8 + (size_t)n * 8);
+}
+// LDS of the variant: tables, spins, energy accumulators.
+__host__ __device__ inline size_t swar_big_lds_bytes(int n, int qw) {
+    const size_t o_E = (kSwarSOffset + (size_t)2 * n * qw * 4 + 7) & ~(size_t)7;
+    return o_E + (size_t)4 * qw * 8;
+}
+__device__ inline void swar_big_layout(int n, int qw, SwarLds *L, unsigned char *base) {
+    L->tab = reinterpret_cast<uint32_t *>(base);
+    L->S = reinterpret_cast<uint32_t *>(base + kSwarSOffset);
+    L->E2 = reinterpret_cast<unsigned long long *>(base + ((kSwarSOffset + (size_t)2 * n * qw * 4 + 7) & ~(size_t)7));
+}
+
+// Byte-parallel records and site constants of positions [i0, n) step `step`, record
+// addresses based at `sb` (the LDS address of the spin words, or 0 for addresses
+// relative to them).
+__device__ inline void swar_build(uint2 *rec, uint2 *co, int32_t *hpos, const SaItem &a, uint32_t sb, int i0,
+                                  int step) {
+    const int n = a.n, D = a.D, Ds = swar_rec_stride(D);
     const int32_t *img = a.image;
-    if (tid <= a.C) cs[tid] = img[3 + tid];
     const uint32_t *recs = reinterpret_cast<const uint32_t *>(img + kImgHeader + 3 * n);
     const uint32_t inv = (uint32_t)n * (uint32_t)a.qw;  // offset of ~S
-    const uint32_t sb = swar_lds_addr(L.S);
-    for (int idx = tid; idx < n * Ds; idx += T) {
+    for (int idx = i0; idx < n * Ds; idx += step) {
         const int p = idx / Ds, k = idx - p * Ds;
         uint2 v = make_uint2(sb, 0u);  // padding: a valid address, weight 0
         if (k < D) {
@@ -107,9 +129,9 @@ __device__ inline void swar_load_instance(const SwarLds &L, const SaItem &a, int
             const uint32_t off = (r >> 16) * (uint32_t)a.qw + (J < 0 ? inv : 0u);
             v = make_uint2(sb + 4u * off, (uint32_t)(J < 0 ? -J : J) * 0x01010101u);
         }
-        L.rec[idx] = v;
+        rec[idx] = v;
     }
-    for (int p = tid; p < n; p += T) {
+    for (int p = i0; p < n; p += step) {
         int32_t s = 0;
         for (int k = 0; k < D; ++k) {
             const int32_t J = (int32_t)(int16_t)(recs[(size_t)p * D + k] & 0xffffu);
@@ -117,9 +139,22 @@ __device__ inline void swar_load_instance(const SwarLds &L, const SaItem &a, int
         }
         const int32_t h = img[kImgHeader + 2 * n + p];
         const uint32_t c16 = (uint32_t)(4 * (h - s)) & 0xffffu;
-        L.hpos[p] = h;
-        L.co[p] = make_uint2(c16 | (c16 << 16), (uint32_t)img[kImgHeader + p]);
+        hpos[p] = h;
+        co[p] = make_uint2(c16 | (c16 << 16), (uint32_t)img[kImgHeader + p]);
     }
+}
+
+// Colour-class bounds only (the instance of the global-memory variant).  Ends with a barrier.
+__device__ inline void swar_load_colours(const SaItem &a, int *cs) {
+    if ((int)threadIdx.x <= a.C) cs[threadIdx.x] = a.image[3 + threadIdx.x];
+    __syncthreads();
+}
+
+// Expands the image's 32-bit records into byte-parallel records.  Ends with a barrier.
+__device__ inline void swar_load_instance(const SwarLds &L, const SaItem &a, int *cs) {
+    const int T = blockDim.x, tid = threadIdx.x;
+    if (tid <= a.C) cs[tid] = a.image[3 + tid];
+    swar_build(L.rec, L.co, L.hpos, a, swar_lds_addr(L.S), tid, T);
     __syncthreads();
 }
 
@@ -134,7 +169,7 @@ template <int DK, int W>
 __device__ __forceinline__ void swar_agree(const uint2 *__restrict__ rp, uint32_t qb, int D, uint32_t (&P)[W]) {
     auto word = [&](uint32_t addr, uint32_t (&w)[W]) {
         if constexpr (W == 2) {
-            const uint2 v = swar_ld64(addr);
+            const uint2 v = swar_ld64(addr + qb);
             w[0] = v.x;
             w[1] = v.y;
         } else {
@@ -213,8 +248,10 @@ struct SwarChunk {
 constexpr long long kSwarPoisonEnergy = INT64_MIN;
 
 // W = quad words per lane: 1, or 2 when qw = 2 and a lane holds its site's whole
-// row (the neighbour addresses are then the records' offsets as they stand).
-template <int DK, int W>
+// row (the neighbour addresses are then the records' addresses as they stand).
+// BIG: records and site constants in global memory, record addresses relative to
+// the spin words.
+template <int DK, int W, bool BIG = false>
 __device__ void swar_run(const SwarLds &L, const SaItem &a, const int *cs, const SwarChunk &ch = SwarChunk()) {
     static_assert(W == 1 || W == 2, "one or two words per lane");
     const int n = a.n, D = a.D, qw = W == 2 ? 2 : a.qw, T = blockDim.x, tid = threadIdx.x;
@@ -224,7 +261,7 @@ __device__ void swar_run(const SwarLds &L, const SaItem &a, const int *cs, const
     const int qa = W == 2 ? 0 : tid % lps, slot = tid / lps, nslots = T / lps;
     const bool active = slot < nslots;
     const uint32_t inv = (uint32_t)n * (uint32_t)qw;
-    const uint32_t qb = 4u * (uint32_t)qa;
+    const uint32_t qb = 4u * (uint32_t)qa + (BIG ? swar_lds_addr(L.S) : 0u);
     const int ls0 = ch.ls0, lsend = ch.count < 0 ? a.sweeps : ls0 + ch.count;
     for (int k = tid; k < 2 * kSwarTabWords; k += T) {
         const int i = k % kSwarTabWords - kSwarTabHalf;

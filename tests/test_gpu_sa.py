@@ -211,3 +211,48 @@ def test_sa_streamed_launch_resumes_from_states(spv, ctx):
                                             init_spins=torch.as_tensor(init).cuda()))
     osp, oE = oracle.sa_sample(inst, betas[40:], reads=reads, seed=555, sweep_offset=40, init=init)
     assert np.array_equal(S.cpu().numpy(), osp) and np.array_equal(E.cpu().numpy(), oE)
+
+
+@pytest.mark.parametrize("name,make,reads,sweeps,br", [c for c in SMALL[:3]] + [SMALL[5], SMALL[9]],
+                         ids=[c[0] for c in SMALL[:3]] + [SMALL[5][0], SMALL[9][0]])
+@pytest.mark.parametrize("shape", [{}, {"SPVAR_SA_WPL": 2, "SPVAR_SA_THREADS": 256}], ids=["default", "w2"])
+def test_sa_global_instance_forced_small(spv, ctx, name, make, reads, sweeps, br, shape):
+    """The byte-parallel body with its instance in global memory (records read through L2,
+    spins in LDS), forced on small cases, against the oracle."""
+    inst = make()
+    betas = si.linear_betas(br[0], br[1], sweeps)
+    P = spv.Problem.from_instance(inst)
+    _say(f"[sa] {name} global instance {shape}")
+    sp, E = _with_env(dict(shape, SPVAR_SA_BIG=1), lambda: spv.spv_sample(ctx, P, betas, reads, 31))
+    osp, oE = oracle.sa_sample(inst, betas, reads=reads, seed=31, threads=8)
+    assert np.array_equal(sp.cpu().numpy(), osp) and np.array_equal(E.cpu().numpy(), oE)
+
+
+@pytest.mark.parametrize("M,reads,sweeps", [(20, 40, 60), (32, 16, 30)], ids=["chimera20_n3200", "chimera32_n8192"])
+def test_sa_beyond_lds_matches_oracle(spv, ctx, M, reads, sweeps):
+    """Chimera instances whose records do not fit the LDS (N = 3200 and 8192) take the
+    global-instance body automatically; the sample equals the oracle's."""
+    inst = si.chimera(M, seed=40 + M)
+    betas = si.linear_betas(0.1, 5.0, sweeps)
+    P = spv.Problem.from_instance(inst)
+    _say(f"[sa] beyond LDS: chimera{M} n={inst.n}")
+    sp, E = spv.spv_sample(ctx, P, betas, reads, 77)
+    osp, oE = oracle.sa_sample(inst, betas, reads=reads, seed=77, threads=8)
+    assert np.array_equal(sp.cpu().numpy(), osp) and np.array_equal(E.cpu().numpy(), oE)
+
+
+def test_sa_beyond_lds_streamed_sampled_reads(spv, ctx):
+    """N = 3200 with 10,000 reads x 200 sweeps: the streamed launch over the global instance;
+    sampled reads recomputed by the oracle, every energy equal to its state's."""
+    inst = si.chimera(20, seed=61)
+    betas = si.linear_betas(0.1, 5.0, 200)
+    P = spv.Problem.from_instance(inst)
+    _say("[sa] beyond LDS, streamed: chimera20 10000 reads x 200 sweeps")
+    sp, E = spv.spv_sample(ctx, P, betas, 10000, 5)
+    shape = spv.spv_sample_last_shape(ctx)
+    assert shape["chunks"] > 1
+    sp, E = sp.cpu().numpy(), E.cpu().numpy()
+    for r in (0, 1, 4097, 9999):
+        osp, oE = oracle.sa_sample(inst, betas, seed=5, r_begin=r, r_end=r + 1)
+        assert np.array_equal(sp[r], osp[0]) and E[r] == oE[0], r
+    assert np.array_equal(E, oracle.energy(inst, sp))

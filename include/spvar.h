@@ -132,6 +132,11 @@ spv_status spv_problem_check(spv_ctx *ctx, const spv_problem *P);
  * scratch; the sample is bit-identical to the one-launch schedule.  A streamed
  * task waits (bounded) for its group's previous chunk; should a wait ever be
  * abandoned, every read of that group reports energy INT64_MIN.
+ * An instance too large for the LDS beside its replicas' spins is read from
+ * global memory (the LDS keeps the spins and threshold tables), so n is bounded
+ * by the spins of one replica quad: 4n bytes plus the tables within the LDS
+ * (about 37,000 variables; about 19,900 for the byte-parallel body, which holds
+ * a complement plane).  SPV_ECAPACITY beyond that.
  */
 spv_status spv_sample(spv_ctx *ctx, const spv_problem *P, const double *betas, int32_t sweeps,
                       int32_t reads, uint64_t seed, uint32_t sweep_offset,

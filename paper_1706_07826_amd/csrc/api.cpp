@@ -429,24 +429,29 @@ spv_status spv_sample(spv_ctx *ctx, const spv_problem *P, const double *betas, i
     // path is fastest with 2 quads per 256-thread workgroup, each lane holding both
     // words of its site (fewer instructions per update); when they do not fill the
     // device (residual problems, 1,000 reads) two lanes per site (2 quads per
-    // 512-thread workgroup) finish sooner.  The general path: 1 quad per 256 threads.
+    // 512-thread workgroup) finish sooner.  The general path: 1 quad per workgroup,
+    // 512 threads when the workgroups outnumber the CUs, else 1024 (measured on the
+    // L = 10 and L = 20 Gaussian cubes: more sites in flight per CU when few
+    // workgroups share it), and no more threads than sites.
     const bool swar = sa_use_swar(nd, row_len);
     const bool saturated = ((reads + 3) / 4 + 1) / 2 > c->num_cus;
     int qw = sa_qw_env();
     if (qw <= 0) qw = swar ? 2 : 1;
     int threads = sa_threads_env();
-    if (threads <= 0) threads = (swar && !saturated) ? 512 : 256;
+    if (threads <= 0) {
+        if (swar)
+            threads = saturated ? 256 : 512;
+        else
+            threads = std::min((reads + 3) / 4 > c->num_cus ? 512 : 1024, std::max(64, (n + 63) / 64 * 64));
+    }
     threads = std::max(64, std::min(1024, threads / qw * qw));
-    // An instance that does not fit the LDS beside its replicas moves to global
-    // memory (byte-parallel body): LDS then holds the tables and the spins only.
+    // An instance that does not fit the LDS beside its replicas stays in global
+    // memory: LDS then holds the tables and the spins only.
     const int qw0 = qw;
-    bool big = swar && sa_big_env();
+    bool big = sa_big_env();
     if (!big) {
         while (qw > 1 && sa_lds_bytes(n, D, row_len, qw) + 256 > c->lds_max) --qw;
         if (sa_lds_bytes(n, D, row_len, qw) + 256 > c->lds_max) {
-            if (!swar)
-                return set_err(c, SPV_ECAPACITY, "instance needs %zu B of LDS > %zu",
-                               sa_lds_bytes(n, D, row_len, qw), c->lds_max);
             big = true;
             qw = qw0;
         }
@@ -456,9 +461,12 @@ spv_status spv_sample(spv_ctx *ctx, const spv_problem *P, const double *betas, i
         if (sa_lds_bytes(n, D, row_len, qw, true) + 256 > c->lds_max)
             return set_err(c, SPV_ECAPACITY, "spins of one quad need %zu B of LDS > %zu",
                            sa_lds_bytes(n, D, row_len, qw, true), c->lds_max);
-        st = ensure(c, c->sa_big, sa_big_bytes(n, D));
-        if (st) return st;
-        L.big = static_cast<unsigned char *>(c->sa_big.p);
+        L.global_instance = true;
+        if (swar) {
+            st = ensure(c, c->sa_big, sa_big_bytes(n, D));
+            if (st) return st;
+            L.big = static_cast<unsigned char *>(c->sa_big.p);
+        }
     }
     int wpl = sa_wpl_env();
     if (wpl <= 0) wpl = saturated ? 2 : 1;
@@ -472,7 +480,7 @@ spv_status spv_sample(spv_ctx *ctx, const spv_problem *P, const double *betas, i
     c->last_sa_shape[1] = L.qw;
     c->last_sa_shape[2] = L.wpl;
     c->last_sa_shape[3] = plan == 1 ? 1 : sa_stream_chunks_of(L, plan);
-    c->last_sa_shape[4] = L.big != nullptr ? 1 : 0;
+    c->last_sa_shape[4] = L.global_instance ? 1 : 0;
     if (plan != 1) {
         st = ensure(c, c->sa_stream, sa_stream_bytes(n, reads, qw));
         if (st) return st;

@@ -154,8 +154,9 @@ struct SaLaunch {
     int threads;  // workgroup size
     int wpl = 1;  // byte-parallel body: quad words per lane (2 needs qw = 2)
     int spin_limit = 1 << 22;  // streamed launch: bounded wait for a group's previous chunk
-    unsigned char *big = nullptr;  // byte-parallel body: global instance buffer (sa_big_bytes) when
-                                   // the instance does not fit the LDS; null: instance in LDS
+    bool global_instance = false;  // the instance stays in global memory (does not fit the LDS)
+    unsigned char *big = nullptr;  // byte-parallel body with global_instance: its instance buffer
+                                   // (sa_big_bytes); the general body reads the image itself
 };
 hipError_t launch_sa(const SaLaunch &L, hipStream_t s, size_t lds_limit);
 // Streamed launch of the byte-parallel body (resident workgroups, chunked sweeps).

@@ -111,8 +111,9 @@ __global__ __launch_bounds__(256) void prep_nbr_kernel(const int32_t *__restrict
 
 // ND = number of threshold digits; ND = 0 selects the byte-parallel path, whose
 // neighbour loop is straight-line code for a record count DK (0: any).
-// BIG (byte-parallel body only): the instance lives in global memory (a.big),
-// built beforehand by big_prep_kernel; LDS holds the tables and the spins.
+// BIG: the instance lives in global memory, LDS holds the tables and the spins.
+// The byte-parallel body reads its own records from a.big (built beforehand by
+// big_prep_kernel); the general body reads the prepared image itself.
 template <int ND, int DK = 0, bool BIG = false>
 __global__ __launch_bounds__(1024) void sa_kernel(core::SaItem a) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -132,6 +133,11 @@ __global__ __launch_bounds__(1024) void sa_kernel(core::SaItem a) {
             core::swar_run<DK, 2, BIG>(L, a, cs);
         else
             core::swar_run<DK, 1, BIG>(L, a, cs);
+    } else if constexpr (BIG) {
+        core::SaLds L;
+        core::sa_big_layout(a.n, a.row_len, a.qw, &L, smem);
+        core::sa_bind_image(&L, a, cs);
+        core::sa_run<ND, true>(L, a, cs);
     } else {
         core::SaLds L;
         core::sa_layout(a.n, a.D, a.row_len, a.qw, &L, smem);
@@ -321,7 +327,8 @@ bool sa_use_swar(int nd, int row_len) {
 size_t sa_lds_bytes(int n, int D, int row_len, int qw, bool big) {
     if (sa_use_swar(1 + (row_len > kDigitSize ? 1 : 0), row_len))
         return big ? core::swar_big_lds_bytes(n, qw) : core::swar_layout(n, D, row_len, qw, nullptr, nullptr);
-    return core::sa_layout(n, D, row_len, qw, nullptr, nullptr);
+    return big ? core::sa_big_layout(n, row_len, qw, nullptr, nullptr)
+               : core::sa_layout(n, D, row_len, qw, nullptr, nullptr);
 }
 
 size_t sa_big_bytes(int n, int D) { return core::swar_big_bytes(n, D); }
@@ -353,11 +360,28 @@ hipError_t launch_sa(const SaLaunch &L, hipStream_t s, size_t lds_limit) {
     a.k0 = (uint32_t)L.seed;
     a.k1 = (uint32_t)(L.seed >> 32);
     a.big = L.big;
-    const bool big = L.big != nullptr;
+    const bool swar = sa_use_swar(L.nd, L.row_len);
+    const bool big = L.global_instance;
     const size_t lds = sa_lds_bytes(L.n, L.D, L.row_len, L.qw, big);
-    if (lds > lds_limit || (big && !sa_use_swar(L.nd, L.row_len))) return hipErrorInvalidValue;
+    if (lds > lds_limit || (big && swar && L.big == nullptr)) return hipErrorInvalidValue;
     const int quads = (L.reads + 3) / 4;
     const int grid = (quads + L.qw - 1) / L.qw;
+    if (big && !swar) {
+        switch (L.nd) {
+            case 1:
+                hipLaunchKernelGGL((sa_kernel<1, 0, true>), dim3(grid), dim3(L.threads), lds, s, a);
+                break;
+            case 2:
+                hipLaunchKernelGGL((sa_kernel<2, 0, true>), dim3(grid), dim3(L.threads), lds, s, a);
+                break;
+            case 3:
+                hipLaunchKernelGGL((sa_kernel<3, 0, true>), dim3(grid), dim3(L.threads), lds, s, a);
+                break;
+            default:
+                return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     if (big) {
         hipError_t e = launch_big_prep(a, s);
         if (e != hipSuccess) return e;
@@ -437,7 +461,7 @@ int sa_stream_plan(const SaLaunch &L, int num_cus, int force_grid) {
     const int quads = (L.reads + 3) / 4;
     const int G = (quads + L.qw - 1) / L.qw;
     const int W = (L.wpl == 2 && L.qw == 2) ? 2 : 1;
-    const bool big = L.big != nullptr;
+    const bool big = L.global_instance;
     const size_t lds = sa_lds_bytes(L.n, L.D, L.row_len, L.qw, big);
     const int dk = (L.D == 6 || L.D == 4 || L.D == 8) ? L.D : 0;
     int per_cu = 0;

@@ -55,6 +55,25 @@ __host__ __device__ inline size_t sa_layout(int n, int D, int row_len, int qw, S
     return end;
 }
 
+// Layout when the instance stays in global memory (too large for the LDS beside
+// the spins): LDS holds the two threshold rows, the spins and the accumulators.
+__host__ __device__ inline size_t sa_big_layout(int n, int row_len, int qw, SaLds *L,
+                                                unsigned char *base) {
+    size_t o_tab = 0;
+    size_t o_S = o_tab + (size_t)2 * row_len * 4;
+    size_t o_E = (o_S + (size_t)n * qw * 4 + 7) & ~(size_t)7;
+    size_t end = o_E + (size_t)4 * qw * 8;
+    if (L) {
+        L->nbr = nullptr;
+        L->hpos = nullptr;
+        L->ord = nullptr;
+        L->tab = reinterpret_cast<uint32_t *>(base + o_tab);
+        L->S = reinterpret_cast<uint32_t *>(base + o_S);
+        L->E2 = reinterpret_cast<unsigned long long *>(base + o_E);
+    }
+    return end;
+}
+
 // One schedule over quads [q0, q0 + qw) of one instance.
 struct SaItem {
     const int32_t *image;
@@ -76,12 +95,12 @@ struct Fields {
 // nb points at record 0 of p, consecutive records `stride` apart.
 __device__ __forceinline__ Fields local_fields(const uint32_t *__restrict__ nb,
                                                const uint32_t *__restrict__ S, int D, int qw,
-                                               int q, int32_t hv, int stride) {
+                                               int q, int32_t hv, size_t stride) {
     Fields F;
 #pragma unroll
     for (int b = 0; b < 4; ++b) F.f[b] = hv;
     for (int k = 0; k < D; ++k) {
-        const uint32_t rec = nb[(size_t)k * stride];
+        const uint32_t rec = nb[k * stride];
         const int32_t Jv = (int32_t)(int16_t)(rec & 0xffffu);
         const uint32_t w = S[(rec >> 16) * qw + q];
 #pragma unroll
@@ -125,6 +144,19 @@ __device__ __forceinline__ uint32_t metropolis_mask(const int32_t x[4], const ui
     return mask;
 }
 
+// Points the instance fields at the image in global memory (records position-major:
+// record k of position p at nbr[p * D + k]) and loads the colour-class starts.
+// Ends with a barrier.
+__device__ inline void sa_bind_image(SaLds *L, const SaItem &a, int *cs) {
+    const int32_t *img = a.image;
+    const int n = a.n;
+    if ((int)threadIdx.x <= a.C) cs[threadIdx.x] = img[3 + threadIdx.x];
+    L->ord = const_cast<int32_t *>(img + kImgHeader);
+    L->hpos = const_cast<int32_t *>(img + kImgHeader + 2 * n);
+    L->nbr = reinterpret_cast<uint32_t *>(const_cast<int32_t *>(img + kImgHeader + 3 * n));
+    __syncthreads();
+}
+
 // Copies the instance image into LDS (ELL records, biases, order).  Ends with a barrier.
 __device__ inline void sa_load_instance(const SaLds &L, const SaItem &a, int *cs) {
     const int n = a.n, D = a.D, T = blockDim.x, tid = threadIdx.x;
@@ -142,12 +174,14 @@ __device__ inline void sa_load_instance(const SaLds &L, const SaItem &a, int *cs
     __syncthreads();
 }
 
-// The whole schedule for quads [q0, q0+qw) of an instance resident in LDS.
+// The whole schedule for quads [q0, q0+qw) of an instance resident in LDS
+// (neighbour-major records), or in global memory when BIG (position-major).
 // Starts and ends with a barrier, so LDS can be reused by the caller.
-template <int ND>
+template <int ND, bool BIG = false>
 __device__ void sa_run(const SaLds &L, const SaItem &a, const int *cs) {
     const int n = a.n, D = a.D, qw = a.qw, T = blockDim.x, tid = threadIdx.x;
     const int q0 = a.q0;
+    const size_t rec_p = BIG ? (size_t)D : 1, rec_k = BIG ? 1 : (size_t)n;
     const int q = tid % qw, slot = tid / qw, nslots = T / qw;
     const bool active = slot < nslots;
     for (int k = tid; k < a.row_len; k += T) L.tab[k] = a.tables[k];
@@ -187,7 +221,7 @@ __device__ void sa_run(const SaLds &L, const SaItem &a, const int *cs) {
             const int pe = cs[c + 1];
             for (int p = cs[c] + slot; active && p < pe; p += nslots) {
                 const uint32_t self = L.S[(size_t)p * qw + q];
-                const Fields F = local_fields(L.nbr + p, L.S, D, qw, q, L.hpos[p], n);
+                const Fields F = local_fields(L.nbr + p * rec_p, L.S, D, qw, q, L.hpos[p], rec_k);
                 int32_t x[4];
 #pragma unroll
                 for (int b = 0; b < 4; ++b) x[b] = dev::spin_of(self, b) > 0 ? -F.f[b] : F.f[b];
@@ -204,7 +238,7 @@ __device__ void sa_run(const SaLds &L, const SaItem &a, const int *cs) {
         long long e2[4] = {0, 0, 0, 0};
         for (int p = slot; active && p < n; p += nslots) {
             const uint32_t self = L.S[(size_t)p * qw + q];
-            const Fields F = local_fields(L.nbr + p, L.S, D, qw, q, L.hpos[p], n);
+            const Fields F = local_fields(L.nbr + p * rec_p, L.S, D, qw, q, L.hpos[p], rec_k);
 #pragma unroll
             for (int b = 0; b < 4; ++b)
                 e2[b] += (long long)dev::spin_of(self, b) * ((long long)L.hpos[p] + F.f[b]);

@@ -256,3 +256,56 @@ def test_sa_beyond_lds_streamed_sampled_reads(spv, ctx):
         osp, oE = oracle.sa_sample(inst, betas, seed=5, r_begin=r, r_end=r + 1)
         assert np.array_equal(sp[r], osp[0]) and E[r] == oE[0], r
     assert np.array_equal(E, oracle.energy(inst, sp))
+
+
+def _x_bound(inst):
+    a, b, w = inst.edges()
+    xb = np.abs(np.asarray(inst.h, np.int64)).copy()
+    np.add.at(xb, a, np.abs(w))
+    np.add.at(xb, b, np.abs(w))
+    return int(xb.max())
+
+
+GENERAL = [
+    ("cubic4_one_digit_wide_table", lambda: si.cubic_lattice(4, "gauss", seed=4, scale_log2=5), 20, 50, (0.1, 3.0)),
+    SMALL[3],
+    SMALL[4],
+]
+
+
+@pytest.mark.parametrize("name,make,reads,sweeps,br", GENERAL, ids=[c[0] for c in GENERAL])
+def test_sa_general_body_global_instance_forced_small(spv, ctx, name, make, reads, sweeps, br):
+    """The general body (tables wider than one byte-parallel row) reading its instance
+    from global memory, forced on small cases, against the oracle."""
+    inst = make()
+    if name.startswith("cubic4_one"):
+        assert 256 <= _x_bound(inst) < 512  # one digit, but too wide for the byte-parallel body
+    betas = si.linear_betas(br[0], br[1], sweeps)
+    P = spv.Problem.from_instance(inst)
+    _say(f"[sa] general body, global instance: {name} n={inst.n}")
+    sp, E = _with_env({"SPVAR_SA_BIG": 1}, lambda: spv.spv_sample(ctx, P, betas, reads, 32))
+    assert spv.spv_sample_last_shape(ctx)["global_instance"] == 1
+    osp, oE = oracle.sa_sample(inst, betas, reads=reads, seed=32, threads=8)
+    assert np.array_equal(sp.cpu().numpy(), osp) and np.array_equal(E.cpu().numpy(), oE)
+
+
+GENERAL_BIG = [
+    ("cubic20_gauss_n8000", lambda: si.cubic_lattice(20, "gauss", seed=9, scale_log2=10), 12, 30),
+    ("sparse12000_three_digits", lambda: si.random_sparse(12000, 10.0, seed=5, scale_log2=14,
+                                                          dist=("uniform_nonzero", 32767)), 8, 10),
+]
+
+
+@pytest.mark.parametrize("name,make,reads,sweeps", GENERAL_BIG, ids=[c[0] for c in GENERAL_BIG])
+def test_sa_general_body_beyond_lds_matches_oracle(spv, ctx, name, make, reads, sweeps):
+    """Instances with multi-digit tables whose records do not fit the LDS (the L = 20
+    Gaussian cube, N = 8000; a sparse N = 12,000 graph of degree up to 24) take the
+    global-instance general body automatically; the sample equals the oracle's."""
+    inst = make()
+    betas = si.linear_betas(0.1, 3.0, sweeps)
+    P = spv.Problem.from_instance(inst)
+    _say(f"[sa] general body beyond LDS: {name} n={inst.n}")
+    sp, E = spv.spv_sample(ctx, P, betas, reads, 78)
+    assert spv.spv_sample_last_shape(ctx)["global_instance"] == 1
+    osp, oE = oracle.sa_sample(inst, betas, reads=reads, seed=78, threads=8)
+    assert np.array_equal(sp.cpu().numpy(), osp) and np.array_equal(E.cpu().numpy(), oE)

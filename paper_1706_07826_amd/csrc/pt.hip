@@ -200,11 +200,15 @@ __global__ __launch_bounds__(1024) void pt_kernel(PtArgs a) {
                         d[b] = up[b] ? (((uint32_t)x[b] >> (kDigitBits * j)) & (kDigitSize - 1)) : 0u;
                         need |= pass[b] && d[b] != 0;
                     }
+                    // thresholds loaded for every replica (a zero digit reads a valid entry it
+                    // ignores), so the four LDS reads overlap the Philox block
+                    uint32_t th[4];
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) th[b] = tb[b][j * kDigitSize + d[b]];
                     if (need) {
                         const dev::Words4 w = dev::philox(i, t, quad, (2u << 24) | (uint32_t)j, a.k0, a.k1);
 #pragma unroll
-                        for (int b = 0; b < 4; ++b)
-                            if (d[b] != 0) pass[b] = pass[b] && (w.w[b] < tb[b][j * kDigitSize + d[b]]);
+                        for (int b = 0; b < 4; ++b) pass[b] = pass[b] & ((d[b] == 0) | (w.w[b] < th[b]));
                     }
                 }
                 uint32_t mask = 0;

@@ -53,6 +53,8 @@ constexpr int kRecBatch = 8;
 // Local fields f[b] = h + sum_k J_k s_k[b] of the 4 replicas in word q of
 // position p (spins S[pos][nq], records rec(k, p) = pos << 16 | uint16 J).
 // DK > 0: exactly DK records per site (straight-line code); DK = 0: D at run time.
+// Positions (16 bits) and word counts fit 24 bits, so the word index takes the
+// full-rate 24-bit multiply rather than the quarter-rate 32-bit one.
 template <int DK = 0, typename Rec>
 __device__ __forceinline__ void quad_fields(Rec rec, int D, int p, const uint32_t *__restrict__ S, int nq, int q,
                                             int32_t h, int32_t f[4]) {
@@ -63,7 +65,7 @@ __device__ __forceinline__ void quad_fields(Rec rec, int D, int p, const uint32_
 #pragma unroll
         for (int u = 0; u < DK; ++u) rr[u] = rec(u, p);
 #pragma unroll
-        for (int u = 0; u < DK; ++u) w[u] = S[(rr[u] >> 16) * (uint32_t)nq + (uint32_t)q];
+        for (int u = 0; u < DK; ++u) w[u] = S[__umul24(rr[u] >> 16, (uint32_t)nq) + (uint32_t)q];
 #pragma unroll
         for (int u = 0; u < DK; ++u) {
             const int32_t Jv = (int32_t)(int16_t)(rr[u] & 0xffffu);
@@ -78,7 +80,7 @@ __device__ __forceinline__ void quad_fields(Rec rec, int D, int p, const uint32_
         for (int u = 0; u < kRecBatch; ++u) rr[u] = (k0 + u < D) ? rec(k0 + u, p) : 0u;
         uint32_t w[kRecBatch];
 #pragma unroll
-        for (int u = 0; u < kRecBatch; ++u) w[u] = (k0 + u < D) ? S[(rr[u] >> 16) * nq + q] : 0u;
+        for (int u = 0; u < kRecBatch; ++u) w[u] = (k0 + u < D) ? S[__umul24(rr[u] >> 16, (uint32_t)nq) + q] : 0u;
 #pragma unroll
         for (int u = 0; u < kRecBatch; ++u) {
             const int32_t Jv = (int32_t)(int16_t)(rr[u] & 0xffffu);

@@ -102,7 +102,7 @@ __device__ __forceinline__ Fields local_fields(const uint32_t *__restrict__ nb,
     for (int k = 0; k < D; ++k) {
         const uint32_t rec = nb[k * stride];
         const int32_t Jv = (int32_t)(int16_t)(rec & 0xffffu);
-        const uint32_t w = S[(rec >> 16) * qw + q];
+        const uint32_t w = S[__umul24(rec >> 16, (uint32_t)qw) + q];
 #pragma unroll
         for (int b = 0; b < 4; ++b) F.f[b] += Jv * dev::spin_of(w, b);
     }
@@ -130,11 +130,15 @@ __device__ __forceinline__ uint32_t metropolis_mask(const int32_t x[4], const ui
             d[b] = up[b] ? (((uint32_t)x[b] >> (kDigitBits * j)) & (kDigitSize - 1)) : 0u;
             need |= pass[b] && d[b] != 0;
         }
+        // thresholds loaded for every replica (a zero digit reads a valid entry it
+        // ignores), so the four LDS reads overlap the Philox block
+        uint32_t th[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) th[b] = tab[j * kDigitSize + d[b]];
         if (need) {
             const dev::Words4 w = dev::philox(i, t, quad, (2u << 24) | (uint32_t)j, k0, k1);
 #pragma unroll
-            for (int b = 0; b < 4; ++b)
-                if (d[b] != 0) pass[b] = pass[b] && (w.w[b] < tab[j * kDigitSize + d[b]]);
+            for (int b = 0; b < 4; ++b) pass[b] = pass[b] & ((d[b] == 0) | (w.w[b] < th[b]));
         }
     }
     uint32_t mask = 0;

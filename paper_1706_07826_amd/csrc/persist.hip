@@ -87,41 +87,98 @@ __device__ __forceinline__ unsigned long long order_key(long long e) {
 }
 
 // 1. Elite selection: the first m rows in (E, row) order, emitted by row.
+// The m-th smallest key is found by a radix select, most significant byte
+// first, that starts at the highest byte in which the smallest and largest keys
+// differ (the bytes above are common to every key, so every pass over them
+// would keep all keys and the rank unchanged).  Each wavefront counts into its
+// own histogram, so keys sharing a byte value do not serialise on one counter.
 __global__ __launch_bounds__(1024) void elite_kernel(const long long *__restrict__ E, int R, int m,
                                                      FixScratch f) {
-    __shared__ unsigned int hist[256];
+    constexpr int kWaves = 1024 / 64;
+    __shared__ unsigned int hist[kWaves][256];
+    __shared__ unsigned long long kmin_w[kWaves], kmax_w[kWaves];
     __shared__ unsigned long long prefix_s;
-    __shared__ int need_s;
+    __shared__ int need_s, pass0_s;
     __shared__ int tmp[1024 / 64 + 1];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
+    {
+        unsigned long long lo = ~0ull, hi = 0ull;
+        for (int r = tid; r < R; r += blockDim.x) {
+            const unsigned long long key = order_key(E[r]);
+            lo = key < lo ? key : lo;
+            hi = key > hi ? key : hi;
+        }
+        for (int d = 32; d >= 1; d >>= 1) {
+            const unsigned long long ol = __shfl_xor(lo, d, 64), oh = __shfl_xor(hi, d, 64);
+            lo = ol < lo ? ol : lo;
+            hi = oh > hi ? oh : hi;
+        }
+        if (lane == 0) {
+            kmin_w[wid] = lo;
+            kmax_w[wid] = hi;
+        }
+    }
+    __syncthreads();
     if (tid == 0) {
-        prefix_s = 0ull;
+        unsigned long long lo = kmin_w[0], hi = kmax_w[0];
+        for (int w = 1; w < nw; ++w) {
+            lo = kmin_w[w] < lo ? kmin_w[w] : lo;
+            hi = kmax_w[w] > hi ? kmax_w[w] : hi;
+        }
+        const unsigned long long x = lo ^ hi;
+        const int p0 = x == 0ull ? -1 : (63 - __clzll((long long)x)) / 8;
+        pass0_s = p0;
+        prefix_s = p0 < 0 ? lo : (p0 == 7 ? 0ull : lo & (~0ull << (8 * p0 + 8)));
         need_s = m;  // rank (1-based) of the wanted key among the candidates
         f.hdr[0] = 0;
     }
     __syncthreads();
-    // Radix select over the 64-bit order-preserving keys, most significant byte first.
-    for (int pass = 7; pass >= 0; --pass) {
-        for (int k = tid; k < 256; k += blockDim.x) hist[k] = 0;
+    for (int pass = pass0_s; pass >= 0; --pass) {
+        for (int k = tid; k < kWaves * 256; k += blockDim.x) (&hist[0][0])[k] = 0u;
         __syncthreads();
         const unsigned long long prefix = prefix_s;
         const int shift = 8 * pass;
         const unsigned long long hi_mask = (pass == 7) ? 0ull : (~0ull << (shift + 8));
         for (int r = tid; r < R; r += blockDim.x) {
             const unsigned long long key = order_key(E[r]);
-            if ((key & hi_mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+            if ((key & hi_mask) == prefix) atomicAdd(&hist[wid][(key >> shift) & 255u], 1u);
         }
         __syncthreads();
-        if (tid == 0) {
-            int need = need_s;
-            unsigned int acc = 0;
-            int b = 0;
-            for (; b < 256; ++b) {
-                if (acc + hist[b] >= (unsigned int)need) break;
-                acc += hist[b];
+        if (tid < 256) {
+            unsigned int c = 0;
+            for (int w = 0; w < nw; ++w) c += hist[w][tid];
+            hist[0][tid] = c;
+        }
+        __syncthreads();
+        if (wid == 0) {
+            // lane l holds bins 4l..4l+3; the first lane whose inclusive count
+            // reaches the rank holds the wanted bin
+            const int need = need_s;
+            unsigned int c[4], sum = 0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                c[u] = hist[0][4 * lane + u];
+                sum += c[u];
             }
-            need_s = need - (int)acc;
-            prefix_s = prefix | ((unsigned long long)b << shift);
+            unsigned int incl = sum;
+            for (int d = 1; d < 64; d <<= 1) {
+                const unsigned int y = __shfl_up(incl, d, 64);
+                if (lane >= d) incl += y;
+            }
+            const unsigned long long hit = __ballot(incl >= (unsigned int)need);
+            const int src = __ffsll((long long)hit) - 1;
+            if (lane == src) {
+                unsigned int acc = incl - sum;
+                int b = 4 * lane;
+#pragma unroll
+                for (int u = 0; u < 3; ++u)
+                    if (acc + c[u] < (unsigned int)need && b == 4 * lane + u) {
+                        acc += c[u];
+                        ++b;
+                    }
+                need_s = need - (int)acc;
+                prefix_s = prefix | ((unsigned long long)b << shift);
+            }
         }
         __syncthreads();
     }

@@ -87,6 +87,29 @@ def test_persist_parity(spv, ctx, name, make, R, eps, theta, gauge, mirror, eran
         assert info["pivot"] >= 0
 
 
+ELITE_KEYS = [
+    ("full_int64_range", lambda rng, R: rng.integers(-2**62, 2**62, size=R)),
+    ("all_equal", lambda rng, R: np.full(R, -5)),
+    ("common_high_bytes_low_byte_ties", lambda rng, R: -10**12 + rng.integers(0, 200, size=R)),
+    ("sign_crossing", lambda rng, R: rng.integers(-1, 1, size=R)),
+    ("wide_40_bit", lambda rng, R: rng.integers(-2**40, 2**40, size=R)),
+]
+
+
+@pytest.mark.parametrize("name,make_E", ELITE_KEYS, ids=[c[0] for c in ELITE_KEYS])
+def test_persist_elite_selection_over_key_ranges(spv, ctx, name, make_E):
+    """Elite selection (the m lowest (E, row) keys) over energies that share all, some or none of
+    their high bytes, with ties at the cut; random rows and a low threshold make the fixed set
+    depend on exactly which rows are elite."""
+    inst = si.random_sparse(200, 3.0, seed=31)
+    R = 3000
+    rng = np.random.default_rng(32)
+    S = si.random_spins(R, inst.n, seed=33)
+    E = np.asarray(make_E(rng, R), dtype=np.int64)
+    print(f"[persist] elite keys: {name}", flush=True)
+    _compare(spv, ctx, inst, S, E, 0.02, 0.2, 0)
+
+
 def test_persist_on_oracle_sampler_output(spv, ctx):
     inst = si.cubic_lattice(4, "pm1", seed=21)
     S, E = oracle.sa_sample(inst, si.linear_betas(0.1, 3.0, 300), reads=200, seed=5, threads=8)

@@ -289,6 +289,25 @@ def test_sa_general_body_global_instance_forced_small(spv, ctx, name, make, read
     assert np.array_equal(sp.cpu().numpy(), osp) and np.array_equal(E.cpu().numpy(), oE)
 
 
+def test_sa_general_body_global_instance_ragged_reads_and_resume(spv, ctx):
+    """The global-instance general body with a read count that leaves the last quad partly
+    empty, from caller states at a sweep offset, against the oracle."""
+    import torch
+
+    inst = si.cubic_lattice(5, "gauss", seed=12, scale_log2=10)
+    betas = si.linear_betas(0.1, 3.0, 70)
+    P = spv.Problem.from_instance(inst)
+    reads = 13
+    init = si.random_spins(reads, inst.n, seed=23)
+    _say("[sa] general body, global instance: 13 reads from caller states, sweep offset 30")
+    sp, E = _with_env({"SPVAR_SA_BIG": 1},
+                      lambda: spv.spv_sample(ctx, P, betas[30:], reads, 556, sweep_offset=30,
+                                             init_spins=torch.as_tensor(init).cuda()))
+    assert spv.spv_sample_last_shape(ctx)["global_instance"] == 1
+    osp, oE = oracle.sa_sample(inst, betas[30:], reads=reads, seed=556, sweep_offset=30, init=init)
+    assert np.array_equal(sp.cpu().numpy(), osp) and np.array_equal(E.cpu().numpy(), oE)
+
+
 GENERAL_BIG = [
     ("cubic20_gauss_n8000", lambda: si.cubic_lattice(20, "gauss", seed=9, scale_log2=10), 12, 30),
     ("sparse12000_three_digits", lambda: si.random_sparse(12000, 10.0, seed=5, scale_log2=14,

@@ -2,7 +2,8 @@
 
 A ctypes wrapper around ``spvar_oracle.c``: a plain, slow, sequential C
 implementation of the samplers (Metropolis SA, parallel tempering with
-Houdayer cluster moves and the top-10 sample of Sec. III.D.1) and of the
+Houdayer cluster moves and the top-10 sample of Sec. III.D.1, simulated
+quantum annealing as path-integral Monte Carlo) and of the
 persistence step (Algorithm 1: elite selection, fixing, reduction).  Its
 definitions are written out in the header comment of that file.
 
@@ -71,6 +72,8 @@ def lib():
         L.orc_ispvar.argtypes = [vp, vp, i32, i32, u64, i32, f64, f64, i32, vp, vp, vp]
         L.orc_icm_step.argtypes = [vp, vp, vp, vp, vp, u32, vp]
         L.orc_colour_jp.argtypes = [vp, u64, vp, vp, i32]
+        L.orc_sqa_coupling.argtypes = [f64, f64, i32, i32, vp]
+        L.orc_sqa_sample.argtypes = [vp, vp, vp, i32, i32, u64, i32, i32, vp, vp, vp, vp, vp]
         L.orc_icm_step.restype = C.c_int
         L.orc_swap_test.argtypes = [i64, f64, i32, u32, u32, u32, u64]
         L.orc_swap_test.restype = C.c_int
@@ -208,6 +211,50 @@ def sa_sample(inst, betas, reads=None, seed=0, sweep_offset=0, r_begin=0, r_end=
         with ThreadPoolExecutor(threads) as ex:
             list(ex.map(lambda p: run(*p), _split(r_begin, r_end, threads)))
     return spins, E
+
+
+def sqa_coupling(beta, gamma, trotter, scale_log2):
+    """Inter-slice coupling Jp of one SQA sweep in integer units."""
+    out = np.zeros(1, dtype=np.int64)
+    rc = lib().orc_sqa_coupling(float(beta), float(gamma), int(trotter), int(scale_log2), _ptr(out))
+    if rc:
+        raise OracleError(rc, "sqa_coupling")
+    return int(out[0])
+
+
+def sqa_sample(inst, betas, gammas, trotter, reads=None, seed=0, r_begin=0, r_end=None, slices=False,
+               threads=1):
+    """Reads [r_begin, r_end) of an SQA job (path-integral Monte Carlo over `trotter` slices).
+    Returns (spins int8[R][n], E int64[R], best int32[R]) -- the lowest-energy slice of each
+    read -- and, with slices=True, also (slices int8[R][P][n], Ecl int64[R][P])."""
+    b = _Bound(inst)
+    betas = np.ascontiguousarray(betas, dtype=np.float64)
+    gammas = np.ascontiguousarray(gammas, dtype=np.float64)
+    assert betas.size == gammas.size
+    if r_end is None:
+        r_end = reads
+    R, n, P = r_end - r_begin, inst.n, int(trotter)
+    spins = np.zeros((R, n), dtype=np.int8)
+    E = np.zeros(R, dtype=np.int64)
+    best = np.zeros(R, dtype=np.int32)
+    sl = np.zeros((R, P, n), dtype=np.int8) if slices else None
+    ecl = np.zeros((R, P), dtype=np.int64) if slices else None
+
+    def run(lo, hi):
+        a, z = lo - r_begin, hi - r_begin
+        rc = lib().orc_sqa_sample(b.ref, _ptr(betas), _ptr(gammas), betas.size, P,
+                                  C.c_uint64(seed & (2**64 - 1)), lo, hi,
+                                  _ptr(sl[a:z]) if slices else None, _ptr(ecl[a:z]) if slices else None,
+                                  _ptr(spins[a:z]), _ptr(E[a:z]), _ptr(best[a:z]))
+        if rc:
+            raise OracleError(rc, "sqa_sample")
+
+    if threads <= 1 or R < 2:
+        run(r_begin, r_end)
+    else:
+        with ThreadPoolExecutor(threads) as ex:
+            list(ex.map(lambda q: run(*q), _split(r_begin, r_end, threads)))
+    return (spins, E, best, sl, ecl) if slices else (spins, E, best)
 
 
 def pt_sample(inst, betas, runs, chains, sweeps, seed=0, sweep_offset=0, icm=None, run_begin=0,

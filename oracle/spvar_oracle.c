@@ -87,6 +87,25 @@
  *    0's fixing rows, start 0's solving rows, start 1's fixing rows, ...; a
  *    solving row is completed with the start's fixed values.
  *
+ *  Simulated quantum annealing (Sec. III, "SQA": discrete-time path-integral
+ *    Monte Carlo of the transverse-field Ising model, written from the
+ *    Suzuki-Trotter mapping of Martonak, Santoro and Tosatti, Phys. Rev. B 66,
+ *    094203 (2002)).  The paper names the sampler but not its parameters; the
+ *    Trotter number P and the schedules beta_t, Gamma_t are the caller's.  P
+ *    slices s^0..s^{P-1} per read form a ring; the effective energy in integer
+ *    units is E_eff = sum_k E(s^k) - Jp_t sum_k sum_i s^k_i s^{(k+1) mod P}_i,
+ *    sampled at inverse temperature beta_t / P, with Jp_t = round(P * Jperp *
+ *    2^scale) (half away from zero) and Jperp = -ln(tanh(beta_t Gamma_t / P))
+ *    / (2 beta_t), evaluated in double in exactly that order.  Updating spin i
+ *    of slice k: g = f_i(s^k) - Jp_t (s^{k-1}_i + s^{k+1}_i), x = -s^k_i g, the
+ *    digit test above with tables for beta_t / P.  A sweep visits the colour
+ *    classes in order and, inside a class, the even slices and then the odd
+ *    ones (each an independent set).  Slice k of read u is replica r = u P +
+ *    (k mod 2) P/2 + floor(k/2) (even slices first), so its random words are
+ *    Philox(i, t, r>>2, (6<<24)|j)[r&3] and its initial spins those of replica
+ *    r above.  The sample of a read is its lowest-energy slice after the last
+ *    sweep (ties: lowest k), with that slice's energy E.
+ *
  *  Colour classes (the sweep's independent sets; not a step the paper states:
  *    the parallel sweep needs them).  Jones-Plassmann: vertex v has priority
  *    (word 0 of Philox(v, 0, 0, 5 << 24) under the seed, then v), higher
@@ -123,6 +142,7 @@
 #define TAG_METRO 2u
 #define TAG_SWAP 3u
 #define TAG_ICM 4u
+#define TAG_SQA 6u
 #define DIGIT_BITS 9
 #define DIGIT_SIZE 512
 #define TOPK 10
@@ -398,6 +418,126 @@ int orc_sa_sample(const orc_problem *P, const double *betas, int32_t sweeps, uin
     }
     free(tables);
     free(order);
+    return ORC_OK;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Simulated quantum annealing (path-integral Monte Carlo over P slices).  */
+/* ---------------------------------------------------------------------- */
+/* Inter-slice coupling of one sweep in integer units (see the header). */
+int orc_sqa_coupling(double beta, double gamma, int32_t trotter, int32_t scale_log2, int64_t *jp)
+{
+    double arg, jperp, v;
+    if (!(beta > 0.0) || !(gamma > 0.0) || isinf(beta) || isinf(gamma) || trotter < 1)
+        return ORC_EINVAL;
+    arg = beta * gamma / (double)trotter;
+    jperp = -0.5 * log(tanh(arg)) / beta;
+    v = jperp * (double)trotter * ldexp(1.0, scale_log2);
+    if (!(v >= 0.0) || !(v < 16777216.0))
+        return ORC_ERANGE;
+    *jp = (int64_t)floor(v + 0.5);
+    return ORC_OK;
+}
+
+/* Replica index of slice k of read u (even slices first). */
+static uint32_t sqa_replica(int32_t u, int32_t k, int32_t trotter)
+{
+    return (uint32_t)((int64_t)u * trotter + (int64_t)(k & 1) * (trotter / 2) + (k >> 1));
+}
+
+/* Reads u in [r_begin, r_end): slices_out [R][P][n] and Ecl_out [R][P] hold
+ * every slice after the last sweep (either may be NULL); spins_out [R][n],
+ * E_out [R] and best_out [R] the sample (lowest-energy slice). */
+int orc_sqa_sample(const orc_problem *P, const double *betas, const double *gammas, int32_t sweeps,
+                   int32_t trotter, uint64_t seed, int32_t r_begin, int32_t r_end, int8_t *slices_out,
+                   int64_t *Ecl_out, int8_t *spins_out, int64_t *E_out, int32_t *best_out)
+{
+    int32_t nd, t, u, k, c, par, i, j;
+    int64_t jmax = 0, *jp;
+    uint32_t *tables;
+    int8_t *s;
+    const int32_t n = P ? P->n : 0;
+    int rc = check_problem(P);
+    if (rc)
+        return rc;
+    if (sweeps < 0 || trotter < 2 || (trotter & 1) || r_begin < 0 || r_end < r_begin)
+        return ORC_EINVAL;
+    jp = (int64_t *)malloc(sizeof(int64_t) * (size_t)(sweeps > 0 ? sweeps : 1));
+    if (!jp)
+        return ORC_ENOMEM;
+    for (t = 0; t < sweeps; ++t) {
+        rc = orc_sqa_coupling(betas[t], gammas[t], trotter, P->scale_log2, &jp[t]);
+        if (rc) {
+            free(jp);
+            return rc;
+        }
+        if (jp[t] > jmax)
+            jmax = jp[t];
+    }
+    nd = digits_for(orc_x_max(P) + 2 * jmax);
+    tables = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(sweeps > 0 ? sweeps : 1) * nd * DIGIT_SIZE);
+    s = (int8_t *)malloc((size_t)trotter * (n > 0 ? n : 1));
+    if (!tables || !s) {
+        free(jp);
+        free(tables);
+        free(s);
+        return ORC_ENOMEM;
+    }
+    for (t = 0; t < sweeps; ++t)
+        build_table(betas[t] / (double)trotter, 2, P->scale_log2, nd, tables + (size_t)t * nd * DIGIT_SIZE);
+    for (u = r_begin; u < r_end; ++u) {
+        int64_t bestE = 0;
+        int32_t best = 0;
+        for (k = 0; k < trotter; ++k)
+            init_spins(n, sqa_replica(u, k, trotter), seed, s + (size_t)k * n);
+        for (t = 0; t < sweeps; ++t) {
+            const uint32_t *T = tables + (size_t)t * nd * DIGIT_SIZE;
+            for (c = 0; c < P->n_colours; ++c)
+                for (par = 0; par < 2; ++par)
+                    for (i = 0; i < n; ++i) {
+                        if (P->colour[i] != c)
+                            continue;
+                        for (k = par; k < trotter; k += 2) {
+                            int8_t *sk = s + (size_t)k * n;
+                            const int8_t up = s[(size_t)((k + trotter - 1) % trotter) * n + i];
+                            const int8_t dn = s[(size_t)((k + 1) % trotter) * n + i];
+                            const int64_t g = local_field(P, sk, i) - jp[t] * (int64_t)(up + dn);
+                            const int64_t x = -(int64_t)sk[i] * g;
+                            const uint32_t r = sqa_replica(u, k, trotter);
+                            int accept = 1;
+                            if (x > 0)
+                                for (j = 0; j < nd && accept; ++j) {
+                                    uint32_t d = (uint32_t)((x >> (DIGIT_BITS * j)) & (DIGIT_SIZE - 1));
+                                    if (d != 0) {
+                                        uint32_t w = philox_word((uint32_t)i, (uint32_t)t, r >> 2,
+                                                                 (TAG_SQA << 24) | (uint32_t)j, seed, (int)(r & 3));
+                                        if (!(w < T[j * DIGIT_SIZE + d]))
+                                            accept = 0;
+                                    }
+                                }
+                            if (accept)
+                                sk[i] = (int8_t)(-sk[i]);
+                        }
+                    }
+        }
+        for (k = 0; k < trotter; ++k) {
+            const int64_t E = orc_energy(P, s + (size_t)k * n);
+            if (Ecl_out)
+                Ecl_out[(size_t)(u - r_begin) * trotter + k] = E;
+            if (k == 0 || E < bestE) {
+                bestE = E;
+                best = k;
+            }
+        }
+        if (slices_out)
+            memcpy(slices_out + (size_t)(u - r_begin) * trotter * n, s, (size_t)trotter * n);
+        memcpy(spins_out + (size_t)(u - r_begin) * n, s + (size_t)best * n, (size_t)n);
+        E_out[u - r_begin] = bestE;
+        best_out[u - r_begin] = best;
+    }
+    free(jp);
+    free(tables);
+    free(s);
     return ORC_OK;
 }
 

@@ -171,6 +171,35 @@ spv_status spv_lds_probe(spv_ctx *ctx, int32_t iters, double *bytes_per_s, hipSt
  * context scratch.  EINVAL for iters outside [1, 2^24]. */
 spv_status spv_philox_probe(spv_ctx *ctx, int32_t iters, double *blocks_per_s, hipStream_t stream);
 
+/*
+ * Simulated quantum annealing (Sec. III sampler "SQA": discrete-time
+ * path-integral Monte Carlo of the transverse-field Ising model; the paper
+ * names it without its parameters, so the Trotter number and both schedules
+ * are the caller's).
+ *   betas [sweeps]   host: inverse temperatures beta_t > 0, finite
+ *   gammas [sweeps]  host: transverse fields Gamma_t > 0, finite (same units as
+ *                    the couplings' real values)
+ *   trotter          slices P per read: a multiple of 8 in [8, 256]
+ *   reads            independent reads u = 0..reads-1
+ *   seed             Philox key
+ *   spins            device [reads][n] int8: each read's lowest-energy slice
+ *                    after the last sweep (ties: lowest slice index)
+ *   energies         device [reads] int64: E of that slice
+ * Each sweep samples E_eff = sum_k E(s^k) - Jp_t sum_k sum_i s^k_i s^{k+1}_i
+ * (slice ring) at inverse temperature beta_t / P, with Jp_t = round(P Jperp
+ * 2^scale_log2) half away from zero and Jperp = -ln(tanh(beta_t Gamma_t / P)) /
+ * (2 beta_t); sweeps visit the colour classes in order and, within a class,
+ * the even slices, then the odd ones.  Slice k of read u uses replica index
+ * u P + (k mod 2) P/2 + floor(k/2) for its Philox counters (Metropolis tag 6,
+ * initial state tag 1).  Bit-identical to the oracle.  EINVAL for bad
+ * arguments; ERANGE when Jp_t reaches 2^24 or x_bound + 2 max Jp needs more
+ * than 3 base-512 digits; ECAPACITY when the instance and one read's P slices
+ * (P/4 words per variable) exceed a workgroup's LDS.
+ */
+spv_status spv_sqa_sample(spv_ctx *ctx, const spv_problem *P, const double *betas, const double *gammas,
+                          int32_t sweeps, int32_t trotter, int32_t reads, uint64_t seed, int8_t *spins,
+                          int64_t *energies, hipStream_t stream);
+
 /* The launch shape the last spv_sample call on this context used: threads per
  * workgroup, quads (4 replicas) per workgroup, quad words per lane, sweep chunks
  * per group (1: one launch over all workgroups; more: streamed), and whether the

@@ -92,6 +92,7 @@ _SIGS = {
     "spv_last_error": ([_vp], C.c_char_p),
     "spv_problem_check": ([_vp, _P], C.c_int),
     "spv_sample": ([_vp, _P, _vp, _i32, _i32, _u64, _u32, _vp, _vp, _vp, _vp], C.c_int),
+    "spv_sqa_sample": ([_vp, _P, _vp, _vp, _i32, _i32, _i32, _u64, _vp, _vp, _vp], C.c_int),
     "spv_energy": ([_vp, _P, _vp, _i32, _vp, _vp], C.c_int),
     "spv_persist_fix": ([_vp, _P, _vp, _vp, _i32, _f64, _f64, _i32, C.POINTER(spv_fix_out), _vp],
                         C.c_int),
@@ -224,6 +225,25 @@ def spv_sample(ctx, P, betas, reads, seed, sweep_offset=0, init_spins=None, spin
                          _ptr(init_spins), _ptr(spins) if P.n else None, _ptr(energies),
                          _stream(stream))
     ctx.check(rc, "spv_sample")
+    return spins, energies
+
+
+def spv_sqa_sample(ctx, P, betas, gammas, trotter, reads, seed, spins=None, energies=None, stream=None):
+    """Simulated quantum annealing over `trotter` slices; returns (spins int8 [reads][n] -- each
+    read's lowest-energy slice --, energies int64 [reads]) on the device."""
+    b = np.ascontiguousarray(betas, dtype=np.float64)
+    g = np.ascontiguousarray(gammas, dtype=np.float64)
+    if b.size != g.size:
+        raise ValueError("betas and gammas differ in length")
+    if spins is None:
+        spins = torch.empty((reads, P.n), dtype=torch.int8, device=ctx.device)
+    if energies is None:
+        energies = torch.empty(reads, dtype=torch.int64, device=ctx.device)
+    ps = P.c_struct()
+    rc = _lib.spv_sqa_sample(ctx.handle, C.byref(ps), _ptr(b), _ptr(g), b.size, int(trotter), int(reads),
+                             C.c_uint64(seed & (2**64 - 1)), _ptr(spins) if P.n else None, _ptr(energies),
+                             _stream(stream))
+    ctx.check(rc, "spv_sqa_sample")
     return spins, energies
 
 

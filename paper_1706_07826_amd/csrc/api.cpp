@@ -313,7 +313,7 @@ void spv_ctx_destroy(spv_ctx *ctx) {
     if (ctx->c.stage) (void)hipHostFree(ctx->c.stage);
     if (ctx->c.stage_done) (void)hipEventDestroy(ctx->c.stage_done);
     for (DevBuf *b : {&ctx->c.image, &ctx->c.tables, &ctx->c.tables2, &ctx->c.scratch, &ctx->c.scratch2,
-                      &ctx->c.rounds, &ctx->c.pt, &ctx->c.pt_tab, &ctx->c.top, &ctx->c.serve, &ctx->c.merge, &ctx->c.ms, &ctx->c.tree, &ctx->c.sa_stream, &ctx->c.sa_big})
+                      &ctx->c.rounds, &ctx->c.pt, &ctx->c.pt_tab, &ctx->c.top, &ctx->c.serve, &ctx->c.merge, &ctx->c.ms, &ctx->c.tree, &ctx->c.sa_stream, &ctx->c.sa_big, &ctx->c.sqa})
         if (b->p) (void)hipFree(b->p);
     delete ctx;
 }
@@ -489,6 +489,79 @@ spv_status spv_sample(spv_ctx *ctx, const spv_problem *P, const double *betas, i
     }
     e = launch_sa(L, stream, c->lds_max);
     return hip_check(c, e, "sa launch");
+}
+
+spv_status spv_sqa_sample(spv_ctx *ctx, const spv_problem *P, const double *betas, const double *gammas,
+                          int32_t sweeps, int32_t trotter, int32_t reads, uint64_t seed, int8_t *spins,
+                          int64_t *energies, hipStream_t stream) {
+    if (!ctx) return SPV_EINVAL;
+    Ctx *c = &ctx->c;
+    DeviceGuard g(c->device);
+    spv_status st = check_problem_host(c, P);
+    if (st) return st;
+    if (sweeps < 0 || reads < 0) return set_err(c, SPV_EINVAL, "sweeps=%d reads=%d", sweeps, reads);
+    if (trotter < 8 || trotter > 256 || trotter % 8 != 0)
+        return set_err(c, SPV_EINVAL, "trotter=%d: a multiple of 8 in [8, 256]", trotter);
+    if (sweeps > 0 && (!betas || !gammas)) return set_err(c, SPV_EINVAL, "NULL betas/gammas");
+    // Inter-slice coupling per sweep, Jp = round(P Jperp 2^scale) with
+    // Jperp = -ln(tanh(beta Gamma / P)) / (2 beta), in double in this order.
+    std::vector<int32_t> jp((size_t)std::max(sweeps, 1), 0);
+    std::vector<double> bp((size_t)std::max(sweeps, 1), 0.0);
+    int64_t jmax = 0;
+    for (int t = 0; t < sweeps; ++t) {
+        const double beta = betas[t], gamma = gammas[t];
+        if (!(beta > 0.0) || !(gamma > 0.0) || std::isinf(beta) || std::isinf(gamma))
+            return set_err(c, SPV_EINVAL, "sweep %d: beta=%g gamma=%g (both > 0 and finite)", t, beta, gamma);
+        const double arg = beta * gamma / (double)trotter;
+        const double jperp = -0.5 * std::log(std::tanh(arg)) / beta;
+        const double v = jperp * (double)trotter * std::ldexp(1.0, P->scale_log2);
+        if (!(v >= 0.0) || !(v < 16777216.0))
+            return set_err(c, SPV_ERANGE, "sweep %d: slice coupling %g units outside [0, 2^24)", t, v);
+        jp[t] = (int32_t)std::floor(v + 0.5);
+        jmax = std::max<int64_t>(jmax, jp[t]);
+        bp[t] = beta / (double)trotter;
+    }
+    if (reads == 0) return SPV_OK;
+    if (!energies || (P->n > 0 && !spins)) return set_err(c, SPV_EINVAL, "NULL spins/energies");
+    if (P->n == 0) return hip_check(c, hipMemsetAsync(energies, 0, 8ull * reads, stream), "memset");
+    const int64_t xeff = (int64_t)P->x_bound + 2 * jmax;
+    if (xeff >= (int64_t)1 << 26) return set_err(c, SPV_ERANGE, "x_bound + 2 Jp = %lld beyond 2^26", (long long)xeff);
+    const int nd = digits_for(xeff);
+    if (nd > 3) return set_err(c, SPV_ERANGE, "x_bound + 2 Jp = %lld needs %d digits (max 3)", (long long)xeff, nd);
+    const int row_len = table_row_len(xeff);
+    const int n = P->n, D = P->max_degree;
+    if (sqa_lds_bytes(n, D, row_len, trotter) + 256 > c->lds_max)
+        return set_err(c, SPV_ECAPACITY, "SQA: %d slices of %d variables need %zu B of LDS > %zu", trotter, n,
+                       sqa_lds_bytes(n, D, row_len, trotter), c->lds_max);
+    st = ensure(c, c->image, image_words(n, D) * 4);
+    if (st) return st;
+    hipError_t e = launch_prep(P, static_cast<int32_t *>(c->image.p), stream);
+    if (e != hipSuccess) return hip_check(c, e, "prep launch");
+    if (sweeps > 0) {
+        if ((st = upload_tables(c, c->tables, bp.data(), sweeps, 2, P->scale_log2, nd, row_len, stream))) return st;
+        if ((st = upload(c, c->sqa, 0, jp.data(), sizeof(int32_t) * (size_t)sweeps, stream))) return st;
+    }
+    SqaLaunch L;
+    L.image = static_cast<const int32_t *>(c->image.p);
+    L.tables = static_cast<const uint32_t *>(c->tables.p);
+    L.jp = static_cast<const int32_t *>(c->sqa.p);
+    L.out = spins;
+    L.energies = energies;
+    L.n = n;
+    L.D = D;
+    L.C = P->n_colours;
+    L.row_len = row_len;
+    L.nd = nd;
+    L.sweeps = sweeps;
+    L.reads = reads;
+    L.P = trotter;
+    L.seed = seed;
+    // one lane per (site, word of one parity) of the largest colour class
+    const int tasks = (n + P->n_colours - 1) / P->n_colours * (trotter / 8);
+    L.threads = std::max(64, std::min(1024, (tasks + 63) / 64 * 64));
+    L.threads -= L.threads % (trotter / 8);
+    e = launch_sqa(L, stream);
+    return hip_check(c, e, "sqa launch");
 }
 
 spv_status spv_sample_last_shape(const spv_ctx *ctx, int32_t *threads, int32_t *quads_per_wg,

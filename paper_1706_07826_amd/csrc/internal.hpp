@@ -72,6 +72,7 @@ struct Ctx {
     DevBuf tree;    // tree pre-processing scratch
     DevBuf sa_stream;  // streamed SA: task counter, tagged spin words between chunks
     DevBuf sa_big;     // SA: byte-parallel instance in global memory (problems too large for LDS)
+    DevBuf sqa;        // SQA: inter-slice coupling per sweep
     TableCache tcache;
     std::vector<uint32_t> host_tables;
     void *batch_host = nullptr;  // pinned staging of descriptors and items
@@ -159,6 +160,18 @@ struct SaLaunch {
                                    // (sa_big_bytes); the general body reads the image itself
 };
 hipError_t launch_sa(const SaLaunch &L, hipStream_t s, size_t lds_limit);
+// Simulated quantum annealing: one workgroup per read, P Trotter slices in LDS.
+struct SqaLaunch {
+    const int32_t *image;
+    const uint32_t *tables;  // [sweeps][row_len] at beta_t / P
+    const int32_t *jp;       // [sweeps]
+    int8_t *out;
+    int64_t *energies;
+    int n, D, C, row_len, nd, sweeps, reads, P, threads;
+    uint64_t seed;
+};
+hipError_t launch_sqa(const SqaLaunch &L, hipStream_t s);
+size_t sqa_lds_bytes(int n, int D, int row_len, int P);
 // Streamed launch of the byte-parallel body (resident workgroups, chunked sweeps).
 int sa_stream_plan(const SaLaunch &L, int num_cus, int force_grid);  // 1: use launch_sa
 size_t sa_stream_bytes(int n, int reads, int qw);

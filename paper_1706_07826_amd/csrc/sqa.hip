@@ -1,0 +1,222 @@
+// Simulated quantum annealing (Sec. III, "SQA": discrete-time path-integral
+// Monte Carlo of the transverse-field Ising model over P Trotter slices, the
+// Suzuki-Trotter mapping of Martonak, Santoro and Tosatti, PRB 66, 094203).
+//
+// One workgroup per read.  LDS holds the position-ordered instance (the same
+// ELL image as the general SA body), the acceptance rows of this sweep and the
+// next (beta_t / P) and the read's P slices as P/4 words per site: slice
+// k = 2m + parity lives in word parity * P/8 + m/4, byte m % 4, so a word holds
+// four slices of one parity.  A sweep visits the colour classes in order and,
+// inside a class, the even-slice words and then the odd-slice words: every
+// update in such a pass reads only words the pass does not write (the
+// neighbouring sites of the class are in other classes, the neighbouring slices
+// have the other parity), and one Philox block serves the four slices of a word.
+//
+// Update of slice k at site i: g = f_i(s^k) - Jp_t (s^{k-1}_i + s^{k+1}_i) over
+// the slice ring, x = -s g, accepted iff x <= 0 or every nonzero base-512 digit
+// of x passes its threshold; the random words are Philox(i, t, quad, 6 << 24 |
+// digit)[byte], quad = read * P/4 + word.  After the last sweep the read's
+// sample is its lowest-energy slice (ties: lowest k).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "device.hpp"
+#include "internal.hpp"
+#include "sa_core.hpp"
+
+namespace spv {
+
+namespace {
+
+constexpr uint32_t kTagSqa = 6u;
+
+struct SqaArgs {
+    const int32_t *image;
+    const uint32_t *tables;  // [sweeps][row_len], thresholds for beta_t / P
+    const int32_t *jp;       // [sweeps] inter-slice coupling, integer units
+    int8_t *out;             // [reads][n]
+    int64_t *energies;       // [reads]
+    int n, D, C, row_len, sweeps, reads, P;
+    uint32_t k0, k1;
+};
+
+// Xor mask (0xFE per accepted byte) of the digit tests for x[b] (slice tag).
+template <int ND>
+__device__ __forceinline__ uint32_t sqa_mask(const int32_t x[4], const uint32_t *tab, uint32_t i, uint32_t t,
+                                             uint32_t quad, uint32_t k0, uint32_t k1) {
+    bool pass[4], up[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        up[b] = x[b] > 0;
+        pass[b] = true;
+    }
+#pragma unroll
+    for (int j = 0; j < ND; ++j) {
+        uint32_t d[4], th[4];
+        bool need = false;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            d[b] = up[b] ? (((uint32_t)x[b] >> (kDigitBits * j)) & (kDigitSize - 1)) : 0u;
+            need |= pass[b] && d[b] != 0;
+            th[b] = tab[j * kDigitSize + d[b]];  // a zero digit reads a valid entry it ignores
+        }
+        if (need) {
+            const dev::Words4 w = dev::philox(i, t, quad, (kTagSqa << 24) | (uint32_t)j, k0, k1);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) pass[b] = pass[b] & ((d[b] == 0) | (w.w[b] < th[b]));
+        }
+    }
+    uint32_t mask = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+        if (!up[b] || pass[b]) mask |= 0xFEu << (8 * b);
+    return mask;
+}
+
+template <int ND>
+__global__ __launch_bounds__(1024) void sqa_kernel(SqaArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int cs[kMaxColours + 1];
+    __shared__ int best_s;
+    __shared__ long long bestE_s;
+    const int n = a.n, D = a.D, P = a.P, qw = P / 4, G8 = P / 8, T = blockDim.x, tid = threadIdx.x;
+    const int read = blockIdx.x;
+    core::SaItem it;
+    it.image = a.image;
+    it.n = n;
+    it.D = D;
+    it.C = a.C;
+    core::SaLds L;
+    core::sa_layout(n, D, a.row_len, qw, &L, smem);
+    core::sa_load_instance(L, it, cs);  // ends with a barrier
+    const uint32_t quad0 = (uint32_t)read * (uint32_t)qw;
+    for (int k = tid; k < a.row_len; k += T) L.tab[k] = a.tables[k];
+    for (int k = tid; k < 4 * qw; k += T) L.E2[k] = 0ull;
+    // Initial slices: replica r = read * P + parity * P/2 + m, i.e. quad quad0 + word.
+    for (int idx = tid; idx < n * qw; idx += T) {
+        const int p = idx / qw, w = idx - p * qw;
+        const dev::Words4 r = dev::philox((uint32_t)L.ord[p], 0u, quad0 + (uint32_t)w, 1u << 24, a.k0, a.k1);
+        uint32_t word = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) word |= ((r.w[b] >> 31) ? 0x01u : 0xFFu) << (8 * b);
+        L.S[idx] = word;
+    }
+    __syncthreads();
+
+    const int q = tid % G8, slot = tid / G8, nslots = T / G8;
+    const bool active = slot < nslots;
+    for (int ls = 0; ls < a.sweeps; ++ls) {
+        const uint32_t t = (uint32_t)ls;
+        const int32_t jp = a.jp[ls];
+        const uint32_t *tcur = L.tab + (ls & 1) * a.row_len;
+        uint32_t *tnext = L.tab + ((ls + 1) & 1) * a.row_len;
+        if (ls + 1 < a.sweeps)
+            for (int k = tid; k < a.row_len; k += T) tnext[k] = a.tables[(size_t)(ls + 1) * a.row_len + k];
+        for (int c = 0; c < a.C; ++c) {
+            const int pe = cs[c + 1];
+#pragma unroll 1
+            for (int par = 0; par < 2; ++par) {
+                const int w = par * G8 + q;
+                // words of the other parity holding slices k - 1 and k + 1
+                const int wa = par ? q : G8 + q;
+                const int wb = par ? (q + 1 == G8 ? 0 : q + 1) : G8 + (q == 0 ? G8 - 1 : q - 1);
+                for (int p = cs[c] + slot; active && p < pe; p += nslots) {
+                    const uint32_t *row = L.S + (size_t)p * qw;
+                    const uint32_t self = row[w], A = row[wa], B = row[wb];
+                    const core::Fields F = core::local_fields(L.nbr + p, L.S, D, qw, w, L.hpos[p], n);
+                    // even word: k-1 = odd slice m-1 (A byte b-1, or B byte 3), k+1 = odd slice m (A byte b);
+                    // odd word: k-1 = even slice m (A byte b), k+1 = even slice m+1 (A byte b+1, or B byte 0)
+                    const uint32_t up = par ? A : __builtin_amdgcn_alignbyte(A, B, 3);
+                    const uint32_t dn = par ? __builtin_amdgcn_alignbyte(B, A, 1) : A;
+                    int32_t x[4];
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        const int32_t g = F.f[b] - jp * (dev::spin_of(up, b) + dev::spin_of(dn, b));
+                        x[b] = dev::spin_of(self, b) > 0 ? -g : g;
+                    }
+                    const uint32_t mask = sqa_mask<ND>(x, tcur, (uint32_t)L.ord[p], t, quad0 + (uint32_t)w, a.k0, a.k1);
+                    if (mask) L.S[(size_t)p * qw + w] = self ^ mask;
+                }
+                __syncthreads();
+            }
+        }
+    }
+
+    // Classical energy of every slice: 2E = sum_p s_p (h_p + f_p).
+    {
+        for (int idx = tid; idx < n * qw; idx += T) {
+            const int p = idx / qw, w = idx - p * qw;
+            const uint32_t self = L.S[idx];
+            const core::Fields F = core::local_fields(L.nbr + p, L.S, D, qw, w, L.hpos[p], n);
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                atomicAdd(&L.E2[w * 4 + b],
+                          (unsigned long long)((long long)dev::spin_of(self, b) * ((long long)L.hpos[p] + F.f[b])));
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int best = 0;
+        long long bestE = 0;
+        for (int k = 0; k < P; ++k) {
+            const int m = k >> 1, w = (k & 1) * G8 + (m >> 2), b = m & 3;
+            const long long E = ((long long)L.E2[w * 4 + b]) / 2;
+            if (k == 0 || E < bestE) {
+                bestE = E;
+                best = k;
+            }
+        }
+        best_s = best;
+        bestE_s = bestE;
+    }
+    __syncthreads();
+    const int best = best_s, m = best >> 1, bw = (best & 1) * G8 + (m >> 2), bb = m & 3;
+    if (tid == 0) a.energies[read] = bestE_s;
+    const int32_t *pos_of = a.image + kImgHeader + n;
+    const unsigned char *Sb = reinterpret_cast<const unsigned char *>(L.S);
+    for (int i = tid; i < n; i += T)
+        a.out[(size_t)read * n + i] = (int8_t)Sb[((size_t)pos_of[i] * qw + bw) * 4 + bb];
+}
+
+}  // namespace
+
+size_t sqa_lds_bytes(int n, int D, int row_len, int P) {
+    return core::sa_layout(n, D, row_len, P / 4, nullptr, nullptr);
+}
+
+hipError_t launch_sqa(const SqaLaunch &L, hipStream_t s) {
+    SqaArgs a;
+    a.image = L.image;
+    a.tables = L.tables;
+    a.jp = L.jp;
+    a.out = L.out;
+    a.energies = L.energies;
+    a.n = L.n;
+    a.D = L.D;
+    a.C = L.C;
+    a.row_len = L.row_len;
+    a.sweeps = L.sweeps;
+    a.reads = L.reads;
+    a.P = L.P;
+    a.k0 = (uint32_t)L.seed;
+    a.k1 = (uint32_t)(L.seed >> 32);
+    const size_t lds = sqa_lds_bytes(L.n, L.D, L.row_len, L.P);
+    if (L.P % 8 != 0 || L.P < 8 || L.threads % (L.P / 8) != 0 || L.reads < 1) return hipErrorInvalidValue;
+    switch (L.nd) {
+        case 1:
+            hipLaunchKernelGGL(sqa_kernel<1>, dim3(L.reads), dim3(L.threads), lds, s, a);
+            break;
+        case 2:
+            hipLaunchKernelGGL(sqa_kernel<2>, dim3(L.reads), dim3(L.threads), lds, s, a);
+            break;
+        case 3:
+            hipLaunchKernelGGL(sqa_kernel<3>, dim3(L.reads), dim3(L.threads), lds, s, a);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace spv

@@ -1,0 +1,116 @@
+"""GPU parity of simulated quantum annealing (path-integral Monte Carlo over P Trotter slices)
+through the C ABI, bit for bit against the oracle: each read's lowest-energy slice and its
+energy, over one-, two- and three-digit acceptance tables, several Trotter numbers, ragged
+read counts and the degenerate cases; argument and range errors from the host."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import spvar_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def spv():
+    import paper_1706_07826_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(spv):
+    return spv.Context(0)
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _sched(sweeps, b0=0.2, b1=3.0, g0=3.0, g1=0.05):
+    return si.linear_betas(b0, b1, sweeps), np.geomspace(g0, g1, sweeps) if sweeps else np.zeros(0)
+
+
+def _no_edges(n):
+    return si.from_edges(n, [], [], [], np.arange(1, n + 1) * (-1) ** np.arange(n), np.zeros(n), 1)
+
+
+CASES = [
+    # name, instance, trotter, reads, sweeps
+    ("chimera2_P8", lambda: si.chimera(2, seed=1), 8, 13, 40),
+    ("chimera3_P16", lambda: si.chimera(3, seed=2), 16, 9, 30),
+    ("cubic4_pm1_P32", lambda: si.cubic_lattice(4, "pm1", seed=3), 32, 5, 25),
+    ("cubic4_gauss_two_digits_P8", lambda: si.cubic_lattice(4, "gauss", seed=4, scale_log2=10), 8, 11, 30),
+    ("sparse40_greedy_P24", lambda: si.random_sparse(40, 3.0, seed=5), 24, 7, 30),
+    ("no_edges_P8", lambda: _no_edges(9), 8, 6, 20),
+    ("single_spin_P8", lambda: _no_edges(1), 8, 5, 15),
+    ("zero_sweeps_P8", lambda: si.chimera(2, seed=6), 8, 4, 0),
+]
+
+
+@pytest.mark.parametrize("name,make,P,reads,sweeps", CASES, ids=[c[0] for c in CASES])
+def test_sqa_parity(spv, ctx, name, make, P, reads, sweeps):
+    inst = make()
+    b, g = _sched(sweeps)
+    _say(f"[sqa] {name} n={inst.n} P={P} reads={reads} sweeps={sweeps}")
+    Pr = spv.Problem.from_instance(inst)
+    sp, E = spv.spv_sqa_sample(ctx, Pr, b, g, P, reads, 41)
+    osp, oE, _ = oracle.sqa_sample(inst, b, g, P, reads=reads, seed=41, threads=8)
+    assert np.array_equal(sp.cpu().numpy(), osp) and np.array_equal(E.cpu().numpy(), oE)
+
+
+def test_sqa_three_digit_tables(spv, ctx):
+    """A weak final field makes the slice coupling large: x_bound + 2 Jp spans three digits."""
+    inst = si.cubic_lattice(4, "gauss", seed=7, scale_log2=10)
+    b, g = _sched(30, 0.1, 0.3, 0.1, 0.05)
+    jmax = max(oracle.sqa_coupling(x, y, 8, 10) for x, y in zip(b, g))
+    assert oracle.x_max(inst) + 2 * jmax >= 512 ** 2
+    _say("[sqa] three digits")
+    sp, E = spv.spv_sqa_sample(ctx, spv.Problem.from_instance(inst), b, g, 8, 6, 42)
+    osp, oE, _ = oracle.sqa_sample(inst, b, g, 8, reads=6, seed=42, threads=6)
+    assert np.array_equal(sp.cpu().numpy(), osp) and np.array_equal(E.cpu().numpy(), oE)
+
+
+def test_sqa_chimera8_config_size_sampled_reads(spv, ctx):
+    """Chimera 8x8 (N = 512), 16 slices, 400 reads x 300 sweeps on the device; 24 reads
+    recomputed by the oracle, every energy equal to its state's."""
+    inst = si.chimera(8, seed=8)
+    b, g = _sched(300, 0.1, 5.0, 3.0, 0.01)
+    _say("[sqa] chimera8 P=16 400 reads x 300 sweeps")
+    sp, E = spv.spv_sqa_sample(ctx, spv.Problem.from_instance(inst), b, g, 16, 400, 43)
+    sp, E = sp.cpu().numpy(), E.cpu().numpy()
+    rows = np.r_[0:8, 190:198, 392:400]
+    osp, oE, _ = oracle.sqa_sample(inst, b, g, 16, seed=43, r_begin=0, r_end=8, threads=8)
+    assert np.array_equal(sp[0:8], osp) and np.array_equal(E[0:8], oE)
+    for lo in (190, 392):
+        osp, oE, _ = oracle.sqa_sample(inst, b, g, 16, seed=43, r_begin=lo, r_end=lo + 8, threads=8)
+        assert np.array_equal(sp[lo:lo + 8], osp) and np.array_equal(E[lo:lo + 8], oE)
+    assert np.array_equal(E, oracle.energy(inst, sp))
+    assert rows.size == 24
+
+
+def test_sqa_rejects_bad_arguments(spv, ctx):
+    import paper_1706_07826_amd as m
+
+    inst = si.chimera(2, seed=9)
+    Pr = spv.Problem.from_instance(inst)
+    b, g = _sched(10)
+    for P in (4, 12, 0, 264):
+        with pytest.raises(m.SpvError) as ei:
+            spv.spv_sqa_sample(ctx, Pr, b, g, P, 4, 1)
+        assert ei.value.code == -1
+    g0 = g.copy()
+    g0[3] = 0.0
+    with pytest.raises(m.SpvError) as ei:
+        spv.spv_sqa_sample(ctx, Pr, b, g0, 8, 4, 1)
+    assert ei.value.code == -1
+    with pytest.raises(m.SpvError) as ei:  # Jp at 2^24 and beyond
+        gi = si.cubic_lattice(4, "gauss", seed=10, scale_log2=10)
+        spv.spv_sqa_sample(ctx, spv.Problem.from_instance(gi), np.full(3, 0.01), np.full(3, 1e-300), 8, 4, 1)
+    assert ei.value.code == -4
+    # the context stays usable
+    sp, E = spv.spv_sqa_sample(ctx, Pr, b, g, 8, 4, 1)
+    osp, oE, _ = oracle.sqa_sample(inst, b, g, 8, reads=4, seed=1)
+    assert np.array_equal(sp.cpu().numpy(), osp) and np.array_equal(E.cpu().numpy(), oE)

@@ -109,7 +109,8 @@ def main():
                     help="after timing, run one device copy of this size (counter calibration)")
     ap.add_argument("--workload", default="chimera8_sa",
                     choices=["chimera8_sa", "residual_batch", "cubic10_pt", "cubic20_pticm", "serving",
-                             "spvar_round", "multistart", "spvar_tree", "cubic4_ispvar", "chimera32_sa"])
+                             "spvar_round", "multistart", "spvar_tree", "cubic4_ispvar", "chimera32_sa",
+                             "chimera8_sqa"])
     ap.add_argument("--pt-runs", type=int, default=0, help="PT workloads: runs per step (0 = the config's)")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--serving-slots", type=int, default=16)
@@ -153,6 +154,8 @@ def main():
         return bench_cubic4_ispvar(args)
     if args.workload == "chimera32_sa":
         return bench_chimera32_sa(args)
+    if args.workload == "chimera8_sqa":
+        return bench_chimera8_sqa(args)
 
     cfg = cf.CHIMERA8_SA
     inst = cf.instance(cfg)
@@ -733,6 +736,75 @@ def bench_chimera32_sa(args):
                                "instance in global memory"},
         "launch": spv.spv_sample_last_shape(ctx),
         "best_E": int(energies.min().item()),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_chimera8_sqa(args):
+    """SQA on the Chimera 8x8 instance of the SA workload: 16 Trotter slices, 1000 reads x 2000
+    sweeps, beta 0.1 -> 5.0 (linear), Gamma 3.0 -> 0.01 (geometric), then persistence (elite 0.05,
+    threshold 0.95) on the reads' lowest-energy slices.  Spin-updates count every slice."""
+    import numpy as np
+    import torch
+
+    import paper_1706_07826_amd as spv
+    from spvar_inputs import configs as cf, linear_betas
+
+    cfg = cf.CHIMERA8_SA
+    inst = cf.instance(cfg)
+    trotter, reads, sweeps = 16, 1000, 2000
+    betas, gammas = linear_betas(0.1, 5.0, sweeps), np.geomspace(3.0, 0.01, sweeps)
+    ctx = spv.Context(0)
+    P = spv.Problem.from_instance(inst)
+    stream = torch.cuda.current_stream()
+    spins = torch.empty((reads, inst.n), dtype=torch.int8, device="cuda")
+    energies = torch.empty(reads, dtype=torch.int64, device="cuda")
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        spv.spv_sqa_sample(ctx, P, betas, gammas, trotter, reads, 11, spins=spins, energies=energies)
+        if ev is not None:
+            ev[1].record(stream)
+        return spv.spv_persist_fix(ctx, P, spins, energies, cfg["elite"], cfg["theta"], cfg["gauge"])
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    last = None
+    for k in range(args.steps):
+        last = step(events[k])
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    sqa_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
+    updates = reads * trotter * inst.n * sweeps
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = max(1, min(16, os.cpu_count() or 1))
+        cpu_reads = 4 * threads
+        t1 = time.perf_counter()
+        oracle.sqa_sample(inst, betas, gammas, trotter, seed=11, r_begin=0, r_end=cpu_reads, threads=threads)
+        cdt = time.perf_counter() - t1
+        cpu = {"value": round(cpu_reads * trotter * inst.n * sweeps / cdt, 1), "unit": "spin-updates/s",
+               "cores": threads, "kind": "oracle",
+               "sample": f"reads 0..{cpu_reads - 1} of {reads} (all {sweeps} sweeps, {trotter} slices), "
+                         f"{threads} threads, {cdt:.1f} s wall"}
+    out = {
+        "metric": BASELINE_METRIC, "value": round(updates / dt, 1), "unit": "spin-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic (seeded Chimera U{+-1..+-6} instance)",
+        "config": {"workload": "chimera8_sqa: Chimera 8x8 K4,4 N=512, SQA 16 slices, 1000 reads x 2000 "
+                               "sweeps, beta 0.1->5.0, Gamma 3.0->0.01; persistence elite 0.05, threshold 0.95"},
+        "sqa_kernel_ms": round(sqa_ms, 3),
+        "kernel_spin_updates_per_s": round(updates / (sqa_ms / 1e3), 1),
+        "fixed_per_solve": last.info()["n_fixed"],
+        "best_E": int(energies.min().item()),
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 

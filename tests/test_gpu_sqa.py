@@ -91,6 +91,19 @@ def test_sqa_chimera8_config_size_sampled_reads(spv, ctx):
     assert rows.size == 24
 
 
+def test_sqa_cubic10_gauss_sampled_reads(spv, ctx):
+    """The L = 10 Gaussian cube (N = 1000, couplers at scale 2^10, two digits), 16 slices,
+    96 reads x 120 sweeps; 8 reads recomputed by the oracle, every energy equal to its state's."""
+    inst = si.cubic_lattice(10, "gauss", seed=12, scale_log2=10)
+    b, g = _sched(120, 0.2, 3.0, 3.0, 0.05)
+    _say("[sqa] cubic10 gauss P=16 96 reads x 120 sweeps")
+    sp, E = spv.spv_sqa_sample(ctx, spv.Problem.from_instance(inst), b, g, 16, 96, 44)
+    sp, E = sp.cpu().numpy(), E.cpu().numpy()
+    osp, oE, _ = oracle.sqa_sample(inst, b, g, 16, seed=44, r_begin=88, r_end=96, threads=8)
+    assert np.array_equal(sp[88:], osp) and np.array_equal(E[88:], oE)
+    assert np.array_equal(E, oracle.energy(inst, sp))
+
+
 def test_sqa_rejects_bad_arguments(spv, ctx):
     import paper_1706_07826_amd as m
 

@@ -559,6 +559,8 @@ spv_status spv_sqa_sample(spv_ctx *ctx, const spv_problem *P, const double *beta
     // one lane per (site, word of one parity) of the largest colour class
     const int tasks = (n + P->n_colours - 1) / P->n_colours * (trotter / 8);
     L.threads = std::max(64, std::min(1024, (tasks + 63) / 64 * 64));
+    if (const char *v = getenv("SPVAR_SQA_THREADS"))  // tuning: workgroup size (results do not depend on it)
+        if (atoi(v) >= 64 && atoi(v) <= 1024) L.threads = atoi(v);
     L.threads -= L.threads % (trotter / 8);
     e = launch_sqa(L, stream);
     return hip_check(c, e, "sqa launch");

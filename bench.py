@@ -22,7 +22,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-BASELINE_METRIC = "spin-updates/s (batched vs plain, bit-exact); SPVAR solves/s; p50/p99 latency"
+METRIC_NAME = "spin-updates/s (batched vs plain, bit-exact); SPVAR solves/s; p50/p99 latency"
 
 # VALU lane-slots per Metropolis update (algorithmic count, the roofline's
 # numerator).  A Philox4x32-10 block is 10 rounds of two 32x32->64 products
@@ -243,7 +243,7 @@ def main():
                          f"{threads} threads, {dt:.1f} s wall"}
 
     out = {
-        "metric": BASELINE_METRIC, "value": round(value, 1), "unit": "spin-updates/s",
+        "metric": METRIC_NAME, "value": round(value, 1), "unit": "spin-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
         "data": "synthetic (seeded Chimera U{+-1..+-6} instance; no paper instances available)",
@@ -300,7 +300,7 @@ def bench_residual_batch(args):
     plain_s = time.perf_counter() - t0
     same = all(torch.equal(a, b) for a, b in zip(sp + en, psp + pen))
     out = {
-        "metric": BASELINE_METRIC, "value": round(updates / batched_s, 1), "unit": "spin-updates/s",
+        "metric": METRIC_NAME, "value": round(updates / batched_s, 1), "unit": "spin-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(batched_s * 1e3, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int32", "data": "synthetic residual-shaped instances",
@@ -346,7 +346,7 @@ def bench_pt(args, cfg, label):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     out = {
-        "metric": BASELINE_METRIC, "value": round(updates / dt, 1), "unit": "spin-updates/s",
+        "metric": METRIC_NAME, "value": round(updates / dt, 1), "unit": "spin-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
         "data": f"synthetic Gaussian cubic L={cfg['L']} instance",
@@ -447,7 +447,7 @@ def bench_serving(args):
         loads[str(f)] = run(f * sat["requests_per_s"])
     srv.close()
     out = {
-        "metric": BASELINE_METRIC, "value": sat["spin_updates_per_s"], "unit": "spin-updates/s",
+        "metric": METRIC_NAME, "value": sat["spin_updates_per_s"], "unit": "spin-updates/s",
         "n_gpus": 1, "steps": nreq, "warmup": 12, "ms_per_step": round(1e3 / sat["requests_per_s"], 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
         "data": "synthetic Chimera N=512, Gaussian cubic N=1000 and N=8000 instances",
@@ -506,7 +506,7 @@ def bench_spvar_round(args):
     updates = reads * sweeps * (inst.n + n_res)
     off = out["fx"].info()["offset"]
     res = {
-        "metric": BASELINE_METRIC, "value": round(updates / dt, 1), "unit": "spin-updates/s",
+        "metric": METRIC_NAME, "value": round(updates / dt, 1), "unit": "spin-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
         "data": "synthetic (seeded Chimera U{+-1..+-6} instance)",
@@ -551,7 +551,7 @@ def bench_multistart(args):
     n_free = out["info"][:, 1]
     updates = cfg["sweeps"] * (S * F * inst.n + Rs * int(n_free.sum()))
     res = {
-        "metric": BASELINE_METRIC, "value": round(updates / dt, 1), "unit": "spin-updates/s",
+        "metric": METRIC_NAME, "value": round(updates / dt, 1), "unit": "spin-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
         "data": "synthetic (seeded Chimera U{+-1..+-6} instance)",
@@ -633,7 +633,7 @@ def bench_spvar_tree(args):
     updates = reads * sweeps * (inst.n + ti["n_free"])
     off = out["fx"].info()["offset"] + ti["offset"]
     res = {
-        "metric": BASELINE_METRIC, "value": round(updates / dt, 1), "unit": "spin-updates/s",
+        "metric": METRIC_NAME, "value": round(updates / dt, 1), "unit": "spin-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
         "data": "synthetic (seeded Chimera U{+-1..+-6} instance)",
@@ -689,7 +689,7 @@ def bench_cubic4_ispvar(args):
         cpu = {"value": round(1.0 / cdt, 3), "unit": "SPVAR solves/s", "cores": 1, "kind": "oracle",
                "sample": f"one full solve ({cfg['rounds']} rounds), {cdt:.2f} s, identical fixes: {same}"}
     out = {
-        "metric": BASELINE_METRIC, "value": round(1.0 / dt, 3), "unit": "SPVAR solves/s",
+        "metric": METRIC_NAME, "value": round(1.0 / dt, 3), "unit": "SPVAR solves/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
         "data": "synthetic (seeded +-1 cubic L=4 instance)",
@@ -728,7 +728,7 @@ def bench_chimera32_sa(args):
     dt = (time.perf_counter() - t0) / args.steps
     updates = reads * inst.n * betas.size
     out = {
-        "metric": BASELINE_METRIC, "value": round(updates / dt, 1), "unit": "spin-updates/s",
+        "metric": METRIC_NAME, "value": round(updates / dt, 1), "unit": "spin-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
         "data": "synthetic (seeded Chimera U{+-1..+-6} instance)",
@@ -794,7 +794,7 @@ def bench_chimera8_sqa(args):
                "sample": f"reads 0..{cpu_reads - 1} of {reads} (all {sweeps} sweeps, {trotter} slices), "
                          f"{threads} threads, {cdt:.1f} s wall"}
     out = {
-        "metric": BASELINE_METRIC, "value": round(updates / dt, 1), "unit": "spin-updates/s",
+        "metric": METRIC_NAME, "value": round(updates / dt, 1), "unit": "spin-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
         "data": "synthetic (seeded Chimera U{+-1..+-6} instance)",

@@ -91,6 +91,23 @@ def test_sqa_chimera8_config_size_sampled_reads(spv, ctx):
     assert rows.size == 24
 
 
+def test_sqa_workload_size_sampled_reads(spv, ctx):
+    """The chimera8_sqa workload as the benchmark launches it (Chimera 8x8 instance of the SA
+    workload, 16 slices, 1000 reads x 2000 sweeps, beta 0.1 -> 5.0, Gamma 3.0 -> 0.01): reads 0,
+    499 and 999 recomputed by the oracle, every energy equal to its state's."""
+    from spvar_inputs import configs as cf
+
+    inst = cf.instance(cf.CHIMERA8_SA)
+    b, g = si.linear_betas(0.1, 5.0, 2000), np.geomspace(3.0, 0.01, 2000)
+    _say("[sqa] workload size: chimera8 P=16 1000 reads x 2000 sweeps")
+    sp, E = spv.spv_sqa_sample(ctx, spv.Problem.from_instance(inst), b, g, 16, 1000, 11)
+    sp, E = sp.cpu().numpy(), E.cpu().numpy()
+    for r in (0, 499, 999):
+        osp, oE, _ = oracle.sqa_sample(inst, b, g, 16, seed=11, r_begin=r, r_end=r + 1)
+        assert np.array_equal(sp[r], osp[0]) and E[r] == oE[0], r
+    assert np.array_equal(E, oracle.energy(inst, sp))
+
+
 def test_sqa_cubic10_gauss_sampled_reads(spv, ctx):
     """The L = 10 Gaussian cube (N = 1000, couplers at scale 2^10, two digits), 16 slices,
     96 reads x 120 sweeps; 8 reads recomputed by the oracle, every energy equal to its state's."""

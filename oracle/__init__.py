@@ -80,7 +80,8 @@ def lib():
         L.orc_components.argtypes = [vp, vp]
         L.orc_components.restype = i32
         L.orc_merge_sorted.argtypes = [vp, vp, i32, vp, i32, vp, vp, vp]
-        L.orc_multistart.argtypes = [vp, vp, i32, u64, i32, i32, i32, f64, f64, i32, i32, vp, vp, vp, vp,
+        L.orc_multistart.argtypes = [vp, vp, i32, u64, i32, i32, i32, f64, f64, i32, i32, i32, i32, vp,
+                                     vp, vp, vp, vp,
                                      vp, vp, vp]
         L.orc_multistart.restype = C.c_int
         L.orc_tree_peel.argtypes = [vp] * 12
@@ -398,12 +399,15 @@ def merge_sorted(inst, comp, n_comp, samples):
 
 
 def multistart(inst, betas, seed, starts, fixing_reads, solving_reads, elite_frac, threshold, gauge=0,
-               merge=False):
-    """Multi-start SPVAR (Algorithm 2).  Returns a dict: fixing_E [S][F], solving_E [S][Rs]
-    (full-problem energies), fixed_mask/fixed_val [S][n], info [S][4] (n_fixed, n_free, offset,
-    components), best_E and best_spins [n]."""
+               merge=False, gammas=None, trotter=0):
+    """Multi-start SPVAR (Algorithm 2) with SA, or with SQA when `gammas` is given (`trotter`
+    slices).  Returns a dict: fixing_E [S][F], solving_E [S][Rs] (full-problem energies),
+    fixed_mask/fixed_val [S][n], info [S][4] (n_fixed, n_free, offset, components), best_E and
+    best_spins [n]."""
     b = _Bound(inst)
     bt = np.ascontiguousarray(betas, dtype=np.float64)
+    gm = None if gammas is None else np.ascontiguousarray(gammas, dtype=np.float64)
+    sampler = 0 if gm is None else 1
     n, S, F, Rs = inst.n, int(starts), int(fixing_reads), int(solving_reads)
     out = dict(fixing_E=np.zeros((S, F), np.int64), solving_E=np.zeros((S, max(Rs, 0)), np.int64),
                fixed_mask=np.zeros((S, n), np.uint8), fixed_val=np.zeros((S, n), np.int8),
@@ -411,7 +415,7 @@ def multistart(inst, betas, seed, starts, fixing_reads, solving_reads, elite_fra
     best = C.c_int64(0)
     rc = lib().orc_multistart(b.ref, _ptr(bt), bt.size, C.c_uint64(seed & (2**64 - 1)), S, F, Rs,
                               float(elite_frac), float(threshold), int(gauge), int(bool(merge)),
-                              _ptr(out["fixing_E"]), _ptr(out["solving_E"]), _ptr(out["fixed_mask"]),
+                              sampler, int(trotter), _ptr(gm), _ptr(out["fixing_E"]), _ptr(out["solving_E"]), _ptr(out["fixed_mask"]),
                               _ptr(out["fixed_val"]), _ptr(out["info"]), _ptr(out["best_spins"]),
                               C.byref(best))
     if rc != 0:

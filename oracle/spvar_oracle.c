@@ -79,9 +79,10 @@
  *    partial solution.
  *
  *  Multi-start SPVAR (Algorithm 2): start s fixes variables from reads
- *    [s*F, (s+1)*F) of one SA job on the problem (seed), records their
- *    energies, then samples its modified problem with Rs reads of an SA job
- *    with seed + 1 + s and records E' + offset_s (optionally after the
+ *    [s*F, (s+1)*F) of one sampler job (SA, or SQA as below) on the problem
+ *    (seed), records their energies, then samples its modified problem with Rs
+ *    reads of a job of the same sampler with seed + 1 + s and records E' +
+ *    offset_s (optionally after the
  *    recombination above over the modified problem's components).  The best
  *    state is the first minimum of the recorded energies in the order: start
  *    0's fixing rows, start 0's solving rows, start 1's fixing rows, ...; a
@@ -1289,9 +1290,29 @@ int orc_merge_sorted(const orc_problem *P, const int32_t *comp, int32_t n_comp, 
 
 /* fixing_E [S][F], solving_E [S][Rs], fixed_mask/fixed_val [S][n],
  * info [S][4] = (n_fixed, n_free, offset, components or 0), best_spins [n]. */
+/* One sample, reads [0, R) of a job on Q: SA (sampler 0) or SQA over `trotter`
+ * slices with the Gamma schedule `gammas` (sampler 1). */
+static int ms_sample(const orc_problem *Q, int32_t sampler, const double *betas, const double *gammas,
+                     int32_t sweeps, int32_t trotter, uint64_t seed, int32_t R, int8_t *spins, int64_t *E)
+{
+    int32_t *bk;
+    int rc;
+    if (sampler == 0)
+        return orc_sa_sample(Q, betas, sweeps, seed, 0, 0, R, NULL, NULL, spins, E);
+    if (sampler != 1 || !gammas)
+        return ORC_EINVAL;
+    bk = (int32_t *)malloc(sizeof(int32_t) * (size_t)(R > 0 ? R : 1));
+    if (!bk)
+        return ORC_ENOMEM;
+    rc = orc_sqa_sample(Q, betas, gammas, sweeps, trotter, seed, 0, R, NULL, NULL, spins, E, bk);
+    free(bk);
+    return rc;
+}
+
 int orc_multistart(const orc_problem *P, const double *betas, int32_t sweeps, uint64_t seed,
                    int32_t starts, int32_t F, int32_t Rs, double elite_frac, double threshold,
-                   int32_t gauge, int32_t merge, int64_t *fixing_E, int64_t *solving_E,
+                   int32_t gauge, int32_t merge, int32_t sampler, int32_t trotter, const double *gammas,
+                   int64_t *fixing_E, int64_t *solving_E,
                    uint8_t *fixed_mask, int8_t *fixed_val, int64_t *info_o, int8_t *best_spins,
                    int64_t *best_E)
 {
@@ -1319,8 +1340,8 @@ int orc_multistart(const orc_problem *P, const double *betas, int32_t sweeps, ui
         rc = ORC_EINVAL;
         goto done;
     }
-    /* fixing samples of every start: one SA job, start s owns reads [s*F, (s+1)*F) */
-    rc = orc_sa_sample(P, betas, sweeps, seed, 0, 0, starts * F, NULL, NULL, fs, fixing_E);
+    /* fixing samples of every start: one sampler job, start s owns reads [s*F, (s+1)*F) */
+    rc = ms_sample(P, sampler, betas, gammas, sweeps, trotter, seed, starts * F, fs, fixing_E);
     if (rc)
         goto done;
     for (s = 0; s < starts; ++s) {
@@ -1350,7 +1371,7 @@ int orc_multistart(const orc_problem *P, const double *betas, int32_t sweeps, ui
         red.colour = co;
         if (Rs > 0) {
             if (nf > 0) {
-                rc = orc_sa_sample(&red, betas, sweeps, seed + 1 + (uint64_t)s, 0, 0, Rs, NULL, NULL, ss, se);
+                rc = ms_sample(&red, sampler, betas, gammas, sweeps, trotter, seed + 1 + (uint64_t)s, Rs, ss, se);
                 if (rc)
                     goto done;
                 if (merge) {

@@ -89,3 +89,37 @@ def test_recombination_never_worsens_the_best_solving_energy():
     assert np.array_equal(a["fixing_E"], b["fixing_E"])
     assert np.all(b["solving_E"].min(axis=1) <= a["solving_E"].min(axis=1))
     assert np.all(np.diff(b["solving_E"], axis=1) >= 0)
+
+
+# ------------------------------------------------ SQA as the sampler (SQA_SPVAR) --
+@pytest.mark.parametrize("merge", [False, True])
+def test_sqa_driver_records_real_states_and_its_own_samples(merge):
+    """With SQA as the sampler: the best state is a real state with the recorded energy, the
+    fixing energies are reads [s*F, (s+1)*F) of one SQA job, and the solving energies are SQA
+    jobs on each start's reduced problem (seed + 1 + s) plus its offset."""
+    inst = si.disjoint_union([si.chimera(1, seed=5), si.random_sparse(16, 2.0, seed=6)], perm_seed=2)
+    b, g = si.linear_betas(0.2, 3.0, 50), np.geomspace(3.0, 0.05, 50)
+    out = oracle.multistart(inst, b, seed=13, starts=3, fixing_reads=24, solving_reads=16, elite_frac=0.25,
+                            threshold=1.0, merge=merge, gammas=g, trotter=8)
+    assert out["best_E"] == int(oracle.energy(inst, out["best_spins"][None])[0])
+    assert out["best_E"] == np.concatenate([out["fixing_E"].ravel(), out["solving_E"].ravel()]).min()
+    for s in range(3):
+        S, E, _ = oracle.sqa_sample(inst, b, g, 8, seed=13, r_begin=24 * s, r_end=24 * (s + 1))
+        assert np.array_equal(out["fixing_E"][s], E)
+        if not merge:
+            fx = oracle.persist_fix(inst, S, E, 0.25, 1.0, 0)
+            assert np.array_equal(out["fixed_mask"][s], fx["fixed_mask"])
+            if fx["n_free"]:
+                _, E2, _ = oracle.sqa_sample(fx["reduced"], b, g, 8, seed=13 + 1 + s, reads=16)
+                assert np.array_equal(out["solving_E"][s], E2 + fx["offset"])
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_sqa_driver_reaches_brute_force_ground_state(seed):
+    inst = si.random_sparse(14, 2.5, seed=50 + seed)
+    ground = _brute_ground(inst)
+    sw = 200
+    out = oracle.multistart(inst, si.linear_betas(0.1, 4.0, sw), seed=seed, starts=3, fixing_reads=16,
+                            solving_reads=16, elite_frac=0.25, threshold=1.0, gammas=np.geomspace(3.0, 0.02, sw),
+                            trotter=8)
+    assert out["best_E"] == ground

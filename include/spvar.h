@@ -374,9 +374,10 @@ spv_status spv_merge_components(spv_ctx *ctx, const spv_problem *P, const int32_
 /*
  * Multi-start SPVAR (Algorithm 2): `starts` independent starts.  Start s
  * applies SPVAR (Algorithm 1, spv_persist_fix) to reads [s*F, (s+1)*F) of one
- * SA job on P with `seed` (F = fixing_reads), then samples its modified
- * problem with Rs = solving_reads reads of an SA job with seed + 1 + s (all
- * starts in one batched launch), optionally recombining that sample over the
+ * sampler job on P with `seed` (F = fixing_reads), then samples its modified
+ * problem with Rs = solving_reads reads of a job of the same sampler with
+ * seed + 1 + s (SA: all starts in one batched launch; SQA, spv_sqa_sample: one
+ * launch per start), optionally recombining that sample over the
  * modified problem's components (Sec. II.C).  Every recorded energy is a
  * full-problem energy (E' + the start's offset).  The call waits for
  * `stream` (it reads back the per-start sizes).
@@ -392,6 +393,9 @@ typedef struct {
     double threshold;
     int32_t gauge;
     int32_t merge;           /* 1: recombine each solving sample over its components */
+    int32_t sampler;         /* 0: SA; 1: SQA with `trotter` slices and the Gamma schedule `gammas` */
+    int32_t trotter;         /* SQA: as spv_sqa_sample */
+    const double *gammas;    /* SQA: host [sweeps] */
 } spv_multistart_params;
 
 typedef struct {

@@ -63,7 +63,8 @@ SPV_BATCH_TUNE = 2
 class spv_multistart_params(C.Structure):
     _fields_ = [("starts", C.c_int32), ("fixing_reads", C.c_int32), ("solving_reads", C.c_int32),
                 ("betas", C.c_void_p), ("sweeps", C.c_int32), ("seed", C.c_uint64), ("elite_frac", C.c_double),
-                ("threshold", C.c_double), ("gauge", C.c_int32), ("merge", C.c_int32)]
+                ("threshold", C.c_double), ("gauge", C.c_int32), ("merge", C.c_int32), ("sampler", C.c_int32),
+                ("trotter", C.c_int32), ("gammas", C.c_void_p)]
 
 
 class spv_multistart_out(C.Structure):
@@ -433,11 +434,13 @@ def spv_merge_components(ctx, P, comp, n_comp, samples, part=False, stream=None)
 
 
 def spv_multistart(ctx, P, betas, seed, starts, fixing_reads, solving_reads, elite_frac, threshold, gauge=0,
-                   merge=False, stream=None):
-    """Multi-start SPVAR (Algorithm 2).  Returns a dict: fixing_E [S][F], solving_E [S][Rs]
-    (full-problem energies), fixed_mask/fixed_val [S][n] (device), info [S][4] (host: n_fixed,
-    n_free, offset, components), best_E (host int) and best_spins [n] (device)."""
+                   merge=False, gammas=None, trotter=0, stream=None):
+    """Multi-start SPVAR (Algorithm 2) with SA, or with SQA when `gammas` is given (`trotter`
+    slices).  Returns a dict: fixing_E [S][F], solving_E [S][Rs] (full-problem energies),
+    fixed_mask/fixed_val [S][n] (device), info [S][4] (host: n_fixed, n_free, offset,
+    components), best_E (host int) and best_spins [n] (device)."""
     b = np.ascontiguousarray(betas, dtype=np.float64)
+    gm = None if gammas is None else np.ascontiguousarray(gammas, dtype=np.float64)
     dev, n, S, F, Rs = ctx.device, P.n, int(starts), int(fixing_reads), int(solving_reads)
     res = dict(fixing_E=torch.empty((S, F), dtype=torch.int64, device=dev),
                solving_E=torch.empty((S, max(Rs, 1)), dtype=torch.int64, device=dev),
@@ -446,7 +449,8 @@ def spv_multistart(ctx, P, betas, seed, starts, fixing_reads, solving_reads, eli
                info=np.zeros((S, 4), np.int64), best_spins=torch.empty(max(n, 1), dtype=torch.int8, device=dev))
     best = C.c_int64(0)
     prm = spv_multistart_params(S, F, Rs, b.ctypes.data, b.size, C.c_uint64(seed & (2**64 - 1)),
-                                float(elite_frac), float(threshold), int(gauge), int(bool(merge)))
+                                float(elite_frac), float(threshold), int(gauge), int(bool(merge)),
+                                0 if gm is None else 1, int(trotter), None if gm is None else gm.ctypes.data)
     out = spv_multistart_out(res["fixing_E"].data_ptr(), res["solving_E"].data_ptr(),
                              res["fixed_mask"].data_ptr(), res["fixed_val"].data_ptr(), res["info"].ctypes.data,
                              res["best_spins"].data_ptr(), C.addressof(best))

@@ -1,7 +1,7 @@
-// Multi-start SPVAR (Algorithm 2) on the device: one SA launch for the fixing
-// samples of every start, the persistence step per start, one batched launch
-// for the starts' modified problems, optional recombination over components,
-// and the best recorded state.
+// Multi-start SPVAR (Algorithm 2) on the device: one sampler launch for the
+// fixing samples of every start, the persistence step per start, the starts'
+// modified problems sampled (SA: one batched launch; SQA: a launch per start),
+// optional recombination over components, and the best recorded state.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,6 +29,8 @@ spv_status spv_multistart(spv_ctx *ctx, const spv_problem *P, const spv_multista
     if (!out->fixing_E || (Rs > 0 && !out->solving_E))
         return set_err(c, SPV_EINVAL, "spv_multistart: NULL energy output");
     if ((st = check_betas(c, prm->betas, prm->sweeps))) return st;
+    const bool sqa = prm->sampler == 1;
+    if (prm->sampler != 0 && !sqa) return set_err(c, SPV_EINVAL, "spv_multistart: sampler=%d", prm->sampler);
 
     // Working set.
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
@@ -69,10 +71,11 @@ spv_status spv_multistart(spv_ctx *ctx, const spv_problem *P, const spv_multista
     }
     auto blk = [&](int s, size_t off) { return starts + (size_t)s * pstride + off; };
 
-    // 1. Fixing samples of every start: one SA job, start s owns reads [s*F, (s+1)*F).
-    if ((st = spv_sample(ctx, P, prm->betas, prm->sweeps, S * F, prm->seed, 0, nullptr, fs, out->fixing_E,
-                         stream)))
-        return st;
+    // 1. Fixing samples of every start: one sampler job, start s owns reads [s*F, (s+1)*F).
+    st = sqa ? spv_sqa_sample(ctx, P, prm->betas, prm->gammas, prm->sweeps, prm->trotter, S * F, prm->seed, fs,
+                              out->fixing_E, stream)
+             : spv_sample(ctx, P, prm->betas, prm->sweeps, S * F, prm->seed, 0, nullptr, fs, out->fixing_E, stream);
+    if (st) return st;
     // 2. SPVAR per start.
     for (int s = 0; s < S; ++s) {
         spv_fix_out fo;
@@ -128,10 +131,16 @@ spv_status spv_multistart(spv_ctx *ctx, const spv_problem *P, const spv_multista
             en.push_back(Ered + (size_t)s * Rs);
             who.push_back(s);
         }
-        if (!probs.empty() &&
-            (st = spv_sample_batch(ctx, (int32_t)probs.size(), probs.data(), prm->betas, prm->sweeps, reads.data(),
-                                   seeds.data(), sp.data(), en.data(), nullptr, stream)))
+        if (sqa) {
+            for (size_t b = 0; b < probs.size(); ++b)
+                if ((st = spv_sqa_sample(ctx, &probs[b], prm->betas, prm->gammas, prm->sweeps, prm->trotter, Rs,
+                                         seeds[b], sp[b], en[b], stream)))
+                    return st;
+        } else if (!probs.empty() &&
+                   (st = spv_sample_batch(ctx, (int32_t)probs.size(), probs.data(), prm->betas, prm->sweeps,
+                                          reads.data(), seeds.data(), sp.data(), en.data(), nullptr, stream))) {
             return st;
+        }
         // 4. Optional recombination over each modified problem's components (Sec. II.C).
         if (merge) {
             for (size_t b = 0; b < probs.size(); ++b) {

@@ -65,3 +65,23 @@ def test_multistart_chimera8_paper_parameters(spv, ctx):
     got = _run(spv, ctx, inst, betas, seed=2002, starts=10, fixing_reads=200, solving_reads=100,
                elite_frac=0.05, threshold=0.95, merge=True)
     assert got["best_E"] == int(oracle.energy(inst, got["best_spins"].cpu().numpy()[None])[0])
+
+
+SQA_CASES = [
+    ("chimera2_sqa_3starts", lambda: si.chimera(2, seed=21), 8,
+     dict(seed=23, starts=3, fixing_reads=24, solving_reads=17, elite_frac=0.25, threshold=1.0)),
+    ("union_sqa_merge_P16", lambda: si.disjoint_union([si.chimera(1, seed=22), si.random_sparse(20, 2.0, seed=23)],
+                                                      perm_seed=4), 16,
+     dict(seed=25, starts=2, fixing_reads=20, solving_reads=13, elite_frac=0.2, threshold=1.0, merge=True)),
+    ("cubic4_sqa_gauge_auto", lambda: si.cubic_lattice(4, "pm1", seed=24), 8,
+     dict(seed=27, starts=2, fixing_reads=32, solving_reads=9, elite_frac=0.1, threshold=1.0, gauge=2)),
+]
+
+
+@pytest.mark.parametrize("name,make,P,kw", SQA_CASES, ids=[c[0] for c in SQA_CASES])
+def test_multistart_with_sqa_matches_oracle(spv, ctx, name, make, P, kw):
+    """SQA as the driver's sampler (both samples): every recorded quantity bit for bit."""
+    inst = make()
+    betas, gammas = si.linear_betas(0.2, 3.0, 40), np.geomspace(3.0, 0.05, 40)
+    print(f"[multistart] {name} n={inst.n} P={P}", flush=True)
+    _run(spv, ctx, inst, betas, gammas=gammas, trotter=P, **kw)

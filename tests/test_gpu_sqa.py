@@ -144,3 +144,22 @@ def test_sqa_rejects_bad_arguments(spv, ctx):
     sp, E = spv.spv_sqa_sample(ctx, Pr, b, g, 8, 4, 1)
     osp, oE, _ = oracle.sqa_sample(inst, b, g, 8, reads=4, seed=1)
     assert np.array_equal(sp.cpu().numpy(), osp) and np.array_equal(E.cpu().numpy(), oE)
+
+
+def test_sqa_empty_problem_zero_reads_and_capacity(spv, ctx):
+    import paper_1706_07826_amd as m
+    import torch
+
+    b, g = _sched(5)
+    empty = si.from_edges(0, [], [], [], [], [], 1)
+    sp, E = spv.spv_sqa_sample(ctx, spv.Problem.from_instance(empty), b, g, 8, 3, 1)
+    assert tuple(sp.shape) == (3, 0) and np.array_equal(E.cpu().numpy(), np.zeros(3, np.int64))
+    inst = si.chimera(2, seed=31)
+    sp, E = spv.spv_sqa_sample(ctx, spv.Problem.from_instance(inst), b, g, 8, 0, 1)
+    assert tuple(sp.shape) == (0, inst.n) and E.numel() == 0
+    # 256 slices of an 800-variable instance: 64 words per variable (200 KiB) exceed a workgroup's LDS
+    big = si.chimera(10, seed=32)
+    with pytest.raises(m.SpvError) as ei:
+        spv.spv_sqa_sample(ctx, spv.Problem.from_instance(big), b, g, 256, 2, 1)
+    assert ei.value.code == -5
+    torch.cuda.synchronize()

@@ -188,7 +188,8 @@ __device__ void sa_run(const SaLds &L, const SaItem &a, const int *cs) {
     const size_t rec_p = BIG ? (size_t)D : 1, rec_k = BIG ? 1 : (size_t)n;
     const int q = tid % qw, slot = tid / qw, nslots = T / qw;
     const bool active = slot < nslots;
-    for (int k = tid; k < a.row_len; k += T) L.tab[k] = a.tables[k];
+    // (no sweeps: no table was uploaded, so none is read)
+    for (int k = tid; a.sweeps > 0 && k < a.row_len; k += T) L.tab[k] = a.tables[k];
     for (int k = tid; k < 4 * qw; k += T) L.E2[k] = 0ull;
     // Initial state.
     if (a.init == nullptr) {

@@ -91,7 +91,7 @@ __global__ __launch_bounds__(1024) void sqa_kernel(SqaArgs a) {
     core::sa_layout(n, D, a.row_len, qw, &L, smem);
     core::sa_load_instance(L, it, cs);  // ends with a barrier
     const uint32_t quad0 = (uint32_t)read * (uint32_t)qw;
-    for (int k = tid; k < a.row_len; k += T) L.tab[k] = a.tables[k];
+    for (int k = tid; a.sweeps > 0 && k < a.row_len; k += T) L.tab[k] = a.tables[k];  // none uploaded without sweeps
     for (int k = tid; k < 4 * qw; k += T) L.E2[k] = 0ull;
     // Initial slices: replica r = read * P + parity * P/2 + m, i.e. quad quad0 + word.
     for (int idx = tid; idx < n * qw; idx += T) {

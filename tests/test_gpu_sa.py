@@ -328,3 +328,18 @@ def test_sa_general_body_beyond_lds_matches_oracle(spv, ctx, name, make, reads, 
     assert spv.spv_sample_last_shape(ctx)["global_instance"] == 1
     osp, oE = oracle.sa_sample(inst, betas, reads=reads, seed=78, threads=8)
     assert np.array_equal(sp.cpu().numpy(), osp) and np.array_equal(E.cpu().numpy(), oE)
+
+
+def test_zero_sweeps_on_a_fresh_context_reads_no_table(spv):
+    """Regression: with no sweeps no acceptance table is uploaded, so the general body (and SQA)
+    must not read one; on a fresh context the table pointer is not even allocated."""
+    ctx2 = spv.Context(0)
+    inst = si.cubic_lattice(4, "gauss", seed=4, scale_log2=10)  # multi-digit: the general body
+    P = spv.Problem.from_instance(inst)
+    sp, E = spv.spv_sample(ctx2, P, np.zeros(0), 9, 3)
+    osp, oE = oracle.sa_sample(inst, np.zeros(0), reads=9, seed=3)
+    assert np.array_equal(sp.cpu().numpy(), osp) and np.array_equal(E.cpu().numpy(), oE)
+    ctx3 = spv.Context(0)
+    sp, E = spv.spv_sqa_sample(ctx3, P, np.zeros(0), np.zeros(0), 8, 5, 4)
+    osp, oE, _ = oracle.sqa_sample(inst, np.zeros(0), np.zeros(0), 8, reads=5, seed=4)
+    assert np.array_equal(sp.cpu().numpy(), osp) and np.array_equal(E.cpu().numpy(), oE)

@@ -555,6 +555,7 @@ spv_status spv_sqa_sample(spv_ctx *ctx, const spv_problem *P, const double *beta
     L.sweeps = sweeps;
     L.reads = reads;
     L.P = trotter;
+    L.x_bound = P->x_bound;
     L.seed = seed;
     // one lane per (site, word of one parity) of the largest colour class
     const int tasks = (n + P->n_colours - 1) / P->n_colours * (trotter / 8);

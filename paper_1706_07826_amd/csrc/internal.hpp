@@ -167,7 +167,7 @@ struct SqaLaunch {
     const int32_t *jp;       // [sweeps]
     int8_t *out;
     int64_t *energies;
-    int n, D, C, row_len, nd, sweeps, reads, P, threads;
+    int n, D, C, row_len, nd, sweeps, reads, P, threads, x_bound;
     uint64_t seed;
 };
 hipError_t launch_sqa(const SqaLaunch &L, hipStream_t s);

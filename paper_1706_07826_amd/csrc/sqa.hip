@@ -37,14 +37,15 @@ struct SqaArgs {
     const int32_t *jp;       // [sweeps] inter-slice coupling, integer units
     int8_t *out;             // [reads][n]
     int64_t *energies;       // [reads]
-    int n, D, C, row_len, sweeps, reads, P;
+    int n, D, C, row_len, sweeps, reads, P, x_bound;
     uint32_t k0, k1;
 };
 
-// Xor mask (0xFE per accepted byte) of the digit tests for x[b] (slice tag).
+// Xor mask (0xFE per accepted byte) of the digit tests for x[b] (slice tag); digits
+// from ndt on are zero for every x of this sweep (ndt is wave-uniform).
 template <int ND>
 __device__ __forceinline__ uint32_t sqa_mask(const int32_t x[4], const uint32_t *tab, uint32_t i, uint32_t t,
-                                             uint32_t quad, uint32_t k0, uint32_t k1) {
+                                             uint32_t quad, uint32_t k0, uint32_t k1, int ndt) {
     bool pass[4], up[4];
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
@@ -53,6 +54,7 @@ __device__ __forceinline__ uint32_t sqa_mask(const int32_t x[4], const uint32_t 
     }
 #pragma unroll
     for (int j = 0; j < ND; ++j) {
+        if (j >= ndt) break;
         uint32_t d[4], th[4];
         bool need = false;
 #pragma unroll
@@ -109,6 +111,10 @@ __global__ __launch_bounds__(1024) void sqa_kernel(SqaArgs a) {
     for (int ls = 0; ls < a.sweeps; ++ls) {
         const uint32_t t = (uint32_t)ls;
         const int32_t jp = a.jp[ls];
+        // digits that |x| <= x_bound + 2 Jp can have in this sweep
+        const int64_t xmax = (int64_t)a.x_bound + 2 * (int64_t)jp;
+        int ndt = 1;
+        while (ndt < ND && (xmax >> (kDigitBits * ndt)) != 0) ++ndt;
         const uint32_t *tcur = L.tab + (ls & 1) * a.row_len;
         uint32_t *tnext = L.tab + ((ls + 1) & 1) * a.row_len;
         if (ls + 1 < a.sweeps)
@@ -135,7 +141,8 @@ __global__ __launch_bounds__(1024) void sqa_kernel(SqaArgs a) {
                         const int32_t g = F.f[b] - jp * (dev::spin_of(up, b) + dev::spin_of(dn, b));
                         x[b] = dev::spin_of(self, b) > 0 ? -g : g;
                     }
-                    const uint32_t mask = sqa_mask<ND>(x, tcur, (uint32_t)L.ord[p], t, quad0 + (uint32_t)w, a.k0, a.k1);
+                    const uint32_t mask =
+                        sqa_mask<ND>(x, tcur, (uint32_t)L.ord[p], t, quad0 + (uint32_t)w, a.k0, a.k1, ndt);
                     if (mask) L.S[(size_t)p * qw + w] = self ^ mask;
                 }
                 __syncthreads();
@@ -199,6 +206,7 @@ hipError_t launch_sqa(const SqaLaunch &L, hipStream_t s) {
     a.sweeps = L.sweeps;
     a.reads = L.reads;
     a.P = L.P;
+    a.x_bound = L.x_bound;
     a.k0 = (uint32_t)L.seed;
     a.k1 = (uint32_t)(L.seed >> 32);
     const size_t lds = sqa_lds_bytes(L.n, L.D, L.row_len, L.P);

@@ -515,34 +515,37 @@ spv_status spv_batch_last_shape(const spv_ctx *ctx, int32_t *threads, int32_t *q
  * frees up.  Results depend only on the request (counter-based randomness),
  * never on what else is in flight.
  *
- * Request kinds: SPV_REQ_SA (spv_sample) and SPV_REQ_PT (spv_pt_sample, top-10
- * sample).  With elite_frac > 0 the persistence step (spv_persist_fix) runs on
- * the produced sample (SA: all reads; PT: the filled top-10 entries as
- * assembled by spv_top_sample, once the run has ended) into fix_out.
+ * Request kinds: SPV_REQ_SA (spv_sample), SPV_REQ_PT (spv_pt_sample, top-10
+ * sample) and SPV_REQ_SQA (spv_sqa_sample).  With elite_frac > 0 the
+ * persistence step (spv_persist_fix) runs on the produced sample (SA and SQA:
+ * all reads; PT: the filled top-10 entries as assembled by spv_top_sample, once
+ * the run has ended) into fix_out.
  * Every pointer in a request must stay valid until the request completes;
- * `betas` is copied at submission.
+ * `betas` and `gammas` are copied at submission.
  * Slots are HIP streams; HIP spreads streams over GPU_MAX_HW_QUEUES hardware
  * queues (4 by default) and runs the kernels of one queue in order, so for
  * full overlap set that variable to at least `slots` before the HIP runtime
  * starts.
  */
-typedef enum { SPV_REQ_SA = 1, SPV_REQ_PT = 2 } spv_req_kind;
+typedef enum { SPV_REQ_SA = 1, SPV_REQ_PT = 2, SPV_REQ_SQA = 3 } spv_req_kind;
 
 typedef struct {
     int32_t kind;
     spv_problem problem;
     uint64_t seed;
-    const double *betas;  /* host: SA [sweeps], PT [K] */
+    const double *betas;  /* host: SA and SQA [sweeps], PT [K] */
     int32_t sweeps;
-    int32_t reads;        /* SA */
-    int8_t *spins;        /* SA: device [reads][n] */
-    int64_t *energies;    /* SA: device [reads] */
+    int32_t reads;        /* SA, SQA */
+    int8_t *spins;        /* SA, SQA: device [reads][n] */
+    int64_t *energies;    /* SA, SQA: device [reads] */
     int32_t K, runs, chains, icm_lo, icm_hi; /* PT */
     spv_pt_out pt_out;    /* PT outputs; top_spins/top_E/top_count required for persistence */
     double elite_frac;    /* > 0 enables persistence */
     double threshold;
     int32_t gauge;
     spv_fix_out fix_out;
+    const double *gammas; /* SQA: host [sweeps] */
+    int32_t trotter;      /* SQA: slices per read */
 } spv_request;
 
 typedef struct {

@@ -571,7 +571,7 @@ def spv_batch_last_shape(ctx):
 
 
 # ----------------------------------------------------------------------------- serving
-SPV_REQ_SA, SPV_REQ_PT = 1, 2
+SPV_REQ_SA, SPV_REQ_PT, SPV_REQ_SQA = 1, 2, 3
 
 
 class spv_request(C.Structure):
@@ -580,7 +580,8 @@ class spv_request(C.Structure):
                 ("spins", C.c_void_p), ("energies", C.c_void_p), ("K", C.c_int32),
                 ("runs", C.c_int32), ("chains", C.c_int32), ("icm_lo", C.c_int32),
                 ("icm_hi", C.c_int32), ("pt_out", spv_pt_out), ("elite_frac", C.c_double),
-                ("threshold", C.c_double), ("gauge", C.c_int32), ("fix_out", spv_fix_out)]
+                ("threshold", C.c_double), ("gauge", C.c_int32), ("fix_out", spv_fix_out),
+                ("gammas", C.c_void_p), ("trotter", C.c_int32)]
 
 
 class spv_server_cfg(C.Structure):
@@ -659,6 +660,14 @@ class Server:
         self._fix(req, P, elite_frac, threshold, gauge, keep)
         return req, keep
 
+    def prepare_sqa(self, P, betas, gammas, trotter, reads, seed, elite_frac=0.0, threshold=1.0, gauge=0):
+        """Request struct and output buffers of an SQA (+ persistence) request, not yet submitted."""
+        req, keep = self.prepare_sa(P, betas, reads, seed, elite_frac, threshold, gauge)
+        g = np.ascontiguousarray(gammas, dtype=np.float64)
+        keep["gammas"] = g
+        req.kind, req.gammas, req.trotter = SPV_REQ_SQA, g.ctypes.data, int(trotter)
+        return req, keep
+
     def prepare_pt(self, P, betas, runs, chains, sweeps, seed, icm=None, elite_frac=0.0, threshold=1.0,
                    gauge=0, final=True):
         """Request struct and output buffers of a PT (+ persistence) request, not yet submitted."""
@@ -684,6 +693,9 @@ class Server:
 
     def submit_sa(self, P, betas, reads, seed, elite_frac=0.0, threshold=1.0, gauge=0):
         return self._submit(*self.prepare_sa(P, betas, reads, seed, elite_frac, threshold, gauge))
+
+    def submit_sqa(self, P, betas, gammas, trotter, reads, seed, elite_frac=0.0, threshold=1.0, gauge=0):
+        return self._submit(*self.prepare_sqa(P, betas, gammas, trotter, reads, seed, elite_frac, threshold, gauge))
 
     def submit_pt(self, P, betas, runs, chains, sweeps, seed, icm=None, elite_frac=0.0, threshold=1.0,
                   gauge=0):

@@ -30,7 +30,7 @@ enum State { kPending, kRunning, kDone };
 
 struct Record {
     spv_request req;
-    std::vector<double> betas;
+    std::vector<double> betas, gammas;
     int64_t lds = 0, hbm = 0;
     State state = kPending;
     bool fix_pending = false;  // tempering request whose persistence step follows the sampling
@@ -78,6 +78,12 @@ void footprint(spv_server *s, const spv_request &r, int64_t *lds, int64_t *hbm) 
         L = wgs * (int64_t)sa_lds_bytes(P.n, D, row_len, qw);
         H += (int64_t)r.sweeps * row_len * 4;
         R = r.reads;
+    } else if (r.kind == SPV_REQ_SQA) {
+        // one workgroup per read; the rows are sized for the largest (three-digit) table
+        const int rl = 3 * kDigitSize;
+        L = (int64_t)r.reads * (int64_t)sqa_lds_bytes(P.n, D, rl, std::max(r.trotter, 8));
+        H += (int64_t)r.sweeps * (rl * 4 + 4);
+        R = r.reads;
     } else {
         if (pt_lds_footprint(&s->parent->c, &P, r.K, r.runs, r.chains, r.icm_lo, r.icm_hi, &L) != SPV_OK)
             L = 0;  // the launch itself reports the error
@@ -98,9 +104,12 @@ spv_status launch(Slot &sl, Record &rec) {
     spv_ctx *x = sl.ctx;
     const spv_request &r = rec.req;
     spv_status st;
-    if (r.kind == SPV_REQ_SA) {
-        st = spv_sample(x, &r.problem, rec.betas.data(), r.sweeps, r.reads, r.seed, 0, nullptr, r.spins,
-                        r.energies, sl.stream);
+    if (r.kind == SPV_REQ_SA || r.kind == SPV_REQ_SQA) {
+        st = r.kind == SPV_REQ_SA
+                 ? spv_sample(x, &r.problem, rec.betas.data(), r.sweeps, r.reads, r.seed, 0, nullptr, r.spins,
+                              r.energies, sl.stream)
+                 : spv_sqa_sample(x, &r.problem, rec.betas.data(), rec.gammas.data(), r.sweeps, r.trotter, r.reads,
+                                  r.seed, r.spins, r.energies, sl.stream);
         if (st == SPV_OK && r.elite_frac > 0)
             st = spv_persist_fix(x, &r.problem, r.spins, r.energies, r.reads, r.elite_frac, r.threshold,
                                  r.gauge, &r.fix_out, sl.stream);
@@ -254,10 +263,14 @@ spv_status spv_server_submit(spv_server *s, const spv_request *req, uint64_t *ti
     if (!s || !req || !ticket) return SPV_EINVAL;
     Ctx *c = &s->parent->c;
     const spv_request &r = *req;
-    if (r.kind != SPV_REQ_SA && r.kind != SPV_REQ_PT) return set_err(c, SPV_EINVAL, "request kind %d", r.kind);
-    const int nb = r.kind == SPV_REQ_SA ? r.sweeps : r.K;
+    if (r.kind != SPV_REQ_SA && r.kind != SPV_REQ_PT && r.kind != SPV_REQ_SQA)
+        return set_err(c, SPV_EINVAL, "request kind %d", r.kind);
+    const bool sampled = r.kind == SPV_REQ_SA || r.kind == SPV_REQ_SQA;
+    const int nb = sampled ? r.sweeps : r.K;
     if (nb < 0 || (nb > 0 && !r.betas)) return set_err(c, SPV_EINVAL, "request betas");
-    if (r.kind == SPV_REQ_SA && (r.reads < 1 || !r.energies || (r.problem.n > 0 && !r.spins)))
+    if (r.kind == SPV_REQ_SQA && (r.trotter < 8 || r.trotter > 256 || r.trotter % 8 != 0 || (nb > 0 && !r.gammas)))
+        return set_err(c, SPV_EINVAL, "SQA request: trotter=%d or NULL gammas", r.trotter);
+    if (sampled && (r.reads < 1 || !r.energies || (r.problem.n > 0 && !r.spins)))
         return set_err(c, SPV_EINVAL, "SA request outputs");
     if (r.kind == SPV_REQ_PT && r.elite_frac > 0 && (!r.pt_out.top_spins || !r.pt_out.top_E || !r.pt_out.top_count))
         return set_err(c, SPV_EINVAL, "PT request with persistence needs top_spins, top_E and top_count");
@@ -265,6 +278,8 @@ spv_status spv_server_submit(spv_server *s, const spv_request *req, uint64_t *ti
     rec.req = r;
     rec.betas.assign(r.betas, r.betas + std::max(nb, 0));
     rec.req.betas = nullptr;
+    if (r.kind == SPV_REQ_SQA) rec.gammas.assign(r.gammas, r.gammas + std::max(nb, 0));
+    rec.req.gammas = nullptr;
     footprint(s, r, &rec.lds, &rec.hbm);
     rec.res.lds_bytes = rec.lds;
     rec.res.hbm_bytes = rec.hbm;

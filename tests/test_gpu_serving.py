@@ -45,6 +45,9 @@ def _alone(spv, ctx, r, P):
     if r["kind"] == "sa":
         S, E = spv.spv_sample(ctx, P, r["betas"], r["reads"], r["seed"])
         out = dict(spins=S, energies=E)
+    elif r["kind"] == "sqa":
+        S, E = spv.spv_sqa_sample(ctx, P, r["betas"], r["gammas"], r["trotter"], r["reads"], r["seed"])
+        out = dict(spins=S, energies=E)
     else:
         out = spv.spv_pt_sample(ctx, P, r["betas"], r["runs"], r["chains"], r["sweeps"], r["seed"], icm=r["icm"])
         S, E = spv.spv_top_sample(ctx, out)
@@ -55,10 +58,11 @@ def _alone(spv, ctx, r, P):
 
 
 def _submit(srv, r, P):
-    if r["kind"] == "sa":
-        kw = {} if not r["fix"] else dict(elite_frac=r["fix"][0], threshold=r["fix"][1], gauge=r["fix"][2])
-        return srv.submit_sa(P, r["betas"], r["reads"], r["seed"], **kw)
     kw = {} if not r["fix"] else dict(elite_frac=r["fix"][0], threshold=r["fix"][1], gauge=r["fix"][2])
+    if r["kind"] == "sa":
+        return srv.submit_sa(P, r["betas"], r["reads"], r["seed"], **kw)
+    if r["kind"] == "sqa":
+        return srv.submit_sqa(P, r["betas"], r["gammas"], r["trotter"], r["reads"], r["seed"], **kw)
     return srv.submit_pt(P, r["betas"], r["runs"], r["chains"], r["sweeps"], r["seed"], icm=r["icm"], **kw)
 
 
@@ -67,7 +71,7 @@ def _same(a, b):
 
 
 def _check_against_alone(r, got, want):
-    if r["kind"] == "sa":
+    if r["kind"] in ("sa", "sqa"):
         assert _same(got["spins"], want["spins"]) and _same(got["energies"], want["energies"])
     else:
         for key in ("final_spins", "final_E", "top_spins", "top_E", "top_count"):
@@ -189,3 +193,34 @@ def test_top_sample_matches_oracle_formation(spv, ctx):
     want = oracle.pt_sample(inst, betas, 3, 2, 40, seed=9, icm=(0, 7), threads=3)
     wS, wE = oracle.top_sample(want)
     assert np.array_equal(S.cpu().numpy(), wS) and np.array_equal(E.cpu().numpy(), wE)
+
+
+def test_mixed_stream_with_sqa_requests(spv, ctx):
+    """SQA requests (with and without persistence) served among SA and PT requests: every
+    result equals the same call made alone; one SQA request is recomputed by the oracle."""
+    reqs = []
+    for k in range(4):
+        sw = 25 + 10 * k
+        reqs.append(dict(kind="sqa", inst=si.chimera(2 + k % 2, seed=300 + k), betas=si.linear_betas(0.2, 3.0, sw),
+                         gammas=np.geomspace(3.0, 0.05, sw), trotter=8 * (1 + k % 2), reads=9 + 7 * k, seed=900 + k,
+                         fix=(0.25, 0.9, 0) if k % 2 == 0 else None))
+    reqs += _mix()[:4] + _mix()[10:12]
+    Ps = [spv.Problem.from_instance(r["inst"]) for r in reqs]
+    print(f"[serving] {len(reqs)} requests with SQA, alone", flush=True)
+    alone = [_alone(spv, ctx, r, P) for r, P in zip(reqs, Ps)]
+    print("[serving] mixed with SQA on 3 slots", flush=True)
+    srv = spv.Server(ctx, slots=3)
+    tickets = [_submit(srv, r, P) for r, P in zip(reqs, Ps)]
+    results = [srv.wait(t) for t in tickets]
+    srv.drain()
+    for r, (res, keep), want in zip(reqs, results, alone):
+        assert res.status == 0
+        _check_against_alone(r, keep, want)
+    srv.close()
+    r0, (_, k0) = reqs[0], results[0]
+    osp, oE, _ = oracle.sqa_sample(r0["inst"], r0["betas"], r0["gammas"], r0["trotter"], reads=r0["reads"],
+                                   seed=r0["seed"], threads=8)
+    assert np.array_equal(k0["spins"].cpu().numpy(), osp) and np.array_equal(k0["energies"].cpu().numpy(), oE)
+    w = oracle.persist_fix(r0["inst"], osp, oE, *r0["fix"])
+    assert np.array_equal(k0["fix"]["fixed_val"][:r0["inst"].n].cpu().numpy(), w["fixed_val"])
+    assert int(k0["fix"]["info"][2]) == w["offset"]

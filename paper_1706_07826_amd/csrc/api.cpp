@@ -530,9 +530,12 @@ spv_status spv_sqa_sample(spv_ctx *ctx, const spv_problem *P, const double *beta
     if (nd > 3) return set_err(c, SPV_ERANGE, "x_bound + 2 Jp = %lld needs %d digits (max 3)", (long long)xeff, nd);
     const int row_len = table_row_len(xeff);
     const int n = P->n, D = P->max_degree;
-    if (sqa_lds_bytes(n, D, row_len, trotter) + 256 > c->lds_max)
+    // The instance moves to global memory when it does not fit beside the slices.
+    bool big = getenv("SPVAR_SQA_BIG") && getenv("SPVAR_SQA_BIG")[0] == '1';
+    if (!big && sqa_lds_bytes(n, D, row_len, trotter) + 256 > c->lds_max) big = true;
+    if (sqa_lds_bytes(n, D, row_len, trotter, true) + 256 > c->lds_max)
         return set_err(c, SPV_ECAPACITY, "SQA: %d slices of %d variables need %zu B of LDS > %zu", trotter, n,
-                       sqa_lds_bytes(n, D, row_len, trotter), c->lds_max);
+                       sqa_lds_bytes(n, D, row_len, trotter, true), c->lds_max);
     st = ensure(c, c->image, image_words(n, D) * 4);
     if (st) return st;
     hipError_t e = launch_prep(P, static_cast<int32_t *>(c->image.p), stream);
@@ -556,6 +559,7 @@ spv_status spv_sqa_sample(spv_ctx *ctx, const spv_problem *P, const double *beta
     L.reads = reads;
     L.P = trotter;
     L.x_bound = P->x_bound;
+    L.global_instance = big;
     L.seed = seed;
     // one lane per (site, word of one parity) of the largest colour class
     const int tasks = (n + P->n_colours - 1) / P->n_colours * (trotter / 8);

@@ -168,10 +168,11 @@ struct SqaLaunch {
     int8_t *out;
     int64_t *energies;
     int n, D, C, row_len, nd, sweeps, reads, P, threads, x_bound;
+    bool global_instance = false;  // the instance stays in the global image
     uint64_t seed;
 };
 hipError_t launch_sqa(const SqaLaunch &L, hipStream_t s);
-size_t sqa_lds_bytes(int n, int D, int row_len, int P);
+size_t sqa_lds_bytes(int n, int D, int row_len, int P, bool big = false);
 // Streamed launch of the byte-parallel body (resident workgroups, chunked sweeps).
 int sa_stream_plan(const SaLaunch &L, int num_cus, int force_grid);  // 1: use launch_sa
 size_t sa_stream_bytes(int n, int reads, int qw);

@@ -81,7 +81,10 @@ void footprint(spv_server *s, const spv_request &r, int64_t *lds, int64_t *hbm) 
     } else if (r.kind == SPV_REQ_SQA) {
         // one workgroup per read; the rows are sized for the largest (three-digit) table
         const int rl = 3 * kDigitSize;
-        L = (int64_t)r.reads * (int64_t)sqa_lds_bytes(P.n, D, rl, std::max(r.trotter, 8));
+        const int Pq = std::max(r.trotter, 8);
+        const size_t in_lds = sqa_lds_bytes(P.n, D, rl, Pq);
+        L = (int64_t)r.reads * (int64_t)(in_lds + 256 <= (size_t)s->parent->c.lds_max
+                                             ? in_lds : sqa_lds_bytes(P.n, D, rl, Pq, true));
         H += (int64_t)r.sweeps * (rl * 4 + 4);
         R = r.reads;
     } else {

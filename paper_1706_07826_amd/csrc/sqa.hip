@@ -3,7 +3,8 @@
 // Suzuki-Trotter mapping of Martonak, Santoro and Tosatti, PRB 66, 094203).
 //
 // One workgroup per read.  LDS holds the position-ordered instance (the same
-// ELL image as the general SA body), the acceptance rows of this sweep and the
+// ELL image as the general SA body; read from global memory instead when it
+// does not fit beside the slices), the acceptance rows of this sweep and the
 // next (beta_t / P) and the read's P slices as P/4 words per site: slice
 // k = 2m + parity lives in word parity * P/8 + m/4, byte m % 4, so a word holds
 // four slices of one parity.  A sweep visits the colour classes in order and,
@@ -76,7 +77,9 @@ __device__ __forceinline__ uint32_t sqa_mask(const int32_t x[4], const uint32_t 
     return mask;
 }
 
-template <int ND>
+// BIG: the instance stays in the global image (position-major records), LDS holds
+// the acceptance rows and the slices only.
+template <int ND, bool BIG = false>
 __global__ __launch_bounds__(1024) void sqa_kernel(SqaArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int cs[kMaxColours + 1];
@@ -90,8 +93,15 @@ __global__ __launch_bounds__(1024) void sqa_kernel(SqaArgs a) {
     it.D = D;
     it.C = a.C;
     core::SaLds L;
-    core::sa_layout(n, D, a.row_len, qw, &L, smem);
-    core::sa_load_instance(L, it, cs);  // ends with a barrier
+    if constexpr (BIG) {
+        core::sa_big_layout(n, a.row_len, qw, &L, smem);
+        core::sa_bind_image(&L, it, cs);  // ends with a barrier
+    } else {
+        core::sa_layout(n, D, a.row_len, qw, &L, smem);
+        core::sa_load_instance(L, it, cs);  // ends with a barrier
+    }
+    // record k of position p: nbr[p * rec_p + k * rec_k]
+    const size_t rec_p = BIG ? (size_t)D : 1, rec_k = BIG ? 1 : (size_t)n;
     const uint32_t quad0 = (uint32_t)read * (uint32_t)qw;
     for (int k = tid; a.sweeps > 0 && k < a.row_len; k += T) L.tab[k] = a.tables[k];  // none uploaded without sweeps
     for (int k = tid; k < 4 * qw; k += T) L.E2[k] = 0ull;
@@ -130,7 +140,7 @@ __global__ __launch_bounds__(1024) void sqa_kernel(SqaArgs a) {
                 for (int p = cs[c] + slot; active && p < pe; p += nslots) {
                     const uint32_t *row = L.S + (size_t)p * qw;
                     const uint32_t self = row[w], A = row[wa], B = row[wb];
-                    const core::Fields F = core::local_fields(L.nbr + p, L.S, D, qw, w, L.hpos[p], n);
+                    const core::Fields F = core::local_fields(L.nbr + p * rec_p, L.S, D, qw, w, L.hpos[p], rec_k);
                     // even word: k-1 = odd slice m-1 (A byte b-1, or B byte 3), k+1 = odd slice m (A byte b);
                     // odd word: k-1 = even slice m (A byte b), k+1 = even slice m+1 (A byte b+1, or B byte 0)
                     const uint32_t up = par ? A : __builtin_amdgcn_alignbyte(A, B, 3);
@@ -155,7 +165,7 @@ __global__ __launch_bounds__(1024) void sqa_kernel(SqaArgs a) {
         for (int idx = tid; idx < n * qw; idx += T) {
             const int p = idx / qw, w = idx - p * qw;
             const uint32_t self = L.S[idx];
-            const core::Fields F = core::local_fields(L.nbr + p, L.S, D, qw, w, L.hpos[p], n);
+            const core::Fields F = core::local_fields(L.nbr + p * rec_p, L.S, D, qw, w, L.hpos[p], rec_k);
 #pragma unroll
             for (int b = 0; b < 4; ++b)
                 atomicAdd(&L.E2[w * 4 + b],
@@ -188,8 +198,9 @@ __global__ __launch_bounds__(1024) void sqa_kernel(SqaArgs a) {
 
 }  // namespace
 
-size_t sqa_lds_bytes(int n, int D, int row_len, int P) {
-    return core::sa_layout(n, D, row_len, P / 4, nullptr, nullptr);
+size_t sqa_lds_bytes(int n, int D, int row_len, int P, bool big) {
+    return big ? core::sa_big_layout(n, row_len, P / 4, nullptr, nullptr)
+               : core::sa_layout(n, D, row_len, P / 4, nullptr, nullptr);
 }
 
 hipError_t launch_sqa(const SqaLaunch &L, hipStream_t s) {
@@ -209,21 +220,29 @@ hipError_t launch_sqa(const SqaLaunch &L, hipStream_t s) {
     a.x_bound = L.x_bound;
     a.k0 = (uint32_t)L.seed;
     a.k1 = (uint32_t)(L.seed >> 32);
-    const size_t lds = sqa_lds_bytes(L.n, L.D, L.row_len, L.P);
+    const size_t lds = sqa_lds_bytes(L.n, L.D, L.row_len, L.P, L.global_instance);
     if (L.P % 8 != 0 || L.P < 8 || L.threads % (L.P / 8) != 0 || L.reads < 1) return hipErrorInvalidValue;
+#define SPV_SQA(ND_)                                                                                  \
+    do {                                                                                              \
+        if (L.global_instance)                                                                        \
+            hipLaunchKernelGGL((sqa_kernel<ND_, true>), dim3(L.reads), dim3(L.threads), lds, s, a);   \
+        else                                                                                          \
+            hipLaunchKernelGGL((sqa_kernel<ND_, false>), dim3(L.reads), dim3(L.threads), lds, s, a);  \
+    } while (0)
     switch (L.nd) {
         case 1:
-            hipLaunchKernelGGL(sqa_kernel<1>, dim3(L.reads), dim3(L.threads), lds, s, a);
+            SPV_SQA(1);
             break;
         case 2:
-            hipLaunchKernelGGL(sqa_kernel<2>, dim3(L.reads), dim3(L.threads), lds, s, a);
+            SPV_SQA(2);
             break;
         case 3:
-            hipLaunchKernelGGL(sqa_kernel<3>, dim3(L.reads), dim3(L.threads), lds, s, a);
+            SPV_SQA(3);
             break;
         default:
             return hipErrorInvalidValue;
     }
+#undef SPV_SQA
     return hipGetLastError();
 }
 

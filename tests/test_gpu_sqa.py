@@ -163,3 +163,40 @@ def test_sqa_empty_problem_zero_reads_and_capacity(spv, ctx):
         spv.spv_sqa_sample(ctx, spv.Problem.from_instance(big), b, g, 256, 2, 1)
     assert ei.value.code == -5
     torch.cuda.synchronize()
+
+
+def _with_env(env, fn):
+    import os
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update({k: str(v) for k, v in env.items()})
+    try:
+        return fn()
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+@pytest.mark.parametrize("name,make,P,reads,sweeps", [CASES[i] for i in (0, 3, 4)], ids=[CASES[i][0] for i in (0, 3, 4)])
+def test_sqa_global_instance_forced_small(spv, ctx, name, make, P, reads, sweeps):
+    """The instance read from the global image (slices and rows in LDS), forced on small cases."""
+    inst = make()
+    b, g = _sched(sweeps)
+    _say(f"[sqa] global instance forced: {name}")
+    Pr = spv.Problem.from_instance(inst)
+    sp, E = _with_env({"SPVAR_SQA_BIG": 1}, lambda: spv.spv_sqa_sample(ctx, Pr, b, g, P, reads, 45))
+    osp, oE, _ = oracle.sqa_sample(inst, b, g, P, reads=reads, seed=45, threads=8)
+    assert np.array_equal(sp.cpu().numpy(), osp) and np.array_equal(E.cpu().numpy(), oE)
+
+
+def test_sqa_beyond_lds_cubic20(spv, ctx):
+    """The L = 20 Gaussian cube (N = 8000): its records do not fit beside 8 slices, so the
+    instance stays in global memory; 6 reads x 20 sweeps against the oracle."""
+    inst = si.cubic_lattice(20, "gauss", seed=13, scale_log2=10)
+    b, g = _sched(20, 0.2, 3.0, 3.0, 0.05)
+    _say("[sqa] beyond LDS: cubic20 gauss P=8")
+    sp, E = spv.spv_sqa_sample(ctx, spv.Problem.from_instance(inst), b, g, 8, 6, 46)
+    osp, oE, _ = oracle.sqa_sample(inst, b, g, 8, reads=6, seed=46, threads=6)
+    assert np.array_equal(sp.cpu().numpy(), osp) and np.array_equal(E.cpu().numpy(), oE)

@@ -193,8 +193,9 @@ spv_status spv_philox_probe(spv_ctx *ctx, int32_t iters, double *blocks_per_s, h
  * u P + (k mod 2) P/2 + floor(k/2) for its Philox counters (Metropolis tag 6,
  * initial state tag 1).  Bit-identical to the oracle.  EINVAL for bad
  * arguments; ERANGE when Jp_t reaches 2^24 or x_bound + 2 max Jp needs more
- * than 3 base-512 digits; ECAPACITY when the instance and one read's P slices
- * (P/4 words per variable) exceed a workgroup's LDS.
+ * than 3 base-512 digits; ECAPACITY when one read's P slices (P/4 words per
+ * variable) and the two acceptance rows exceed a workgroup's LDS (the instance
+ * itself is read from global memory when it does not fit beside them).
  */
 spv_status spv_sqa_sample(spv_ctx *ctx, const spv_problem *P, const double *betas, const double *gammas,
                           int32_t sweeps, int32_t trotter, int32_t reads, uint64_t seed, int8_t *spins,

@@ -85,3 +85,25 @@ def test_multistart_with_sqa_matches_oracle(spv, ctx, name, make, P, kw):
     betas, gammas = si.linear_betas(0.2, 3.0, 40), np.geomspace(3.0, 0.05, 40)
     print(f"[multistart] {name} n={inst.n} P={P}", flush=True)
     _run(spv, ctx, inst, betas, gammas=gammas, trotter=P, **kw)
+
+
+def test_multistart_sqa_workload_size_sampled(spv, ctx):
+    """The multistart_sqa workload as the benchmark launches it (Chimera 8x8, 20 starts x (1000 +
+    1000 reads) x 2000 sweeps, 16 slices): sampled fixing rows of the first and last starts
+    recomputed by the oracle, and the best state's energy re-evaluated."""
+    inst = cf.instance(cf.CHIMERA8_SA)
+    betas = cf.betas(cf.CHIMERA8_SA)
+    gammas = np.geomspace(3.0, 0.01, betas.size)
+    cfg = cf.CHIMERA8_SA
+    print("[multistart] SQA workload size", flush=True)
+    got = spv.spv_multistart(ctx, spv.Problem.from_instance(inst), betas, cfg["seed"], 20, 1000, 1000, cfg["elite"],
+                             cfg["theta"], cfg["gauge"], merge=True, gammas=gammas, trotter=16)
+    fE = got["fixing_E"].cpu().numpy()
+    for s, r in ((0, 0), (0, 999), (19, 500)):
+        _, oE, _ = oracle.sqa_sample(inst, betas, gammas, 16, seed=cfg["seed"], r_begin=1000 * s + r,
+                                     r_end=1000 * s + r + 1)
+        assert fE[s, r] == oE[0], (s, r)
+    best = got["best_spins"].cpu().numpy()
+    assert got["best_E"] == int(oracle.energy(inst, best[None])[0])
+    allE = np.concatenate([fE.ravel(), got["solving_E"].cpu().numpy().ravel()])
+    assert got["best_E"] == allE.min()

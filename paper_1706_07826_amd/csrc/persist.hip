@@ -218,7 +218,22 @@ __global__ __launch_bounds__(64) void bitmap_kernel(const int8_t *__restrict__ S
     const int i0 = blockIdx.y * cols_per_block;
     const int i1 = min(n, i0 + cols_per_block);
     bool bad = false;
-    for (int i = i0; i < i1; ++i) {
+    int i = i0;
+    // rows read 4 columns at a time when every row starts on a 4-byte boundary
+    // (cols_per_block is a multiple of 4, so i0 keeps that alignment)
+    if ((n & 3) == 0 && (reinterpret_cast<uintptr_t>(S) & 3) == 0) {
+        for (; i + 4 <= i1; i += 4) {
+            const uint32_t v4 = valid ? *reinterpret_cast<const uint32_t *>(srow + i) : 0x01010101u;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int8_t v = (int8_t)(v4 >> (8 * b));
+                bad |= (v != 1 && v != -1);
+                const unsigned long long word = __ballot(valid && v > 0);
+                if (lane == 0) f.bits[(size_t)(i + b) * f.W + w] = word;
+            }
+        }
+    }
+    for (; i < i1; ++i) {
         const int8_t v = valid ? srow[i] : (int8_t)1;
         bad |= (v != 1 && v != -1);
         const unsigned long long word = __ballot(valid && v > 0);
@@ -545,7 +560,7 @@ hipError_t launch_persist_fix(const FixLaunch &L, hipStream_t s) {
                        reinterpret_cast<const long long *>(L.energies), L.R, L.m, f);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int cols = 256;
+    const int cols = 64;  // a multiple of 4 (the kernel's 4-column reads)
     if (n > 0) {
         hipLaunchKernelGGL(bitmap_kernel, dim3(f.W, (n + cols - 1) / cols), dim3(64), 0, s,
                            L.samples, n, L.m, f, cols);

@@ -241,7 +241,7 @@ spv_status spv_sample_batch(spv_ctx *ctx, int32_t B, const spv_problem *problems
             }
     float tuned_ms = -1.f;
     if (!have && (flags & SPV_BATCH_TUNE)) {
-        static const Shape cand[] = {{256, 1, 4}, {256, 2, 4}, {512, 1, 2}, {512, 2, 2},
+        static const Shape cand[] = {{64, 2, 16}, {128, 2, 8}, {128, 4, 8}, {256, 1, 4}, {256, 2, 4}, {512, 1, 2}, {512, 2, 2},
                                      {512, 4, 2}, {1024, 2, 1}, {1024, 4, 1}, {1024, 8, 1}};
         const int tsweeps = std::min(sweeps, 24);
         hipEvent_t e0, e1;

@@ -136,10 +136,20 @@ spv_status spv_multistart(spv_ctx *ctx, const spv_problem *P, const spv_multista
                 if ((st = spv_sqa_sample(ctx, &probs[b], prm->betas, prm->gammas, prm->sweeps, prm->trotter, Rs,
                                          seeds[b], sp[b], en[b], stream)))
                     return st;
-        } else if (!probs.empty() &&
-                   (st = spv_sample_batch(ctx, (int32_t)probs.size(), probs.data(), prm->betas, prm->sweeps,
-                                          reads.data(), seeds.data(), sp.data(), en.data(), nullptr, stream))) {
-            return st;
+        } else if (!probs.empty()) {
+            // Residuals after fixing are small: a workgroup just wide enough for one
+            // colour class x 2 quad words (one wavefront for ~60 free variables), so each
+            // item's barriers stay cheap and many items share a CU.
+            int cls = 1;
+            for (const spv_problem &q2 : probs) cls = std::max(cls, (q2.n + q2.n_colours - 1) / q2.n_colours);
+            spv_batch_opts bo;
+            bo.threads = std::min(256, (2 * cls + 63) / 64 * 64);
+            bo.quads_per_item = 2;
+            bo.wgs_per_cu = std::min(16, 1024 / bo.threads);
+            bo.flags = 0;
+            if ((st = spv_sample_batch(ctx, (int32_t)probs.size(), probs.data(), prm->betas, prm->sweeps, reads.data(),
+                                       seeds.data(), sp.data(), en.data(), &bo, stream)))
+                return st;
         }
         // 4. Optional recombination over each modified problem's components (Sec. II.C).
         if (merge) {

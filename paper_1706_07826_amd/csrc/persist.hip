@@ -195,13 +195,16 @@ __global__ __launch_bounds__(1024) void elite_kernel(const long long *__restrict
             lt = key < kstar;
             eq = key == kstar;
         }
-        int eq_tot;
-        const int eq_pre = dev::block_exclusive_scan(eq ? 1 : 0, tmp, &eq_tot);
-        const bool take = lt || (eq && eq_base + eq_pre < need_eq);
+        // one scan of both counts (lt in the low 16 bits, eq in the high 16; a chunk
+        // holds at most 1024 rows); the chunk takes its lt rows and its first `rem`
+        // eq rows, so a taken row's slot is lt_pre + min(eq_pre, rem)
         int tot;
-        const int pre = dev::block_exclusive_scan(take ? 1 : 0, tmp, &tot);
-        if (take) f.elite[out_base + pre] = r;
-        out_base += tot;
+        const int pre = dev::block_exclusive_scan((lt ? 1 : 0) | (eq ? 1 << 16 : 0), tmp, &tot);
+        const int lt_pre = pre & 0xFFFF, eq_pre = pre >> 16, lt_tot = tot & 0xFFFF, eq_tot = tot >> 16;
+        const int rem = need_eq - eq_base > 0 ? need_eq - eq_base : 0;
+        const bool take = lt || (eq && eq_pre < rem);
+        if (take) f.elite[out_base + lt_pre + min(eq_pre, rem)] = r;
+        out_base += lt_tot + min(eq_tot, rem);
         eq_base += eq_tot;
     }
 }

@@ -14,7 +14,7 @@ def pytest_configure(config):
 
 
 def pytest_collection_modifyitems(config, items):
-    # GPU tests skip cleanly where no HIP device is visible; on the GPU machine they run.
+    # GPU tests skip cleanly where no HIP device is visible; with an MI355X they run.
     try:
         import torch
         have_gpu = torch.cuda.is_available()

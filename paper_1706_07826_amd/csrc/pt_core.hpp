@@ -22,6 +22,46 @@ __device__ __forceinline__ long long wave_sum(long long v) {
     return v;
 }
 
+// Xor mask (0xFE per accepted byte) of the Metropolis decisions for x[b] = -s f of
+// four replicas at their own temperatures (acceptance rows tb[b]): a byte is accepted
+// iff every nonzero digit of x passes (x <= 0 has none).  The first digit's block is
+// drawn without a branch (some byte of a word almost always has a nonzero first
+// digit), so the decisions stay lane masks; a later digit's block is drawn where
+// some byte has that digit nonzero (a byte already rejected stays rejected).
+template <int ND>
+__device__ __forceinline__ uint32_t metropolis_mask4(const int32_t x[4], const uint32_t *const tb[4], uint32_t i,
+                                                     uint32_t t, uint32_t quad, uint32_t k0, uint32_t k1) {
+    uint32_t d[4], th[4], mask = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        d[b] = x[b] > 0 ? ((uint32_t)x[b] & (kDigitSize - 1)) : 0u;
+        th[b] = tb[b][d[b]];  // a zero digit reads a valid entry it ignores
+    }
+    {
+        const dev::Words4 w = dev::philox(i, t, quad, 2u << 24, k0, k1);
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            if ((d[b] == 0) | (w.w[b] < th[b])) mask |= 0xFEu << (8 * b);
+    }
+#pragma unroll
+    for (int j = 1; j < ND; ++j) {
+        bool need = false;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            d[b] = x[b] > 0 ? (((uint32_t)x[b] >> (kDigitBits * j)) & (kDigitSize - 1)) : 0u;
+            need |= d[b] != 0;
+            th[b] = tb[b][j * kDigitSize + d[b]];
+        }
+        if (need) {
+            const dev::Words4 w = dev::philox(i, t, quad, (2u << 24) | (uint32_t)j, k0, k1);
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                if ((d[b] != 0) & (w.w[b] >= th[b])) mask &= ~(0xFEu << (8 * b));
+        }
+    }
+    return mask;
+}
+
 // Replica-exchange decision (digit test of D with the tables of dbeta_k).  The
 // thresholds of every nonzero digit are fetched together, then compared.
 __device__ inline bool swap_test(long long D, const uint32_t *__restrict__ T, int nd, uint32_t k, uint32_t t,

@@ -259,41 +259,13 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                 int32_t f[4];
                 ptc::quad_fields<DK>(NBR, D, p, L_S, nq, q, HPOS(p), f);
                 int32_t x[4];
-                bool up[4], pass[4];
 #pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    x[b] = dev::spin_of(self, b) > 0 ? -f[b] : f[b];
-                    up[b] = x[b] > 0;
-                    pass[b] = true;
-                }
-                const uint32_t i = (uint32_t)ORD(p);
-#pragma unroll
-                for (int j = 0; j < ND; ++j) {
-                    uint32_t d[4];
-                    bool need = false;
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) {
-                        d[b] = up[b] ? (((uint32_t)x[b] >> (kDigitBits * j)) & (kDigitSize - 1)) : 0u;
-                        need |= pass[b] && d[b] != 0;
-                    }
-                    // thresholds loaded for every replica (a zero digit reads a valid entry it
-                    // ignores), so the four LDS reads overlap the Philox block
-                    uint32_t th[4];
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) th[b] = tb[b][j * kDigitSize + d[b]];
-                    if (need) {
-                        const dev::Words4 w = dev::philox(i, t, quad, (2u << 24) | (uint32_t)j, a.k0, a.k1);
-#pragma unroll
-                        for (int b = 0; b < 4; ++b) pass[b] = pass[b] & ((d[b] == 0) | (w.w[b] < th[b]));
-                    }
-                }
-                uint32_t mask = 0;
+                for (int b = 0; b < 4; ++b) x[b] = dev::spin_of(self, b) > 0 ? -f[b] : f[b];
+                const uint32_t mask =
+                    ptc::metropolis_mask4<ND>(x, tb, (uint32_t)ORD(p), t, quad, a.k0, a.k1);
 #pragma unroll
                 for (int b = 0; b < 4; ++b)
-                    if (!up[b] || pass[b]) {
-                        mask |= 0xFEu << (8 * b);
-                        dE[b] += 2ll * x[b];
-                    }
+                    if (mask & (0xFEu << (8 * b))) dE[b] += 2ll * x[b];
                 if (mask) L_S[(size_t)p * nq + q] = self ^ mask;
             }
             __syncthreads();

@@ -109,42 +109,46 @@ __device__ __forceinline__ Fields local_fields(const uint32_t *__restrict__ nb,
     return F;
 }
 
-// Xor mask (0xFE per accepted byte) of the Metropolis decisions for x[b] = -s f.
+// Xor mask (0xFE per accepted byte) of the Metropolis decisions for x[b] = -s f: a
+// byte is accepted iff every nonzero digit of x passes its threshold (x <= 0 has
+// none).  The first digit's block is drawn without a branch (some byte of a word
+// almost always has a nonzero first digit), so the decisions stay lane masks; a
+// later digit's block is drawn where some byte has that digit nonzero (a byte
+// already rejected stays rejected, so testing it again changes nothing).
+// Thresholds are loaded for every byte (a zero digit reads a valid entry it
+// ignores), so the four LDS reads overlap the Philox block.
 template <int ND>
 __device__ __forceinline__ uint32_t metropolis_mask(const int32_t x[4], const uint32_t *tab,
                                                     uint32_t i, uint32_t t, uint32_t quad,
                                                     uint32_t k0, uint32_t k1) {
-    bool pass[4];
-    bool up[4];
+    uint32_t d[4], th[4], mask = 0;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-        up[b] = x[b] > 0;
-        pass[b] = true;
+        d[b] = x[b] > 0 ? ((uint32_t)x[b] & (kDigitSize - 1)) : 0u;
+        th[b] = tab[d[b]];
+    }
+    {
+        const dev::Words4 w = dev::philox(i, t, quad, 2u << 24, k0, k1);
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            if ((d[b] == 0) | (w.w[b] < th[b])) mask |= 0xFEu << (8 * b);
     }
 #pragma unroll
-    for (int j = 0; j < ND; ++j) {
-        uint32_t d[4];
+    for (int j = 1; j < ND; ++j) {
         bool need = false;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            d[b] = up[b] ? (((uint32_t)x[b] >> (kDigitBits * j)) & (kDigitSize - 1)) : 0u;
-            need |= pass[b] && d[b] != 0;
+            d[b] = x[b] > 0 ? (((uint32_t)x[b] >> (kDigitBits * j)) & (kDigitSize - 1)) : 0u;
+            need |= d[b] != 0;
+            th[b] = tab[j * kDigitSize + d[b]];
         }
-        // thresholds loaded for every replica (a zero digit reads a valid entry it
-        // ignores), so the four LDS reads overlap the Philox block
-        uint32_t th[4];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) th[b] = tab[j * kDigitSize + d[b]];
         if (need) {
             const dev::Words4 w = dev::philox(i, t, quad, (2u << 24) | (uint32_t)j, k0, k1);
 #pragma unroll
-            for (int b = 0; b < 4; ++b) pass[b] = pass[b] & ((d[b] == 0) | (w.w[b] < th[b]));
+            for (int b = 0; b < 4; ++b)
+                if ((d[b] != 0) & (w.w[b] >= th[b])) mask &= ~(0xFEu << (8 * b));
         }
     }
-    uint32_t mask = 0;
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-        if (!up[b] || pass[b]) mask |= 0xFEu << (8 * b);
     return mask;
 }
 

@@ -43,37 +43,43 @@ struct SqaArgs {
 };
 
 // Xor mask (0xFE per accepted byte) of the digit tests for x[b] (slice tag); digits
-// from ndt on are zero for every x of this sweep (ndt is wave-uniform).
+// from ndt on are zero for every x of this sweep (ndt is wave-uniform).  A byte is
+// accepted iff every nonzero digit of x passes (x <= 0 has none).  The first digit's
+// block is drawn without a branch (some byte of a word almost always has a nonzero
+// first digit); a later digit's block is drawn where some byte has that digit nonzero
+// (a byte already rejected stays rejected, so testing it again changes nothing).
 template <int ND>
 __device__ __forceinline__ uint32_t sqa_mask(const int32_t x[4], const uint32_t *tab, uint32_t i, uint32_t t,
                                              uint32_t quad, uint32_t k0, uint32_t k1, int ndt) {
-    bool pass[4], up[4];
+    uint32_t d[4], th[4], mask = 0;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-        up[b] = x[b] > 0;
-        pass[b] = true;
+        d[b] = x[b] > 0 ? ((uint32_t)x[b] & (kDigitSize - 1)) : 0u;
+        th[b] = tab[d[b]];  // a zero digit reads a valid entry it ignores
+    }
+    {
+        const dev::Words4 w = dev::philox(i, t, quad, kTagSqa << 24, k0, k1);
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            if ((d[b] == 0) | (w.w[b] < th[b])) mask |= 0xFEu << (8 * b);
     }
 #pragma unroll
-    for (int j = 0; j < ND; ++j) {
+    for (int j = 1; j < ND; ++j) {
         if (j >= ndt) break;
-        uint32_t d[4], th[4];
         bool need = false;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            d[b] = up[b] ? (((uint32_t)x[b] >> (kDigitBits * j)) & (kDigitSize - 1)) : 0u;
-            need |= pass[b] && d[b] != 0;
-            th[b] = tab[j * kDigitSize + d[b]];  // a zero digit reads a valid entry it ignores
+            d[b] = x[b] > 0 ? (((uint32_t)x[b] >> (kDigitBits * j)) & (kDigitSize - 1)) : 0u;
+            need |= d[b] != 0;
+            th[b] = tab[j * kDigitSize + d[b]];
         }
         if (need) {
             const dev::Words4 w = dev::philox(i, t, quad, (kTagSqa << 24) | (uint32_t)j, k0, k1);
 #pragma unroll
-            for (int b = 0; b < 4; ++b) pass[b] = pass[b] & ((d[b] == 0) | (w.w[b] < th[b]));
+            for (int b = 0; b < 4; ++b)
+                if ((d[b] != 0) & (w.w[b] >= th[b])) mask &= ~(0xFEu << (8 * b));
         }
     }
-    uint32_t mask = 0;
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-        if (!up[b] || pass[b]) mask |= 0xFEu << (8 * b);
     return mask;
 }
 
@@ -148,7 +154,7 @@ __global__ __launch_bounds__(1024) void sqa_kernel(SqaArgs a) {
                     int32_t x[4];
 #pragma unroll
                     for (int b = 0; b < 4; ++b) {
-                        const int32_t g = F.f[b] - jp * (dev::spin_of(up, b) + dev::spin_of(dn, b));
+                        const int32_t g = F.f[b] - __mul24(jp, dev::spin_of(up, b) + dev::spin_of(dn, b));  // |Jp| < 2^24
                         x[b] = dev::spin_of(self, b) > 0 ? -g : g;
                     }
                     const uint32_t mask =

@@ -25,6 +25,7 @@
 #include "device.hpp"
 #include "internal.hpp"
 #include "sa_core.hpp"
+#include "swar_core.hpp"
 
 namespace spv {
 
@@ -83,6 +84,25 @@ __device__ __forceinline__ uint32_t sqa_mask(const int32_t x[4], const uint32_t 
     return mask;
 }
 
+// Classical fields of the four slices of one word from records expanded for the
+// slice rows: record k of a position holds the LDS byte address of its neighbour's
+// row of slice words and J sign-extended, so a neighbour costs one 8-byte read, one
+// add and the four multiply-adds.  `w4` is the word's byte offset in a row.
+__device__ __forceinline__ core::Fields sqa_fields(const uint2 *__restrict__ nb, int n, int D, uint32_t w4,
+                                                   int32_t hv) {
+    core::Fields F;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) F.f[b] = hv;
+    for (int k = 0; k < D; ++k) {
+        const uint2 r = nb[(size_t)k * n];
+        const uint32_t s = core::swar_ld32(r.x + w4);
+        const int32_t J = (int32_t)r.y;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) F.f[b] += __mul24(J, dev::spin_of(s, b));  // |J| < 2^15
+    }
+    return F;
+}
+
 // BIG: the instance stays in the global image (position-major records), LDS holds
 // the acceptance rows and the slices only.
 template <int ND, bool BIG = false>
@@ -103,9 +123,24 @@ __global__ __launch_bounds__(1024) void sqa_kernel(SqaArgs a) {
         core::sa_big_layout(n, a.row_len, qw, &L, smem);
         core::sa_bind_image(&L, it, cs);  // ends with a barrier
     } else {
-        core::sa_layout(n, D, a.row_len, qw, &L, smem);
-        core::sa_load_instance(L, it, cs);  // ends with a barrier
+        // the record area holds n * D expanded records of two words each
+        core::sa_layout(n, 2 * D, a.row_len, qw, &L, smem);
+        if (tid <= a.C) cs[tid] = a.image[3 + tid];
+        const uint32_t *recs = reinterpret_cast<const uint32_t *>(a.image + kImgHeader + 3 * n);
+        uint2 *nb2 = reinterpret_cast<uint2 *>(L.nbr);
+        const uint32_t sb = core::swar_lds_addr(L.S), row_bytes = 4u * (uint32_t)qw;
+        for (int idx = tid; idx < n * D; idx += T) {  // neighbour-major: record k of p at [k * n + p]
+            const int p = idx / D, k = idx - p * D;
+            const uint32_t r = recs[idx];
+            nb2[(size_t)k * n + p] = make_uint2(sb + (r >> 16) * row_bytes, (uint32_t)(int32_t)(int16_t)(r & 0xffffu));
+        }
+        for (int k = tid; k < n; k += T) {
+            L.hpos[k] = a.image[kImgHeader + 2 * n + k];
+            L.ord[k] = a.image[kImgHeader + k];
+        }
+        __syncthreads();
     }
+    const uint2 *const nb2 = reinterpret_cast<const uint2 *>(L.nbr);
     // record k of position p: nbr[p * rec_p + k * rec_k]
     const size_t rec_p = BIG ? (size_t)D : 1, rec_k = BIG ? 1 : (size_t)n;
     const uint32_t quad0 = (uint32_t)read * (uint32_t)qw;
@@ -146,7 +181,11 @@ __global__ __launch_bounds__(1024) void sqa_kernel(SqaArgs a) {
                 for (int p = cs[c] + slot; active && p < pe; p += nslots) {
                     const uint32_t *row = L.S + (size_t)p * qw;
                     const uint32_t self = row[w], A = row[wa], B = row[wb];
-                    const core::Fields F = core::local_fields(L.nbr + p * rec_p, L.S, D, qw, w, L.hpos[p], rec_k);
+                    core::Fields F;
+                    if constexpr (BIG)
+                        F = core::local_fields(L.nbr + p * rec_p, L.S, D, qw, w, L.hpos[p], rec_k);
+                    else
+                        F = sqa_fields(nb2 + p, n, D, 4u * (uint32_t)w, L.hpos[p]);
                     // even word: k-1 = odd slice m-1 (A byte b-1, or B byte 3), k+1 = odd slice m (A byte b);
                     // odd word: k-1 = even slice m (A byte b), k+1 = even slice m+1 (A byte b+1, or B byte 0)
                     const uint32_t up = par ? A : __builtin_amdgcn_alignbyte(A, B, 3);
@@ -171,7 +210,11 @@ __global__ __launch_bounds__(1024) void sqa_kernel(SqaArgs a) {
         for (int idx = tid; idx < n * qw; idx += T) {
             const int p = idx / qw, w = idx - p * qw;
             const uint32_t self = L.S[idx];
-            const core::Fields F = core::local_fields(L.nbr + p * rec_p, L.S, D, qw, w, L.hpos[p], rec_k);
+            core::Fields F;
+            if constexpr (BIG)
+                F = core::local_fields(L.nbr + p * rec_p, L.S, D, qw, w, L.hpos[p], rec_k);
+            else
+                F = sqa_fields(nb2 + p, n, D, 4u * (uint32_t)w, L.hpos[p]);
 #pragma unroll
             for (int b = 0; b < 4; ++b)
                 atomicAdd(&L.E2[w * 4 + b],
@@ -206,7 +249,7 @@ __global__ __launch_bounds__(1024) void sqa_kernel(SqaArgs a) {
 
 size_t sqa_lds_bytes(int n, int D, int row_len, int P, bool big) {
     return big ? core::sa_big_layout(n, row_len, P / 4, nullptr, nullptr)
-               : core::sa_layout(n, D, row_len, P / 4, nullptr, nullptr);
+               : core::sa_layout(n, 2 * D, row_len, P / 4, nullptr, nullptr);  // expanded records
 }
 
 hipError_t launch_sqa(const SqaLaunch &L, hipStream_t s) {

@@ -224,7 +224,8 @@ spv_status spv_energy(spv_ctx *ctx, const spv_problem *P, const int8_t *spins, i
  *                   the gauge was not applied), m, k_min, status (0, or a
  *                   negative spv_status detected on the device: SPV_EINVAL
  *                   for an entry other than +-1 in an elite row (the only
- *                   rows read), SPV_ERANGE for an h' outside int32,
+ *                   rows read) or for an energy of INT64_MIN (the mark of an
+ *                   abandoned streamed sample, spv_sample), SPV_ERANGE for an h' outside int32,
  *                   SPV_EINTERNAL for an unresolved gauge hash)
  */
 typedef struct {
@@ -556,7 +557,8 @@ typedef struct {
 } spv_server_cfg;
 
 typedef struct {
-    int32_t status;       /* SPV_OK or the request's error */
+    int32_t status;       /* SPV_OK or the request's error (with persistence: also a
+                             nonzero device status of the fixing step, fix_out.info[7]) */
     int64_t submit_ns;    /* host steady clock, nanoseconds */
     int64_t start_ns;     /* launched on a slot */
     int64_t done_ns;      /* completion observed */

@@ -917,6 +917,10 @@ int orc_persist_fix(const orc_problem *P, const int8_t *samples, const int64_t *
         for (i = 0; i < n; ++i)
             if (samples[(size_t)r * n + i] != 1 && samples[(size_t)r * n + i] != -1)
                 return ORC_EINVAL;
+    /* INT64_MIN is no energy of any state (|E| <= sum|J| + sum|h|): it marks an invalid read. */
+    for (r = 0; r < R; ++r)
+        if (energies[r] == INT64_MIN)
+            return ORC_EINVAL;
     mm = ceil(elite_frac * (double)R);
     m = (int32_t)mm;
     if (m < 1)

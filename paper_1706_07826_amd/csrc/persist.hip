@@ -130,7 +130,9 @@ __global__ __launch_bounds__(1024) void elite_kernel(const long long *__restrict
         pass0_s = p0;
         prefix_s = p0 < 0 ? lo : (p0 == 7 ? 0ull : lo & (~0ull << (8 * p0 + 8)));
         need_s = m;  // rank (1-based) of the wanted key among the candidates
-        f.hdr[0] = 0;
+        // INT64_MIN is no energy (|E| <= sum |J| + sum |h| < 2^62): it marks the reads of an
+        // abandoned streamed sample, which must not be fixed from.
+        f.hdr[0] = lo == 0ull ? (long long)SPV_EINVAL : 0;
     }
     __syncthreads();
     for (int pass = pass0_s; pass >= 0; --pass) {

@@ -174,6 +174,16 @@ void progress_locked(spv_server *s) {
             if (st == SPV_OK) continue;
             rec.res.status = st;
         }
+        if (q == hipSuccess && rec.res.status == SPV_OK && rec.req.elite_frac > 0 && rec.req.fix_out.info) {
+            // The persistence step's device status (info[7]) becomes the request's status.
+            int64_t dev_status = 0;
+            DeviceGuard g(s->device);
+            hipError_t e = hipMemcpyAsync(&dev_status, rec.req.fix_out.info + 7, sizeof dev_status,
+                                          hipMemcpyDeviceToHost, sl.stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(sl.stream);
+            if (e != hipSuccess) rec.res.status = SPV_EDEVICE;
+            else if (dev_status != 0) rec.res.status = (spv_status)dev_status;
+        }
         rec.res.done_ns = now_ns();
         if (q != hipSuccess && rec.res.status == SPV_OK) rec.res.status = SPV_EDEVICE;
         rec.state = kDone;

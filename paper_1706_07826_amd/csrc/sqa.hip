@@ -193,7 +193,7 @@ __global__ __launch_bounds__(1024) void sqa_kernel(SqaArgs a) {
                     int32_t x[4];
 #pragma unroll
                     for (int b = 0; b < 4; ++b) {
-                        const int32_t g = F.f[b] - __mul24(jp, dev::spin_of(up, b) + dev::spin_of(dn, b));  // |Jp| < 2^24
+                        const int32_t g = F.f[b] - jp * (dev::spin_of(up, b) + dev::spin_of(dn, b));  // full 32-bit product: Jp <= 2^24
                         x[b] = dev::spin_of(self, b) > 0 ? -g : g;
                     }
                     const uint32_t mask =

@@ -175,10 +175,50 @@ def test_sa_streamed_launch_abandoned_wait_is_marked(spv, ctx):
     S, E = _with_env({"SPVAR_SA_STREAM": 16, "SPVAR_SA_SPIN": 1},
                      lambda: spv.spv_sample(ctx, P, betas, 30, 1234))
     osp, oE = oracle.sa_sample(inst, betas, reads=30, seed=1234)
-    E = E.cpu().numpy()
-    marked = E == np.iinfo(np.int64).min
-    assert np.all(marked | (E == oE))
+    En = E.cpu().numpy()
+    marked = En == np.iinfo(np.int64).min
+    assert np.all(marked | (En == oE))
     assert set(np.unique(S.cpu().numpy())).issubset({-1, 1})
+    # Persistence refuses a sample holding marked reads (it would fix from abandoned states).
+    fx = spv.spv_persist_fix(ctx, P, S, E, 0.1, 1.0, 2)
+    if marked.any():
+        with pytest.raises(spv.SpvError) as ei:
+            fx.info()
+        assert ei.value.code == -1
+    else:
+        want = oracle.persist_fix(inst, osp, oE, 0.1, 1.0, 2)
+        assert fx.info()["n_free"] == want["n_free"]
+    # ISPVAR under the same wait limit: the oracle's fixes, or an error, never a silent fix.
+    def ispvar():
+        return spv.spv_ispvar(ctx, P, betas, 30, 1234, 2, 0.1, 1.0, 2)
+    try:
+        fm, fv, info = _with_env({"SPVAR_SA_STREAM": 16, "SPVAR_SA_SPIN": 1}, ispvar)
+    except spv.SpvError as e:
+        assert e.code == -1
+    else:
+        want = oracle.ispvar(inst, betas, 30, 1234, 2, 0.1, 1.0, 2)
+        assert np.array_equal(fv.cpu().numpy()[:inst.n], want["fixed_val"])
+
+
+def test_persist_fix_rejects_marked_energy(spv, ctx):
+    """A sample whose energies hold INT64_MIN (the mark of an abandoned streamed read) is
+    refused by persistence with SPV_EINVAL in info[7], on the device as in the oracle."""
+    inst = si.chimera(2, seed=21)
+    betas = si.linear_betas(0.1, 3.0, 50)
+    P = spv.Problem.from_instance(inst)
+    S, E = spv.spv_sample(ctx, P, betas, 40, 5)
+    E[17] = np.iinfo(np.int64).min
+    _say("[sa] persistence on a planted INT64_MIN energy")
+    with pytest.raises(spv.SpvError) as ei:
+        spv.spv_persist_fix(ctx, P, S, E, 0.25, 1.0, 0).info()
+    assert ei.value.code == -1
+    with pytest.raises(oracle.OracleError):
+        oracle.persist_fix(inst, S.cpu().numpy(), E.cpu().numpy(), 0.25, 1.0, 0)
+    # the context stays usable
+    E2 = spv.spv_energy(ctx, P, S)
+    fx = spv.spv_persist_fix(ctx, P, S, E2, 0.25, 1.0, 0)
+    want = oracle.persist_fix(inst, S.cpu().numpy(), E2.cpu().numpy(), 0.25, 1.0, 0)
+    assert fx.info()["offset"] == want["offset"]
 
 
 @pytest.mark.parametrize("name,make,reads,sweeps,br", SMALL[:6], ids=[c[0] for c in SMALL[:6]])

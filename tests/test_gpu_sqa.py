@@ -73,6 +73,46 @@ def test_sqa_three_digit_tables(spv, ctx):
     assert np.array_equal(sp.cpu().numpy(), osp) and np.array_equal(E.cpu().numpy(), oE)
 
 
+def _beta_for_top_coupling(gamma, trotter, scale_log2):
+    """The beta (bisected on the oracle's coupling) whose slice coupling rounds to 2^24, the
+    largest the library accepts."""
+    lo, hi = 1e-4, 0.01  # coupling out of range at lo, inside at hi (it falls with beta)
+
+    def jp(b):
+        try:
+            return oracle.sqa_coupling(b, gamma, trotter, scale_log2)
+        except oracle.OracleError:
+            return None
+    assert jp(lo) is None and jp(hi) is not None
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if mid in (lo, hi):
+            break
+        if jp(mid) is None:
+            lo = mid
+        else:
+            hi = mid
+    return hi, jp(hi)
+
+
+def test_sqa_slice_coupling_above_2_23(spv, ctx):
+    """Slice couplings in [2^23, 2^24] (tiny beta at strong Gamma): the slice term needs the full
+    32-bit product; a signed 24-bit multiply would wrap these couplings negative. The first sweep
+    sits exactly at the accepted maximum 2^24."""
+    inst = si.cubic_lattice(4, "pm1", seed=13, scale_log2=10)
+    b_top, j_top = _beta_for_top_coupling(3.0, 8, 10)
+    assert j_top == 1 << 24, j_top
+    b = np.r_[b_top, np.linspace(0.0021, 0.0031, 11), si.linear_betas(0.05, 3.0, 20)]
+    g = np.r_[np.full(12, 3.0), np.geomspace(3.0, 0.05, 20)]
+    jps = [oracle.sqa_coupling(x, y, 8, 10) for x, y in zip(b, g)]
+    assert sum((1 << 23) <= j < (1 << 24) for j in jps) >= 10 and max(jps) == 1 << 24
+    Pr = spv.Problem.from_instance(inst)
+    _say(f"[sqa] Jp up to 2^24: n={inst.n} P=8 reads=12 sweeps={b.size}")
+    sp, E = spv.spv_sqa_sample(ctx, Pr, b, g, 8, 12, 45)
+    osp, oE, _ = oracle.sqa_sample(inst, b, g, 8, reads=12, seed=45, threads=6)
+    assert np.array_equal(sp.cpu().numpy(), osp) and np.array_equal(E.cpu().numpy(), oE)
+
+
 def test_sqa_chimera8_config_size_sampled_reads(spv, ctx):
     """Chimera 8x8 (N = 512), 16 slices, 400 reads x 300 sweeps on the device; 24 reads
     recomputed by the oracle, every energy equal to its state's."""

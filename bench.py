@@ -205,12 +205,13 @@ def main():
         torch.cuda.synchronize()
 
     mean_deg = inst.nnz / inst.n
-    byte_parallel = P.x_bound <= 255  # the library's rule for its byte-parallel body
+    max_degree, x_bound = spv.spv_problem_check(ctx, P)  # the bounds the library derives at ingest
+    byte_parallel = x_bound <= 255  # the library's rule for its byte-parallel body
     philox_slots = PEAK_VALU_TSLOTS * 1e12 / spv.spv_philox_probe(ctx)  # measured issue slots per block
     spu = slots_per_update(mean_deg, byte_parallel, philox_slots)
     achieved = updates * spu / (sa_ms / 1e3) / 1e12
     shape = spv.spv_sample_last_shape(ctx)
-    dk = P.max_degree if P.max_degree in (4, 6, 8) else 0
+    dk = max_degree if max_degree in (4, 6, 8) else 0
     if not byte_parallel:
         kernel = "sa_kernel<1>"
     elif shape["chunks"] > 1:
@@ -228,7 +229,7 @@ def main():
     if byte_parallel:
         probe = spv.spv_lds_probe(ctx)
         roofline["lds"] = lds_object(updates / (sa_ms / 1e3),
-                                     sa_lds_bytes_per_update(P.max_degree, shape["words_per_lane"]), probe,
+                                     sa_lds_bytes_per_update(max_degree, shape["words_per_lane"]), probe,
                                      "competing bound: LDS traffic of the sweep against the measured LDS peak")
 
     cpu = None
@@ -357,9 +358,10 @@ def bench_pt(args, cfg, label):
     }
     # the Metropolis part of the sweep against the measured LDS peak (the cluster moves and
     # the exchange add latency-bound work on top; records are LDS-resident at N = 1000)
-    nd = 2 if P.x_bound > 511 else 1
+    max_degree, x_bound = spv.spv_problem_check(ctx, P)
+    nd = 2 if x_bound > 511 else 1
     probe = spv.spv_lds_probe(ctx)
-    out["lds"] = lds_object(updates / dt, pt_lds_bytes_per_update(P.max_degree, nd, inst.n <= 4096), probe,
+    out["lds"] = lds_object(updates / dt, pt_lds_bytes_per_update(max_degree, nd, inst.n <= 4096), probe,
                             "Metropolis LDS traffic of the whole step against the measured LDS peak")
     print(json.dumps(out), flush=True)
 

@@ -80,11 +80,16 @@ typedef struct spv_ctx spv_ctx;
  *                   two variables of one class (sweeps go class by class)
  *   n_colours       host: 1..16
  *   scale_log2      host: 0..30, real value = integer / 2^scale_log2
- *   max_degree      host: >= every row length (1..64)
- *   x_bound         host: >= max_i (|h_i| + sum_j |J_ij|), < 2^26
- * The host fields are trusted by the sampling calls; spv_problem_check()
- * verifies all of them.  Kernels clamp every index, so a malformed instance
- * yields wrong numbers but never an out-of-bounds access.
+ * Every sampling call (spv_sample, spv_sqa_sample, spv_pt_sample,
+ * spv_sample_batch, spv_ispvar, spv_multistart, spv_energy, and the server at
+ * submission) ingests the instance first: one device pass validates the CSR
+ * (row_ptr order and ends, columns in range, sorted, no self loops, equal
+ * transposed entries, |J| <= 32767, at most 64 entries per row) and the colour
+ * classes, and derives the two bounds the sampler is sized by, the longest row
+ * and x_bound = max_i (|h_i| + sum_j |J_ij|), which must stay below 2^26.  The
+ * call waits for `stream` to read them back; a failure returns its status
+ * (SPV_EASYM, SPV_ECOLOUR, SPV_ERANGE, SPV_ECAPACITY) before any launch.
+ * The arrays must not change while a call that reads them is in flight.
  */
 typedef struct {
     int32_t n;
@@ -96,8 +101,6 @@ typedef struct {
     const uint8_t *colour;
     int32_t n_colours;
     int32_t scale_log2;
-    int32_t max_degree;
-    int32_t x_bound;
 } spv_problem;
 
 /* Context on HIP device `device`.  *out receives the handle. */
@@ -109,11 +112,13 @@ const char *spv_last_error(const spv_ctx *ctx);
 const char *spv_version(void);
 
 /*
- * Full validation of a problem (synchronous: copies it to the host).
- * Checks symmetry, sortedness, self loops, |J| <= 32767, colouring,
- * max_degree and x_bound.  Returns SPV_OK or the first violation.
+ * Instance ingest on its own (Sec. I: the Ising instance J, h), synchronous
+ * (waits for the device first): the validation every sampling call performs,
+ * returning SPV_OK or the first violation.  On success the derived bounds are
+ * written to max_degree (longest row, >= 1) and x_bound (max_i |h_i| +
+ * sum_j |J_ij|); either pointer may be NULL.
  */
-spv_status spv_problem_check(spv_ctx *ctx, const spv_problem *P);
+spv_status spv_problem_check(spv_ctx *ctx, const spv_problem *P, int32_t *max_degree, int32_t *x_bound);
 
 /*
  * Simulated annealing (Sec. III.A sampler; one Metropolis sweep per beta).

@@ -35,8 +35,7 @@ class SpvError(RuntimeError):
 class spv_problem(C.Structure):
     _fields_ = [("n", C.c_int32), ("nnz", C.c_int32), ("row_ptr", C.c_void_p),
                 ("col", C.c_void_p), ("J", C.c_void_p), ("h", C.c_void_p),
-                ("colour", C.c_void_p), ("n_colours", C.c_int32), ("scale_log2", C.c_int32),
-                ("max_degree", C.c_int32), ("x_bound", C.c_int32)]
+                ("colour", C.c_void_p), ("n_colours", C.c_int32), ("scale_log2", C.c_int32)]
 
 
 class spv_fix_out(C.Structure):
@@ -91,7 +90,7 @@ _SIGS = {
     "spv_ctx_create": ([_i32, C.POINTER(_vp)], C.c_int),
     "spv_ctx_destroy": ([_vp], None),
     "spv_last_error": ([_vp], C.c_char_p),
-    "spv_problem_check": ([_vp, _P], C.c_int),
+    "spv_problem_check": ([_vp, _P, _vp, _vp], C.c_int),
     "spv_sample": ([_vp, _P, _vp, _i32, _i32, _u64, _u32, _vp, _vp, _vp, _vp], C.c_int),
     "spv_sqa_sample": ([_vp, _P, _vp, _vp, _i32, _i32, _i32, _u64, _vp, _vp, _vp], C.c_int),
     "spv_energy": ([_vp, _P, _vp, _i32, _vp, _vp], C.c_int),
@@ -171,25 +170,18 @@ def spv_ctx_create(device=0):
 class Problem:
     """An Ising instance resident on the device (CSR + colouring) with its host metadata."""
 
-    def __init__(self, n, nnz, row_ptr, col, J, h, colour, n_colours, scale_log2, max_degree,
-                 x_bound):
+    def __init__(self, n, nnz, row_ptr, col, J, h, colour, n_colours, scale_log2):
         self.n, self.nnz = int(n), int(nnz)
         self.row_ptr, self.col, self.J, self.h, self.colour = row_ptr, col, J, h, colour
         self.n_colours, self.scale_log2 = int(n_colours), int(scale_log2)
-        self.max_degree, self.x_bound = int(max_degree), int(x_bound)
 
     @classmethod
     def from_instance(cls, inst, device="cuda"):
         rp = np.asarray(inst.row_ptr, np.int32)
-        deg = np.diff(rp)
-        rows = np.repeat(np.arange(inst.n), deg)
-        absJ = np.zeros(inst.n, np.int64)
-        np.add.at(absJ, rows, np.abs(np.asarray(inst.J, np.int64)))
-        xb = int((np.abs(np.asarray(inst.h, np.int64)) + absJ).max()) if inst.n else 0
         t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a, dtype=dt)).to(device)
         return cls(inst.n, int(rp[-1]), t(rp, np.int32), t(inst.col, np.int32),
                    t(inst.J, np.int32), t(inst.h, np.int32), t(inst.colour, np.uint8),
-                   inst.n_colours, inst.scale_log2, max(1, int(deg.max()) if inst.n else 1), xb)
+                   inst.n_colours, inst.scale_log2)
 
     def c_struct(self):
         return spv_problem(self.n, self.nnz, self.row_ptr.data_ptr(),
@@ -197,7 +189,7 @@ class Problem:
                            self.J.data_ptr() if self.nnz else None,
                            self.h.data_ptr() if self.n else None,
                            self.colour.data_ptr() if self.n else None, self.n_colours,
-                           self.scale_log2, self.max_degree, self.x_bound)
+                           self.scale_log2)
 
     def to_host(self):
         """numpy copy (row_ptr, col, J, h, colour) for inspection and tests."""
@@ -208,8 +200,11 @@ class Problem:
 
 
 def spv_problem_check(ctx, P):
+    """Validates P on the device; returns the bounds the library derived (max_degree, x_bound)."""
     ps = P.c_struct()
-    ctx.check(_lib.spv_problem_check(ctx.handle, C.byref(ps)), "spv_problem_check")
+    md, xb = C.c_int32(0), C.c_int32(0)
+    ctx.check(_lib.spv_problem_check(ctx.handle, C.byref(ps), C.byref(md), C.byref(xb)), "spv_problem_check")
+    return md.value, xb.value
 
 
 def spv_sample(ctx, P, betas, reads, seed, sweep_offset=0, init_spins=None, spins=None,
@@ -263,7 +258,7 @@ def spv_colour(ctx, P, seed=0, stream=None):
     colour = torch.empty(max(P.n, 1), dtype=torch.uint8, device=ctx.device)
     nc = C.c_int32(0)
     ps = spv_problem(P.n, P.nnz, P.row_ptr.data_ptr(), P.col.data_ptr() if P.nnz else None, None, None, None, 1,
-                     P.scale_log2, P.max_degree, P.x_bound)
+                     P.scale_log2)
     ctx.check(_lib.spv_colour(ctx.handle, C.byref(ps), C.c_uint64(seed & (2**64 - 1)), _ptr(colour), C.byref(nc),
                               _stream(stream)), "spv_colour")
     return colour[:P.n], nc.value
@@ -317,7 +312,7 @@ class FixResult:
         k = self._keep
         P = self.parent
         return Problem(i["n_free"], i["nnz_free"], k["row_ptr"][:i["n_free"] + 1], k["col"], k["J"],
-                       k["h"], k["colour"], P.n_colours, P.scale_log2, P.max_degree, P.x_bound)
+                       k["h"], k["colour"], P.n_colours, P.scale_log2)
 
     @property
     def orig_index(self):
@@ -498,7 +493,7 @@ class TreeResult:
         raises a remaining variable's degree or its |h| + sum |J|, so the parent's bounds hold."""
         i, k, P = self.info(), self._keep, self.parent_problem
         return Problem(i["n_free"], i["nnz_free"], k["row_ptr"][:i["n_free"] + 1], k["col"], k["J"], k["h"],
-                       k["colour"], P.n_colours, P.scale_log2, P.max_degree, P.x_bound)
+                       k["colour"], P.n_colours, P.scale_log2)
 
 
 def spv_tree_reduce(ctx, P, out=None, stream=None):

@@ -91,13 +91,103 @@ spv_status check_problem_host(Ctx *c, const spv_problem *P) {
         return set_err(c, SPV_EINVAL, "n_colours=%d outside [1, %d]", P->n_colours, kMaxColours);
     if (P->scale_log2 < 0 || P->scale_log2 > 30)
         return set_err(c, SPV_EINVAL, "scale_log2=%d outside [0, 30]", P->scale_log2);
-    if (P->x_bound < 0 || P->x_bound >= (1 << 26))
-        return set_err(c, SPV_ERANGE, "x_bound=%d outside [0, 2^26)", P->x_bound);
     if (P->n > 0) {
-        if (P->max_degree < 1 || P->max_degree > kMaxDegree)
-            return set_err(c, SPV_EINVAL, "max_degree=%d outside [1, %d]", P->max_degree, kMaxDegree);
         if (!P->row_ptr || !P->h || !P->colour || (P->nnz > 0 && (!P->col || !P->J)))
             return set_err(c, SPV_EINVAL, "problem array pointer is NULL");
+    } else if (P->nnz != 0) {
+        return set_err(c, SPV_EASYM, "n=0 with nnz=%d", P->nnz);
+    }
+    return SPV_OK;
+}
+
+spv_status ingest(Ctx *c, const spv_problem *P, int B, int flags, hipStream_t s, Inst *out) {
+    if (B < 0 || (B > 0 && (!P || !out))) return set_err(c, SPV_EINVAL, "ingest: B=%d or NULL problem", B);
+    int n_max = 0;
+    const bool structure = (flags & kIngestStructure) != 0;
+    for (int b = 0; b < B; ++b) {
+        spv_status st = SPV_OK;
+        if (!structure) {
+            st = check_problem_host(c, &P[b]);
+        } else if (P[b].n < 0 || P[b].n > kMaxN) {
+            st = set_err(c, SPV_ECAPACITY, "n=%d outside [0, %d]", P[b].n, kMaxN);
+        } else if (P[b].nnz < 0 || (P[b].n == 0 && P[b].nnz != 0)) {
+            st = set_err(c, SPV_EASYM, "n=%d with nnz=%d", P[b].n, P[b].nnz);
+        } else if (P[b].n > 0 && (!P[b].row_ptr || (P[b].nnz > 0 && !P[b].col))) {
+            st = set_err(c, SPV_EINVAL, "problem array pointer is NULL");
+        }
+        if (st) return B > 1 ? set_err(c, st, "instance %d: %s", b, std::string(c->err).c_str()) : st;
+        static_cast<spv_problem &>(out[b]) = P[b];
+        out[b].max_degree = 1;
+        out[b].x_bound = 0;
+        n_max = std::max(n_max, P[b].n);
+    }
+    if (n_max == 0) return SPV_OK;
+    const size_t b_desc = ((size_t)B * sizeof(IngestDesc) + 255) & ~(size_t)255;
+    const size_t bytes = b_desc + (size_t)B * sizeof(IngestResult);
+    if (c->ingest_host_bytes < bytes) {
+        if (c->ingest_host) (void)hipHostFree(c->ingest_host);
+        c->ingest_host = nullptr;
+        c->ingest_host_bytes = 0;
+        if (hipHostMalloc(&c->ingest_host, bytes, hipHostMallocDefault) != hipSuccess)
+            return set_err(c, SPV_ENOMEM, "hipHostMalloc(%zu)", bytes);
+        c->ingest_host_bytes = bytes;
+    }
+    spv_status st = ensure(c, c->ingest, bytes);
+    if (st) return st;
+    unsigned char *hb = static_cast<unsigned char *>(c->ingest_host);
+    IngestDesc *hd = reinterpret_cast<IngestDesc *>(hb);
+    IngestResult *hr = reinterpret_cast<IngestResult *>(hb + b_desc);
+    for (int b = 0; b < B; ++b) {
+        hd[b].row_ptr = P[b].row_ptr;
+        hd[b].col = P[b].col;
+        hd[b].J = structure ? nullptr : P[b].J;
+        hd[b].h = structure ? nullptr : P[b].h;
+        hd[b].colour = P[b].colour;
+        hd[b].n = P[b].n;
+        hd[b].nnz = P[b].nnz;
+        hd[b].n_colours = P[b].n_colours;
+        hd[b].check_colours = (!structure && (flags & kIngestColours)) ? 1 : 0;
+        std::memset(&hr[b], 0, sizeof hr[b]);
+        hr[b].first_bad = ~0ull;
+    }
+    unsigned char *db = static_cast<unsigned char *>(c->ingest.p);
+    hipError_t e = hipMemcpyAsync(db, hb, bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = launch_ingest(reinterpret_cast<const IngestDesc *>(db), reinterpret_cast<IngestResult *>(db + b_desc), B,
+                          n_max, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(hr, db + b_desc, (size_t)B * sizeof(IngestResult), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_check(c, e, "ingest");
+    for (int b = 0; b < B; ++b) {
+        char where[32] = "";
+        if (B > 1) snprintf(where, sizeof where, "instance %d: ", b);
+        const unsigned long long f = hr[b].first_bad;
+        if (f != ~0ull) {
+            const long long row = (long long)(f >> 8) - 1;
+            switch ((unsigned)(f & 0xff)) {
+            case kChkRowPtrEnds:
+                return set_err(c, SPV_EASYM, "%srow_ptr[0] != 0 or row_ptr[n] != nnz=%d", where, P[b].nnz);
+            case kChkRowPtrOrder:
+                return set_err(c, SPV_EASYM, "%srow_ptr decreases or leaves [0, nnz] at row %lld", where, row);
+            case kChkDegree:
+                return set_err(c, SPV_ECAPACITY, "%srow %lld has more than %d entries", where, row, kMaxDegree);
+            case kChkColourRange:
+                return set_err(c, SPV_ECOLOUR, "%scolour of %lld >= n_colours=%d", where, row, P[b].n_colours);
+            case kChkColRange: return set_err(c, SPV_EASYM, "%srow %lld has a column outside [0, n)", where, row);
+            case kChkSelfLoop: return set_err(c, SPV_EASYM, "%sself loop at %lld", where, row);
+            case kChkUnsorted: return set_err(c, SPV_EASYM, "%srow %lld not strictly increasing", where, row);
+            case kChkJRange: return set_err(c, SPV_ERANGE, "%srow %lld has |J| > 32767", where, row);
+            case kChkColourEdge: return set_err(c, SPV_ECOLOUR, "%srow %lld has an edge inside its colour", where, row);
+            case kChkNoTranspose:
+                return set_err(c, SPV_EASYM, "%srow %lld has an entry with no equal transpose", where, row);
+            default: return set_err(c, SPV_EINTERNAL, "%singest code %llu", where, f);
+            }
+        }
+        if (hr[b].x_max >= (1ull << 26))
+            return set_err(c, SPV_ERANGE, "%smax_i |h_i| + sum_j |J_ij| = %llu, not below 2^26", where, hr[b].x_max);
+        out[b].max_degree = std::max(1, hr[b].max_degree);
+        out[b].x_bound = (int32_t)hr[b].x_max;
     }
     return SPV_OK;
 }
@@ -226,7 +316,7 @@ spv_status plan_pt_split(Ctx *c, int n, int D, int K, int runs, int chains, int 
     }
 }
 
-spv_status pt_lds_footprint(Ctx *c, const spv_problem *P, int K, int runs, int chains, int icm_lo, int icm_hi,
+spv_status pt_lds_footprint(Ctx *c, const Inst *P, int K, int runs, int chains, int icm_lo, int icm_hi,
                             int64_t *lds_total) {
     const int n = P->n, D = P->max_degree > 0 ? P->max_degree : 1;
     const int nd = digits_for(P->x_bound), row_len = table_row_len(P->x_bound);
@@ -311,67 +401,41 @@ void spv_ctx_destroy(spv_ctx *ctx) {
     (void)hipDeviceSynchronize();
     batch_release(&ctx->c);
     if (ctx->c.stage) (void)hipHostFree(ctx->c.stage);
+    if (ctx->c.ingest_host) (void)hipHostFree(ctx->c.ingest_host);
     if (ctx->c.stage_done) (void)hipEventDestroy(ctx->c.stage_done);
     for (DevBuf *b : {&ctx->c.image, &ctx->c.tables, &ctx->c.tables2, &ctx->c.scratch, &ctx->c.scratch2,
-                      &ctx->c.rounds, &ctx->c.pt, &ctx->c.pt_tab, &ctx->c.top, &ctx->c.serve, &ctx->c.merge, &ctx->c.ms, &ctx->c.tree, &ctx->c.sa_stream, &ctx->c.sa_big, &ctx->c.sqa})
+                      &ctx->c.rounds, &ctx->c.pt, &ctx->c.pt_tab, &ctx->c.top, &ctx->c.serve, &ctx->c.merge, &ctx->c.ms, &ctx->c.tree, &ctx->c.sa_stream, &ctx->c.sa_big, &ctx->c.sqa, &ctx->c.ingest})
         if (b->p) (void)hipFree(b->p);
     delete ctx;
 }
 
 const char *spv_last_error(const spv_ctx *ctx) { return ctx ? ctx->c.err.c_str() : "no context"; }
 
-spv_status spv_problem_check(spv_ctx *ctx, const spv_problem *P) {
+spv_status spv_problem_check(spv_ctx *ctx, const spv_problem *P, int32_t *max_degree, int32_t *x_bound) {
     if (!ctx) return SPV_EINVAL;
     Ctx *c = &ctx->c;
     DeviceGuard g(c->device);
-    spv_status st = check_problem_host(c, P);
-    if (st) return st;
-    const int n = P->n, nnz = P->nnz;
-    std::vector<int32_t> rp(n + 1), col(nnz), J(nnz), h(n);
-    std::vector<uint8_t> co(n);
+    // Synchronous: the problem arrays may come from work on any stream.
     hipError_t e = hipDeviceSynchronize();
-    if (e == hipSuccess) e = hipMemcpy(rp.data(), P->row_ptr, 4ull * (n + 1), hipMemcpyDeviceToHost);
-    if (e == hipSuccess && nnz) e = hipMemcpy(col.data(), P->col, 4ull * nnz, hipMemcpyDeviceToHost);
-    if (e == hipSuccess && nnz) e = hipMemcpy(J.data(), P->J, 4ull * nnz, hipMemcpyDeviceToHost);
-    if (e == hipSuccess && n) e = hipMemcpy(h.data(), P->h, 4ull * n, hipMemcpyDeviceToHost);
-    if (e == hipSuccess && n) e = hipMemcpy(co.data(), P->colour, n, hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return hip_check(c, e, "problem copy");
-    if (rp[0] != 0 || rp[n] != nnz) return set_err(c, SPV_EASYM, "row_ptr[0]=%d, row_ptr[n]=%d, nnz=%d", rp[0], rp[n], nnz);
-    long long xmax = 0;
-    for (int i = 0; i < n; ++i) {
-        if (rp[i + 1] < rp[i]) return set_err(c, SPV_EASYM, "row_ptr decreases at row %d", i);
-        if (rp[i + 1] - rp[i] > P->max_degree)
-            return set_err(c, SPV_EINVAL, "row %d has %d entries > max_degree %d", i, rp[i + 1] - rp[i], P->max_degree);
-        if (co[i] >= P->n_colours) return set_err(c, SPV_ECOLOUR, "colour[%d]=%d >= n_colours", i, co[i]);
-        long long x = std::llabs((long long)h[i]);
-        for (int k = rp[i]; k < rp[i + 1]; ++k) {
-            const int j = col[k];
-            if (j < 0 || j >= n) return set_err(c, SPV_EASYM, "col[%d]=%d out of range", k, j);
-            if (j == i) return set_err(c, SPV_EASYM, "self loop at %d", i);
-            if (k > rp[i] && col[k - 1] >= j) return set_err(c, SPV_EASYM, "row %d not strictly increasing", i);
-            if (J[k] > 32767 || J[k] < -32767) return set_err(c, SPV_ERANGE, "|J[%d]|=%d > 32767", k, J[k]);
-            if (co[j] == co[i]) return set_err(c, SPV_ECOLOUR, "edge (%d,%d) inside colour %d", i, j, co[i]);
-            // symmetric partner
-            const int *b = col.data() + rp[j], *en = col.data() + rp[j + 1];
-            const int *f = std::lower_bound(b, en, i);
-            if (f == en || *f != i || J[f - col.data()] != J[k])
-                return set_err(c, SPV_EASYM, "J(%d,%d) has no equal transpose entry", i, j);
-            x += std::llabs((long long)J[k]);
-        }
-        xmax = std::max(xmax, x);
-    }
-    if (xmax > P->x_bound) return set_err(c, SPV_ERANGE, "x_bound=%d < max_i |h_i|+sum|J_ij| = %lld", P->x_bound, xmax);
+    if (e != hipSuccess) return hip_check(c, e, "hipDeviceSynchronize");
+    Inst Q;
+    const spv_status st = ingest(c, P, 1, kIngestColours, nullptr, &Q);
+    if (st) return st;
+    if (max_degree) *max_degree = Q.max_degree;
+    if (x_bound) *x_bound = Q.x_bound;
     return SPV_OK;
 }
 
-spv_status spv_energy(spv_ctx *ctx, const spv_problem *P, const int8_t *spins, int32_t R,
+spv_status spv_energy(spv_ctx *ctx, const spv_problem *P0, const int8_t *spins, int32_t R,
                       int64_t *energies, hipStream_t stream) {
     if (!ctx) return SPV_EINVAL;
     Ctx *c = &ctx->c;
     DeviceGuard g(c->device);
-    spv_status st = check_problem_host(c, P);
-    if (st) return st;
     if (R < 0) return set_err(c, SPV_EINVAL, "R=%d < 0", R);
+    Inst Q;
+    spv_status st = ingest(c, P0, 1, kIngestColours, stream, &Q);
+    if (st) return st;
+    const Inst *P = &Q;
     if (R == 0) return SPV_OK;
     if (!energies || (P->n > 0 && !spins)) return set_err(c, SPV_EINVAL, "NULL spins/energies");
     if (P->n == 0) return hip_check(c, hipMemsetAsync(energies, 0, 8ull * R, stream), "memset");
@@ -383,14 +447,17 @@ spv_status spv_energy(spv_ctx *ctx, const spv_problem *P, const int8_t *spins, i
     return hip_check(c, e, "energy launch");
 }
 
-spv_status spv_sample(spv_ctx *ctx, const spv_problem *P, const double *betas, int32_t sweeps,
-                      int32_t reads, uint64_t seed, uint32_t sweep_offset, const int8_t *init_spins,
-                      int8_t *spins, int64_t *energies, hipStream_t stream) {
+}  // extern "C"
+
+namespace spv {
+
+spv_status sample_inst(spv_ctx *ctx, const Inst *P, const double *betas, int32_t sweeps, int32_t reads,
+                       uint64_t seed, uint32_t sweep_offset, const int8_t *init_spins, int8_t *spins,
+                       int64_t *energies, hipStream_t stream) {
     if (!ctx) return SPV_EINVAL;
     Ctx *c = &ctx->c;
     DeviceGuard g(c->device);
-    spv_status st = check_problem_host(c, P);
-    if (st) return st;
+    spv_status st = SPV_OK;
     if (sweeps < 0 || reads < 0) return set_err(c, SPV_EINVAL, "sweeps=%d reads=%d", sweeps, reads);
     if ((st = check_betas(c, betas, sweeps))) return st;
     if (reads == 0) return SPV_OK;
@@ -491,14 +558,33 @@ spv_status spv_sample(spv_ctx *ctx, const spv_problem *P, const double *betas, i
     return hip_check(c, e, "sa launch");
 }
 
-spv_status spv_sqa_sample(spv_ctx *ctx, const spv_problem *P, const double *betas, const double *gammas,
-                          int32_t sweeps, int32_t trotter, int32_t reads, uint64_t seed, int8_t *spins,
-                          int64_t *energies, hipStream_t stream) {
+}  // namespace spv
+
+extern "C" {
+
+spv_status spv_sample(spv_ctx *ctx, const spv_problem *P, const double *betas, int32_t sweeps,
+                      int32_t reads, uint64_t seed, uint32_t sweep_offset, const int8_t *init_spins,
+                      int8_t *spins, int64_t *energies, hipStream_t stream) {
     if (!ctx) return SPV_EINVAL;
     Ctx *c = &ctx->c;
     DeviceGuard g(c->device);
-    spv_status st = check_problem_host(c, P);
+    Inst Q;
+    const spv_status st = ingest(c, P, 1, kIngestColours, stream, &Q);
     if (st) return st;
+    return sample_inst(ctx, &Q, betas, sweeps, reads, seed, sweep_offset, init_spins, spins, energies, stream);
+}
+
+}  // extern "C"
+
+namespace spv {
+
+spv_status sqa_inst(spv_ctx *ctx, const Inst *P, const double *betas, const double *gammas, int32_t sweeps,
+                    int32_t trotter, int32_t reads, uint64_t seed, int8_t *spins, int64_t *energies,
+                    hipStream_t stream) {
+    if (!ctx) return SPV_EINVAL;
+    Ctx *c = &ctx->c;
+    DeviceGuard g(c->device);
+    spv_status st = SPV_OK;
     if (sweeps < 0 || reads < 0) return set_err(c, SPV_EINVAL, "sweeps=%d reads=%d", sweeps, reads);
     if (trotter < 8 || trotter > 256 || trotter % 8 != 0)
         return set_err(c, SPV_EINVAL, "trotter=%d: a multiple of 8 in [8, 256]", trotter);
@@ -571,6 +657,22 @@ spv_status spv_sqa_sample(spv_ctx *ctx, const spv_problem *P, const double *beta
     return hip_check(c, e, "sqa launch");
 }
 
+}  // namespace spv
+
+extern "C" {
+
+spv_status spv_sqa_sample(spv_ctx *ctx, const spv_problem *P, const double *betas, const double *gammas,
+                          int32_t sweeps, int32_t trotter, int32_t reads, uint64_t seed, int8_t *spins,
+                          int64_t *energies, hipStream_t stream) {
+    if (!ctx) return SPV_EINVAL;
+    Ctx *c = &ctx->c;
+    DeviceGuard g(c->device);
+    Inst Q;
+    const spv_status st = ingest(c, P, 1, kIngestColours, stream, &Q);
+    if (st) return st;
+    return sqa_inst(ctx, &Q, betas, gammas, sweeps, trotter, reads, seed, spins, energies, stream);
+}
+
 spv_status spv_sample_last_shape(const spv_ctx *ctx, int32_t *threads, int32_t *quads_per_wg,
                                  int32_t *words_per_lane, int32_t *chunks, int32_t *global_instance) {
     if (!ctx) return SPV_EINVAL;
@@ -621,15 +723,17 @@ spv_status spv_persist_fix(spv_ctx *ctx, const spv_problem *P, const int8_t *sam
     return hip_check(c, launch_persist_fix(L, stream), "persist launch");
 }
 
-spv_status spv_ispvar(spv_ctx *ctx, const spv_problem *P, const double *betas, int32_t sweeps,
+spv_status spv_ispvar(spv_ctx *ctx, const spv_problem *P0, const double *betas, int32_t sweeps,
                       int32_t reads, uint64_t seed, int32_t rounds, double elite_frac,
                       double threshold, int32_t gauge, uint8_t *fixed_mask, int8_t *fixed_val,
                       int64_t *round_info, int32_t *rounds_run, hipStream_t stream) {
     if (!ctx) return SPV_EINVAL;
     Ctx *c = &ctx->c;
     DeviceGuard g(c->device);
-    spv_status st = check_problem_host(c, P);
+    Inst Q;
+    spv_status st = ingest(c, P0, 1, kIngestColours, stream, &Q);
     if (st) return st;
+    const Inst *P = &Q;
     if (rounds < 0 || reads < 1) return set_err(c, SPV_EINVAL, "rounds=%d reads=%d", rounds, reads);
     if (!rounds_run || (rounds > 0 && !round_info) || (P->n > 0 && (!fixed_mask || !fixed_val)))
         return set_err(c, SPV_EINVAL, "NULL output");
@@ -690,7 +794,7 @@ spv_status spv_ispvar(spv_ctx *ctx, const spv_problem *P, const double *betas, i
         if (e == hipSuccess) e = launch_iota(n, orig_cur, fixed_mask, fixed_val, stream);
     }
     if (e != hipSuccess) return hip_check(c, e, "ispvar setup");
-    spv_problem cur = *P;
+    Inst cur = *P;  // reduced problems keep the parent's bounds
     int b = 0;
     int64_t offset_total = 0;
     std::vector<int64_t> hE(reads);
@@ -701,7 +805,7 @@ spv_status spv_ispvar(spv_ctx *ctx, const spv_problem *P, const double *betas, i
         cur.h = pb[b].h;
         cur.colour = pb[b].co;
         if (cur.n == 0) break;
-        st = spv_sample(ctx, &cur, betas, sweeps, reads, seed + (uint64_t)rd, 0, nullptr, spins, E, stream);
+        st = sample_inst(ctx, &cur, betas, sweeps, reads, seed + (uint64_t)rd, 0, nullptr, spins, E, stream);
         if (st) return st;
         spv_fix_out out;
         out.fixed_mask = fm;
@@ -738,13 +842,16 @@ spv_status spv_ispvar(spv_ctx *ctx, const spv_problem *P, const double *betas, i
     return SPV_OK;
 }
 
-spv_status spv_pt_sample(spv_ctx *ctx, const spv_problem *P, const spv_pt_params *prm,
-                         const spv_pt_out *out, hipStream_t stream) {
+}  // extern "C"
+
+namespace spv {
+
+spv_status pt_inst(spv_ctx *ctx, const Inst *P, const spv_pt_params *prm, const spv_pt_out *out,
+                   hipStream_t stream) {
     if (!ctx) return SPV_EINVAL;
     Ctx *c = &ctx->c;
     DeviceGuard g(c->device);
-    spv_status st = check_problem_host(c, P);
-    if (st) return st;
+    spv_status st = SPV_OK;
     if (!prm || !out) return set_err(c, SPV_EINVAL, "NULL params/out");
     const int K = prm->K, runs = prm->runs, chains = prm->chains;
     if (K < 1 || runs < 1 || chains < 1 || chains > 64 || prm->sweeps < 0)
@@ -816,7 +923,7 @@ spv_status spv_pt_sample(spv_ctx *ctx, const spv_problem *P, const spv_pt_params
     unsigned char *base = static_cast<unsigned char *>(c->pt_tab.p);
     unsigned char *sbase = static_cast<unsigned char *>(c->pt.p);
     hipError_t e = hipSuccess;
-    spv_problem Pp = *P;
+    Inst Pp = *P;
     Pp.max_degree = D;
     e = launch_prep(&Pp, static_cast<int32_t *>(c->image.p), stream);
     if (e != hipSuccess) return hip_check(c, e, "prep launch");
@@ -875,6 +982,21 @@ spv_status spv_pt_sample(spv_ctx *ctx, const spv_problem *P, const spv_pt_params
     L.nqa = nqa;
     L.threads = threads;
     return hip_check(c, launch_pt(L, stream), "pt launch");
+}
+
+}  // namespace spv
+
+extern "C" {
+
+spv_status spv_pt_sample(spv_ctx *ctx, const spv_problem *P, const spv_pt_params *prm,
+                         const spv_pt_out *out, hipStream_t stream) {
+    if (!ctx) return SPV_EINVAL;
+    Ctx *c = &ctx->c;
+    DeviceGuard g(c->device);
+    Inst Q;
+    const spv_status st = ingest(c, P, 1, kIngestColours, stream, &Q);
+    if (st) return st;
+    return pt_inst(ctx, &Q, prm, out, stream);
 }
 
 spv_status spv_top_sample(spv_ctx *ctx, const int8_t *top_spins, const int64_t *top_E,
@@ -955,17 +1077,18 @@ spv_status spv_merge_components(spv_ctx *ctx, const spv_problem *P, const int32_
                      "merge launch");
 }
 
-spv_status spv_colour(spv_ctx *ctx, const spv_problem *P, uint64_t seed, uint8_t *colour, int32_t *n_colours,
+spv_status spv_colour(spv_ctx *ctx, const spv_problem *P0, uint64_t seed, uint8_t *colour, int32_t *n_colours,
                       hipStream_t stream) {
     if (!ctx) return SPV_EINVAL;
     Ctx *c = &ctx->c;
     DeviceGuard g(c->device);
-    if (!P || !n_colours) return set_err(c, SPV_EINVAL, "spv_colour: NULL argument");
-    if (P->n < 0 || P->n > kMaxN) return set_err(c, SPV_ECAPACITY, "spv_colour: n=%d outside [0, %d]", P->n, kMaxN);
-    if (P->nnz < 0 || (P->n > 0 && (!P->row_ptr || !colour || (P->nnz > 0 && !P->col))))
-        return set_err(c, SPV_EINVAL, "spv_colour: NULL array");
-    if (P->n > 0 && (P->max_degree < 1 || P->max_degree > kMaxDegree))
-        return set_err(c, SPV_EINVAL, "spv_colour: max_degree=%d outside [1, %d]", P->max_degree, kMaxDegree);
+    if (!P0 || !n_colours) return set_err(c, SPV_EINVAL, "spv_colour: NULL argument");
+    if (P0->n > 0 && !colour) return set_err(c, SPV_EINVAL, "spv_colour: NULL colour output");
+    // The colouring is the output here, and only the graph structure is read.
+    Inst Q;
+    spv_status st0 = ingest(c, P0, 1, kIngestStructure, stream, &Q);
+    if (st0) return st0;
+    const Inst *P = &Q;
     if (P->n == 0) {
         *n_colours = 1;
         return SPV_OK;

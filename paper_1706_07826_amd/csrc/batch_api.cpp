@@ -154,12 +154,11 @@ spv_status ensure_batch_buf(Ctx *c, size_t bytes) {
 
 using namespace spv;
 
-extern "C" {
+namespace spv {
 
-spv_status spv_sample_batch(spv_ctx *ctx, int32_t B, const spv_problem *problems, const double *betas,
-                            int32_t sweeps, const int32_t *reads, const uint64_t *seeds,
-                            int8_t *const *spins, int64_t *const *energies, const spv_batch_opts *opts,
-                            hipStream_t stream) {
+spv_status sample_batch_inst(spv_ctx *ctx, int32_t B, const Inst *problems, const double *betas, int32_t sweeps,
+                             const int32_t *reads, const uint64_t *seeds, int8_t *const *spins,
+                             int64_t *const *energies, const spv_batch_opts *opts, hipStream_t stream) {
     if (!ctx) return SPV_EINVAL;
     Ctx *c = &ctx->c;
     DeviceGuard g(c->device);
@@ -174,8 +173,7 @@ spv_status spv_sample_batch(spv_ctx *ctx, int32_t B, const spv_problem *problems
     pl.insts.resize(B);
     int x_max = 0;
     for (int b = 0; b < B; ++b) {
-        const spv_problem *P = &problems[b];
-        if ((st = check_problem_host(c, P))) return set_err(c, st, "instance %d: %s", b, c->err.c_str());
+        const Inst *P = &problems[b];
         if (reads[b] < 0) return set_err(c, SPV_EINVAL, "reads[%d]=%d", b, reads[b]);
         if (reads[b] > 0 && (!energies[b] || (P->n > 0 && !spins[b])))
             return set_err(c, SPV_EINVAL, "instance %d: NULL output", b);
@@ -328,6 +326,25 @@ spv_status spv_sample_batch(spv_ctx *ctx, int32_t B, const spv_problem *problems
         if ((st = enqueue(c, pl, ly, n_items, sh, sweeps, 0, stream))) return st;
     }
     return hip_check(c, hipEventRecord(c->batch_done, stream), "event record");
+}
+
+}  // namespace spv
+
+extern "C" {
+
+spv_status spv_sample_batch(spv_ctx *ctx, int32_t B, const spv_problem *problems, const double *betas,
+                            int32_t sweeps, const int32_t *reads, const uint64_t *seeds,
+                            int8_t *const *spins, int64_t *const *energies, const spv_batch_opts *opts,
+                            hipStream_t stream) {
+    if (!ctx) return SPV_EINVAL;
+    Ctx *c = &ctx->c;
+    DeviceGuard g(c->device);
+    if (B < 0 || B > 65535 || (B > 0 && !problems))
+        return set_err(c, SPV_EINVAL, "B=%d (at most 65535) or NULL problems", B);
+    std::vector<Inst> Q((size_t)B);
+    const spv_status st = ingest(c, problems, B, kIngestColours, stream, Q.data());
+    if (st) return st;
+    return sample_batch_inst(ctx, B, Q.data(), betas, sweeps, reads, seeds, spins, energies, opts, stream);
 }
 
 spv_status spv_batch_last_shape(const spv_ctx *ctx, int32_t *threads, int32_t *quads_per_item,

@@ -96,7 +96,7 @@ __global__ __launch_bounds__(1024) void colour_jp_kernel(const int32_t *__restri
 
 size_t colour_lds_bytes(int n) { return (size_t)2 * (size_t)(n > 0 ? n : 1) + 16; }
 
-hipError_t launch_colour(const spv_problem *P, uint64_t seed, uint8_t *colour, uint32_t *prio, int *info,
+hipError_t launch_colour(const Inst *P, uint64_t seed, uint8_t *colour, uint32_t *prio, int *info,
                          hipStream_t s) {
     const int n = P->n;
     hipLaunchKernelGGL(colour_prio_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, (uint32_t)seed,

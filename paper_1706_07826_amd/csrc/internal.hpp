@@ -25,6 +25,20 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
+// An instance together with the two bounds the library derives from its CSR at
+// ingest (the samplers size their tables, digits and layouts by them).  Reduced
+// problems keep their parent's bounds, which stay upper bounds: fixing only
+// removes couplers, and |h'_u| + sum_{j free} |J_uj| <= |h_u| + sum_j |J_uj|.
+struct Inst : spv_problem {
+    int32_t max_degree = 1;  // longest row (1 when no row has an entry)
+    int32_t x_bound = 0;     // max_i |h_i| + sum_j |J_ij|
+};
+
+// Ingest flags: also check the colour classes (every sampling call needs them);
+// or the graph structure only (row_ptr and col; J, h and colour are not read).
+constexpr int kIngestColours = 1;
+constexpr int kIngestStructure = 2;
+
 // Packed instance image written by the prep kernel (device memory):
 //   int32 header[kImgHeader]: n, D, C, class_start[C+1] (padded to 32 entries)
 //   int32 order[n]    position p -> original variable i (colour-major, index order)
@@ -73,6 +87,9 @@ struct Ctx {
     DevBuf sa_stream;  // streamed SA: task counter, tagged spin words between chunks
     DevBuf sa_big;     // SA: byte-parallel instance in global memory (problems too large for LDS)
     DevBuf sqa;        // SQA: inter-slice coupling per sweep
+    DevBuf ingest;     // instance ingest: descriptors and results
+    void *ingest_host = nullptr;  // pinned staging of the ingest descriptors and results
+    size_t ingest_host_bytes = 0;
     TableCache tcache;
     std::vector<uint32_t> host_tables;
     void *batch_host = nullptr;  // pinned staging of descriptors and items
@@ -119,9 +136,27 @@ int table_row_len(int64_t x_bound);
 uint32_t threshold_word(double beta, int64_t unit, int scale_log2, int digit, uint32_t d);
 int swap_digits(double dbeta, int scale_log2);
 spv_status check_problem_host(Ctx *c, const spv_problem *P);
+// Validates B problems on the device (CSR shape and symmetry, coupler range, and
+// with kIngestColours the colour classes) and derives each one's bounds into
+// out[b]; waits for stream s.  The first failure sets the status and message.
+spv_status ingest(Ctx *c, const spv_problem *P, int B, int flags, hipStream_t s, Inst *out);
 spv_status check_betas(Ctx *c, const double *b, int count);
 spv_status upload_tables(Ctx *c, DevBuf &dst, const double *betas, int count, int unit, int scale,
                          int nd, int row_len, hipStream_t s);
+
+// The sampling entry points on an ingested instance (the public calls ingest
+// first; internal drivers pass reduced problems that keep their parent's bounds).
+spv_status sample_inst(spv_ctx *ctx, const Inst *P, const double *betas, int32_t sweeps, int32_t reads,
+                       uint64_t seed, uint32_t sweep_offset, const int8_t *init_spins, int8_t *spins,
+                       int64_t *energies, hipStream_t stream);
+spv_status sqa_inst(spv_ctx *ctx, const Inst *P, const double *betas, const double *gammas, int32_t sweeps,
+                    int32_t trotter, int32_t reads, uint64_t seed, int8_t *spins, int64_t *energies,
+                    hipStream_t stream);
+spv_status pt_inst(spv_ctx *ctx, const Inst *P, const spv_pt_params *prm, const spv_pt_out *out,
+                   hipStream_t stream);
+spv_status sample_batch_inst(spv_ctx *ctx, int32_t B, const Inst *problems, const double *betas, int32_t sweeps,
+                             const int32_t *reads, const uint64_t *seeds, int8_t *const *spins,
+                             int64_t *const *energies, const spv_batch_opts *opts, hipStream_t stream);
 
 // Makes `dev` current for the lifetime of the guard.
 struct DeviceGuard {
@@ -136,8 +171,37 @@ struct DeviceGuard {
 };
 
 // ---- launchers (device translation units) ----
+// Instance ingest (ingest.hip): one descriptor and one result per problem.
+struct IngestDesc {
+    const int32_t *row_ptr;
+    const int32_t *col;
+    const int32_t *J;
+    const int32_t *h;
+    const uint8_t *colour;
+    int32_t n, nnz, n_colours, check_colours;
+};
+struct IngestResult {
+    unsigned long long first_bad;  // (row + 1) << 8 | check of the first failure; ~0 when valid
+    unsigned long long x_max;      // max_i |h_i| + sum_j |J_ij|
+    int32_t max_degree;
+    int32_t pad;
+    long long pad2;
+};
+enum IngestCheck : unsigned {
+    kChkRowPtrEnds = 0,   // row_ptr[0] != 0 or row_ptr[n] != nnz (row 0: the whole problem)
+    kChkRowPtrOrder = 1,  // row_ptr decreases, or leaves [0, nnz]
+    kChkDegree = 2,       // more than kMaxDegree entries in a row
+    kChkColourRange = 3,  // colour[i] >= n_colours
+    kChkColRange = 4,     // col outside [0, n)
+    kChkSelfLoop = 5,
+    kChkUnsorted = 6,     // columns not strictly increasing
+    kChkJRange = 7,       // |J| > 32767
+    kChkColourEdge = 8,   // an edge inside a colour class
+    kChkNoTranspose = 9,  // J(j, i) missing or different from J(i, j)
+};
+hipError_t launch_ingest(const IngestDesc *d, IngestResult *r, int B, int n_max, hipStream_t s);
 // Packs the CSR into the position-ordered ELL image (one workgroup).
-hipError_t launch_prep(const spv_problem *P, int32_t *image, hipStream_t s);
+hipError_t launch_prep(const Inst *P, int32_t *image, hipStream_t s);
 
 struct SaLaunch {
     const int32_t *image;
@@ -283,7 +347,7 @@ spv_status plan_pt_split(Ctx *c, int n, int D, int K, int runs, int chains, int 
                          int icm_hi, bool single_fits, PtSplit *sp);
 unsigned pt_spin_limit();
 // LDS claimed by one spv_pt_sample launch with the shapes it would pick.
-spv_status pt_lds_footprint(Ctx *c, const spv_problem *P, int K, int runs, int chains, int icm_lo, int icm_hi,
+spv_status pt_lds_footprint(Ctx *c, const Inst *P, int K, int runs, int chains, int icm_lo, int icm_hi,
                             int64_t *lds_total);
 size_t ptx_lds_bytes(int n, int D, int m, int chains, int row_len, int nw_icm, bool big);
 int ptx_msg_words(int n);
@@ -313,7 +377,7 @@ hipError_t run_philox_probe(int iters, int num_cus, uint32_t *out, double *block
 
 // Colour classes (colour.hip): prio [n] and info [4] are scratch.
 size_t colour_lds_bytes(int n);
-hipError_t launch_colour(const spv_problem *P, uint64_t seed, uint8_t *colour, uint32_t *prio, int *info,
+hipError_t launch_colour(const Inst *P, uint64_t seed, uint8_t *colour, uint32_t *prio, int *info,
                          hipStream_t s);
 
 // Tree pre-processing (tree.hip).

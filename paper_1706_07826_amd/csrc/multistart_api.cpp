@@ -14,13 +14,15 @@ using namespace spv;
 
 extern "C" {
 
-spv_status spv_multistart(spv_ctx *ctx, const spv_problem *P, const spv_multistart_params *prm,
+spv_status spv_multistart(spv_ctx *ctx, const spv_problem *P0, const spv_multistart_params *prm,
                           const spv_multistart_out *out, hipStream_t stream) {
     if (!ctx) return SPV_EINVAL;
     Ctx *c = &ctx->c;
     DeviceGuard g(c->device);
-    spv_status st = check_problem_host(c, P);
+    Inst Q;
+    spv_status st = ingest(c, P0, 1, kIngestColours, stream, &Q);
     if (st) return st;
+    const Inst *P = &Q;
     if (!prm || !out) return set_err(c, SPV_EINVAL, "spv_multistart: NULL params/out");
     const int S = prm->starts, F = prm->fixing_reads, Rs = prm->solving_reads, n = P->n, nnz = P->nnz;
     if (S < 1 || F < 1 || Rs < 0 || (long long)S * F > (1ll << 30) || (long long)S * Rs > (1ll << 30))
@@ -72,9 +74,9 @@ spv_status spv_multistart(spv_ctx *ctx, const spv_problem *P, const spv_multista
     auto blk = [&](int s, size_t off) { return starts + (size_t)s * pstride + off; };
 
     // 1. Fixing samples of every start: one sampler job, start s owns reads [s*F, (s+1)*F).
-    st = sqa ? spv_sqa_sample(ctx, P, prm->betas, prm->gammas, prm->sweeps, prm->trotter, S * F, prm->seed, fs,
+    st = sqa ? sqa_inst(ctx, P, prm->betas, prm->gammas, prm->sweeps, prm->trotter, S * F, prm->seed, fs,
                               out->fixing_E, stream)
-             : spv_sample(ctx, P, prm->betas, prm->sweeps, S * F, prm->seed, 0, nullptr, fs, out->fixing_E, stream);
+             : sample_inst(ctx, P, prm->betas, prm->sweeps, S * F, prm->seed, 0, nullptr, fs, out->fixing_E, stream);
     if (st) return st;
     // 2. SPVAR per start.
     for (int s = 0; s < S; ++s) {
@@ -107,7 +109,7 @@ spv_status spv_multistart(spv_ctx *ctx, const spv_problem *P, const spv_multista
     const int64_t *E_used = Ered;
     if (Rs > 0) {
         // 3. Solving samples of the starts' modified problems in one batched launch.
-        std::vector<spv_problem> probs;
+        std::vector<Inst> probs;
         std::vector<int32_t> reads;
         std::vector<uint64_t> seeds;
         std::vector<int8_t *> sp;
@@ -116,7 +118,7 @@ spv_status spv_multistart(spv_ctx *ctx, const spv_problem *P, const spv_multista
         for (int s = 0; s < S; ++s) {
             const int nf = (int)hinfo[(size_t)s * 8 + 0];
             if (nf == 0) continue;
-            spv_problem q2 = *P;
+            Inst q2 = *P;  // keeps the parent's bounds
             q2.n = nf;
             q2.nnz = (int32_t)hinfo[(size_t)s * 8 + 1];
             q2.row_ptr = reinterpret_cast<const int32_t *>(blk(s, o_rp));
@@ -133,7 +135,7 @@ spv_status spv_multistart(spv_ctx *ctx, const spv_problem *P, const spv_multista
         }
         if (sqa) {
             for (size_t b = 0; b < probs.size(); ++b)
-                if ((st = spv_sqa_sample(ctx, &probs[b], prm->betas, prm->gammas, prm->sweeps, prm->trotter, Rs,
+                if ((st = sqa_inst(ctx, &probs[b], prm->betas, prm->gammas, prm->sweeps, prm->trotter, Rs,
                                          seeds[b], sp[b], en[b], stream)))
                     return st;
         } else if (!probs.empty()) {
@@ -141,13 +143,13 @@ spv_status spv_multistart(spv_ctx *ctx, const spv_problem *P, const spv_multista
             // colour class x 2 quad words (one wavefront for ~60 free variables), so each
             // item's barriers stay cheap and many items share a CU.
             int cls = 1;
-            for (const spv_problem &q2 : probs) cls = std::max(cls, (q2.n + q2.n_colours - 1) / q2.n_colours);
+            for (const Inst &q2 : probs) cls = std::max(cls, (q2.n + q2.n_colours - 1) / q2.n_colours);
             spv_batch_opts bo;
             bo.threads = std::min(256, (2 * cls + 63) / 64 * 64);
             bo.quads_per_item = 2;
             bo.wgs_per_cu = std::min(16, 1024 / bo.threads);
             bo.flags = 0;
-            if ((st = spv_sample_batch(ctx, (int32_t)probs.size(), probs.data(), prm->betas, prm->sweeps, reads.data(),
+            if ((st = sample_batch_inst(ctx, (int32_t)probs.size(), probs.data(), prm->betas, prm->sweeps, reads.data(),
                                        seeds.data(), sp.data(), en.data(), &bo, stream)))
                 return st;
         }

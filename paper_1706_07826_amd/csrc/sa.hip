@@ -301,7 +301,7 @@ __global__ __launch_bounds__(256) void energy_kernel(const int32_t *__restrict__
 
 }  // namespace
 
-hipError_t launch_prep(const spv_problem *P, int32_t *image, hipStream_t s) {
+hipError_t launch_prep(const Inst *P, int32_t *image, hipStream_t s) {
     hipLaunchKernelGGL(prep_order_kernel, dim3(1), dim3(1024), 0, s, P->colour, P->n,
                        P->max_degree, P->n_colours, image);
     hipError_t e = hipGetLastError();

@@ -30,6 +30,7 @@ enum State { kPending, kRunning, kDone };
 
 struct Record {
     spv_request req;
+    spv::Inst inst;  // the request's problem as ingested at submission
     std::vector<double> betas, gammas;
     int64_t lds = 0, hbm = 0;
     State state = kPending;
@@ -59,6 +60,8 @@ struct spv_server {
     std::condition_variable cv;
     std::atomic<bool> stop{false};
     std::thread worker;
+    hipStream_t ingest_stream = nullptr;  // validation of submitted problems
+    std::mutex ingest_mu;                 // one submission ingests at a time (parent scratch)
 };
 
 using namespace spv;
@@ -66,8 +69,7 @@ using namespace spv;
 namespace {
 
 // LDS and scratch a request claims while in flight (default launch shapes).
-void footprint(spv_server *s, const spv_request &r, int64_t *lds, int64_t *hbm) {
-    const spv_problem &P = r.problem;
+void footprint(spv_server *s, const spv_request &r, const Inst &P, int64_t *lds, int64_t *hbm) {
     const int D = std::max(1, P.max_degree);
     const int nd = digits_for(P.x_bound), row_len = table_row_len(P.x_bound);
     int64_t L = 0, H = (int64_t)image_words(std::max(P.n, 1), D) * 4;
@@ -109,10 +111,10 @@ spv_status launch(Slot &sl, Record &rec) {
     spv_status st;
     if (r.kind == SPV_REQ_SA || r.kind == SPV_REQ_SQA) {
         st = r.kind == SPV_REQ_SA
-                 ? spv_sample(x, &r.problem, rec.betas.data(), r.sweeps, r.reads, r.seed, 0, nullptr, r.spins,
-                              r.energies, sl.stream)
-                 : spv_sqa_sample(x, &r.problem, rec.betas.data(), rec.gammas.data(), r.sweeps, r.trotter, r.reads,
-                                  r.seed, r.spins, r.energies, sl.stream);
+                 ? sample_inst(x, &rec.inst, rec.betas.data(), r.sweeps, r.reads, r.seed, 0, nullptr, r.spins,
+                               r.energies, sl.stream)
+                 : sqa_inst(x, &rec.inst, rec.betas.data(), rec.gammas.data(), r.sweeps, r.trotter, r.reads,
+                            r.seed, r.spins, r.energies, sl.stream);
         if (st == SPV_OK && r.elite_frac > 0)
             st = spv_persist_fix(x, &r.problem, r.spins, r.energies, r.reads, r.elite_frac, r.threshold,
                                  r.gauge, &r.fix_out, sl.stream);
@@ -127,7 +129,7 @@ spv_status launch(Slot &sl, Record &rec) {
         prm.sweep_offset = 0;
         prm.icm_lo = r.icm_lo;
         prm.icm_hi = r.icm_hi;
-        st = spv_pt_sample(x, &r.problem, &prm, &r.pt_out, sl.stream);
+        st = pt_inst(x, &rec.inst, &prm, &r.pt_out, sl.stream);
         // The sample size (filled top-10 entries) is known once the run ends.
         rec.fix_pending = st == SPV_OK && r.elite_frac > 0;
     }
@@ -267,6 +269,10 @@ spv_status spv_server_create(spv_ctx *ctx, const spv_server_cfg *cfg, spv_server
         sl.ctx->c.stream_private = true;
         sl.ctx->c.own_stream = sl.stream;
     }
+    if (hipStreamCreateWithFlags(&s->ingest_stream, hipStreamNonBlocking) != hipSuccess) {
+        spv_server_destroy(s);
+        return set_err(c, SPV_EDEVICE, "server stream creation failed");
+    }
     s->worker = std::thread(worker_loop, s);
     *out = s;
     return SPV_OK;
@@ -293,7 +299,14 @@ spv_status spv_server_submit(spv_server *s, const spv_request *req, uint64_t *ti
     rec.req.betas = nullptr;
     if (r.kind == SPV_REQ_SQA) rec.gammas.assign(r.gammas, r.gammas + std::max(nb, 0));
     rec.req.gammas = nullptr;
-    footprint(s, r, &rec.lds, &rec.hbm);
+    {
+        // Validate the problem and derive its bounds once, on the server's own stream
+        // (the problem arrays must be ready when the request is submitted).
+        std::lock_guard<std::mutex> ilk(s->ingest_mu);
+        const spv_status st = ingest(c, &r.problem, 1, kIngestColours, s->ingest_stream, &rec.inst);
+        if (st) return st;
+    }
+    footprint(s, r, rec.inst, &rec.lds, &rec.hbm);
     rec.res.lds_bytes = rec.lds;
     rec.res.hbm_bytes = rec.hbm;
     if (rec.lds > s->lds_budget || (s->hbm_budget > 0 && rec.hbm > s->hbm_budget))
@@ -358,6 +371,7 @@ void spv_server_destroy(spv_server *s) {
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
         if (sl.ctx) spv_ctx_destroy(sl.ctx);
     }
+    if (s->ingest_stream) (void)hipStreamDestroy(s->ingest_stream);
     delete s;
 }
 

@@ -139,13 +139,13 @@ def test_device_status_for_bad_sample_and_range(spv, ctx):
     with pytest.raises(spv.SpvError) as e:
         r.info()
     assert e.value.code == -1
-    # h'_0 = h_0 + J_01 v_1 leaves int32.  Valid problems cannot get there
-    # (x_bound < 2^26 bounds every |h'|); the host field is understated on
-    # purpose so that the device-side check is exercised.
+    # h'_0 = h_0 + J_01 v_1 leaves int32.  A sampling call would refuse this
+    # instance at ingest (max |h| + sum |J| >= 2^26); persistence does not ingest,
+    # so its own device-side check is exercised.
     big_h = si.from_edges(3, [0, 1], [1, 2], [30000, 30000], [2**31 - 20000, 0, 0], [0, 1, 0], 2)
     P = spv.Problem(3, 4, *[torch.as_tensor(a).cuda() for a in
                             (big_h.row_ptr, big_h.col, big_h.J, big_h.h, big_h.colour)],
-                    2, 0, 2, 100)
+                    2, 0)
     S = np.array([[1, 1, 1], [-1, 1, 1], [1, 1, 1], [1, 1, 1]], np.int8)
     E = np.array([0, 0, 1, 1], np.int64)
     r = spv.spv_persist_fix(ctx, P, torch.as_tensor(S).cuda(), torch.as_tensor(E).cuda(), 0.5, 1.0, 0)

@@ -42,6 +42,22 @@ class _Problem(C.Structure):
                 ("n_colours", C.c_int32), ("scale_log2", C.c_int32)]
 
 
+class _MsParams(C.Structure):
+    _fields_ = [("betas", C.c_void_p), ("sweeps", C.c_int32), ("seed", C.c_uint64),
+                ("starts", C.c_int32), ("corr_reads", C.c_int32), ("fixing_reads", C.c_int32),
+                ("solving_reads", C.c_int32), ("elite_frac", C.c_double), ("threshold", C.c_double),
+                ("gauge", C.c_int32), ("corr_elite_frac", C.c_double), ("corr_threshold", C.c_double),
+                ("corr_after", C.c_int32), ("preprocess", C.c_int32), ("merge", C.c_int32),
+                ("sampler", C.c_int32), ("trotter", C.c_int32), ("gammas", C.c_void_p)]
+
+
+class _MsOut(C.Structure):
+    _fields_ = [("corr_E", C.c_void_p), ("fixing_E", C.c_void_p), ("solving_E", C.c_void_p),
+                ("fixed_mask", C.c_void_p), ("fixed_val", C.c_void_p), ("info", C.c_void_p),
+                ("info_pre", C.c_void_p), ("start_best", C.c_void_p), ("best_spins", C.c_void_p),
+                ("best_E", C.c_void_p)]
+
+
 _lib = None
 
 
@@ -80,10 +96,12 @@ def lib():
         L.orc_components.argtypes = [vp, vp]
         L.orc_components.restype = i32
         L.orc_merge_sorted.argtypes = [vp, vp, i32, vp, i32, vp, vp, vp]
-        L.orc_multistart.argtypes = [vp, vp, i32, u64, i32, i32, i32, f64, f64, i32, i32, i32, i32, vp,
-                                     vp, vp, vp, vp,
-                                     vp, vp, vp]
+        L.orc_multistart.argtypes = [vp, C.POINTER(_MsParams), C.POINTER(_MsOut)]
         L.orc_multistart.restype = C.c_int
+        L.orc_ms_split.argtypes = [i32, i32, vp, vp, vp]
+        L.orc_ms_split.restype = None
+        L.orc_r99.argtypes = [vp, i32, i64, f64, vp]
+        L.orc_r99.restype = f64
         L.orc_tree_peel.argtypes = [vp] * 12
         L.orc_tree_peel.restype = C.c_int
         L.orc_tree_expand.argtypes = [i32, vp, vp, vp, vp, vp, i32, i32, vp, i32, vp]
@@ -399,30 +417,53 @@ def merge_sorted(inst, comp, n_comp, samples):
 
 
 def multistart(inst, betas, seed, starts, fixing_reads, solving_reads, elite_frac, threshold, gauge=0,
-               merge=False, gammas=None, trotter=0):
+               merge=False, gammas=None, trotter=0, corr_reads=0, corr_elite_frac=0.2, corr_threshold=1.0,
+               corr_after=0, preprocess=0):
     """Multi-start SPVAR (Algorithm 2) with SA, or with SQA when `gammas` is given (`trotter`
-    slices).  Returns a dict: fixing_E [S][F], solving_E [S][Rs] (full-problem energies),
-    fixed_mask/fixed_val [S][n], info [S][4] (n_fixed, n_free, offset, components), best_E and
-    best_spins [n]."""
+    slices); an optional correlation step of `corr_reads` reads per start (before the SPVAR step,
+    or after it with corr_after=1) and optional tree pre-processing (bit 0: before the loop,
+    bit 1: after each SPVAR step).  Returns a dict: corr_E [S][Rc], fixing_E [S][F], solving_E
+    [S][Rs] (full-problem energies), fixed_mask/fixed_val [S][n], info [S][8] (correlation-fixed,
+    SPVAR-fixed, tree-removed, n_free, offset, components, correlation pivot, 0), info_pre [8],
+    start_best [S], best_E and best_spins [n]."""
     b = _Bound(inst)
     bt = np.ascontiguousarray(betas, dtype=np.float64)
     gm = None if gammas is None else np.ascontiguousarray(gammas, dtype=np.float64)
-    sampler = 0 if gm is None else 1
-    n, S, F, Rs = inst.n, int(starts), int(fixing_reads), int(solving_reads)
-    out = dict(fixing_E=np.zeros((S, F), np.int64), solving_E=np.zeros((S, max(Rs, 0)), np.int64),
+    n, S, F, Rs, Rc = inst.n, int(starts), int(fixing_reads), int(solving_reads), int(corr_reads)
+    out = dict(corr_E=np.zeros((S, max(Rc, 0)), np.int64), fixing_E=np.zeros((S, F), np.int64),
+               solving_E=np.zeros((S, max(Rs, 0)), np.int64),
                fixed_mask=np.zeros((S, n), np.uint8), fixed_val=np.zeros((S, n), np.int8),
-               info=np.zeros((S, 4), np.int64), best_spins=np.zeros(max(n, 1), np.int8))
+               info=np.zeros((S, 8), np.int64), info_pre=np.zeros(8, np.int64),
+               start_best=np.zeros(S, np.int64), best_spins=np.zeros(max(n, 1), np.int8))
     best = C.c_int64(0)
-    rc = lib().orc_multistart(b.ref, _ptr(bt), bt.size, C.c_uint64(seed & (2**64 - 1)), S, F, Rs,
-                              float(elite_frac), float(threshold), int(gauge), int(bool(merge)),
-                              sampler, int(trotter), _ptr(gm), _ptr(out["fixing_E"]), _ptr(out["solving_E"]), _ptr(out["fixed_mask"]),
-                              _ptr(out["fixed_val"]), _ptr(out["info"]), _ptr(out["best_spins"]),
-                              C.byref(best))
+    prm = _MsParams(_ptr(bt), bt.size, seed & (2**64 - 1), S, Rc, F, Rs, float(elite_frac), float(threshold),
+                    int(gauge), float(corr_elite_frac), float(corr_threshold), int(corr_after), int(preprocess),
+                    int(bool(merge)), 0 if gm is None else 1, int(trotter), _ptr(gm))
+    o = _MsOut(_ptr(out["corr_E"]), _ptr(out["fixing_E"]), _ptr(out["solving_E"]), _ptr(out["fixed_mask"]),
+               _ptr(out["fixed_val"]), _ptr(out["info"]), _ptr(out["info_pre"]), _ptr(out["start_best"]),
+               _ptr(out["best_spins"]), C.cast(C.pointer(best), C.c_void_p))
+    rc = lib().orc_multistart(b.ref, C.byref(prm), C.byref(o))
     if rc != 0:
         raise OracleError(rc, "multistart")
     out["best_E"] = int(best.value)
     out["best_spins"] = out["best_spins"][:n]
     return out
+
+
+def ms_split(total, zero_bias):
+    """Per-start sample split (correlation, fixing, solving) of the parameter appendix."""
+    c, f, s = C.c_int32(), C.c_int32(), C.c_int32()
+    lib().orc_ms_split(int(total), int(bool(zero_bias)), C.byref(c), C.byref(f), C.byref(s))
+    return c.value, f.value, s.value
+
+
+def r99(start_best, e_target, per_start):
+    """R99 of a multi-start run (Sec. III.A): returns (R99, p); R99 is -1 when no start reached
+    e_target."""
+    sb = np.ascontiguousarray(start_best, dtype=np.int64)
+    p = C.c_double()
+    v = lib().orc_r99(_ptr(sb), sb.size, int(e_target), float(per_start), C.byref(p))
+    return v, p.value
 
 
 def colour_jp(inst, seed=0, max_colours=16):

@@ -78,15 +78,30 @@
  *    energies.  The best merged row therefore holds every component's best
  *    partial solution.
  *
- *  Multi-start SPVAR (Algorithm 2): start s fixes variables from reads
- *    [s*F, (s+1)*F) of one sampler job (SA, or SQA as below) on the problem
- *    (seed), records their energies, then samples its modified problem with Rs
- *    reads of a job of the same sampler with seed + 1 + s and records E' +
- *    offset_s (optionally after the
- *    recombination above over the modified problem's components).  The best
- *    state is the first minimum of the recorded energies in the order: start
- *    0's fixing rows, start 0's solving rows, start 1's fixing rows, ...; a
- *    solving row is completed with the start's fixed values.
+ *  Multi-start SPVAR (Algorithm 2; zero-bias handling of Sec. II.C; sample
+ *    split of the parameter appendix).  [Optional] the problem is tree
+ *    pre-processed first (below).  Every start then runs stages on its own
+ *    current problem; each stage samples that problem and records the
+ *    energies in full-problem units (E' plus every offset above it), and the
+ *    reductions follow one another:
+ *      correlation step (corr_reads > 0; before the SPVAR step when
+ *        corr_after == 0, the "pre-fixing" of the appendix, else after the
+ *        SPVAR step and the tree step, the order the algorithm box lists):
+ *        persistence with the gauge on, so the pivot's class of perfectly
+ *        (anti)correlated variables is fixed, with the correlation elite
+ *        fraction and threshold;
+ *      SPVAR step (Algorithm 1): persistence with the caller's gauge mode,
+ *        elite fraction and fixing threshold;
+ *      [optional] tree pre-processing of the modified problem;
+ *      solving step (solving_reads > 0): a sample of the modified problem,
+ *        optionally recombined over its components as above.
+ *    The first stage samples the problem every start shares: one sampler job
+ *    with `seed`, start s owning reads [s*R, (s+1)*R).  The k-th later
+ *    sampling stage (k = 1, 2) of start s uses seed + 1 + (k-1)*starts + s.
+ *    The best state is the first minimum of the recorded energies in the
+ *    order start 0 stage by stage, start 1, ...; it is lifted to the full
+ *    problem through the reductions in reverse (fixed values; tree
+ *    completion).  start_best[s] is the lowest energy start s recorded.
  *
  *  Simulated quantum annealing (Sec. III, "SQA": discrete-time path-integral
  *    Monte Carlo of the transverse-field Ising model, written from the
@@ -158,6 +173,33 @@ typedef struct {
     int32_t n_colours;
     int32_t scale_log2;
 } orc_problem;
+
+/* Parameters and outputs of the multi-start driver (definition above). */
+typedef struct {
+    const double *betas;      /* [sweeps] */
+    int32_t sweeps;
+    uint64_t seed;
+    int32_t starts, corr_reads, fixing_reads, solving_reads;
+    double elite_frac, threshold;
+    int32_t gauge;
+    double corr_elite_frac, corr_threshold;
+    int32_t corr_after;       /* 0: correlation step before the SPVAR step, 1: after it (and the tree) */
+    int32_t preprocess;       /* bit 0: tree before the loop; bit 1: tree after each SPVAR step */
+    int32_t merge;
+    int32_t sampler, trotter; /* 0 SA; 1 SQA over `trotter` slices with `gammas` */
+    const double *gammas;
+} orc_ms_params;
+
+typedef struct {
+    int64_t *corr_E, *fixing_E, *solving_E; /* [S][Rc], [S][F], [S][Rs] */
+    uint8_t *fixed_mask;                    /* [S][n] */
+    int8_t *fixed_val;                      /* [S][n] */
+    int64_t *info;                          /* [S][8] */
+    int64_t *info_pre;                      /* [8] */
+    int64_t *start_best;                    /* [S] */
+    int8_t *best_spins;                     /* [n] */
+    int64_t *best_E;
+} orc_ms_out;
 
 /* ---------------------------------------------------------------------- */
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two    */
@@ -1292,136 +1334,339 @@ int orc_merge_sorted(const orc_problem *P, const int32_t *comp, int32_t n_comp, 
 /* Multi-start SPVAR (Algorithm 2).                                        */
 /* ---------------------------------------------------------------------- */
 
-/* fixing_E [S][F], solving_E [S][Rs], fixed_mask/fixed_val [S][n],
- * info [S][4] = (n_fixed, n_free, offset, components or 0), best_spins [n]. */
-/* One sample, reads [0, R) of a job on Q: SA (sampler 0) or SQA over `trotter`
- * slices with the Gamma schedule `gammas` (sampler 1). */
-static int ms_sample(const orc_problem *Q, int32_t sampler, const double *betas, const double *gammas,
-                     int32_t sweeps, int32_t trotter, uint64_t seed, int32_t R, int8_t *spins, int64_t *E)
+int orc_tree_peel(const orc_problem *P, uint8_t *kind, int8_t *value, int32_t *parent, int32_t *round,
+                  int32_t *row_ptr_o, int32_t *col_o, int32_t *J_o, int32_t *h_o, uint8_t *colour_o,
+                  int32_t *orig_o, int64_t *info);
+int orc_tree_expand(int32_t n, const uint8_t *kind, const int8_t *value, const int32_t *parent,
+                    const int32_t *round, const int32_t *orig, int32_t n_free, int32_t rounds,
+                    const int8_t *reduced, int32_t R, int8_t *full);
+
+/* One reduction of a start's problem: a persistence step (type 1) or a tree
+ * peel (type 2), with the problem it leaves. */
+typedef struct {
+    int32_t type, n_prev, n_next, rounds;
+    int64_t offset;
+    int32_t *orig;            /* [n_next] -> index in the previous problem */
+    int8_t *val;              /* [n_prev] type 1: fixed value or 0; type 2: tree value */
+    uint8_t *kind, *mask;     /* [n_prev] type 2: tree kind; type 1: fixed mask */
+    int32_t *parent, *round;  /* [n_prev] type 2 */
+    int32_t *rp, *cl, *jv, *hv;
+    uint8_t *co;
+    orc_problem out;
+} ms_level;
+
+static int ms_level_alloc(ms_level *L, int32_t n, int32_t nnz)
+{
+    size_t nn = (size_t)(n > 0 ? n : 1), zz = (size_t)(nnz > 0 ? nnz : 1);
+    memset(L, 0, sizeof *L);
+    L->orig = (int32_t *)malloc(4 * nn);
+    L->val = (int8_t *)malloc(nn);
+    L->kind = (uint8_t *)malloc(nn);
+    L->mask = (uint8_t *)malloc(nn);
+    L->parent = (int32_t *)malloc(4 * nn);
+    L->round = (int32_t *)malloc(4 * nn);
+    L->rp = (int32_t *)malloc(4 * (nn + 1));
+    L->cl = (int32_t *)malloc(4 * zz);
+    L->jv = (int32_t *)malloc(4 * zz);
+    L->hv = (int32_t *)malloc(4 * nn);
+    L->co = (uint8_t *)malloc(nn);
+    return (L->orig && L->val && L->kind && L->mask && L->parent && L->round && L->rp && L->cl && L->jv &&
+            L->hv && L->co) ? ORC_OK : ORC_ENOMEM;
+}
+
+static void ms_level_free(ms_level *L)
+{
+    free(L->orig); free(L->val); free(L->kind); free(L->mask); free(L->parent); free(L->round);
+    free(L->rp); free(L->cl); free(L->jv); free(L->hv); free(L->co);
+    memset(L, 0, sizeof *L);
+}
+
+static void ms_level_out(ms_level *L, const orc_problem *Q, int32_t n_next)
+{
+    L->n_prev = Q->n;
+    L->n_next = n_next;
+    L->out = *Q;
+    L->out.n = n_next;
+    L->out.row_ptr = L->rp;
+    L->out.col = L->cl;
+    L->out.J = L->jv;
+    L->out.h = L->hv;
+    L->out.colour = L->co;
+}
+
+/* Persistence (Algorithm 1) on a sample of Q as a level; info as orc_persist_fix. */
+static int ms_persist(const orc_problem *Q, const int8_t *S, const int64_t *E, int32_t R, double elite, double thr,
+                      int32_t gauge, ms_level *L, int64_t *info)
+{
+    int rc = orc_persist_fix(Q, S, E, R, elite, thr, gauge, L->mask, L->val, L->rp, L->cl, L->jv, L->hv, L->co,
+                             L->orig, info);
+    if (rc)
+        return rc;
+    L->type = 1;
+    L->offset = info[2];
+    ms_level_out(L, Q, (int32_t)info[0]);
+    return ORC_OK;
+}
+
+/* Tree peel of Q as a level; info as orc_tree_peel. */
+static int ms_tree(const orc_problem *Q, ms_level *L, int64_t *info)
+{
+    int rc = orc_tree_peel(Q, L->kind, L->val, L->parent, L->round, L->rp, L->cl, L->jv, L->hv, L->co, L->orig,
+                           info);
+    if (rc)
+        return rc;
+    L->type = 2;
+    L->offset = info[2];
+    L->rounds = (int32_t)info[5];
+    ms_level_out(L, Q, (int32_t)info[0]);
+    return ORC_OK;
+}
+
+/* A state of the problem left by levels lv[0..top-1] (of the base problem when
+ * top == 0), lifted through the levels in reverse to the base problem.  a and b
+ * hold the base size. */
+static void ms_lift(const ms_level *const *lv, int32_t top, const int8_t *state, int32_t n_base, int8_t *a,
+                    int8_t *b, int8_t *out)
+{
+    int32_t k, i, u, n_cur = top > 0 ? lv[top - 1]->n_next : n_base;
+    int8_t *cur = a, *prev = b, *t;
+    memcpy(cur, state, (size_t)n_cur);
+    for (k = top - 1; k >= 0; --k) {
+        const ms_level *L = lv[k];
+        if (L->type == 1) {
+            for (i = 0; i < L->n_prev; ++i)
+                prev[i] = L->val[i];
+            for (u = 0; u < L->n_next; ++u)
+                prev[L->orig[u]] = cur[u];
+        } else {
+            orc_tree_expand(L->n_prev, L->kind, L->val, L->parent, L->round, L->orig, L->n_next, L->rounds, cur,
+                            1, prev);
+        }
+        t = cur;
+        cur = prev;
+        prev = t;
+    }
+    memcpy(out, cur, (size_t)n_base);
+}
+
+/* One sampling stage: the reads [r0, r0 + R) of a job on Q with `seed`: SA
+ * (sampler 0) or SQA over `trotter` slices with the Gamma schedule (sampler 1). */
+static int ms_sample(const orc_problem *Q, const orc_ms_params *p, uint64_t seed, int32_t r0, int32_t R,
+                     int8_t *spins, int64_t *E)
 {
     int32_t *bk;
     int rc;
-    if (sampler == 0)
-        return orc_sa_sample(Q, betas, sweeps, seed, 0, 0, R, NULL, NULL, spins, E);
-    if (sampler != 1 || !gammas)
+    if (p->sampler == 0)
+        return orc_sa_sample(Q, p->betas, p->sweeps, seed, 0, r0, r0 + R, NULL, NULL, spins, E);
+    if (p->sampler != 1 || !p->gammas)
         return ORC_EINVAL;
     bk = (int32_t *)malloc(sizeof(int32_t) * (size_t)(R > 0 ? R : 1));
     if (!bk)
         return ORC_ENOMEM;
-    rc = orc_sqa_sample(Q, betas, gammas, sweeps, trotter, seed, 0, R, NULL, NULL, spins, E, bk);
+    rc = orc_sqa_sample(Q, p->betas, p->gammas, p->sweeps, p->trotter, seed, r0, r0 + R, NULL, NULL, spins, E, bk);
     free(bk);
     return rc;
 }
 
-int orc_multistart(const orc_problem *P, const double *betas, int32_t sweeps, uint64_t seed,
-                   int32_t starts, int32_t F, int32_t Rs, double elite_frac, double threshold,
-                   int32_t gauge, int32_t merge, int32_t sampler, int32_t trotter, const double *gammas,
-                   int64_t *fixing_E, int64_t *solving_E,
-                   uint8_t *fixed_mask, int8_t *fixed_val, int64_t *info_o, int8_t *best_spins,
-                   int64_t *best_E)
+/* Sample split of the parameter appendix: zero-bias problems give 40 % of the
+ * total to the correlation step and halve the rest between fixing and solving
+ * (fixing takes the odd read); otherwise fixing and solving halve it. */
+void orc_ms_split(int32_t total, int32_t zero_bias, int32_t *corr, int32_t *fix, int32_t *solve)
 {
-    int32_t n = P->n, nnz = P->row_ptr[n], s, r, i;
-    int32_t *rp = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n + 1));
-    int32_t *cl = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
-    int32_t *jv = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
-    int32_t *hv = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
-    uint8_t *co = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
-    int32_t *orig = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
-    int32_t *comp = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
-    int8_t *fs = (int8_t *)malloc((size_t)starts * F * (size_t)(n > 0 ? n : 1));
-    int8_t *ss = (int8_t *)malloc((size_t)(Rs > 0 ? Rs : 1) * (size_t)(n > 0 ? n : 1));
-    int8_t *mg = (int8_t *)malloc((size_t)(Rs > 0 ? Rs : 1) * (size_t)(n > 0 ? n : 1));
-    int64_t *se = (int64_t *)malloc(sizeof(int64_t) * (size_t)(Rs > 0 ? Rs : 1));
-    int64_t info[8];
-    int64_t best = INT64_MAX;
+    int32_t c = zero_bias ? (int32_t)(((int64_t)2 * total) / 5) : 0, rest = total - c;
+    *corr = c;
+    *fix = (rest + 1) / 2;
+    *solve = rest - *fix;
+}
+
+/* R99 of a multi-start run (Sec. III.A): p = fraction of starts whose lowest
+ * recorded energy reaches e_target; starts for 99 % confidence n99 =
+ * ln(0.01) / ln(1 - p), at least one start (so 1 when p >= 0.99), not rounded;
+ * R99 = n99 * per_start (the total sample of one start).  p == 0: not
+ * measurable, returns -1. */
+double orc_r99(const int64_t *start_best, int32_t starts, int64_t e_target, double per_start, double *p_out)
+{
+    int32_t s, hit = 0;
+    double p, n99;
+    for (s = 0; s < starts; ++s)
+        hit += start_best[s] <= e_target;
+    p = starts > 0 ? (double)hit / (double)starts : 0.0;
+    if (p_out)
+        *p_out = p;
+    if (hit == 0)
+        return -1.0;
+    n99 = hit == starts ? 1.0 : log(0.01) / log(1.0 - p);
+    if (n99 < 1.0)
+        n99 = 1.0;
+    return n99 * per_start;
+}
+
+int orc_multistart(const orc_problem *P, const orc_ms_params *p, orc_ms_out *o)
+{
+    int32_t n = P->n, nnz = P->row_ptr[n], S = p->starts, s, r, i, k;
+    int32_t Rc = p->corr_reads, F = p->fixing_reads, Rs = p->solving_reads;
+    int32_t Rmax = Rc > F ? Rc : F;
+    ms_level pre, lv_own[4];
+    const ms_level *lv[5];
+    orc_problem base = *P;
+    int64_t off_pre = 0, best = INT64_MAX, info[8];
+    int8_t *smp = NULL, *mg = NULL, *la = NULL, *lb = NULL, *lifted = NULL;
+    int64_t *E = NULL;
+    int32_t *map = NULL, *map2 = NULL, *comp = NULL;
+    int32_t n_pre_lv = 0, n_base, kinds[4], nst;
     int rc = ORC_OK;
-    orc_problem red;
-    if (!rp || !cl || !jv || !hv || !co || !orig || !comp || !fs || !ss || !mg || !se) {
+    memset(&pre, 0, sizeof pre);
+    memset(lv_own, 0, sizeof lv_own);
+    if (S < 1 || F < 1 || Rc < 0 || Rs < 0 || (Rc > 0 && !(p->corr_elite_frac > 0.0)) || p->corr_after < 0 ||
+        p->corr_after > 1 || p->preprocess < 0 || p->preprocess > 3)
+        return ORC_EINVAL;
+    if (Rs > Rmax)
+        Rmax = Rs;
+    if (n < 1)
+        return ORC_EINVAL;
+    smp = (int8_t *)malloc((size_t)Rmax * n);
+    mg = (int8_t *)malloc((size_t)Rmax * n);
+    E = (int64_t *)malloc(sizeof(int64_t) * (size_t)Rmax);
+    la = (int8_t *)malloc((size_t)n);
+    lb = (int8_t *)malloc((size_t)n);
+    lifted = (int8_t *)malloc((size_t)n);
+    map = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    map2 = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    comp = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    if (!smp || !mg || !E || !la || !lb || !lifted || !map || !map2 || !comp) {
         rc = ORC_ENOMEM;
         goto done;
     }
-    if (starts < 1 || F < 1 || Rs < 0) {
-        rc = ORC_EINVAL;
-        goto done;
-    }
-    /* fixing samples of every start: one sampler job, start s owns reads [s*F, (s+1)*F) */
-    rc = ms_sample(P, sampler, betas, gammas, sweeps, trotter, seed, starts * F, fs, fixing_E);
-    if (rc)
-        goto done;
-    for (s = 0; s < starts; ++s) {
-        const int8_t *fsamp = fs + (size_t)s * F * n;
-        const int64_t *fe = fixing_E + (size_t)s * F;
-        uint8_t *fm = fixed_mask + (size_t)s * n;
-        int8_t *fv = fixed_val + (size_t)s * n;
-        int64_t off;
-        int32_t nf, nc = 0;
-        for (r = 0; r < F; ++r)
-            if (fe[r] < best) {
-                best = fe[r];
-                memcpy(best_spins, fsamp + (size_t)r * n, (size_t)n);
-            }
-        rc = orc_persist_fix(P, fsamp, fe, F, elite_frac, threshold, gauge, fm, fv, rp, cl, jv, hv, co,
-                             orig, info);
-        if (rc)
+    /* [Optional] pre-processing of the problem before the loop */
+    if (p->preprocess & 1) {
+        if ((rc = ms_level_alloc(&pre, n, nnz)) || (rc = ms_tree(P, &pre, info)))
             goto done;
-        nf = (int32_t)info[0];
-        off = info[2];
-        red = *P;
-        red.n = nf;
-        red.row_ptr = rp;
-        red.col = cl;
-        red.J = jv;
-        red.h = hv;
-        red.colour = co;
-        if (Rs > 0) {
-            if (nf > 0) {
-                rc = ms_sample(&red, sampler, betas, gammas, sweeps, trotter, seed + 1 + (uint64_t)s, Rs, ss, se);
-                if (rc)
-                    goto done;
-                if (merge) {
-                    nc = orc_components(&red, comp);
-                    if (nc < 0) {
-                        rc = nc;
-                        goto done;
-                    }
-                    rc = orc_merge_sorted(&red, comp, nc, ss, Rs, mg, se, NULL);
+        for (k = 0; k < 8; ++k)
+            o->info_pre[k] = info[k];
+        base = pre.out;
+        off_pre = pre.offset;
+        lv[0] = &pre;
+        n_pre_lv = 1;
+    } else {
+        for (k = 0; k < 8; ++k)
+            o->info_pre[k] = 0;
+        o->info_pre[0] = n;
+    }
+    n_base = n;
+    for (k = 0; k < 4; ++k)
+        if ((rc = ms_level_alloc(&lv_own[k], n, nnz)))
+            goto done;
+    /* the stages of every start, in order: 0 correlation, 1 SPVAR fixing, 2 tree, 3 solving */
+    nst = 0;
+    if (Rc > 0 && p->corr_after == 0)
+        kinds[nst++] = 0;
+    kinds[nst++] = 1;
+    if (p->preprocess & 2)
+        kinds[nst++] = 2;
+    if (Rc > 0 && p->corr_after == 1)
+        kinds[nst++] = 0;
+    for (s = 0; s < S; ++s) {
+        const orc_problem *Q = &base;
+        int64_t off = off_pre, sbest = INT64_MAX;
+        int32_t depth = n_pre_lv, nlev = 0, k_sample = 0, j;
+        int64_t *oinfo = o->info + (size_t)s * 8;
+        uint8_t *fm = o->fixed_mask + (size_t)s * n;
+        int8_t *fv = o->fixed_val + (size_t)s * n;
+        for (i = 0; i < 8; ++i)
+            oinfo[i] = 0;
+        oinfo[6] = -1;
+        for (i = 0; i < n; ++i) {
+            fm[i] = 0;
+            fv[i] = 0;
+        }
+        for (i = 0; i < base.n; ++i)
+            map[i] = n_pre_lv ? pre.orig[i] : i;
+        for (j = 0; j <= nst; ++j) {
+            const int32_t kind = j < nst ? kinds[j] : 3;
+            int32_t R = kind == 0 ? Rc : kind == 1 ? F : kind == 3 ? Rs : 0;
+            int64_t *rec = kind == 0 ? o->corr_E + (size_t)s * Rc
+                                     : kind == 1 ? o->fixing_E + (size_t)s * F : o->solving_E + (size_t)s * Rs;
+            ms_level *L;
+            if (kind == 3 && Rs == 0)
+                break;
+            if (kind != 2) {
+                /* a sample of the current problem, recorded in full-problem units */
+                if (Q->n > 0) {
+                    if (k_sample == 0)
+                        rc = ms_sample(Q, p, p->seed, s * R, R, smp, E);
+                    else
+                        rc = ms_sample(Q, p, p->seed + 1 + (uint64_t)(k_sample - 1) * S + (uint64_t)s, 0, R, smp,
+                                       E);
                     if (rc)
                         goto done;
-                    memcpy(ss, mg, (size_t)Rs * nf);
+                    if (kind == 3 && p->merge) {
+                        int32_t nc = orc_components(Q, comp);
+                        if (nc < 0) {
+                            rc = nc;
+                            goto done;
+                        }
+                        if ((rc = orc_merge_sorted(Q, comp, nc, smp, R, mg, E, NULL)))
+                            goto done;
+                        memcpy(smp, mg, (size_t)R * Q->n);
+                        oinfo[5] = nc;
+                    }
+                } else {
+                    for (r = 0; r < R; ++r)
+                        E[r] = 0;
                 }
+                ++k_sample;
+                for (r = 0; r < R; ++r) {
+                    rec[r] = E[r] + off;
+                    if (rec[r] < sbest)
+                        sbest = rec[r];
+                    if (rec[r] < best) {
+                        best = rec[r];
+                        ms_lift(lv, depth, smp + (size_t)r * Q->n, n_base, la, lb, lifted);
+                        memcpy(o->best_spins, lifted, (size_t)n);
+                    }
+                }
+                if (kind == 3)
+                    break;
+            }
+            if (Q->n == 0)
+                continue; /* nothing left to fix or peel */
+            L = &lv_own[nlev];
+            if (kind == 2) {
+                if ((rc = ms_tree(Q, L, info)))
+                    goto done;
+                oinfo[2] += info[3] + info[4];
             } else {
-                for (r = 0; r < Rs; ++r)
-                    se[r] = 0;
+                const int corr = kind == 0;
+                if ((rc = ms_persist(Q, smp, E, R, corr ? p->corr_elite_frac : p->elite_frac,
+                                     corr ? p->corr_threshold : p->threshold, corr ? 1 : p->gauge, L, info)))
+                    goto done;
+                for (i = 0; i < L->n_prev; ++i)
+                    if (L->mask[i]) {
+                        fm[map[i]] = 1;
+                        fv[map[i]] = L->val[i];
+                    }
+                oinfo[corr ? 0 : 1] += info[3];
+                if (corr && info[4] >= 0)
+                    oinfo[6] = map[info[4]];
             }
-            for (r = 0; r < Rs; ++r) {
-                solving_E[(size_t)s * Rs + r] = se[r] + off;
-                if (se[r] + off < best) {
-                    best = se[r] + off;
-                    for (i = 0; i < n; ++i)
-                        best_spins[i] = fm[i] ? fv[i] : 0;
-                    for (i = 0; i < nf; ++i)
-                        best_spins[orig[i]] = ss[(size_t)r * nf + i];
-                }
-            }
+            for (i = 0; i < L->n_next; ++i)
+                map2[i] = map[L->orig[i]];
+            memcpy(map, map2, sizeof(int32_t) * (size_t)L->n_next);
+            off += L->offset;
+            lv[depth++] = L;
+            ++nlev;
+            Q = &L->out;
         }
-        info_o[s * 4 + 0] = info[3];
-        info_o[s * 4 + 1] = nf;
-        info_o[s * 4 + 2] = off;
-        info_o[s * 4 + 3] = nc;
+        oinfo[3] = Q->n;
+        oinfo[4] = off;
+        o->start_best[s] = sbest;
     }
-    *best_E = best;
+    *o->best_E = best;
 done:
-    free(rp);
-    free(cl);
-    free(jv);
-    free(hv);
-    free(co);
-    free(orig);
-    free(comp);
-    free(fs);
-    free(ss);
-    free(mg);
-    free(se);
+    ms_level_free(&pre);
+    for (k = 0; k < 4; ++k)
+        ms_level_free(&lv_own[k]);
+    free(smp); free(mg); free(E); free(la); free(lb); free(lifted); free(map); free(map2); free(comp);
     return rc;
 }
 

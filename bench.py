@@ -556,7 +556,7 @@ def bench_multistart(args, sqa=False):
         out = step()
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
-    n_free = out["info"][:, 1]
+    n_free = out["info"][:, 3]
     updates = trotter * cfg["sweeps"] * (S * F * inst.n + Rs * int(n_free.sum()))
     res = {
         "metric": METRIC_NAME, "value": round(updates / dt, 1), "unit": "spin-updates/s",
@@ -568,7 +568,7 @@ def bench_multistart(args, sqa=False):
                                f"{f', SQA {trotter} slices' if sqa else ''}, elite {cfg['elite']}, "
                                f"threshold {cfg['theta']}, recombination over components"},
         "starts_per_s": round(S / dt, 2), "mean_free": round(float(n_free.mean()), 1),
-        "mean_components": round(float(out["info"][:, 3].mean()), 1), "best_E": out["best_E"],
+        "mean_components": round(float(out["info"][:, 5].mean()), 1), "best_E": out["best_E"],
     }
     print(json.dumps(res), flush=True)
 

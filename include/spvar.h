@@ -379,26 +379,46 @@ spv_status spv_merge_components(spv_ctx *ctx, const spv_problem *P, const int32_
                                 int64_t *part_E, hipStream_t stream);
 
 /*
- * Multi-start SPVAR (Algorithm 2): `starts` independent starts.  Start s
- * applies SPVAR (Algorithm 1, spv_persist_fix) to reads [s*F, (s+1)*F) of one
- * sampler job on P with `seed` (F = fixing_reads), then samples its modified
- * problem with Rs = solving_reads reads of a job of the same sampler with
- * seed + 1 + s (SA: all starts in one batched launch; SQA, spv_sqa_sample: one
- * launch per start), optionally recombining that sample over the
- * modified problem's components (Sec. II.C).  Every recorded energy is a
- * full-problem energy (E' + the start's offset).  The call waits for
- * `stream` (it reads back the per-start sizes).
+ * Multi-start SPVAR (Algorithm 2), with the zero-bias handling of Sec. II.C and
+ * the sample split of the parameter appendix.  [Optional] (preprocess bit 0)
+ * the problem is tree pre-processed first (spv_tree_reduce).  Each of the
+ * `starts` independent starts then runs these stages on its own current
+ * problem; a sampling stage draws a sample of that problem and records its
+ * energies in full-problem units (E' plus the offsets of every reduction so
+ * far), and each reduction modifies the start's problem:
+ *   correlation step (corr_reads > 0; before the SPVAR step when corr_after is
+ *     0 -- the appendix's "pre-fixing" -- or after the SPVAR and tree steps
+ *     when it is 1, the order the algorithm box lists): a sample of
+ *     corr_reads, then spv_persist_fix with the gauge on, corr_elite_frac and
+ *     corr_threshold, which fixes the pivot's class of perfectly
+ *     (anti)correlated variables (threshold 1.0);
+ *   SPVAR step (Algorithm 1): a sample of fixing_reads, then spv_persist_fix
+ *     with gauge, elite_frac and threshold;
+ *   [optional] (preprocess bit 1) tree pre-processing of the modified problem;
+ *   solving step (solving_reads > 0): a sample of the modified problem,
+ *     optionally recombined over its components (Sec. II.C).
+ * The first sampling stage samples the problem all starts share: one job with
+ * `seed`, start s owning reads [s*R, (s+1)*R).  The k-th later sampling stage
+ * (k = 1, 2) of start s uses seed + 1 + (k-1)*starts + s (SA: one batched
+ * launch over the starts; SQA, spv_sqa_sample: a launch per start).  A start
+ * whose problem became empty records its offset.  The call waits for `stream`
+ * (it reads back the per-start sizes after each reduction).
  */
 typedef struct {
-    int32_t starts;          /* num_starts >= 1 */
-    int32_t fixing_reads;    /* fixing_sample_size F >= 1 */
-    int32_t solving_reads;   /* solving_sample_size Rs >= 0 */
-    const double *betas;     /* host [sweeps]: SA schedule of both samples */
+    int32_t starts;          /* num_starts, 1..4096 */
+    int32_t corr_reads;      /* correlation step sample per start (0: no correlation step) */
+    int32_t fixing_reads;    /* fixing_sample_size >= 1 */
+    int32_t solving_reads;   /* solving_sample_size >= 0 */
+    const double *betas;     /* host [sweeps]: the schedule of every sample */
     int32_t sweeps;
     uint64_t seed;
-    double elite_frac;       /* as spv_persist_fix */
+    double elite_frac;       /* SPVAR step, as spv_persist_fix */
     double threshold;
     int32_t gauge;
+    double corr_elite_frac;  /* correlation step: correlation_elite_threshold, (0, 1] */
+    double corr_threshold;   /* correlation_threshold, (0, 1] (1.0 in the paper) */
+    int32_t corr_after;      /* 0: correlation step before the SPVAR step; 1: after it */
+    int32_t preprocess;      /* bit 0: tree step before the loop; bit 1: after each SPVAR step */
     int32_t merge;           /* 1: recombine each solving sample over its components */
     int32_t sampler;         /* 0: SA; 1: SQA with `trotter` slices and the Gamma schedule `gammas` */
     int32_t trotter;         /* SQA: as spv_sqa_sample */
@@ -406,20 +426,39 @@ typedef struct {
 } spv_multistart_params;
 
 typedef struct {
-    int64_t *fixing_E;       /* device [starts][F] */
-    int64_t *solving_E;      /* device [starts][Rs]: full-problem energies (sorted when merged) */
-    uint8_t *fixed_mask;     /* device [starts][n] or NULL */
-    int8_t *fixed_val;       /* device [starts][n] or NULL */
-    int64_t *info;           /* host [starts][4] or NULL: n_fixed, n_free, offset, components
-                                (0 unless merged) */
+    int64_t *corr_E;         /* device [starts][corr_reads] (NULL when corr_reads == 0) */
+    int64_t *fixing_E;       /* device [starts][fixing_reads] */
+    int64_t *solving_E;      /* device [starts][solving_reads]: sorted when recombined */
+    uint8_t *fixed_mask;     /* device [starts][n] or NULL: fixed by the correlation and SPVAR steps */
+    int8_t *fixed_val;       /* device [starts][n] or NULL: their values (0 where not fixed) */
+    int64_t *info;           /* host [starts][8] or NULL: fixed by the correlation step, fixed by
+                                the SPVAR step, removed by the tree step, n_free of the final
+                                problem, its offset, its components (0 unless recombined), the
+                                correlation pivot (original index, -1 when none), 0 */
+    int64_t *info_pre;       /* host [8] or NULL: spv_tree_reduce info of the pre-processing
+                                (n, nnz, 0, ... when not applied) */
+    int64_t *start_best;     /* host [starts] or NULL: each start's lowest recorded energy */
     int8_t *best_spins;      /* device [n] or NULL: the first lowest recorded state in the order
-                                start 0 fixing rows, start 0 solving rows, start 1 ..., a
-                                solving row completed with its start's fixed values */
+                                start 0 stage by stage, start 1, ..., lifted to the full problem
+                                through the start's reductions in reverse */
     int64_t *best_E;         /* host or NULL */
 } spv_multistart_out;
 
 spv_status spv_multistart(spv_ctx *ctx, const spv_problem *P, const spv_multistart_params *params,
                           const spv_multistart_out *out, hipStream_t stream);
+
+/* Per-start sample split of the parameter appendix for a total of `total`
+ * reads: zero-bias problems give floor(2 total / 5) to the correlation step and
+ * halve the rest between fixing (the odd read) and solving; otherwise fixing
+ * and solving halve the total.  Any output pointer may be NULL.  Host only. */
+void spv_multistart_split(int32_t total, int32_t zero_bias, int32_t *corr, int32_t *fix, int32_t *solve);
+
+/* R99 of a multi-start run (Sec. III.A): p = the fraction of starts whose lowest
+ * recorded energy (start_best, host [starts]) is <= e_target; the starts needed
+ * for 99 % confidence n99 = ln(0.01) / ln(1 - p), at least 1 (1 when p >= 0.99),
+ * not rounded; returns n99 * per_start (the total sample one start draws), or
+ * -1 when no start reached e_target.  *p receives p (p may be NULL).  Host only. */
+double spv_r99(const int64_t *start_best, int32_t starts, int64_t e_target, double per_start, double *p);
 
 /*
  * Tree / degree-1 pre-processing (Sec. II.C): variables with at most one

@@ -1551,6 +1551,7 @@ int orc_multistart(const orc_problem *P, const orc_ms_params *p, orc_ms_out *o)
         for (k = 0; k < 8; ++k)
             o->info_pre[k] = 0;
         o->info_pre[0] = n;
+        o->info_pre[1] = nnz;
     }
     n_base = n;
     for (k = 0; k < 4; ++k)
@@ -1678,7 +1679,7 @@ done:
  * for an inferred variable the factor f with s = f * s_parent; parent [n];
  * round [n] (-1 for remaining variables); reduced CSR (row_ptr_o [n+1], col_o,
  * J_o, h_o, colour_o), orig_o [n'] (reduced -> original); info [8] = n_free,
- * nnz_free, offset, n_fixed, n_inferred, rounds, 0, 0. */
+ * nnz_free, offset, n_fixed, n_inferred, rounds, 0, n_removed. */
 int orc_tree_peel(const orc_problem *P, uint8_t *kind, int8_t *value, int32_t *parent, int32_t *round,
                   int32_t *row_ptr_o, int32_t *col_o, int32_t *J_o, int32_t *h_o, uint8_t *colour_o,
                   int32_t *orig_o, int64_t *info)
@@ -1789,7 +1790,7 @@ int orc_tree_peel(const orc_problem *P, uint8_t *kind, int8_t *value, int32_t *p
     info[4] = n_inf;
     info[5] = rd;
     info[6] = 0;
-    info[7] = 0;
+    info[7] = n - nf; /* removed variables */
     free(h); free(deg); free(nb); free(nbk); free(peel); free(newidx);
     return ORC_OK;
 }

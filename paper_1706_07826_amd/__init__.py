@@ -60,15 +60,18 @@ SPV_BATCH_TUNE = 2
 
 
 class spv_multistart_params(C.Structure):
-    _fields_ = [("starts", C.c_int32), ("fixing_reads", C.c_int32), ("solving_reads", C.c_int32),
-                ("betas", C.c_void_p), ("sweeps", C.c_int32), ("seed", C.c_uint64), ("elite_frac", C.c_double),
-                ("threshold", C.c_double), ("gauge", C.c_int32), ("merge", C.c_int32), ("sampler", C.c_int32),
-                ("trotter", C.c_int32), ("gammas", C.c_void_p)]
+    _fields_ = [("starts", C.c_int32), ("corr_reads", C.c_int32), ("fixing_reads", C.c_int32),
+                ("solving_reads", C.c_int32), ("betas", C.c_void_p), ("sweeps", C.c_int32), ("seed", C.c_uint64),
+                ("elite_frac", C.c_double), ("threshold", C.c_double), ("gauge", C.c_int32),
+                ("corr_elite_frac", C.c_double), ("corr_threshold", C.c_double), ("corr_after", C.c_int32),
+                ("preprocess", C.c_int32), ("merge", C.c_int32), ("sampler", C.c_int32), ("trotter", C.c_int32),
+                ("gammas", C.c_void_p)]
 
 
 class spv_multistart_out(C.Structure):
-    _fields_ = [("fixing_E", C.c_void_p), ("solving_E", C.c_void_p), ("fixed_mask", C.c_void_p),
-                ("fixed_val", C.c_void_p), ("info", C.c_void_p), ("best_spins", C.c_void_p),
+    _fields_ = [("corr_E", C.c_void_p), ("fixing_E", C.c_void_p), ("solving_E", C.c_void_p),
+                ("fixed_mask", C.c_void_p), ("fixed_val", C.c_void_p), ("info", C.c_void_p),
+                ("info_pre", C.c_void_p), ("start_best", C.c_void_p), ("best_spins", C.c_void_p),
                 ("best_E", C.c_void_p)]
 
 
@@ -109,6 +112,8 @@ _SIGS = {
     "spv_components": ([_vp, _P, _vp, _vp, _vp], C.c_int),
     "spv_merge_components": ([_vp, _P, _vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp], C.c_int),
     "spv_multistart": ([_vp, _P, C.POINTER(spv_multistart_params), C.POINTER(spv_multistart_out), _vp], C.c_int),
+    "spv_multistart_split": ([_i32, _i32, _vp, _vp, _vp], None),
+    "spv_r99": ([_vp, _i32, C.c_int64, _f64, _vp], _f64),
     "spv_tree_reduce": ([_vp, _P, C.POINTER(spv_tree_out), _vp], C.c_int),
     "spv_tree_complete": ([_vp, _i32, C.POINTER(spv_tree_out), _i32, _i32, _vp, _i32, _vp, _vp], C.c_int),
 }
@@ -429,34 +434,58 @@ def spv_merge_components(ctx, P, comp, n_comp, samples, part=False, stream=None)
 
 
 def spv_multistart(ctx, P, betas, seed, starts, fixing_reads, solving_reads, elite_frac, threshold, gauge=0,
-                   merge=False, gammas=None, trotter=0, stream=None):
+                   merge=False, gammas=None, trotter=0, corr_reads=0, corr_elite_frac=0.2, corr_threshold=1.0,
+                   corr_after=0, preprocess=0, stream=None):
     """Multi-start SPVAR (Algorithm 2) with SA, or with SQA when `gammas` is given (`trotter`
-    slices).  Returns a dict: fixing_E [S][F], solving_E [S][Rs] (full-problem energies),
-    fixed_mask/fixed_val [S][n] (device), info [S][4] (host: n_fixed, n_free, offset,
-    components), best_E (host int) and best_spins [n] (device)."""
+    slices); an optional correlation step of `corr_reads` reads per start (before the SPVAR step,
+    or after it with corr_after=1) and optional tree pre-processing (bit 0: before the loop, bit 1:
+    after each SPVAR step).  Returns a dict: corr_E [S][Rc], fixing_E [S][F], solving_E [S][Rs]
+    (device, full-problem energies), fixed_mask/fixed_val [S][n] (device), info [S][8], info_pre [8],
+    start_best [S] (host), best_E (host int) and best_spins [n] (device)."""
     b = np.ascontiguousarray(betas, dtype=np.float64)
     gm = None if gammas is None else np.ascontiguousarray(gammas, dtype=np.float64)
-    dev, n, S, F, Rs = ctx.device, P.n, int(starts), int(fixing_reads), int(solving_reads)
-    res = dict(fixing_E=torch.empty((S, F), dtype=torch.int64, device=dev),
+    dev, n, S = ctx.device, P.n, int(starts)
+    F, Rs, Rc = int(fixing_reads), int(solving_reads), int(corr_reads)
+    res = dict(corr_E=torch.empty((S, max(Rc, 1)), dtype=torch.int64, device=dev),
+               fixing_E=torch.empty((S, F), dtype=torch.int64, device=dev),
                solving_E=torch.empty((S, max(Rs, 1)), dtype=torch.int64, device=dev),
                fixed_mask=torch.empty((S, max(n, 1)), dtype=torch.uint8, device=dev),
                fixed_val=torch.empty((S, max(n, 1)), dtype=torch.int8, device=dev),
-               info=np.zeros((S, 4), np.int64), best_spins=torch.empty(max(n, 1), dtype=torch.int8, device=dev))
+               info=np.zeros((S, 8), np.int64), info_pre=np.zeros(8, np.int64), start_best=np.zeros(S, np.int64),
+               best_spins=torch.empty(max(n, 1), dtype=torch.int8, device=dev))
     best = C.c_int64(0)
-    prm = spv_multistart_params(S, F, Rs, b.ctypes.data, b.size, C.c_uint64(seed & (2**64 - 1)),
-                                float(elite_frac), float(threshold), int(gauge), int(bool(merge)),
+    prm = spv_multistart_params(S, Rc, F, Rs, b.ctypes.data, b.size, C.c_uint64(seed & (2**64 - 1)),
+                                float(elite_frac), float(threshold), int(gauge), float(corr_elite_frac),
+                                float(corr_threshold), int(corr_after), int(preprocess), int(bool(merge)),
                                 0 if gm is None else 1, int(trotter), None if gm is None else gm.ctypes.data)
-    out = spv_multistart_out(res["fixing_E"].data_ptr(), res["solving_E"].data_ptr(),
-                             res["fixed_mask"].data_ptr(), res["fixed_val"].data_ptr(), res["info"].ctypes.data,
+    out = spv_multistart_out(res["corr_E"].data_ptr() if Rc > 0 else None, res["fixing_E"].data_ptr(),
+                             res["solving_E"].data_ptr(), res["fixed_mask"].data_ptr(), res["fixed_val"].data_ptr(),
+                             res["info"].ctypes.data, res["info_pre"].ctypes.data, res["start_best"].ctypes.data,
                              res["best_spins"].data_ptr(), C.addressof(best))
     ps = P.c_struct()
     ctx.check(_lib.spv_multistart(ctx.handle, C.byref(ps), C.byref(prm), C.byref(out), _stream(stream)),
               "spv_multistart")
+    res["corr_E"] = res["corr_E"][:, :Rc]
     res["solving_E"] = res["solving_E"][:, :Rs]
     res["fixed_mask"], res["fixed_val"] = res["fixed_mask"][:, :n], res["fixed_val"][:, :n]
     res["best_spins"] = res["best_spins"][:n]
     res["best_E"] = int(best.value)
     return res
+
+
+def spv_multistart_split(total, zero_bias):
+    """Per-start sample split of the parameter appendix: (correlation, fixing, solving) reads."""
+    c, f, s = C.c_int32(), C.c_int32(), C.c_int32()
+    _lib.spv_multistart_split(int(total), int(bool(zero_bias)), C.byref(c), C.byref(f), C.byref(s))
+    return c.value, f.value, s.value
+
+
+def spv_r99(start_best, e_target, per_start):
+    """R99 of a multi-start run (Sec. III.A): (R99, p); R99 is -1 when no start reached e_target."""
+    sb = np.ascontiguousarray(start_best, dtype=np.int64)
+    p = C.c_double()
+    v = _lib.spv_r99(sb.ctypes.data, sb.size, int(e_target), float(per_start), C.byref(p))
+    return v, p.value
 
 
 class TreeResult:

@@ -83,6 +83,8 @@ struct Ctx {
     DevBuf serve;   // serving slot: assembled tempering sample
     DevBuf merge;   // component count and recombination scratch
     DevBuf ms;      // multi-start working set
+    void *ms_host = nullptr;  // pinned staging of the multi-start driver's per-start values
+    size_t ms_host_bytes = 0;
     DevBuf tree;    // tree pre-processing scratch
     DevBuf sa_stream;  // streamed SA: task counter, tagged spin words between chunks
     DevBuf sa_big;     // SA: byte-parallel instance in global memory (problems too large for LDS)
@@ -362,12 +364,32 @@ hipError_t launch_merge(const spv_problem *P, const int32_t *comp, int C, const 
                         int64_t *merged_E, int64_t *part_E, void *scratch, hipStream_t s);
 
 // Multi-start driver helpers (multistart.hip).
-hipError_t launch_ms_offset(const int64_t *Ered, const int64_t *info, int info_stride, int S, int Rs,
-                            int64_t *solving_E, hipStream_t s);
-hipError_t launch_ms_best(const int64_t *fixE, const int64_t *solE, int S, int F, int Rs, int n,
-                          const int8_t *fix_spins, const int8_t *sol_spins, size_t sol_stride, const uint8_t *fmask,
-                          const int8_t *fval, const int32_t *orig, size_t orig_stride, const int64_t *info,
-                          int info_stride, int64_t *best, int8_t *best_spins, hipStream_t s);
+// Per-start values of the current stage (device arrays in the driver's working set).
+struct MsStageParams {
+    const long long *off;  // [S] offset of the start's current problem (all reductions so far)
+    const int *ncur;       // [S] variables of the start's current problem
+    const int *n_prev;     // [S] the level's input size (0: the level did not run for the start)
+    const int *n_next;     // [S] the level's output size
+};
+// Byte offsets of the fields of one reduction level slot (persistence or tree output).
+struct MsLevelOffsets {
+    size_t rp, col, J, h, co, orig, val, mask, kind, parent, round, order, info;
+};
+// The recorded energies of a start's sampling stages in stage order ([S][R[j]] each).
+struct MsRecords {
+    const long long *E[3];
+    int R[3];
+    int nst;
+};
+hipError_t launch_ms_record(int64_t *rec, int S, int R, const MsStageParams &prm, hipStream_t s);
+hipError_t launch_ms_compose(const MsStageParams &prm, int S, int n, const unsigned char *lvl, size_t lvl_stride,
+                             MsLevelOffsets lo, bool with_fixes, const int32_t *map_cur, int32_t *map_next,
+                             uint8_t *fm, int8_t *fv, hipStream_t s);
+hipError_t launch_ms_map_init(int32_t *map, int S, int n, int n_base, const int32_t *pre_orig, uint8_t *fm,
+                              int8_t *fv, hipStream_t s);
+hipError_t launch_ms_best(const MsRecords &rc, int S, int64_t *sb_E, int64_t *sb_pos, int64_t *best, hipStream_t s);
+hipError_t launch_ms_lift(const int8_t *cur, int n_next, const int32_t *orig, const int8_t *val, int n_prev,
+                          int8_t *prev, hipStream_t s);
 
 // LDS read-bandwidth probe (probe.hip): synchronous on `s`; `out` receives at most
 // 2 * num_cus words.

@@ -270,6 +270,25 @@ spv_status spv_persist_fix(spv_ctx *ctx, const spv_problem *P, const int8_t *sam
                            hipStream_t stream);
 
 /*
+ * spv_persist_fix for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same computation and outputs, with its scratch in a file-scope device
+ * array of 16 MiB per device (held until the process ends; its address is
+ * looked up when a context is created on the device) instead of context
+ * memory.  Calls no allocating routine and no memset.  SPV_ECAPACITY when the
+ * call needs more scratch than that (about 64 + 4R + 8n ceil(m/64) + 8n +
+ * 16 (power of two >= 2n) + 8n bytes, m the elite size).  Every call on a
+ * device shares that device's array: calls that overlap on one device (on
+ * different streams, or from different threads) race; calls ordered on one
+ * stream do not.  The array keeps the last call's contents; each call writes
+ * what it reads before reading it.
+ */
+spv_status spv_persist_fix_noalloc(spv_ctx *ctx, const spv_problem *P, const int8_t *samples,
+                                   const int64_t *energies, int32_t R, double elite_frac,
+                                   double threshold, int32_t gauge, const spv_fix_out *out,
+                                   hipStream_t stream);
+
+/*
  * Iterated SPVAR (Sec. II.B "ISPVAR"): `rounds` rounds of spv_sample
  * (round r uses seed + r) followed by spv_persist_fix on the current reduced
  * problem; fixes are never undone; stops early when nothing is left.

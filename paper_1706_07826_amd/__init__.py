@@ -99,6 +99,8 @@ _SIGS = {
     "spv_energy": ([_vp, _P, _vp, _i32, _vp, _vp], C.c_int),
     "spv_persist_fix": ([_vp, _P, _vp, _vp, _i32, _f64, _f64, _i32, C.POINTER(spv_fix_out), _vp],
                         C.c_int),
+    "spv_persist_fix_noalloc": ([_vp, _P, _vp, _vp, _i32, _f64, _f64, _i32, C.POINTER(spv_fix_out), _vp],
+                                C.c_int),
     "spv_ispvar": ([_vp, _P, _vp, _i32, _i32, _u64, _i32, _f64, _f64, _i32, _vp, _vp, _vp, _vp, _vp],
                    C.c_int),
     "spv_pt_sample": ([_vp, _P, C.POINTER(spv_pt_params), C.POINTER(spv_pt_out), _vp], C.c_int),
@@ -324,7 +326,9 @@ class FixResult:
         return self._keep["orig_index"][:self.info()["n_free"]]
 
 
-def spv_persist_fix(ctx, P, samples, energies, elite_frac, threshold, gauge=0, stream=None):
+def spv_persist_fix(ctx, P, samples, energies, elite_frac, threshold, gauge=0, stream=None, noalloc=False):
+    """Persistence and reduction (Algorithm 1).  noalloc=True calls spv_persist_fix_noalloc (scratch
+    in the library's static device array); the outputs are allocated here either way."""
     dev = ctx.device
     n, nnz = P.n, P.nnz
     keep = dict(fixed_mask=torch.empty(max(n, 1), dtype=torch.uint8, device=dev),
@@ -339,10 +343,10 @@ def spv_persist_fix(ctx, P, samples, energies, elite_frac, threshold, gauge=0, s
     out = spv_fix_out(*[keep[k].data_ptr() for k in ("fixed_mask", "fixed_val", "row_ptr", "col", "J",
                                                      "h", "colour", "orig_index", "info")])
     ps = P.c_struct()
-    rc = _lib.spv_persist_fix(ctx.handle, C.byref(ps), _ptr(samples) if n else None, _ptr(energies),
-                              int(energies.shape[0]), float(elite_frac), float(threshold), int(gauge),
-                              C.byref(out), _stream(stream))
-    ctx.check(rc, "spv_persist_fix")
+    fn = _lib.spv_persist_fix_noalloc if noalloc else _lib.spv_persist_fix
+    rc = fn(ctx.handle, C.byref(ps), _ptr(samples) if n else None, _ptr(energies), int(energies.shape[0]),
+            float(elite_frac), float(threshold), int(gauge), C.byref(out), _stream(stream))
+    ctx.check(rc, "spv_persist_fix_noalloc" if noalloc else "spv_persist_fix")
     keep["fixed_mask"] = keep["fixed_mask"][:n]
     keep["fixed_val"] = keep["fixed_val"][:n]
     return FixResult(ctx, P, out, keep)

@@ -391,6 +391,12 @@ spv_status spv_ctx_create(int32_t device, spv_ctx **out) {
     }
     x->c.num_cus = cus;
     x->c.lds_max = (size_t)lds;
+    // Set-up of the allocation-free persistence: this device's scratch address.
+    void *na = nullptr;
+    if (noalloc_scratch(device, &na) != hipSuccess) {
+        delete x;
+        return SPV_EDEVICE;
+    }
     *out = x;
     return SPV_OK;
 }
@@ -684,12 +690,15 @@ spv_status spv_sample_last_shape(const spv_ctx *ctx, int32_t *threads, int32_t *
     return SPV_OK;
 }
 
-spv_status spv_persist_fix(spv_ctx *ctx, const spv_problem *P, const int8_t *samples,
-                           const int64_t *energies, int32_t R, double elite_frac, double threshold,
-                           int32_t gauge, const spv_fix_out *out, hipStream_t stream) {
-    if (!ctx) return SPV_EINVAL;
-    Ctx *c = &ctx->c;
-    DeviceGuard g(c->device);
+}  // extern "C"
+
+namespace spv {
+
+// Argument checks and launch parameters shared by both persistence entry points;
+// *scratch_bytes receives the scratch the launch needs.
+spv_status persist_prepare(Ctx *c, const spv_problem *P, const int8_t *samples, const int64_t *energies, int32_t R,
+                           double elite_frac, double threshold, int32_t gauge, const spv_fix_out *out, FixLaunch *L,
+                           size_t *scratch_bytes) {
     spv_status st = check_problem_host(c, P);
     if (st) return st;
     if (R < 1) return set_err(c, SPV_EINVAL, "R=%d < 1", R);
@@ -706,20 +715,59 @@ spv_status spv_persist_fix(spv_ctx *ctx, const spv_problem *P, const int8_t *sam
     const double kk = std::ceil(threshold * (double)m);
     const int kmin = (int)kk;
     if (kmin < 1) return set_err(c, SPV_EINVAL, "k_min < 1");
-    st = ensure(c, c->scratch, fix_scratch_bytes(P->n, R, m));
-    if (st) return st;
+    L->P = P;
+    L->image = nullptr;
+    L->samples = samples;
+    L->energies = energies;
+    L->R = R;
+    L->m = m;
+    L->kmin = kmin;
+    L->gauge_mode = gauge;
+    L->out = out;
+    L->scratch = nullptr;
+    L->scratch_bytes = 0;
+    *scratch_bytes = fix_scratch_bytes(P->n, R, m);
+    return SPV_OK;
+}
+
+}  // namespace spv
+
+extern "C" {
+
+spv_status spv_persist_fix(spv_ctx *ctx, const spv_problem *P, const int8_t *samples,
+                           const int64_t *energies, int32_t R, double elite_frac, double threshold,
+                           int32_t gauge, const spv_fix_out *out, hipStream_t stream) {
+    if (!ctx) return SPV_EINVAL;
+    Ctx *c = &ctx->c;
+    DeviceGuard g(c->device);
     FixLaunch L;
-    L.P = P;
-    L.image = nullptr;
-    L.samples = samples;
-    L.energies = energies;
-    L.R = R;
-    L.m = m;
-    L.kmin = kmin;
-    L.gauge_mode = gauge;
-    L.out = out;
+    size_t bytes = 0;
+    spv_status st = persist_prepare(c, P, samples, energies, R, elite_frac, threshold, gauge, out, &L, &bytes);
+    if (st) return st;
+    if ((st = ensure(c, c->scratch, bytes))) return st;
     L.scratch = c->scratch.p;
     L.scratch_bytes = c->scratch.bytes;
+    return hip_check(c, launch_persist_fix(L, stream), "persist launch");
+}
+
+spv_status spv_persist_fix_noalloc(spv_ctx *ctx, const spv_problem *P, const int8_t *samples,
+                                   const int64_t *energies, int32_t R, double elite_frac, double threshold,
+                                   int32_t gauge, const spv_fix_out *out, hipStream_t stream) {
+    if (!ctx) return SPV_EINVAL;
+    Ctx *c = &ctx->c;
+    DeviceGuard g(c->device);
+    FixLaunch L;
+    size_t bytes = 0;
+    spv_status st = persist_prepare(c, P, samples, energies, R, elite_frac, threshold, gauge, out, &L, &bytes);
+    if (st) return st;
+    if (bytes > kNoAllocScratchBytes)
+        return set_err(c, SPV_ECAPACITY, "spv_persist_fix_noalloc: n=%d, R=%d, m=%d need %zu B of scratch > %zu",
+                       P->n, R, L.m, bytes, kNoAllocScratchBytes);
+    void *p = nullptr;
+    const hipError_t e = noalloc_scratch(c->device, &p);
+    if (e != hipSuccess) return hip_check(c, e, "spv_persist_fix_noalloc scratch");
+    L.scratch = p;
+    L.scratch_bytes = kNoAllocScratchBytes;
     return hip_check(c, launch_persist_fix(L, stream), "persist launch");
 }
 

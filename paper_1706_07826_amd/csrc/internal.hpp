@@ -262,6 +262,12 @@ struct FixLaunch {
     size_t scratch_bytes;
 };
 size_t fix_scratch_bytes(int n, int R, int m);
+// Allocation-free persistence: the largest scratch it serves, and the per-device
+// address of its file-scope scratch array (looked up once per device, with that
+// device current).
+constexpr size_t kNoAllocScratchBytes = (size_t)16 << 20;
+constexpr int kMaxDevices = 64;
+hipError_t noalloc_scratch(int device, void **ptr);
 hipError_t launch_compose(int n_cur, const uint8_t *fm_round, const int8_t *fv_round,
                           const int32_t *orig_cur, uint8_t *fixed_mask, int8_t *fixed_val,
                           const int64_t *info, const int32_t *orig_out, int32_t *orig_new,

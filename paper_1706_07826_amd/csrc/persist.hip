@@ -19,10 +19,33 @@
 //                     folds fixed neighbours into h', reduces the offset.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "device.hpp"
 #include "internal.hpp"
 
 namespace spv {
+
+// Scratch of the allocation-free persistence entry point: one copy per device,
+// alive until the process ends.  Host code never passes this name to a kernel
+// (on the host it is only a stand-in); it uses the per-device address that
+// noalloc_scratch looks up.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+hipError_t noalloc_scratch(int device, void **ptr) {
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));  // `device` is current
+        if (e != hipSuccess) return e;
+        addr[device] = p;
+    }
+    *ptr = addr[device];
+    return hipSuccess;
+}
 
 namespace {
 

@@ -1,16 +1,19 @@
 #!/usr/bin/env python3
 """Throughput benchmark of the sample-persistence hot path on one MI355X.
 
-One step = one full pass of the path over one batch of synthetic input:
-spv_sample (Metropolis simulated annealing, 10,000 reads x 2,000 sweeps on the
-Chimera 8x8 instance, N = 512) followed by spv_persist_fix (elite 5 %,
-threshold 0.95).  Inputs are resident in device memory before timing starts.
-
-Prints ONE JSON line.  `value` is spin-updates/s of the whole step
-(reads x n x sweeps / step time).  The roofline object covers the dominant
-kernel (the SA sweep), timed with events on the stream it runs on.  The
-cpu_baseline object times the CPU oracle on a bounded sample of the same
-workload (a subset of reads, all sweeps).
+Default (headline): one JSON line carrying the metric's three clauses.
+  * value: spin-updates/s of the residual batch -- 512 residual-shaped instances
+    (n log-uniform 50..1000), 1000 reads x 1000 sweeps each, in one persistent,
+    graph-replayed launch per step -- beside the plain path (one spv_sample
+    launch per instance), their ratio and whether the outputs are bit-identical.
+  * spvar_solves: SPVAR solves/s on the Chimera 8x8 instance (N = 512): one solve
+    = spv_sample (SA, 10,000 reads x 2,000 sweeps) + spv_persist_fix.
+  * serving: p50/p99 latency of a mixed request stream (SA N=512, PT N=1000,
+    PT-ICM N=8000, each + persistence) at Poisson arrivals of 0.8 x saturation.
+Inputs are resident in device memory before timing starts.  Each part carries
+the roofline object of its dominant kernel (timed with HIP events on the stream
+it runs on) and a cpu_baseline: the CPU oracle on a bounded sample of the same
+workload.  --workload selects a single workload's own line instead.
 """
 import argparse
 import json
@@ -80,14 +83,14 @@ def sources_digest(paths):
     return h.hexdigest()
 
 
-def profiled_traffic_bytes(kernel):
-    """HBM bytes per launch of the SA kernel from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE scaled by a copy of known size), or None
-    when the summary covers another kernel or any source of the kernel changed
-    after the counters were taken."""
+def profiled_traffic_bytes(kernel, workload="chimera8_sa"):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter summary
+    profiles/<kernel>_<workload>.json (FETCH_SIZE and WRITE_SIZE scaled by a copy of known
+    size), or None when the summary covers another kernel or any of the kernel's sources
+    changed after the counters were taken."""
     base = kernel.split("<")[0]
     try:
-        with open(os.path.join(ROOT, "profiles", f"{base}_chimera8_sa.json")) as f:
+        with open(os.path.join(ROOT, "profiles", f"{base}_{workload}.json")) as f:
             prof = json.load(f)
         digest = sources_digest(prof["sources"])
     except (OSError, KeyError, ValueError):
@@ -96,6 +99,35 @@ def profiled_traffic_bytes(kernel):
         return None
     kib = prof["fetch_kib"] * prof["fetch_scale"] + prof["write_kib"] * prof["write_scale"]
     return int(round(kib * 1024))
+
+
+def pt_slots_per_update(mean_degree, digits, philox_slots):
+    """VALU lane-slots per tempering Metropolis update (general body): one Philox block per
+    quad and digit tested, one multiply-add per neighbour, about 4 for the field, sign,
+    threshold compares and flip."""
+    return digits * philox_slots / 4.0 + mean_degree + 4
+
+
+def cpu_threads():
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+_PROBES = {}
+
+
+def measured_philox_slots(spv, ctx):
+    """Issue slots one Philox block costs at full occupancy (spv_philox_probe): the best of
+    three probe runs, measured once per process and shared by every roofline of the line."""
+    if "philox" not in _PROBES:
+        _PROBES["philox"] = min(PEAK_VALU_TSLOTS * 1e12 / spv.spv_philox_probe(ctx) for _ in range(3))
+    return _PROBES["philox"]
+
+
+def measured_lds_peak(spv, ctx):
+    """The device's LDS read bandwidth (spv_lds_probe), best of two runs, once per process."""
+    if "lds" not in _PROBES:
+        _PROBES["lds"] = max(spv.spv_lds_probe(ctx) for _ in range(2))
+    return _PROBES["lds"]
 
 
 def main():
@@ -107,17 +139,18 @@ def main():
     ap.add_argument("--cpu-reads", type=int, default=0, help="oracle reads (0 = 640 per thread, at most all)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after timing, run one device copy of this size (counter calibration)")
-    ap.add_argument("--workload", default="chimera8_sa",
-                    choices=["chimera8_sa", "residual_batch", "cubic10_pt", "cubic20_pticm", "serving",
+    ap.add_argument("--workload", default="headline",
+                    choices=["headline", "chimera8_sa", "residual_batch", "cubic10_pt", "cubic20_pticm", "serving",
                              "spvar_round", "multistart", "spvar_tree", "cubic4_ispvar", "chimera32_sa",
                              "chimera8_sqa", "multistart_sqa"])
     ap.add_argument("--pt-runs", type=int, default=0, help="PT workloads: runs per step (0 = the config's)")
-    ap.add_argument("--serving-requests", type=int, default=2000)
+    ap.add_argument("--serving-requests", type=int, default=2000,
+                    help="serving workload: requests per load level (the headline uses 400 / 800)")
     ap.add_argument("--serving-slots", type=int, default=16)
     ap.add_argument("--hw-queues", type=int, default=-1,
                     help="GPU_MAX_HW_QUEUES for this process (-1: 32 for serving, unchanged otherwise)")
     args = ap.parse_args()
-    hwq = args.hw_queues if args.hw_queues >= 0 else (32 if args.workload == "serving" else 0)
+    hwq = args.hw_queues if args.hw_queues >= 0 else (32 if args.workload in ("serving", "headline") else 0)
     if hwq:
         # HIP reads it when the runtime starts: one hardware queue per serving slot keeps
         # a long request's kernel from blocking the slots that share its queue.
@@ -158,6 +191,21 @@ def main():
         return bench_chimera32_sa(args)
     if args.workload == "chimera8_sqa":
         return bench_chimera8_sqa(args)
+
+    if args.workload == "headline":
+        return bench_headline(args)
+    print(json.dumps(part_chimera8_sa(args)), flush=True)
+
+
+def part_chimera8_sa(args, line=True):
+    """Config 2: one step = spv_sample (SA, 10,000 reads x 2,000 sweeps, Chimera 8x8, N=512) +
+    spv_persist_fix (elite 5 %, threshold 0.95).  Returns the bench line (line=True) or the
+    block the headline line carries."""
+    import numpy as np
+    import torch
+
+    import paper_1706_07826_amd as spv
+    from spvar_inputs import configs as cf
 
     cfg = cf.CHIMERA8_SA
     inst = cf.instance(cfg)
@@ -207,7 +255,7 @@ def main():
     mean_deg = inst.nnz / inst.n
     max_degree, x_bound = spv.spv_problem_check(ctx, P)  # the bounds the library derives at ingest
     byte_parallel = x_bound <= 255  # the library's rule for its byte-parallel body
-    philox_slots = PEAK_VALU_TSLOTS * 1e12 / spv.spv_philox_probe(ctx)  # measured issue slots per block
+    philox_slots = measured_philox_slots(spv, ctx)  # measured issue slots per block
     spu = slots_per_update(mean_deg, byte_parallel, philox_slots)
     achieved = updates * spu / (sa_ms / 1e3) / 1e12
     shape = spv.spv_sample_last_shape(ctx)
@@ -227,7 +275,7 @@ def main():
     roofline["philox_slots"] = round(philox_slots, 2)  # measured: spv_philox_probe
     roofline["philox_instructions"] = PHILOX_INSTRUCTIONS
     if byte_parallel:
-        probe = spv.spv_lds_probe(ctx)
+        probe = measured_lds_peak(spv, ctx)
         roofline["lds"] = lds_object(updates / (sa_ms / 1e3),
                                      sa_lds_bytes_per_update(max_degree, shape["words_per_lane"]), probe,
                                      "competing bound: LDS traffic of the sweep against the measured LDS peak")
@@ -259,10 +307,18 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out), flush=True)
+    if line:
+        return out
+    return {"workload": out["config"]["workload"], "spvar_solves_per_s": out["spvar_solves_per_s"],
+            "spin_updates_per_s": out["value"], "ms_per_step": out["ms_per_step"],
+            "fixed_per_solve": out["fixed_per_solve"], "roofline": roofline, "cpu_baseline": cpu}
 
 
 def bench_residual_batch(args):
+    print(json.dumps(part_residual_batch(args)), flush=True)
+
+
+def part_residual_batch(args):
     """Residual batch: 512 instances (n log-uniform 50..1000), 1000 reads x 1000 sweeps
     each.  Batched persistent launch (graph-replayed, autotuned shape) vs the plain path
     (one spv_sample launch per instance, default shape), outputs compared bit for bit."""
@@ -286,11 +342,18 @@ def bench_residual_batch(args):
     for _ in range(args.warmup):
         spv.spv_sample_batch(ctx, probs, betas, reads, seeds, spins=sp, energies=en, graph=True)
     torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
+        # the replayed graph on this stream: descriptor copy, image prep, batch_sa_kernel
+        events[k][0].record(stream)
         spv.spv_sample_batch(ctx, probs, betas, reads, seeds, spins=sp, energies=en, graph=True)
+        events[k][1].record(stream)
     torch.cuda.synchronize()
     batched_s = (time.perf_counter() - t0) / args.steps
+    graph_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
     psp = [torch.empty_like(t) for t in sp]
     pen = [torch.empty_like(t) for t in en]
     for b, P in enumerate(probs):  # warm-up of the plain path
@@ -302,6 +365,51 @@ def bench_residual_batch(args):
     torch.cuda.synchronize()
     plain_s = time.perf_counter() - t0
     same = all(torch.equal(a, b) for a, b in zip(sp + en, psp + pen))
+    if args.calib_copy_mib:
+        src = torch.ones(args.calib_copy_mib << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+    # VALU roofline of the batched kernel: the byte-parallel body's algorithmic slots per update
+    # at the batch's mean degree, over the replayed graph's duration (HIP events on its stream)
+    bounds = [spv.spv_problem_check(ctx, P) for P in probs]
+    byte_parallel = max(xb for _, xb in bounds) <= 255
+    mean_deg = sum(i.nnz for i in insts) / sum(i.n for i in insts)
+    philox_slots = measured_philox_slots(spv, ctx)
+    spu = slots_per_update(mean_deg, byte_parallel, philox_slots)
+    achieved = updates * spu / (graph_ms / 1e3) / 1e12
+    dk = max(md for md, _ in bounds)
+    if not byte_parallel:
+        kernel = "batch_sa_kernel<1>"
+    elif dk in (4, 6, 8):
+        kernel = f"batch_sa_kernel<0, {dk}>"
+    else:
+        kernel = "batch_sa_kernel<0>"
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_VALU_TSLOTS, 3),
+                "unit": "Tslot/s", "frac": round(achieved / PEAK_VALU_TSLOTS, 4),
+                "traffic": profiled_traffic_bytes(kernel, "residual_batch"), "kernel": kernel,
+                "kernel_ms": round(graph_ms, 4), "slots_per_update": round(spu, 3),
+                "philox_slots": round(philox_slots, 2), "mean_degree": round(mean_deg, 3),
+                "note": "kernel_ms spans the replayed graph (descriptor copy + image prep + the batched "
+                        "kernel), so it bounds the kernel's own duration from above"}
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle on the first 16 reads of every instance (all sweeps), instances spread
+        # over the host threads
+        import oracle
+        from concurrent.futures import ThreadPoolExecutor
+        threads = cpu_threads()
+        r_cpu = min(16, cfg["reads"])
+        t1 = time.perf_counter()
+        with ThreadPoolExecutor(threads) as ex:
+            list(ex.map(lambda b: oracle.sa_sample(insts[b], betas, seed=seeds[b], r_begin=0, r_end=r_cpu,
+                                                  threads=1), range(len(insts))))
+        cdt = time.perf_counter() - t1
+        cu = sum(i.n for i in insts) * r_cpu * cfg["sweeps"]
+        cpu = {"value": round(cu / cdt, 1), "unit": "spin-updates/s", "cores": threads, "kind": "oracle",
+               "sample": f"reads 0..{r_cpu - 1} of every one of the {len(insts)} instances (all {cfg['sweeps']} "
+                         f"sweeps), {threads} threads, {cdt:.1f} s wall"}
     out = {
         "metric": METRIC_NAME, "value": round(updates / batched_s, 1), "unit": "spin-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -312,9 +420,9 @@ def bench_residual_batch(args):
                    "instances": len(insts), "total_n": sum(i.n for i in insts)},
         "plain_spin_updates_per_s": round(updates / plain_s, 1), "plain_ms": round(plain_s * 1e3, 3),
         "batched_over_plain": round(plain_s / batched_s, 3), "bit_identical": bool(same),
-        "batch_shape": shape,
+        "batch_shape": shape, "roofline": roofline, "cpu_baseline": cpu,
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def bench_pt(args, cfg, label):
@@ -360,13 +468,17 @@ def bench_pt(args, cfg, label):
     # the exchange add latency-bound work on top; records are LDS-resident at N = 1000)
     max_degree, x_bound = spv.spv_problem_check(ctx, P)
     nd = 2 if x_bound > 511 else 1
-    probe = spv.spv_lds_probe(ctx)
+    probe = measured_lds_peak(spv, ctx)
     out["lds"] = lds_object(updates / dt, pt_lds_bytes_per_update(max_degree, nd, inst.n <= 4096), probe,
                             "Metropolis LDS traffic of the whole step against the measured LDS peak")
     print(json.dumps(out), flush=True)
 
 
 def bench_serving(args):
+    print(json.dumps(part_serving(args, args.serving_requests, (0.5, 0.8, 0.95))), flush=True)
+
+
+def part_serving(args, nreq, load_fracs, line=True):
     """Serving stream: requests of three kinds (by count 60 % SA on the Chimera N=512 instance,
     1000 reads x 1000 sweeps + persistence; 30 % PT on the cubic N=1000 instance, 32 betas x 4
     runs x 1000 sweeps + persistence; 10 % PT with Houdayer moves on the cubic N=8000 instance,
@@ -387,7 +499,6 @@ def bench_serving(args):
         "pticm8000": dict(P=spv.Problem.from_instance(cf.instance(c5)), betas=cf.betas(c5), cfg=c5),
     }
     updates = {"sa512": 512 * 1000 * 1000, "pt1000": 1000 * 32 * 4 * 1000, "pticm8000": 8000 * 80 * 1000}
-    nreq = args.serving_requests
     rng = np.random.default_rng(31337)
     mix = rng.choice(["sa512", "pt1000", "pticm8000"], size=nreq, p=[0.6, 0.3, 0.1])
     base_seed = 5000
@@ -447,9 +558,10 @@ def bench_serving(args):
         srv.release(t)
     sat = run(0)
     loads = {}
-    for f in (0.5, 0.8, 0.95):
+    for f in load_fracs:
         loads[str(f)] = run(f * sat["requests_per_s"])
     srv.close()
+    roofline, cpu = serving_roofline_and_cpu(args, ctx, kinds)
     out = {
         "metric": METRIC_NAME, "value": sat["spin_updates_per_s"], "unit": "spin-updates/s",
         "n_gpus": 1, "steps": nreq, "warmup": 12, "ms_per_step": round(1e3 / sat["requests_per_s"], 3),
@@ -459,8 +571,112 @@ def bench_serving(args):
                                "32 betas x 4 runs x 1000 sweeps + fix, 10 % PT-ICM N=8000 40 betas x 2 chains "
                                "x 1000 sweeps + fix), burst then Poisson at 0.5/0.8/0.95 of saturation",
                    "slots": args.serving_slots, "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES")},
-        "saturation": sat, "poisson": loads,
+        "saturation": sat, "poisson": loads, "roofline": roofline, "cpu_baseline": cpu,
     }
+    if line:
+        return out
+    top = loads[str(load_fracs[-1])] if load_fracs else sat
+    return {"workload": out["config"]["workload"], "load": load_fracs[-1] if load_fracs else "burst",
+            "p50_ms": top["p50_ms"], "p99_ms": top["p99_ms"], "requests_per_s": sat["requests_per_s"],
+            "spin_updates_per_s": sat["spin_updates_per_s"], "saturation": sat, "poisson": loads,
+            "slots": args.serving_slots, "roofline": roofline, "cpu_baseline": cpu}
+
+
+def serving_roofline_and_cpu(args, ctx, kinds):
+    """The serving stream's dominant kernel by device time is the N=8000 tempering kernel with
+    cluster moves (10 % of the requests, each about two orders of magnitude longer than an SA
+    request): its VALU roofline from one request run alone, timed with HIP events on its
+    stream.  cpu_baseline: the oracle's throughput on a bounded sample of every request kind
+    (SA: 64 reads; PT N=1000: 4 runs of 250 sweeps; PT-ICM N=8000: one run of 20 sweeps), and
+    the latency a request of each kind would have on the host threads at those rates."""
+    import numpy as np
+    import torch
+
+    import paper_1706_07826_amd as spv
+
+    d = kinds["pticm8000"]
+    P, betas, c = d["P"], d["betas"], d["cfg"]
+    K = betas.size
+    stream = torch.cuda.current_stream()
+    spv.spv_pt_sample(ctx, P, betas, 1, 2, 1000, 1, icm=(0, K), final=False)  # warm-up
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(stream)
+    spv.spv_pt_sample(ctx, P, betas, 1, 2, 1000, 2, icm=(0, K), final=False)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1])
+    md, xb = spv.spv_problem_check(ctx, P)
+    digits = 1 if xb < 512 else (2 if xb < 512 * 512 else 3)
+    philox_slots = measured_philox_slots(spv, ctx)
+    upd = P.n * K * 2 * 1000
+    spu = pt_slots_per_update(P.nnz / P.n, digits, philox_slots)
+    achieved = upd * spu / (ms / 1e3) / 1e12
+    probe = measured_lds_peak(spv, ctx)
+    roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": round(PEAK_VALU_TSLOTS, 3),
+                "unit": "Tslot/s", "frac": round(achieved / PEAK_VALU_TSLOTS, 5), "traffic": None,
+                "kernel": f"ptx_kernel<{digits}, true, {md}>", "kernel_ms": round(ms, 3),
+                "slots_per_update": round(spu, 3),
+                "lds": lds_object(upd / (ms / 1e3), pt_lds_bytes_per_update(md, digits, False), probe,
+                                  "LDS traffic of the Metropolis updates against the measured LDS peak"),
+                "note": "one PT-ICM request alone (N=8000, 40 betas x 2 chains x 1000 sweeps, Houdayer moves "
+                        "at every slot); a run spans K/4 = 10 workgroups, so each sweep is latency-bound"}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        from concurrent.futures import ThreadPoolExecutor
+        from spvar_inputs import configs as cf
+        threads = cpu_threads()
+        sa, pt = kinds["sa512"], kinds["pt1000"]
+        inst_sa, inst_pt, inst_icm = cf.instance(sa["cfg"]), cf.instance(pt["cfg"]), cf.instance(c)
+        rates = {}
+        t1 = time.perf_counter()
+        oracle.sa_sample(inst_sa, sa["betas"], seed=5000, r_begin=0, r_end=64, threads=threads)
+        dt = time.perf_counter() - t1
+        rates["sa512"] = 64 * inst_sa.n * 1000 / dt
+        t1 = time.perf_counter()
+        oracle.pt_sample(inst_pt, pt["betas"], 4, 1, 250, seed=5001, threads=min(4, threads))
+        dt = time.perf_counter() - t1
+        rates["pt1000"] = 4 * 32 * inst_pt.n * 250 / dt
+        t1 = time.perf_counter()
+        oracle.pt_sample(inst_icm, betas, 1, 2, 20, seed=5002, icm=(0, K), threads=1)
+        dt = time.perf_counter() - t1
+        rates["pticm8000"] = 80 * inst_icm.n * 20 / dt
+        upd_kind = {"sa512": 512 * 1000 * 1000, "pt1000": 1000 * 32 * 4 * 1000, "pticm8000": 8000 * 80 * 1000}
+        mix = {"sa512": 0.6, "pt1000": 0.3, "pticm8000": 0.1}
+        mean_upd = sum(mix[k] * upd_kind[k] for k in mix)
+        mean_s = sum(mix[k] * upd_kind[k] / rates[k] for k in mix)
+        cpu = {"value": round(mean_upd / mean_s, 1), "unit": "spin-updates/s", "cores": threads, "kind": "oracle",
+               "latency_ms": {k: round(upd_kind[k] / rates[k] * 1e3, 1) for k in mix},
+               "sample": f"SA N=512 64 reads x 1000 sweeps on {threads} threads; PT N=1000 4 runs x 250 sweeps "
+                         f"on {min(4, threads)} threads (one run per thread); PT-ICM N=8000 1 run x 20 sweeps "
+                         "on 1 thread (a run is sequential); value = the request mix's spin-updates/s at "
+                         "those rates, latency_ms = one request of each kind at its rate"}
+    return roofline, cpu
+
+
+def bench_headline(args):
+    """The metric's three clauses in one line: the config-4 residual batch, batched vs plain
+    (value = batched spin-updates/s); config-2 SPVAR solves/s (SA + persistence); config-5
+    serving p50/p99 (a burst for the saturation rate, then Poisson arrivals at 0.8 of it).
+    Each carries the roofline of its dominant kernel and a CPU-oracle baseline."""
+    batch = part_residual_batch(args)
+    solves = part_chimera8_sa(args, line=False)
+    serving = part_serving(args, 400, (0.8,), line=False)
+    out = {k: batch[k] for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+                                 "higher_is_better", "scaling", "vs_baseline", "dtype")}
+    out["data"] = ("synthetic: residual-shaped instances cut from a seeded Chimera 16x16 parent; seeded Chimera "
+                   "8x8 and Gaussian cubic L=10 / L=20 instances (no paper instances available)")
+    out["config"] = dict(batch["config"])
+    out["plain"] = {"spin_updates_per_s": batch["plain_spin_updates_per_s"], "ms": batch["plain_ms"],
+                    "launches": batch["config"]["instances"]}
+    out["batched_over_plain"] = batch["batched_over_plain"]
+    out["bit_identical"] = batch["bit_identical"]
+    out["batch_shape"] = batch["batch_shape"]
+    out["roofline"] = batch["roofline"]
+    out["cpu_baseline"] = batch["cpu_baseline"]
+    out["spvar_solves"] = solves
+    out["serving"] = serving
     print(json.dumps(out), flush=True)
 
 

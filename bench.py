@@ -116,10 +116,11 @@ _PROBES = {}
 
 
 def measured_philox_slots(spv, ctx):
-    """Issue slots one Philox block costs at full occupancy (spv_philox_probe): the best of
-    three probe runs, measured once per process and shared by every roofline of the line."""
+    """Issue slots one Philox block costs at full occupancy (spv_philox_probe): the median of
+    five probe runs, measured once per process and shared by every roofline of the line."""
     if "philox" not in _PROBES:
-        _PROBES["philox"] = min(PEAK_VALU_TSLOTS * 1e12 / spv.spv_philox_probe(ctx) for _ in range(3))
+        runs = sorted(PEAK_VALU_TSLOTS * 1e12 / spv.spv_philox_probe(ctx) for _ in range(5))
+        _PROBES["philox"] = runs[2]
     return _PROBES["philox"]
 
 
@@ -383,7 +384,8 @@ def part_residual_batch(args):
     if not byte_parallel:
         kernel = "batch_sa_kernel<1>"
     elif dk in (4, 6, 8):
-        kernel = f"batch_sa_kernel<0, {dk}>"
+        # quads_per_item 0: the paired body (a lane holds both words of a pair of quads)
+        kernel = f"batch_sa_paired_kernel<{dk}>" if shape["quads_per_item"] == 0 else f"batch_sa_kernel<0, {dk}>"
     else:
         kernel = "batch_sa_kernel<0>"
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_VALU_TSLOTS, 3),
@@ -393,6 +395,8 @@ def part_residual_batch(args):
                 "philox_slots": round(philox_slots, 2), "mean_degree": round(mean_deg, 3),
                 "note": "kernel_ms spans the replayed graph (descriptor copy + image prep + the batched "
                         "kernel), so it bounds the kernel's own duration from above"}
+    if shape["quads_per_item"] == 0:
+        roofline["traffic"] = profiled_traffic_bytes(kernel, "residual_batch")
     cpu = None
     if not args.no_cpu_baseline:
         # the oracle on the first 16 reads of every instance (all sweeps), instances spread

@@ -546,12 +546,22 @@ spv_status spv_tree_complete(spv_ctx *ctx, int32_t n, const spv_tree_out *t, int
  *                 cached per batch shape and replayed on later calls with the
  *                 same shape; SPV_BATCH_TUNE times candidate shapes on this
  *                 batch (short schedule) the first time a shape class is seen
- *                 and keeps the fastest on the context.
+ *                 and keeps the fastest on the context; SPV_BATCH_PAIRED with
+ *                 threads (and wgs_per_cu) selects the paired body.
+ * Two sampler bodies serve the batch.  The one-word body: an item is
+ * (instance, block of quads_per_item quads), a lane holds one quad word of a
+ * site.  The paired body (images of 4, 6 or 8 records per site on the
+ * byte-parallel path; the default there): a lane holds both words of a pair of
+ * quads of one site, and an item is (instance, k pairs) with k chosen per
+ * instance so that k x class size fills the workgroup; the pairs share the
+ * instance's records in LDS.  spv_batch_last_shape reports quads_per_item 0
+ * for the paired body.  Both give the bits of one spv_sample per instance.
  * Descriptors are staged in pinned host memory; a call waits for the previous
  * batched launch on the context to finish reading them.
  */
 #define SPV_BATCH_GRAPH 1u
 #define SPV_BATCH_TUNE 2u
+#define SPV_BATCH_PAIRED 4u
 typedef struct {
     int32_t threads;
     int32_t quads_per_item;

@@ -57,6 +57,7 @@ class spv_batch_opts(C.Structure):
 
 SPV_BATCH_GRAPH = 1
 SPV_BATCH_TUNE = 2
+SPV_BATCH_PAIRED = 4
 
 
 class spv_multistart_params(C.Structure):
@@ -566,7 +567,7 @@ def spv_tree_complete(ctx, tree, reduced_spins, full=None, stream=None):
 
 
 def spv_sample_batch(ctx, problems, betas, reads, seeds, spins=None, energies=None, threads=0,
-                     quads_per_item=0, wgs_per_cu=0, graph=False, tune=False, stream=None):
+                     quads_per_item=0, wgs_per_cu=0, graph=False, tune=False, paired=False, stream=None):
     """Batched SA over many problems in one persistent launch.  Returns (spins, energies) lists
     of device tensors ([reads_b][n_b] int8, [reads_b] int64)."""
     B = len(problems)
@@ -582,7 +583,8 @@ def spv_sample_batch(ctx, problems, betas, reads, seeds, spins=None, energies=No
     sp = np.array([t.data_ptr() if t.numel() else 0 for t in spins] or [0], dtype=np.uint64)
     en = np.array([t.data_ptr() if t.numel() else 0 for t in energies] or [0], dtype=np.uint64)
     opts = spv_batch_opts(int(threads), int(quads_per_item), int(wgs_per_cu),
-                          (SPV_BATCH_GRAPH if graph else 0) | (SPV_BATCH_TUNE if tune else 0))
+                          (SPV_BATCH_GRAPH if graph else 0) | (SPV_BATCH_TUNE if tune else 0) |
+                          (SPV_BATCH_PAIRED if paired else 0))
     rc = _lib.spv_sample_batch(ctx.handle, B, arr, _ptr(b), b.size, _ptr(rd), _ptr(sd), _ptr(sp),
                                _ptr(en), C.byref(opts), _stream(stream))
     ctx.check(rc, "spv_sample_batch")

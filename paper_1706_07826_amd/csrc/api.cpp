@@ -188,6 +188,7 @@ spv_status ingest(Ctx *c, const spv_problem *P, int B, int flags, hipStream_t s,
             return set_err(c, SPV_ERANGE, "%smax_i |h_i| + sum_j |J_ij| = %llu, not below 2^26", where, hr[b].x_max);
         out[b].max_degree = std::max(1, hr[b].max_degree);
         out[b].x_bound = (int32_t)hr[b].x_max;
+        for (int k = 0; k < kMaxColours; ++k) out[b].class_n[k] = (flags & kIngestColours) ? hr[b].class_n[k] : 0;
     }
     return SPV_OK;
 }
@@ -843,6 +844,7 @@ spv_status spv_ispvar(spv_ctx *ctx, const spv_problem *P0, const double *betas, 
     }
     if (e != hipSuccess) return hip_check(c, e, "ispvar setup");
     Inst cur = *P;  // reduced problems keep the parent's bounds
+    for (int k = 0; k < kMaxColours; ++k) cur.class_n[k] = 0;
     int b = 0;
     int64_t offset_total = 0;
     std::vector<int64_t> hE(reads);

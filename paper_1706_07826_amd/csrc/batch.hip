@@ -116,6 +116,8 @@ struct BatchArgs {
     const uint32_t *tables;
     int row_len, sweeps, qw, n_max, D_max;
     uint32_t sweep_offset;
+    int pairs_qw;  // paired body: the spin area holds 2 n_max pairs_qw words (every item's 4 n copies)
+    int kmax;      // paired body: most copies an item has
 };
 
 // ND = 0: byte-parallel body; DK > 0: every image has exactly DK records per site.
@@ -174,6 +176,48 @@ __global__ __launch_bounds__(1024) void batch_sa_kernel(BatchArgs a) {
     }
 }
 
+// Paired body: an item is (instance, first quad, copies); see swar_run_pairs.
+template <int DK>
+__global__ __launch_bounds__(1024) void batch_sa_paired_kernel(BatchArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int cs[kMaxColours + 1];
+    __shared__ int item_s;
+    core::SwarLds L;
+    core::swar_layout(a.n_max, DK, a.row_len, a.pairs_qw, &L, smem, 2 * a.kmax);
+    int loaded = -1;
+    for (;;) {
+        if (threadIdx.x == 0) item_s = atomicAdd(a.counter, 1);
+        __syncthreads();
+        const int item = item_s;
+        __syncthreads();
+        if (item >= a.n_items) break;
+        const int b = a.items[3 * item];
+        const BatchInst in = a.insts[b];
+        core::SaItem it;
+        it.image = a.images + in.image_off;
+        it.tables = a.tables;
+        it.init = nullptr;
+        it.out = in.out;
+        it.energies = in.energies;
+        it.n = in.n;
+        it.D = in.D;
+        it.C = in.C;
+        it.row_len = a.row_len;
+        it.sweeps = a.sweeps;
+        it.reads = in.reads;
+        it.q0 = a.items[3 * item + 1];
+        it.qw = 2;  // records address region 0: S [n][2], then ~S [n][2]
+        it.sweep_offset = a.sweep_offset;
+        it.k0 = (uint32_t)in.seed;
+        it.k1 = (uint32_t)(in.seed >> 32);
+        if (b != loaded) {
+            core::swar_load_instance(L, it, cs);
+            loaded = b;
+        }
+        core::swar_run_pairs<DK>(L, it, cs, a.items[3 * item + 2]);
+    }
+}
+
 }  // namespace
 
 hipError_t launch_batch_prep(const BatchInst *insts, int B, int n_max, int32_t *images, hipStream_t s) {
@@ -183,6 +227,10 @@ hipError_t launch_batch_prep(const BatchInst *insts, int B, int n_max, int32_t *
     if (e != hipSuccess || n_max <= 0) return e;
     hipLaunchKernelGGL(batch_prep_nbr_kernel, dim3((n_max + 255) / 256, B), dim3(256), 0, s, insts, images);
     return hipGetLastError();
+}
+
+size_t batch_paired_lds_bytes(int n_max, int D_max, int row_len, int pairs_qw, int kmax) {
+    return core::swar_layout(n_max, D_max, row_len, pairs_qw, nullptr, nullptr, 2 * kmax);
 }
 
 size_t batch_lds_bytes(int n_max, int D_max, int row_len, int qw, int nd) {
@@ -208,6 +256,20 @@ hipError_t launch_batch_sa(const BatchLaunch &L, hipStream_t s) {
     a.n_max = L.n_max;
     a.D_max = L.D_max;
     a.sweep_offset = L.sweep_offset;
+    a.pairs_qw = L.pairs_qw;
+    a.kmax = L.kmax;
+    if (L.paired) {
+        const size_t plds = batch_paired_lds_bytes(L.n_max, L.dk, L.row_len, L.pairs_qw, L.kmax);
+        if (L.dk == 6)
+            hipLaunchKernelGGL((batch_sa_paired_kernel<6>), dim3(L.grid), dim3(L.threads), plds, s, a);
+        else if (L.dk == 4)
+            hipLaunchKernelGGL((batch_sa_paired_kernel<4>), dim3(L.grid), dim3(L.threads), plds, s, a);
+        else if (L.dk == 8)
+            hipLaunchKernelGGL((batch_sa_paired_kernel<8>), dim3(L.grid), dim3(L.threads), plds, s, a);
+        else
+            return hipErrorInvalidValue;
+        return hipGetLastError();
+    }
     const size_t lds = batch_lds_bytes(L.n_max, L.D_max, L.row_len, L.qw, L.nd);
     switch (sa_use_swar(L.nd, L.row_len) ? 0 : L.nd) {
         case 0:

@@ -32,13 +32,84 @@ namespace {
 
 struct Shape {
     int threads, qw, wgs_per_cu;
+    bool paired = false;  // the paired body (copies of 2 quads per item, chosen per instance)
 };
 
 struct Plan {
     int B = 0, n_max = 0, D_max = 1, nd = 1, row_len = 1, scale = 0, dk = 0;
     long long image_words = 0, total_quads = 0;
     std::vector<BatchInst> insts;
+    std::vector<std::vector<int>> classes;  // class sizes per instance (empty: not counted)
 };
+
+constexpr int kMaxPairCopies = 64;
+
+// The paired body's item list and LDS: per instance, the copy count k that fills the
+// most lanes of a class pass (k x class size over whole multiples of the workgroup,
+// class size estimated as ceil(n / C)), within the spin area the LDS leaves after the
+// records and site constants (lds_wg bytes per workgroup).  Returns false when even one
+// copy of the largest instance does not fit.
+struct PairPlan {
+    std::vector<int32_t> items;
+    int pairs_qw = 0, kmax = 1;
+    size_t lds = 0;
+};
+
+bool make_pair_items(const Plan &pl, int threads, size_t lds_wg, PairPlan *pp) {
+    // the spin area is allocated in granules of 2 n_max words: keep one granule of margin
+    const size_t fixed = batch_paired_lds_bytes(pl.n_max, pl.dk, pl.row_len, 0, kMaxPairCopies) + 512 +
+                         8 * (size_t)std::max(pl.n_max, 1);
+    if (fixed >= lds_wg) return false;
+    const size_t s_budget = lds_wg - fixed;
+    std::vector<int> order(pl.B);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return pl.insts[a].n > pl.insts[b].n; });
+    pp->items.clear();
+    pp->kmax = 1;
+    long long s_words = 0;
+    for (int b : order) {
+        const BatchInst &in = pl.insts[b];
+        const int quads = (in.reads + 3) / 4;
+        if (quads == 0 || in.n <= 0) continue;
+        const int pairs = (quads + 1) / 2;
+        const long long per_copy = 16ll * in.n;  // bytes of one pair's region
+        if (per_copy > (long long)s_budget) return false;
+        const int kcap = (int)std::min<long long>({(long long)kMaxPairCopies, (long long)pairs,
+                                                    (long long)s_budget / per_copy});
+        std::vector<int> cls = pl.classes[b];
+        if (cls.empty()) cls.assign(in.C, std::max(1, (in.n + in.C - 1) / in.C));  // estimate
+        int best_k = 1;
+        double best_u = -1.0;
+        for (int k = 1; k <= kcap; ++k) {
+            long long tasks = 0, slots = 0;
+            for (int c : cls) {
+                const long long t = (long long)k * c;
+                tasks += t;
+                slots += (t + threads - 1) / threads * threads;
+            }
+            const double u = slots ? (double)tasks / (double)slots : 0.0;
+            if (u >= best_u - 1e-9) {
+                best_u = u;
+                best_k = k;
+            }
+        }
+        // the instance's pairs in items of as equal a size as best_k allows
+        const int n_it = (pairs + best_k - 1) / best_k, base_k = pairs / n_it, extra = pairs % n_it;
+        for (int j = 0, first = 0; j < n_it; ++j) {
+            const int k = base_k + (j < extra ? 1 : 0);
+            pp->items.push_back(b);
+            pp->items.push_back(2 * first);
+            pp->items.push_back(k);
+            pp->kmax = std::max(pp->kmax, k);
+            s_words = std::max<long long>(s_words, 4ll * in.n * k);
+            first += k;
+        }
+    }
+    const int nm = std::max(pl.n_max, 1);
+    pp->pairs_qw = (int)((s_words + 2ll * nm - 1) / (2ll * nm));
+    pp->lds = batch_paired_lds_bytes(pl.n_max, pl.dk, pl.row_len, pp->pairs_qw, pp->kmax);
+    return pp->lds + 256 <= lds_wg;
+}
 
 size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
@@ -90,7 +161,7 @@ Layout layout_for(const Plan &pl, size_t n_items) {
 }
 
 spv_status enqueue(Ctx *c, const Plan &pl, const Layout &ly, size_t n_items, const Shape &sh,
-                   int sweeps, uint32_t sweep_offset, hipStream_t s) {
+                   int sweeps, uint32_t sweep_offset, hipStream_t s, const PairPlan *pp = nullptr) {
     unsigned char *dev = static_cast<unsigned char *>(c->batch.p);
     hipError_t e = hipMemcpyAsync(dev, c->batch_host, ly.host, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_check(c, e, "batch descriptor upload");
@@ -115,6 +186,12 @@ spv_status enqueue(Ctx *c, const Plan &pl, const Layout &ly, size_t n_items, con
     L.threads = sh.threads;
     L.grid = (int)std::max<size_t>(1, std::min<size_t>(n_items, (size_t)c->num_cus * sh.wgs_per_cu));
     L.sweep_offset = sweep_offset;
+    if (sh.paired && pp) {
+        L.paired = true;
+        L.pairs_qw = pp->pairs_qw;
+        L.kmax = pp->kmax;
+        L.qw = 2;
+    }
     return hip_check(c, launch_batch_sa(L, s), "batch launch");
 }
 
@@ -171,9 +248,15 @@ spv_status sample_batch_inst(spv_ctx *ctx, int32_t B, const Inst *problems, cons
     Plan pl;
     pl.B = B;
     pl.insts.resize(B);
+    pl.classes.resize(B);
     int x_max = 0;
     for (int b = 0; b < B; ++b) {
         const Inst *P = &problems[b];
+        {
+            long long counted = 0;
+            for (int c = 0; c < P->n_colours && c < kMaxColours; ++c) counted += P->class_n[c];
+            if (counted == P->n && P->n > 0) pl.classes[b].assign(P->class_n, P->class_n + P->n_colours);
+        }
         if (reads[b] < 0) return set_err(c, SPV_EINVAL, "reads[%d]=%d", b, reads[b]);
         if (reads[b] > 0 && (!energies[b] || (P->n > 0 && !spins[b])))
             return set_err(c, SPV_EINVAL, "instance %d: NULL output", b);
@@ -222,25 +305,48 @@ spv_status sample_batch_inst(spv_ctx *ctx, int32_t B, const Inst *problems, cons
     if (!c->batch_done && hipEventCreateWithFlags(&c->batch_done, hipEventDisableTiming) != hipSuccess)
         return set_err(c, SPV_EDEVICE, "event create");
 
-    // Shape: explicit, tuned, or default.
+    // Shape: explicit, tuned, or default.  The paired body serves batches whose images
+    // have 4, 6 or 8 records per site on the byte-parallel path.
     const uint32_t flags = opts ? opts->flags : 0u;
+    const bool paired_ok = pl.dk == 4 || pl.dk == 6 || pl.dk == 8;
+    const size_t lds_cu = c->lds_max;  // LDS of one CU (the largest workgroup allocation)
     Shape sh{256, 2, 4};
+    if (paired_ok) sh = Shape{1024, 2, 1, true};
     const std::vector<long long> tkey = {pl.n_max, pl.D_max, pl.nd, B, pl.total_quads / 64};
     bool have = false;
-    if (opts && opts->threads > 0 && opts->quads_per_item > 0) {
-        sh = {opts->threads, opts->quads_per_item, opts->wgs_per_cu > 0 ? opts->wgs_per_cu : 4};
+    if (opts && opts->threads > 0 && (flags & SPV_BATCH_PAIRED)) {
+        if (!paired_ok)
+            return set_err(c, SPV_EINVAL, "the paired body needs byte-parallel images of 4, 6 or 8 records per site");
+        sh = Shape{opts->threads, 2, opts->wgs_per_cu > 0 ? opts->wgs_per_cu : 1, true};
+        have = true;
+    } else if (opts && opts->threads > 0 && opts->quads_per_item > 0) {
+        sh = Shape{opts->threads, opts->quads_per_item, opts->wgs_per_cu > 0 ? opts->wgs_per_cu : 4, false};
         have = true;
     }
     if (!have)
         for (auto &t : c->tuned)
             if (t.key == tkey) {
-                sh = {t.threads, t.qw, t.wgs_per_cu};
+                sh = Shape{t.threads, t.qw, t.wgs_per_cu, t.paired};
                 have = true;
             }
+    // Items, layout and (paired body) per-instance copies of a shape.
+    PairPlan pp;
+    auto items_of = [&](const Shape &x, std::vector<int32_t> *items) -> bool {
+        if (x.paired) {
+            if (!make_pair_items(pl, x.threads, lds_cu / (size_t)x.wgs_per_cu, &pp)) return false;
+            *items = pp.items;
+            return true;
+        }
+        if (batch_lds_bytes(pl.n_max, pl.D_max, pl.row_len, x.qw, pl.nd) + 512 > c->lds_max) return false;
+        *items = make_items(pl, x.qw, x.threads);
+        return true;
+    };
     float tuned_ms = -1.f;
     if (!have && (flags & SPV_BATCH_TUNE)) {
-        static const Shape cand[] = {{64, 2, 16}, {128, 2, 8}, {128, 4, 8}, {256, 1, 4}, {256, 2, 4}, {512, 1, 2}, {512, 2, 2},
-                                     {512, 4, 2}, {1024, 2, 1}, {1024, 4, 1}, {1024, 8, 1}};
+        static const Shape cand[] = {{64, 2, 16},        {128, 2, 8},         {128, 4, 8},         {256, 1, 4},
+                                     {256, 2, 4},        {512, 1, 2},         {512, 2, 2},         {512, 4, 2},
+                                     {1024, 2, 1},       {1024, 4, 1},        {1024, 8, 1},        {1024, 2, 1, true},
+                                     {512, 2, 2, true},  {512, 2, 1, true},   {256, 2, 4, true},   {256, 2, 2, true}};
         const int tsweeps = std::min(sweeps, 24);
         hipEvent_t e0, e1;
         if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
@@ -248,12 +354,13 @@ spv_status sample_batch_inst(spv_ctx *ctx, int32_t B, const Inst *problems, cons
         float best = 1e30f;
         Shape bs = sh;
         for (const Shape &cs : cand) {
-            if (batch_lds_bytes(pl.n_max, pl.D_max, pl.row_len, cs.qw, pl.nd) + 512 > c->lds_max) continue;
-            const std::vector<int32_t> items = make_items(pl, cs.qw, cs.threads);
+            if (cs.paired && !paired_ok) continue;
+            std::vector<int32_t> items;
+            if (!items_of(cs, &items)) continue;
             const Layout ly = layout_for(pl, items.size() / 3);
             if ((st = ensure_batch_buf(c, ly.total)) || (st = stage(c, pl, items, ly))) break;
             (void)hipEventRecord(e0, stream);
-            st = enqueue(c, pl, ly, items.size() / 3, cs, tsweeps, 0, stream);
+            st = enqueue(c, pl, ly, items.size() / 3, cs, tsweeps, 0, stream, &pp);
             (void)hipEventRecord(e1, stream);
             (void)hipEventRecord(c->batch_done, stream);
             if (st) break;
@@ -272,20 +379,25 @@ spv_status sample_batch_inst(spv_ctx *ctx, int32_t B, const Inst *problems, cons
         if (st) return st;
         sh = bs;
         tuned_ms = best;
-        c->tuned.push_back({tkey, sh.threads, sh.qw, sh.wgs_per_cu, best});
+        c->tuned.push_back({tkey, sh.threads, sh.qw, sh.wgs_per_cu, best, sh.paired});
     }
     if (sh.threads < 64 || sh.threads > 1024 || sh.threads % 64 || sh.qw < 1 || sh.qw > sh.threads ||
         sh.wgs_per_cu < 1 || sh.wgs_per_cu > 32)
         return set_err(c, SPV_EINVAL, "batch shape threads=%d quads_per_item=%d wgs_per_cu=%d", sh.threads,
                        sh.qw, sh.wgs_per_cu);
-    if (batch_lds_bytes(pl.n_max, pl.D_max, pl.row_len, sh.qw, pl.nd) + 512 > c->lds_max)
-        return set_err(c, SPV_ECAPACITY, "largest instance (n=%d) needs more LDS than a workgroup has", pl.n_max);
+    std::vector<int32_t> items;
+    if (!items_of(sh, &items)) {
+        if (!sh.paired || have)
+            return set_err(c, SPV_ECAPACITY, "largest instance (n=%d) needs more LDS than a workgroup has", pl.n_max);
+        sh = Shape{256, 2, 4, false};  // default paired shape does not fit: the one-word body
+        if (!items_of(sh, &items))
+            return set_err(c, SPV_ECAPACITY, "largest instance (n=%d) needs more LDS than a workgroup has", pl.n_max);
+    }
     c->last_shape[0] = sh.threads;
-    c->last_shape[1] = sh.qw;
+    c->last_shape[1] = sh.paired ? 0 : sh.qw;
     c->last_shape[2] = sh.wgs_per_cu;
     c->last_tuned_ms = tuned_ms;
 
-    const std::vector<int32_t> items = make_items(pl, sh.qw, sh.threads);
     const size_t n_items = items.size() / 3;
     const Layout ly = layout_for(pl, n_items);
     if ((st = ensure_batch_buf(c, ly.total))) return st;
@@ -293,7 +405,8 @@ spv_status sample_batch_inst(spv_ctx *ctx, int32_t B, const Inst *problems, cons
     if (n_items == 0) return SPV_OK;
     if (flags & SPV_BATCH_GRAPH) {
         const std::vector<long long> key = {B, (long long)n_items, pl.n_max, pl.D_max, pl.nd, pl.row_len,
-                                            sweeps, sh.threads, sh.qw, sh.wgs_per_cu,
+                                            sweeps, sh.threads, sh.qw, sh.wgs_per_cu, sh.paired ? 1 : 0,
+                                            pp.pairs_qw, pp.kmax,
                                             (long long)(uintptr_t)c->batch.p,
                                             (long long)(uintptr_t)c->batch_host,
                                             (long long)(uintptr_t)c->tables.p, (long long)(uintptr_t)stream};
@@ -309,7 +422,7 @@ spv_status sample_batch_inst(spv_ctx *ctx, int32_t B, const Inst *problems, cons
             hipGraph_t graph = nullptr;
             hipError_t e = hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return hip_check(c, e, "begin capture");
-            st = enqueue(c, pl, ly, n_items, sh, sweeps, 0, c->capture_stream);
+            st = enqueue(c, pl, ly, n_items, sh, sweeps, 0, c->capture_stream, &pp);
             e = hipStreamEndCapture(c->capture_stream, &graph);
             if (st) {
                 if (graph) (void)hipGraphDestroy(graph);
@@ -323,7 +436,7 @@ spv_status sample_batch_inst(spv_ctx *ctx, int32_t B, const Inst *problems, cons
         hipError_t e = hipGraphLaunch(exec, stream);
         if (e != hipSuccess) return hip_check(c, e, "graph launch");
     } else {
-        if ((st = enqueue(c, pl, ly, n_items, sh, sweeps, 0, stream))) return st;
+        if ((st = enqueue(c, pl, ly, n_items, sh, sweeps, 0, stream, &pp))) return st;
     }
     return hip_check(c, hipEventRecord(c->batch_done, stream), "event record");
 }

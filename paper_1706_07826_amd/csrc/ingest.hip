@@ -21,6 +21,9 @@ __device__ __forceinline__ unsigned long long umax(unsigned long long a, unsigne
 __global__ __launch_bounds__(256) void ingest_kernel(const IngestDesc *__restrict__ descs,
                                                      IngestResult *__restrict__ res) {
     const IngestDesc P = descs[blockIdx.y];
+    __shared__ int cnt[kMaxColours];
+    if (threadIdx.x < kMaxColours) cnt[threadIdx.x] = 0;
+    __syncthreads();
     unsigned long long bad = ~0ull, xmax = 0ull;
     int dmax = 0;
     const int stride = (int)(gridDim.x * blockDim.x);
@@ -39,6 +42,7 @@ __global__ __launch_bounds__(256) void ingest_kernel(const IngestDesc *__restric
         if (P.check_colours) {
             ci = P.colour[i];
             if (ci >= P.n_colours) bad = umin(bad, row | kChkColourRange);
+            else atomicAdd(&cnt[ci], 1);
         }
         const int hv = P.h ? P.h[i] : 0;  // structure-only ingest reads neither h nor J
         unsigned long long x = (unsigned long long)(hv < 0 ? -(long long)hv : (long long)hv);
@@ -76,12 +80,14 @@ __global__ __launch_bounds__(256) void ingest_kernel(const IngestDesc *__restric
         const int od = __shfl_xor(dmax, d, 64);
         dmax = od > dmax ? od : dmax;
     }
+    IngestResult *R = res + blockIdx.y;
     if ((threadIdx.x & 63) == 0) {
-        IngestResult *R = res + blockIdx.y;
         if (bad != ~0ull) atomicMin(&R->first_bad, bad);
         if (xmax) atomicMax(&R->x_max, xmax);
         if (dmax) atomicMax(&R->max_degree, dmax);
     }
+    __syncthreads();
+    if (threadIdx.x < kMaxColours && cnt[threadIdx.x]) atomicAdd(&R->class_n[threadIdx.x], cnt[threadIdx.x]);
 }
 
 }  // namespace

@@ -32,6 +32,8 @@ struct DevBuf {
 struct Inst : spv_problem {
     int32_t max_degree = 1;  // longest row (1 when no row has an entry)
     int32_t x_bound = 0;     // max_i |h_i| + sum_j |J_ij|
+    int32_t class_n[16] = {};  // variables per colour class when counted at ingest (all 0: unknown;
+                               // reduced problems do not inherit them); launch planning only
 };
 
 // Ingest flags: also check the colour classes (every sampling call needs them);
@@ -108,6 +110,7 @@ struct Ctx {
         std::vector<long long> key;
         int threads, qw, wgs_per_cu;
         float ms;
+        bool paired;
     };
     std::vector<TuneEntry> tuned;
     int last_shape[3] = {0, 0, 0};
@@ -188,6 +191,7 @@ struct IngestResult {
     int32_t max_degree;
     int32_t pad;
     long long pad2;
+    int32_t class_n[16];           // variables per colour class (with the colour check)
 };
 enum IngestCheck : unsigned {
     kChkRowPtrEnds = 0,   // row_ptr[0] != 0 or row_ptr[n] != nnz (row 0: the whole problem)
@@ -301,10 +305,14 @@ struct BatchLaunch {
     int row_len, nd, sweeps, qw, n_max, D_max, grid, threads;
     int dk;  // every image padded to this many records per site (0: per-instance degree)
     uint32_t sweep_offset;
+    bool paired = false;  // paired body (items are instance, first quad, copies of 2 quads)
+    int pairs_qw = 0;     // paired body: spin area of 2 n_max pairs_qw words
+    int kmax = 0;         // paired body: most copies of an item
 };
 // Small instances get up to this many quads per work item (energy accumulators are sized for it).
 constexpr int kBatchMaxItemQuads = 16;
 size_t batch_lds_bytes(int n_max, int D_max, int row_len, int qw, int nd);
+size_t batch_paired_lds_bytes(int n_max, int D_max, int row_len, int pairs_qw, int kmax);
 hipError_t launch_batch_prep(const BatchInst *insts, int B, int n_max, int32_t *images, hipStream_t s);
 hipError_t launch_batch_sa(const BatchLaunch &L, hipStream_t s);
 

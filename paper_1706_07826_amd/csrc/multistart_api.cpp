@@ -96,6 +96,7 @@ Inst level_problem(const Inst &parent, unsigned char *L, const MsLevelOffsets &o
     Inst q = parent;
     q.n = n;
     q.nnz = nnz;
+    for (int k = 0; k < kMaxColours; ++k) q.class_n[k] = 0;  // not counted for the reduced problem
     q.row_ptr = reinterpret_cast<const int32_t *>(L + o.rp);
     q.col = reinterpret_cast<const int32_t *>(L + o.col);
     q.J = reinterpret_cast<const int32_t *>(L + o.J);

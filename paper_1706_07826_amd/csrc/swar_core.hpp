@@ -399,5 +399,153 @@ __device__ void swar_run(const SwarLds &L, const SaItem &a, const int *cs, const
     __syncthreads();
 }
 
+// q = x / d and r = x - q d for 0 <= x < 2^20 and 1 <= d < 2^16: the float quotient
+// through v_rcp_f32 is within 1 of the true one (relative error below 2^-21), so one
+// correction in each direction makes it exact.
+__device__ __forceinline__ void swar_divmod(int x, int d, int &q, int &r) {
+    q = (int)((float)x * __builtin_amdgcn_rcpf((float)d));
+    r = x - q * d;
+    if (r < 0) {
+        --q;
+        r += d;
+    }
+    if (r >= d) {
+        ++q;
+        r -= d;
+    }
+}
+
+// Paired body of the batched launch: `copies` pairs of quad words of one instance.
+// Pair k has its own region of the spin area, S_k [n][2] then ~S_k [n][2] (4n words
+// at k * 4n), and every pair shares the instance's records, whose neighbour addresses
+// are those of region 0 (the lane adds its region's byte offset).  A lane holds one
+// site of one pair, both words (8 replicas, as the two-words-per-lane body), and the
+// lanes of a class pass take (pair, site) tasks pair-major, so small instances fill
+// the workgroup with several pairs.  Pair k's quads are q0 + 2k and q0 + 2k + 1; the
+// counters, tables and update order are the one-instance launch's, so the bits are too.
+template <int DK>
+__device__ void swar_run_pairs(const SwarLds &L, const SaItem &a, const int *cs, int copies) {
+    static_assert(DK > 0, "the paired body unrolls a fixed record count");
+    constexpr int Ds = swar_rec_stride(DK);
+    const int n = a.n, T = blockDim.x, tid = threadIdx.x, q0 = a.q0;
+    const uint32_t region = 4u * (uint32_t)n, inv = 2u * (uint32_t)n;
+    for (int k = tid; k < 2 * kSwarTabWords; k += T) {
+        const int i = k % kSwarTabWords - kSwarTabHalf;
+        L.tab[k] = (i >= 0 && k < kSwarTabWords && i < a.row_len && a.sweeps > 0) ? a.tables[i] : 0xFFFFFFFFu;
+    }
+    for (int k = tid; k < 8 * copies; k += T) L.E2[k] = 0ull;
+    for (int v = tid; v < copies * n; v += T) {
+        int k, p;
+        swar_divmod(v, n, k, p);
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const dev::Words4 w = dev::philox(L.co[p].y, 0u, (uint32_t)(q0 + 2 * k + b), 1u << 24, a.k0, a.k1);
+            uint32_t word = 0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) word |= ((w.w[e] >> 31) ? 0xFFu : 0x00u) << (8 * e);
+            swar_store(L.S, (uint32_t)k * region + 2u * (uint32_t)p + (uint32_t)b, inv, word);
+        }
+    }
+    __syncthreads();
+
+    auto sweep = [&](auto buf, int ls) {
+        constexpr int B = decltype(buf)::value;
+        const uint32_t t = a.sweep_offset + (uint32_t)ls;
+        const char *tz = reinterpret_cast<const char *>(L.tab + B * kSwarTabWords + kSwarTabHalf);
+        if (ls + 1 < a.sweeps) {
+            uint32_t *tnext = L.tab + (1 - B) * kSwarTabWords + kSwarTabHalf;
+            for (int k = tid; k < a.row_len; k += T) tnext[k] = a.tables[(size_t)(ls + 1) * a.row_len + k];
+        }
+        for (int c = 0; c < a.C; ++c) {
+            const int pb = cs[c], cls = cs[c + 1] - pb;
+            if (cls > 0) {
+                // this lane's first task and the step between its tasks, as (pair, site)
+                int k, loc, dk, dl;
+                swar_divmod(tid, cls, k, loc);
+                swar_divmod(T, cls, dk, dl);
+                while (k < copies) {
+                    const int p = pb + loc;
+                    const uint32_t at = (uint32_t)k * region + 2u * (uint32_t)p;
+                    const uint2 sv = *reinterpret_cast<const uint2 *>(L.S + at);
+                    const uint32_t self[2] = {sv.x, sv.y};
+                    uint32_t P[2];
+                    swar_agree<DK, 2>(L.rec + (uint32_t)p * (uint32_t)Ds, 4u * (uint32_t)k * region, DK, P);
+                    const uint2 co = L.co[p];
+                    uint32_t mask[2];
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) {
+                        swar_i16x2 xlo, xhi;  // 4x
+                        swar_x16(P[b], self[b], co.x, &xlo, &xhi);
+                        const dev::Words4 r =
+                            dev::philox(co.y, t, (uint32_t)(q0 + 2 * k + b), 2u << 24, a.k0, a.k1);
+                        const int32_t o[4] = {xlo.x, xlo.y, xhi.x, xhi.y};
+                        uint32_t th[4];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) th[e] = *reinterpret_cast<const uint32_t *>(tz + o[e]);
+                        uint32_t m = 0;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            m |= (uint32_t)((o[e] <= 0) | (r.w[e] < th[e])) * (0xFFu << (8 * e));
+                        mask[b] = m;
+                    }
+                    if (mask[0] | mask[1]) {
+                        const uint2 v = make_uint2(self[0] ^ mask[0], self[1] ^ mask[1]);
+                        *reinterpret_cast<uint2 *>(L.S + at) = v;
+                        *reinterpret_cast<uint2 *>(L.S + at + inv) = make_uint2(~v.x, ~v.y);
+                    }
+                    loc += dl;
+                    k += dk;
+                    if (loc >= cls) {
+                        loc -= cls;
+                        ++k;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    };
+    for (int ls = 0; ls < a.sweeps; ls += 2) {
+        sweep(std::integral_constant<int, 0>{}, ls);
+        if (ls + 1 < a.sweeps) sweep(std::integral_constant<int, 1>{}, ls + 1);
+    }
+
+    // 2E of every replica, sum over sites of s (h + f), one task per (pair, site)
+    for (int v = tid; v < copies * n; v += T) {
+        int k, p;
+        swar_divmod(v, n, k, p);
+        uint32_t P[2];
+        swar_agree<DK, 2>(L.rec + (uint32_t)p * (uint32_t)Ds, 4u * (uint32_t)k * region, DK, P);
+        const long long cp = swar_cp(L.co[p]), hp = L.hpos[p];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const uint32_t self = L.S[(uint32_t)k * region + 2u * (uint32_t)p + (uint32_t)b];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const long long f = cp + 2 * (long long)((P[b] >> (8 * e)) & 0xffu);
+                const long long s = ((self >> (8 * e)) & 0xffu) ? 1 : -1;
+                atomicAdd(&L.E2[(2 * k + b) * 4 + e], (unsigned long long)(s * (hp + f)));
+            }
+        }
+    }
+    __syncthreads();
+    for (int rl = tid; rl < 8 * copies; rl += T) {
+        const int r = 4 * q0 + rl;
+        if (r < a.reads) a.energies[r] = ((long long)L.E2[rl]) / 2;
+    }
+    const int32_t *pos_of = a.image + kImgHeader + n;
+    const unsigned char *Sb = reinterpret_cast<const unsigned char *>(L.S);
+    for (int idx = tid; idx < 8 * copies * n; idx += T) {
+        int rl, i;
+        swar_divmod(idx, n, rl, i);
+        const int r = 4 * q0 + rl;
+        if (r < a.reads) {
+            const int k = rl >> 3, b = (rl >> 2) & 1, e = rl & 3;
+            a.out[(size_t)r * n + i] =
+                Sb[((size_t)k * region + 2 * (size_t)pos_of[i] + (size_t)b) * 4 + (size_t)e] ? 1 : -1;
+        }
+    }
+    __syncthreads();
+}
+
 }  // namespace core
 }  // namespace spv

@@ -62,6 +62,48 @@ def test_batch_every_shape_gives_the_same_bits(spv, ctx, threads, qpi, wpc):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("threads,wpc", [(1024, 1), (512, 1), (256, 4)])
+def test_batch_paired_body_matches_oracle_and_one_word_body(spv, ctx, threads, wpc):
+    """The paired body (a lane holds both quad words of a pair; an item runs k pairs of one
+    instance in separate LDS regions sharing its records) against the oracle and the
+    one-word body, ragged read counts included (odd quad counts leave a half-used pair)."""
+    insts, reads, seeds = _small_batch()
+    betas = si.linear_betas(0.1, 5.0, 50)
+    probs = [spv.Problem.from_instance(i) for i in insts]
+    print(f"[batch] paired body threads={threads} wgs_per_cu={wpc}", flush=True)
+    sp, en = spv.spv_sample_batch(ctx, probs, betas, reads, seeds, threads=threads, wgs_per_cu=wpc, paired=True)
+    assert spv.spv_batch_last_shape(ctx)["quads_per_item"] == 0
+    one_sp, one_en = spv.spv_sample_batch(ctx, probs, betas, reads, seeds, threads=256, quads_per_item=2,
+                                          wgs_per_cu=4)
+    for b, inst in enumerate(insts):
+        osp, oE = oracle.sa_sample(inst, betas, reads=reads[b], seed=seeds[b])
+        assert np.array_equal(sp[b].cpu().numpy(), osp), b
+        assert np.array_equal(en[b].cpu().numpy(), oE), b
+        assert np.array_equal(one_sp[b].cpu().numpy(), osp) and np.array_equal(one_en[b].cpu().numpy(), oE), b
+
+
+def test_batch_paired_body_many_pairs_per_item(spv, ctx):
+    """Small instances with many reads: items of up to 64 pairs (512 replicas) of one instance,
+    sweeps past the table prefetch of both buffers, against the oracle on sampled reads."""
+    insts = [si.random_sparse(n, 2.0, seed=70 + n, j_max=3, h_max=3) for n in (12, 30, 47, 64, 90)]
+    for i in insts:
+        i.colour, i.n_colours = si.greedy_colouring(i)
+    degs = [int(np.diff(i.row_ptr).max()) for i in insts]
+    assert max(degs) in (4, 6, 8), degs  # the paired body needs padded images of 4, 6 or 8 records
+    reads = [1000, 999, 517, 1000, 333]
+    seeds = [40 + b for b in range(len(insts))]
+    betas = si.linear_betas(0.1, 3.0, 33)
+    probs = [spv.Problem.from_instance(i) for i in insts]
+    print("[batch] paired body, many pairs per item", flush=True)
+    sp, en = spv.spv_sample_batch(ctx, probs, betas, reads, seeds, threads=1024, wgs_per_cu=1, paired=True)
+    for b, inst in enumerate(insts):
+        s_b, e_b = sp[b].cpu().numpy(), en[b].cpu().numpy()
+        assert np.array_equal(e_b, oracle.energy(inst, s_b)), b
+        for lo in (0, reads[b] // 2, reads[b] - 9):
+            osp, oE = oracle.sa_sample(inst, betas, seed=seeds[b], r_begin=lo, r_end=lo + 9)
+            assert np.array_equal(s_b[lo:lo + 9], osp) and np.array_equal(e_b[lo:lo + 9], oE), (b, lo)
+
+
 def test_batch_graph_replay_and_tuner(spv, ctx):
     insts, reads, seeds = _small_batch()
     betas = si.linear_betas(0.1, 5.0, 40)

@@ -31,7 +31,7 @@ TOPK = 10
 def build():
     """Compile the oracle (plain C, -O2, no SIMD intrinsics)."""
     tmp = LIB_PATH + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-shared", "-fPIC", "-o", tmp,
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-shared", "-fPIC", "-fopenmp", "-o", tmp,
                            _SRC, "-lm"])
     os.replace(tmp, LIB_PATH)
 
@@ -106,6 +106,8 @@ def lib():
         L.orc_tree_peel.restype = C.c_int
         L.orc_tree_expand.argtypes = [i32, vp, vp, vp, vp, vp, i32, i32, vp, i32, vp]
         L.orc_tree_expand.restype = C.c_int
+        L.orc_set_slot_threads.argtypes = [i32]
+        L.orc_set_slot_threads.restype = None
         for f in (L.orc_sa_sample, L.orc_pt_sample, L.orc_persist_fix, L.orc_ispvar, L.orc_merge_sorted):
             f.restype = C.c_int
         _lib = L
@@ -274,6 +276,12 @@ def sqa_sample(inst, betas, gammas, trotter, reads=None, seed=0, r_begin=0, r_en
         with ThreadPoolExecutor(threads) as ex:
             list(ex.map(lambda q: run(*q), _split(r_begin, r_end, threads)))
     return (spins, E, best, sl, ecl) if slices else (spins, E, best)
+
+
+def set_slot_threads(threads):
+    """Host threads that share one tempering run (slots, cluster-move pairs and top-10 lists of a
+    sweep are independent; the result does not depend on it)."""
+    lib().orc_set_slot_threads(int(threads))
 
 
 def pt_sample(inst, betas, runs, chains, sweeps, seed=0, sweep_offset=0, icm=None, run_begin=0,

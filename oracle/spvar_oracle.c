@@ -147,6 +147,11 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#else
+static int omp_get_thread_num(void) { return 0; }
+#endif
 
 #define ORC_OK 0
 #define ORC_EINVAL (-1)
@@ -733,6 +738,18 @@ int orc_swap_test(int64_t D, double dbeta, int32_t scale_log2, uint32_t k, uint3
  *     only for run_begin: the state after every sweep, for tests)
  * icm_lo..icm_hi: slot window of the cluster moves (needs chains == 2).
  */
+/* Host threads that share one tempering run (1: sequential).  Inside a sweep the
+ * slots' Metropolis sweeps, the cluster moves of the K slot pairs and the top-10
+ * offers of the lists touch disjoint replicas and lists, so spreading them over
+ * threads leaves every replica's own sequence of updates, and so the result,
+ * unchanged; the replica exchange stays sequential. */
+static int32_t g_slot_threads = 1;
+
+void orc_set_slot_threads(int32_t threads)
+{
+    g_slot_threads = threads < 1 ? 1 : threads;
+}
+
 int orc_pt_sample(const orc_problem *P, const double *betas, int32_t K, int32_t runs,
                   int32_t chains, int32_t sweeps, uint64_t seed, uint32_t sweep_offset,
                   int32_t icm_lo, int32_t icm_hi, int32_t run_begin, int32_t run_end,
@@ -740,7 +757,7 @@ int orc_pt_sample(const orc_problem *P, const double *betas, int32_t K, int32_t 
                   int32_t *top_count, int64_t *log_E, int8_t *log_spins)
 {
     int32_t n = P->n, nd, k, run, ch, ls, half = K / 2;
-    int32_t nrep = chains * K;
+    int32_t nrep = chains * K, nth = g_slot_threads;
     uint32_t *mtab = NULL, *stab = NULL;
     int32_t *snd = NULL, *order = NULL, *queue = NULL;
     int8_t *S = NULL, *tmp = NULL;
@@ -766,8 +783,8 @@ int orc_pt_sample(const orc_problem *P, const double *betas, int32_t K, int32_t 
     stab = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)K * 7 * DIGIT_SIZE);
     snd = (int32_t *)malloc(sizeof(int32_t) * (size_t)K);
     order = default_order(P);
-    queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
-    inc = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
+    queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)nth * (n > 0 ? n : 1)); /* one per thread */
+    inc = (uint8_t *)malloc((size_t)nth * (n > 0 ? n : 1));
     S = (int8_t *)malloc((size_t)nrep * (n > 0 ? n : 1));
     tmp = (int8_t *)malloc((size_t)(n > 0 ? n : 1));
     E = (int64_t *)malloc(sizeof(int64_t) * (size_t)nrep);
@@ -805,13 +822,16 @@ int orc_pt_sample(const orc_problem *P, const double *betas, int32_t K, int32_t 
         for (ls = 0; ls < sweeps; ++ls) {
             uint32_t t = sweep_offset + (uint32_t)ls;
             /* 1. Metropolis on every slot. */
-            for (ch = 0; ch < chains; ++ch)
-                for (k = 0; k < K; ++k) {
-                    uint32_t r = (uint32_t)((run * chains + ch) * K + k);
-                    E[ch * K + k] += metropolis_sweep(P, order, S + (size_t)(ch * K + k) * n,
-                                                      mtab + (size_t)k * nd * DIGIT_SIZE, nd, t, r,
-                                                      seed);
+            {
+                int32_t x;
+#pragma omp parallel for num_threads(nth) schedule(static) if (nth > 1)
+                for (x = 0; x < nrep; ++x) {
+                    int32_t xc = x / K, xk = x % K;
+                    uint32_t r = (uint32_t)((run * chains + xc) * K + xk);
+                    E[x] += metropolis_sweep(P, order, S + (size_t)x * n, mtab + (size_t)xk * nd * DIGIT_SIZE, nd,
+                                             t, r, seed);
                 }
+            }
             /* 2. Replica exchange inside each chain. */
             for (ch = 0; ch < chains; ++ch) {
                 uint32_t c = (uint32_t)(run * chains + ch);
@@ -831,16 +851,26 @@ int orc_pt_sample(const orc_problem *P, const double *betas, int32_t K, int32_t 
                 }
             }
             /* 3. Isoenergetic cluster moves between the two chains. */
-            for (k = icm_lo; k < icm_hi; ++k) {
-                uint32_t w = philox_word((uint32_t)k, t, (uint32_t)run, TAG_ICM << 24, seed, 0);
-                icm_move(P, S + (size_t)k * n, S + (size_t)(K + k) * n, &E[k], &E[K + k], w, queue,
-                         inc);
+            {
+                int32_t x;
+#pragma omp parallel for num_threads(nth) schedule(dynamic) if (nth > 1)
+                for (x = icm_lo; x < icm_hi; ++x) {
+                    size_t tid = (size_t)omp_get_thread_num();
+                    uint32_t w = philox_word((uint32_t)x, t, (uint32_t)run, TAG_ICM << 24, seed, 0);
+                    icm_move(P, S + (size_t)x * n, S + (size_t)(K + x) * n, &E[x], &E[K + x], w,
+                             queue + tid * (size_t)n, inc + tid * (size_t)n);
+                }
             }
-            /* 4. Offer the colder half to the top-10 lists. */
-            for (ch = 0; ch < chains; ++ch)
-                for (k = K - half; k < K; ++k)
-                    topk_offer(&lists[ch * half + (k - (K - half))], n, E[ch * K + k],
-                               S + (size_t)(ch * K + k) * n, when++);
+            /* 4. Offer the colder half to the top-10 lists (offer numbers in (chain, slot) order). */
+            {
+                int32_t x;
+#pragma omp parallel for num_threads(nth) schedule(static) if (nth > 1)
+                for (x = 0; x < chains * half; ++x) {
+                    int32_t xc = x / half, xk = K - half + x % half;
+                    topk_offer(&lists[x], n, E[xc * K + xk], S + (size_t)(xc * K + xk) * n, when + x);
+                }
+                when += chains * half;
+            }
             if (log_E && run == run_begin) {
                 memcpy(log_E + (size_t)ls * nrep, E, sizeof(int64_t) * (size_t)nrep);
                 if (log_spins)

@@ -129,3 +129,18 @@ def test_pt_final_energies_and_run_subsets():
     assert np.array_equal(full["final_E"].reshape(-1), _brute.energies(inst, fs))
     S, E = oracle.top_sample(full)
     assert S.shape[0] == int(full["top_count"].sum()) and np.array_equal(E, _brute.energies(inst, S))
+
+
+def test_slot_threads_leave_the_run_unchanged():
+    """Spreading a run's independent slots, cluster-move pairs and top-10 lists over host
+    threads gives the sequential run's bits (final states, energies, top-10 lists)."""
+    inst = si.cubic_lattice(6, "gauss", seed=12, scale_log2=10)
+    betas = si.geometric_betas(0.2, 5.0, 10)
+    seq = oracle.pt_sample(inst, betas, 2, 2, 40, seed=9, icm=(0, 10))
+    oracle.set_slot_threads(4)
+    try:
+        par = oracle.pt_sample(inst, betas, 2, 2, 40, seed=9, icm=(0, 10))
+    finally:
+        oracle.set_slot_threads(1)
+    for key in ("final_spins", "final_E", "top_E", "top_count", "top_spins"):
+        assert np.array_equal(seq[key], par[key]), key

@@ -82,7 +82,7 @@ def lib():
         L.orc_swap_digits.restype = i32
         L.orc_sa_sample.argtypes = [vp, vp, i32, u64, u32, i32, i32, vp, vp, vp, vp]
         L.orc_pt_sample.argtypes = [vp, vp, i32, i32, i32, i32, u64, u32, i32, i32, i32, i32,
-                                    vp, vp, vp, vp, vp, vp, vp]
+                                    vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.orc_persist_fix.argtypes = [vp, vp, vp, i32, f64, f64, i32, vp, vp, vp, vp, vp, vp, vp,
                                       vp, vp]
         L.orc_ispvar.argtypes = [vp, vp, i32, i32, u64, i32, f64, f64, i32, vp, vp, vp]
@@ -285,10 +285,13 @@ def set_slot_threads(threads):
 
 
 def pt_sample(inst, betas, runs, chains, sweeps, seed=0, sweep_offset=0, icm=None, run_begin=0,
-              run_end=None, final=True, top=True, log=False, threads=1):
+              run_end=None, final=True, top=True, log=False, threads=1, resume=None):
     """Runs [run_begin, run_end) of a PT job.  Returns a dict with
     final_spins [runs][chains][K][n], final_E, top_spins [runs][chains][K/2][10][n], top_E,
-    top_count and (log=True, first run only) log_E [sweeps][chains][K], log_spins."""
+    top_count and (log=True, first run only) log_E [sweeps][chains][K], log_spins.
+    resume: a checkpoint for the same run range, a dict whose final_spins (or None) start the
+    slots and whose top_spins/top_E/top_count (all or none) start the lists; pass the earlier
+    call's sweep_offset + sweeps as sweep_offset to continue its random streams."""
     b = _Bound(inst)
     betas = np.ascontiguousarray(betas, dtype=np.float64)
     K = betas.size
@@ -306,6 +309,15 @@ def pt_sample(inst, betas, runs, chains, sweeps, seed=0, sweep_offset=0, icm=Non
     le = np.zeros((sweeps, chains, K), dtype=np.int64) if log else None
     lsp = np.zeros((sweeps, chains, K, n), dtype=np.int8) if log else None
     lo_icm, hi_icm = (0, 0) if icm is None else icm
+    rs = rts = rte = rtc = None
+    if resume is not None:
+        def arr(key, shape, dt):
+            v = resume.get(key)
+            return None if v is None else np.ascontiguousarray(np.asarray(v, dtype=dt).reshape(shape))
+        rs = arr("final_spins", (nr, chains, K, n), np.int8)
+        rts = arr("top_spins", (nr, chains, half, TOPK, n), np.int8)
+        rte = arr("top_E", (nr, chains, half, TOPK), np.int64)
+        rtc = arr("top_count", (nr, chains, half), np.int32)
 
     def run(a, z):
         sl = slice(a - run_begin, z - run_begin)
@@ -316,7 +328,9 @@ def pt_sample(inst, betas, runs, chains, sweeps, seed=0, sweep_offset=0, icm=Non
             _ptr(None if ts is None else ts[sl]), _ptr(None if te is None else te[sl]),
             _ptr(None if tc is None else tc[sl]),
             _ptr(le if (log and a == run_begin) else None),
-            _ptr(lsp if (log and a == run_begin) else None))
+            _ptr(lsp if (log and a == run_begin) else None),
+            _ptr(None if rs is None else rs[sl]), _ptr(None if rts is None else rts[sl]),
+            _ptr(None if rte is None else rte[sl]), _ptr(None if rtc is None else rtc[sl]))
         if rc:
             raise OracleError(rc, "pt_sample")
 

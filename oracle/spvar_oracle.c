@@ -55,6 +55,15 @@
  *    inserted twice; eviction removes the worst, latest-inserted among ties;
  *    output order (E, insertion).
  *
+ *  Tempering checkpoint (continuing a run, Sec. III.D.1): a run resumed from
+ *    the final states and top-10 lists of an earlier call, with sweep_offset
+ *    advanced by that call's sweeps, is the same Markov chain under the same
+ *    counter-based random words as one uninterrupted call: the slots start
+ *    from the given states (a byte > 0 is +1, any other -1; energies are
+ *    recomputed) and each list from its given entries, taken as inserted
+ *    before any offer of the call in their listed order.  A list whose given
+ *    count lies outside 0..10 starts empty and reports count -1.
+ *
  *  Persistence (Algorithm 1): elite = first m = max(1, ceil(eps*R)) rows in
  *    (E, row) order; gauge (Sec. II.C zero-bias handling): classes of
  *    variables whose elite columns are equal up to a global sign, pivot p =
@@ -754,7 +763,9 @@ int orc_pt_sample(const orc_problem *P, const double *betas, int32_t K, int32_t 
                   int32_t chains, int32_t sweeps, uint64_t seed, uint32_t sweep_offset,
                   int32_t icm_lo, int32_t icm_hi, int32_t run_begin, int32_t run_end,
                   int8_t *final_spins, int64_t *final_E, int8_t *top_spins, int64_t *top_E,
-                  int32_t *top_count, int64_t *log_E, int8_t *log_spins)
+                  int32_t *top_count, int64_t *log_E, int8_t *log_spins, const int8_t *resume_spins,
+                  const int8_t *resume_top_spins, const int64_t *resume_top_E,
+                  const int32_t *resume_top_count)
 {
     int32_t n = P->n, nd, k, run, ch, ls, half = K / 2;
     int32_t nrep = chains * K, nth = g_slot_threads;
@@ -764,6 +775,7 @@ int orc_pt_sample(const orc_problem *P, const double *betas, int32_t K, int32_t 
     uint8_t *inc = NULL;
     int64_t *E = NULL;
     topk_list *lists = NULL;
+    uint8_t *bad = NULL; /* per list: its checkpoint count was outside 0..10 */
     int rc = check_problem(P);
     if (rc)
         return rc;
@@ -771,6 +783,9 @@ int orc_pt_sample(const orc_problem *P, const double *betas, int32_t K, int32_t 
         run_end < run_begin)
         return ORC_EINVAL;
     if (icm_hi > icm_lo && (chains != 2 || icm_lo < 0 || icm_hi > K))
+        return ORC_EINVAL;
+    if ((resume_top_count != NULL) != (resume_top_E != NULL) ||
+        (resume_top_count != NULL) != (resume_top_spins != NULL))
         return ORC_EINVAL;
     for (k = 0; k < K; ++k) {
         if (!(betas[k] >= 0.0) || isinf(betas[k]))
@@ -789,7 +804,8 @@ int orc_pt_sample(const orc_problem *P, const double *betas, int32_t K, int32_t 
     tmp = (int8_t *)malloc((size_t)(n > 0 ? n : 1));
     E = (int64_t *)malloc(sizeof(int64_t) * (size_t)nrep);
     lists = (topk_list *)calloc((size_t)chains * (half > 0 ? half : 1), sizeof(topk_list));
-    if (!mtab || !stab || !snd || !order || !queue || !inc || !S || !tmp || !E || !lists) {
+    bad = (uint8_t *)calloc((size_t)chains * (half > 0 ? half : 1), 1);
+    if (!mtab || !stab || !snd || !order || !queue || !inc || !S || !tmp || !E || !lists || !bad) {
         rc = ORC_ENOMEM;
         goto done;
     }
@@ -810,13 +826,36 @@ int orc_pt_sample(const orc_problem *P, const double *betas, int32_t K, int32_t 
     for (run = run_begin; run < run_end; ++run) {
         int32_t lr = run - run_begin;
         int64_t when = 0;
-        for (ch = 0; ch < chains * half; ++ch)
-            lists[ch].count = 0;
+        for (ch = 0; ch < chains * half; ++ch) {
+            topk_list *L = &lists[ch];
+            size_t base = ((size_t)lr * chains * half + ch) * TOPK;
+            int32_t c = resume_top_count ? resume_top_count[(size_t)lr * chains * half + ch] : 0;
+            int32_t e, i;
+            L->count = 0;
+            bad[ch] = c < 0 || c > TOPK;
+            if (bad[ch] || !resume_top_count)
+                continue;
+            /* checkpoint entries count as inserted before this call, in list order */
+            for (e = 0; e < c; ++e) {
+                L->E[e] = resume_top_E[base + e];
+                L->when[e] = (int64_t)e - TOPK;
+                for (i = 0; i < n; ++i)
+                    L->state[(size_t)e * n + i] = resume_top_spins[(base + e) * n + i] > 0 ? 1 : -1;
+            }
+            L->count = c;
+        }
         for (ch = 0; ch < chains; ++ch)
             for (k = 0; k < K; ++k) {
                 uint32_t r = (uint32_t)((run * chains + ch) * K + k);
                 int8_t *s = S + (size_t)(ch * K + k) * n;
-                init_spins(n, r, seed, s);
+                if (resume_spins) {
+                    const int8_t *from = resume_spins + ((size_t)lr * nrep + ch * K + k) * n;
+                    int32_t i;
+                    for (i = 0; i < n; ++i)
+                        s[i] = from[i] > 0 ? 1 : -1;
+                } else {
+                    init_spins(n, r, seed, s);
+                }
                 E[ch * K + k] = orc_energy(P, s);
             }
         for (ls = 0; ls < sweeps; ++ls) {
@@ -910,7 +949,7 @@ int orc_pt_sample(const orc_problem *P, const double *betas, int32_t K, int32_t 
                         memcpy(top_spins + (base + rank) * n, L->state + (size_t)best * n, (size_t)n);
                 }
                 if (top_count)
-                    top_count[(size_t)lr * chains * half + ch] = L->count;
+                    top_count[(size_t)lr * chains * half + ch] = bad[ch] ? -1 : L->count;
             }
         }
     }
@@ -919,6 +958,7 @@ done:
         for (k = 0; k < chains * half; ++k)
             free(lists[k].state);
     free(lists);
+    free(bad);
     free(E);
     free(tmp);
     free(S);

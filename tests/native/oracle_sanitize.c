@@ -325,10 +325,26 @@ static void test_pt_sqa(void)
     for (tt = 1; tt <= 2; ++tt) {
         orc_set_slot_threads(tt);
         CHECK(orc_pt_sample(&g.p, betas, K, runs, chains, sweeps, 3, 0, 0, K, 0, runs, fs, fE, ts, tE, tc, NULL,
-                            NULL) == ORC_OK);
+                            NULL, NULL, NULL, NULL, NULL) == ORC_OK);
         check_energies(&g.p, fs, fE, runs * chains * K);
     }
     orc_set_slot_threads(1);
+    {
+        /* a run stopped after 15 sweeps and resumed from its checkpoint equals the 40-sweep run */
+        int8_t *fs2 = (int8_t *)malloc((size_t)runs * chains * K * n);
+        int8_t *ts2 = (int8_t *)malloc((size_t)runs * chains * half * TOPK * n);
+        int64_t fE2[2 * 2 * 6], tE2[2 * 2 * 3 * TOPK];
+        int32_t tc2[2 * 2 * 3];
+        CHECK(orc_pt_sample(&g.p, betas, K, runs, chains, 15, 3, 0, 0, K, 0, runs, fs2, fE2, ts2, tE2, tc2, NULL,
+                            NULL, NULL, NULL, NULL, NULL) == ORC_OK);
+        CHECK(orc_pt_sample(&g.p, betas, K, runs, chains, sweeps - 15, 3, 15, 0, K, 0, runs, fs2, fE2, ts2, tE2,
+                            tc2, NULL, NULL, fs2, ts2, tE2, tc2) == ORC_OK);
+        CHECK(memcmp(fs, fs2, (size_t)runs * chains * K * n) == 0 && memcmp(fE, fE2, sizeof fE) == 0);
+        CHECK(memcmp(ts, ts2, (size_t)runs * chains * half * TOPK * n) == 0 && memcmp(tE, tE2, sizeof tE) == 0 &&
+              memcmp(tc, tc2, sizeof tc) == 0);
+        free(fs2);
+        free(ts2);
+    }
     {
         const int32_t P = 8, R = 6, sw = 20;
         double b[20], gm[20];

@@ -323,6 +323,28 @@ spv_status spv_ispvar(spv_ctx *ctx, const spv_problem *P, const double *betas, i
  * once; should a workgroup still wait for a neighbour beyond a bounded spin,
  * it stops and writes top_count = -1 for its lists (and spv_top_sample then
  * reports SPV_EINVAL).  SPV_ECAPACITY when no layout fits.
+ *
+ * Checkpoint and resume: the outputs of a call (final_spins and the three
+ * top-10 arrays) are its checkpoint.  A call given them as resume_* with the
+ * same problem, betas, runs, chains, seed and cluster-move slots, and with
+ * sweep_offset advanced by the earlier call's sweeps, continues those runs:
+ * N sweeps then a resumed M sweeps give the bits of one (N + M)-sweep call.
+ *   resume_spins      device [runs][chains][K][n] int8 or NULL (Philox initial
+ *                     state): the slots' starting states; a byte > 0 is +1,
+ *                     any other byte -1; energies are recomputed from them
+ *   resume_top_spins  device [runs][chains][K/2][10][n] int8, resume_top_E
+ *                     [..][10] int64, resume_top_count [runs][chains][K/2]
+ *                     int32: all three or all NULL (empty lists; with n = 0
+ *                     resume_top_spins may be NULL alone).  Entries
+ *                     0..count-1 of a list start it, as inserted before any
+ *                     offer of this call in their listed order (spins read as
+ *                     above; E taken as given, so pass the checkpoint's own
+ *                     energies).  A count outside 0..10 (such as the -1 of an
+ *                     abandoned wait) starts that list empty and its output
+ *                     count is -1 again.
+ * The resume arrays may be the very arrays `out` names (a run continued in
+ * place); any other overlap with the outputs is undefined.  The serving loop's
+ * tempering requests always start fresh.
  */
 typedef struct {
     int32_t K;
@@ -334,6 +356,10 @@ typedef struct {
     uint32_t sweep_offset;
     int32_t icm_lo;
     int32_t icm_hi;
+    const int8_t *resume_spins;
+    const int8_t *resume_top_spins;
+    const int64_t *resume_top_E;
+    const int32_t *resume_top_count;
 } spv_pt_params;
 
 /* Any member may be NULL when not wanted.  All device pointers.

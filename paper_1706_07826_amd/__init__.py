@@ -47,7 +47,9 @@ class spv_fix_out(C.Structure):
 class spv_pt_params(C.Structure):
     _fields_ = [("K", C.c_int32), ("runs", C.c_int32), ("chains", C.c_int32),
                 ("sweeps", C.c_int32), ("betas", C.c_void_p), ("seed", C.c_uint64),
-                ("sweep_offset", C.c_uint32), ("icm_lo", C.c_int32), ("icm_hi", C.c_int32)]
+                ("sweep_offset", C.c_uint32), ("icm_lo", C.c_int32), ("icm_hi", C.c_int32),
+                ("resume_spins", C.c_void_p), ("resume_top_spins", C.c_void_p), ("resume_top_E", C.c_void_p),
+                ("resume_top_count", C.c_void_p)]
 
 
 class spv_batch_opts(C.Structure):
@@ -372,24 +374,49 @@ def spv_ispvar(ctx, P, betas, reads, seed, rounds, elite_frac, threshold, gauge=
 
 
 def spv_pt_sample(ctx, P, betas, runs, chains, sweeps, seed, sweep_offset=0, icm=None, final=True,
-                  top=True, stream=None):
+                  top=True, stream=None, resume=None, in_place=False):
     """Parallel tempering (+ Houdayer moves between chains 0 and 1 at slots icm=(lo, hi)).
     Returns a dict of device tensors: final_spins [runs][chains][K][n], final_E, top_spins
-    [runs][chains][K/2][10][n], top_E, top_count."""
+    [runs][chains][K/2][10][n], top_E, top_count.
+    resume: the dict of an earlier call (its final_spins, or None, start the slots; its
+    top_spins/top_E/top_count, all or none, start the lists) with sweep_offset advanced by that
+    call's sweeps; in_place=True writes the outputs into the resume tensors themselves."""
     b = np.ascontiguousarray(betas, dtype=np.float64)
     K = b.size
     half = K // 2
     dev = ctx.device
     n = P.n
-    res = dict(
-        final_spins=torch.empty((runs, chains, K, n), dtype=torch.int8, device=dev) if final else None,
-        final_E=torch.empty((runs, chains, K), dtype=torch.int64, device=dev) if final else None,
-        top_spins=torch.empty((runs, chains, half, TOPK, n), dtype=torch.int8, device=dev) if top else None,
-        top_E=torch.empty((runs, chains, half, TOPK), dtype=torch.int64, device=dev) if top else None,
-        top_count=torch.empty((runs, chains, half), dtype=torch.int32, device=dev) if top else None)
+    shapes = dict(final_spins=((runs, chains, K, n), torch.int8), final_E=((runs, chains, K), torch.int64),
+                  top_spins=((runs, chains, half, TOPK, n), torch.int8),
+                  top_E=((runs, chains, half, TOPK), torch.int64), top_count=((runs, chains, half), torch.int32))
+    given = {}
+    if resume is not None:
+        for k, (shape, dt) in shapes.items():
+            t = resume.get(k)
+            if t is None:
+                continue
+            if tuple(t.shape) != shape or t.dtype != dt or not t.is_contiguous() or t.device != torch.device(dev):
+                raise ValueError(f"resume[{k!r}] must be a contiguous {dt} tensor of shape {shape} on {dev}")
+            given[k] = t
+    rs = {k: v for k, v in given.items() if k != "final_E"}  # energies are recomputed
+    wanted = dict(final_spins=final, final_E=final, top_spins=top, top_E=top, top_count=top)
+    res = {}
+    for k, (shape, dt) in shapes.items():
+        if not wanted[k]:
+            res[k] = None
+        elif in_place and k in given:
+            res[k] = given[k]
+        else:
+            res[k] = torch.empty(shape, dtype=dt, device=dev)
     lo, hi = (0, 0) if icm is None else icm
+
+    def rp(k):
+        t = rs.get(k)
+        return _ptr(t).value if t is not None and t.numel() else None
+
     params = spv_pt_params(K, runs, chains, sweeps, b.ctypes.data, C.c_uint64(seed & (2**64 - 1)),
-                           int(sweep_offset), int(lo), int(hi))
+                           int(sweep_offset), int(lo), int(hi), rp("final_spins"), rp("top_spins"),
+                           rp("top_E"), rp("top_count"))
     out = spv_pt_out(*[(_ptr(res[k]).value if res[k] is not None and res[k].numel() else None)
                        for k in ("final_spins", "final_E", "top_spins", "top_E", "top_count")])
     ps = P.c_struct()

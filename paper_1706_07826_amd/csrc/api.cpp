@@ -913,6 +913,14 @@ spv_status pt_inst(spv_ctx *ctx, const Inst *P, const spv_pt_params *prm, const 
     if (icm && (chains != 2 || prm->icm_lo < 0 || prm->icm_hi > K))
         return set_err(c, SPV_EINVAL, "cluster moves need chains == 2 and 0 <= icm_lo < icm_hi <= K");
     if ((long long)runs * chains * K >= (1ll << 31)) return set_err(c, SPV_ERANGE, "too many replicas");
+    const bool rs_top = prm->resume_top_count != nullptr;
+    if (rs_top != (prm->resume_top_E != nullptr) || (P->n > 0 && rs_top != (prm->resume_top_spins != nullptr)))
+        return set_err(c, SPV_EINVAL, "resume_top_spins, resume_top_E and resume_top_count: all three or none");
+    PtResume rs;
+    rs.spins = prm->resume_spins;
+    rs.top_spins = prm->resume_top_spins;
+    rs.top_E = prm->resume_top_E;
+    rs.top_count = prm->resume_top_count;
     const int n = P->n, D = P->max_degree > 0 ? P->max_degree : 1;
     const int nd = digits_for(P->x_bound);
     if (nd > 3) return set_err(c, SPV_ERANGE, "x_bound=%d needs %d digits (max 3)", P->x_bound, nd);
@@ -1006,6 +1014,7 @@ spv_status pt_inst(spv_ctx *ctx, const Inst *P, const spv_pt_params *prm, const 
         X.threads = sp.threads;
         X.big = sp.big;
         X.spin_limit = pt_spin_limit();
+        X.resume = rs;
         return hip_check(c, launch_ptx(X, stream), "split pt launch");
     }
     PtLaunch L;
@@ -1031,6 +1040,7 @@ spv_status pt_inst(spv_ctx *ctx, const Inst *P, const spv_pt_params *prm, const 
     L.scratch = sbase;
     L.nqa = nqa;
     L.threads = threads;
+    L.resume = rs;
     return hip_check(c, launch_pt(L, stream), "pt launch");
 }
 

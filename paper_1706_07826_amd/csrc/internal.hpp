@@ -316,6 +316,14 @@ size_t batch_paired_lds_bytes(int n_max, int D_max, int row_len, int pairs_qw, i
 hipError_t launch_batch_prep(const BatchInst *insts, int B, int n_max, int32_t *images, hipStream_t s);
 hipError_t launch_batch_sa(const BatchLaunch &L, hipStream_t s);
 
+// Checkpoint a tempering launch starts from (null members: fresh start).
+struct PtResume {
+    const int8_t *spins = nullptr;      // [runs][chains][K][n]
+    const int8_t *top_spins = nullptr;  // [runs][Ls][10][n]
+    const int64_t *top_E = nullptr;     // [runs][Ls][10]
+    const int32_t *top_count = nullptr; // [runs][Ls]
+};
+
 struct PtLaunch {
     const int32_t *image;
     int n, D, C;
@@ -331,6 +339,7 @@ struct PtLaunch {
     void *scratch;         // top-10 states [runs][chains*(K/2)][10][n]
     int nqa;               // quads per run window
     int threads;
+    PtResume resume;
 };
 size_t pt_lds_bytes(int n, int D, int K, int chains, int row_len, int nqa, int nw_icm);
 hipError_t launch_pt(const PtLaunch &L, hipStream_t s);
@@ -354,6 +363,7 @@ struct PtxLaunch {
     int G, m, threads;
     bool big;
     unsigned spin_limit;
+    PtResume resume;
 };
 struct PtSplit {
     bool use = false, big = false;

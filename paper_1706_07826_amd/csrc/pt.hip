@@ -41,6 +41,7 @@ struct PtArgs {
     long long *top_E;
     int32_t *top_count;
     int8_t *tops;  // [runs][L][10][n], position order
+    PtResume rs;   // checkpoint to start from
     int n, D, C, K, chains, sweeps, row_len, nqa, icm_lo, icm_hi, nw_icm;
     uint32_t sweep_offset, k0, k1;
 };
@@ -55,6 +56,7 @@ struct PtLds {
     long long *LE;     // [L][10]
     int32_t *Lwhen;    // [L][10]
     int32_t *Lcnt;     // [L]
+    int32_t *Lbad;     // [L] checkpoint count was outside 0..10
     int32_t *Lord;     // [L][10]
     int32_t *acc;      // [cK]
     uint32_t *vis;     // [nw_icm][nwords]
@@ -75,7 +77,8 @@ __host__ __device__ inline size_t pt_layout(int n, int D, int K, int chains, int
     const size_t o_nbr = take((size_t)n * D * 4), o_h = take((size_t)n * 4), o_ord = take((size_t)n * 4),
                  o_pos = take((size_t)n * 4), o_tab = take((size_t)K * row_len * 4),
                  o_S = take((size_t)n * nqa * 4), o_E = take((size_t)cK * 8), o_LE = take((size_t)Ls * 80),
-                 o_Lw = take((size_t)Ls * 40), o_Lc = take((size_t)Ls * 4), o_Lo = take((size_t)Ls * 40),
+                 o_Lw = take((size_t)Ls * 40), o_Lc = take((size_t)Ls * 4), o_Lb = take((size_t)Ls * 4),
+                 o_Lo = take((size_t)Ls * 40),
                  o_acc = take((size_t)cK * 4 + 4), o_vis = take((size_t)nw_icm * nwords * 4),
                  o_q = take((size_t)nw_icm * n * 2);
     if (L) {
@@ -90,6 +93,7 @@ __host__ __device__ inline size_t pt_layout(int n, int D, int K, int chains, int
         L->LE = reinterpret_cast<long long *>(base + o_LE);
         L->Lwhen = reinterpret_cast<int32_t *>(base + o_Lw);
         L->Lcnt = reinterpret_cast<int32_t *>(base + o_Lc);
+        L->Lbad = reinterpret_cast<int32_t *>(base + o_Lb);
         L->Lord = reinterpret_cast<int32_t *>(base + o_Lo);
         L->acc = reinterpret_cast<int32_t *>(base + o_acc);
         L->vis = reinterpret_cast<uint32_t *>(base + o_vis);
@@ -125,8 +129,30 @@ __global__ __launch_bounds__(1024) void pt_kernel(PtArgs a) {
     }
     for (int k = tid; k < K * a.row_len; k += T) L.tab[k] = a.mtab[k];
     for (int k = tid; k < cK; k += T) L.E[k] = 0;
-    for (int k = tid; k < Ls; k += T) L.Lcnt[k] = 0;
+    for (int k = tid; k < Ls; k += T) {
+        const int c = a.rs.top_count ? a.rs.top_count[(size_t)run * Ls + k] : 0;
+        const bool bad = c < 0 || c > 10;
+        L.Lcnt[k] = bad ? 0 : c;
+        L.Lbad[k] = bad ? 1 : 0;
+    }
     __syncthreads();
+    if (a.rs.top_count) {
+        // Checkpoint entries, inserted before this launch's offers in list order.
+        for (int le = tid; le < Ls * 10; le += T) {
+            const int li = le / 10, e = le - li * 10;
+            if (e < L.Lcnt[li]) {
+                L.LE[le] = a.rs.top_E[(size_t)run * Ls * 10 + le];
+                L.Lwhen[le] = e - 10;
+            }
+        }
+        for (size_t idx = tid; idx < (size_t)Ls * 10 * n; idx += T) {
+            const int lr = (int)(idx / n), i = (int)(idx - (size_t)lr * n);
+            if (lr % 10 < L.Lcnt[lr / 10]) {
+                const size_t row = (size_t)run * Ls * 10 + lr;
+                a.tops[row * n + L.pos[i]] = a.rs.top_spins[row * n + i] > 0 ? (int8_t)1 : (int8_t)-1;
+            }
+        }
+    }
 
     const int q = tid % nqa, slot_t = tid / nqa, nslots = T / nqa;
     const bool active = slot_t < nslots;
@@ -155,6 +181,17 @@ __global__ __launch_bounds__(1024) void pt_kernel(PtArgs a) {
         L.S[(size_t)p * nqa + q] = word;
     }
     __syncthreads();
+    if (a.rs.spins) {
+        // The run's own replicas start from the checkpoint (a neighbouring run's
+        // bytes of a shared quad keep their Philox values; they are never read back).
+        for (int idx = tid; idx < cK * n; idx += T) {
+            const int l = idx / n, i = idx - l * n;
+            const int r = r0 + l;
+            L.Sb[((size_t)L.pos[i] * nqa + ((r >> 2) - qf)) * 4 + (r & 3)] =
+                a.rs.spins[(size_t)r * n + i] > 0 ? (unsigned char)0x01 : (unsigned char)0xFF;
+        }
+        __syncthreads();
+    }
     {
         long long e2[4] = {0, 0, 0, 0};
         for (int p = slot_t; active && p < n; p += nslots) {
@@ -423,7 +460,7 @@ __global__ __launch_bounds__(1024) void pt_kernel(PtArgs a) {
                     rank += (LE[o] < LE[e] || (LE[o] == LE[e] && LW[o] < LW[e])) ? 1 : 0;
                 L.Lord[li * 10 + rank] = e;
             }
-            if (e == 0 && a.top_count) a.top_count[(size_t)run * Ls + li] = cnt;
+            if (e == 0 && a.top_count) a.top_count[(size_t)run * Ls + li] = L.Lbad[li] ? -1 : cnt;
         }
         __syncthreads();
         if (a.top_E)
@@ -460,6 +497,7 @@ hipError_t launch_pt(const PtLaunch &P, hipStream_t s) {
     a.top_E = reinterpret_cast<long long *>(P.out->top_E);
     a.top_count = P.out->top_count;
     a.tops = static_cast<int8_t *>(P.scratch);
+    a.rs = P.resume;
     a.n = P.n;
     a.D = P.D;
     a.C = P.C;

@@ -53,6 +53,7 @@ struct PtxArgs {
     int32_t *top_count;
     int8_t *tops;          // [runs][Ls][10][n], position order
     uint32_t *xw;          // [runs][G][side 2][buf 2][chains][xmsg] tagged boundary messages
+    PtResume rs;           // checkpoint to start from
     int n, D, C, K, chains, sweeps, row_len, icm_lo, icm_hi, nw_icm, G, m, xmsg;
     uint32_t sweep_offset, k0, k1;
     unsigned spin_limit;
@@ -70,6 +71,7 @@ struct PtxLds {
     long long *LE;      // [chains*m][10]
     int32_t *Lwhen;     // [chains*m][10]
     int32_t *Lcnt;      // [chains*m]
+    int32_t *Lbad;      // [chains*m] checkpoint count was outside 0..10
     int32_t *Lord;      // [chains*m][10]
     int32_t *acc;       // [chains*m]
     int32_t *cin;       // [2*chains] accepted boundary pairs (side, chain)
@@ -96,7 +98,8 @@ __host__ __device__ inline size_t ptx_layout(int n, int D, int m, int chains, in
     const size_t o_nbr = take(in_lds * n * D * 4), o_h = take(in_lds * n * 4), o_ord = take(in_lds * n * 4),
                  o_pos = take(in_lds * n * 4), o_tab = take((size_t)m * row_len * 4), o_S = take((size_t)n * nq * 4),
                  o_E = take((size_t)nl * 8), o_LE = take((size_t)nl * 80), o_Lw = take((size_t)nl * 40),
-                 o_Lc = take((size_t)nl * 4), o_Lo = take((size_t)nl * 40), o_acc = take((size_t)nl * 4),
+                 o_Lc = take((size_t)nl * 4), o_Lb = take((size_t)nl * 4), o_Lo = take((size_t)nl * 40),
+                 o_acc = take((size_t)nl * 4),
                  o_cin = take((size_t)2 * chains * 4), o_par = take((size_t)nw_icm * ((n + 1) & ~1) * 2),
                  o_dm = take((size_t)nw_icm * vstride * 4), o_misc = take(16),
                  o_ub = take(nw_icm ? (size_t)16 * kJoinBuf * 4 : 0), o_uj = take(nw_icm ? (size_t)16 * kJoinBuf : 0);
@@ -112,6 +115,7 @@ __host__ __device__ inline size_t ptx_layout(int n, int D, int m, int chains, in
         L->LE = reinterpret_cast<long long *>(base + o_LE);
         L->Lwhen = reinterpret_cast<int32_t *>(base + o_Lw);
         L->Lcnt = reinterpret_cast<int32_t *>(base + o_Lc);
+        L->Lbad = reinterpret_cast<int32_t *>(base + o_Lb);
         L->Lord = reinterpret_cast<int32_t *>(base + o_Lo);
         L->acc = reinterpret_cast<int32_t *>(base + o_acc);
         L->cin = reinterpret_cast<int32_t *>(base + o_cin);
@@ -157,6 +161,7 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
     auto *const L_LE = Lay.LE;
     auto *const L_Lwhen = Lay.Lwhen;
     auto *const L_Lcnt = Lay.Lcnt;
+    auto *const L_Lbad = Lay.Lbad;
     auto *const L_Lord = Lay.Lord;
     auto *const L_acc = Lay.acc;
     auto *const L_cin = Lay.cin;
@@ -168,7 +173,6 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
     const int tid = threadIdx.x, T = blockDim.x, lane = dev::lane_id(), wid = tid >> 6, nw = T >> 6;
     const int run = blockIdx.x / G, g = blockIdx.x - run * G;
     const int s0 = g * a.m, mg = min(a.m, K - s0), qpc = mg >> 2, nq = chains * qpc, nl = chains * mg;
-    const int half = K / 2, Ls = chains * half;
     const int32_t *img = a.image;
     const uint32_t *gnbr = reinterpret_cast<const uint32_t *>(img + kImgHeader + 3 * n);
     const int32_t *gord = img + kImgHeader, *gpos = img + kImgHeader + n, *ghpos = img + kImgHeader + 2 * n;
@@ -201,11 +205,39 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
         }
     }
     for (int k = tid; k < mg * row_len; k += T) L_tab[k] = a.mtab[(size_t)s0 * row_len + k];
+    const int half = K / 2, Ls = chains * half;
+    // Local slot l = chain * mg + (slot - s0); slots k >= K - half hold list gl.
+    auto list_of = [=](int l) __attribute__((always_inline)) -> int {
+        const int ch = l / mg, k = s0 + (l - ch * mg);
+        return k >= K - half ? ch * half + (k - (K - half)) : -1;
+    };
     for (int k = tid; k < nl; k += T) {
         L_E[k] = 0;
-        L_Lcnt[k] = 0;
+        const int gl = list_of(k);
+        const int c = (gl >= 0 && a.rs.top_count) ? a.rs.top_count[(size_t)run * Ls + gl] : 0;
+        const bool bad = c < 0 || c > 10;
+        L_Lcnt[k] = bad ? 0 : c;
+        L_Lbad[k] = bad ? 1 : 0;
     }
     __syncthreads();
+    if (a.rs.top_count) {
+        // Checkpoint entries, inserted before this launch's offers in list order.
+        for (int le = tid; le < nl * 10; le += T) {
+            const int l = le / 10, e = le - l * 10, gl = list_of(l);
+            if (gl >= 0 && e < L_Lcnt[l]) {
+                L_LE[le] = a.rs.top_E[((size_t)run * Ls + gl) * 10 + e];
+                L_Lwhen[le] = e - 10;
+            }
+        }
+        for (size_t idx = tid; idx < (size_t)nl * 10 * n; idx += T) {
+            const int lr = (int)(idx / n), i = (int)(idx - (size_t)lr * n);
+            const int l = lr / 10, e = lr - l * 10, gl = list_of(l);
+            if (gl >= 0 && e < L_Lcnt[l]) {
+                const size_t row = ((size_t)run * Ls + gl) * 10 + e;
+                a.tops[row * n + POS(i)] = a.rs.top_spins[row * n + i] > 0 ? (int8_t)1 : (int8_t)-1;
+            }
+        }
+    }
 
     const int q = tid % nq, pt = tid / nq, nstr = T / nq;
     const bool active = pt < nstr;
@@ -229,6 +261,16 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
         L_S[(size_t)p * nq + q] = word;
     }
     __syncthreads();
+    if (a.rs.spins) {
+        // The group's replicas start from the checkpoint.
+        for (int idx = tid; idx < nl * n; idx += T) {
+            const int l = idx / n, i = idx - l * n;
+            const int ch = l / mg, slot = s0 + (l - ch * mg);
+            *sbyte(l, POS(i)) =
+                a.rs.spins[(((size_t)run * chains + ch) * K + slot) * n + i] > 0 ? (unsigned char)0x01 : (unsigned char)0xFF;
+        }
+        __syncthreads();
+    }
     {
         long long e2[4] = {0, 0, 0, 0};
         for (int p = pt; active && p < n; p += nstr) {
@@ -718,7 +760,8 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                 for (int o = 0; o < cnt; ++o) rank += (LE[o] < LE[e] || (LE[o] == LE[e] && LW[o] < LW[e])) ? 1 : 0;
                 L_Lord[li * 10 + rank] = e;
             }
-            if (e == 0 && a.top_count) a.top_count[(size_t)run * Ls + ch * half + (k - (K - half))] = cnt;
+            if (e == 0 && a.top_count)
+                a.top_count[(size_t)run * Ls + ch * half + (k - (K - half))] = L_Lbad[l] ? -1 : cnt;
         }
         __syncthreads();
         if (a.top_E)
@@ -787,6 +830,7 @@ hipError_t launch_ptx(const PtxLaunch &P, hipStream_t s) {
     a.top_E = reinterpret_cast<long long *>(P.out->top_E);
     a.top_count = P.out->top_count;
     a.tops = P.tops;
+    a.rs = P.resume;
     a.xw = P.xw;
     a.xmsg = ptx_msg_words(P.n);
     a.n = P.n;

@@ -119,7 +119,7 @@ spv_status launch(Slot &sl, Record &rec) {
             st = spv_persist_fix(x, &r.problem, r.spins, r.energies, r.reads, r.elite_frac, r.threshold,
                                  r.gauge, &r.fix_out, sl.stream);
     } else {
-        spv_pt_params prm;
+        spv_pt_params prm{};  // no checkpoint: serving runs start fresh
         prm.K = r.K;
         prm.runs = r.runs;
         prm.chains = r.chains;

@@ -112,6 +112,23 @@ const char *spv_last_error(const spv_ctx *ctx);
 const char *spv_version(void);
 
 /*
+ * Race detection (debug build of the library with SPV_LDS_SHADOW=1,
+ * libspvar_shadow.so).  The Metropolis class passes of the sampling kernels
+ * (Sec. III.A, one colour class at a time) check, on every pass, that no spin
+ * word is written by two tasks and that no task reads a neighbour word another
+ * task of the pass writes, against a per-workgroup bitmap in LDS (8 KiB of LDS
+ * per workgroup, taken from the planners' limit).  Conflicts are counted, never
+ * trapped.  Waits for the device, then writes counts[0..3]: write-write
+ * conflicts, read-write conflicts, class passes checked, launches whose spin
+ * area exceeded the bitmap (unchecked); reset != 0 clears them.  SPV_EINVAL in
+ * the normal build.  In the debug build only, the environment variable
+ * SPVAR_SHADOW_ALLOW_COLOUR_EDGES lets colourings with an edge inside a class
+ * through ingest (instead of SPV_ECOLOUR), so the detector can be shown the
+ * races such a colouring causes; samples are then not reproducible.
+ */
+spv_status spv_debug_lds_shadow(spv_ctx *ctx, uint64_t counts[4], int32_t reset);
+
+/*
  * Instance ingest on its own (Sec. I: the Ising instance J, h), synchronous
  * (waits for the device first): the validation every sampling call performs,
  * returning SPV_OK or the first violation.  On success the derived bounds are

@@ -14,7 +14,9 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libspvar.so")
+# SPVAR_LIBRARY=shadow loads the race-detection build (libspvar_shadow.so) instead.
+LIB_PATH = os.path.join(_HERE, "libspvar_shadow.so" if os.environ.get("SPVAR_LIBRARY") == "shadow"
+                        else "libspvar.so")
 
 SPV_STATUS = {0: "SPV_OK", -1: "SPV_EINVAL", -2: "SPV_EASYM", -3: "SPV_ECOLOUR", -4: "SPV_ERANGE",
               -5: "SPV_ECAPACITY", -6: "SPV_EBUDGET", -7: "SPV_EDEVICE", -8: "SPV_EAGAIN",
@@ -93,6 +95,7 @@ _vp, _i32, _u32, _u64, _f64 = C.c_void_p, C.c_int32, C.c_uint32, C.c_uint64, C.c
 _P = C.POINTER(spv_problem)
 _SIGS = {
     "spv_version": ([], C.c_char_p),
+    "spv_debug_lds_shadow": ([_vp, _vp, _i32], C.c_int),
     "spv_ctx_create": ([_i32, C.POINTER(_vp)], C.c_int),
     "spv_ctx_destroy": ([_vp], None),
     "spv_last_error": ([_vp], C.c_char_p),
@@ -664,6 +667,14 @@ for _name, (_args, _res) in {
     _f.restype = _res
     _SIGS[_name] = (_args, _res)
 EXPORTED = sorted(_SIGS)
+
+
+def spv_debug_lds_shadow(ctx, reset=False):
+    """Race-detection counts of the debug build (write-write and read-write conflicts, class
+    passes checked, launches not covered) as a dict; SpvError in the normal build."""
+    v = (C.c_uint64 * 4)()
+    ctx.check(_lib.spv_debug_lds_shadow(ctx.handle, v, 1 if reset else 0), "spv_debug_lds_shadow")
+    return dict(write_write=v[0], read_write=v[1], passes=v[2], uncovered=v[3])
 
 
 def _fix_buffers(dev, n, nnz):

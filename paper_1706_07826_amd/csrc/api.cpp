@@ -147,6 +147,10 @@ spv_status ingest(Ctx *c, const spv_problem *P, int B, int flags, hipStream_t s,
         hd[b].nnz = P[b].nnz;
         hd[b].n_colours = P[b].n_colours;
         hd[b].check_colours = (!structure && (flags & kIngestColours)) ? 1 : 0;
+        // race-detection build only: colourings with an edge inside a class may be let
+        // through, so that the detector can be shown to see the races they cause
+        if (kLdsShadow && hd[b].check_colours && std::getenv("SPVAR_SHADOW_ALLOW_COLOUR_EDGES"))
+            hd[b].check_colours = 2;
         std::memset(&hr[b], 0, sizeof hr[b]);
         hr[b].first_bad = ~0ull;
     }
@@ -373,7 +377,21 @@ int sa_wpl_env() {
 
 extern "C" {
 
-const char *spv_version(void) { return "spvar-mi355x 0.1"; }
+const char *spv_version(void) { return kLdsShadow ? "spvar-mi355x 0.1 (LDS race detection)" : "spvar-mi355x 0.1"; }
+
+spv_status spv_debug_lds_shadow(spv_ctx *ctx, uint64_t counts[4], int32_t reset) {
+    if (!ctx || !counts) return SPV_EINVAL;
+    Ctx *c = &ctx->c;
+    if (!kLdsShadow) return set_err(c, SPV_EINVAL, "library built without LDS race detection (SPV_LDS_SHADOW=1)");
+    DeviceGuard g(c->device);
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_check(c, e, "synchronize before reading the race counts");
+    unsigned long long v[4] = {0, 0, 0, 0};
+    if ((e = shadow_stats_sa(v, reset != 0)) != hipSuccess) return hip_check(c, e, "race counts (SA)");
+    if ((e = shadow_stats_batch(v, reset != 0)) != hipSuccess) return hip_check(c, e, "race counts (batch)");
+    for (int k = 0; k < 4; ++k) counts[k] = (uint64_t)v[k];
+    return SPV_OK;
+}
 
 spv_status spv_ctx_create(int32_t device, spv_ctx **out) {
     if (!out) return SPV_EINVAL;
@@ -391,7 +409,7 @@ spv_status spv_ctx_create(int32_t device, spv_ctx **out) {
         return SPV_EDEVICE;
     }
     x->c.num_cus = cus;
-    x->c.lds_max = (size_t)lds;
+    x->c.lds_max = (size_t)lds - kShadowLdsBytes;
     // Set-up of the allocation-free persistence: this device's scratch address.
     void *na = nullptr;
     if (noalloc_scratch(device, &na) != hipSuccess) {

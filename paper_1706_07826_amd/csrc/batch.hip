@@ -297,4 +297,6 @@ hipError_t launch_batch_sa(const BatchLaunch &L, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t shadow_stats_batch(unsigned long long *out, bool reset) { return shadow::read_stats(out, reset); }
+
 }  // namespace spv

@@ -59,7 +59,7 @@ __global__ __launch_bounds__(256) void ingest_kernel(const IngestDesc *__restric
             const int Jk = P.J ? P.J[k] : 0;
             if (Jk > 32767 || Jk < -32767) bad = umin(bad, row | kChkJRange);
             x += (unsigned long long)(Jk < 0 ? -(long long)Jk : (long long)Jk);
-            if (P.check_colours && P.colour[j] == ci) bad = umin(bad, row | kChkColourEdge);
+            if (P.check_colours == 1 && P.colour[j] == ci) bad = umin(bad, row | kChkColourEdge);
             // the transposed entry, by bisection over row j (an out-of-order row j is
             // that row's own failure)
             const int ja = P.row_ptr[j], jb = P.row_ptr[j + 1];

@@ -183,7 +183,8 @@ struct IngestDesc {
     const int32_t *J;
     const int32_t *h;
     const uint8_t *colour;
-    int32_t n, nnz, n_colours, check_colours;
+    int32_t n, nnz, n_colours;
+    int32_t check_colours;  // 0: none, 1: range and independence, 2: range only (race-detection runs)
 };
 struct IngestResult {
     unsigned long long first_bad;  // (row + 1) << 8 | check of the first failure; ~0 when valid
@@ -315,6 +316,19 @@ size_t batch_lds_bytes(int n_max, int D_max, int row_len, int qw, int nd);
 size_t batch_paired_lds_bytes(int n_max, int D_max, int row_len, int pairs_qw, int kmax);
 hipError_t launch_batch_prep(const BatchInst *insts, int B, int n_max, int32_t *images, hipStream_t s);
 hipError_t launch_batch_sa(const BatchLaunch &L, hipStream_t s);
+
+// Race-detection build (SPV_LDS_SHADOW=1): the Metropolis class passes of the SA
+// bodies check their LDS accesses against a bitmap that takes this much static LDS
+// from every workgroup (so the planners' LDS limit is lowered by it).
+#ifndef SPV_LDS_SHADOW
+#define SPV_LDS_SHADOW 0
+#endif
+constexpr bool kLdsShadow = SPV_LDS_SHADOW != 0;
+constexpr size_t kShadowLdsBytes = kLdsShadow ? 8192 : 0;
+// Adds the counts of the unit's instrumented kernels to out[4] (write-write,
+// read-write, passes checked, launches not covered); no-ops in the normal build.
+hipError_t shadow_stats_sa(unsigned long long *out, bool reset);
+hipError_t shadow_stats_batch(unsigned long long *out, bool reset);
 
 // Checkpoint a tempering launch starts from (null members: fresh start).
 struct PtResume {

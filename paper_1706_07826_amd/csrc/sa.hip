@@ -564,4 +564,6 @@ hipError_t launch_energy(const int32_t *image, int n, int D, const int8_t *spins
     return hipGetLastError();
 }
 
+hipError_t shadow_stats_sa(unsigned long long *out, bool reset) { return shadow::read_stats(out, reset); }
+
 }  // namespace spv

@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
+#include "lds_shadow.hpp"
 #include "internal.hpp"
 
 namespace spv {
@@ -218,6 +219,25 @@ __device__ void sa_run(const SaLds &L, const SaItem &a, const int *cs) {
         }
     }
     __syncthreads();
+    const shadow::Pass sh = shadow::begin((uint32_t)n * (uint32_t)qw);
+    // Debug build: the class pass's writes, then its neighbour reads, against the bitmap.
+    auto shadow_pass = [&](int c, bool before) {
+        const int pe = cs[c + 1];
+        if (before) {
+            for (int p = cs[c] + slot; active && p < pe; p += nslots) shadow::mark(sh, (uint32_t)(p * qw + q));
+            shadow::barrier();
+            for (int p = cs[c] + slot; active && p < pe; p += nslots)
+                for (int k = 0; k < D; ++k) {
+                    const uint32_t r = L.nbr[(size_t)p * rec_p + (size_t)k * rec_k];
+                    if ((r & 0xffffu) == 0u) continue;  // padding or J = 0: the value read is unused
+                    shadow::check(sh, (r >> 16) * (uint32_t)qw + (uint32_t)q);
+                }
+            shadow::count_pass(sh);
+        } else {
+            for (int p = cs[c] + slot; active && p < pe; p += nslots) shadow::unmark(sh, (uint32_t)(p * qw + q));
+            shadow::barrier();
+        }
+    };
 
     for (int ls = 0; ls < a.sweeps; ++ls) {
         const uint32_t t = a.sweep_offset + (uint32_t)ls;
@@ -227,6 +247,7 @@ __device__ void sa_run(const SaLds &L, const SaItem &a, const int *cs) {
             for (int k = tid; k < a.row_len; k += T)
                 tnext[k] = a.tables[(size_t)(ls + 1) * a.row_len + k];
         for (int c = 0; c < a.C; ++c) {
+            if constexpr (shadow::kOn) shadow_pass(c, true);
             const int pe = cs[c + 1];
             for (int p = cs[c] + slot; active && p < pe; p += nslots) {
                 const uint32_t self = L.S[(size_t)p * qw + q];
@@ -239,6 +260,7 @@ __device__ void sa_run(const SaLds &L, const SaItem &a, const int *cs) {
                 if (mask) L.S[(size_t)p * qw + q] = self ^ mask;
             }
             __syncthreads();
+            if constexpr (shadow::kOn) shadow_pass(c, false);
         }
     }
 

@@ -18,6 +18,7 @@
 
 #include "device.hpp"
 #include "internal.hpp"
+#include "lds_shadow.hpp"
 #include "sa_core.hpp"
 
 namespace spv {
@@ -296,6 +297,30 @@ __device__ void swar_run(const SwarLds &L, const SaItem &a, const int *cs, const
         }
     }
     __syncthreads();
+    const shadow::Pass sh = shadow::begin(inv);
+    const uint32_t s_addr = swar_lds_addr(L.S);
+    // Debug build: the class pass's writes, then its neighbour reads, against the bitmap.
+    auto shadow_pass = [&](int c, bool before) {
+        const int pe = cs[c + 1];
+        if (before) {
+            for (int p = cs[c] + slot; active && p < pe; p += nslots)
+                for (int b = 0; b < W; ++b) shadow::mark(sh, (uint32_t)p * (uint32_t)qw + (uint32_t)(qa + b));
+            shadow::barrier();
+            for (int p = cs[c] + slot; active && p < pe; p += nslots)
+                for (int k = 0; k < (DK > 0 ? DK : D); ++k) {
+                    const uint2 r = L.rec[(uint32_t)p * (uint32_t)Ds + (uint32_t)k];
+                    if (r.y == 0u) continue;  // padding or J = 0: the value read is unused
+                    uint32_t w = (r.x + qb - s_addr) >> 2;
+                    if (w >= inv) w -= inv;
+                    for (int b = 0; b < W; ++b) shadow::check(sh, w + (uint32_t)b);
+                }
+            shadow::count_pass(sh);
+        } else {
+            for (int p = cs[c] + slot; active && p < pe; p += nslots)
+                for (int b = 0; b < W; ++b) shadow::unmark(sh, (uint32_t)p * (uint32_t)qw + (uint32_t)(qa + b));
+            shadow::barrier();
+        }
+    };
 
     // One sweep reading table buffer B (a compile-time constant) and filling the other.
     auto sweep = [&](auto buf, int ls) {
@@ -307,6 +332,7 @@ __device__ void swar_run(const SwarLds &L, const SaItem &a, const int *cs, const
             for (int k = tid; k < a.row_len; k += T) tnext[k] = a.tables[(size_t)(ls + 1) * a.row_len + k];
         }
         for (int c = 0; c < a.C; ++c) {
+            if constexpr (shadow::kOn) shadow_pass(c, true);
             const int pe = cs[c + 1];
             for (int p = cs[c] + slot; active && p < pe; p += nslots) {
                 const uint32_t at = (uint32_t)p * (uint32_t)qw + (uint32_t)qa;
@@ -349,6 +375,7 @@ __device__ void swar_run(const SwarLds &L, const SaItem &a, const int *cs, const
                 }
             }
             __syncthreads();
+            if constexpr (shadow::kOn) shadow_pass(c, false);
         }
     };
     for (int ls = ls0; ls < lsend; ls += 2) {
@@ -447,6 +474,33 @@ __device__ void swar_run_pairs(const SwarLds &L, const SaItem &a, const int *cs,
         }
     }
     __syncthreads();
+    // Debug build: bit of S word w of pair k is k * 2n + w.
+    const shadow::Pass sh = shadow::begin((uint32_t)copies * inv);
+    const uint32_t s_addr = swar_lds_addr(L.S);
+    auto shadow_pass = [&](int pb, int cls, bool before) {
+        if (before) {
+            for (int v = tid; v < copies * cls; v += T)
+                for (int b = 0; b < 2; ++b)
+                    shadow::mark(sh, (uint32_t)(v / cls) * inv + 2u * (uint32_t)(pb + v % cls) + (uint32_t)b);
+            shadow::barrier();
+            for (int v = tid; v < copies * cls; v += T) {
+                const int k = v / cls, p = pb + v % cls;
+                for (int j = 0; j < DK; ++j) {
+                    const uint2 r = L.rec[(uint32_t)p * (uint32_t)Ds + (uint32_t)j];
+                    if (r.y == 0u) continue;  // padding or J = 0: the value read is unused
+                    uint32_t w = (r.x - s_addr) >> 2;  // region 0 address
+                    if (w >= inv) w -= inv;
+                    for (int b = 0; b < 2; ++b) shadow::check(sh, (uint32_t)k * inv + w + (uint32_t)b);
+                }
+            }
+            shadow::count_pass(sh);
+        } else {
+            for (int v = tid; v < copies * cls; v += T)
+                for (int b = 0; b < 2; ++b)
+                    shadow::unmark(sh, (uint32_t)(v / cls) * inv + 2u * (uint32_t)(pb + v % cls) + (uint32_t)b);
+            shadow::barrier();
+        }
+    };
 
     auto sweep = [&](auto buf, int ls) {
         constexpr int B = decltype(buf)::value;
@@ -458,6 +512,7 @@ __device__ void swar_run_pairs(const SwarLds &L, const SaItem &a, const int *cs,
         }
         for (int c = 0; c < a.C; ++c) {
             const int pb = cs[c], cls = cs[c + 1] - pb;
+            if constexpr (shadow::kOn) shadow_pass(pb, cls, true);
             if (cls > 0) {
                 // this lane's first task and the step between its tasks, as (pair, site)
                 int k, loc, dk, dl;
@@ -502,6 +557,7 @@ __device__ void swar_run_pairs(const SwarLds &L, const SaItem &a, const int *cs,
                 }
             }
             __syncthreads();
+            if constexpr (shadow::kOn) shadow_pass(pb, cls, false);
         }
     };
     for (int ls = 0; ls < a.sweeps; ls += 2) {

@@ -76,6 +76,7 @@ int main() {
     CHECK(spv_persist_fix_noalloc(nullptr, &P, nullptr, nullptr, 1, 0.1, 1.0, 0, nullptr, nullptr) == SPV_EINVAL);
     CHECK(spv_multistart(nullptr, &P, nullptr, nullptr, nullptr) == SPV_EINVAL);
     CHECK(spv_server_create(nullptr, nullptr, nullptr) == SPV_EINVAL);
+    CHECK(spv_debug_lds_shadow(nullptr, nullptr, 0) == SPV_EINVAL);
     if (failures) {
         std::fprintf(stderr, "%d checks failed\n", failures);
         return 1;

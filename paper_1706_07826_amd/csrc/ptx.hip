@@ -487,6 +487,27 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
             auto dis = [=](int j, int p) __attribute__((always_inline)) -> bool {
                 return pa[j][(size_t)p * pstride] != pb[j][(size_t)p * pstride];
             };
+            // The batch's disagreements at position p as bits (bit j: pair j).  When its
+            // pairs lie in one quad word per chain, one XOR of the two words gives them all
+            // (a byte is 0xFE where the replicas differ and 0 where they agree).
+            const int la0 = kq - s0, qa0 = la0 >> 2, off0 = la0 & 3;
+            const bool word_dis = off0 + nb <= 4;
+            const uint32_t pmask = (1u << nb) - 1u;
+            auto dis_bits = [=](int p) __attribute__((always_inline)) -> uint32_t {
+                if (word_dis) {
+                    const uint32_t x =
+                        (L_S[(size_t)p * nq + qa0] ^ L_S[(size_t)p * nq + qpc + qa0]) >> (8 * off0);
+                    uint32_t m = (x >> 1) & 0x01010101u;
+                    m |= m >> 7;
+                    m |= m >> 14;
+                    return m & pmask;
+                }
+                uint32_t m = 0;
+#pragma unroll
+                for (int j = 0; j < kIcmBatch; ++j)
+                    if (j < nb && dis(j, p)) m |= 1u << j;
+                return m;
+            };
             // disagreement masks in variable-index order, 64 variables per chunk
             for (int c0 = wid; c0 < nchunks; c0 += 4 * nw) {
                 int pp[4];
@@ -495,12 +516,15 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                     const int i = (c0 + u * nw) * 64 + lane;
                     pp[u] = (c0 + u * nw < nchunks && i < n) ? POS(i) : -1;
                 }
+                uint32_t db[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) db[u] = pp[u] >= 0 ? dis_bits(pp[u]) : 0u;
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
 #pragma unroll
                     for (int j = 0; j < kIcmBatch; ++j) {
                         if (j >= nb) break;
-                        const unsigned long long m = __ballot(pp[u] >= 0 && dis(j, pp[u]));
+                        const unsigned long long m = __ballot((db[u] >> j) & 1u);
                         if (lane == 0 && c0 + u * nw < nchunks) L_dmask[(size_t)j * nchunks + c0 + u * nw] = m;
                     }
             }
@@ -569,24 +593,28 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                 };
                 for (int p0 = wid * 64; p0 < n; p0 += nw * 64) {
                     const int p = p0 + lane;
-                    unsigned dp = 0;
-#pragma unroll
-                    for (int j = 0; j < kIcmBatch; ++j)
-                        if (j < nb && p < n && dis(j, p)) dp |= 1u << j;
+                    const uint32_t dp = p < n ? dis_bits(p) : 0u;
                     for (int k0 = 0; k0 < D; k0 += ptc::kRecBatch) {
                         uint32_t rr[ptc::kRecBatch];
 #pragma unroll
                         for (int uu = 0; uu < ptc::kRecBatch; ++uu)
                             rr[uu] = (dp && k0 + uu < D) ? NBR(k0 + uu, p) : 0u;
+                        // the pairs each edge joins, every neighbour's words read before the joins
+                        uint32_t fb[ptc::kRecBatch];
+#pragma unroll
+                        for (int uu = 0; uu < ptc::kRecBatch; ++uu) {
+                            const int u = (int)(rr[uu] >> 16);
+                            const bool edge_ok = k0 + uu < D && (rr[uu] & 0xffffu) != 0u && u > p;
+                            fb[uu] = edge_ok ? (dp & dis_bits(u)) : 0u;
+                        }
 #pragma unroll
                         for (int uu = 0; uu < ptc::kRecBatch; ++uu) {
                             if (k0 + uu >= D) break;
                             const int u = (int)(rr[uu] >> 16);
-                            const bool edge_ok = (rr[uu] & 0xffffu) != 0u && u > p;
 #pragma unroll
                             for (int j = 0; j < kIcmBatch; ++j) {
                                 if (j >= nb) break;
-                                const bool f = edge_ok && ((dp >> j) & 1u) && dis(j, u);
+                                const bool f = (fb[uu] >> j) & 1u;
                                 const unsigned long long msk = __ballot(f);
                                 if (f) {
                                     const int at = cnt + __popcll(msk & lanemask_lt());
@@ -617,9 +645,11 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
             for (int j = 0; j < kIcmBatch; ++j) dA[j] = dB[j] = 0;
             for (int p = tid; p < n; p += T) {
                 unsigned in = 0;
+                const uint32_t dpb = dis_bits(p);
 #pragma unroll
                 for (int j = 0; j < kIcmBatch; ++j)
-                    if (root[j] != 0xffffffffu && dis(j, p) && ptc::uf_find(L_parent + (size_t)j * n16, (uint32_t)p) == root[j])
+                    if (root[j] != 0xffffffffu && ((dpb >> j) & 1u) &&
+                        ptc::uf_find(L_parent + (size_t)j * n16, (uint32_t)p) == root[j])
                         in |= 1u << j;
                 if (!in) continue;
                 const int32_t hp = HPOS(p);

@@ -493,6 +493,27 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
             const int la0 = kq - s0, qa0 = la0 >> 2, off0 = la0 & 3;
             const bool word_dis = off0 + nb <= 4;
             const uint32_t pmask = (1u << nb) - 1u;
+            // Chain 0's spin bytes of the batch's pairs at position p (byte j: pair j) and
+            // their disagreement bits.
+            auto pair_bytes = [=](int p, uint32_t &wa, uint32_t &db) __attribute__((always_inline)) {
+                if (word_dis) {
+                    const uint32_t w0 = L_S[(size_t)p * nq + qa0], w1 = L_S[(size_t)p * nq + qpc + qa0];
+                    wa = w0 >> (8 * off0);
+                    uint32_t m = (((w0 ^ w1) >> (8 * off0)) >> 1) & 0x01010101u;
+                    m |= m >> 7;
+                    m |= m >> 14;
+                    db = m & pmask;
+                    return;
+                }
+                wa = 0;
+                db = 0;
+#pragma unroll
+                for (int j = 0; j < kIcmBatch; ++j) {
+                    const unsigned char x = pa[j][(size_t)p * pstride], y = pb[j][(size_t)p * pstride];
+                    wa |= (uint32_t)x << (8 * j);
+                    if (j < nb && x != y) db |= 1u << j;
+                }
+            };
             auto dis_bits = [=](int p) __attribute__((always_inline)) -> uint32_t {
                 if (word_dis) {
                     const uint32_t x =
@@ -640,9 +661,9 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                 const int sp = j < nb ? L_misc[j] : -1;
                 root[j] = sp >= 0 ? ptc::uf_find(L_parent + (size_t)j * n16, (uint32_t)sp) : 0xffffffffu;
             }
-            long long dA[kIcmBatch], dB[kIcmBatch];
+            long long dA[kIcmBatch];
 #pragma unroll
-            for (int j = 0; j < kIcmBatch; ++j) dA[j] = dB[j] = 0;
+            for (int j = 0; j < kIcmBatch; ++j) dA[j] = 0;
             for (int p = tid; p < n; p += T) {
                 unsigned in = 0;
                 const uint32_t dpb = dis_bits(p);
@@ -652,43 +673,44 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                         ptc::uf_find(L_parent + (size_t)j * n16, (uint32_t)p) == root[j])
                         in |= 1u << j;
                 if (!in) continue;
+                // f = h + sum of J s over the neighbours that agree (those outside the
+                // cluster); replica B's field is the same (it agrees with A there) and its
+                // spin at p is -s_A, so its energy change is -dA: the pair energy is
+                // conserved exactly
                 const int32_t hp = HPOS(p);
-                int32_t fA[kIcmBatch], fB[kIcmBatch];
+                int32_t fA[kIcmBatch];
 #pragma unroll
-                for (int j = 0; j < kIcmBatch; ++j) fA[j] = fB[j] = hp;
+                for (int j = 0; j < kIcmBatch; ++j) fA[j] = hp;
                 for (int k0 = 0; k0 < D; k0 += ptc::kRecBatch) {
                     uint32_t rr[ptc::kRecBatch];
 #pragma unroll
                     for (int uu = 0; uu < ptc::kRecBatch; ++uu) rr[uu] = k0 + uu < D ? NBR(k0 + uu, p) : 0u;
+                    uint32_t wa[ptc::kRecBatch], db[ptc::kRecBatch];
+#pragma unroll
+                    for (int uu = 0; uu < ptc::kRecBatch; ++uu) pair_bytes((int)(rr[uu] >> 16), wa[uu], db[uu]);
 #pragma unroll
                     for (int uu = 0; uu < ptc::kRecBatch; ++uu) {
-                        const int u = (int)(rr[uu] >> 16);
                         const int32_t Jv = (int32_t)(int16_t)(rr[uu] & 0xffffu);
-                        if (Jv == 0) continue;
+                        if (k0 + uu >= D || Jv == 0) continue;
 #pragma unroll
-                        for (int j = 0; j < kIcmBatch; ++j) {
-                            if (!((in >> j) & 1u)) continue;
-                            const int au = (int)(int8_t)pa[j][(size_t)u * pstride];
-                            const int bu = (int)(int8_t)pb[j][(size_t)u * pstride];
-                            if (au == bu) {
-                                fA[j] += Jv * au;
-                                fB[j] += Jv * bu;
-                            }
-                        }
+                        for (int j = 0; j < kIcmBatch; ++j)
+                            if (((in >> j) & 1u) && !((db[uu] >> j) & 1u))
+                                fA[j] += Jv * (int32_t)(int8_t)(wa[uu] >> (8 * j));
                     }
                 }
+                uint32_t wp, dbp;
+                pair_bytes(p, wp, dbp);
 #pragma unroll
                 for (int j = 0; j < kIcmBatch; ++j)
                     if ((in >> j) & 1u) {
                         atomicOr(&memb[(size_t)j * vstr + (p >> 5)], 1u << (p & 31));
-                        dA[j] += -2ll * (int)(int8_t)pa[j][(size_t)p * pstride] * (long long)fA[j];
-                        dB[j] += -2ll * (int)(int8_t)pb[j][(size_t)p * pstride] * (long long)fB[j];
+                        dA[j] += -2ll * (int32_t)(int8_t)(wp >> (8 * j)) * (long long)fA[j];
                     }
             }
 #pragma unroll
             for (int j = 0; j < kIcmBatch; ++j) {
                 if (j >= nb) break;
-                const long long sa = wave_sum(dA[j]), sb = wave_sum(dB[j]);
+                const long long sa = wave_sum(dA[j]), sb = -sa;
                 const int la = kq + j - s0, lb = mg + la;
                 if (lane == 0) {
                     if (sa) atomicAdd(reinterpret_cast<unsigned long long *>(&L_E[la]), (unsigned long long)sa);

@@ -40,6 +40,11 @@ CASES = [
     ("zero_sweeps_G2", lambda: si.chimera(2, seed=7), 8, 2, 1, 0, None, 2, 0, 0),
     ("one_sweep_G2", lambda: si.chimera(2, seed=8), 8, 2, 1, 1, None, 2, 0, 1),
     ("K4_G1_forced_split", lambda: si.chimera(2, seed=9), 4, 3, 2, 40, (0, 4), 1, 0, 0),
+    # 8 slots per group with the cluster moves from slot 1: a batch of pairs spans two quad words
+    ("sparse40_K16_G2_icm_straddling_batch", lambda: si.random_sparse(40, 3.0, seed=12), 16, 2, 2, 60, (1, 15), 2,
+     0, 0),
+    ("cubic4_K16_G2_icm_straddling_batch_big", lambda: si.cubic_lattice(4, "gauss", seed=13, scale_log2=10), 16, 1,
+     2, 45, (3, 14), 2, 1, 0),
     # many waves per workgroup on the cluster moves (1024 threads)
     ("cubic10_K8_G2_icm_wide", lambda: si.cubic_lattice(10, "gauss", seed=10, scale_log2=10), 8, 2, 2, 30,
      (0, 8), 2, 0, 0),

@@ -43,6 +43,8 @@ CASES = [
     # 8 slots per group with the cluster moves from slot 1: a batch of pairs spans two quad words
     ("sparse40_K16_G2_icm_straddling_batch", lambda: si.random_sparse(40, 3.0, seed=12), 16, 2, 2, 60, (1, 15), 2,
      0, 0),
+    # n not a multiple of 4: the top-10 states copied and compared byte by byte
+    ("sparse42_K8_G2_icm_ragged_n", lambda: si.random_sparse(42, 3.0, seed=14), 8, 2, 2, 70, (0, 8), 2, 0, 0),
     ("cubic4_K16_G2_icm_straddling_batch_big", lambda: si.cubic_lattice(4, "gauss", seed=13, scale_log2=10), 16, 1,
      2, 45, (3, 14), 2, 1, 0),
     # many waves per workgroup on the cluster moves (1024 threads)

@@ -150,21 +150,31 @@ __global__ __launch_bounds__(1024) void sa_kernel(core::SaItem a) {
 // sweeps) tasks from a counter in chunk-major order, so that the replicas are
 // spread over the whole device however their count divides into workgroups.  A
 // group's spin words pass from one chunk to the next through global memory as
-// self-validating 64-bit words {spins, tag}, stored and polled with relaxed
+// self-validating 32-bit words {tag, spins}, stored and polled with relaxed
 // device-scope atomics (tag = chunks done, plus an abandoned-wait bit; the
 // words are cleared before every launch), so no cache-wide fence is needed.  A
-// task polls (bounded) until every word of its group carries the previous
-// chunk's tag.  Every task uses the same counters as the one-launch schedule,
-// so the sample is bit-identical.
+// spin byte of the byte-parallel body is a mask (0xFF or 0), so a word carries 4
+// spin words as 4-bit nibbles under a 16-bit tag.  A task polls (bounded) until
+// every word of its group carries the previous chunk's tag.  Every task uses the
+// same counters as the one-launch schedule, so the sample is bit-identical.
 struct StreamArgs {
     core::SaItem a;
     int G, K, Lc;    // groups, chunks per group, sweeps per chunk
     int *counter;
-    unsigned long long *state;  // [G][n][qw] {spin word, tag}
+    uint32_t *state;  // [G][ceil(n qw / 4)] {tag << 16, 4 spin words as nibbles}
     int spin_limit;
 };
 
-constexpr uint32_t kTagPoison = 1u << 8;
+constexpr uint32_t kTagPoison = 1u << 8;  // tags are chunk counts <= 255 plus this bit
+
+// Spin word (4 mask bytes) <-> nibble (bit b = byte b).
+__device__ __forceinline__ uint32_t spin_nibble(uint32_t w) {
+    uint32_t m = w & 0x01010101u;
+    m |= m >> 7;
+    m |= m >> 14;
+    return m & 0xFu;
+}
+__device__ __forceinline__ uint32_t spin_word(uint32_t nib) { return ((nib * 0x00204081u) & 0x01010101u) * 0xFFu; }
 
 // Every branch of the task loop depends on wave-uniform values only (the task
 // index is read back with readfirstlane), so that no lane can be split from its
@@ -184,7 +194,7 @@ __global__ __launch_bounds__(1024) void sa_stream_kernel(StreamArgs s) {
         core::swar_load_instance(L, s.a, cs);
     }
     const int ntask = s.G * s.K, T = blockDim.x, tid = threadIdx.x;
-    const int words = s.a.n * s.a.qw;
+    const int words = s.a.n * s.a.qw, hw = (words + 3) / 4;
     const uint32_t inv = (uint32_t)words;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     for (;;) {
@@ -202,26 +212,32 @@ __global__ __launch_bounds__(1024) void sa_stream_kernel(StreamArgs s) {
         const int tau = __builtin_amdgcn_readfirstlane(task_s);
         if (tau >= ntask) break;
         const int g = tau % s.G, k = tau / s.G;
-        unsigned long long *st = s.state + (size_t)g * (size_t)words;
+        uint32_t *st = s.state + (size_t)g * (size_t)hw;
         if (k > 0) {
             // resume: every word must carry this launch's tag for k chunks done
             const uint32_t want = (uint32_t)k;
             bool late = false, poison = false;
-            for (int w = tid; w < words; w += T) {
-                unsigned long long v = 0;
+            for (int h = tid; h < hw; h += T) {
+                uint32_t v = 0;
                 for (int spins = 0;; ++spins) {
-                    v = __hip_atomic_load(st + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    if (((uint32_t)(v >> 32) & ~kTagPoison) == want) break;
+                    v = __hip_atomic_load(st + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (((v >> 16) & ~kTagPoison) == want) break;
                     if (spins >= s.spin_limit) {
                         late = true;
                         break;
                     }
                     __builtin_amdgcn_s_sleep(2);
                 }
-                poison |= ((uint32_t)(v >> 32) & kTagPoison) != 0;
-                const uint32_t word = (uint32_t)v;
-                L.S[w] = word;
-                L.S[w + inv] = ~word;
+                poison |= ((v >> 16) & kTagPoison) != 0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int w = 4 * h + q;
+                    if (w < words) {
+                        const uint32_t word = spin_word((v >> (4 * q)) & 0xFu);
+                        L.S[w] = word;
+                        L.S[w + inv] = ~word;
+                    }
+                }
             }
             if (late) late_s = 1;
             if (poison) poison_s = 1;
@@ -242,18 +258,22 @@ __global__ __launch_bounds__(1024) void sa_stream_kernel(StreamArgs s) {
         core::swar_run<DK, W, BIG>(L, it, cs, ch);  // ends with a barrier
         if (ch.keep) {
             const uint32_t tag = (poisoned ? kTagPoison : 0u) | (uint32_t)(k + 1);
-            for (int w = tid; w < words; w += T)
-                __hip_atomic_store(st + w, ((unsigned long long)tag << 32) | L.S[w], __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+            for (int h = tid; h < hw; h += T) {
+                uint32_t pay = 0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (4 * h + q < words) pay |= spin_nibble(L.S[4 * h + q]) << (4 * q);
+                __hip_atomic_store(st + h, (tag << 16) | pay, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
     }
 }
 
 // Task counter and tags back to zero (no word then matches a chunk tag >= 1).
-__global__ void stream_reset_kernel(int *counter, unsigned long long *state, size_t words) {
+__global__ void stream_reset_kernel(int *counter, uint32_t *state, size_t words) {
     const size_t i0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i0 == 0) *counter = 0;
-    for (size_t i = i0; i < words; i += (size_t)gridDim.x * blockDim.x) state[i] = 0ull;
+    for (size_t i = i0; i < words; i += (size_t)gridDim.x * blockDim.x) state[i] = 0u;
 }
 
 // The global-memory instance of the byte-parallel body (record addresses relative
@@ -445,7 +465,7 @@ static int stream_chunks(int G, int sweeps, int resident) {
 
 size_t sa_stream_bytes(int n, int reads, int qw) {
     const size_t G = (size_t)((reads + 3) / 4 + qw - 1) / (size_t)qw;
-    return 256 + G * (size_t)n * (size_t)qw * 8;
+    return 256 + G * (((size_t)n * (size_t)qw + 3) / 4) * 4;
 }
 
 // Chunks per group for a streamed launch of L, or 1 when the plain launch is used
@@ -526,9 +546,9 @@ hipError_t launch_sa_stream(const SaLaunch &L, int plan, void *buf, hipStream_t 
     a.K = (L.sweeps + a.Lc - 1) / a.Lc;
     unsigned char *b = static_cast<unsigned char *>(buf);
     a.counter = reinterpret_cast<int *>(b);
-    a.state = reinterpret_cast<unsigned long long *>(b + 256);
+    a.state = reinterpret_cast<uint32_t *>(b + 256);
     a.spin_limit = L.spin_limit;
-    const size_t words = (size_t)G * (size_t)L.n * (size_t)L.qw;
+    const size_t words = (size_t)G * (((size_t)L.n * (size_t)L.qw + 3) / 4);
     const int rgrid = (int)std::min<size_t>(1024, std::max<size_t>(1, (words + 255) / 256));
     hipLaunchKernelGGL(stream_reset_kernel, dim3(rgrid), dim3(256), 0, s, a.counter, a.state, words);
     hipError_t e = hipGetLastError();

@@ -389,6 +389,8 @@ spv_status spv_debug_lds_shadow(spv_ctx *ctx, uint64_t counts[4], int32_t reset)
     unsigned long long v[4] = {0, 0, 0, 0};
     if ((e = shadow_stats_sa(v, reset != 0)) != hipSuccess) return hip_check(c, e, "race counts (SA)");
     if ((e = shadow_stats_batch(v, reset != 0)) != hipSuccess) return hip_check(c, e, "race counts (batch)");
+    if ((e = shadow_stats_pt(v, reset != 0)) != hipSuccess) return hip_check(c, e, "race counts (tempering)");
+    if ((e = shadow_stats_ptx(v, reset != 0)) != hipSuccess) return hip_check(c, e, "race counts (split tempering)");
     for (int k = 0; k < 4; ++k) counts[k] = (uint64_t)v[k];
     return SPV_OK;
 }

@@ -329,6 +329,8 @@ constexpr size_t kShadowLdsBytes = kLdsShadow ? 8192 : 0;
 // read-write, passes checked, launches not covered); no-ops in the normal build.
 hipError_t shadow_stats_sa(unsigned long long *out, bool reset);
 hipError_t shadow_stats_batch(unsigned long long *out, bool reset);
+hipError_t shadow_stats_pt(unsigned long long *out, bool reset);
+hipError_t shadow_stats_ptx(unsigned long long *out, bool reset);
 
 // Checkpoint a tempering launch starts from (null members: fresh start).
 struct PtResume {

@@ -20,6 +20,7 @@
 
 #include "device.hpp"
 #include "internal.hpp"
+#include "lds_shadow.hpp"
 #include "pt_core.hpp"
 
 namespace spv {
@@ -209,11 +210,32 @@ __global__ __launch_bounds__(1024) void pt_kernel(PtArgs a) {
     for (int l = tid; l < cK; l += T) L.E[l] /= 2;  // sum of s(h + f) counts every coupler twice
     __syncthreads();
 
+    // Race-detection build: each class pass's spin-word writes, then its neighbour
+    // reads, against the LDS bitmap (a word is (position, quad)).
+    const shadow::Pass sh = shadow::begin((uint32_t)n * (uint32_t)nqa);
+    auto shadow_pass = [&](int c, bool before) {
+        const int pe = cs[c + 1];
+        if (before) {
+            for (int p = cs[c] + slot_t; active && p < pe; p += nslots) shadow::mark(sh, (uint32_t)(p * nqa + q));
+            shadow::barrier();
+            for (int p = cs[c] + slot_t; active && p < pe; p += nslots)
+                for (int k = 0; k < D; ++k) {
+                    const uint32_t rec = nbr_rec(k, p);
+                    if ((rec & 0xffffu) != 0u) shadow::check(sh, (rec >> 16) * (uint32_t)nqa + (uint32_t)q);
+                }
+            shadow::count_pass(sh);
+        } else {
+            for (int p = cs[c] + slot_t; active && p < pe; p += nslots) shadow::unmark(sh, (uint32_t)(p * nqa + q));
+            shadow::barrier();
+        }
+    };
+
     for (int ls = 0; ls < a.sweeps; ++ls) {
         const uint32_t t = a.sweep_offset + (uint32_t)ls;
         // 1. Metropolis on every slot.
         long long dE[4] = {0, 0, 0, 0};
         for (int c = 0; c < a.C; ++c) {
+            if constexpr (shadow::kOn) shadow_pass(c, true);
             const int pe = cs[c + 1];
             for (int p = cs[c] + slot_t; active && p < pe; p += nslots) {
                 const uint32_t self = L.S[(size_t)p * nqa + q];
@@ -230,6 +252,7 @@ __global__ __launch_bounds__(1024) void pt_kernel(PtArgs a) {
                 if (mask) L.S[(size_t)p * nqa + q] = self ^ mask;
             }
             __syncthreads();
+            if constexpr (shadow::kOn) shadow_pass(c, false);
         }
         // Fold the energy changes of the sweep.
         if (pow2) {
@@ -528,5 +551,7 @@ hipError_t launch_pt(const PtLaunch &P, hipStream_t s) {
     }
     return hipGetLastError();
 }
+
+hipError_t shadow_stats_pt(unsigned long long *out, bool reset) { return shadow::read_stats(out, reset); }
 
 }  // namespace spv

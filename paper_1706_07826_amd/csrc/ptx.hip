@@ -31,6 +31,7 @@
 
 #include "device.hpp"
 #include "internal.hpp"
+#include "lds_shadow.hpp"
 #include "pt_core.hpp"
 
 namespace spv {
@@ -290,11 +291,32 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
     for (int l = tid; l < nl; l += T) L_E[l] /= 2;  // sum of s(h + f) counts every coupler twice
     __syncthreads();
 
+    // Race-detection build: each class pass's spin-word writes, then its neighbour
+    // reads, against the LDS bitmap (a word is (position, quad)).
+    const shadow::Pass sh = shadow::begin((uint32_t)n * (uint32_t)nq);
+    auto shadow_pass = [&](int c, bool before) {
+        const int pe = cs[c + 1];
+        if (before) {
+            for (int p = cs[c] + pt; active && p < pe; p += nstr) shadow::mark(sh, (uint32_t)(p * nq + q));
+            shadow::barrier();
+            for (int p = cs[c] + pt; active && p < pe; p += nstr)
+                for (int k = 0; k < D; ++k) {
+                    const uint32_t rec = NBR(k, p);
+                    if ((rec & 0xffffu) != 0u) shadow::check(sh, (rec >> 16) * (uint32_t)nq + (uint32_t)q);
+                }
+            shadow::count_pass(sh);
+        } else {
+            for (int p = cs[c] + pt; active && p < pe; p += nstr) shadow::unmark(sh, (uint32_t)(p * nq + q));
+            shadow::barrier();
+        }
+    };
+
     for (int ls = 0; ls < a.sweeps; ++ls) {
         const uint32_t t = a.sweep_offset + (uint32_t)ls;
         // 1. Metropolis on the group's replicas.
         long long dE[4] = {0, 0, 0, 0};
         for (int c = 0; c < a.C; ++c) {
+            if constexpr (shadow::kOn) shadow_pass(c, true);
             const int pe = cs[c + 1];
             for (int p = cs[c] + pt; active && p < pe; p += nstr) {
                 const uint32_t self = L_S[(size_t)p * nq + q];
@@ -311,6 +333,7 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                 if (mask) L_S[(size_t)p * nq + q] = self ^ mask;
             }
             __syncthreads();
+            if constexpr (shadow::kOn) shadow_pass(c, false);
         }
         if (pow2) {
 #pragma unroll
@@ -914,5 +937,7 @@ hipError_t launch_ptx(const PtxLaunch &P, hipStream_t s) {
     void *args[] = {&a};
     return hipLaunchKernel(f, dim3(P.runs * P.G), dim3(P.threads), args, lds, s);
 }
+
+hipError_t shadow_stats_ptx(unsigned long long *out, bool reset) { return shadow::read_stats(out, reset); }
 
 }  // namespace spv

@@ -1,13 +1,16 @@
 """Runs the sampling kernels of the race-detection build (libspvar_shadow.so, loaded with
-SPVAR_LIBRARY=shadow) over every SA body and launch shape, checks each sample bit for bit
-against the oracle, and prints the detector's counts as one JSON line per phase:
+SPVAR_LIBRARY=shadow) over every SA body and launch shape and the tempering kernels, checks
+each result bit for bit against the oracle, and prints the detector's counts as one JSON line
+per phase:
 
 * "clean": valid colourings through the byte-parallel body (two words per lane, one word per
   lane, streamed, instance in global memory), the general body (x_bound > 255, in LDS and in
-  global memory) and the batched launch (one-word and paired bodies);
+  global memory), the batched launch (one-word and paired bodies) and the tempering kernels
+  (one workgroup per run; the ladder split over workgroups with the instance in LDS and in
+  global memory; cluster moves on);
 * "one_class": a colouring with every site in one class (edges inside the class), let through
   ingest by SPVAR_SHADOW_ALLOW_COLOUR_EDGES, where every class pass reads neighbours that the
-  same pass writes.
+  same pass writes, through SA and through tempering.
 
 Run by tests/test_gpu_lds_shadow.py in a process of its own."""
 import json
@@ -77,6 +80,17 @@ def main():
         for b, inst in enumerate(insts):
             oS, oE = oracle.sa_sample(inst, betas, reads=reads[b], seed=seeds[b])
             assert np.array_equal(sp[b].cpu().numpy(), oS) and np.array_equal(en[b].cpu().numpy(), oE), (label, b)
+    cube = si.cubic_lattice(4, "gauss", seed=9, scale_log2=10)
+    for label, env, K in (("pt_one_workgroup", {"SPVAR_PT_SPLIT": 0}, 6),
+                          ("pt_split", {"SPVAR_PT_SPLIT": 1, "SPVAR_PT_GROUPS": 2}, 8),
+                          ("pt_split_big", {"SPVAR_PT_SPLIT": 1, "SPVAR_PT_GROUPS": 2, "SPVAR_PT_BIG": 1}, 8)):
+        say(f"[shadow] {label}: K={K}")
+        betas_pt = si.geometric_betas(0.2, 5.0, K)
+        Pc = spv.Problem.from_instance(cube)
+        got = with_env(env, lambda: spv.spv_pt_sample(ctx, Pc, betas_pt, 2, 2, 30, 4, icm=(0, K)))
+        want = oracle.pt_sample(cube, betas_pt, 2, 2, 30, seed=4, icm=(0, K))
+        for key in ("final_spins", "final_E", "top_E", "top_count", "top_spins"):
+            assert np.array_equal(got[key].cpu().numpy(), want[key]), (label, key)
     clean = spv.spv_debug_lds_shadow(ctx, reset=True)
     print(json.dumps(dict(phase="clean", **clean)), flush=True)
 
@@ -95,6 +109,11 @@ def main():
     with_env({"SPVAR_SHADOW_ALLOW_COLOUR_EDGES": 1}, lambda: spv.spv_sample(ctx, P, betas, 16, 1))
     races = spv.spv_debug_lds_shadow(ctx, reset=True)
     print(json.dumps(dict(phase="one_class", refused=refused, **races)), flush=True)
+    say("[shadow] one_class through tempering")
+    with_env({"SPVAR_SHADOW_ALLOW_COLOUR_EDGES": 1, "SPVAR_PT_SPLIT": 1, "SPVAR_PT_GROUPS": 1},
+             lambda: spv.spv_pt_sample(ctx, P, si.geometric_betas(0.2, 3.0, 4), 1, 1, 5, 2))
+    races_pt = spv.spv_debug_lds_shadow(ctx, reset=True)
+    print(json.dumps(dict(phase="one_class_pt", **races_pt)), flush=True)
 
 
 if __name__ == "__main__":

@@ -113,8 +113,8 @@ const char *spv_version(void);
 
 /*
  * Race detection (debug build of the library with SPV_LDS_SHADOW=1,
- * libspvar_shadow.so).  The Metropolis class passes of the SA and tempering
- * kernels (Sec. III.A, III.D.1; one colour class at a time) check, on every pass, that no spin
+ * libspvar_shadow.so).  The Metropolis class passes of the SA, tempering and
+ * SQA kernels (Sec. III.A, III.D.1; one colour class at a time) check, on every pass, that no spin
  * word is written by two tasks and that no task reads a neighbour word another
  * task of the pass writes, against a per-workgroup bitmap in LDS (8 KiB of LDS
  * per workgroup, taken from the planners' limit).  Conflicts are counted, never

@@ -391,6 +391,7 @@ spv_status spv_debug_lds_shadow(spv_ctx *ctx, uint64_t counts[4], int32_t reset)
     if ((e = shadow_stats_batch(v, reset != 0)) != hipSuccess) return hip_check(c, e, "race counts (batch)");
     if ((e = shadow_stats_pt(v, reset != 0)) != hipSuccess) return hip_check(c, e, "race counts (tempering)");
     if ((e = shadow_stats_ptx(v, reset != 0)) != hipSuccess) return hip_check(c, e, "race counts (split tempering)");
+    if ((e = shadow_stats_sqa(v, reset != 0)) != hipSuccess) return hip_check(c, e, "race counts (SQA)");
     for (int k = 0; k < 4; ++k) counts[k] = (uint64_t)v[k];
     return SPV_OK;
 }

@@ -331,6 +331,7 @@ hipError_t shadow_stats_sa(unsigned long long *out, bool reset);
 hipError_t shadow_stats_batch(unsigned long long *out, bool reset);
 hipError_t shadow_stats_pt(unsigned long long *out, bool reset);
 hipError_t shadow_stats_ptx(unsigned long long *out, bool reset);
+hipError_t shadow_stats_sqa(unsigned long long *out, bool reset);
 
 // Checkpoint a tempering launch starts from (null members: fresh start).
 struct PtResume {

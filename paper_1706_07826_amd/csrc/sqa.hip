@@ -24,6 +24,7 @@
 
 #include "device.hpp"
 #include "internal.hpp"
+#include "lds_shadow.hpp"
 #include "sa_core.hpp"
 #include "swar_core.hpp"
 
@@ -159,6 +160,36 @@ __global__ __launch_bounds__(1024) void sqa_kernel(SqaArgs a) {
 
     const int q = tid % G8, slot = tid / G8, nslots = T / G8;
     const bool active = slot < nslots;
+    // Race-detection build: each (class, parity) pass's slice-word writes, then its
+    // reads (the ring neighbours' words of the other parity and the classical
+    // neighbours' words), against the LDS bitmap.
+    const shadow::Pass sh = shadow::begin((uint32_t)n * (uint32_t)qw);
+    auto shadow_pass = [&](int c, int par, bool before) {
+        const int pe = cs[c + 1], w = par * G8 + q;
+        const int wa = par ? q : G8 + q;
+        const int wb = par ? (q + 1 == G8 ? 0 : q + 1) : G8 + (q == 0 ? G8 - 1 : q - 1);
+        if (before) {
+            for (int p = cs[c] + slot; active && p < pe; p += nslots) shadow::mark(sh, (uint32_t)(p * qw + w));
+            shadow::barrier();
+            for (int p = cs[c] + slot; active && p < pe; p += nslots) {
+                shadow::check(sh, (uint32_t)(p * qw + wa));
+                shadow::check(sh, (uint32_t)(p * qw + wb));
+                for (int k = 0; k < D; ++k) {
+                    if constexpr (BIG) {
+                        const uint32_t rec = L.nbr[(size_t)p * rec_p + (size_t)k * rec_k];
+                        if ((rec & 0xffffu) != 0u) shadow::check(sh, (rec >> 16) * (uint32_t)qw + (uint32_t)w);
+                    } else {
+                        const uint2 r = nb2[(size_t)k * n + p];
+                        if (r.y != 0u) shadow::check(sh, (r.x - core::swar_lds_addr(L.S)) / 4u + (uint32_t)w);
+                    }
+                }
+            }
+            shadow::count_pass(sh);
+        } else {
+            for (int p = cs[c] + slot; active && p < pe; p += nslots) shadow::unmark(sh, (uint32_t)(p * qw + w));
+            shadow::barrier();
+        }
+    };
     for (int ls = 0; ls < a.sweeps; ++ls) {
         const uint32_t t = (uint32_t)ls;
         const int32_t jp = a.jp[ls];
@@ -174,6 +205,7 @@ __global__ __launch_bounds__(1024) void sqa_kernel(SqaArgs a) {
             const int pe = cs[c + 1];
 #pragma unroll 1
             for (int par = 0; par < 2; ++par) {
+                if constexpr (shadow::kOn) shadow_pass(c, par, true);
                 const int w = par * G8 + q;
                 // words of the other parity holding slices k - 1 and k + 1
                 const int wa = par ? q : G8 + q;
@@ -201,6 +233,7 @@ __global__ __launch_bounds__(1024) void sqa_kernel(SqaArgs a) {
                     if (mask) L.S[(size_t)p * qw + w] = self ^ mask;
                 }
                 __syncthreads();
+                if constexpr (shadow::kOn) shadow_pass(c, par, false);
             }
         }
     }
@@ -294,5 +327,7 @@ hipError_t launch_sqa(const SqaLaunch &L, hipStream_t s) {
 #undef SPV_SQA
     return hipGetLastError();
 }
+
+hipError_t shadow_stats_sqa(unsigned long long *out, bool reset) { return shadow::read_stats(out, reset); }
 
 }  // namespace spv

@@ -7,7 +7,7 @@ per phase:
   lane, streamed, instance in global memory), the general body (x_bound > 255, in LDS and in
   global memory), the batched launch (one-word and paired bodies) and the tempering kernels
   (one workgroup per run; the ladder split over workgroups with the instance in LDS and in
-  global memory; cluster moves on);
+  global memory; cluster moves on) and SQA (instance in LDS and in global memory);
 * "one_class": a colouring with every site in one class (edges inside the class), let through
   ingest by SPVAR_SHADOW_ALLOW_COLOUR_EDGES, where every class pass reads neighbours that the
   same pass writes, through SA and through tempering.
@@ -91,6 +91,14 @@ def main():
         want = oracle.pt_sample(cube, betas_pt, 2, 2, 30, seed=4, icm=(0, K))
         for key in ("final_spins", "final_E", "top_E", "top_count", "top_spins"):
             assert np.array_equal(got[key].cpu().numpy(), want[key]), (label, key)
+    for label, env in (("sqa", {}), ("sqa_big", {"SPVAR_SQA_BIG": 1})):
+        say(f"[shadow] {label}: P=8")
+        b = si.linear_betas(0.2, 3.0, 20)
+        g = np.geomspace(3.0, 0.05, 20)
+        Ps = spv.Problem.from_instance(swar)
+        sp, E = with_env(env, lambda: spv.spv_sqa_sample(ctx, Ps, b, g, 8, 6, 43))
+        osp, oE, _ = oracle.sqa_sample(swar, b, g, 8, reads=6, seed=43)
+        assert np.array_equal(sp.cpu().numpy(), osp) and np.array_equal(E.cpu().numpy(), oE), label
     clean = spv.spv_debug_lds_shadow(ctx, reset=True)
     print(json.dumps(dict(phase="clean", **clean)), flush=True)
 

@@ -318,19 +318,47 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
         for (int c = 0; c < a.C; ++c) {
             if constexpr (shadow::kOn) shadow_pass(c, true);
             const int pe = cs[c + 1];
-            for (int p = cs[c] + pt; active && p < pe; p += nstr) {
+            auto update = [&](int p, auto rec, int32_t hp, uint32_t ord) __attribute__((always_inline)) {
                 const uint32_t self = L_S[(size_t)p * nq + q];
                 int32_t f[4];
-                ptc::quad_fields<DK>(NBR, D, p, L_S, nq, q, HPOS(p), f);
+                ptc::quad_fields<DK>(rec, D, p, L_S, nq, q, hp, f);
                 int32_t x[4];
 #pragma unroll
                 for (int b = 0; b < 4; ++b) x[b] = dev::spin_of(self, b) > 0 ? -f[b] : f[b];
-                const uint32_t mask =
-                    ptc::metropolis_mask4<ND>(x, tb, (uint32_t)ORD(p), t, quad, a.k0, a.k1);
+                // The key enters each site's draws opaquely: otherwise the twenty round
+                // keys are hoisted out of the loop, outgrow the scalar registers and
+                // come back one vector-lane read at a time.
+                uint32_t k0 = a.k0, k1 = a.k1;
+                asm volatile("" : "+s"(k0), "+s"(k1));
+                const uint32_t mask = ptc::metropolis_mask4<ND>(x, tb, ord, t, quad, k0, k1);
 #pragma unroll
                 for (int b = 0; b < 4; ++b)
                     if (mask & (0xFEu << (8 * b))) dE[b] += 2ll * x[b];
                 if (mask) L_S[(size_t)p * nq + q] = self ^ mask;
+            };
+            if constexpr (BIG && DK > 0) {
+                // Records, h and index of a site come from global memory: those of the
+                // thread's next site are in flight while the current one is updated.
+                uint32_t rn[DK];
+                int32_t hn = 0, on = 0;
+                auto fetch = [&](int pp) __attribute__((always_inline)) {
+#pragma unroll
+                    for (int u = 0; u < DK; ++u) rn[u] = gnbr[(size_t)pp * DK + u];
+                    hn = ghpos[pp];
+                    on = gord[pp];
+                };
+                int p = cs[c] + pt;
+                if (active && p < pe) fetch(p);
+                for (; active && p < pe; p += nstr) {
+                    uint32_t rr[DK];
+#pragma unroll
+                    for (int u = 0; u < DK; ++u) rr[u] = rn[u];
+                    const int32_t hp = hn, od = on;
+                    if (p + nstr < pe) fetch(p + nstr);
+                    update(p, [&](int u, int) __attribute__((always_inline)) { return rr[u]; }, hp, (uint32_t)od);
+                }
+            } else {
+                for (int p = cs[c] + pt; active && p < pe; p += nstr) update(p, NBR, HPOS(p), (uint32_t)ORD(p));
             }
             __syncthreads();
             if constexpr (shadow::kOn) shadow_pass(c, false);

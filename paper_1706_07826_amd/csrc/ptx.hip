@@ -2,11 +2,13 @@
 // (Sec. III.D.1 "PTICM" at sizes where one run does not fit one workgroup, or
 // where there are too few runs to fill the device).
 //
-// A run's K slots are cut into G groups of m consecutive slots (m a multiple
-// of 4, so every quad of 4 replicas of the replica index r = (run * chains +
-// chain) * K + slot lies inside one group).  Workgroup (run, g) holds the
-// group's slots of EVERY chain, so the Houdayer partners (chain 0 and chain 1
-// at one slot) share its LDS.  A sweep is
+// A run's K slots are cut into G groups of m consecutive slots, m a multiple
+// of 4 (every quad of 4 replicas of the replica index r = (run * chains +
+// chain) * K + slot lies inside one group) or m = 2 (a group owns half of each
+// of its quads: it draws the quad's whole random block and updates its own two
+// bytes; the other two bytes of its LDS copy are never changed or read out).
+// Workgroup (run, g) holds the group's slots of EVERY chain, so the Houdayer
+// partners (chain 0 and chain 1 at one slot) share its LDS.  A sweep is
 //   1. Metropolis on the group's replicas (colour classes in order),
 //   2. replica exchange of pairs (k, k+1), k = t mod 2.  With m even, pairs
 //      inside the group are decided from LDS energies and swapped byte-wise;
@@ -88,7 +90,7 @@ constexpr int kJoinBuf = 128;
 
 __host__ __device__ inline size_t ptx_layout(int n, int D, int m, int chains, int row_len, int nw_icm, bool big,
                                              PtxLds *L, unsigned char *base) {
-    const int nq = chains * m / 4, nl = chains * m, vstride = 2 * ((n + 63) / 64);
+    const int nq = chains * ((m + 3) / 4), nl = chains * m, vstride = 2 * ((n + 63) / 64);
     size_t o = 0;
     auto take = [&](size_t bytes) {
         size_t at = o;
@@ -173,7 +175,10 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
     auto *const L_ubj = Lay.ubj;
     const int tid = threadIdx.x, T = blockDim.x, lane = dev::lane_id(), wid = tid >> 6, nw = T >> 6;
     const int run = blockIdx.x / G, g = blockIdx.x - run * G;
-    const int s0 = g * a.m, mg = min(a.m, K - s0), qpc = mg >> 2, nq = chains * qpc, nl = chains * mg;
+    // boff: byte of the quad word holding the group's first slot (2 for the upper
+    // half of a quad when m = 2, else 0)
+    const int s0 = g * a.m, mg = min(a.m, K - s0), boff = s0 & 3, qpc = (boff + mg + 3) >> 2, nq = chains * qpc,
+              nl = chains * mg;
     const int32_t *img = a.image;
     const uint32_t *gnbr = reinterpret_cast<const uint32_t *>(img + kImgHeader + 3 * n);
     const int32_t *gord = img + kImgHeader, *gpos = img + kImgHeader + n, *ghpos = img + kImgHeader + 2 * n;
@@ -188,7 +193,7 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
     auto POS = [=](int i) __attribute__((always_inline)) -> int32_t { return BIG ? gpos[i] : lpos[i]; };
     // byte of local replica l = chain * mg + (slot - s0) at position p
     auto sbyte = [=](int l, int p) __attribute__((always_inline)) -> unsigned char * {
-        const int ch = l / mg, o = l - ch * mg;
+        const int ch = l / mg, o = l - ch * mg + boff;
         return Sb + ((size_t)p * nq + ch * qpc + (o >> 2)) * 4 + (o & 3);
     };
 
@@ -244,12 +249,18 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
     const bool active = pt < nstr;
     const int chq = q / qpc, jq = q - chq * qpc;
     const uint32_t quad = (uint32_t)((((size_t)run * chains + chq) * K + s0) / 4 + jq);
+    // byte b of the thread's word is the group's local slot 4 jq + b - boff; own marks
+    // (0xFE) the bytes that are the group's
     int loc[4];
     const uint32_t *tb[4];
+    uint32_t own = 0;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-        loc[b] = chq * mg + 4 * jq + b;
-        tb[b] = L_tab + (size_t)(4 * jq + b) * row_len;
+        const int o = 4 * jq + b - boff;
+        const bool mine = o >= 0 && o < mg;
+        own |= mine ? 0xFEu << (8 * b) : 0u;
+        loc[b] = chq * mg + (mine ? o : 0);
+        tb[b] = L_tab + (size_t)(mine ? o : 0) * row_len;
     }
     const bool pow2 = (nq & (nq - 1)) == 0 && nq <= 64;
 
@@ -285,7 +296,8 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
         if (active)
 #pragma unroll
             for (int b = 0; b < 4; ++b)
-                atomicAdd(reinterpret_cast<unsigned long long *>(&L_E[loc[b]]), (unsigned long long)e2[b]);
+                if (own & (0xFEu << (8 * b)))
+                    atomicAdd(reinterpret_cast<unsigned long long *>(&L_E[loc[b]]), (unsigned long long)e2[b]);
     }
     __syncthreads();
     for (int l = tid; l < nl; l += T) L_E[l] /= 2;  // sum of s(h + f) counts every coupler twice
@@ -327,10 +339,13 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                 for (int b = 0; b < 4; ++b) x[b] = dev::spin_of(self, b) > 0 ? -f[b] : f[b];
                 // The key enters each site's draws opaquely: otherwise the twenty round
                 // keys are hoisted out of the loop, outgrow the scalar registers and
-                // come back one vector-lane read at a time.
+                // come back one vector-lane read at a time.  (Unoptimised device builds
+                // keep it in vector registers, where a scalar operand cannot bind.)
                 uint32_t k0 = a.k0, k1 = a.k1;
+#ifdef __OPTIMIZE__
                 asm volatile("" : "+s"(k0), "+s"(k1));
-                const uint32_t mask = ptc::metropolis_mask4<ND>(x, tb, ord, t, quad, k0, k1);
+#endif
+                const uint32_t mask = own & ptc::metropolis_mask4<ND>(x, tb, ord, t, quad, k0, k1);
 #pragma unroll
                 for (int b = 0; b < 4; ++b)
                     if (mask & (0xFEu << (8 * b))) dE[b] += 2ll * x[b];
@@ -531,9 +546,9 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
             unsigned char *pa[kIcmBatch], *pb[kIcmBatch];
 #pragma unroll
             for (int j = 0; j < kIcmBatch; ++j) {
-                const int la = min(kq + j, ke - 1) - s0, lb = mg + la;
-                pa[j] = Sb + (size_t)(((la % mg) >> 2)) * 4 + (la & 3);
-                pb[j] = Sb + (size_t)(qpc + ((lb % mg) >> 2)) * 4 + (lb & 3);
+                const int o = min(kq + j, ke - 1) - s0 + boff;
+                pa[j] = Sb + (size_t)(o >> 2) * 4 + (o & 3);
+                pb[j] = Sb + (size_t)(qpc + (o >> 2)) * 4 + (o & 3);
             }
             auto dis = [=](int j, int p) __attribute__((always_inline)) -> bool {
                 return pa[j][(size_t)p * pstride] != pb[j][(size_t)p * pstride];
@@ -541,7 +556,7 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
             // The batch's disagreements at position p as bits (bit j: pair j).  When its
             // pairs lie in one quad word per chain, one XOR of the two words gives them all
             // (a byte is 0xFE where the replicas differ and 0 where they agree).
-            const int la0 = kq - s0, qa0 = la0 >> 2, off0 = la0 & 3;
+            const int o0 = kq - s0 + boff, qa0 = o0 >> 2, off0 = o0 & 3;
             const bool word_dis = off0 + nb <= 4;
             const uint32_t pmask = (1u << nb) - 1u;
             // Chain 0's spin bytes of the batch's pairs at position p (byte j: pair j) and

@@ -47,6 +47,20 @@ CASES = [
     ("sparse42_K8_G2_icm_ragged_n", lambda: si.random_sparse(42, 3.0, seed=14), 8, 2, 2, 70, (0, 8), 2, 0, 0),
     ("cubic4_K16_G2_icm_straddling_batch_big", lambda: si.cubic_lattice(4, "gauss", seed=13, scale_log2=10), 16, 1,
      2, 45, (3, 14), 2, 1, 0),
+    # groups of 2 slots (more groups than quads, cluster moves on): each group owns half of
+    # every quad word it holds, the upper half when its first slot is 2 mod 4
+    ("cubic4_K8_G4_icm_half_quads", lambda: si.cubic_lattice(4, "gauss", seed=15, scale_log2=10), 8, 2, 2, 80,
+     (0, 8), 4, 0, 0),
+    ("sparse40_K16_G8_icm_half_quads_window_offset", lambda: si.random_sparse(40, 3.0, seed=16), 16, 2, 2, 61,
+     (3, 13), 8, 0, 5),
+    ("cubic4_K12_G6_icm_half_quads_big", lambda: si.cubic_lattice(4, "gauss", seed=17, scale_log2=10), 12, 1, 2,
+     50, (0, 12), 6, 1, 0),
+    ("sparse42_K8_G4_icm_half_quads_ragged_n", lambda: si.random_sparse(42, 3.0, seed=18), 8, 2, 2, 40, (0, 8), 4,
+     0, 0),
+    ("chimera2_K8_G4_icm_half_quads_one_digit", lambda: si.chimera(2, seed=19), 8, 2, 2, 45, (0, 8), 4, 0, 1),
+    ("zero_sweeps_G4_half_quads", lambda: si.chimera(2, seed=20), 8, 2, 2, 0, (0, 8), 4, 0, 0),
+    ("cubic10_K8_G4_icm_half_quads_wide", lambda: si.cubic_lattice(10, "gauss", seed=21, scale_log2=10), 8, 1, 2,
+     30, (0, 8), 4, 0, 0),
     # many waves per workgroup on the cluster moves (1024 threads)
     ("cubic10_K8_G2_icm_wide", lambda: si.cubic_lattice(10, "gauss", seed=10, scale_log2=10), 8, 2, 2, 30,
      (0, 8), 2, 0, 0),
@@ -83,7 +97,7 @@ def test_single_workgroup_kernel_forced(spv, ctx, monkeypatch, K, chains, icm):
 def test_cubic20_pticm_config_shape(spv, ctx):
     """The N=8000 PT-ICM shape (40 slots x 2 chains, Houdayer at every slot,
     one run) on the default plan (instance in global memory, one workgroup per
-    4 slots), a short schedule against the oracle."""
+    2 slots), a short schedule against the oracle."""
     cfg = cf.CUBIC20_PTICM
     inst = cf.instance(cfg)
     betas = cf.betas(cfg)

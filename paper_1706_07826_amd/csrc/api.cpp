@@ -269,8 +269,9 @@ spv_status upload(Ctx *c, DevBuf &dst, size_t dst_off, const void *src, size_t b
 // Ladder split of a tempering job (see the split kernel): whether to use it,
 // the group count G and size m, the workgroup shape and whether the instance
 // stays in LDS.  Groups hold a multiple of 4 slots; with cluster moves on, and
-// more workgroups available than quads, groups of 2 slots (half a quad each),
-// which halves every group's cluster-move work.  SPVAR_PT_SPLIT=0 disables the
+// more workgroups available than quads, groups of 2 slots (half a quad each) or,
+// beyond K / 2 groups, of 1 slot: every group's cluster-move work shrinks with
+// its slot count.  SPVAR_PT_SPLIT=0 disables the
 // split, =1 forces it (K % 4 == 0); SPVAR_PT_GROUPS fixes G; SPVAR_PT_BIG=1
 // reads the instance from global memory even when it would fit in LDS.
 static int env_int(const char *name, int dflt) {
@@ -285,7 +286,7 @@ spv_status plan_pt_split(Ctx *c, int n, int D, int K, int runs, int chains, int 
     sp->use = false;
     const int mode = env_int("SPVAR_PT_SPLIT", -1);
     if (mode == 0 || K % 4 != 0 || n < 1) return SPV_OK;
-    const int quads = K / 4, maxg = icm_hi > icm_lo ? K / 2 : quads;
+    const int quads = K / 4, maxg = icm_hi > icm_lo ? K : quads;
     int G = env_int("SPVAR_PT_GROUPS", 0);
     if (G <= 0) G = std::max(1, std::min(maxg, c->num_cus / std::max(runs, 1)));
     G = std::min(G, maxg);
@@ -293,7 +294,7 @@ spv_status plan_pt_split(Ctx *c, int n, int D, int K, int runs, int chains, int 
     for (;; ++G) {
         if (G > maxg)
             return set_err(c, SPV_ECAPACITY, "PT run does not fit even split into %d groups (n=%d)", maxg, n);
-        const int m = G > quads ? 2 : 4 * ((quads + G - 1) / G);
+        const int m = G > K / 2 ? 1 : G > quads ? 2 : 4 * ((quads + G - 1) / G);
         const int Gr = (K + m - 1) / m;
         const int nq = chains * ((m + 3) / 4);
         const long long tasks = (long long)n * nq;

@@ -4,17 +4,18 @@
 //
 // A run's K slots are cut into G groups of m consecutive slots, m a multiple
 // of 4 (every quad of 4 replicas of the replica index r = (run * chains +
-// chain) * K + slot lies inside one group) or m = 2 (a group owns half of each
-// of its quads: it draws the quad's whole random block and updates its own two
-// bytes; the other two bytes of its LDS copy are never changed or read out).
+// chain) * K + slot lies inside one group), or m = 2 or 1 (a group owns half
+// or a quarter of its quad: it draws the quad's whole random block and updates
+// its own bytes; the other bytes of its LDS copy are never changed or read out).
 // Workgroup (run, g) holds the group's slots of EVERY chain, so the Houdayer
 // partners (chain 0 and chain 1 at one slot) share its LDS.  A sweep is
 //   1. Metropolis on the group's replicas (colour classes in order),
-//   2. replica exchange of pairs (k, k+1), k = t mod 2.  With m even, pairs
-//      inside the group are decided from LDS energies and swapped byte-wise;
-//      on odd sweeps the two pairs that straddle a group boundary are decided
-//      by both neighbours from the energies each publishes (with the two edge
-//      configurations) as sweep-tagged atomic words; an accepted pair copies
+//   2. replica exchange of pairs (k, k+1), k = t mod 2.  Pairs inside the
+//      group are decided from LDS energies and swapped byte-wise; a pair that
+//      straddles a group boundary (on odd sweeps when m is even; the lower and
+//      the upper boundary on alternate sweeps when m = 1) is decided by both
+//      neighbours from the energies each publishes (with the edge
+//      configuration) as sweep-tagged atomic words; an accepted pair copies
 //      the partner's published configuration in,
 //   3. Houdayer moves at the group's slots, one slot pair at a time with the
 //      whole workgroup (lock-free union-find over the disagreeing sites),
@@ -175,13 +176,18 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
     auto *const L_ubj = Lay.ubj;
     const int tid = threadIdx.x, T = blockDim.x, lane = dev::lane_id(), wid = tid >> 6, nw = T >> 6;
     const int run = blockIdx.x / G, g = blockIdx.x - run * G;
-    // boff: byte of the quad word holding the group's first slot (2 for the upper
-    // half of a quad when m = 2, else 0)
+    // boff: byte of the quad word holding the group's first slot (0 when m is a
+    // multiple of 4)
     const int s0 = g * a.m, mg = min(a.m, K - s0), boff = s0 & 3, qpc = (boff + mg + 3) >> 2, nq = chains * qpc,
               nl = chains * mg;
     const int32_t *img = a.image;
     const uint32_t *gnbr = reinterpret_cast<const uint32_t *>(img + kImgHeader + 3 * n);
     const int32_t *gord = img + kImgHeader, *gpos = img + kImgHeader + n, *ghpos = img + kImgHeader + 2 * n;
+#ifdef __OPTIMIZE__
+    // Kept as values of their own: otherwise each use rebuilds them from the whole
+    // argument block, which comes back from spill lanes sixteen registers at a time.
+    asm volatile("" : "+s"(gnbr), "+s"(gord), "+s"(ghpos));
+#endif
     const uint32_t *const lnbr = L_nbr;
     const int32_t *const lhpos = L_hpos, *const lord = L_ord, *const lpos = L_pos;
     unsigned char *const Sb = L_Sb;
@@ -196,6 +202,8 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
         const int ch = l / mg, o = l - ch * mg + boff;
         return Sb + ((size_t)p * nq + ch * qpc + (o >> 2)) * 4 + (o & 3);
     };
+    // a replica's bytes lie pst apart: loops over positions take sbyte(l, 0) once
+    const uint32_t pst = (uint32_t)nq * 4u;
 
     if (tid <= a.C) cs[tid] = img[3 + tid];
     if (tid == 0) stop = 0;
@@ -263,6 +271,8 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
         tb[b] = L_tab + (size_t)(mine ? o : 0) * row_len;
     }
     const bool pow2 = (nq & (nq - 1)) == 0 && nq <= 64;
+    // the group owns 1 or 2 bytes of each of its words (the same bytes in every word)
+    const bool part = qpc == 1 && mg < 4;
 
     // Initial state and energies.
     for (int p = pt; active && p < n; p += nstr) {
@@ -326,7 +336,7 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
     for (int ls = 0; ls < a.sweeps; ++ls) {
         const uint32_t t = a.sweep_offset + (uint32_t)ls;
         // 1. Metropolis on the group's replicas.
-        long long dE[4] = {0, 0, 0, 0};
+        long long dE[4] = {0, 0, 0, 0}, dEp[2] = {0, 0};
         for (int c = 0; c < a.C; ++c) {
             if constexpr (shadow::kOn) shadow_pass(c, true);
             const int pe = cs[c + 1];
@@ -351,6 +361,65 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                     if (mask & (0xFEu << (8 * b))) dE[b] += 2ll * x[b];
                 if (mask) L_S[(size_t)p * nq + q] = self ^ mask;
             };
+            // A group of 1 or 2 slots owns bytes boff.. of its words: those bytes alone are
+            // updated (the quad's random blocks drawn whole, so the draws are the same).
+            auto update_part = [&](int p, const uint32_t *rr, int32_t hp, uint32_t ord) __attribute__((always_inline)) {
+                const uint32_t self = L_S[(size_t)p * nq + q];
+                uint32_t wv[DK > 0 ? DK : 1];
+#pragma unroll
+                for (int u = 0; u < DK; ++u) wv[u] = L_S[__umul24(rr[u] >> 16, (uint32_t)nq) + (uint32_t)q];
+                uint32_t k0 = a.k0, k1 = a.k1;
+#ifdef __OPTIMIZE__
+                asm volatile("" : "+s"(k0), "+s"(k1));
+#endif
+                int32_t x[2];
+                uint32_t d[2], th[2];
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    const int sh = 24 - 8 * min(boff + i, 3);  // (i = 1 of a 1-slot group is unused)
+                    int32_t f = hp;
+#pragma unroll
+                    for (int u = 0; u < DK; ++u)
+                        f += (int32_t)(int16_t)(rr[u] & 0xffffu) * ((int32_t)(wv[u] << sh) >> 24);
+                    x[i] = ((int32_t)(self << sh) >> 24) > 0 ? -f : f;
+                    d[i] = x[i] > 0 ? ((uint32_t)x[i] & (kDigitSize - 1)) : 0u;
+                    th[i] = L_tab[(size_t)min(i, mg - 1) * row_len + d[i]];
+                }
+                auto pick = [&](const dev::Words4 &w, int i) __attribute__((always_inline)) -> uint32_t {
+                    const int bb = min(boff + i, 3);
+                    return bb == 0 ? w.w[0] : bb == 1 ? w.w[1] : bb == 2 ? w.w[2] : w.w[3];
+                };
+                bool acc[2];
+                {
+                    const dev::Words4 w = dev::philox(ord, t, quad, 2u << 24, k0, k1);
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) acc[i] = (d[i] == 0) | (pick(w, i) < th[i]);
+                }
+#pragma unroll
+                for (int j = 1; j < ND; ++j) {
+                    bool need = false;
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) {
+                        d[i] = x[i] > 0 ? (((uint32_t)x[i] >> (kDigitBits * j)) & (kDigitSize - 1)) : 0u;
+                        need |= i < mg && d[i] != 0;
+                        th[i] = L_tab[(size_t)min(i, mg - 1) * row_len + j * kDigitSize + d[i]];
+                    }
+                    if (need) {
+                        const dev::Words4 w = dev::philox(ord, t, quad, (2u << 24) | (uint32_t)j, k0, k1);
+#pragma unroll
+                        for (int i = 0; i < 2; ++i)
+                            if ((d[i] != 0) & (pick(w, i) >= th[i])) acc[i] = false;
+                    }
+                }
+                uint32_t mask = 0;
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+                    if (i < mg && acc[i]) {
+                        mask |= 0xFEu << (8 * (boff + i));
+                        dEp[i] += 2ll * x[i];
+                    }
+                if (mask) L_S[(size_t)p * nq + q] = self ^ mask;
+            };
             if constexpr (BIG && DK > 0) {
                 // Records, h and index of a site come from global memory: those of the
                 // thread's next site are in flight while the current one is updated.
@@ -362,22 +431,37 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                     hn = ghpos[pp];
                     on = gord[pp];
                 };
-                int p = cs[c] + pt;
-                if (active && p < pe) fetch(p);
-                for (; active && p < pe; p += nstr) {
-                    uint32_t rr[DK];
+                auto sites = [&](auto body) __attribute__((always_inline)) {
+                    int p = cs[c] + pt;
+                    if (active && p < pe) fetch(p);
+                    for (; active && p < pe; p += nstr) {
+                        uint32_t rr[DK];
 #pragma unroll
-                    for (int u = 0; u < DK; ++u) rr[u] = rn[u];
-                    const int32_t hp = hn, od = on;
-                    if (p + nstr < pe) fetch(p + nstr);
-                    update(p, [&](int u, int) __attribute__((always_inline)) { return rr[u]; }, hp, (uint32_t)od);
-                }
+                        for (int u = 0; u < DK; ++u) rr[u] = rn[u];
+                        const int32_t hp = hn, od = on;
+                        if (p + nstr < pe) fetch(p + nstr);
+                        body(p, rr, hp, (uint32_t)od);
+                    }
+                };
+                if (part)
+                    sites([&](int p, const uint32_t *rr, int32_t hp, uint32_t od)
+                              __attribute__((always_inline)) { update_part(p, rr, hp, od); });
+                else
+                    sites([&](int p, const uint32_t *rr, int32_t hp, uint32_t od) __attribute__((always_inline)) {
+                        update(p, [&](int u, int) __attribute__((always_inline)) { return rr[u]; }, hp, od);
+                    });
             } else {
                 for (int p = cs[c] + pt; active && p < pe; p += nstr) update(p, NBR, HPOS(p), (uint32_t)ORD(p));
             }
             __syncthreads();
             if constexpr (shadow::kOn) shadow_pass(c, false);
         }
+        if (part)
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    if (i < mg && boff + i == b) dE[b] += dEp[i];
         if (pow2) {
 #pragma unroll
             for (int b = 0; b < 4; ++b)
@@ -396,8 +480,14 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
         __syncthreads();
 
         // 2. Replica exchange.
+        // This sweep's pairs (k, k+1) have k of parity par: nin of them lie inside the
+        // group from slot kin on; lo_act / hi_act: the pair across the lower / upper
+        // boundary is one of them.  Each boundary pair comes every other sweep, so
+        // a side publishes every other sweep and its two buffers alternate.
         const int par = (int)(t & 1u);
-        const bool edge = par == 1 && G > 1;
+        const int kin = s0 + ((s0 ^ par) & 1), nin = max(0, (s0 + mg - kin) / 2);
+        const bool lo_act = g > 0 && ((s0 - 1) & 1) == par, hi_act = g < G - 1 && ((s0 + mg - 1) & 1) == par;
+        const bool edge = lo_act || hi_act;
         const int buf = (int)((t >> 1) & 1u);
         // Boundary messages: relaxed agent-scope atomic words, each 16 payload bits
         // under a 16-bit sweep tag (never 0; the area is cleared before the launch).
@@ -417,32 +507,36 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
             }
         };
         if (edge) {
-            // publish the first and last slot of every chain (pre-exchange states, energies)
-            const bool lo_nb = g > 0, hi_nb = g < G - 1;
-            for (int idx = tid; idx < 2 * chains * xmsg; idx += T) {
-                const int sc = idx / xmsg, w = idx - sc * xmsg;
-                const int side = sc / chains, ch = sc - side * chains;
-                if ((side == 0 && !lo_nb) || (side == 1 && !hi_nb)) continue;
-                const int l = ch * mg + (side ? mg - 1 : 0);
-                uint32_t pay;
-                if (w < 4) {
-                    pay = (uint32_t)(((unsigned long long)L_E[l] >> (16 * w)) & 0xFFFFu);
-                } else {
-                    const int p = 2 * (w - 4);
-                    pay = (uint32_t)*sbyte(l, p) | (p + 1 < n ? (uint32_t)*sbyte(l, p + 1) << 8 : 0u);
+            // publish the first / last slot of every chain for an active lower / upper
+            // boundary pair (pre-exchange states, energies)
+            for (int side = 0; side < 2; ++side) {
+                if (side == 0 ? !lo_act : !hi_act) continue;
+                for (int ch = 0; ch < chains; ++ch) {
+                    const int l = ch * mg + (side ? mg - 1 : 0);
+                    const unsigned char *rb = sbyte(l, 0);
+                    uint32_t *dst = msg(g, side, ch);
+                    const unsigned long long El = (unsigned long long)L_E[l];
+                    for (int w = tid; w < xmsg; w += T) {
+                        uint32_t pay;
+                        if (w < 4) {
+                            pay = (uint32_t)((El >> (16 * w)) & 0xFFFFu);
+                        } else {
+                            const uint32_t p = 2u * (uint32_t)(w - 4);
+                            pay = (uint32_t)rb[p * pst] | ((int)p + 1 < n ? (uint32_t)rb[(p + 1u) * pst] << 8 : 0u);
+                        }
+                        __hip_atomic_store(dst + w, tag | pay, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
                 }
-                __hip_atomic_store(msg(g, side, ch) + w, tag | pay, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             __syncthreads();
         }
         {
-            const int nin = (mg - par) / 2;            // pairs inside the group
-            const int per = nin + (edge ? 2 : 0);      // + the two straddling pairs
+            const int per = nin + (edge ? 2 : 0);      // + the straddling pairs
             if (tid < chains * per) {
                 const int ch = tid / per, e = tid - ch * per;
                 const uint32_t cctr = (uint32_t)(run * chains + ch);
                 if (e < nin) {
-                    const int k = s0 + par + 2 * e;
+                    const int k = kin + 2 * e;
                     const int la = ch * mg + (k - s0);
                     const long long Dd = L_E[la] - L_E[la + 1];
                     if (swap_test(Dd, a.stab + (size_t)k * 7 * kDigitSize, a.snd[k], (uint32_t)k, t, cctr, a.k0,
@@ -452,7 +546,7 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                         L_E[la + 1] = x;
                         L_acc[atomicAdd(&nacc, 1)] = la;
                     }
-                } else if ((e == nin && g > 0) || (e == nin + 1 && g < G - 1)) {
+                } else if ((e == nin && lo_act) || (e == nin + 1 && hi_act)) {
                     // the pair straddling a group boundary: (s0 - 1, s0) against the lower
                     // neighbour's last slot, (s0 + mg - 1, s0 + mg) against the upper one's first
                     const int side = e - nin;
@@ -484,48 +578,46 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
         if (stop) break;
         {
             const int na = nacc;
-            for (int idx = tid; idx < n * na; idx += T) {
-                const int pr = idx / n, p = idx - pr * n;
+            for (int pr = 0; pr < na; ++pr) {
                 const int la = L_acc[pr];
-                unsigned char *A = sbyte(la, p), *B = sbyte(la + 1, p);
-                const unsigned char x = *A;
-                *A = *B;
-                *B = x;
+                unsigned char *A = sbyte(la, 0), *B = sbyte(la + 1, 0);
+                for (int p = tid; p < n; p += T) {
+                    const uint32_t o = (uint32_t)p * pst;
+                    const unsigned char x = A[o];
+                    A[o] = B[o];
+                    B[o] = x;
+                }
             }
             if (edge) {
                 // an accepted straddling pair takes the neighbour's published configuration
                 // (kCopyBatch words per thread loaded together; a word whose tag is not
                 // yet the expected one is waited for)
-                const int nwd = xmsg - 4, total = 2 * chains * nwd;
-                for (int i0 = tid; i0 < total; i0 += kCopyBatch * T) {
-                    const uint32_t *src[kCopyBatch];
-                    uint32_t v[kCopyBatch];
+                const int nwd = xmsg - 4;
+                for (int sc = 0; sc < 2 * chains; ++sc) {
+                    if (!L_cin[sc]) continue;
+                    const int side = sc / chains, ch = sc - side * chains;
+                    const uint32_t *src = msg(side == 0 ? g - 1 : g + 1, side == 0 ? 1 : 0, ch) + 4;
+                    unsigned char *rb = sbyte(ch * mg + (side ? mg - 1 : 0), 0);
+                    for (int w0 = tid; w0 < nwd; w0 += kCopyBatch * T) {
+                        uint32_t v[kCopyBatch];
 #pragma unroll
-                    for (int u = 0; u < kCopyBatch; ++u) {
-                        const int idx = i0 + u * T;
-                        src[u] = nullptr;
-                        if (idx < total) {
-                            const int sc = idx / nwd, w = idx - sc * nwd;
-                            if (L_cin[sc]) {
-                                const int side = sc / chains, ch = sc - side * chains;
-                                src[u] = msg(side == 0 ? g - 1 : g + 1, side == 0 ? 1 : 0, ch) + 4 + w;
+                        for (int u = 0; u < kCopyBatch; ++u) {
+                            const int w = w0 + u * T;
+                            v[u] = w < nwd ? __hip_atomic_load(src + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+                        }
+#pragma unroll
+                        for (int u = 0; u < kCopyBatch; ++u) {
+                            const int w = w0 + u * T;
+                            if (w >= nwd) continue;
+                            const int pay = (v[u] & 0xFFFF0000u) == tag ? (int)(v[u] & 0xFFFFu) : recv(src + w);
+                            if (pay < 0) {
+                                stop = 1;
+                                continue;
                             }
+                            const uint32_t p = 2u * (uint32_t)w;
+                            rb[p * pst] = (unsigned char)(pay & 0xFF);
+                            if ((int)p + 1 < n) rb[(p + 1u) * pst] = (unsigned char)(pay >> 8);
                         }
-                        v[u] = src[u] ? __hip_atomic_load(src[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
-                    }
-#pragma unroll
-                    for (int u = 0; u < kCopyBatch; ++u) {
-                        if (!src[u]) continue;
-                        int pay = (v[u] & 0xFFFF0000u) == tag ? (int)(v[u] & 0xFFFFu) : recv(src[u]);
-                        if (pay < 0) {
-                            stop = 1;
-                            continue;
-                        }
-                        const int idx = i0 + u * T, sc = idx / nwd, w = idx - sc * nwd;
-                        const int side = sc / chains, ch = sc - side * chains;
-                        const int l = ch * mg + (side ? mg - 1 : 0), p = 2 * w;
-                        *sbyte(l, p) = (unsigned char)(pay & 0xFF);
-                        if (p + 1 < n) *sbyte(l, p + 1) = (unsigned char)(pay >> 8);
                     }
                 }
             }
@@ -615,10 +707,8 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                         if (lane == 0 && c0 + u * nw < nchunks) L_dmask[(size_t)j * nchunks + c0 + u * nw] = m;
                     }
             }
-            for (int idx = tid; idx < nb * n16; idx += T) {
-                const int j = idx / n16, p = idx - j * n16;
-                L_parent[idx] = (uint16_t)p;
-            }
+            for (int j = 0; j < nb; ++j)
+                for (int p = tid; p < n16; p += T) L_parent[(size_t)j * n16 + p] = (uint16_t)p;
             __syncthreads();
             if (wid < nb) {
                 // seed of pair wid = the target-th disagreeing variable
@@ -813,11 +903,12 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
             }
             if (!cand) continue;
             int8_t *base = a.tops + ((size_t)run * Ls + gl) * 10 * n;
+            const unsigned char *rb = sbyte(l, 0);
             bool dup = false;
             for (int e = 0; e < cnt && !dup; ++e) {
                 if (LE[e] != Ec) continue;
                 bool diff = false;
-                for (int p = lane; p < n; p += 64) diff |= base[(size_t)e * n + p] != (int8_t)*sbyte(l, p);
+                for (int p = lane; p < n; p += 64) diff |= base[(size_t)e * n + p] != (int8_t)rb[(uint32_t)p * pst];
                 dup = !__any(diff);
             }
             if (dup) continue;
@@ -827,7 +918,7 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                 for (int e = 1; e < 10; ++e)
                     if (LE[e] > LE[victim] || (LE[e] == LE[victim] && LW[e] > LW[victim])) victim = e;
             }
-            for (int p = lane; p < n; p += 64) base[(size_t)victim * n + p] = (int8_t)*sbyte(l, p);
+            for (int p = lane; p < n; p += 64) base[(size_t)victim * n + p] = (int8_t)rb[(uint32_t)p * pst];
             __builtin_amdgcn_wave_barrier();
             if (lane == 0) {
                 LE[victim] = Ec;

@@ -7,8 +7,8 @@ per phase:
   lane, streamed, instance in global memory), the general body (x_bound > 255, in LDS and in
   global memory), the batched launch (one-word and paired bodies) and the tempering kernels
   (one workgroup per run; the ladder split over workgroups with the instance in LDS and in
-  global memory, and into groups of 2 slots that own half of each quad word; cluster moves
-  on) and SQA (instance in LDS and in global memory);
+  global memory, and into groups of 2 slots and of 1 slot that own part of each quad word;
+  cluster moves on) and SQA (instance in LDS and in global memory);
 * "one_class": a colouring with every site in one class (edges inside the class), let through
   ingest by SPVAR_SHADOW_ALLOW_COLOUR_EDGES, where every class pass reads neighbours that the
   same pass writes, through SA and through tempering.
@@ -85,7 +85,8 @@ def main():
     for label, env, K in (("pt_one_workgroup", {"SPVAR_PT_SPLIT": 0}, 6),
                           ("pt_split", {"SPVAR_PT_SPLIT": 1, "SPVAR_PT_GROUPS": 2}, 8),
                           ("pt_split_big", {"SPVAR_PT_SPLIT": 1, "SPVAR_PT_GROUPS": 2, "SPVAR_PT_BIG": 1}, 8),
-                          ("pt_split_half_quads", {"SPVAR_PT_SPLIT": 1, "SPVAR_PT_GROUPS": 4}, 8)):
+                          ("pt_split_half_quads", {"SPVAR_PT_SPLIT": 1, "SPVAR_PT_GROUPS": 4}, 8),
+                          ("pt_split_single_slots", {"SPVAR_PT_SPLIT": 1, "SPVAR_PT_GROUPS": 8}, 8)):
         say(f"[shadow] {label}: K={K}")
         betas_pt = si.geometric_betas(0.2, 5.0, K)
         Pc = spv.Problem.from_instance(cube)

@@ -55,6 +55,8 @@ CASES = [
     ("split_K12_G3_big_window", lambda: si.random_sparse(40, 3.0, seed=5), 12, 2, 2, (2, 10), 1, 3, 1),
     ("split_K8_G4_icm_half_quads", lambda: si.cubic_lattice(4, "gauss", seed=6, scale_log2=10), 8, 2, 2, (0, 8), 1,
      4, 0),
+    ("split_K8_G8_icm_single_slots", lambda: si.cubic_lattice(4, "gauss", seed=7, scale_log2=10), 8, 2, 2, (0, 8),
+     1, 8, 0),
 ]
 
 

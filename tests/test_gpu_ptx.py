@@ -61,6 +61,21 @@ CASES = [
     ("zero_sweeps_G4_half_quads", lambda: si.chimera(2, seed=20), 8, 2, 2, 0, (0, 8), 4, 0, 0),
     ("cubic10_K8_G4_icm_half_quads_wide", lambda: si.cubic_lattice(10, "gauss", seed=21, scale_log2=10), 8, 1, 2,
      30, (0, 8), 4, 0, 0),
+    # groups of 1 slot (a quarter of each quad word; the lower and upper boundary pairs on
+    # alternate sweeps)
+    ("cubic4_K8_G8_icm_single_slots", lambda: si.cubic_lattice(4, "gauss", seed=22, scale_log2=10), 8, 2, 2, 80,
+     (0, 8), 8, 0, 0),
+    ("sparse40_K16_G16_icm_single_slots_window_offset", lambda: si.random_sparse(40, 3.0, seed=23), 16, 2, 2, 63,
+     (3, 13), 16, 0, 3),
+    ("cubic4_K12_G12_icm_single_slots_big", lambda: si.cubic_lattice(4, "gauss", seed=24, scale_log2=10), 12, 1, 2,
+     50, (0, 12), 12, 1, 0),
+    ("sparse42_K8_G8_icm_single_slots_ragged_n", lambda: si.random_sparse(42, 3.0, seed=25), 8, 2, 2, 40, (0, 8),
+     8, 0, 1),
+    ("chimera2_K12_G7_icm_single_slots_one_digit", lambda: si.chimera(2, seed=26), 12, 2, 2, 51, (0, 12), 7, 0, 0),
+    ("zero_sweeps_G8_single_slots", lambda: si.chimera(2, seed=27), 8, 2, 2, 0, (0, 8), 8, 0, 0),
+    ("one_sweep_G8_single_slots_odd_offset", lambda: si.chimera(2, seed=28), 8, 2, 2, 1, (0, 8), 8, 0, 1),
+    ("cubic10_K8_G8_icm_single_slots_wide", lambda: si.cubic_lattice(10, "gauss", seed=29, scale_log2=10), 8, 1, 2,
+     30, (0, 8), 8, 0, 0),
     # many waves per workgroup on the cluster moves (1024 threads)
     ("cubic10_K8_G2_icm_wide", lambda: si.cubic_lattice(10, "gauss", seed=10, scale_log2=10), 8, 2, 2, 30,
      (0, 8), 2, 0, 0),
@@ -97,7 +112,7 @@ def test_single_workgroup_kernel_forced(spv, ctx, monkeypatch, K, chains, icm):
 def test_cubic20_pticm_config_shape(spv, ctx):
     """The N=8000 PT-ICM shape (40 slots x 2 chains, Houdayer at every slot,
     one run) on the default plan (instance in global memory, one workgroup per
-    2 slots), a short schedule against the oracle."""
+    slot), a short schedule against the oracle."""
     cfg = cf.CUBIC20_PTICM
     inst = cf.instance(cfg)
     betas = cf.betas(cfg)

@@ -632,6 +632,9 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
         // (the pairs share every neighbour-record fetch).
         const int kb = max(a.icm_lo, s0), ke = min(a.icm_hi, s0 + mg);
         const int nchunks = (n + 63) / 64, vstr = 2 * nchunks, n16 = (n + 1) & ~1;
+        // records per site (compile-time when DK > 0, so record batches stay in registers)
+        const int Dn = DK > 0 ? DK : D;
+        constexpr int KB = DK > 0 ? DK : ptc::kRecBatch;
         const size_t pstride = (size_t)nq * 4;
         for (int kq = kb; a.nw_icm > 0 && kq < ke; kq += a.nw_icm) {
             const int nb = min(a.nw_icm, ke - kq);
@@ -768,25 +771,23 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                     cnt -= m;
                     __builtin_amdgcn_wave_barrier();
                 };
-                for (int p0 = wid * 64; p0 < n; p0 += nw * 64) {
-                    const int p = p0 + lane;
+                auto scan_site = [&](int p, auto rec) __attribute__((always_inline)) {
                     const uint32_t dp = p < n ? dis_bits(p) : 0u;
-                    for (int k0 = 0; k0 < D; k0 += ptc::kRecBatch) {
-                        uint32_t rr[ptc::kRecBatch];
+                    for (int k0 = 0; k0 < Dn; k0 += KB) {
+                        uint32_t rr[KB];
 #pragma unroll
-                        for (int uu = 0; uu < ptc::kRecBatch; ++uu)
-                            rr[uu] = (dp && k0 + uu < D) ? NBR(k0 + uu, p) : 0u;
+                        for (int uu = 0; uu < KB; ++uu) rr[uu] = (dp && k0 + uu < Dn) ? rec(k0 + uu, p) : 0u;
                         // the pairs each edge joins, every neighbour's words read before the joins
-                        uint32_t fb[ptc::kRecBatch];
+                        uint32_t fb[KB];
 #pragma unroll
-                        for (int uu = 0; uu < ptc::kRecBatch; ++uu) {
+                        for (int uu = 0; uu < KB; ++uu) {
                             const int u = (int)(rr[uu] >> 16);
-                            const bool edge_ok = k0 + uu < D && (rr[uu] & 0xffffu) != 0u && u > p;
+                            const bool edge_ok = k0 + uu < Dn && (rr[uu] & 0xffffu) != 0u && u > p;
                             fb[uu] = edge_ok ? (dp & dis_bits(u)) : 0u;
                         }
 #pragma unroll
-                        for (int uu = 0; uu < ptc::kRecBatch; ++uu) {
-                            if (k0 + uu >= D) break;
+                        for (int uu = 0; uu < KB; ++uu) {
+                            if (k0 + uu >= Dn) break;
                             const int u = (int)(rr[uu] >> 16);
 #pragma unroll
                             for (int j = 0; j < kIcmBatch; ++j) {
@@ -803,6 +804,26 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                             }
                         }
                     }
+                };
+                if constexpr (BIG && DK > 0) {
+                    // the records of the wavefront's next 64 sites are in flight while
+                    // the current ones are scanned
+                    uint32_t rn[DK];
+                    auto fetch = [&](int pp) __attribute__((always_inline)) {
+#pragma unroll
+                        for (int u = 0; u < DK; ++u) rn[u] = pp < n ? gnbr[(size_t)pp * DK + u] : 0u;
+                    };
+                    int p0 = wid * 64;
+                    if (p0 < n) fetch(p0 + lane);
+                    for (; p0 < n; p0 += nw * 64) {
+                        uint32_t rr[DK];
+#pragma unroll
+                        for (int u = 0; u < DK; ++u) rr[u] = rn[u];
+                        if (p0 + nw * 64 < n) fetch(p0 + nw * 64 + lane);
+                        scan_site(p0 + lane, [&](int k, int) __attribute__((always_inline)) { return rr[k]; });
+                    }
+                } else {
+                    for (int p0 = wid * 64; p0 < n; p0 += nw * 64) scan_site(p0 + lane, NBR);
                 }
                 if (cnt > 0) run_joins(cnt);
             }
@@ -820,7 +841,7 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
             long long dA[kIcmBatch];
 #pragma unroll
             for (int j = 0; j < kIcmBatch; ++j) dA[j] = 0;
-            for (int p = tid; p < n; p += T) {
+            auto energy_site = [&](int p, auto rec, int32_t hp) __attribute__((always_inline)) {
                 unsigned in = 0;
                 const uint32_t dpb = dis_bits(p);
 #pragma unroll
@@ -828,26 +849,25 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                     if (root[j] != 0xffffffffu && ((dpb >> j) & 1u) &&
                         ptc::uf_find(L_parent + (size_t)j * n16, (uint32_t)p) == root[j])
                         in |= 1u << j;
-                if (!in) continue;
+                if (!in) return;
                 // f = h + sum of J s over the neighbours that agree (those outside the
                 // cluster); replica B's field is the same (it agrees with A there) and its
                 // spin at p is -s_A, so its energy change is -dA: the pair energy is
                 // conserved exactly
-                const int32_t hp = HPOS(p);
                 int32_t fA[kIcmBatch];
 #pragma unroll
                 for (int j = 0; j < kIcmBatch; ++j) fA[j] = hp;
-                for (int k0 = 0; k0 < D; k0 += ptc::kRecBatch) {
-                    uint32_t rr[ptc::kRecBatch];
+                for (int k0 = 0; k0 < Dn; k0 += KB) {
+                    uint32_t rr[KB];
 #pragma unroll
-                    for (int uu = 0; uu < ptc::kRecBatch; ++uu) rr[uu] = k0 + uu < D ? NBR(k0 + uu, p) : 0u;
-                    uint32_t wa[ptc::kRecBatch], db[ptc::kRecBatch];
+                    for (int uu = 0; uu < KB; ++uu) rr[uu] = k0 + uu < Dn ? rec(k0 + uu, p) : 0u;
+                    uint32_t wa[KB], db[KB];
 #pragma unroll
-                    for (int uu = 0; uu < ptc::kRecBatch; ++uu) pair_bytes((int)(rr[uu] >> 16), wa[uu], db[uu]);
+                    for (int uu = 0; uu < KB; ++uu) pair_bytes((int)(rr[uu] >> 16), wa[uu], db[uu]);
 #pragma unroll
-                    for (int uu = 0; uu < ptc::kRecBatch; ++uu) {
+                    for (int uu = 0; uu < KB; ++uu) {
                         const int32_t Jv = (int32_t)(int16_t)(rr[uu] & 0xffffu);
-                        if (k0 + uu >= D || Jv == 0) continue;
+                        if (k0 + uu >= Dn || Jv == 0) continue;
 #pragma unroll
                         for (int j = 0; j < kIcmBatch; ++j)
                             if (((in >> j) & 1u) && !((db[uu] >> j) & 1u))
@@ -862,6 +882,29 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                         atomicOr(&memb[(size_t)j * vstr + (p >> 5)], 1u << (p & 31));
                         dA[j] += -2ll * (int32_t)(int8_t)(wp >> (8 * j)) * (long long)fA[j];
                     }
+            };
+            if constexpr (BIG && DK > 0) {
+                // the records and h of the thread's next site are in flight while the
+                // current one is tested and summed
+                uint32_t rn[DK];
+                int32_t hn = 0;
+                auto fetch = [&](int pp) __attribute__((always_inline)) {
+#pragma unroll
+                    for (int u = 0; u < DK; ++u) rn[u] = gnbr[(size_t)pp * DK + u];
+                    hn = ghpos[pp];
+                };
+                int p = tid;
+                if (p < n) fetch(p);
+                for (; p < n; p += T) {
+                    uint32_t rr[DK];
+#pragma unroll
+                    for (int u = 0; u < DK; ++u) rr[u] = rn[u];
+                    const int32_t hp = hn;
+                    if (p + T < n) fetch(p + T);
+                    energy_site(p, [&](int k, int) __attribute__((always_inline)) { return rr[k]; }, hp);
+                }
+            } else {
+                for (int p = tid; p < n; p += T) energy_site(p, NBR, HPOS(p));
             }
 #pragma unroll
             for (int j = 0; j < kIcmBatch; ++j) {

@@ -624,7 +624,8 @@ def serving_roofline_and_cpu(args, ctx, kinds):
                 "lds": lds_object(upd / (ms / 1e3), pt_lds_bytes_per_update(md, digits, False), probe,
                                   "LDS traffic of the Metropolis updates against the measured LDS peak"),
                 "note": "one PT-ICM request alone (N=8000, 40 betas x 2 chains x 1000 sweeps, Houdayer moves "
-                        "at every slot); a run spans K/4 = 10 workgroups, so each sweep is latency-bound"}
+                        "at every slot); a run spans at most one workgroup per slot (40 of 256 CUs), and its "
+                        "sweeps are a chain of dependent steps"}
     cpu = None
     if not args.no_cpu_baseline:
         import oracle

@@ -333,9 +333,11 @@ spv_status spv_ispvar(spv_ctx *ctx, const spv_problem *P, const double *betas, i
  * states seen (Sec. III.D.1 sample formation).
  * Replica index r = (run * chains + chain) * K + slot (keyed by slot, so the
  * random stream follows the temperature).
- * When K % 4 == 0 a run's ladder may be split over several workgroups that
- * exchange their boundary slots every other sweep (the split is chosen from
- * the run count and the LDS footprint; results do not depend on it).  The
+ * When K % 4 == 0 a run's ladder may be split over several workgroups of
+ * consecutive slots (a multiple of 4 slots each, or with cluster moves on 2 or
+ * 1) that decide the slot pairs straddling their boundaries from energies and
+ * edge states published through global memory (the split is chosen from the
+ * run count and the LDS footprint; results do not depend on it).  The
  * split launch is only made when all its workgroups fit on the device at
  * once; should a workgroup still wait for a neighbour beyond a bounded spin,
  * it stops and writes top_count = -1 for its lists (and spv_top_sample then

@@ -94,7 +94,9 @@ void footprint(spv_server *s, const spv_request &r, const Inst &P, int64_t *lds,
             L = 0;  // the launch itself reports the error
         R = (int64_t)r.runs * r.chains * (r.K / 2) * kTopK;
         H += (int64_t)r.K * row_len * 4 + (int64_t)r.K * 7 * kDigitSize * 4 + R * std::max(P.n, 1);
-        H += (int64_t)r.runs * (r.K / 4) * 4 * r.chains * (int64_t)ptx_msg_words(std::max(P.n, 1)) * 4;
+        // boundary messages: at most K / 4 groups per run, or K with cluster moves on
+        const int64_t gmax = r.icm_hi > r.icm_lo ? r.K : r.K / 4;
+        H += (int64_t)r.runs * gmax * 4 * r.chains * (int64_t)ptx_msg_words(std::max(P.n, 1)) * 4;
         if (r.elite_frac > 0) H += R * (std::max(P.n, 1) + 8);  // assembled sample
     }
     if (r.elite_frac > 0 && R > 0) {

@@ -273,7 +273,9 @@ spv_status upload(Ctx *c, DevBuf &dst, size_t dst_off, const void *src, size_t b
 // beyond K / 2 groups, of 1 slot: every group's cluster-move work shrinks with
 // its slot count.  SPVAR_PT_SPLIT=0 disables the
 // split, =1 forces it (K % 4 == 0); SPVAR_PT_GROUPS fixes G; SPVAR_PT_BIG=1
-// reads the instance from global memory even when it would fit in LDS.
+// reads the instance from global memory even when it would fit in LDS;
+// SPVAR_PT_ESUM=0 keeps a group with one slot pair on the separate cluster
+// energy pass.
 static int env_int(const char *name, int dflt) {
     const char *v = getenv(name);
     return v && *v ? atoi(v) : dflt;
@@ -303,8 +305,9 @@ spv_status plan_pt_split(Ctx *c, int n, int D, int K, int runs, int chains, int 
         if (threads > 1024) continue;
         const int icm_slots = icm_hi > icm_lo ? std::min(m, icm_hi - icm_lo) : 0;
         for (int big = env_int("SPVAR_PT_BIG", 0) ? 1 : 0; big < 2; ++big) {
-            for (int nw = std::min(icm_slots, 4); nw >= (icm_slots ? 1 : 0); --nw) {
-                const size_t lds = ptx_lds_bytes(n, D, m, chains, row_len, nw, big != 0) + 256;
+            for (int nw = std::min(icm_slots, 4); nw >= (icm_slots ? 1 : 0); --nw)
+            for (int esum = nw == 1 && env_int("SPVAR_PT_ESUM", 1) ? 1 : 0; esum >= 0; --esum) {
+                const size_t lds = ptx_lds_bytes(n, D, m, chains, row_len, nw, big != 0, esum != 0) + 256;
                 if (lds > c->lds_max) continue;
                 int bpc = 0;
                 hipError_t e = ptx_max_groups_resident(nd, big != 0, D, threads, lds, &bpc);
@@ -317,6 +320,7 @@ spv_status plan_pt_split(Ctx *c, int n, int D, int K, int runs, int chains, int 
                 sp->m = m;
                 sp->threads = threads;
                 sp->nw_icm = nw;
+                sp->esum = esum != 0;
                 sp->big = big != 0;
                 return SPV_OK;
             }
@@ -338,7 +342,7 @@ spv_status pt_lds_footprint(Ctx *c, const Inst *P, int K, int runs, int chains, 
                                   lds <= c->lds_max, &sp);
     if (st) return st;
     if (sp.use)
-        *lds_total = (int64_t)runs * sp.G * (int64_t)(ptx_lds_bytes(n, D, sp.m, chains, row_len, sp.nw_icm, sp.big) + 256);
+        *lds_total = (int64_t)runs * sp.G * (int64_t)(ptx_lds_bytes(n, D, sp.m, chains, row_len, sp.nw_icm, sp.big, sp.esum) + 256);
     else
         *lds_total = (int64_t)runs * (int64_t)lds;
     return SPV_OK;
@@ -1024,6 +1028,7 @@ spv_status pt_inst(spv_ctx *ctx, const Inst *P, const spv_pt_params *prm, const 
         X.icm_lo = icm ? prm->icm_lo : 0;
         X.icm_hi = icm ? prm->icm_hi : 0;
         X.nw_icm = sp.nw_icm;
+        X.esum = sp.esum;
         X.mtab = reinterpret_cast<const uint32_t *>(base);
         X.row_len = row_len;
         X.nd = nd;

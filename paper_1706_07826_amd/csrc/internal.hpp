@@ -379,11 +379,12 @@ struct PtxLaunch {
     uint32_t *xw;             // [runs][G][2][2][chains][ptx_msg_words(n)]
     int G, m, threads;
     bool big;
+    bool esum;                // one slot pair per group: cluster energy terms gathered in the joins
     unsigned spin_limit;
     PtResume resume;
 };
 struct PtSplit {
-    bool use = false, big = false;
+    bool use = false, big = false, esum = false;
     int G = 1, m = 0, threads = 256, nw_icm = 0;
 };
 spv_status plan_pt_split(Ctx *c, int n, int D, int K, int runs, int chains, int row_len, int nd, int icm_lo,
@@ -392,7 +393,7 @@ unsigned pt_spin_limit();
 // LDS claimed by one spv_pt_sample launch with the shapes it would pick.
 spv_status pt_lds_footprint(Ctx *c, const Inst *P, int K, int runs, int chains, int icm_lo, int icm_hi,
                             int64_t *lds_total);
-size_t ptx_lds_bytes(int n, int D, int m, int chains, int row_len, int nw_icm, bool big);
+size_t ptx_lds_bytes(int n, int D, int m, int chains, int row_len, int nw_icm, bool big, bool esum);
 int ptx_msg_words(int n);
 hipError_t ptx_max_groups_resident(int nd, bool big, int D, int threads, size_t lds, int *blocks_per_cu);
 hipError_t launch_ptx(const PtxLaunch &L, hipStream_t s);

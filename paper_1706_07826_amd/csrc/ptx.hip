@@ -58,7 +58,7 @@ struct PtxArgs {
     int8_t *tops;          // [runs][Ls][10][n], position order
     uint32_t *xw;          // [runs][G][side 2][buf 2][chains][xmsg] tagged boundary messages
     PtResume rs;           // checkpoint to start from
-    int n, D, C, K, chains, sweeps, row_len, icm_lo, icm_hi, nw_icm, G, m, xmsg;
+    int n, D, C, K, chains, sweeps, row_len, icm_lo, icm_hi, nw_icm, G, m, xmsg, esum;
     uint32_t sweep_offset, k0, k1;
     unsigned spin_limit;
 };
@@ -84,13 +84,14 @@ struct PtxLds {
     int32_t *misc;             // [4] broadcast scalars
     uint32_t *ubuf;            // [16 waves][kJoinBuf] pending joins: site | neighbour << 16
     unsigned char *ubj;        // [16 waves][kJoinBuf] their slot pair
+    int32_t *esite;            // [n] one slot pair's cluster energy terms (esum)
 };
 
 // Pending-join buffer per wavefront (64 appended at most on top of < 64 pending).
 constexpr int kJoinBuf = 128;
 
 __host__ __device__ inline size_t ptx_layout(int n, int D, int m, int chains, int row_len, int nw_icm, bool big,
-                                             PtxLds *L, unsigned char *base) {
+                                             bool esum, PtxLds *L, unsigned char *base) {
     const int nq = chains * ((m + 3) / 4), nl = chains * m, vstride = 2 * ((n + 63) / 64);
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -106,7 +107,8 @@ __host__ __device__ inline size_t ptx_layout(int n, int D, int m, int chains, in
                  o_acc = take((size_t)nl * 4),
                  o_cin = take((size_t)2 * chains * 4), o_par = take((size_t)nw_icm * ((n + 1) & ~1) * 2),
                  o_dm = take((size_t)nw_icm * vstride * 4), o_misc = take(16),
-                 o_ub = take(nw_icm ? (size_t)16 * kJoinBuf * 4 : 0), o_uj = take(nw_icm ? (size_t)16 * kJoinBuf : 0);
+                 o_ub = take(nw_icm ? (size_t)16 * kJoinBuf * 4 : 0), o_uj = take(nw_icm ? (size_t)16 * kJoinBuf : 0),
+                 o_es = take(esum ? (size_t)n * 4 : 0);
     if (L) {
         L->nbr = reinterpret_cast<uint32_t *>(base + o_nbr);
         L->hpos = reinterpret_cast<int32_t *>(base + o_h);
@@ -128,6 +130,7 @@ __host__ __device__ inline size_t ptx_layout(int n, int D, int m, int chains, in
         L->misc = reinterpret_cast<int32_t *>(base + o_misc);
         L->ubuf = reinterpret_cast<uint32_t *>(base + o_ub);
         L->ubj = base + o_uj;
+        L->esite = reinterpret_cast<int32_t *>(base + o_es);
     }
     return o;
 }
@@ -152,7 +155,7 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
     __shared__ int stop;
     const int n = a.n, D = a.D, K = a.K, chains = a.chains, G = a.G, row_len = a.row_len, xmsg = a.xmsg;
     PtxLds Lay;
-    ptx_layout(n, D, a.m, chains, row_len, a.nw_icm, BIG, &Lay, smem);
+    ptx_layout(n, D, a.m, chains, row_len, a.nw_icm, BIG, a.esum != 0, &Lay, smem);
     // LDS regions as plain locals (keeps the layout record out of scratch memory)
     auto *const L_nbr = Lay.nbr;
     auto *const L_hpos = Lay.hpos;
@@ -174,6 +177,7 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
     auto *const L_misc = Lay.misc;
     auto *const L_ubuf = Lay.ubuf;
     auto *const L_ubj = Lay.ubj;
+    auto *const L_es = Lay.esite;
     const int tid = threadIdx.x, T = blockDim.x, lane = dev::lane_id(), wid = tid >> 6, nw = T >> 6;
     const int run = blockIdx.x / G, g = blockIdx.x - run * G;
     // boff: byte of the quad word holding the group's first slot (0 when m is a
@@ -634,6 +638,11 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
         const int nchunks = (n + 63) / 64, vstr = 2 * nchunks, n16 = (n + 1) & ~1;
         // records per site (compile-time when DK > 0, so record batches stay in registers)
         const int Dn = DK > 0 ? DK : D;
+        // One slot pair per pass (esum): the join scan also gathers, for every
+        // disagreeing site v, E_v = sum of J s_v s_u over its agreeing neighbours u in
+        // replica A, so the energy pass needs no neighbour reads (a cluster's change is
+        // -2 sum over its sites of s_v h_v + E_v, as in the general pass below).
+        const bool esum = a.esum != 0;
         constexpr int KB = DK > 0 ? DK : ptc::kRecBatch;
         const size_t pstride = (size_t)nq * 4;
         for (int kq = kb; a.nw_icm > 0 && kq < ke; kq += a.nw_icm) {
@@ -712,6 +721,8 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
             }
             for (int j = 0; j < nb; ++j)
                 for (int p = tid; p < n16; p += T) L_parent[(size_t)j * n16 + p] = (uint16_t)p;
+            if (esum)
+                for (int p = tid; p < n; p += T) L_es[p] = 0;
             __syncthreads();
             if (wid < nb) {
                 // seed of pair wid = the target-th disagreeing variable
@@ -772,18 +783,38 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                     __builtin_amdgcn_wave_barrier();
                 };
                 auto scan_site = [&](int p, auto rec) __attribute__((always_inline)) {
-                    const uint32_t dp = p < n ? dis_bits(p) : 0u;
+                    uint32_t dp = 0, ap = 0;
+                    if (esum) {
+                        if (p < n) pair_bytes(p, ap, dp);
+                    } else {
+                        dp = p < n ? dis_bits(p) : 0u;
+                    }
+                    // with esum every site's edges are read (an agreeing site may border a
+                    // disagreeing one)
+                    const bool need = esum ? p < n : dp != 0u;
                     for (int k0 = 0; k0 < Dn; k0 += KB) {
                         uint32_t rr[KB];
 #pragma unroll
-                        for (int uu = 0; uu < KB; ++uu) rr[uu] = (dp && k0 + uu < Dn) ? rec(k0 + uu, p) : 0u;
+                        for (int uu = 0; uu < KB; ++uu) rr[uu] = (need && k0 + uu < Dn) ? rec(k0 + uu, p) : 0u;
                         // the pairs each edge joins, every neighbour's words read before the joins
                         uint32_t fb[KB];
 #pragma unroll
                         for (int uu = 0; uu < KB; ++uu) {
                             const int u = (int)(rr[uu] >> 16);
                             const bool edge_ok = k0 + uu < Dn && (rr[uu] & 0xffffu) != 0u && u > p;
-                            fb[uu] = edge_ok ? (dp & dis_bits(u)) : 0u;
+                            if (esum) {
+                                uint32_t au = 0, du = 0;
+                                if (edge_ok) pair_bytes(u, au, du);
+                                fb[uu] = dp & du;
+                                if (edge_ok && ((dp ^ du) & 1u)) {
+                                    // an edge with one disagreeing end: its term goes to that end
+                                    const int32_t Jv = (int32_t)(int16_t)(rr[uu] & 0xffffu);
+                                    const int32_t prod = Jv * (int32_t)(int8_t)(ap & 0xFFu) * (int32_t)(int8_t)(au & 0xFFu);
+                                    atomicAdd(&L_es[(dp & 1u) ? p : u], prod);
+                                }
+                            } else {
+                                fb[uu] = edge_ok ? (dp & dis_bits(u)) : 0u;
+                            }
                         }
 #pragma unroll
                         for (int uu = 0; uu < KB; ++uu) {
@@ -883,28 +914,52 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                         dA[j] += -2ll * (int32_t)(int8_t)(wp >> (8 * j)) * (long long)fA[j];
                     }
             };
-            if constexpr (BIG && DK > 0) {
-                // the records and h of the thread's next site are in flight while the
-                // current one is tested and summed
-                uint32_t rn[DK];
-                int32_t hn = 0;
-                auto fetch = [&](int pp) __attribute__((always_inline)) {
-#pragma unroll
-                    for (int u = 0; u < DK; ++u) rn[u] = gnbr[(size_t)pp * DK + u];
-                    hn = ghpos[pp];
+            if (esum) {
+                // the seed's cluster: its disagreeing sites whose root is the seed's
+                auto esite = [&](int p, int32_t hp) __attribute__((always_inline)) {
+                    uint32_t wp, dbp;
+                    pair_bytes(p, wp, dbp);
+                    if (root[0] == 0xffffffffu || !(dbp & 1u)) return;
+                    if (ptc::uf_find(L_parent, (uint32_t)p) != root[0]) return;
+                    atomicOr(&memb[p >> 5], 1u << (p & 31));
+                    dA[0] += -2ll * ((long long)(int8_t)(wp & 0xFFu) * hp + (long long)L_es[p]);
                 };
-                int p = tid;
-                if (p < n) fetch(p);
-                for (; p < n; p += T) {
-                    uint32_t rr[DK];
-#pragma unroll
-                    for (int u = 0; u < DK; ++u) rr[u] = rn[u];
-                    const int32_t hp = hn;
-                    if (p + T < n) fetch(p + T);
-                    energy_site(p, [&](int k, int) __attribute__((always_inline)) { return rr[k]; }, hp);
+                if constexpr (BIG) {
+                    // the next site's bias is in flight while the current one is tested
+                    int p = tid;
+                    int32_t hn = p < n ? ghpos[p] : 0;
+                    for (; p < n; p += T) {
+                        const int32_t hp = hn;
+                        if (p + T < n) hn = ghpos[p + T];
+                        esite(p, hp);
+                    }
+                } else {
+                    for (int p = tid; p < n; p += T) esite(p, HPOS(p));
                 }
             } else {
-                for (int p = tid; p < n; p += T) energy_site(p, NBR, HPOS(p));
+                if constexpr (BIG && DK > 0) {
+                    // the records and h of the thread's next site are in flight while the
+                    // current one is tested and summed
+                    uint32_t rn[DK];
+                    int32_t hn = 0;
+                    auto fetch = [&](int pp) __attribute__((always_inline)) {
+#pragma unroll
+                        for (int u = 0; u < DK; ++u) rn[u] = gnbr[(size_t)pp * DK + u];
+                        hn = ghpos[pp];
+                    };
+                    int p = tid;
+                    if (p < n) fetch(p);
+                    for (; p < n; p += T) {
+                        uint32_t rr[DK];
+#pragma unroll
+                        for (int u = 0; u < DK; ++u) rr[u] = rn[u];
+                        const int32_t hp = hn;
+                        if (p + T < n) fetch(p + T);
+                        energy_site(p, [&](int k, int) __attribute__((always_inline)) { return rr[k]; }, hp);
+                    }
+                } else {
+                    for (int p = tid; p < n; p += T) energy_site(p, NBR, HPOS(p));
+                }
             }
 #pragma unroll
             for (int j = 0; j < kIcmBatch; ++j) {
@@ -1060,8 +1115,8 @@ void *ptx_fn(int nd, bool big, int D) {
 
 int ptx_msg_words(int n) { return 4 + (n + 1) / 2; }
 
-size_t ptx_lds_bytes(int n, int D, int m, int chains, int row_len, int nw_icm, bool big) {
-    return ptx_layout(n, D, m, chains, row_len, nw_icm, big, nullptr, nullptr);
+size_t ptx_lds_bytes(int n, int D, int m, int chains, int row_len, int nw_icm, bool big, bool esum) {
+    return ptx_layout(n, D, m, chains, row_len, nw_icm, big, esum, nullptr, nullptr);
 }
 
 hipError_t ptx_max_groups_resident(int nd, bool big, int D, int threads, size_t lds, int *blocks_per_cu) {
@@ -1095,6 +1150,7 @@ hipError_t launch_ptx(const PtxLaunch &P, hipStream_t s) {
     a.icm_lo = P.icm_lo;
     a.icm_hi = P.icm_hi;
     a.nw_icm = P.nw_icm;
+    a.esum = P.esum ? 1 : 0;
     a.G = P.G;
     a.m = P.m;
     a.sweep_offset = P.sweep_offset;
@@ -1108,7 +1164,7 @@ hipError_t launch_ptx(const PtxLaunch &P, hipStream_t s) {
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    const size_t lds = ptx_lds_bytes(P.n, P.D, P.m, P.chains, P.row_len, P.nw_icm, P.big);
+    const size_t lds = ptx_lds_bytes(P.n, P.D, P.m, P.chains, P.row_len, P.nw_icm, P.big, P.esum);
     void *f = ptx_fn(P.nd, P.big, P.D);
     if (!f) return hipErrorInvalidValue;
     void *args[] = {&a};

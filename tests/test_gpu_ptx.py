@@ -98,6 +98,22 @@ def test_split_pt_parity(spv, ctx, monkeypatch, name, make, K, runs, chains, swe
     _check(got, want)
 
 
+@pytest.mark.parametrize("esum", ["0", "1"])
+def test_single_slot_groups_with_and_without_gathered_cluster_terms(spv, ctx, monkeypatch, esum):
+    """Groups of one slot pair either gather each disagreeing site's cluster energy term in the
+    join scan (the default) or run the separate energy pass over the records: both bit for bit
+    against the oracle."""
+    inst = si.cubic_lattice(5, "gauss", seed=31, scale_log2=10)
+    monkeypatch.setenv("SPVAR_PT_SPLIT", "1")
+    monkeypatch.setenv("SPVAR_PT_GROUPS", "12")
+    monkeypatch.setenv("SPVAR_PT_ESUM", esum)
+    P = spv.Problem.from_instance(inst)
+    betas = si.geometric_betas(0.2, 5.0, 12)
+    got = spv.spv_pt_sample(ctx, P, betas, 2, 2, 60, seed=77, icm=(0, 12))
+    want = oracle.pt_sample(inst, betas, 2, 2, 60, seed=77, icm=(0, 12), threads=4)
+    _check(got, want)
+
+
 @pytest.mark.parametrize("K,chains,icm", [(8, 1, None), (8, 2, (0, 8)), (12, 2, (3, 9))])
 def test_single_workgroup_kernel_forced(spv, ctx, monkeypatch, K, chains, icm):
     monkeypatch.setenv("SPVAR_PT_SPLIT", "0")

@@ -763,7 +763,8 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
             __syncthreads();
             // The masks are consumed: their words now collect cluster membership.
             uint32_t *const memb = reinterpret_cast<uint32_t *>(L_dmask);
-            for (int wd = tid; wd < nb * vstr; wd += T) memb[wd] = 0u;
+            if (!esum)
+                for (int wd = tid; wd < nb * vstr; wd += T) memb[wd] = 0u;
             // join the endpoints of every J != 0 edge between disagreeing sites.  Each
             // wavefront scans 64 sites at a time and appends the qualifying
             // (pair, site, neighbour) joins to its own LDS buffer; whenever 64 are
@@ -921,8 +922,10 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                     pair_bytes(p, wp, dbp);
                     if (root[0] == 0xffffffffu || !(dbp & 1u)) return;
                     if (ptc::uf_find(L_parent, (uint32_t)p) != root[0]) return;
-                    atomicOr(&memb[p >> 5], 1u << (p & 31));
                     dA[0] += -2ll * ((long long)(int8_t)(wp & 0xFFu) * hp + (long long)L_es[p]);
+                    // no other thread reads this site's bytes in this pass: flip it here
+                    pa[0][(size_t)p * pstride] = (unsigned char)(-(int)(int8_t)pa[0][(size_t)p * pstride]);
+                    pb[0][(size_t)p * pstride] = (unsigned char)(-(int)(int8_t)pb[0][(size_t)p * pstride]);
                 };
                 if constexpr (BIG) {
                     // the next site's bias is in flight while the current one is tested
@@ -972,8 +975,8 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                 }
             }
             __syncthreads();
-            // flip the clusters in both replicas
-            for (int p = tid; p < n; p += T)
+            // flip the clusters in both replicas (the gathered-terms pass flipped its own)
+            for (int p = tid; !esum && p < n; p += T)
 #pragma unroll
                 for (int j = 0; j < kIcmBatch; ++j)
                     if (j < nb && ((memb[(size_t)j * vstr + (p >> 5)] >> (p & 31)) & 1u)) {

@@ -298,7 +298,7 @@ spv_status plan_pt_split(Ctx *c, int n, int D, int K, int runs, int chains, int 
             return set_err(c, SPV_ECAPACITY, "PT run does not fit even split into %d groups (n=%d)", maxg, n);
         const int m = G > K / 2 ? 1 : G > quads ? 2 : 4 * ((quads + G - 1) / G);
         const int Gr = (K + m - 1) / m;
-        const int nq = chains * ((m + 3) / 4);
+        const int nq = chains * ((m + 3) / 4);  // (one word per site when packed: fewer tasks)
         const long long tasks = (long long)n * nq;
         int threads = env_int("SPVAR_PT_THREADS", tasks >= 1536 ? 1024 : tasks >= 768 ? 512 : 256);
         while (threads < nq) threads *= 2;

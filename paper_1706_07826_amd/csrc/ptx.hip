@@ -92,7 +92,8 @@ constexpr int kJoinBuf = 128;
 
 __host__ __device__ inline size_t ptx_layout(int n, int D, int m, int chains, int row_len, int nw_icm, bool big,
                                              bool esum, PtxLds *L, unsigned char *base) {
-    const int nq = chains * ((m + 3) / 4), nl = chains * m, vstride = 2 * ((n + 63) / 64);
+    const int nq = (big && m == 1 && chains == 2) ? 1 : chains * ((m + 3) / 4), nl = chains * m,
+              vstride = 2 * ((n + 63) / 64);
     size_t o = 0;
     auto take = [&](size_t bytes) {
         size_t at = o;
@@ -182,8 +183,12 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
     const int run = blockIdx.x / G, g = blockIdx.x - run * G;
     // boff: byte of the quad word holding the group's first slot (0 when m is a
     // multiple of 4)
-    const int s0 = g * a.m, mg = min(a.m, K - s0), boff = s0 & 3, qpc = (boff + mg + 3) >> 2, nq = chains * qpc,
-              nl = chains * mg;
+    const int s0 = g * a.m, mg = min(a.m, K - s0), boff = s0 & 3, qpc = (boff + mg + 3) >> 2;
+    // pk: a group of one slot (cluster moves on, two chains) reading its instance from
+    // the global image keeps both chains' bytes of its slot in one word per site,
+    // chain c in byte c (with the instance in LDS the layout stays one word per chain)
+    const bool pk = BIG && mg == 1 && chains == 2;
+    const int nq = pk ? 1 : chains * qpc, nl = chains * mg;
     const int32_t *img = a.image;
     const uint32_t *gnbr = reinterpret_cast<const uint32_t *>(img + kImgHeader + 3 * n);
     const int32_t *gord = img + kImgHeader, *gpos = img + kImgHeader + n, *ghpos = img + kImgHeader + 2 * n;
@@ -203,6 +208,7 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
     auto POS = [=](int i) __attribute__((always_inline)) -> int32_t { return BIG ? gpos[i] : lpos[i]; };
     // byte of local replica l = chain * mg + (slot - s0) at position p
     auto sbyte = [=](int l, int p) __attribute__((always_inline)) -> unsigned char * {
+        if (pk) return Sb + (size_t)p * 4 + l;
         const int ch = l / mg, o = l - ch * mg + boff;
         return Sb + ((size_t)p * nq + ch * qpc + (o >> 2)) * 4 + (o & 3);
     };
@@ -261,6 +267,11 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
     const bool active = pt < nstr;
     const int chq = q / qpc, jq = q - chq * qpc;
     const uint32_t quad = (uint32_t)((((size_t)run * chains + chq) * K + s0) / 4 + jq);
+    // pk: chain 1's quad (byte 1 of the word draws its word boff from that quad's block)
+    const uint32_t quad1 = (uint32_t)((((size_t)run * chains + 1) * K + s0) / 4);
+    auto wsel = [](const dev::Words4 &w, int i) __attribute__((always_inline)) -> uint32_t {
+        return i == 0 ? w.w[0] : i == 1 ? w.w[1] : i == 2 ? w.w[2] : w.w[3];
+    };
     // byte b of the thread's word is the group's local slot 4 jq + b - boff; own marks
     // (0xFE) the bytes that are the group's
     int loc[4];
@@ -273,17 +284,29 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
         own |= mine ? 0xFEu << (8 * b) : 0u;
         loc[b] = chq * mg + (mine ? o : 0);
         tb[b] = L_tab + (size_t)(mine ? o : 0) * row_len;
+        if (pk) {
+            // byte b < 2: chain b of the group's slot (local replica b), table row 0
+            loc[b] = b < 2 ? b : 0;
+            tb[b] = L_tab;
+        }
     }
+    if (pk) own = 0xFEFEu;
     const bool pow2 = (nq & (nq - 1)) == 0 && nq <= 64;
     // the group owns 1 or 2 bytes of each of its words (the same bytes in every word)
-    const bool part = qpc == 1 && mg < 4;
+    const bool part = !pk && qpc == 1 && mg < 4;
 
     // Initial state and energies.
     for (int p = pt; active && p < n; p += nstr) {
         const dev::Words4 w = dev::philox((uint32_t)ORD(p), 0u, quad, 1u << 24, a.k0, a.k1);
         uint32_t word = 0;
+        if (pk) {
+            const dev::Words4 w1 = dev::philox((uint32_t)ORD(p), 0u, quad1, 1u << 24, a.k0, a.k1);
+            word = ((wsel(w, boff) >> 31) ? 0x01u : 0xFFu) | (((wsel(w1, boff) >> 31) ? 0x01u : 0xFFu) << 8) |
+                   0x01010000u;
+        } else {
 #pragma unroll
-        for (int b = 0; b < 4; ++b) word |= ((w.w[b] >> 31) ? 0x01u : 0xFFu) << (8 * b);
+            for (int b = 0; b < 4; ++b) word |= ((w.w[b] >> 31) ? 0x01u : 0xFFu) << (8 * b);
+        }
         L_S[(size_t)p * nq + q] = word;
     }
     __syncthreads();
@@ -424,6 +447,56 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                     }
                 if (mask) L_S[(size_t)p * nq + q] = self ^ mask;
             };
+            // pk: bytes 0 and 1 of the site's word are chains 0 and 1 of the group's slot;
+            // each draws word boff of its own chain's quad block, digit by digit.
+            auto update_pk = [&](int p, auto rec, int32_t hp, uint32_t ord) __attribute__((always_inline)) {
+                const uint32_t self = L_S[p];
+                int32_t f[4];
+                ptc::quad_fields<DK>(rec, D, p, L_S, 1, 0, hp, f);
+                uint32_t k0 = a.k0, k1 = a.k1;
+#ifdef __OPTIMIZE__
+                asm volatile("" : "+s"(k0), "+s"(k1));
+#endif
+                int32_t x[2];
+                uint32_t d[2], th[2];
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    x[i] = dev::spin_of(self, i) > 0 ? -f[i] : f[i];
+                    d[i] = x[i] > 0 ? ((uint32_t)x[i] & (kDigitSize - 1)) : 0u;
+                    th[i] = L_tab[d[i]];
+                }
+                bool acc[2];
+                {
+                    const dev::Words4 w0 = dev::philox(ord, t, quad, 2u << 24, k0, k1);
+                    const dev::Words4 w1 = dev::philox(ord, t, quad1, 2u << 24, k0, k1);
+                    acc[0] = (d[0] == 0) | (wsel(w0, boff) < th[0]);
+                    acc[1] = (d[1] == 0) | (wsel(w1, boff) < th[1]);
+                }
+#pragma unroll
+                for (int j = 1; j < ND; ++j) {
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) {
+                        d[i] = x[i] > 0 ? (((uint32_t)x[i] >> (kDigitBits * j)) & (kDigitSize - 1)) : 0u;
+                        th[i] = L_tab[j * kDigitSize + d[i]];
+                    }
+                    if (d[0] != 0) {
+                        const dev::Words4 w = dev::philox(ord, t, quad, (2u << 24) | (uint32_t)j, k0, k1);
+                        if (wsel(w, boff) >= th[0]) acc[0] = false;
+                    }
+                    if (d[1] != 0) {
+                        const dev::Words4 w = dev::philox(ord, t, quad1, (2u << 24) | (uint32_t)j, k0, k1);
+                        if (wsel(w, boff) >= th[1]) acc[1] = false;
+                    }
+                }
+                uint32_t mask = 0;
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+                    if (acc[i]) {
+                        mask |= 0xFEu << (8 * i);
+                        dEp[i] += 2ll * x[i];
+                    }
+                if (mask) L_S[p] = self ^ mask;
+            };
             if constexpr (BIG && DK > 0) {
                 // Records, h and index of a site come from global memory: those of the
                 // thread's next site are in flight while the current one is updated.
@@ -447,13 +520,19 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                         body(p, rr, hp, (uint32_t)od);
                     }
                 };
-                if (part)
+                if (pk)
+                    sites([&](int p, const uint32_t *rr, int32_t hp, uint32_t od) __attribute__((always_inline)) {
+                        update_pk(p, [&](int u, int) __attribute__((always_inline)) { return rr[u]; }, hp, od);
+                    });
+                else if (part)
                     sites([&](int p, const uint32_t *rr, int32_t hp, uint32_t od)
                               __attribute__((always_inline)) { update_part(p, rr, hp, od); });
                 else
                     sites([&](int p, const uint32_t *rr, int32_t hp, uint32_t od) __attribute__((always_inline)) {
                         update(p, [&](int u, int) __attribute__((always_inline)) { return rr[u]; }, hp, od);
                     });
+            } else if (pk) {
+                for (int p = cs[c] + pt; active && p < pe; p += nstr) update_pk(p, NBR, HPOS(p), (uint32_t)ORD(p));
             } else {
                 for (int p = cs[c] + pt; active && p < pe; p += nstr) update(p, NBR, HPOS(p), (uint32_t)ORD(p));
             }
@@ -466,6 +545,10 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
 #pragma unroll
                 for (int b = 0; b < 4; ++b)
                     if (i < mg && boff + i == b) dE[b] += dEp[i];
+        if (pk) {
+            dE[0] += dEp[0];
+            dE[1] += dEp[1];
+        }
         if (pow2) {
 #pragma unroll
             for (int b = 0; b < 4; ++b)
@@ -651,8 +734,8 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
 #pragma unroll
             for (int j = 0; j < kIcmBatch; ++j) {
                 const int o = min(kq + j, ke - 1) - s0 + boff;
-                pa[j] = Sb + (size_t)(o >> 2) * 4 + (o & 3);
-                pb[j] = Sb + (size_t)(qpc + (o >> 2)) * 4 + (o & 3);
+                pa[j] = pk ? Sb : Sb + (size_t)(o >> 2) * 4 + (o & 3);
+                pb[j] = pk ? Sb + 1 : Sb + (size_t)(qpc + (o >> 2)) * 4 + (o & 3);
             }
             auto dis = [=](int j, int p) __attribute__((always_inline)) -> bool {
                 return pa[j][(size_t)p * pstride] != pb[j][(size_t)p * pstride];
@@ -666,6 +749,13 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
             // Chain 0's spin bytes of the batch's pairs at position p (byte j: pair j) and
             // their disagreement bits.
             auto pair_bytes = [=](int p, uint32_t &wa, uint32_t &db) __attribute__((always_inline)) {
+                if (pk) {
+                    // one word: chain 0's byte, then chain 1's
+                    const uint32_t w = L_S[p];
+                    wa = w & 0xFFu;
+                    db = ((w ^ (w >> 8)) >> 1) & 1u;
+                    return;
+                }
                 if (word_dis) {
                     const uint32_t w0 = L_S[(size_t)p * nq + qa0], w1 = L_S[(size_t)p * nq + qpc + qa0];
                     wa = w0 >> (8 * off0);
@@ -685,6 +775,10 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                 }
             };
             auto dis_bits = [=](int p) __attribute__((always_inline)) -> uint32_t {
+                if (pk) {
+                    const uint32_t w = L_S[p];
+                    return ((w ^ (w >> 8)) >> 1) & 1u;
+                }
                 if (word_dis) {
                     const uint32_t x =
                         (L_S[(size_t)p * nq + qa0] ^ L_S[(size_t)p * nq + qpc + qa0]) >> (8 * off0);

@@ -877,6 +877,10 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                     cnt -= m;
                     __builtin_amdgcn_wave_barrier();
                 };
+                // Every edge is taken from its smaller end, and the last colour class (the
+                // highest positions; no edge joins two sites of one class) has none: the
+                // scan stops where that class begins.
+                const int scan_end = a.C > 0 ? min(n, cs[a.C - 1]) : 0;
                 auto scan_site = [&](int p, auto rec) __attribute__((always_inline)) {
                     uint32_t dp = 0, ap = 0;
                     if (esum) {
@@ -940,16 +944,16 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                         for (int u = 0; u < DK; ++u) rn[u] = pp < n ? gnbr[(size_t)pp * DK + u] : 0u;
                     };
                     int p0 = wid * 64;
-                    if (p0 < n) fetch(p0 + lane);
-                    for (; p0 < n; p0 += nw * 64) {
+                    if (p0 < scan_end) fetch(p0 + lane);
+                    for (; p0 < scan_end; p0 += nw * 64) {
                         uint32_t rr[DK];
 #pragma unroll
                         for (int u = 0; u < DK; ++u) rr[u] = rn[u];
-                        if (p0 + nw * 64 < n) fetch(p0 + nw * 64 + lane);
+                        if (p0 + nw * 64 < scan_end) fetch(p0 + nw * 64 + lane);
                         scan_site(p0 + lane, [&](int k, int) __attribute__((always_inline)) { return rr[k]; });
                     }
                 } else {
-                    for (int p0 = wid * 64; p0 < n; p0 += nw * 64) scan_site(p0 + lane, NBR);
+                    for (int p0 = wid * 64; p0 < scan_end; p0 += nw * 64) scan_site(p0 + lane, NBR);
                 }
                 if (cnt > 0) run_joins(cnt);
             }

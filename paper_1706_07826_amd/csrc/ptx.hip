@@ -77,6 +77,7 @@ struct PtxLds {
     int32_t *Lcnt;      // [chains*m]
     int32_t *Lbad;      // [chains*m] checkpoint count was outside 0..10
     int32_t *Lord;      // [chains*m][10]
+    int32_t *Lins;      // [chains*m] entry a list's offer replaces this sweep (-1: none)
     int32_t *acc;       // [chains*m]
     int32_t *cin;       // [2*chains] accepted boundary pairs (side, chain)
     uint16_t *parent;          // [pairs][n rounded to even] union-find forests over positions
@@ -105,6 +106,7 @@ __host__ __device__ inline size_t ptx_layout(int n, int D, int m, int chains, in
                  o_pos = take(in_lds * n * 4), o_tab = take((size_t)m * row_len * 4), o_S = take((size_t)n * nq * 4),
                  o_E = take((size_t)nl * 8), o_LE = take((size_t)nl * 80), o_Lw = take((size_t)nl * 40),
                  o_Lc = take((size_t)nl * 4), o_Lb = take((size_t)nl * 4), o_Lo = take((size_t)nl * 40),
+                 o_Li = take((size_t)nl * 4),
                  o_acc = take((size_t)nl * 4),
                  o_cin = take((size_t)2 * chains * 4), o_par = take((size_t)nw_icm * ((n + 1) & ~1) * 2),
                  o_dm = take((size_t)nw_icm * vstride * 4), o_misc = take(16),
@@ -124,6 +126,7 @@ __host__ __device__ inline size_t ptx_layout(int n, int D, int m, int chains, in
         L->Lcnt = reinterpret_cast<int32_t *>(base + o_Lc);
         L->Lbad = reinterpret_cast<int32_t *>(base + o_Lb);
         L->Lord = reinterpret_cast<int32_t *>(base + o_Lo);
+        L->Lins = reinterpret_cast<int32_t *>(base + o_Li);
         L->acc = reinterpret_cast<int32_t *>(base + o_acc);
         L->cin = reinterpret_cast<int32_t *>(base + o_cin);
         L->parent = reinterpret_cast<uint16_t *>(base + o_par);
@@ -171,6 +174,7 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
     auto *const L_Lcnt = Lay.Lcnt;
     auto *const L_Lbad = Lay.Lbad;
     auto *const L_Lord = Lay.Lord;
+    auto *const L_Lins = Lay.Lins;
     auto *const L_acc = Lay.acc;
     auto *const L_cin = Lay.cin;
     auto *const L_parent = Lay.parent;
@@ -813,10 +817,6 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                         if (lane == 0 && c0 + u * nw < nchunks) L_dmask[(size_t)j * nchunks + c0 + u * nw] = m;
                     }
             }
-            for (int j = 0; j < nb; ++j)
-                for (int p = tid; p < n16; p += T) L_parent[(size_t)j * n16 + p] = (uint16_t)p;
-            if (esum)
-                for (int p = tid; p < n; p += T) L_es[p] = 0;
             __syncthreads();
             if (wid < nb) {
                 // seed of pair wid = the target-th disagreeing variable
@@ -853,6 +853,16 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                     }
                 }
                 if (lane == 0) L_misc[j] = seed_p;
+            }
+            // fresh forests and energy terms, written by the other wavefronts while the
+            // seeds are searched (by all of them when every wavefront searches a seed)
+            const int iw = T > 64 * nb ? nb : 0;
+            if (wid >= iw) {
+                const int t0 = tid - 64 * iw, ts = T - 64 * iw;
+                for (int j = 0; j < nb; ++j)
+                    for (int p = t0; p < n16; p += ts) L_parent[(size_t)j * n16 + p] = (uint16_t)p;
+                if (esum)
+                    for (int p = t0; p < n; p += ts) L_es[p] = 0;
             }
             __syncthreads();
             // The masks are consumed: their words now collect cluster membership.
@@ -1084,8 +1094,28 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
             __syncthreads();
         }
 
-        // 4. Top-10 lists of the group's colder slots.
+        // 4. Top-10 lists of the group's colder slots: a wavefront per list decides the
+        // offer (candidate test, duplicate check, victim entry) and updates the list;
+        // the inserted state is stored by that wavefront, or for long states (where one
+        // wavefront's copy outlasts a barrier) by the whole workgroup afterwards.
         const int kc = max(K - half, s0), ncold = max(0, s0 + mg - kc);
+        const bool wide_copy = n >= 2048;
+        // replica l's state into dst by threads first, first + step, ...
+        auto store_state = [&](int l, int8_t *dst, int first, int step) __attribute__((always_inline)) {
+            if (pk && (n & 3) == 0) {
+                // chain l's byte of four consecutive sites' words per thread, one word store
+                const int sh = 8 * l;
+                for (int w = first; w < (n >> 2); w += step) {
+                    const uint4 v = *reinterpret_cast<const uint4 *>(L_S + 4 * w);
+                    *reinterpret_cast<uint32_t *>(dst + 4 * w) =
+                        ((v.x >> sh) & 0xFFu) | (((v.y >> sh) & 0xFFu) << 8) | (((v.z >> sh) & 0xFFu) << 16) |
+                        (((v.w >> sh) & 0xFFu) << 24);
+                }
+            } else {
+                const unsigned char *rb = sbyte(l, 0);
+                for (int p = first; p < n; p += step) dst[p] = (int8_t)rb[(uint32_t)p * pst];
+            }
+        };
         for (int li = wid; li < chains * ncold; li += nw) {
             const int ch = li / ncold, k = kc + (li - ch * ncold);
             const int l = ch * mg + (k - s0);
@@ -1094,37 +1124,55 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
             const int cnt = L_Lcnt[l];
             long long *LE = L_LE + (size_t)l * 10;
             int32_t *LW = L_Lwhen + (size_t)l * 10;
+            int8_t *base = a.tops + ((size_t)run * Ls + gl) * 10 * n;
+            int victim = -1;
             bool cand = cnt < 10;
             if (!cand) {
                 long long worst = LE[0];
                 for (int e = 1; e < 10; ++e) worst = LE[e] > worst ? LE[e] : worst;
                 cand = Ec < worst;
             }
-            if (!cand) continue;
-            int8_t *base = a.tops + ((size_t)run * Ls + gl) * 10 * n;
-            const unsigned char *rb = sbyte(l, 0);
-            bool dup = false;
-            for (int e = 0; e < cnt && !dup; ++e) {
-                if (LE[e] != Ec) continue;
-                bool diff = false;
-                for (int p = lane; p < n; p += 64) diff |= base[(size_t)e * n + p] != (int8_t)rb[(uint32_t)p * pst];
-                dup = !__any(diff);
+            if (cand) {
+                const unsigned char *rb = sbyte(l, 0);
+                bool dup = false;
+                for (int e = 0; e < cnt && !dup; ++e) {
+                    if (LE[e] != Ec) continue;
+                    bool diff = false;
+                    for (int p = lane; p < n; p += 64)
+                        diff |= base[(size_t)e * n + p] != (int8_t)rb[(uint32_t)p * pst];
+                    dup = !__any(diff);
+                }
+                if (!dup) {
+                    victim = cnt;
+                    if (cnt == 10) {
+                        victim = 0;
+                        for (int e = 1; e < 10; ++e)
+                            if (LE[e] > LE[victim] || (LE[e] == LE[victim] && LW[e] > LW[victim])) victim = e;
+                    }
+                    if (!wide_copy) store_state(l, base + (size_t)victim * n, lane, 64);
+                }
             }
-            if (dup) continue;
-            int victim = cnt;
-            if (cnt == 10) {
-                victim = 0;
-                for (int e = 1; e < 10; ++e)
-                    if (LE[e] > LE[victim] || (LE[e] == LE[victim] && LW[e] > LW[victim])) victim = e;
-            }
-            for (int p = lane; p < n; p += 64) base[(size_t)victim * n + p] = (int8_t)rb[(uint32_t)p * pst];
             __builtin_amdgcn_wave_barrier();
             if (lane == 0) {
-                LE[victim] = Ec;
-                LW[victim] = ls;
-                if (cnt < 10) L_Lcnt[l] = cnt + 1;
+                if (wide_copy) L_Lins[li] = victim;
+                if (victim >= 0) {
+                    LE[victim] = Ec;
+                    LW[victim] = ls;
+                    if (cnt < 10) L_Lcnt[l] = cnt + 1;
+                }
             }
             __builtin_amdgcn_wave_barrier();
+        }
+        if (wide_copy && ncold > 0) {
+            __syncthreads();
+            for (int li = 0; li < chains * ncold; ++li) {
+                const int victim = L_Lins[li];
+                if (victim < 0) continue;
+                const int ch = li / ncold, k = kc + (li - ch * ncold);
+                const int l = ch * mg + (k - s0);
+                const int gl = ch * half + (k - (K - half));
+                store_state(l, a.tops + (((size_t)run * Ls + gl) * 10 + victim) * n, tid, T);
+            }
         }
         __syncthreads();
     }

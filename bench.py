@@ -460,6 +460,13 @@ def bench_pt(args, cfg, label):
         fx = step()
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
+    if args.calib_copy_mib:
+        # a plain copy of known size, for scaling the HBM counters of a profiled run
+        src = torch.ones(args.calib_copy_mib << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
     out = {
         "metric": METRIC_NAME, "value": round(updates / dt, 1), "unit": "spin-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3),

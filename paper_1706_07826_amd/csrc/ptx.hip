@@ -7,6 +7,9 @@
 // chain) * K + slot lies inside one group), or m = 2 or 1 (a group owns half
 // or a quarter of its quad: it draws the quad's whole random block and updates
 // its own bytes; the other bytes of its LDS copy are never changed or read out).
+// A group of one slot reading its instance from the global image keeps both
+// chains' bytes of that slot in one word per site (byte c: chain c), each byte
+// drawing from its own chain's quad block.
 // Workgroup (run, g) holds the group's slots of EVERY chain, so the Houdayer
 // partners (chain 0 and chain 1 at one slot) share its LDS.  A sweep is
 //   1. Metropolis on the group's replicas (colour classes in order),
@@ -17,8 +20,10 @@
 //      neighbours from the energies each publishes (with the edge
 //      configuration) as sweep-tagged atomic words; an accepted pair copies
 //      the partner's published configuration in,
-//   3. Houdayer moves at the group's slots, one slot pair at a time with the
-//      whole workgroup (lock-free union-find over the disagreeing sites),
+//   3. Houdayer moves at the group's slots, up to four slot pairs at a time
+//      with the whole workgroup (lock-free union-find over the disagreeing
+//      sites; with one pair, the join scan also gathers each disagreeing
+//      site's energy term, so the energy pass needs no neighbour reads),
 //   4. the top-10 offers of the group's colder slots.
 // The instance lives in LDS when it fits beside the replicas; otherwise the
 // neighbour records, biases and orderings are read from the global image
@@ -26,8 +31,7 @@
 //
 // Waits for a neighbour's words are bounded: a workgroup whose neighbour does
 // not publish within the spin limit stops and marks its lists with
-// top_count = -1.  The
-// host only launches grids that fit on the device at once.
+// top_count = -1.  The host only launches grids that fit on the device at once.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

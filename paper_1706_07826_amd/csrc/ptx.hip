@@ -646,10 +646,16 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                     // neighbour's last slot, (s0 + mg - 1, s0 + mg) against the upper one's first
                     const int side = e - nin;
                     const uint32_t *m = msg(side == 0 ? g - 1 : g + 1, side == 0 ? 1 : 0, ch);
+                    // the four energy words are loaded together (one round trip when the
+                    // message is there); a word without the expected tag is waited for
+                    uint32_t ew[4];
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) ew[w] = __hip_atomic_load(m + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     unsigned long long eu = 0;
                     bool ok = true;
+#pragma unroll
                     for (int w = 0; w < 4; ++w) {
-                        const int v = recv(m + w);
+                        const int v = (ew[w] & 0xFFFF0000u) == tag ? (int)(ew[w] & 0xFFFFu) : recv(m + w);
                         ok = ok && v >= 0;
                         eu |= (unsigned long long)(v < 0 ? 0 : v) << (16 * w);
                     }
@@ -1130,29 +1136,39 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
             int32_t *LW = L_Lwhen + (size_t)l * 10;
             int8_t *base = a.tops + ((size_t)run * Ls + gl) * 10 * n;
             int victim = -1;
-            bool cand = cnt < 10;
-            if (!cand) {
-                long long worst = LE[0];
-                for (int e = 1; e < 10; ++e) worst = LE[e] > worst ? LE[e] : worst;
-                cand = Ec < worst;
+            // lane e holds entry e: one butterfly over 16 lanes gives the entry ordered
+            // last by (energy, insertion stamp), the worst one and a full list's victim
+            // (stamps are distinct, so the order is strict)
+            const bool held = lane < cnt;
+            const long long le = held ? LE[lane] : (long long)0x8000000000000000ll;
+            const int32_t lw = held ? LW[lane] : (int32_t)0x80000000;
+            long long bk = le;
+            int32_t bw = lw, bi = lane;
+#pragma unroll
+            for (int off = 8; off >= 1; off >>= 1) {
+                const long long ok = __shfl_xor(bk, off, 64);
+                const int32_t ow = __shfl_xor(bw, off, 64), oi = __shfl_xor(bi, off, 64);
+                if (ok > bk || (ok == bk && ow > bw)) {
+                    bk = ok;
+                    bw = ow;
+                    bi = oi;
+                }
             }
+            const long long worst = __shfl(bk, 0, 64);
+            const bool cand = cnt < 10 || Ec < worst;
             if (cand) {
                 const unsigned char *rb = sbyte(l, 0);
                 bool dup = false;
-                for (int e = 0; e < cnt && !dup; ++e) {
-                    if (LE[e] != Ec) continue;
+                // entries of equal energy get a full comparison of their states
+                for (unsigned long long eq = __ballot(held && le == Ec); eq && !dup; eq &= eq - 1) {
+                    const int e = __ffsll((long long)eq) - 1;
                     bool diff = false;
                     for (int p = lane; p < n; p += 64)
                         diff |= base[(size_t)e * n + p] != (int8_t)rb[(uint32_t)p * pst];
                     dup = !__any(diff);
                 }
                 if (!dup) {
-                    victim = cnt;
-                    if (cnt == 10) {
-                        victim = 0;
-                        for (int e = 1; e < 10; ++e)
-                            if (LE[e] > LE[victim] || (LE[e] == LE[victim] && LW[e] > LW[victim])) victim = e;
-                    }
+                    victim = cnt < 10 ? cnt : __shfl(bi, 0, 64);
                     if (!wide_copy) store_state(l, base + (size_t)victim * n, lane, 64);
                 }
             }

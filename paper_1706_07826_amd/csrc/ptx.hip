@@ -155,6 +155,9 @@ __global__ void xw_zero_kernel(uint32_t *w, size_t count) {
 
 // ND threshold digits; BIG: instance read from the global image; DK: records per
 // site fixed at compile time (0: D at run time).
+// a byte in LDS, addressed with 32-bit offsets
+typedef __attribute__((address_space(3))) const unsigned char lds_u8;
+
 template <int ND, bool BIG, int DK>
 __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1122,8 +1125,12 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                         (((v.w >> sh) & 0xFFu) << 24);
                 }
             } else {
-                const unsigned char *rb = sbyte(l, 0);
-                for (int p = first; p < n; p += step) dst[p] = (int8_t)rb[(uint32_t)p * pst];
+                // 32-bit LDS offsets stepped by addition (no 64-bit address arithmetic)
+                const lds_u8 *rb = (const lds_u8 *)sbyte(l, 0);
+                const uint32_t ostep = (uint32_t)step * pst;
+                uint32_t o = (uint32_t)first * pst;
+                for (uint32_t p = (uint32_t)first; p < (uint32_t)n; p += (uint32_t)step, o += ostep)
+                    dst[p] = (int8_t)rb[o];
             }
         };
         for (int li = wid; li < chains * ncold; li += nw) {
@@ -1157,18 +1164,19 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
             const long long worst = __shfl(bk, 0, 64);
             const bool cand = cnt < 10 || Ec < worst;
             if (cand) {
-                const unsigned char *rb = sbyte(l, 0);
+                const lds_u8 *rb = (const lds_u8 *)sbyte(l, 0);
                 bool dup = false;
                 // entries of equal energy get a full comparison of their states
                 for (unsigned long long eq = __ballot(held && le == Ec); eq && !dup; eq &= eq - 1) {
-                    const int e = __ffsll((long long)eq) - 1;
+                    const int8_t *ent = base + (size_t)(__ffsll((long long)eq) - 1) * n;
                     bool diff = false;
-                    for (int p = lane; p < n; p += 64)
-                        diff |= base[(size_t)e * n + p] != (int8_t)rb[(uint32_t)p * pst];
+                    uint32_t o = (uint32_t)lane * pst;
+                    for (uint32_t p = (uint32_t)lane; p < (uint32_t)n; p += 64u, o += 64u * pst)
+                        diff |= ent[p] != (int8_t)rb[o];
                     dup = !__any(diff);
                 }
                 if (!dup) {
-                    victim = cnt < 10 ? cnt : __shfl(bi, 0, 64);
+                    victim = __builtin_amdgcn_readfirstlane(cnt < 10 ? cnt : __shfl(bi, 0, 64));
                     if (!wide_copy) store_state(l, base + (size_t)victim * n, lane, 64);
                 }
             }

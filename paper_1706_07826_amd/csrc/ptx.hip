@@ -82,6 +82,7 @@ struct PtxLds {
     int32_t *Lbad;      // [chains*m] checkpoint count was outside 0..10
     int32_t *Lord;      // [chains*m][10]
     int32_t *Lins;      // [chains*m] entry a list's offer replaces this sweep (-1: none)
+    long long *Lmax;    // [chains*m] a full list's largest energy (LLONG_MAX: not known)
     int32_t *acc;       // [chains*m]
     int32_t *cin;       // [2*chains] accepted boundary pairs (side, chain)
     uint16_t *parent;          // [pairs][n rounded to even] union-find forests over positions
@@ -110,7 +111,7 @@ __host__ __device__ inline size_t ptx_layout(int n, int D, int m, int chains, in
                  o_pos = take(in_lds * n * 4), o_tab = take((size_t)m * row_len * 4), o_S = take((size_t)n * nq * 4),
                  o_E = take((size_t)nl * 8), o_LE = take((size_t)nl * 80), o_Lw = take((size_t)nl * 40),
                  o_Lc = take((size_t)nl * 4), o_Lb = take((size_t)nl * 4), o_Lo = take((size_t)nl * 40),
-                 o_Li = take((size_t)nl * 4),
+                 o_Li = take((size_t)nl * 4), o_Lm = take((size_t)nl * 8),
                  o_acc = take((size_t)nl * 4),
                  o_cin = take((size_t)2 * chains * 4), o_par = take((size_t)nw_icm * ((n + 1) & ~1) * 2),
                  o_dm = take((size_t)nw_icm * vstride * 4), o_misc = take(16),
@@ -131,6 +132,7 @@ __host__ __device__ inline size_t ptx_layout(int n, int D, int m, int chains, in
         L->Lbad = reinterpret_cast<int32_t *>(base + o_Lb);
         L->Lord = reinterpret_cast<int32_t *>(base + o_Lo);
         L->Lins = reinterpret_cast<int32_t *>(base + o_Li);
+        L->Lmax = reinterpret_cast<long long *>(base + o_Lm);
         L->acc = reinterpret_cast<int32_t *>(base + o_acc);
         L->cin = reinterpret_cast<int32_t *>(base + o_cin);
         L->parent = reinterpret_cast<uint16_t *>(base + o_par);
@@ -182,6 +184,7 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
     auto *const L_Lbad = Lay.Lbad;
     auto *const L_Lord = Lay.Lord;
     auto *const L_Lins = Lay.Lins;
+    auto *const L_Lmax = Lay.Lmax;
     auto *const L_acc = Lay.acc;
     auto *const L_cin = Lay.cin;
     auto *const L_parent = Lay.parent;
@@ -248,6 +251,7 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
     };
     for (int k = tid; k < nl; k += T) {
         L_E[k] = 0;
+        L_Lmax[k] = 0x7FFFFFFFFFFFFFFFll;
         const int gl = list_of(k);
         const int c = (gl >= 0 && a.rs.top_count) ? a.rs.top_count[(size_t)run * Ls + gl] : 0;
         const bool bad = c < 0 || c > 10;
@@ -1139,6 +1143,12 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
             const int gl = ch * half + (k - (K - half));
             const long long Ec = L_E[l];
             const int cnt = L_Lcnt[l];
+            // a full list whose largest energy is known and not above the offered one
+            // fails the candidate test without reading its entries
+            if (cnt == 10 && Ec >= L_Lmax[l]) {
+                if (wide_copy && lane == 0) L_Lins[li] = -1;
+                continue;
+            }
             long long *LE = L_LE + (size_t)l * 10;
             int32_t *LW = L_Lwhen + (size_t)l * 10;
             int8_t *base = a.tops + ((size_t)run * Ls + gl) * 10 * n;
@@ -1188,6 +1198,8 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                     LW[victim] = ls;
                     if (cnt < 10) L_Lcnt[l] = cnt + 1;
                 }
+                // the largest energy stays known while the entries do not change
+                L_Lmax[l] = victim < 0 && cnt == 10 ? worst : 0x7FFFFFFFFFFFFFFFll;
             }
             __builtin_amdgcn_wave_barrier();
         }

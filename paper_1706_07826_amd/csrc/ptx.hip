@@ -83,7 +83,7 @@ struct PtxLds {
     int32_t *Lord;      // [chains*m][10]
     int32_t *Lins;      // [chains*m] entry a list's offer replaces this sweep (-1: none)
     long long *Lmax;    // [chains*m] a full list's largest energy (LLONG_MAX: not known)
-    int32_t *acc;       // [chains*m]
+    int32_t *acc;       // [chains*m] accepted in-group pairs: their replicas' byte offsets
     int32_t *cin;       // [2*chains] accepted boundary pairs (side, chain)
     uint16_t *parent;          // [pairs][n rounded to even] union-find forests over positions
     unsigned long long *dmask; // [pairs][ceil(n / 64)] disagreement masks in variable order
@@ -159,6 +159,7 @@ __global__ void xw_zero_kernel(uint32_t *w, size_t count) {
 // site fixed at compile time (0: D at run time).
 // a byte in LDS, addressed with 32-bit offsets
 typedef __attribute__((address_space(3))) const unsigned char lds_u8;
+typedef __attribute__((address_space(3))) unsigned char lds_mu8;
 
 template <int ND, bool BIG, int DK>
 __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
@@ -646,7 +647,10 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                         const long long x = L_E[la];
                         L_E[la] = L_E[la + 1];
                         L_E[la + 1] = x;
-                        L_acc[atomicAdd(&nacc, 1)] = la;
+                        // the pair's byte offsets of its two replicas (at position 0)
+                        const int ix = atomicAdd(&nacc, 1);
+                        L_acc[2 * ix] = (int)(sbyte(la, 0) - Sb);
+                        L_acc[2 * ix + 1] = (int)(sbyte(la + 1, 0) - Sb);
                     }
                 } else if ((e == nin && lo_act) || (e == nin + 1 && hi_act)) {
                     // the pair straddling a group boundary: (s0 - 1, s0) against the lower
@@ -685,15 +689,33 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
         __syncthreads();
         if (stop) break;
         {
+            // accepted pairs swap their bytes four pairs at a time, every load before
+            // the stores (the pairs' replicas are distinct)
             const int na = nacc;
-            for (int pr = 0; pr < na; ++pr) {
-                const int la = L_acc[pr];
-                unsigned char *A = sbyte(la, 0), *B = sbyte(la + 1, 0);
+            for (int pr0 = 0; pr0 < na; pr0 += 4) {
+                const int nb = min(4, na - pr0);
+                uint32_t oa[4], ob[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int pr = pr0 + min(u, nb - 1);
+                    oa[u] = (uint32_t)L_acc[2 * pr];
+                    ob[u] = (uint32_t)L_acc[2 * pr + 1];
+                }
+                lds_mu8 *const S3 = (lds_mu8 *)Sb;
                 for (int p = tid; p < n; p += T) {
                     const uint32_t o = (uint32_t)p * pst;
-                    const unsigned char x = A[o];
-                    A[o] = B[o];
-                    B[o] = x;
+                    unsigned char x[4], y[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        x[u] = S3[oa[u] + o];
+                        y[u] = S3[ob[u] + o];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (u < nb) {
+                            S3[oa[u] + o] = y[u];
+                            S3[ob[u] + o] = x[u];
+                        }
                 }
             }
             if (edge) {

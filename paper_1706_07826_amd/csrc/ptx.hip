@@ -83,6 +83,7 @@ struct PtxLds {
     int32_t *Lord;      // [chains*m][10]
     int32_t *Lins;      // [chains*m] entry a list's offer replaces this sweep (-1: none)
     long long *Lmax;    // [chains*m] a full list's largest energy (LLONG_MAX: not known)
+    int32_t *snd;       // [m + 1] digit counts of the swap tables of pairs s0-1 .. s0+m-1
     int32_t *acc;       // [chains*m] accepted in-group pairs: their replicas' byte offsets
     int32_t *cin;       // [2*chains] accepted boundary pairs (side, chain)
     uint16_t *parent;          // [pairs][n rounded to even] union-find forests over positions
@@ -111,7 +112,7 @@ __host__ __device__ inline size_t ptx_layout(int n, int D, int m, int chains, in
                  o_pos = take(in_lds * n * 4), o_tab = take((size_t)m * row_len * 4), o_S = take((size_t)n * nq * 4),
                  o_E = take((size_t)nl * 8), o_LE = take((size_t)nl * 80), o_Lw = take((size_t)nl * 40),
                  o_Lc = take((size_t)nl * 4), o_Lb = take((size_t)nl * 4), o_Lo = take((size_t)nl * 40),
-                 o_Li = take((size_t)nl * 4), o_Lm = take((size_t)nl * 8),
+                 o_Li = take((size_t)nl * 4), o_Lm = take((size_t)nl * 8), o_snd = take((size_t)(m + 1) * 4),
                  o_acc = take((size_t)nl * 4),
                  o_cin = take((size_t)2 * chains * 4), o_par = take((size_t)nw_icm * ((n + 1) & ~1) * 2),
                  o_dm = take((size_t)nw_icm * vstride * 4), o_misc = take(16),
@@ -133,6 +134,7 @@ __host__ __device__ inline size_t ptx_layout(int n, int D, int m, int chains, in
         L->Lord = reinterpret_cast<int32_t *>(base + o_Lo);
         L->Lins = reinterpret_cast<int32_t *>(base + o_Li);
         L->Lmax = reinterpret_cast<long long *>(base + o_Lm);
+        L->snd = reinterpret_cast<int32_t *>(base + o_snd);
         L->acc = reinterpret_cast<int32_t *>(base + o_acc);
         L->cin = reinterpret_cast<int32_t *>(base + o_cin);
         L->parent = reinterpret_cast<uint16_t *>(base + o_par);
@@ -186,6 +188,7 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
     auto *const L_Lord = Lay.Lord;
     auto *const L_Lins = Lay.Lins;
     auto *const L_Lmax = Lay.Lmax;
+    auto *const L_snd = Lay.snd;
     auto *const L_acc = Lay.acc;
     auto *const L_cin = Lay.cin;
     auto *const L_parent = Lay.parent;
@@ -244,6 +247,11 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
         }
     }
     for (int k = tid; k < mg * row_len; k += T) L_tab[k] = a.mtab[(size_t)s0 * row_len + k];
+    // the swap tables' digit counts of the pairs this group decides, k = s0 - 1 .. s0 + mg - 1
+    for (int i = tid; i <= mg; i += T) {
+        const int k = s0 - 1 + i;
+        L_snd[i] = k >= 0 && k < K - 1 ? a.snd[k] : 0;
+    }
     const int half = K / 2, Ls = chains * half;
     // Local slot l = chain * mg + (slot - s0); slots k >= K - half hold list gl.
     auto list_of = [=](int l) __attribute__((always_inline)) -> int {
@@ -642,7 +650,7 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                     const int k = kin + 2 * e;
                     const int la = ch * mg + (k - s0);
                     const long long Dd = L_E[la] - L_E[la + 1];
-                    if (swap_test(Dd, a.stab + (size_t)k * 7 * kDigitSize, a.snd[k], (uint32_t)k, t, cctr, a.k0,
+                    if (swap_test(Dd, a.stab + (size_t)k * 7 * kDigitSize, L_snd[k - s0 + 1], (uint32_t)k, t, cctr, a.k0,
                                   a.k1)) {
                         const long long x = L_E[la];
                         L_E[la] = L_E[la + 1];
@@ -677,7 +685,7 @@ __global__ __launch_bounds__(1024) void ptx_kernel(PtxArgs a) {
                         const int lo = ch * mg + (side == 0 ? 0 : mg - 1);
                         const int k = side == 0 ? s0 - 1 : s0 + mg - 1;
                         const long long Dd = side == 0 ? En - L_E[lo] : L_E[lo] - En;
-                        if (swap_test(Dd, a.stab + (size_t)k * 7 * kDigitSize, a.snd[k], (uint32_t)k, t, cctr,
+                        if (swap_test(Dd, a.stab + (size_t)k * 7 * kDigitSize, L_snd[k - s0 + 1], (uint32_t)k, t, cctr,
                                       a.k0, a.k1)) {
                             L_E[lo] = En;
                             L_cin[side * chains + ch] = 1;
